@@ -1,0 +1,199 @@
+"""FP64 CPU oracle for the RelRes Lennard-Jones hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the package smoke check and
+the benchmark's CPU-baseline leg; never by the product path.  It shares no code
+with the HIP library.  The arithmetic lives in ``relres_oracle.c`` (plain C,
+FP64, no FMA contraction); this module only marshals numpy arrays.
+
+Every function follows a passage of arXiv:2104.10231:
+  setup_table   -- mixing (Sec. 2.3), Eq. 14, Eqs. 7/8 solved numerically, Eq. 9
+  pair          -- Eq. 20, case by case
+  compute       -- Eq. 3 energy, forces, pair virial (brute force, all pairs)
+  pairs         -- the two neighbour pair sets (Sec. 2.6 lists)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+REC = 22   # doubles per type-pair record
+# record field offsets
+EPS_FG, SIG_FG, EPS_CG, SIG_CG, FG_SM, CG_SP, CG_CM, G_CM, G_SP, G_SM = 0, 1, 2, 3, 4, 9, 14, 19, 20, 21
+
+_d = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.oracle_record_size.restype = ctypes.c_int
+        L.oracle_lj.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _d]
+        L.oracle_solve_poly.argtypes = [ctypes.c_int, ctypes.c_double, _d, _d]
+        L.oracle_solve_poly.restype = ctypes.c_int
+        L.oracle_setup.argtypes = [ctypes.c_int, _d, _d, _d, _d, ctypes.c_int, _d, _d]
+        L.oracle_setup.restype = ctypes.c_int
+        L.oracle_pair_vec.argtypes = [_d, _d, ctypes.c_int, _d, _d, _d,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_wrap.argtypes = [ctypes.c_int, _d, _d, _d]
+        L.oracle_compute.argtypes = [ctypes.c_int, _d, _d, _i, _i, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _d, _d,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     _d, _d, _d]
+        L.oracle_compute.restype = ctypes.c_int
+        L.oracle_pairs.argtypes = [ctypes.c_int, _d, _d, _i, _i, _i, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
+        L.oracle_pairs.restype = ctypes.c_long
+        assert L.oracle_record_size() == REC
+        _LIB = L
+    return _LIB
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def cutoffs(sys) -> np.ndarray:
+    return np.array([sys.rs_in, sys.rs_out, sys.rc_in, sys.rc_out], np.float64)
+
+
+def lj(eps, sig, r):
+    """u, u', u'' of Eq. 11/12 at distance r."""
+    out = np.zeros(3)
+    lib().oracle_lj(float(eps), float(sig), float(r), out)
+    return out
+
+
+def solve_poly(kind: int, dr: float, u3) -> np.ndarray:
+    """Smoothing-polynomial coefficients from Eq. 7 (kind 0) or Eq. 8 (kind 1)."""
+    g = np.zeros(5)
+    rc = lib().oracle_solve_poly(int(kind), float(dr), _f64(u3), g)
+    if rc:
+        raise ValueError("singular boundary-condition system")
+    return g
+
+
+def setup_table(sys) -> np.ndarray:
+    """(ntypes, ntypes, REC) table of mixed parameters, gammas and Gammas."""
+    nt = sys.ntypes
+    tab = np.zeros(nt * nt * REC)
+    rc = lib().oracle_setup(nt, _f64(sys.eps_fg), _f64(sys.sig_fg), _f64(sys.eps_cg),
+                            _f64(sys.sig_cg), int(sys.mix), cutoffs(sys), tab)
+    if rc == -1:
+        raise ValueError("cutoffs must satisfy r_s- <= r_s+ <= r_c- <= r_c+")
+    if rc:
+        raise ValueError("singular boundary-condition system")
+    return tab.reshape(nt, nt, REC)
+
+
+def pair(rec, cut, r):
+    """Eq. 20 for distances r: returns (u, du/dr, case index 1..5, e_fg, e_cg)."""
+    r = _f64(np.atleast_1d(r))
+    m = r.shape[0]
+    u, du, efg, ecg = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)
+    which = np.zeros(m, np.int32)
+    lib().oracle_pair_vec(_f64(rec), _f64(cut), m, r, u, du, _ptr(which), _ptr(efg), _ptr(ecg))
+    return u, du, which, efg, ecg
+
+
+def wrap(pos, box):
+    pos = _f64(pos)
+    out = np.zeros_like(pos)
+    lib().oracle_wrap(pos.shape[0], pos, _f64(box), out)
+    return out
+
+
+def _excl(sys):
+    if sys.excl_idx is None or len(sys.excl_idx) == 0:
+        return None, None
+    return _i32(sys.excl_offsets), _i32(sys.excl_idx)
+
+
+def compute(sys, pos=None, nthreads: int = 0, sel=None, table=None):
+    """Forces (N,3), energy {total, FG, CG} and virial {xx,yy,zz,xy,xz,yz}.
+
+    With ``sel`` (atom indices) only those atoms' forces are computed and
+    returned (len(sel), 3); E and W are then None.
+    """
+    pos = _f64(sys.pos if pos is None else pos)
+    tab = setup_table(sys) if table is None else table
+    eo, ei = _excl(sys)
+    n = pos.shape[0]
+    if sel is not None:
+        sel = _i32(sel)
+        F = np.zeros((len(sel), 3))
+    else:
+        F = np.zeros((n, 3))
+    E, W = np.zeros(3), np.zeros(6)
+    rc = lib().oracle_compute(n, pos, _f64(sys.box), _i32(sys.types), _i32(sys.mol),
+                              int(bool(sys.exclude_same_mol)), _ptr(eo), _ptr(ei),
+                              sys.ntypes, _f64(tab.reshape(-1)), cutoffs(sys),
+                              int(nthreads), 0 if sel is None else len(sel), _ptr(sel),
+                              F, E, W)
+    if rc:
+        raise MemoryError("oracle_compute failed")
+    if sel is not None:
+        return F, None, None
+    return F, E, W
+
+
+def hybrid_flags(sys) -> np.ndarray:
+    return (np.asarray(sys.eps_cg) > 0.0).astype(np.int32)
+
+
+def pairs(sys, which: int, pos=None, rows=None):
+    """Neighbour pair set: which=0 atom list (r < r_s+ + skin), which=1 site
+    list (hybrid pairs, r < r_c+ + skin).  Returns an (M,2) int32 array of
+    (i, j), i < j, sorted; with ``rows`` the full ordered rows (i, j != i) of
+    the selected atoms."""
+    pos = _f64(sys.pos if pos is None else pos)
+    eo, ei = _excl(sys)
+    r_out = sys.rs_out if which == 0 else sys.rc_out
+    n = pos.shape[0]
+    rsel = None if rows is None else _i32(rows)
+    args = (n, pos, _f64(sys.box), _i32(sys.types), hybrid_flags(sys), _i32(sys.mol),
+            int(bool(sys.exclude_same_mol)), _ptr(eo), _ptr(ei), float(r_out),
+            float(sys.skin), int(which), 0 if rsel is None else len(rsel), _ptr(rsel))
+    cnt = lib().oracle_pairs(*args, None, 0)
+    out = np.zeros((max(cnt, 1), 2), np.int32)
+    cnt2 = lib().oracle_pairs(*args, _ptr(out), cnt)
+    assert cnt2 == cnt
+    return out[:cnt]
+
+
+def cg_params_eq13(eps_mn, sig_mn):
+    """Eq. 13: CG (sigma_ij, eps_ij) of a pair of groups from all FG pair
+    parameters eps_{mu nu}, sigma_{mu nu} (any shape, summed over all pairs)."""
+    e = np.asarray(eps_mn, float).ravel()
+    s = np.asarray(sig_mn, float).ravel()
+    a12 = np.sum(e * s ** 12)
+    a6 = np.sum(e * s ** 6)
+    return a12 ** (1.0 / 6.0) / a6 ** (1.0 / 6.0), a6 ** 2 / a12
+
+
+def cg_params_eq15(eps_sites, sig_sites):
+    """Eq. 15: per-group CG (sigma_l, eps_l) from the FG parameters of the
+    group's sites, valid under geometric mixing."""
+    e = np.asarray(eps_sites, float)
+    s = np.asarray(sig_sites, float)
+    b12 = np.sum(np.sqrt(e * s ** 12))
+    b6 = np.sum(np.sqrt(e * s ** 6))
+    return b12 ** (1.0 / 3.0) / b6 ** (1.0 / 3.0), b6 ** 4 / b12 ** 2

@@ -1,0 +1,405 @@
+/*
+ * relres_oracle.c -- plain, slow, obviously correct FP64 reference for the
+ * Relative Resolution (RelRes) Lennard-Jones pair computation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the package smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no code, header, table or constant with the
+ * HIP path.
+ *
+ * What it computes (paper: "Relative Resolution: A Computationally Efficient
+ * Implementation in LAMMPS", arXiv:2104.10231):
+ *   - per type pair: mixed FG/CG LJ parameters (Sec. 2.3, geometric mixing as
+ *     stated there, or Lorentz-Berthelot), with the CG energy set to zero
+ *     whenever a site is ordinary (Eq. 14);
+ *   - the three smoothing polynomials of Eq. 16 obtained by SOLVING the
+ *     boundary-condition systems of Eq. 7 (f_{s-}^{FG} at r_s-, f_{c-}^{CG} at
+ *     r_c-) and Eq. 8 (f_{s+}^{CG} at r_s+) as 5x5 linear systems by Gaussian
+ *     elimination; the closed forms of Eqs. 17/18 are deliberately NOT used
+ *     here (the tests compare the two);
+ *   - the shifting constants of Eq. 9;
+ *   - the pair potential of Eq. 20 evaluated directly, case by case;
+ *   - the total energy of Eq. 3 as a sum over all non-excluded pairs i<j of a
+ *     periodic orthorhombic box (minimum image), forces F_i = -dE/dx_i and the
+ *     pair virial W_ab = sum_{i<j} d_a F_ij,b with d = x_i - x_j;
+ *   - the two neighbour pair sets that a list-based code must find: atom pairs
+ *     with r < r_s+ + skin and hybrid-hybrid pairs with r < r_c+ + skin.
+ *
+ * Readings where the paper is silent or garbled (also listed in the design doc):
+ *   - Eq. 18 prints gamma_4+ with the wrong sign of its u'' term; the oracle
+ *     does not use Eq. 18 at all, it solves Eq. 8 itself.
+ *   - An empty smoothing zone (r_- == r_+, allowed in Sec. 2.5) makes the
+ *     boundary system singular; the polynomial then reduces to its constant
+ *     term, the potential value at the zone boundary.
+ *   - Pair-set membership is decided in FP64 on wrapped positions:
+ *       dx = x_j - x_i; if dx > L/2: dx -= L; else if dx < -L/2: dx += L;
+ *       r2 = (dx*dx + dy*dy) + dz*dz;  member iff r2 < rl*rl, rl = r_+ + skin
+ *     with every operation separately rounded (built with -ffp-contract=off).
+ *   - Positions are wrapped into [0, L) by
+ *       w = x - L*floor(x/L); if w < 0: w += L; if w >= L: w -= L;
+ *       if w < 0 or w >= L: w = 0
+ *   - An excluded pair loses both its FG and its CG part.
+ *
+ * Build: gcc -O2 -std=c99 -fPIC -shared -fopenmp -ffp-contract=off -lm
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Per-type-pair record, all FP64.  Layout (index: meaning):
+ *   0 eps_fg  1 sig_fg  2 eps_cg  3 sig_cg
+ *   4..8   gamma_{m-}^{FG} (m = 0..4), f_{s-}^{FG}, delta = r - r_s-
+ *   9..13  gamma_{m+}^{CG} (m = 0..4), f_{s+}^{CG}, delta = r - r_s-
+ *   14..18 gamma_{m-}^{CG} (m = 0..4), f_{c-}^{CG}, delta = r - r_c-
+ *   19 Gamma_{c-}  20 Gamma_{s+}  21 Gamma_{s-}
+ */
+#define OR_REC 22
+enum { R_EPS_FG = 0, R_SIG_FG, R_EPS_CG, R_SIG_CG, R_FG_SM = 4, R_CG_SP = 9,
+       R_CG_CM = 14, R_G_CM = 19, R_G_SP = 20, R_G_SM = 21 };
+
+int oracle_record_size(void) { return OR_REC; }
+
+/* ---------------------------------------------------------------------------
+ * LJ potential and its first two derivatives (Eqs. 11/12), textbook calculus:
+ *   u   = 4 eps [ (s/r)^12 - (s/r)^6 ]
+ *   u'  = 4 eps [ -12 s^12 / r^13 + 6 s^6 / r^7 ]
+ *   u'' = 4 eps [ 156 s^12 / r^14 - 42 s^6 / r^8 ]
+ * ------------------------------------------------------------------------- */
+void oracle_lj(double eps, double sig, double r, double out[3])
+{
+    double q = sig / r;
+    double q6 = q * q * q * q * q * q;
+    double q12 = q6 * q6;
+    out[0] = 4.0 * eps * (q12 - q6);
+    out[1] = 4.0 * eps * (-12.0 * q12 + 6.0 * q6) / r;
+    out[2] = 4.0 * eps * (156.0 * q12 - 42.0 * q6) / (r * r);
+}
+
+/* Row of the k-th derivative of sum_m gamma_m delta^m evaluated at delta. */
+static void deriv_row(int k, double delta, double row[5])
+{
+    for (int m = 0; m < 5; ++m) {
+        if (m < k) { row[m] = 0.0; continue; }
+        double c = 1.0;
+        for (int t = 0; t < k; ++t) c *= (double)(m - t);
+        double p = 1.0;
+        for (int t = 0; t < m - k; ++t) p *= delta;
+        row[m] = c * p;
+    }
+}
+
+/* Solve A x = b (5x5) by Gaussian elimination with partial pivoting. */
+static int solve5(double A[5][5], double b[5], double x[5])
+{
+    for (int c = 0; c < 5; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 5; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0) return -1;
+        if (piv != c) {
+            for (int k = 0; k < 5; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < 5; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int k = c; k < 5; ++k) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = 4; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < 5; ++k) s -= A[r][k] * x[k];
+        x[r] = s / A[r][r];
+    }
+    return 0;
+}
+
+/* Smoothing polynomial coefficients from the boundary conditions.
+ * kind 0 (switch-off, Eq. 7): f(0)=u, f'(0)=u', f''(0)=u'', f'(D)=0, f''(D)=0
+ *                             with u = u(r_-)
+ * kind 1 (switch-on,  Eq. 8): f(D)=u, f'(D)=u', f''(D)=u'', f'(0)=0, f''(0)=0
+ *                             with u = u(r_+)
+ * An empty zone (D == 0) keeps only the constant term f = u.              */
+int oracle_solve_poly(int kind, double D, const double u[3], double gamma[5])
+{
+    if (D == 0.0) {
+        gamma[0] = u[0];
+        gamma[1] = gamma[2] = gamma[3] = gamma[4] = 0.0;
+        return 0;
+    }
+    double A[5][5], b[5];
+    double at_u = kind == 0 ? 0.0 : D;     /* where f matches u, u', u'' */
+    double at_0 = kind == 0 ? D : 0.0;     /* where f', f'' vanish      */
+    deriv_row(0, at_u, A[0]); b[0] = u[0];
+    deriv_row(1, at_u, A[1]); b[1] = u[1];
+    deriv_row(2, at_u, A[2]); b[2] = u[2];
+    deriv_row(1, at_0, A[3]); b[3] = 0.0;
+    deriv_row(2, at_0, A[4]); b[4] = 0.0;
+    return solve5(A, b, gamma);
+}
+
+static double poly(const double g[5], double d)
+{
+    return g[0] + g[1] * d + g[2] * d * d + g[3] * d * d * d + g[4] * d * d * d * d;
+}
+
+static double dpoly(const double g[5], double d)
+{
+    return g[1] + 2.0 * g[2] * d + 3.0 * g[3] * d * d + 4.0 * g[4] * d * d * d;
+}
+
+/* Build the per-type-pair table (ntypes*ntypes records of OR_REC doubles).
+ * mix: 0 geometric (eps and sigma geometric means, Sec. 2.3), 1 Lorentz-
+ * Berthelot (eps geometric, sigma arithmetic).  A type is hybrid iff its CG
+ * energy parameter is positive; ordinary-involving pairs get eps_CG = 0
+ * (Eq. 14).  cut = {r_s-, r_s+, r_c-, r_c+}.  Returns 0, or -1 when the cutoff
+ * ordering r_s- <= r_s+ <= r_c- <= r_c+ is violated, -2 on a singular solve. */
+int oracle_setup(int ntypes, const double *eps_fg, const double *sig_fg,
+                 const double *eps_cg, const double *sig_cg, int mix,
+                 const double cut[4], double *table)
+{
+    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    if (!(0.0 <= rsi && rsi <= rso && rso <= rci && rci <= rco)) return -1;
+    double Ds = rso - rsi, Dc = rco - rci;
+    for (int a = 0; a < ntypes; ++a)
+        for (int b = 0; b < ntypes; ++b) {
+            double *R = table + (size_t)(a * ntypes + b) * OR_REC;
+            memset(R, 0, sizeof(double) * OR_REC);
+            R[R_EPS_FG] = sqrt(eps_fg[a] * eps_fg[b]);
+            R[R_SIG_FG] = mix == 0 ? sqrt(sig_fg[a] * sig_fg[b])
+                                   : 0.5 * (sig_fg[a] + sig_fg[b]);
+            int hybrid_pair = eps_cg[a] > 0.0 && eps_cg[b] > 0.0;
+            R[R_EPS_CG] = hybrid_pair ? sqrt(eps_cg[a] * eps_cg[b]) : 0.0;
+            R[R_SIG_CG] = mix == 0 ? sqrt(sig_cg[a] * sig_cg[b])
+                                   : 0.5 * (sig_cg[a] + sig_cg[b]);
+            double u[3];
+            /* f_{s-}^{FG}: switch-off of the FG potential, Eq. 7 at r_s- */
+            oracle_lj(R[R_EPS_FG], R[R_SIG_FG], rsi, u);
+            if (oracle_solve_poly(0, Ds, u, R + R_FG_SM)) return -2;
+            if (hybrid_pair) {
+                /* f_{s+}^{CG}: switch-on of the CG potential, Eq. 8 at r_s+ */
+                oracle_lj(R[R_EPS_CG], R[R_SIG_CG], rso, u);
+                if (oracle_solve_poly(1, Ds, u, R + R_CG_SP)) return -2;
+                /* f_{c-}^{CG}: switch-off of the CG potential, Eq. 7 at r_c- */
+                oracle_lj(R[R_EPS_CG], R[R_SIG_CG], rci, u);
+                if (oracle_solve_poly(0, Dc, u, R + R_CG_CM)) return -2;
+            }
+            /* Eq. 9 */
+            R[R_G_CM] = poly(R + R_CG_CM, Dc);
+            R[R_G_SP] = poly(R + R_CG_CM, Dc) + poly(R + R_FG_SM, Ds);
+            R[R_G_SM] = poly(R + R_CG_CM, Dc) + poly(R + R_FG_SM, Ds) - poly(R + R_CG_SP, 0.0);
+        }
+    return 0;
+}
+
+/* Eq. 20, case by case: returns u~(r), stores du~/dr and the case index
+ * (1..5) that applied.                                                     */
+double oracle_pair(const double *R, const double cut[4], double r,
+                   double *dudr, int *which)
+{
+    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    double u[3];
+    if (r < rsi) {                                  /* [0, r_s-)     */
+        oracle_lj(R[R_EPS_FG], R[R_SIG_FG], r, u);
+        if (which) *which = 1;
+        *dudr = u[1];
+        return u[0] - R[R_G_SM];
+    }
+    if (r < rso) {                                  /* [r_s-, r_s+)  */
+        double g[5], d = r - rsi;
+        for (int m = 0; m < 5; ++m) g[m] = R[R_FG_SM + m] + R[R_CG_SP + m];
+        if (which) *which = 2;
+        *dudr = dpoly(g, d);
+        return poly(g, d) - R[R_G_SP];
+    }
+    if (r < rci) {                                  /* [r_s+, r_c-)  */
+        oracle_lj(R[R_EPS_CG], R[R_SIG_CG], r, u);
+        if (which) *which = 3;
+        *dudr = u[1];
+        return u[0] - R[R_G_CM];
+    }
+    if (r < rco) {                                  /* [r_c-, r_c+)  */
+        double d = r - rci;
+        if (which) *which = 4;
+        *dudr = dpoly(R + R_CG_CM, d);
+        return poly(R + R_CG_CM, d) - R[R_G_CM];
+    }
+    if (which) *which = 5;                          /* [r_c+, inf)   */
+    *dudr = 0.0;
+    return 0.0;
+}
+
+/* Diagnostic split of Eq. 20 into the part carried by the FG potential and
+ * the part carried by the CG potential (their sum is Eq. 20; used only to
+ * report the FG/CG energy breakdown).                                       */
+static void pair_split(const double *R, const double cut[4], double r,
+                       double *e_fg, double *e_cg)
+{
+    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    double Ds = rso - rsi, u[3];
+    double fs_end = poly(R + R_FG_SM, Ds);
+    if (r < rsi) { oracle_lj(R[R_EPS_FG], R[R_SIG_FG], r, u); *e_fg = u[0] - fs_end; }
+    else if (r < rso) *e_fg = poly(R + R_FG_SM, r - rsi) - fs_end;
+    else *e_fg = 0.0;
+    if (r < rsi) *e_cg = R[R_CG_SP] - R[R_G_CM];
+    else if (r < rso) *e_cg = poly(R + R_CG_SP, r - rsi) - R[R_G_CM];
+    else if (r < rci) { oracle_lj(R[R_EPS_CG], R[R_SIG_CG], r, u); *e_cg = u[0] - R[R_G_CM]; }
+    else if (r < rco) *e_cg = poly(R + R_CG_CM, r - rci) - R[R_G_CM];
+    else *e_cg = 0.0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Periodic geometry
+ * ------------------------------------------------------------------------- */
+static double wrap1(double x, double L)
+{
+    double w = x - L * floor(x / L);
+    if (w < 0.0) w += L;
+    if (w >= L) w -= L;
+    if (w < 0.0 || w >= L) w = 0.0;
+    return w;
+}
+
+void oracle_wrap(int n, const double *pos, const double *box, double *out)
+{
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) out[3 * i + k] = wrap1(pos[3 * i + k], box[k]);
+}
+
+/* d = x_j - x_i with the single-shift minimum image, on wrapped positions */
+static void min_image(const double *xi, const double *xj, const double *box, double d[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        double dx = xj[k] - xi[k];
+        double h = 0.5 * box[k];
+        if (dx > h) dx -= box[k];
+        else if (dx < -h) dx += box[k];
+        d[k] = dx;
+    }
+}
+
+static int is_excluded(int i, int j, const int *mol, int same_mol,
+                       const int *eoff, const int *eidx)
+{
+    if (same_mol && mol[i] == mol[j]) return 1;
+    if (eoff) {
+        for (int k = eoff[i]; k < eoff[i + 1]; ++k) if (eidx[k] == j) return 1;
+        for (int k = eoff[j]; k < eoff[j + 1]; ++k) if (eidx[k] == i) return 1;
+    }
+    return 0;
+}
+
+/* Energy (Eq. 3), forces and pair virial by brute force over all pairs.
+ * Each atom i sums over every j != i (so no two threads write one atom);
+ * E and W take each unordered pair once (j > i).  Per-atom partial sums are
+ * combined serially in atom order, so results do not depend on the thread
+ * count.  E_out = {E_total, E_FG part, E_CG part}; W_out = {xx,yy,zz,xy,xz,yz}.
+ * If `sel` is non-NULL only the forces of atoms sel[0..nsel) are computed
+ * (written to F rows 0..nsel) and E, W are not touched.                    */
+int oracle_compute(int n, const double *pos, const double *box, const int *types,
+                   const int *mol, int same_mol, const int *eoff, const int *eidx,
+                   int ntypes, const double *table, const double cut[4],
+                   int nthreads, int nsel, const int *sel,
+                   double *F, double *E_out, double *W_out)
+{
+    double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    int nrows = sel ? nsel : n;
+    double *pe = (double *)calloc((size_t)(nrows > 0 ? nrows : 1) * 9, sizeof(double));
+    if (!w || !pe) { free(w); free(pe); return -1; }
+    oracle_wrap(n, pos, box, w);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int row = 0; row < nrows; ++row) {
+        int i = sel ? sel[row] : row;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        double *acc = pe + (size_t)row * 9;   /* E, Efg, Ecg, W[6] for j > i */
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            if (is_excluded(i, j, mol, same_mol, eoff, eidx)) continue;
+            double d[3];
+            min_image(w + 3 * i, w + 3 * j, box, d);   /* d = x_j - x_i */
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r < cut[3])) continue;               /* case 5: nothing */
+            const double *R = table + (size_t)(types[i] * ntypes + types[j]) * OR_REC;
+            double dudr;
+            double e = oracle_pair(R, cut, r, &dudr, NULL);
+            /* F_i = -dE/dx_i = -u~'(r) (x_i - x_j)/r = +u~'(r) d / r */
+            double s = dudr / r;
+            fx += s * d[0]; fy += s * d[1]; fz += s * d[2];
+            if (j > i) {
+                double efg, ecg;
+                pair_split(R, cut, r, &efg, &ecg);
+                acc[0] += e; acc[1] += efg; acc[2] += ecg;
+                /* W_ab += (x_i - x_j)_a F_ij,b with F_ij = +u~' d / r */
+                double ra[3] = { -d[0], -d[1], -d[2] };
+                double f[3] = { s * d[0], s * d[1], s * d[2] };
+                acc[3] += ra[0] * f[0]; acc[4] += ra[1] * f[1]; acc[5] += ra[2] * f[2];
+                acc[6] += ra[0] * f[1]; acc[7] += ra[0] * f[2]; acc[8] += ra[1] * f[2];
+            }
+        }
+        F[3 * row + 0] = fx; F[3 * row + 1] = fy; F[3 * row + 2] = fz;
+    }
+    if (!sel) {
+        double t[9] = {0};
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < 9; ++k) t[k] += pe[(size_t)i * 9 + k];
+        for (int k = 0; k < 3; ++k) E_out[k] = t[k];
+        for (int k = 0; k < 6; ++k) W_out[k] = t[3 + k];
+    }
+    free(w); free(pe);
+    return 0;
+}
+
+/* Pair sets.  which = 0: all non-excluded pairs with r2 < (r_s+ + skin)^2;
+ * which = 1: non-excluded hybrid-hybrid pairs with r2 < (r_c+ + skin)^2.
+ * Hybrid <=> hybrid_flag[type] != 0.  Pairs are written as (i, j) with i < j,
+ * i-major then j ascending, up to `cap` pairs; the return value is the total
+ * number of pairs (which may exceed cap).  If `row_sel` is non-NULL, only
+ * rows i in row_sel[0..nrow) are enumerated, and j runs over ALL atoms
+ * (ordered pairs (i, j), j != i), which gives full rows for sampled atoms. */
+long oracle_pairs(int n, const double *pos, const double *box, const int *types,
+                  const int *hybrid_flag, const int *mol, int same_mol,
+                  const int *eoff, const int *eidx, double r_out, double skin,
+                  int which, int nrow, const int *row_sel, int *out, long cap)
+{
+    double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!w) return -1;
+    oracle_wrap(n, pos, box, w);
+    double rl = r_out + skin;
+    double rl2 = rl * rl;
+    long cnt = 0;
+    int nr = row_sel ? nrow : n;
+    for (int row = 0; row < nr; ++row) {
+        int i = row_sel ? row_sel[row] : row;
+        if (which == 1 && !hybrid_flag[types[i]]) continue;
+        for (int j = row_sel ? 0 : i + 1; j < n; ++j) {
+            if (j == i) continue;
+            if (which == 1 && !hybrid_flag[types[j]]) continue;
+            if (is_excluded(i, j, mol, same_mol, eoff, eidx)) continue;
+            double d[3];
+            min_image(w + 3 * i, w + 3 * j, box, d);
+            double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            if (r2 < rl2) {
+                if (cnt < cap) { out[2 * cnt] = i; out[2 * cnt + 1] = j; }
+                ++cnt;
+            }
+        }
+    }
+    free(w);
+    return cnt;
+}
+
+/* Evaluate Eq. 20 for a vector of distances with one type-pair record. */
+void oracle_pair_vec(const double *R, const double cut[4], int m, const double *r,
+                     double *u, double *dudr, int *which, double *e_fg, double *e_cg)
+{
+    for (int k = 0; k < m; ++k) {
+        u[k] = oracle_pair(R, cut, r[k], dudr + k, which ? which + k : NULL);
+        if (e_fg && e_cg) pair_split(R, cut, r[k], e_fg + k, e_cg + k);
+    }
+}
