@@ -1,0 +1,204 @@
+"""Benchmark of the RelRes LJ hot path on one MI355X.
+
+Workload (default): the neopentane-like liquid, 4096 molecules x 5 united
+atoms = 20480 atoms, FP32 forces with FP64 energy/virial accumulation, cutoffs
+r_s-/r_s+/r_c-/r_c+ = 5.5/6.0/12.0/14.0 A, skin 2 A.  One step = one force
+call (forces, energy and virial) on the resident positions; the neighbour
+lists are rebuilt every 10 steps inside the timed region.  The same protocol
+is then run for the conventional all-FG system (r_s -> r_c, list at 16 A),
+and the oracle is timed on the host for the CPU baseline.
+
+Prints ONE JSON line (rank 0).  value = RelRes atom-steps/s on this GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make(sys_, precision, pair_math):
+    from paper_2104_10231_amd.relres import RelRes
+    rr = RelRes(rs_in=sys_.rs_in, rs_out=sys_.rs_out, rc_in=sys_.rc_in, rc_out=sys_.rc_out,
+                skin=sys_.skin, eps_fg=sys_.eps_fg, sig_fg=sys_.sig_fg, eps_cg=sys_.eps_cg,
+                sig_cg=sys_.sig_cg, mix=sys_.mix, precision=precision, pair_math=pair_math)
+    csr = len(sys_.excl_idx) > 0
+    rr.set_topology(sys_.types, sys_.mol, sys_.exclude_same_mol,
+                    sys_.excl_offsets if csr else None, sys_.excl_idx if csr else None)
+    return rr
+
+
+def algorithmic_bytes(st, force_bytes):
+    """Bytes one force launch must move at minimum: FP64 positions read once
+    (24 B/atom), forces written once, every list entry (4 B) and row count
+    (4 B) read once.  Neighbour-position gathers are assumed cache hits."""
+    n, ns = st["n_atoms"], st["n_sites"]
+    return n * (24 + 3 * force_bytes) + 4 * (st["atom_entries"] + st["site_entries"]) + 4 * (n + ns)
+
+
+def run_protocol(rr, pos, box, steps, warmup, rebuild_every, timing=False):
+    import torch
+    F = torch.empty((pos.shape[0], 3), dtype=torch.float32 if rr.precision == 32 else torch.float64,
+                    device=pos.device)
+    E = torch.empty(3, dtype=torch.float64, device=pos.device)
+    W = torch.empty(6, dtype=torch.float64, device=pos.device)
+    rr.build_lists(pos, box)
+    for k in range(warmup):
+        if k % rebuild_every == 0:
+            rr.build_lists(pos, box)
+        rr.forces(pos, out=F, energy=E, virial=W)
+    torch.cuda.synchronize()
+    if timing:
+        rr.set_timing(True)
+        rr.timing()                     # reset counters
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if k % rebuild_every == 0:
+            rr.build_lists(pos, box)
+        rr.forces(pos, out=F, energy=E, virial=W)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = rr.timing() if timing else None
+    if timing:
+        rr.set_timing(False)
+    return dt, tm, (F, E, W)
+
+
+def cpu_baseline(sys_, budget_s):
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    oracle.compute(sys_.replace(pos=sys_.pos[:200], types=sys_.types[:200], mol=sys_.mol[:200],
+                                excl_offsets=sys_.excl_offsets[:201]), nthreads=threads)
+    calls, t0 = 0, time.perf_counter()
+    while True:
+        oracle.compute(sys_, nthreads=threads)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or calls >= 50:
+            break
+    return dict(value=sys_.n * calls / el, unit="atom-steps/s", cores=threads, kind="oracle",
+                sample=f"{calls} full FP64 O(N^2) force+energy+virial evaluations of the "
+                       f"{sys_.n}-atom workload ({el:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--rebuild-every", type=int, default=10)
+    ap.add_argument("--workload", default="neopentane_20480",
+                    choices=["neopentane_20480", "propane_1500", "copolymer_98304"])
+    ap.add_argument("--pair-math", type=int, default=0)
+    ap.add_argument("--lanes", type=int, nargs=2, default=None)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-conventional", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the RelRes path "
+              "here is single-GPU, see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as w
+    from paper_2104_10231_amd.relres import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    torch.cuda.set_device(0)
+    s = w.WORKLOADS[args.workload](args.seed)
+    precision = s.precision
+    pos = torch.from_numpy(s.pos).cuda()
+    log(f"[bench] workload {args.workload}: N={s.n}, box {s.box[0]:.3f} A, precision {precision}")
+
+    rr = make(s, precision, args.pair_math)
+    if args.lanes:
+        rr.set_launch(*args.lanes)
+    dt, _, _ = run_protocol(rr, pos, s.box, args.steps, args.warmup, args.rebuild_every)
+    st = rr.stats()
+    value = s.n * args.steps / dt
+    log(f"[bench] RelRes: {dt * 1e3 / args.steps:.4f} ms/step, {value:.4e} atom-steps/s; "
+        f"atom entries {st['atom_entries']}, site entries {st['site_entries']}")
+    # roofline leg: same protocol with HIP events around every force launch
+    dt_t, tm, _ = run_protocol(rr, pos, s.box, args.steps, 0, args.rebuild_every, timing=True)
+    force_us = 1e3 * tm["force_ms"] / max(1, tm["force_calls"])
+    build_us = 1e3 * tm["build_ms"] / max(1, tm["build_calls"])
+    fb = 4 if precision == 32 else 8
+    abytes = algorithmic_bytes(st, fb)
+    achieved = abytes / (force_us * 1e-6) / 1e9
+    log(f"[bench] force kernel {force_us:.2f} us/launch (HIP events), build {build_us:.1f} us; "
+        f"algorithmic {abytes / 1e6:.3f} MB/launch -> {achieved:.1f} GB/s")
+    rr.close()
+
+    conv = None
+    if not args.no_conventional:
+        sc = s.conventional()
+        rc = make(sc, precision, args.pair_math)
+        dtc, _, _ = run_protocol(rc, pos, sc.box, args.steps, args.warmup, args.rebuild_every)
+        stc = rc.stats()
+        _, tmc, _ = run_protocol(rc, pos, sc.box, args.steps, 0, args.rebuild_every, timing=True)
+        rc.close()
+        conv = dict(value=s.n * args.steps / dtc, ms_per_step=dtc * 1e3 / args.steps,
+                    force_us=1e3 * tmc["force_ms"] / max(1, tmc["force_calls"]),
+                    atom_entries=stc["atom_entries"])
+        log(f"[bench] conventional: {conv['ms_per_step']:.4f} ms/step, {conv['value']:.4e} "
+            f"atom-steps/s, force kernel {conv['force_us']:.2f} us, entries {stc['atom_entries']}")
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(s, args.cpu_budget)
+    if cpu:
+        log(f"[bench] cpu oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
+
+    relres_entries = st["atom_entries"] + st["site_entries"]
+    out = {
+        "metric": "RelRes atom-steps/s vs conventional 14 Å LJ, 1 MI355X; % FP32/HBM roofline",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if (precision == 32 and args.pair_math in (0, 32)) else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "atoms": s.n, "sites": int(st["n_sites"]),
+            "box_A": float(s.box[0]), "cutoffs_A": [s.rs_in, s.rs_out, s.rc_in, s.rc_out],
+            "skin_A": s.skin, "rebuild_every": args.rebuild_every, "seed": args.seed,
+            "forces": "fp32" if precision == 32 else "fp64",
+            "pair_math": args.pair_math or precision, "energy_virial": "fp64",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_forces", "kernel_us": force_us,
+            "algorithmic_bytes_per_launch": abytes,
+        },
+        "cpu_baseline": cpu,
+        "conventional": conv,
+        "speedup_vs_conventional": (value / conv["value"]) if conv else None,
+        "list_entries": {"relres": relres_entries,
+                         "conventional": conv["atom_entries"] if conv else None,
+                         "N_star": (relres_entries / conv["atom_entries"]) if conv else None},
+        "build_us": build_us,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * relres.h -- C ABI of the MI355X (gfx950) Relative Resolution Lennard-Jones
+ * hot path.
+ *
+ * The library evaluates the RelRes pair potential of Eq. 20 of "Relative
+ * Resolution: A Computationally Efficient Implementation in LAMMPS"
+ * (arXiv:2104.10231, Sec. 2.5) for a periodic orthorhombic box:
+ *   - near atom pairs interact through the fine-grained (FG) LJ of Eq. 11,
+ *     switched off between r_s- and r_s+ by the polynomial of Eqs. 16/17;
+ *   - pairs of hybrid sites additionally interact through the coarse-grained
+ *     (CG) LJ of Eq. 12, switched on over the same zone (Eq. 18) and off
+ *     between r_c- and r_c+ (Eq. 17), shifted by the constants of Eq. 19;
+ *   - ordinary sites carry no CG interaction (Eq. 14): a type is hybrid iff
+ *     its CG energy parameter is positive (Sec. 2.5, correct use of lj/relres).
+ * Instead of the single long-cutoff neighbour list of a conventional code it
+ * builds the two lists described in Sec. 2.6: an atom list at r_s+ + skin over
+ * all atoms and a site list at r_c+ + skin over hybrid atoms only.
+ *
+ * Conventions
+ *   Units are the caller's (e.g. kcal/mol and Angstrom).  Positions are FP64,
+ *   row-major N x 3, in caller order.  Forces come back in caller order.
+ *   Energy is Eq. 3's total over non-excluded pairs; the virial is the pair
+ *   virial tensor W_ab = sum_{i<j} (x_i - x_j)_a F_ij,b, with F_ij the force
+ *   on i due to j, stored as {xx, yy, zz, xy, xz, yz}.
+ *   "Device pointer" means memory from hipMalloc (or a torch CUDA/HIP tensor)
+ *   on the current device.  The caller owns every pointer it passes; the
+ *   library owns its context and all internal device buffers.
+ *   `stream` is a hipStream_t (NULL = default stream).  All device work is
+ *   enqueued on it; outputs are valid once the stream reaches that point.
+ *   The context is not thread-safe; one context per device and host thread.
+ *
+ * Errors
+ *   Every int-returning function returns RELRES_OK (0) or a negative
+ *   RELRES_ERR_* code; relres_strerror() names it and relres_last_error()
+ *   returns a message with details.  No C++ exception crosses the ABI.
+ */
+#ifndef RELRES_H
+#define RELRES_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RELRES_ABI_VERSION 1
+
+#define RELRES_OK                   0
+#define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
+#define RELRES_ERR_CUTOFF_ORDER    -2  /* r_s- <= r_s+ <= r_c- <= r_c+ and skin >= 0 violated */
+#define RELRES_ERR_BOX_TOO_SMALL   -3  /* some L_k <= 2 (list radius)        */
+#define RELRES_ERR_TOPOLOGY        -4  /* bad type / exclusion arrays        */
+#define RELRES_ERR_HIP             -5  /* a HIP runtime call failed          */
+#define RELRES_ERR_NO_LISTS        -6  /* forces requested before any build  */
+#define RELRES_ERR_LIST_OVERFLOW   -7  /* list capacity could not be grown   */
+#define RELRES_ERR_NONFINITE       -8  /* a position was NaN or infinite     */
+#define RELRES_ERR_STATE           -9  /* call out of order                  */
+
+#define RELRES_MIX_GEOMETRIC   0   /* eps, sigma geometric means (Sec. 2.3)    */
+#define RELRES_MIX_ARITHMETIC  1   /* Lorentz-Berthelot: sigma arithmetic mean */
+
+#define RELRES_MAX_TYPES      32
+#define RELRES_MAX_ATOMS      (1 << 27)
+
+/* Which neighbour list (relres_get_pairs). */
+#define RELRES_LIST_ATOM  0   /* all non-excluded pairs, r < r_s+ + skin        */
+#define RELRES_LIST_SITE  1   /* non-excluded hybrid pairs, r < r_c+ + skin     */
+
+typedef struct relres_ctx relres_ctx;
+
+/* Parameters of the pair style (Sec. 2.5: pair_style lj/relres r_s- r_s+ r_c-
+ * r_c+, pair_coeff per type, pair_modify mix; shift yes is implied: the
+ * shifting constants of Eq. 19 are always applied so that u~(r_c+) = 0).
+ * Per-type arrays are host pointers of length ntypes, copied by
+ * relres_create.  Mixed pair parameters are formed per type pair with `mix`,
+ * for FG and CG alike.  An empty zone (r_- == r_+) is allowed (Sec. 2.5).
+ * The reference (conventional, all-FG) system of Sec. 2.1 is expressed as
+ * r_s- = r_c(inner), r_s+ = r_c- = r_c+ = r_c(outer) with all eps_cg = 0.   */
+typedef struct relres_params {
+    double rs_in, rs_out, rc_in, rc_out;  /* r_s-, r_s+, r_c-, r_c+           */
+    double skin;                          /* Verlet skin added to both lists  */
+    int ntypes;                           /* 1 .. RELRES_MAX_TYPES            */
+    const double *eps_fg, *sig_fg;        /* FG LJ per type (Eq. 11)          */
+    const double *eps_cg, *sig_cg;        /* CG LJ per type (Eq. 12); eps_cg = 0 => ordinary */
+    int mix;                              /* RELRES_MIX_*                     */
+    int precision;                        /* force accumulation and output type:
+                                             64 -> double* forces, 32 -> float* forces */
+    int pair_math;                        /* type of the per-pair terms: 0 = same as
+                                             precision, 32 or 64 (64 with precision 32
+                                             evaluates pairs in FP64 and accumulates
+                                             forces in FP32); energy and virial are
+                                             always accumulated in FP64 */
+} relres_params;
+
+typedef struct relres_stats {
+    long long n_atoms, n_sites;           /* atoms, hybrid atoms              */
+    long long atom_entries, site_entries; /* full-list entries (each pair twice) */
+    int atom_max_row, site_max_row;       /* longest row at the last build   */
+    int atom_capacity, site_capacity;     /* allocated row capacity           */
+    int atom_cells[3], site_cells[3];     /* cell grid of each list           */
+    long long builds, regrows;            /* list builds, capacity regrows    */
+    double box[3];                        /* box of the last build            */
+} relres_stats;
+
+/* Create a context.  Validates the cutoff ordering r_s- <= r_s+ <= r_c- <=
+ * r_c+ (Sec. 2.5), mixes parameters and computes the smoothing coefficients
+ * (Eqs. 17/18) and shifting constants (Eq. 19) in FP64 on the host.
+ * Binds the context to the current HIP device.  *out is NULL on failure.    */
+int relres_create(const relres_params *params, relres_ctx **out);
+
+/* Atoms, by type and molecule (Sec. 3.1, data-file Atoms section), and the
+ * pairs that do not interact at all (neither FG nor CG part): every pair of
+ * one molecule if exclude_same_mol != 0, plus the CSR lists
+ * excl_idx[excl_offsets[i] .. excl_offsets[i+1]) of caller indices (may be
+ * NULL for none; they are symmetrised).  Host arrays, copied.  types[i] must
+ * lie in [0, ntypes).  n_atoms may be 0.                                     */
+int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const int *mol,
+                        int exclude_same_mol, const int *excl_offsets, const int *excl_idx);
+
+/* Build both neighbour lists for the FP64 device positions pos (N x 3, any
+ * periodic image) in the box {Lx, Ly, Lz} (host array).  Every L_k must
+ * exceed twice the largest list radius in use (r_c+ + skin when hybrid atoms
+ * exist, else r_s+ + skin).  Membership is decided in FP64 exactly as
+ *   w = x - L floor(x/L), fixed into [0, L);
+ *   d = w_j - w_i; d -= L if d > L/2; d += L if d < -L/2;
+ *   r2 = (dx dx + dy dy) + dz dz;   member iff r2 < (r_+ + skin)^2
+ * with separately rounded operations.  Synchronises `stream` once to check
+ * the list capacity; grows the lists and rebuilds when a row overflowed.    */
+int relres_build_lists(relres_ctx *ctx, const double *pos, const double box[3], void *stream);
+
+/* Forces, energy and virial for device positions pos (N x 3 FP64) using the
+ * lists of the last build (and its box).  forces: device N x 3, double* when
+ * precision == 64, float* when 32; overwritten.  energy: device double[3] =
+ * {total, FG part, CG part} or NULL; virial: device double[6] or NULL.
+ * Energy and virial are accumulated in FP64 and reduced in a fixed order, so
+ * repeated calls are bitwise identical.  Asynchronous on `stream`.          */
+int relres_forces(relres_ctx *ctx, const double *pos, void *forces, double *energy,
+                  double *virial, void *stream);
+
+/* List statistics of the last build (host struct; synchronises the device). */
+int relres_list_stats(relres_ctx *ctx, relres_stats *out);
+
+/* Copy one list as canonical caller-index pairs (i, j), i < j, sorted by i
+ * then j, into pairs_host (2*cap ints).  *n_out receives the number of pairs,
+ * which may exceed cap (then only cap are written).  Synchronises.         */
+int relres_get_pairs(relres_ctx *ctx, int which, int *pairs_host, long long cap,
+                     long long *n_out);
+
+/* Lanes of a wavefront that share one list row in the force kernel: for rows
+ * of ordinary atoms (atom list) and of hybrid atoms (atom + site list).
+ * Powers of two up to 64; 0 selects a value from the mean row length of the
+ * last build.                                                              */
+int relres_set_launch(relres_ctx *ctx, int lanes_atom, int lanes_site);
+
+/* With enable != 0, HIP events are recorded on the caller's stream right
+ * before and after every force launch and around every list build.
+ * relres_get_timing synchronises, returns the accumulated milliseconds and
+ * launch counts since the previous call, and resets them.                  */
+int relres_set_timing(relres_ctx *ctx, int enable);
+int relres_get_timing(relres_ctx *ctx, double *force_ms, long long *force_calls,
+                      double *build_ms, long long *build_calls);
+
+/* Free the context and all of its device memory (NULL is allowed). */
+void relres_destroy(relres_ctx *ctx);
+
+const char *relres_strerror(int code);
+/* Detail of the most recent error on this thread (never NULL). */
+const char *relres_last_error(void);
+int relres_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RELRES_H */

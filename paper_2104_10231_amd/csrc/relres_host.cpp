@@ -1,0 +1,819 @@
+// relres_host.cpp -- C ABI of the RelRes Lennard-Jones hot path: parameter
+// setup in FP64 on the host, device memory management, and the call sequences
+// of relres_build_lists and relres_forces (kernels in relres_kernels.hip).
+#include "relres.h"
+#include "relres_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace relres;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(RELRES_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+#define TRY(expr)                  \
+    do {                           \
+        int _rc = (expr);          \
+        if (_rc != RELRES_OK) return _rc; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// FP64 parameter setup (Secs. 2.3-2.5)
+// ---------------------------------------------------------------------------
+
+struct LJ3 {
+    double u, du, d2u;   // u, du/dr, d2u/dr2 of Eq. 11 / Eq. 12
+};
+
+LJ3 lj3(double eps, double sig, double r)
+{
+    const double q2 = (sig / r) * (sig / r);
+    const double q6 = q2 * q2 * q2;
+    const double q12 = q6 * q6;
+    return {4.0 * eps * (q12 - q6), 24.0 * eps / r * (q6 - 2.0 * q12),
+            24.0 * eps / (r * r) * (26.0 * q12 - 7.0 * q6)};
+}
+
+// Eq. 17: polynomial that switches a potential off over [r_-, r_- + D),
+// matching u, u', u'' at r_- and with vanishing f', f'' at the far end (Eq. 7).
+// An empty zone keeps only the constant term.
+void switch_off(const LJ3& u, double D, double g[5])
+{
+    g[0] = u.u;
+    if (D == 0.0) {
+        g[1] = g[2] = g[3] = g[4] = 0.0;
+        return;
+    }
+    g[1] = u.du;
+    g[2] = 0.5 * u.d2u;
+    g[3] = -u.du / (D * D) - 2.0 * u.d2u / (3.0 * D);
+    g[4] = u.du / (2.0 * D * D * D) + u.d2u / (4.0 * D * D);
+}
+
+// Eq. 18: polynomial that switches a potential on over [r_+ - D, r_+) with
+// f', f'' vanishing at the near end and matching u, u', u'' at r_+ (Eq. 8).
+// gamma_4+ carries +u''/(4 D^2): with the sign printed in Eq. 18 the second
+// derivative at r_+ would be -5 u'' instead of u''.
+void switch_on(const LJ3& u, double D, double g[5])
+{
+    g[1] = g[2] = 0.0;
+    if (D == 0.0) {
+        g[0] = u.u;
+        g[3] = g[4] = 0.0;
+        return;
+    }
+    g[0] = u.u - 0.5 * u.du * D + u.d2u * D * D / 12.0;
+    g[3] = u.du / (D * D) - u.d2u / (3.0 * D);
+    g[4] = -u.du / (2.0 * D * D * D) + u.d2u / (4.0 * D * D);
+}
+
+double poly_at(const double g[5], double d)
+{
+    return g[0] + d * (g[1] + d * (g[2] + d * (g[3] + d * g[4])));
+}
+
+double mix_sigma(int mix, double a, double b)
+{
+    return mix == RELRES_MIX_GEOMETRIC ? std::sqrt(a * b) : 0.5 * (a + b);
+}
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+int ensure(DBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 64;
+    if (b.p && b.bytes >= bytes) return RELRES_OK;
+    if (b.p) HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    HIP_TRY(hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+    return RELRES_OK;
+}
+
+void release(DBuf& b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+struct GridHost {
+    int n[3] = {0, 0, 0};
+    int ncell = 0;
+    int cap = 0;
+    int members = 0;
+    double rl = 0.0;
+    DBuf rank_of_lin, lin_of_rank, count, start, user_unsorted, user, pos, meta, list, nrow;
+    GridDev dev{};
+};
+
+uint32_t spread3(uint32_t v)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+}  // namespace
+
+struct relres_ctx {
+    int device = 0;
+    double rsi = 0, rso = 0, rci = 0, rco = 0, skin = 0;
+    int ntypes = 0, mix = 0, precision = 64, pair_math = 64;
+    std::vector<int> hybrid;
+    std::vector<PairCoef<double>> coef64;
+    DBuf d_coef64, d_coef32, d_hybrid;
+    double cut64[8] = {0};
+
+    bool topo_set = false;
+    int n = 0, n_sites = 0;
+    int same_mol = 0;
+    bool has_excl = false;
+    DBuf d_types, d_mol, d_excl_off, d_excl_idx;
+
+    GridHost ga, gs;
+    DBuf d_grids, d_wpos, d_key_a, d_key_s, d_user2arow, d_s_arow, d_status;
+    GridDev* h_grids = nullptr;
+    Status* h_status = nullptr;
+    Status* h_zero = nullptr;
+    bool built = false;
+    double box[3] = {0, 0, 0};
+
+    DBuf d_partials, d_counter;
+    int lanes_a = 0, lanes_b = 0;        // caller override, 0 = automatic
+    int auto_la = 4, auto_lb = 16;
+
+    relres_stats stats{};
+
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_force, ev_build;
+    double force_ms = 0, build_ms = 0;
+    long long force_calls = 0, build_calls = 0;
+};
+
+namespace {
+
+int take_events(relres_ctx* c, hipEvent_t& a, hipEvent_t& b)
+{
+    for (hipEvent_t* e : {&a, &b}) {
+        if (c->ev_free.empty()) {
+            hipEvent_t ev;
+            HIP_TRY(hipEventCreate(&ev));
+            c->ev_free.push_back(ev);
+        }
+        *e = c->ev_free.back();
+        c->ev_free.pop_back();
+    }
+    return RELRES_OK;
+}
+
+int next_pow2_clamped(double x, int lo, int hi)
+{
+    int p = 1;
+    while (p < x && p < hi) p <<= 1;
+    return std::max(lo, std::min(hi, p));
+}
+
+int log2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+int setup_grid(GridHost& g, double rl, const double box[3], int members)
+{
+    int n[3];
+    long long total = 1;
+    for (int k = 0; k < 3; ++k) {
+        // a cell edge is at least the list radius (with a margin far above
+        // rounding), so every pair within rl lies in neighbouring cells
+        n[k] = (int)std::floor(box[k] / (rl * (1.0 + 1e-10)));
+        n[k] = std::max(1, std::min(n[k], 1023));
+        total *= n[k];
+    }
+    while (total > (1ll << 22)) {   // keep the cell tables modest in sparse huge boxes
+        total = 1;
+        for (int k = 0; k < 3; ++k) {
+            n[k] = std::max(1, n[k] / 2);
+            total *= n[k];
+        }
+    }
+    const bool same = n[0] == g.n[0] && n[1] == g.n[1] && n[2] == g.n[2] && g.rank_of_lin.p;
+    g.rl = rl;
+    g.members = members;
+    if (!same) {
+        g.n[0] = n[0];
+        g.n[1] = n[1];
+        g.n[2] = n[2];
+        g.ncell = (int)total;
+        std::vector<std::pair<uint32_t, int>> code(g.ncell);
+        for (int x = 0; x < n[0]; ++x)
+            for (int y = 0; y < n[1]; ++y)
+                for (int z = 0; z < n[2]; ++z) {
+                    const int lin = (x * n[1] + y) * n[2] + z;
+                    code[lin] = {spread3(x) << 2 | spread3(y) << 1 | spread3(z), lin};
+                }
+        std::sort(code.begin(), code.end());
+        std::vector<int> rank(g.ncell), lin_of(g.ncell);
+        for (int r = 0; r < g.ncell; ++r) {
+            rank[code[r].second] = r;
+            lin_of[r] = code[r].second;
+        }
+        TRY(ensure(g.rank_of_lin, sizeof(int) * g.ncell));
+        TRY(ensure(g.lin_of_rank, sizeof(int) * g.ncell));
+        TRY(ensure(g.count, sizeof(int) * g.ncell));
+        TRY(ensure(g.start, sizeof(int) * (g.ncell + 1)));
+        HIP_TRY(hipMemcpy(g.rank_of_lin.p, rank.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g.lin_of_rank.p, lin_of.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(g.count.p, 0, sizeof(int) * g.ncell));
+    }
+    TRY(ensure(g.user_unsorted, sizeof(int) * members));
+    TRY(ensure(g.user, sizeof(int) * members));
+    TRY(ensure(g.pos, sizeof(double4) * members));
+    TRY(ensure(g.meta, sizeof(int2) * members));
+    TRY(ensure(g.nrow, sizeof(int) * members));
+    if (g.cap == 0) {
+        const double vol = box[0] * box[1] * box[2];
+        const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * members / vol;
+        g.cap = std::max(16, (int)std::ceil(expect * 1.5 + 16.0));
+        g.cap = (g.cap + 7) & ~7;
+    }
+    TRY(ensure(g.list, sizeof(int) * (size_t)members * g.cap));
+
+    GridDev& d = g.dev;
+    for (int k = 0; k < 3; ++k) {
+        d.n[k] = g.n[k];
+        d.inv_cell[k] = g.n[k] / box[k];
+        if (g.n[k] >= 3) {
+            d.noff[k] = 3;
+            d.off[k][0] = -1; d.off[k][1] = 0; d.off[k][2] = 1;
+        } else if (g.n[k] == 2) {
+            d.noff[k] = 2;
+            d.off[k][0] = 0; d.off[k][1] = 1; d.off[k][2] = 0;
+        } else {
+            d.noff[k] = 1;
+            d.off[k][0] = 0; d.off[k][1] = 0; d.off[k][2] = 0;
+        }
+    }
+    d.ncell = g.ncell;
+    d.rl2 = rl * rl;
+    d.members = members;
+    d.cap = g.cap;
+    d.rank_of_lin = g.rank_of_lin.as<int>();
+    d.lin_of_rank = g.lin_of_rank.as<int>();
+    d.count = g.count.as<int>();
+    d.start = g.start.as<int>();
+    d.user_unsorted = g.user_unsorted.as<int>();
+    d.user = g.user.as<int>();
+    d.pos = g.pos.as<double4>();
+    d.meta = g.meta.as<int2>();
+    d.list = g.list.as<int>();
+    d.nrow = g.nrow.as<int>();
+    return RELRES_OK;
+}
+
+TopoDev topo_of(relres_ctx* c)
+{
+    TopoDev t;
+    t.types = c->d_types.as<int>();
+    t.mol = c->d_mol.as<int>();
+    t.hybrid = c->d_hybrid.as<int>();
+    t.excl_off = c->has_excl ? c->d_excl_off.as<int>() : nullptr;
+    t.excl_idx = c->has_excl ? c->d_excl_idx.as<int>() : nullptr;
+    t.same_mol = c->same_mol;
+    t.n = c->n;
+    return t;
+}
+
+int upload_grids(relres_ctx* c, hipStream_t s)
+{
+    c->h_grids[0] = c->ga.dev;
+    c->h_grids[1] = c->n_sites > 0 ? c->gs.dev : c->ga.dev;
+    HIP_TRY(hipMemcpyAsync(c->d_grids.p, c->h_grids, 2 * sizeof(GridDev), hipMemcpyHostToDevice, s));
+    return RELRES_OK;
+}
+
+int run_lists(relres_ctx* c, hipStream_t s)
+{
+    TRY(upload_grids(c, s));
+    HIP_TRY(hipMemcpyAsync(c->d_status.p, c->h_zero, sizeof(Status), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_lists(c->d_grids.as<GridDev>(), c->ga.ncell, c->n_sites > 0 ? c->gs.ncell : 0,
+                         topo_of(c), c->box, c->d_user2arow.as<int>(), c->d_s_arow.as<int>(),
+                         c->d_status.as<Status>(), s));
+    HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RELRES_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int relres_abi_version(void) { return RELRES_ABI_VERSION; }
+
+const char* relres_last_error(void) { return g_last_error.c_str(); }
+
+const char* relres_strerror(int code)
+{
+    switch (code) {
+    case RELRES_OK: return "ok";
+    case RELRES_ERR_ARG: return "invalid argument";
+    case RELRES_ERR_CUTOFF_ORDER: return "cutoffs must satisfy r_s- <= r_s+ <= r_c- <= r_c+ (and skin >= 0)";
+    case RELRES_ERR_BOX_TOO_SMALL: return "box edge not larger than twice the list radius";
+    case RELRES_ERR_TOPOLOGY: return "invalid topology";
+    case RELRES_ERR_HIP: return "HIP runtime error";
+    case RELRES_ERR_NO_LISTS: return "no neighbour lists: call relres_build_lists first";
+    case RELRES_ERR_LIST_OVERFLOW: return "neighbour list capacity could not be grown";
+    case RELRES_ERR_NONFINITE: return "non-finite position";
+    case RELRES_ERR_STATE: return "call out of order";
+    default: return "unknown error";
+    }
+}
+
+int relres_create(const relres_params* p, relres_ctx** out)
+{
+    if (!out) return fail(RELRES_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(RELRES_ERR_ARG, "params is NULL");
+    if (p->ntypes < 1 || p->ntypes > RELRES_MAX_TYPES)
+        return fail(RELRES_ERR_ARG, "ntypes %d outside [1, %d]", p->ntypes, RELRES_MAX_TYPES);
+    if (!p->eps_fg || !p->sig_fg || !p->eps_cg || !p->sig_cg)
+        return fail(RELRES_ERR_ARG, "per-type parameter array is NULL");
+    if (p->precision != 32 && p->precision != 64)
+        return fail(RELRES_ERR_ARG, "precision must be 32 or 64");
+    if (p->pair_math != 0 && p->pair_math != 32 && p->pair_math != 64)
+        return fail(RELRES_ERR_ARG, "pair_math must be 0, 32 or 64");
+    if (p->precision == 64 && p->pair_math == 32)
+        return fail(RELRES_ERR_ARG, "FP64 forces need FP64 pair terms");
+    if (p->mix != RELRES_MIX_GEOMETRIC && p->mix != RELRES_MIX_ARITHMETIC)
+        return fail(RELRES_ERR_ARG, "unknown mixing rule %d", p->mix);
+    const double cut[5] = {p->rs_in, p->rs_out, p->rc_in, p->rc_out, p->skin};
+    for (double v : cut)
+        if (!std::isfinite(v)) return fail(RELRES_ERR_CUTOFF_ORDER, "non-finite cutoff");
+    if (!(0.0 < p->rs_in && p->rs_in <= p->rs_out && p->rs_out <= p->rc_in &&
+          p->rc_in <= p->rc_out && p->skin >= 0.0))
+        return fail(RELRES_ERR_CUTOFF_ORDER, "need 0 < r_s- <= r_s+ <= r_c- <= r_c+, skin >= 0 "
+                    "(got %g %g %g %g, skin %g)", p->rs_in, p->rs_out, p->rc_in, p->rc_out, p->skin);
+    const int nt = p->ntypes;
+    for (int t = 0; t < nt; ++t) {
+        if (!(std::isfinite(p->eps_fg[t]) && p->eps_fg[t] >= 0.0 && std::isfinite(p->sig_fg[t]) &&
+              p->sig_fg[t] > 0.0))
+            return fail(RELRES_ERR_ARG, "bad FG parameters for type %d", t);
+        if (!(std::isfinite(p->eps_cg[t]) && p->eps_cg[t] >= 0.0 && std::isfinite(p->sig_cg[t])))
+            return fail(RELRES_ERR_ARG, "bad CG parameters for type %d", t);
+        if (p->eps_cg[t] > 0.0 && !(p->sig_cg[t] > 0.0))
+            return fail(RELRES_ERR_ARG, "hybrid type %d needs sigma_CG > 0", t);
+    }
+
+    relres_ctx* c = new relres_ctx();
+    auto bail = [&](int rc) { relres_destroy(c); return rc; };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(RELRES_ERR_HIP, "no HIP device"));
+    c->rsi = p->rs_in; c->rso = p->rs_out; c->rci = p->rc_in; c->rco = p->rc_out;
+    c->skin = p->skin;
+    c->ntypes = nt;
+    c->mix = p->mix;
+    c->precision = p->precision;
+    c->pair_math = p->pair_math ? p->pair_math : p->precision;
+    c->hybrid.resize(nt);
+    for (int t = 0; t < nt; ++t) c->hybrid[t] = p->eps_cg[t] > 0.0 ? 1 : 0;
+
+    const double Ds = c->rso - c->rsi, Dc = c->rco - c->rci;
+    c->coef64.resize((size_t)nt * nt);
+    std::vector<PairCoef<float>> coef32((size_t)nt * nt);
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            PairCoef<double> k{};
+            const double ef = std::sqrt(p->eps_fg[a] * p->eps_fg[b]);
+            const double sf = mix_sigma(c->mix, p->sig_fg[a], p->sig_fg[b]);
+            const double sf6 = sf * sf * sf * sf * sf * sf;
+            k.fg_c12 = 48.0 * ef * sf6 * sf6;
+            k.fg_c6 = 24.0 * ef * sf6;
+            k.fg_e12 = 4.0 * ef * sf6 * sf6;
+            k.fg_e6 = 4.0 * ef * sf6;
+            switch_off(lj3(ef, sf, c->rsi), Ds, k.fg_g);
+            k.fg_shift = poly_at(k.fg_g, Ds);
+            if (c->hybrid[a] && c->hybrid[b]) {           // Eq. 14
+                const double ec = std::sqrt(p->eps_cg[a] * p->eps_cg[b]);
+                const double sc = mix_sigma(c->mix, p->sig_cg[a], p->sig_cg[b]);
+                const double sc6 = sc * sc * sc * sc * sc * sc;
+                k.cg_c12 = 48.0 * ec * sc6 * sc6;
+                k.cg_c6 = 24.0 * ec * sc6;
+                k.cg_e12 = 4.0 * ec * sc6 * sc6;
+                k.cg_e6 = 4.0 * ec * sc6;
+                double g[5];
+                switch_on(lj3(ec, sc, c->rso), Ds, g);
+                k.sp_g0 = g[0];
+                k.sp_g3 = g[3];
+                k.sp_g4 = g[4];
+                switch_off(lj3(ec, sc, c->rci), Dc, k.cm_g);
+                k.cm_shift = poly_at(k.cm_g, Dc);         // Gamma_c- (Eq. 19)
+            }
+            c->coef64[(size_t)a * nt + b] = k;
+            const double* src = reinterpret_cast<const double*>(&k);
+            float* dst = reinterpret_cast<float*>(&coef32[(size_t)a * nt + b]);
+            for (size_t q = 0; q < sizeof(PairCoef<double>) / sizeof(double); ++q) dst[q] = (float)src[q];
+        }
+    c->cut64[0] = c->rsi; c->cut64[1] = c->rso; c->cut64[2] = c->rci; c->cut64[3] = c->rco;
+    for (int k = 0; k < 4; ++k) c->cut64[4 + k] = c->cut64[k] * c->cut64[k];
+
+    int rc;
+    if ((rc = ensure(c->d_coef64, sizeof(PairCoef<double>) * c->coef64.size()))) return bail(rc);
+    if ((rc = ensure(c->d_coef32, sizeof(PairCoef<float>) * coef32.size()))) return bail(rc);
+    if ((rc = ensure(c->d_hybrid, sizeof(int) * nt))) return bail(rc);
+    if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev)))) return bail(rc);
+    if ((rc = ensure(c->d_status, sizeof(Status)))) return bail(rc);
+    if ((rc = ensure(c->d_counter, 64))) return bail(rc);
+    if (hipMemcpy(c->d_coef64.p, c->coef64.data(), sizeof(PairCoef<double>) * c->coef64.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_coef32.p, coef32.data(), sizeof(PairCoef<float>) * coef32.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_hybrid.p, c->hybrid.data(), sizeof(int) * nt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(c->d_counter.p, 0, 64) != hipSuccess)
+        return bail(fail(RELRES_ERR_HIP, "uploading parameters failed"));
+    if (hipHostMalloc((void**)&c->h_grids, 2 * sizeof(GridDev), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_zero, sizeof(Status), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(RELRES_ERR_HIP, "pinned host allocation failed"));
+    std::memset(c->h_grids, 0, 2 * sizeof(GridDev));
+    std::memset(c->h_status, 0, sizeof(Status));
+    std::memset(c->h_zero, 0, sizeof(Status));
+    *out = c;
+    return RELRES_OK;
+}
+
+int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, int exclude_same_mol,
+                        const int* excl_offsets, const int* excl_idx)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (n < 0 || n >= RELRES_MAX_ATOMS) return fail(RELRES_ERR_ARG, "n_atoms %d out of range", n);
+    if (n > 0 && !types) return fail(RELRES_ERR_ARG, "types is NULL");
+    if (exclude_same_mol && n > 0 && !mol) return fail(RELRES_ERR_ARG, "mol is NULL");
+    std::vector<int> t(types, types + n), m(n, 0);
+    if (mol) std::copy(mol, mol + n, m.begin());
+    int sites = 0;
+    for (int i = 0; i < n; ++i) {
+        if (t[i] < 0 || t[i] >= c->ntypes)
+            return fail(RELRES_ERR_TOPOLOGY, "type %d of atom %d outside [0, %d)", t[i], i, c->ntypes);
+        sites += c->hybrid[t[i]];
+    }
+    // exclusions: validate, symmetrise, sort, deduplicate
+    std::vector<int> off(n + 1, 0), idx;
+    if (excl_offsets && n > 0) {
+        if (excl_offsets[0] != 0) return fail(RELRES_ERR_TOPOLOGY, "excl_offsets[0] != 0");
+        for (int i = 0; i < n; ++i)
+            if (excl_offsets[i + 1] < excl_offsets[i])
+                return fail(RELRES_ERR_TOPOLOGY, "excl_offsets decrease at %d", i);
+        if (excl_offsets[n] > 0 && !excl_idx) return fail(RELRES_ERR_TOPOLOGY, "excl_idx is NULL");
+        std::vector<std::vector<int>> part(n);
+        for (int i = 0; i < n; ++i)
+            for (int k = excl_offsets[i]; k < excl_offsets[i + 1]; ++k) {
+                const int j = excl_idx[k];
+                if (j < 0 || j >= n || j == i)
+                    return fail(RELRES_ERR_TOPOLOGY, "bad exclusion %d of atom %d", j, i);
+                part[i].push_back(j);
+                part[j].push_back(i);
+            }
+        for (int i = 0; i < n; ++i) {
+            std::sort(part[i].begin(), part[i].end());
+            part[i].erase(std::unique(part[i].begin(), part[i].end()), part[i].end());
+            off[i + 1] = off[i] + (int)part[i].size();
+            idx.insert(idx.end(), part[i].begin(), part[i].end());
+        }
+    }
+    c->built = false;
+    c->topo_set = false;
+    c->n = n;
+    c->n_sites = sites;
+    c->same_mol = exclude_same_mol ? 1 : 0;
+    c->has_excl = !idx.empty();
+    TRY(ensure(c->d_types, sizeof(int) * n));
+    TRY(ensure(c->d_mol, sizeof(int) * n));
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(c->d_types.p, t.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_mol.p, m.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    }
+    if (c->has_excl) {
+        TRY(ensure(c->d_excl_off, sizeof(int) * (n + 1)));
+        TRY(ensure(c->d_excl_idx, sizeof(int) * idx.size()));
+        HIP_TRY(hipMemcpy(c->d_excl_off.p, off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_excl_idx.p, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
+    }
+    c->topo_set = true;
+    return RELRES_OK;
+}
+
+int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
+    if (!box) return fail(RELRES_ERR_ARG, "box is NULL");
+    if (c->n > 0 && !pos) return fail(RELRES_ERR_ARG, "pos is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!(std::isfinite(box[k]) && box[k] > 0.0)) return fail(RELRES_ERR_ARG, "bad box edge %g", box[k]);
+    hipStream_t s = (hipStream_t)stream;
+    const double rla = c->rso + c->skin, rls = c->rco + c->skin;
+    const bool sites = c->n_sites > 0;
+    const double rmax = sites ? rls : rla;
+    for (int k = 0; k < 3; ++k)
+        if (!(box[k] > 2.0 * rmax))
+            return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g must exceed 2 x %g", box[k], rmax);
+    c->built = false;
+    std::copy(box, box + 3, c->box);
+    TRY(setup_grid(c->ga, rla, box, c->n));
+    if (sites) TRY(setup_grid(c->gs, rls, box, c->n_sites));
+    TRY(ensure(c->d_wpos, sizeof(double4) * c->n));
+    TRY(ensure(c->d_key_a, sizeof(int2) * c->n));
+    TRY(ensure(c->d_key_s, sizeof(int2) * c->n));
+    TRY(ensure(c->d_user2arow, sizeof(int) * c->n));
+    TRY(ensure(c->d_s_arow, sizeof(int) * std::max(1, c->n_sites)));
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        TRY(take_events(c, e0, e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    if (c->n > 0) {
+        TRY(upload_grids(c, s));
+        HIP_TRY(hipMemcpyAsync(c->d_status.p, c->h_zero, sizeof(Status), hipMemcpyHostToDevice, s));
+        const TopoDev topo = topo_of(c);
+        GridDev* gd = c->d_grids.as<GridDev>();
+        HIP_TRY(launch_bin(c->n, pos, box, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
+                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), s));
+        HIP_TRY(launch_scan(gd, sites ? 2 : 1, s));
+        HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
+        const int ncs = sites ? c->gs.ncell : 0;
+        HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
+                                c->d_user2arow.as<int>(), s));
+        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, topo, box, c->d_user2arow.as<int>(),
+                             c->d_s_arow.as<int>(), c->d_status.as<Status>(), s));
+        HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
+        if (c->timing) HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->h_status->nonfinite) return fail(RELRES_ERR_NONFINITE, "non-finite position");
+        // grow rows that overflowed and rebuild the lists (positions stay sorted)
+        for (int attempt = 0; attempt < 3; ++attempt) {
+            const bool ov_a = c->h_status->max_row[0] > c->ga.cap;
+            const bool ov_s = sites && c->h_status->max_row[1] > c->gs.cap;
+            if (!ov_a && !ov_s) break;
+            if (attempt == 2) return fail(RELRES_ERR_LIST_OVERFLOW, "list capacity did not converge");
+            if (ov_a) {
+                c->ga.cap = ((int)(c->h_status->max_row[0] * 1.25) + 8 + 7) & ~7;
+                TRY(setup_grid(c->ga, rla, box, c->n));
+            }
+            if (ov_s) {
+                c->gs.cap = ((int)(c->h_status->max_row[1] * 1.25) + 8 + 7) & ~7;
+                TRY(setup_grid(c->gs, rls, box, c->n_sites));
+            }
+            c->stats.regrows++;
+            TRY(run_lists(c, s));
+        }
+    } else if (c->timing) {
+        HIP_TRY(hipEventRecord(e1, s));
+    }
+    if (c->timing) c->ev_build.push_back({e0, e1});
+
+    relres_stats& st = c->stats;
+    st.n_atoms = c->n;
+    st.n_sites = c->n_sites;
+    st.atom_entries = c->n ? (long long)c->h_status->entries[0] : 0;
+    st.site_entries = (c->n && sites) ? (long long)c->h_status->entries[1] : 0;
+    st.atom_max_row = c->n ? c->h_status->max_row[0] : 0;
+    st.site_max_row = (c->n && sites) ? c->h_status->max_row[1] : 0;
+    st.atom_capacity = c->ga.cap;
+    st.site_capacity = sites ? c->gs.cap : 0;
+    for (int k = 0; k < 3; ++k) {
+        st.atom_cells[k] = c->ga.n[k];
+        st.site_cells[k] = sites ? c->gs.n[k] : 0;
+        st.box[k] = box[k];
+    }
+    st.builds++;
+    // automatic lanes per row: about four list entries per lane
+    const double avg_a = c->n ? (double)st.atom_entries / c->n : 0.0;
+    const double avg_s = c->n_sites ? (double)st.site_entries / c->n_sites : 0.0;
+    c->auto_la = next_pow2_clamped(avg_a / 4.0, 1, 32);
+    c->auto_lb = next_pow2_clamped((avg_a + avg_s) / 4.0, 1, 64);
+    c->built = true;
+    return RELRES_OK;
+}
+
+int relres_set_launch(relres_ctx* c, int lanes_atom, int lanes_site)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    for (int v : {lanes_atom, lanes_site})
+        if (v < 0 || v > 64 || (v & (v - 1)))
+            return fail(RELRES_ERR_ARG, "lanes per row must be 0 (automatic) or a power of two <= 64");
+    c->lanes_a = lanes_atom;
+    c->lanes_b = lanes_site;
+    return RELRES_OK;
+}
+
+int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy, double* virial,
+                  void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n == 0) {
+        if (energy || virial) HIP_TRY(launch_zero_outputs(energy, virial, s));
+        return RELRES_OK;
+    }
+    if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
+    const bool sites = c->n_sites > 0;
+    const int la = c->lanes_a ? c->lanes_a : c->auto_la;
+    const int lb = c->lanes_b ? c->lanes_b : c->auto_lb;
+    auto blocks = [](long long rows, int lanes) {
+        long long b = (rows * lanes + kForceBlock - 1) / kForceBlock;
+        return (int)((b + 7) / 8 * 8);
+    };
+    ForceArgs a{};
+    a.pos = pos;
+    for (int k = 0; k < 3; ++k) {
+        a.box[k] = c->box[k];
+        a.inv_box[k] = 1.0 / c->box[k];
+    }
+    a.n_arow = c->n;
+    a.a_user = c->ga.user.as<int>();
+    a.a_meta = c->ga.meta.as<int2>();
+    a.a_list = c->ga.list.as<int>();
+    a.a_nrow = c->ga.nrow.as<int>();
+    a.a_cap = c->ga.cap;
+    a.n_srow = sites ? c->n_sites : 0;
+    if (sites) {
+        a.s_user = c->gs.user.as<int>();
+        a.s_meta = c->gs.meta.as<int2>();
+        a.s_list = c->gs.list.as<int>();
+        a.s_nrow = c->gs.nrow.as<int>();
+        a.s_cap = c->gs.cap;
+        a.s_arow = c->d_s_arow.as<int>();
+    }
+    a.hybrid = c->d_hybrid.as<int>();
+    a.coef32 = c->d_coef32.p;
+    a.coef64 = c->d_coef64.p;
+    a.ntypes = c->ntypes;
+    a.forces = forces;
+    a.energy = energy;
+    a.virial = virial;
+    a.blocks_a = blocks(c->n, la);
+    a.blocks_b = sites ? blocks(c->n_sites, lb) : 0;
+    a.lanes_a = la;
+    a.lanes_b = lb;
+    a.log_lanes_a = log2i(la);
+    a.log_lanes_b = log2i(lb);
+    TRY(ensure(c->d_partials, sizeof(double) * 8 * (size_t)(a.blocks_a + a.blocks_b)));
+    a.partials = c->d_partials.as<double>();
+    a.counter = c->d_counter.as<unsigned int>();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        TRY(take_events(c, e0, e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    HIP_TRY(launch_forces(a, c->cut64, c->pair_math, c->precision, energy || virial, s));
+    if (c->timing) {
+        HIP_TRY(hipEventRecord(e1, s));
+        c->ev_force.push_back({e0, e1});
+    }
+    return RELRES_OK;
+}
+
+int relres_list_stats(relres_ctx* c, relres_stats* out)
+{
+    if (!c || !out) return fail(RELRES_ERR_ARG, "NULL argument");
+    *out = c->stats;
+    return RELRES_OK;
+}
+
+int relres_get_pairs(relres_ctx* c, int which, int* pairs_host, long long cap, long long* n_out)
+{
+    if (!c || !n_out) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (which != RELRES_LIST_ATOM && which != RELRES_LIST_SITE)
+        return fail(RELRES_ERR_ARG, "which must be RELRES_LIST_ATOM or RELRES_LIST_SITE");
+    if (cap > 0 && !pairs_host) return fail(RELRES_ERR_ARG, "pairs_host is NULL");
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists");
+    *n_out = 0;
+    const bool site = which == RELRES_LIST_SITE;
+    if (c->n == 0 || (site && c->n_sites == 0)) return RELRES_OK;
+    GridHost& g = site ? c->gs : c->ga;
+    const int rows = g.members;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<int> nrow(rows), user(rows), list((size_t)rows * g.cap);
+    HIP_TRY(hipMemcpy(nrow.data(), g.nrow.p, sizeof(int) * rows, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(user.data(), g.user.p, sizeof(int) * rows, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(list.data(), g.list.p, sizeof(int) * list.size(), hipMemcpyDeviceToHost));
+    std::vector<std::pair<int, int>> pr;
+    for (int r = 0; r < rows; ++r) {
+        const int ui = user[r];
+        const int cnt = std::min(nrow[r], g.cap);
+        for (int k = 0; k < cnt; ++k) {
+            const int uj = (int)((uint32_t)list[(size_t)r * g.cap + k] & kIdxMask);
+            if (ui < uj) pr.push_back({ui, uj});
+        }
+    }
+    std::sort(pr.begin(), pr.end());
+    *n_out = (long long)pr.size();
+    const long long w = std::min<long long>(cap, (long long)pr.size());
+    for (long long k = 0; k < w; ++k) {
+        pairs_host[2 * k] = pr[k].first;
+        pairs_host[2 * k + 1] = pr[k].second;
+    }
+    return RELRES_OK;
+}
+
+int relres_set_timing(relres_ctx* c, int enable)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    c->timing = enable != 0;
+    return RELRES_OK;
+}
+
+int relres_get_timing(relres_ctx* c, double* force_ms, long long* force_calls, double* build_ms,
+                      long long* build_calls)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    for (auto* v : {&c->ev_force, &c->ev_build}) {
+        for (auto& pr : *v) {
+            HIP_TRY(hipEventSynchronize(pr.second));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+            if (v == &c->ev_force) { c->force_ms += ms; c->force_calls++; }
+            else { c->build_ms += ms; c->build_calls++; }
+            c->ev_free.push_back(pr.first);
+            c->ev_free.push_back(pr.second);
+        }
+        v->clear();
+    }
+    if (force_ms) *force_ms = c->force_ms;
+    if (force_calls) *force_calls = c->force_calls;
+    if (build_ms) *build_ms = c->build_ms;
+    if (build_calls) *build_calls = c->build_calls;
+    c->force_ms = c->build_ms = 0.0;
+    c->force_calls = c->build_calls = 0;
+    return RELRES_OK;
+}
+
+void relres_destroy(relres_ctx* c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
+                    &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
+                    &c->d_user2arow, &c->d_s_arow, &c->d_status, &c->d_partials, &c->d_counter})
+        release(*b);
+    for (GridHost* g : {&c->ga, &c->gs})
+        for (DBuf* b : {&g->rank_of_lin, &g->lin_of_rank, &g->count, &g->start, &g->user_unsorted,
+                        &g->user, &g->pos, &g->meta, &g->list, &g->nrow})
+            release(*b);
+    if (c->h_grids) (void)hipHostFree(c->h_grids);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->h_zero) (void)hipHostFree(c->h_zero);
+    for (auto* v : {&c->ev_force, &c->ev_build})
+        for (auto& pr : *v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

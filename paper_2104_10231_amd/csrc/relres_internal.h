@@ -1,0 +1,139 @@
+// relres_internal.h -- data layout shared by the host API (relres_host.cpp)
+// and the gfx950 kernels (relres_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace relres {
+
+// A list entry packs the caller index of the neighbour (27 bits) and its atom
+// type (5 bits), so the force kernel needs no separate type gather.
+constexpr int kIdxBits = 27;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+
+// Per-type-pair coefficients of Eq. 20, split into the part carried by the FG
+// potential (non-zero on [0, r_s+)) and the part carried by the CG potential
+// (non-zero on [0, r_c+), hybrid pairs only).  With delta = r - r_-:
+//   FG:  r <  r_s-        u_FG(r)            - f_s-^FG(Dr_s)
+//        r in [r_s-,r_s+) f_s-^FG(delta)     - f_s-^FG(Dr_s)
+//   CG:  r <  r_s-        gamma_0+^CG        - Gamma_c-      (no force)
+//        r in [r_s-,r_s+) f_s+^CG(delta)     - Gamma_c-
+//        r in [r_s+,r_c-) u_CG(r)            - Gamma_c-
+//        r in [r_c-,r_c+) f_c-^CG(delta)     - Gamma_c-
+// Summed, the two parts reproduce every case of Eq. 20 with the constants of
+// Eq. 19 (Gamma_s+ = Gamma_c- + f_s-^FG(Dr_s), Gamma_s- = Gamma_s+ - gamma_0+).
+// LJ terms use  -u'(r)/r = r^-8 (c12 r^-6 - c6),  u(r) = r^-6 (e12 r^-6 - e6)
+// with c12 = 48 eps sig^12, c6 = 24 eps sig^6, e12 = 4 eps sig^12, e6 = 4 eps sig^6.
+template <typename S>
+struct PairCoef {
+    S fg_c12, fg_c6, fg_e12, fg_e6;
+    S fg_g[5];          // f_s-^FG coefficients gamma_0- .. gamma_4-
+    S fg_shift;         // f_s-^FG(Dr_s)
+    S cg_c12, cg_c6, cg_e12, cg_e6;
+    S sp_g0, sp_g3, sp_g4;  // f_s+^CG: gamma_0+, gamma_3+, gamma_4+ (gamma_1+ = gamma_2+ = 0)
+    S cm_g[5];          // f_c-^CG coefficients
+    S cm_shift;         // Gamma_c-
+    S pad;
+};
+
+template <typename S>
+struct Cutoffs {
+    S rsi, rso, rci, rco;        // r_s-, r_s+, r_c-, r_c+
+    S rsi2, rso2, rci2, rco2;    // their squares
+};
+
+// One cell grid with its sorted members and its neighbour list.  Members of
+// the atom grid are all atoms; members of the site grid are the hybrid atoms.
+struct GridDev {
+    int n[3];                 // cells per axis
+    int ncell;
+    double inv_cell[3];       // n_k / L_k
+    int noff[3];              // distinct stencil offsets per axis (1..3)
+    int off[3][3];
+    double rl2;               // list radius squared (membership test)
+    int members;
+    int cap;                  // row capacity of the padded list
+    const int* rank_of_lin;   // Morton rank of a linear cell index
+    const int* lin_of_rank;
+    int* count;               // per cell (by rank); zero between builds
+    int* start;               // ncell + 1 exclusive offsets (by rank)
+    int* user_unsorted;       // member caller indices, cell-grouped
+    int* user;                // member caller indices, cell-grouped, ascending in a cell
+    double4* pos;             // wrapped positions of members (w unused)
+    int2* meta;               // (type, molecule) of members
+    int* list;                // rows x cap entries
+    int* nrow;                // entries per row (true count, may exceed cap)
+};
+
+struct TopoDev {
+    const int* types;
+    const int* mol;
+    const int* hybrid;        // per type: 1 if eps_cg > 0
+    const int* excl_off;      // CSR (caller indices), symmetrised; may be null
+    const int* excl_idx;
+    int same_mol;
+    int n;
+};
+
+struct Status {
+    int nonfinite;
+    int max_row[2];
+    int pad;
+    unsigned long long entries[2];
+};
+
+struct ForceArgs {
+    const double* pos;        // caller positions, N x 3
+    double box[3];
+    double inv_box[3];
+    // atom list rows (all atoms, atom-grid order)
+    int n_arow;
+    const int* a_user;
+    const int2* a_meta;
+    const int* a_list;
+    const int* a_nrow;
+    int a_cap;
+    // site list rows (hybrid atoms, site-grid order)
+    int n_srow;
+    const int* s_user;
+    const int2* s_meta;
+    const int* s_list;
+    const int* s_nrow;
+    int s_cap;
+    const int* s_arow;        // atom-list row of each site row
+    const int* hybrid;        // per type
+    const void* coef32;       // PairCoef<float>[ntypes * ntypes]
+    const void* coef64;       // PairCoef<double>[ntypes * ntypes]
+    int ntypes;
+    void* forces;             // N x 3 of TF, caller order
+    double* energy;           // [3] or null
+    double* virial;           // [6] or null
+    double* partials;         // 8 per block
+    unsigned int* counter;    // last-block ticket, zero between launches
+    int blocks_a, blocks_b;   // multiples of 8
+    int lanes_a, lanes_b;     // lanes per row (powers of two)
+    int log_lanes_a, log_lanes_b;
+};
+
+// Launchers (relres_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_bin(int n, const double* pos, const double box[3], TopoDev topo,
+                      GridDev* grids_dev, double4* wpos, int2* key_a, int2* key_s, Status* st,
+                      hipStream_t s);
+hipError_t launch_scan(GridDev* grids_dev, int ngrids, hipStream_t s);
+hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
+                          hipStream_t s);
+hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,
+                           TopoDev topo, int* user2arow, hipStream_t s);
+hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, TopoDev topo,
+                        const double box[3], const int* user2arow, int* s_arow,
+                        Status* st, hipStream_t s);
+// cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares}
+hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
+                         bool ew, hipStream_t s);
+hipError_t launch_zero_outputs(double* energy, double* virial, hipStream_t s);
+
+constexpr int kForceBlock = 256;
+constexpr int kListBlock = 256;
+
+}  // namespace relres

@@ -1,0 +1,241 @@
+"""Thin Python binding of the RelRes C ABI (include/relres.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP library
+``librelres_hip.so`` built in-tree for gfx950.  PyTorch provides device memory
+and the current stream.  There is no CPU fallback: without the built library,
+or without a GPU, constructing :class:`RelRes` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librelres_hip.so")
+
+RELRES_OK = 0
+MIX_GEOMETRIC = 0
+MIX_ARITHMETIC = 1
+LIST_ATOM = 0
+LIST_SITE = 1
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rs_in", ctypes.c_double), ("rs_out", ctypes.c_double),
+                ("rc_in", ctypes.c_double), ("rc_out", ctypes.c_double),
+                ("skin", ctypes.c_double), ("ntypes", ctypes.c_int),
+                ("eps_fg", _c_double_p), ("sig_fg", _c_double_p),
+                ("eps_cg", _c_double_p), ("sig_cg", _c_double_p),
+                ("mix", ctypes.c_int), ("precision", ctypes.c_int),
+                ("pair_math", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_longlong), ("n_sites", ctypes.c_longlong),
+                ("atom_entries", ctypes.c_longlong), ("site_entries", ctypes.c_longlong),
+                ("atom_max_row", ctypes.c_int), ("site_max_row", ctypes.c_int),
+                ("atom_capacity", ctypes.c_int), ("site_capacity", ctypes.c_int),
+                ("atom_cells", ctypes.c_int * 3), ("site_cells", ctypes.c_int * 3),
+                ("builds", ctypes.c_longlong), ("regrows", ctypes.c_longlong),
+                ("box", ctypes.c_double * 3)]
+
+
+# exported symbol -> (restype, argtypes); mirrors include/relres.h
+SIGNATURES = {
+    "relres_abi_version": (ctypes.c_int, []),
+    "relres_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "relres_last_error": (ctypes.c_char_p, []),
+    "relres_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
+    "relres_set_topology": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "relres_build_lists": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
+                                          ctypes.c_void_p]),
+    "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "relres_list_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "relres_get_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
+    "relres_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "relres_get_timing": (ctypes.c_int, [ctypes.c_void_p, _c_double_p,
+                                         ctypes.POINTER(ctypes.c_longlong), _c_double_p,
+                                         ctypes.POINTER(ctypes.c_longlong)]),
+    "relres_destroy": (None, [ctypes.c_void_p]),
+}
+
+_LIB = None
+
+
+class RelResError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (code {code})")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built HIP library; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"RelRes HIP library not built: {path} missing "
+                          "(run __graft_entry__.build() or paper_2104_10231_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != RELRES_OK:
+        lib = load_library()
+        raise RelResError(rc, where, lib.relres_last_error().decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32(a) -> Optional[np.ndarray]:
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a) -> Optional[int]:
+    return None if a is None else a.ctypes.data
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class RelRes:
+    """One RelRes LJ evaluator bound to the current GPU.
+
+    Parameters follow Sec. 2.5 of the paper (pair_style lj/relres r_s- r_s+
+    r_c- r_c+ with per-type FG/CG epsilon and sigma); ``eps_cg == 0`` marks an
+    ordinary type.  ``precision`` is the force type (32 or 64), ``pair_math``
+    the type of the per-pair terms (0 = same as precision).
+    """
+
+    def __init__(self, *, rs_in: float, rs_out: float, rc_in: float, rc_out: float,
+                 skin: float, eps_fg: Sequence[float], sig_fg: Sequence[float],
+                 eps_cg: Sequence[float], sig_cg: Sequence[float], mix: int = MIX_GEOMETRIC,
+                 precision: int = 32, pair_math: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("RelRes needs a ROCm GPU; none is visible")
+        self._lib = load_library()
+        self._arrays = [_f64(eps_fg), _f64(sig_fg), _f64(eps_cg), _f64(sig_cg)]
+        nt = len(self._arrays[0])
+        p = Params(rs_in, rs_out, rc_in, rc_out, skin, nt,
+                   *[a.ctypes.data_as(_c_double_p) for a in self._arrays],
+                   int(mix), int(precision), int(pair_math))
+        ctx = ctypes.c_void_p()
+        torch.cuda.init()
+        _check(self._lib.relres_create(ctypes.byref(p), ctypes.byref(ctx)), "relres_create")
+        self._ctx = ctx
+        self.precision = int(precision)
+        self.n = 0
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    # -- topology ----------------------------------------------------------
+    def set_topology(self, types, mol=None, exclude_same_mol: bool = True,
+                     excl_offsets=None, excl_idx=None):
+        t = _i32(types)
+        m = _i32(mol)
+        eo = _i32(excl_offsets) if excl_idx is not None and len(excl_idx) else None
+        ei = _i32(excl_idx) if eo is not None else None
+        _check(self._lib.relres_set_topology(self._ctx, int(t.shape[0]), _ptr(t), _ptr(m),
+                                             int(bool(exclude_same_mol)), _ptr(eo), _ptr(ei)),
+               "relres_set_topology")
+        self.n = int(t.shape[0])
+
+    # -- hot path ------------------------------------------------------------
+    def _pos(self, pos: torch.Tensor) -> torch.Tensor:
+        if pos.dtype != torch.float64 or pos.device.type != "cuda" or not pos.is_contiguous():
+            raise TypeError("pos must be a contiguous float64 CUDA tensor of shape (N, 3)")
+        if tuple(pos.shape) != (self.n, 3):
+            raise ValueError(f"pos has shape {tuple(pos.shape)}, expected ({self.n}, 3)")
+        return pos
+
+    def build_lists(self, pos: torch.Tensor, box, stream=None):
+        pos = self._pos(pos)
+        b = (ctypes.c_double * 3)(*[float(x) for x in box])
+        _check(self._lib.relres_build_lists(self._ctx, pos.data_ptr() if self.n else None, b,
+                                            _stream(stream)), "relres_build_lists")
+
+    def forces(self, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
+               energy: Optional[torch.Tensor] = None, virial: Optional[torch.Tensor] = None,
+               want_energy: bool = True, want_virial: bool = True, stream=None):
+        """Return (forces, energy[3], virial[6]); outputs may be given to reuse."""
+        pos = self._pos(pos)
+        dt = torch.float64 if self.precision == 64 else torch.float32
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=dt, device=pos.device)
+        elif out.dtype != dt or tuple(out.shape) != (self.n, 3) or not out.is_contiguous():
+            raise TypeError("out must be a contiguous (N, 3) tensor of the force dtype")
+        if want_energy and energy is None:
+            energy = torch.empty(3, dtype=torch.float64, device=pos.device)
+        if want_virial and virial is None:
+            virial = torch.empty(6, dtype=torch.float64, device=pos.device)
+        _check(self._lib.relres_forces(self._ctx, pos.data_ptr() if self.n else None,
+                                       out.data_ptr() if self.n else None,
+                                       energy.data_ptr() if energy is not None else None,
+                                       virial.data_ptr() if virial is not None else None,
+                                       _stream(stream)), "relres_forces")
+        return out, energy, virial
+
+    # -- inspection ------------------------------------------------------------
+    def set_launch(self, lanes_atom: int = 0, lanes_site: int = 0):
+        _check(self._lib.relres_set_launch(self._ctx, int(lanes_atom), int(lanes_site)),
+               "relres_set_launch")
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.relres_list_stats(self._ctx, ctypes.byref(s)), "relres_list_stats")
+        d = {k: getattr(s, k) for k, _ in Stats._fields_}
+        for k in ("atom_cells", "site_cells", "box"):
+            d[k] = list(d[k])
+        return d
+
+    def pairs(self, which: int) -> np.ndarray:
+        n = ctypes.c_longlong()
+        _check(self._lib.relres_get_pairs(self._ctx, int(which), None, 0, ctypes.byref(n)),
+               "relres_get_pairs")
+        out = np.zeros((max(1, n.value), 2), np.int32)
+        _check(self._lib.relres_get_pairs(self._ctx, int(which), out.ctypes.data, n.value,
+                                          ctypes.byref(n)), "relres_get_pairs")
+        return out[: n.value]
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.relres_set_timing(self._ctx, int(bool(enable))), "relres_set_timing")
+
+    def timing(self) -> dict:
+        fm, bm = ctypes.c_double(), ctypes.c_double()
+        fc, bc = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(self._lib.relres_get_timing(self._ctx, ctypes.byref(fm), ctypes.byref(fc),
+                                           ctypes.byref(bm), ctypes.byref(bc)), "relres_get_timing")
+        return dict(force_ms=fm.value, force_calls=fc.value, build_ms=bm.value,
+                    build_calls=bc.value)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.relres_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (see the design doc for their derivation):
+  * neighbour pair sets: bit-exact (same FP64 membership decision on both sides);
+  * FP64 path: forces within 1e-11 relative RMS, energy and virial within 1e-12;
+  * FP32 path: forces within 1e-5 relative RMS, energy and virial (accumulated
+    in FP64) within 1e-7 relative.
+Relative RMS = ||F_gpu - F_ref||_2 / ||F_ref||_2 over all 3N components; the
+virial error is max_k |W_k - W_ref,k| / max_k |W_ref,k|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from _util import gpu_run, make_relres, pair_set, rel_err, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: (1e-11, 1e-12), 32: (1e-5, 1e-7)}
+
+
+def _check(s, precision, pair_math=0, pos=None, build_pos=None, lanes=None, pairs=True,
+           ref=None, fscale=0.0, escale=0.0):
+    """fscale/escale: magnitudes of the pair terms for results that are
+    themselves near zero (an isolated pair near a zone end); the errors are
+    then measured against max(|result|, scale)."""
+    print(f"[parity] {s.name} N={s.n} precision={precision} pair_math={pair_math} "
+          f"lanes={lanes}", flush=True)
+    rr, F, E, W = gpu_run(s, precision, pair_math, pos=pos, build_pos=build_pos, lanes=lanes)
+    sp = s if pos is None else s.replace(pos=pos)
+    Fr, Er, Wr = oracle.compute(sp) if ref is None else ref
+    ftol, etol = TOL[precision]
+    if pairs:
+        sb = s if build_pos is None else s.replace(pos=build_pos)
+        for which in (0, 1):
+            got, want = pair_set(rr.pairs(which)), pair_set(oracle.pairs(sb, which))
+            assert got == want, f"list {which}: {len(got - want)} extra, {len(want - got)} missing"
+    fden = max(np.sqrt(np.sum(Fr * Fr)), fscale)
+    if fden > 0:
+        assert np.sqrt(np.sum((F - Fr) ** 2)) <= ftol * fden, rel_rms(F, Fr)
+    else:
+        assert np.all(F == 0.0)
+    eden = max(abs(Er[0]), escale)
+    if eden > 0:
+        assert abs(E[0] - Er[0]) <= etol * eden, (E, Er)
+        scale = max(abs(Er[1]), abs(Er[2]), eden)
+        assert abs(E[1] - Er[1]) <= etol * scale and abs(E[2] - Er[2]) <= etol * scale
+    else:
+        assert np.all(E == 0.0)
+    wden = max(np.abs(Wr).max(), fscale * float(np.max(s.box)))
+    if wden > 0:
+        assert np.abs(W - Wr).max() <= etol * wden, rel_err(W, Wr)
+    rr.close()
+    return F, E, W
+
+
+# ---------------------------------------------------------------------------
+# the three workloads
+# ---------------------------------------------------------------------------
+
+def test_propane_1500_fp64():
+    _check(w.propane_liquid(0), 64)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_propane_1500_fp32(seed):
+    _check(w.propane_liquid(seed).replace(precision=32), 32)
+
+
+@pytest.mark.parametrize("pair_math", [32, 64])
+def test_neopentane_20480_fp32(pair_math):
+    _check(w.neopentane_liquid(0), 32, pair_math=pair_math)
+
+
+def test_neopentane_20480_conventional():
+    s = w.neopentane_liquid(0).conventional()
+    _check(s, 32)
+
+
+@pytest.mark.slow
+def test_copolymer_98304_sampled():
+    s = w.copolymer_melt(0)
+    print(f"[parity] copolymer N={s.n} (sampled rows and forces)", flush=True)
+    rr, F, E, W = gpu_run(s, 32)
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(s.n, size=1500, replace=False)).astype(np.int32)
+    hyb = np.nonzero(np.isin(s.types, [1, 3]))[0]
+    srows = np.sort(rng.choice(hyb, size=500, replace=False)).astype(np.int32)
+    for which, r in ((0, rows), (1, srows)):
+        ref = oracle.pairs(s, which, rows=r)
+        gp = rr.pairs(which)
+        got = set()
+        rs = set(r.tolist())
+        for i, j in gp.tolist():
+            if i in rs:
+                got.add((i, j))
+            if j in rs:
+                got.add((j, i))
+        assert got == pair_set(ref), which
+    Fs = oracle.compute(s, sel=rows)[0]
+    assert rel_rms(F[rows], Fs) <= 1e-5, rel_rms(F[rows], Fs)
+    st = rr.stats()
+    assert st["n_sites"] == 24576
+    rr.close()
+
+
+@pytest.mark.slow
+def test_copolymer_98304_energy_virial():
+    s = w.copolymer_melt(0)
+    print(f"[parity] copolymer N={s.n} full energy/virial", flush=True)
+    rr, F, E, W = gpu_run(s, 32, pair_math=64)
+    Fr, Er, Wr = oracle.compute(s)
+    assert rel_rms(F, Fr) <= 1e-5
+    assert abs(E[0] - Er[0]) <= 1e-7 * abs(Er[0])
+    assert rel_err(W, Wr) <= 1e-7
+    rr.close()
+
+
+# ---------------------------------------------------------------------------
+# small systems spanning several tiles, ragged tails and all regimes
+# ---------------------------------------------------------------------------
+
+SMALL = [("propane", 3, 150, 0.8), ("propane", 4, 97, 1.0), ("neopentane", 5, 61, 0.7),
+         ("propane", 6, 130, 0.0), ("neopentane", 7, 40, 1.0)]
+
+
+@pytest.mark.parametrize("kind,seed,n_mol,hf", SMALL)
+@pytest.mark.parametrize("precision", [64, 32])
+def test_small_random_systems(kind, seed, n_mol, hf, precision):
+    s = w.random_molecules(seed, n_mol, 34.0, kind=kind, min_dist=2.9, hybrid_fraction=hf,
+                           precision=precision)
+    _check(s, precision)
+
+
+@pytest.mark.parametrize("lanes", [(1, 1), (2, 4), (4, 8), (8, 16), (16, 32), (32, 64), (64, 64)])
+def test_every_lane_split_gives_the_same_physics(lanes):
+    s = w.random_molecules(8, 140, 36.0, kind="propane", min_dist=2.9, hybrid_fraction=0.9)
+    _check(s, 64, lanes=lanes)
+
+
+def test_lorentz_berthelot_and_csr_exclusions():
+    s = w.random_molecules(9, 120, 35.0, kind="neopentane", min_dist=2.9, hybrid_fraction=0.8)
+    # exclude only pairs of consecutive atoms inside a molecule, as explicit lists
+    offs, lst = [0], []
+    for i in range(s.n):
+        part = [j for j in (i - 1, i + 1) if 0 <= j < s.n and s.mol[j] == s.mol[i]]
+        lst += part
+        offs.append(len(lst))
+    s = s.replace(exclude_same_mol=False, excl_offsets=np.array(offs, np.int32),
+                  excl_idx=np.array(lst, np.int32), mix=w.MIX_ARITHMETIC,
+                  eps_fg=np.array([0.15, 0.07]), sig_fg=np.array([3.9, 3.6]),
+                  eps_cg=np.array([0.0, 2.5]), sig_cg=np.array([3.9, 4.1]))
+    _check(s, 64)
+    _check(s.replace(precision=32), 32)
+
+
+def test_non_cubic_box_and_unwrapped_positions():
+    s = w.random_molecules(10, 130, 34.0, kind="propane", min_dist=2.9)
+    box = np.array([34.0, 41.5, 37.25])
+    pos = w.wrap(s.pos * (box / 34.0), box)
+    s = s.replace(pos=pos, box=box)
+    k = np.random.default_rng(2).integers(-1, 2, size=pos.shape)
+    _check(s, 64, pos=pos + k * box, build_pos=pos + k * box)
+
+
+def test_moved_positions_use_build_lists():
+    """Forces at positions moved by less than skin/2 since the build are exact."""
+    s = w.random_molecules(12, 130, 34.0, kind="propane", min_dist=2.9)
+    moved = s.pos + np.random.default_rng(4).normal(scale=0.15, size=s.pos.shape)
+    _check(s, 64, pos=moved, build_pos=s.pos, pairs=False)
+
+
+def test_list_regrow_on_a_dense_cluster():
+    # molecules packed into a corner of a large box: far above the mean density
+    s = w.random_molecules(13, 90, 22.0, kind="propane", min_dist=2.9)
+    big = s.replace(pos=s.pos + 1.0, box=np.full(3, 60.0))
+    rr, F, E, W = gpu_run(big, 64)
+    st = rr.stats()
+    assert st["regrows"] >= 1 and st["atom_capacity"] >= st["atom_max_row"]
+    Fr, Er, Wr = oracle.compute(big)
+    assert rel_rms(F, Fr) <= 1e-11 and abs(E[0] - Er[0]) <= 1e-12 * abs(Er[0])
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(big, which))
+    rr.close()
+
+
+def test_repeated_calls_are_bitwise_identical():
+    import torch
+    s = w.neopentane_liquid(1)
+    rr = make_relres(s)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)
+    a = [t.clone() for t in rr.forces(p)]
+    rr.build_lists(p, s.box)
+    b = rr.forces(p)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    rr.close()
+
+
+# ---------------------------------------------------------------------------
+# degenerate cases and errors
+# ---------------------------------------------------------------------------
+
+def test_empty_system():
+    import torch
+    s = w.two_atoms(5.0)
+    s = s.replace(pos=np.zeros((0, 3)), types=np.zeros(0, np.int32), mol=np.zeros(0, np.int32),
+                  excl_offsets=np.zeros(1, np.int32))
+    rr = make_relres(s)
+    p = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    rr.build_lists(p, s.box)
+    F, E, W = rr.forces(p)
+    assert F.shape == (0, 3) and torch.all(E == 0) and torch.all(W == 0)
+    assert len(rr.pairs(0)) == 0 and len(rr.pairs(1)) == 0
+    rr.close()
+
+
+@pytest.mark.parametrize("r", [3.1, 5.7, 5.9999, 6.0, 8.5, 12.0, 13.2, 14.5, 15.99])
+@pytest.mark.parametrize("hyb", [(True, True), (True, False), (False, False)])
+def test_two_atoms_every_regime(r, hyb):
+    s = w.two_atoms(r, hybrid=hyb, direction=(1.0, 2.0, -0.5))
+    rec = oracle.setup_table(s)[s.types[0], s.types[1]]
+    near = np.linspace(max(0.5, r - 0.5), r + 0.5, 201)
+    u, du = oracle.pair(rec, oracle.cutoffs(s), near)[:2]
+    _check(s, 64, fscale=float(np.abs(du).max()), escale=float(np.abs(u).max()))
+
+
+def test_single_molecule_and_all_ordinary():
+    s = w.random_molecules(14, 1, 34.0, kind="neopentane")
+    F, E, W = _check(s, 64)
+    assert np.all(F == 0.0) and np.all(E == 0.0)
+    s2 = w.random_molecules(15, 150, 34.0, kind="propane", hybrid_fraction=0.0)
+    _check(s2, 32)
+
+
+def test_errors_are_reported():
+    import torch
+    from paper_2104_10231_amd.relres import RelResError
+    s = w.random_molecules(16, 10, 34.0)
+    rr = make_relres(s)
+    p = torch.from_numpy(s.pos).cuda()
+    with pytest.raises(RelResError) as e:
+        rr.forces(p)
+    assert e.value.code == -6
+    with pytest.raises(RelResError) as e:
+        rr.build_lists(p, [31.0, 34.0, 34.0])
+    assert e.value.code == -3
+    bad = p.clone()
+    bad[3, 1] = float("nan")
+    with pytest.raises(RelResError) as e:
+        rr.build_lists(bad, s.box)
+    assert e.value.code == -8
+    with pytest.raises(RelResError) as e:
+        rr.set_topology(np.full(s.n, 5, np.int32), s.mol)
+    assert e.value.code == -4
+    rr.close()
