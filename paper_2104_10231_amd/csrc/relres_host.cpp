@@ -168,14 +168,19 @@ struct relres_ctx {
     DBuf d_types, d_mol, d_excl_off, d_excl_idx;
 
     GridHost ga, gs;
-    DBuf d_grids, d_wpos, d_key_a, d_key_s, d_user2arow, d_s_arow, d_status;
-    GridDev* h_grids = nullptr;
+    DBuf d_grids, d_wpos, d_key_a, d_key_s, d_user2arow, d_a_rec, d_s_rec, d_status;
+    GridDev* h_grids = nullptr;       // pinned staging of the device descriptors
+    GridDev uploaded[2] = {};         // descriptors currently on the device
+    bool grids_valid = false;
     Status* h_status = nullptr;
     Status* h_zero = nullptr;
+    int nonfinite_seen = 0;
+    int max_row[2] = {0, 0};          // reduced list statistics of the last build
+    long long entries[2] = {0, 0};
     bool built = false;
     double box[3] = {0, 0, 0};
 
-    DBuf d_partials, d_counter;
+    DBuf d_partials;
     int lanes_a = 0, lanes_b = 0;        // caller override, 0 = automatic
     int auto_la = 4, auto_lb = 16;
 
@@ -323,21 +328,43 @@ TopoDev topo_of(relres_ctx* c)
     return t;
 }
 
+// Copy the grid descriptors to the device when they changed since the last
+// upload (new box, cell counts, capacities or buffers).  The staging buffer is
+// reused only after the stream has been synchronised (every build ends so).
 int upload_grids(relres_ctx* c, hipStream_t s)
 {
-    c->h_grids[0] = c->ga.dev;
-    c->h_grids[1] = c->n_sites > 0 ? c->gs.dev : c->ga.dev;
-    HIP_TRY(hipMemcpyAsync(c->d_grids.p, c->h_grids, 2 * sizeof(GridDev), hipMemcpyHostToDevice, s));
+    GridDev want[2] = {c->ga.dev, c->n_sites > 0 ? c->gs.dev : c->ga.dev};
+    if (c->grids_valid && std::memcmp(want, c->uploaded, sizeof want) == 0) return RELRES_OK;
+    std::memcpy(c->h_grids, want, sizeof want);
+    HIP_TRY(hipMemcpyAsync(c->d_grids.p, c->h_grids, sizeof want, hipMemcpyHostToDevice, s));
+    std::memcpy(c->uploaded, want, sizeof want);
+    c->grids_valid = true;
     return RELRES_OK;
+}
+
+void reduce_status(relres_ctx* c)
+{
+    for (int g = 0; g < 2; ++g) {
+        int m = 0;
+        long long e = 0;
+        for (int k = 0; k < kStatSlots; ++k) {
+            m = std::max(m, c->h_status->max_row[g][k]);
+            e += (long long)c->h_status->entries[g][k];
+        }
+        c->max_row[g] = m;
+        c->entries[g] = e;
+    }
 }
 
 int run_lists(relres_ctx* c, hipStream_t s)
 {
     TRY(upload_grids(c, s));
+    // only the list statistics are cleared; the non-finite counter is cumulative
+    c->h_zero->nonfinite = c->h_status->nonfinite;
     HIP_TRY(hipMemcpyAsync(c->d_status.p, c->h_zero, sizeof(Status), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_lists(c->d_grids.as<GridDev>(), c->ga.ncell, c->n_sites > 0 ? c->gs.ncell : 0,
-                         topo_of(c), c->box, c->d_user2arow.as<int>(), c->d_s_arow.as<int>(),
-                         c->d_status.as<Status>(), s));
+                         topo_of(c), c->box, c->d_user2arow.as<int>(), c->d_a_rec.as<int4>(),
+                         c->d_s_rec.as<int4>(), c->d_status.as<Status>(), s));
     HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RELRES_OK;
@@ -464,13 +491,12 @@ int relres_create(const relres_params* p, relres_ctx** out)
     if ((rc = ensure(c->d_hybrid, sizeof(int) * nt))) return bail(rc);
     if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev)))) return bail(rc);
     if ((rc = ensure(c->d_status, sizeof(Status)))) return bail(rc);
-    if ((rc = ensure(c->d_counter, 64))) return bail(rc);
     if (hipMemcpy(c->d_coef64.p, c->coef64.data(), sizeof(PairCoef<double>) * c->coef64.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_coef32.p, coef32.data(), sizeof(PairCoef<float>) * coef32.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_hybrid.p, c->hybrid.data(), sizeof(int) * nt, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->d_counter.p, 0, 64) != hipSuccess)
+        hipMemset(c->d_status.p, 0, sizeof(Status)) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "uploading parameters failed"));
     if (hipHostMalloc((void**)&c->h_grids, 2 * sizeof(GridDev), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
@@ -567,7 +593,8 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
     TRY(ensure(c->d_key_a, sizeof(int2) * c->n));
     TRY(ensure(c->d_key_s, sizeof(int2) * c->n));
     TRY(ensure(c->d_user2arow, sizeof(int) * c->n));
-    TRY(ensure(c->d_s_arow, sizeof(int) * std::max(1, c->n_sites)));
+    TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n)));
+    TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites)));
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -576,39 +603,44 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
     }
     if (c->n > 0) {
         TRY(upload_grids(c, s));
-        HIP_TRY(hipMemcpyAsync(c->d_status.p, c->h_zero, sizeof(Status), hipMemcpyHostToDevice, s));
         const TopoDev topo = topo_of(c);
         GridDev* gd = c->d_grids.as<GridDev>();
         HIP_TRY(launch_bin(c->n, pos, box, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
                            c->d_key_s.as<int2>(), c->d_status.as<Status>(), s));
-        HIP_TRY(launch_scan(gd, sites ? 2 : 1, s));
+        HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
         HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
                                 c->d_user2arow.as<int>(), s));
         HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, topo, box, c->d_user2arow.as<int>(),
-                             c->d_s_arow.as<int>(), c->d_status.as<Status>(), s));
+                             c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
+                             c->d_status.as<Status>(), s));
         HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
         if (c->timing) HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (c->h_status->nonfinite) return fail(RELRES_ERR_NONFINITE, "non-finite position");
+        if (c->h_status->nonfinite != c->nonfinite_seen) {
+            c->nonfinite_seen = c->h_status->nonfinite;
+            return fail(RELRES_ERR_NONFINITE, "non-finite position");
+        }
         // grow rows that overflowed and rebuild the lists (positions stay sorted)
         for (int attempt = 0; attempt < 3; ++attempt) {
-            const bool ov_a = c->h_status->max_row[0] > c->ga.cap;
-            const bool ov_s = sites && c->h_status->max_row[1] > c->gs.cap;
+            reduce_status(c);
+            const bool ov_a = c->max_row[0] > c->ga.cap;
+            const bool ov_s = sites && c->max_row[1] > c->gs.cap;
             if (!ov_a && !ov_s) break;
             if (attempt == 2) return fail(RELRES_ERR_LIST_OVERFLOW, "list capacity did not converge");
             if (ov_a) {
-                c->ga.cap = ((int)(c->h_status->max_row[0] * 1.25) + 8 + 7) & ~7;
+                c->ga.cap = ((int)(c->max_row[0] * 1.25) + 8 + 7) & ~7;
                 TRY(setup_grid(c->ga, rla, box, c->n));
             }
             if (ov_s) {
-                c->gs.cap = ((int)(c->h_status->max_row[1] * 1.25) + 8 + 7) & ~7;
+                c->gs.cap = ((int)(c->max_row[1] * 1.25) + 8 + 7) & ~7;
                 TRY(setup_grid(c->gs, rls, box, c->n_sites));
             }
             c->stats.regrows++;
             TRY(run_lists(c, s));
         }
+        reduce_status(c);
     } else if (c->timing) {
         HIP_TRY(hipEventRecord(e1, s));
     }
@@ -617,10 +649,10 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
     relres_stats& st = c->stats;
     st.n_atoms = c->n;
     st.n_sites = c->n_sites;
-    st.atom_entries = c->n ? (long long)c->h_status->entries[0] : 0;
-    st.site_entries = (c->n && sites) ? (long long)c->h_status->entries[1] : 0;
-    st.atom_max_row = c->n ? c->h_status->max_row[0] : 0;
-    st.site_max_row = (c->n && sites) ? c->h_status->max_row[1] : 0;
+    st.atom_entries = c->n ? c->entries[0] : 0;
+    st.site_entries = (c->n && sites) ? c->entries[1] : 0;
+    st.atom_max_row = c->n ? c->max_row[0] : 0;
+    st.site_max_row = (c->n && sites) ? c->max_row[1] : 0;
     st.atom_capacity = c->ga.cap;
     st.site_capacity = sites ? c->gs.cap : 0;
     for (int k = 0; k < 3; ++k) {
@@ -674,21 +706,15 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
         a.inv_box[k] = 1.0 / c->box[k];
     }
     a.n_arow = c->n;
-    a.a_user = c->ga.user.as<int>();
-    a.a_meta = c->ga.meta.as<int2>();
+    a.a_rec = c->d_a_rec.as<int4>();
     a.a_list = c->ga.list.as<int>();
-    a.a_nrow = c->ga.nrow.as<int>();
     a.a_cap = c->ga.cap;
     a.n_srow = sites ? c->n_sites : 0;
     if (sites) {
-        a.s_user = c->gs.user.as<int>();
-        a.s_meta = c->gs.meta.as<int2>();
+        a.s_rec = c->d_s_rec.as<int4>();
         a.s_list = c->gs.list.as<int>();
-        a.s_nrow = c->gs.nrow.as<int>();
         a.s_cap = c->gs.cap;
-        a.s_arow = c->d_s_arow.as<int>();
     }
-    a.hybrid = c->d_hybrid.as<int>();
     a.coef32 = c->d_coef32.p;
     a.coef64 = c->d_coef64.p;
     a.ntypes = c->ntypes;
@@ -703,7 +729,6 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     a.log_lanes_b = log2i(lb);
     TRY(ensure(c->d_partials, sizeof(double) * 8 * (size_t)(a.blocks_a + a.blocks_b)));
     a.partials = c->d_partials.as<double>();
-    a.counter = c->d_counter.as<unsigned int>();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         TRY(take_events(c, e0, e1));
@@ -798,7 +823,7 @@ void relres_destroy(relres_ctx* c)
     (void)hipDeviceSynchronize();
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
-                    &c->d_user2arow, &c->d_s_arow, &c->d_status, &c->d_partials, &c->d_counter})
+                    &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials})
         release(*b);
     for (GridHost* g : {&c->ga, &c->gs})
         for (DBuf* b : {&g->rank_of_lin, &g->lin_of_rank, &g->count, &g->start, &g->user_unsorted,

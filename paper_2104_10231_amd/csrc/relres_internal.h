@@ -76,33 +76,34 @@ struct TopoDev {
     int n;
 };
 
+// Build status read back by the host after every build.  The list statistics
+// are spread over kStatSlots slots (block b uses slot b mod kStatSlots) so
+// that thousands of blocks do not serialise on one address; the host reduces
+// the slots.  They are cleared by k_scan at every build.
+constexpr int kStatSlots = 64;
 struct Status {
-    int nonfinite;
-    int max_row[2];
+    int nonfinite;            // cumulative count of non-finite positions seen
     int pad;
-    unsigned long long entries[2];
+    int max_row[2][kStatSlots];
+    unsigned long long entries[2][kStatSlots];
 };
 
 struct ForceArgs {
     const double* pos;        // caller positions, N x 3
     double box[3];
     double inv_box[3];
-    // atom list rows (all atoms, atom-grid order)
+    // atom list rows (all atoms, atom-grid order); record = (caller index,
+    // type, stored entries, 1 if hybrid)
     int n_arow;
-    const int* a_user;
-    const int2* a_meta;
+    const int4* a_rec;
     const int* a_list;
-    const int* a_nrow;
     int a_cap;
-    // site list rows (hybrid atoms, site-grid order)
+    // site list rows (hybrid atoms, site-grid order); record = (caller index,
+    // type, stored entries, atom-list row of the same atom)
     int n_srow;
-    const int* s_user;
-    const int2* s_meta;
+    const int4* s_rec;
     const int* s_list;
-    const int* s_nrow;
     int s_cap;
-    const int* s_arow;        // atom-list row of each site row
-    const int* hybrid;        // per type
     const void* coef32;       // PairCoef<float>[ntypes * ntypes]
     const void* coef64;       // PairCoef<double>[ntypes * ntypes]
     int ntypes;
@@ -110,7 +111,6 @@ struct ForceArgs {
     double* energy;           // [3] or null
     double* virial;           // [6] or null
     double* partials;         // 8 per block
-    unsigned int* counter;    // last-block ticket, zero between launches
     int blocks_a, blocks_b;   // multiples of 8
     int lanes_a, lanes_b;     // lanes per row (powers of two)
     int log_lanes_a, log_lanes_b;
@@ -120,13 +120,13 @@ struct ForceArgs {
 hipError_t launch_bin(int n, const double* pos, const double box[3], TopoDev topo,
                       GridDev* grids_dev, double4* wpos, int2* key_a, int2* key_s, Status* st,
                       hipStream_t s);
-hipError_t launch_scan(GridDev* grids_dev, int ngrids, hipStream_t s);
+hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);
 hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,
                            TopoDev topo, int* user2arow, hipStream_t s);
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, TopoDev topo,
-                        const double box[3], const int* user2arow, int* s_arow,
+                        const double box[3], const int* user2arow, int4* a_rec, int4* s_rec,
                         Status* st, hipStream_t s);
 // cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares}
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,

@@ -105,34 +105,58 @@ __global__ void k_bin(int n, const double* __restrict__ pos, double Lx, double L
 }
 
 // One block per grid: exclusive scan of the per-cell counts into `start`,
-// then the counts are cleared for the next build.
-__global__ __launch_bounds__(1024) void k_scan(GridDev* __restrict__ grids)
+// then the counts are cleared for the next build.  Counts are staged through
+// LDS in segments of kScanSeg cells with coalesced loads; each thread scans a
+// contiguous run of its segment.  Block 0 also clears the list statistics.
+constexpr int kScanThreads = 1024;
+constexpr int kScanSeg = 8192;
+__global__ __launch_bounds__(kScanThreads) void k_scan(GridDev* __restrict__ grids,
+                                                       Status* __restrict__ st)
 {
-    __shared__ int sh[1024];
+    __shared__ int vals[kScanSeg];
+    __shared__ int sums[kScanThreads];
+    __shared__ int carry_sh;
+    if (blockIdx.x == 0 && threadIdx.x < 2 * kStatSlots) {
+        const int g = threadIdx.x / kStatSlots, k = threadIdx.x % kStatSlots;
+        st->max_row[g][k] = 0;
+        st->entries[g][k] = 0ull;
+    }
     const GridDev& g = grids[blockIdx.x];
     const int nc = g.ncell;
-    const int T = blockDim.x;
-    const int per = (nc + T - 1) / T;
-    const int b = min(nc, (int)threadIdx.x * per);
-    const int e = min(nc, b + per);
-    int s = 0;
-    for (int c = b; c < e; ++c) s += g.count[c];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        const int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    const int t = threadIdx.x;
+    constexpr int per = kScanSeg / kScanThreads;
+    if (t == 0) carry_sh = 0;
+    for (int seg = 0; seg < nc; seg += kScanSeg) {
+        const int len = min(kScanSeg, nc - seg);
+        for (int k = t; k < kScanSeg; k += kScanThreads) vals[k] = k < len ? g.count[seg + k] : 0;
         __syncthreads();
-        sh[threadIdx.x] += v;
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k) s += vals[t * per + k];
+        sums[t] = s;
+        __syncthreads();
+        for (int off = 1; off < kScanThreads; off <<= 1) {
+            const int v = t >= off ? sums[t - off] : 0;
+            __syncthreads();
+            sums[t] += v;
+            __syncthreads();
+        }
+        int run = carry_sh + sums[t] - s;
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const int v = vals[t * per + k];
+            vals[t * per + k] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int k = t; k < len; k += kScanThreads) {
+            g.start[seg + k] = vals[k];
+            g.count[seg + k] = 0;
+        }
+        if (t == kScanThreads - 1) carry_sh += sums[kScanThreads - 1];
         __syncthreads();
     }
-    int run = sh[threadIdx.x] - s;
-    for (int c = b; c < e; ++c) {
-        const int v = g.count[c];
-        g.start[c] = run;
-        run += v;
-        g.count[c] = 0;
-    }
-    if ((int)threadIdx.x == T - 1) g.start[nc] = sh[T - 1];
+    if (t == 0) g.start[nc] = carry_sh;
 }
 
 __global__ void k_scatter(int n, const GridDev* __restrict__ grids, const int2* __restrict__ key_a,
@@ -161,6 +185,20 @@ __global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int n
         const int c = site ? cell - ncell_a : cell;
         const int b = g.start[c];
         const int len = g.start[c + 1] - b;
+        if (len <= kWave) {
+            // rank by counting with cross-lane reads, no memory traffic
+            const int u = lane < len ? g.user_unsorted[b + lane] : 0x7fffffff;
+            int r = 0;
+            for (int k = 0; k < len; ++k) r += __shfl(u, k) < u;
+            if (lane < len) {
+                const int dst = b + r;
+                g.user[dst] = u;
+                g.pos[dst] = wpos[u];
+                g.meta[dst] = make_int2(topo.types[u], topo.mol[u]);
+                if (!site) user2arow[u] = dst;
+            }
+            continue;
+        }
         for (int base = 0; base < len; base += kWave) {
             const int t = base + lane;
             if (t < len) {
@@ -184,13 +222,14 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
                                                       int ncell_a, TopoDev topo,
                                                       double Lx, double Ly, double Lz,
                                                       const int* __restrict__ user2arow,
-                                                      int* __restrict__ s_arow,
+                                                      int4* __restrict__ a_rec,
+                                                      int4* __restrict__ s_rec,
                                                       Status* __restrict__ st)
 {
     __shared__ double4 c_pos[kChunk];
     __shared__ int2 c_meta[kChunk];
     __shared__ int c_user[kChunk];
-    __shared__ int cell_start[27], cell_pre[28];
+    __shared__ int cell_start[27], cell_cnt[27], cell_pre[28];
     __shared__ int ncells_sh;
     __shared__ int home_cnt[kHomeMax];
     __shared__ int blk_max;
@@ -203,29 +242,43 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
     const int wave = threadIdx.x / kWave;
     const int nw = blockDim.x / kWave;
 
+    if (threadIdx.x < 27) {
+        // one lane per stencil cell: deduplicated offsets, neighbour rank, range
+        const int t = threadIdx.x;
+        const int ix = t / 9, iy = (t / 3) % 3, iz = t % 3;
+        const bool used = ix < g.noff[0] && iy < g.noff[1] && iz < g.noff[2];
+        int cnt = 0, s0 = 0;
+        if (used) {
+            const int lin = g.lin_of_rank[c];
+            const int cz = lin % g.n[2];
+            const int cy = (lin / g.n[2]) % g.n[1];
+            const int cx = lin / (g.n[1] * g.n[2]);
+            const int nx = (cx + g.off[0][ix] + g.n[0]) % g.n[0];
+            const int ny = (cy + g.off[1][iy] + g.n[1]) % g.n[1];
+            const int nz = (cz + g.off[2][iz] + g.n[2]) % g.n[2];
+            const int r = g.rank_of_lin[(nx * g.n[1] + ny) * g.n[2] + nz];
+            s0 = g.start[r];
+            cnt = g.start[r + 1] - s0;
+        }
+        cell_start[t] = s0;
+        cell_cnt[t] = used ? cnt : -1;
+    }
     if (threadIdx.x == 0) {
-        const int lin = g.lin_of_rank[c];
-        const int cz = lin % g.n[2];
-        const int cy = (lin / g.n[2]) % g.n[1];
-        const int cx = lin / (g.n[1] * g.n[2]);
-        int k = 0, acc = 0;
-        for (int ix = 0; ix < g.noff[0]; ++ix)
-            for (int iy = 0; iy < g.noff[1]; ++iy)
-                for (int iz = 0; iz < g.noff[2]; ++iz) {
-                    const int nx = (cx + g.off[0][ix] + g.n[0]) % g.n[0];
-                    const int ny = (cy + g.off[1][iy] + g.n[1]) % g.n[1];
-                    const int nz = (cz + g.off[2][iz] + g.n[2]) % g.n[2];
-                    const int r = g.rank_of_lin[(nx * g.n[1] + ny) * g.n[2] + nz];
-                    const int s0 = g.start[r];
-                    cell_start[k] = s0;
-                    cell_pre[k] = acc;
-                    acc += g.start[r + 1] - s0;
-                    ++k;
-                }
-        cell_pre[k] = acc;
-        ncells_sh = k;
         blk_max = 0;
         blk_sum = 0ull;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int k = 0, acc = 0;
+        for (int t = 0; t < 27; ++t) {
+            if (cell_cnt[t] < 0) continue;
+            cell_start[k] = cell_start[t];
+            cell_pre[k] = acc;
+            acc += cell_cnt[t];
+            ++k;
+        }
+        cell_pre[k] = acc;
+        ncells_sh = k;
     }
     __syncthreads();
     const int ncells = ncells_sh;
@@ -294,13 +347,19 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
             g.nrow[row] = cnt;
             atomicMax(&blk_max, cnt);
             atomicAdd(&blk_sum, (unsigned long long)cnt);
-            if (site) s_arow[row] = user2arow[g.user[row]];
+            // packed row record for the force kernel: one load per row
+            const int u = g.user[row];
+            const int ty = g.meta[row].x;
+            const int stored = min(cnt, cap);
+            if (site) s_rec[row] = make_int4(u, ty, stored, user2arow[u]);
+            else a_rec[row] = make_int4(u, ty, stored, topo.hybrid[ty]);
         }
     }
     __syncthreads();
     if (threadIdx.x == 0 && he > hb) {
-        atomicMax(&st->max_row[site ? 1 : 0], blk_max);
-        atomicAdd(&st->entries[site ? 1 : 0], blk_sum);
+        const int slot = blockIdx.x % kStatSlots;
+        atomicMax(&st->max_row[site ? 1 : 0][slot], blk_max);
+        atomicAdd(&st->entries[site ? 1 : 0][slot], blk_sum);
     }
 }
 
@@ -363,56 +422,94 @@ __device__ __forceinline__ void cg_term(const PairCoef<T>& c, const Cutoffs<T>& 
     }
 }
 
+// Coefficient table staged in LDS when it is small (ntypes <= kLdsTypes).
+constexpr int kLdsTypes = 8;
+
+template <typename S, bool EW>
+struct CoefLds {
+    PairCoef<S> c[kLdsTypes * kLdsTypes];
+    PairCoef<double> c64[(EW && sizeof(S) != sizeof(double)) ? kLdsTypes * kLdsTypes : 1];
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_table(T* dst, const T* __restrict__ src, int count)
+{
+    const int words = count * (int)(sizeof(T) / sizeof(uint32_t));
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    for (int k = threadIdx.x; k < words; k += blockDim.x) d[k] = s[k];
+}
+
+// Entries handled per lane per batch: their list loads, then their position
+// gathers, are issued together before any pair term is computed.
+constexpr int kBatch = 2;
+
 // One list row: the FG part (CG = false, atom list, zero beyond r_s+) or the
 // CG part (CG = true, site list, zero beyond r_c+) of Eq. 20 for every entry.
 // Differences are taken in FP64 with the minimum image; the force terms are
 // evaluated in S and accumulated in TF; energy and virial terms are always
 // evaluated in FP64 (re-evaluated when S is float) and accumulated in FP64.
 template <bool CG, typename S, typename TF, bool EW>
-__device__ __forceinline__ void row_terms(const ForceArgs& a, const PairCoef<S>* __restrict__ crow,
-                                          const PairCoef<double>* __restrict__ crow64,
+__device__ __forceinline__ void row_terms(const ForceArgs& a, const PairCoef<S>* crow,
+                                          const PairCoef<double>* crow64,
                                           const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
                                           double xi, double yi, double zi,
                                           const int* __restrict__ lst, int cnt, int sub, int G,
                                           TF& fx, TF& fy, TF& fz, double* acc)
 {
     const double rmax2 = CG ? cut64.rco2 : cut64.rso2;
-    for (int k = sub; k < cnt; k += G) {
-        const uint32_t e = (uint32_t)lst[k];
-        const int uj = (int)(e & kIdxMask);
-        const int tj = (int)(e >> kIdxBits);
-        double dx = xi - a.pos[3 * uj];
-        double dy = yi - a.pos[3 * uj + 1];
-        double dz = zi - a.pos[3 * uj + 2];
-        dx -= a.box[0] * rint(dx * a.inv_box[0]);
-        dy -= a.box[1] * rint(dy * a.inv_box[1]);
-        dz -= a.box[2] * rint(dz * a.inv_box[2]);
-        const double r2d = dx * dx + dy * dy + dz * dz;
-        if (r2d < rmax2) {
-            S fp, en;
-            if constexpr (CG) cg_term<S>(crow[tj], cut, (S)r2d, fp, en);
-            else fg_term<S>(crow[tj], cut, (S)r2d, fp, en);
-            fx += (TF)(fp * (S)dx);
-            fy += (TF)(fp * (S)dy);
-            fz += (TF)(fp * (S)dz);
-            if constexpr (EW) {
-                double fpd, end;
-                if constexpr (sizeof(S) == sizeof(double)) {
-                    fpd = (double)fp;
-                    end = (double)en;
-                } else if constexpr (CG) {
-                    cg_term<double>(crow64[tj], cut64, r2d, fpd, end);
-                } else {
-                    fg_term<double>(crow64[tj], cut64, r2d, fpd, end);
+    for (int base = sub; base < cnt; base += G * kBatch) {
+        uint32_t e[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int k = base + u * G;
+            e[u] = k < cnt ? (uint32_t)lst[k] : 0xffffffffu;
+        }
+        double px[kBatch], py[kBatch], pz[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int uj = e[u] != 0xffffffffu ? (int)(e[u] & kIdxMask) : 0;
+            px[u] = a.pos[3 * uj];
+            py[u] = a.pos[3 * uj + 1];
+            pz[u] = a.pos[3 * uj + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (e[u] == 0xffffffffu) continue;
+            const int tj = (int)(e[u] >> kIdxBits);
+            double dx = xi - px[u];
+            double dy = yi - py[u];
+            double dz = zi - pz[u];
+            dx -= a.box[0] * rint(dx * a.inv_box[0]);
+            dy -= a.box[1] * rint(dy * a.inv_box[1]);
+            dz -= a.box[2] * rint(dz * a.inv_box[2]);
+            const double r2d = dx * dx + dy * dy + dz * dz;
+            if (r2d < rmax2) {
+                S fp, en;
+                if constexpr (CG) cg_term<S>(crow[tj], cut, (S)r2d, fp, en);
+                else fg_term<S>(crow[tj], cut, (S)r2d, fp, en);
+                fx += (TF)(fp * (S)dx);
+                fy += (TF)(fp * (S)dy);
+                fz += (TF)(fp * (S)dz);
+                if constexpr (EW) {
+                    double fpd, end;
+                    if constexpr (sizeof(S) == sizeof(double)) {
+                        fpd = (double)fp;
+                        end = (double)en;
+                    } else if constexpr (CG) {
+                        cg_term<double>(crow64[tj], cut64, r2d, fpd, end);
+                    } else {
+                        fg_term<double>(crow64[tj], cut64, r2d, fpd, end);
+                    }
+                    const double hf = 0.5 * fpd;
+                    acc[CG ? 1 : 0] += 0.5 * end;
+                    acc[2] += hf * dx * dx;
+                    acc[3] += hf * dy * dy;
+                    acc[4] += hf * dz * dz;
+                    acc[5] += hf * dx * dy;
+                    acc[6] += hf * dx * dz;
+                    acc[7] += hf * dy * dz;
                 }
-                const double hf = 0.5 * fpd;
-                acc[CG ? 1 : 0] += 0.5 * end;
-                acc[2] += hf * dx * dx;
-                acc[3] += hf * dy * dy;
-                acc[4] += hf * dz * dz;
-                acc[5] += hf * dx * dy;
-                acc[6] += hf * dx * dz;
-                acc[7] += hf * dy * dz;
             }
         }
     }
@@ -424,7 +521,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <typename S, typename TF, bool EW>
+template <typename S, typename TF, bool EW, bool LDS>
 __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> cut,
                                                        Cutoffs<double> cut64)
 {
@@ -439,99 +536,112 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const int G = 1 << lg;
     const int row = logical * (kForceBlock >> lg) + ((int)threadIdx.x >> lg);
     const int sub = (int)threadIdx.x & (G - 1);
-    const PairCoef<S>* coef = (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32);
-    const PairCoef<double>* coef64 = (const PairCoef<double>*)a.coef64;
+
+    // row record first: it is the head of every dependent load chain
+    int4 rec = make_int4(-1, 0, 0, 1);
+    int cnt_a = 0;
+    if (!rb) {
+        if (row < a.n_arow) rec = a.a_rec[row];
+    } else if (row < a.n_srow) {
+        rec = a.s_rec[row];
+        cnt_a = a.a_rec[rec.w].z;
+    }
+
+    const PairCoef<S>* coef;
+    const PairCoef<double>* coef64;
+    if constexpr (LDS) {
+        __shared__ CoefLds<S, EW> tab;
+        const int np = a.ntypes * a.ntypes;
+        stage_table(tab.c, (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32), np);
+        if constexpr (EW && sizeof(S) != sizeof(double))
+            stage_table(tab.c64, (const PairCoef<double>*)a.coef64, np);
+        __syncthreads();
+        coef = tab.c;
+        if constexpr (EW && sizeof(S) != sizeof(double)) coef64 = tab.c64;
+        else coef64 = (const PairCoef<double>*)tab.c;
+    } else {
+        coef = (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32);
+        coef64 = (const PairCoef<double>*)a.coef64;
+    }
 
     TF fx = TF(0), fy = TF(0), fz = TF(0);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int ui = -1;
-    if (!rb) {
-        if (row < a.n_arow) {
-            const int ti = a.a_meta[row].x;
-            if (!a.hybrid[ti]) {        // hybrid rows are owned by the site range
-                ui = a.a_user[row];
-                const double xi = a.pos[3 * ui], yi = a.pos[3 * ui + 1], zi = a.pos[3 * ui + 2];
-                const int cnt = min(a.a_nrow[row], a.a_cap);
-                row_terms<false, S, TF, EW>(a, coef + ti * a.ntypes, coef64 + ti * a.ntypes, cut,
-                                            cut64, xi, yi, zi, a.a_list + (size_t)row * a.a_cap,
-                                            cnt, sub, G, fx, fy, fz, acc);
-            }
-        }
-    } else if (row < a.n_srow) {
-        const int ti = a.s_meta[row].x;
-        ui = a.s_user[row];
+    const bool own = rb ? rec.x >= 0 : (rec.x >= 0 && rec.w == 0);   // hybrid atom rows belong to the site range
+    if (own) {
+        const int ui = rec.x, ti = rec.y;
         const double xi = a.pos[3 * ui], yi = a.pos[3 * ui + 1], zi = a.pos[3 * ui + 2];
-        const int ar = a.s_arow[row];
-        const int cnt_a = min(a.a_nrow[ar], a.a_cap);
+        const int ar = rb ? rec.w : row;
+        const int ca = rb ? cnt_a : rec.z;
         row_terms<false, S, TF, EW>(a, coef + ti * a.ntypes, coef64 + ti * a.ntypes, cut, cut64,
-                                    xi, yi, zi, a.a_list + (size_t)ar * a.a_cap, cnt_a, sub, G,
+                                    xi, yi, zi, a.a_list + (size_t)ar * a.a_cap, ca, sub, G,
                                     fx, fy, fz, acc);
-        const int cnt_s = min(a.s_nrow[row], a.s_cap);
-        row_terms<true, S, TF, EW>(a, coef + ti * a.ntypes, coef64 + ti * a.ntypes, cut, cut64,
-                                   xi, yi, zi, a.s_list + (size_t)row * a.s_cap, cnt_s, sub, G,
-                                   fx, fy, fz, acc);
+        if (rb)
+            row_terms<true, S, TF, EW>(a, coef + ti * a.ntypes, coef64 + ti * a.ntypes, cut, cut64,
+                                       xi, yi, zi, a.s_list + (size_t)row * a.s_cap, rec.z, sub,
+                                       G, fx, fy, fz, acc);
     }
     for (int o = G >> 1; o > 0; o >>= 1) {
         fx += __shfl_xor(fx, o);
         fy += __shfl_xor(fy, o);
         fz += __shfl_xor(fz, o);
     }
-    if (ui >= 0 && sub == 0) {
+    if (own && sub == 0) {
         TF* F = (TF*)a.forces;
-        F[3 * ui] = fx;
-        F[3 * ui + 1] = fy;
-        F[3 * ui + 2] = fz;
+        F[3 * rec.x] = fx;
+        F[3 * rec.x + 1] = fy;
+        F[3 * rec.x + 2] = fz;
     }
     if constexpr (EW) {
+        // per-block partial sums in a fixed order; k_reduce_ew adds the blocks
         __shared__ double red[8][kForceBlock / kWave];
-        __shared__ int is_last;
         const int lane = threadIdx.x & (kWave - 1);
         const int wave = threadIdx.x / kWave;
+#pragma unroll
         for (int k = 0; k < 8; ++k) {
             const double v = wave_sum(acc[k]);
             if (lane == 0) red[k][wave] = v;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double* P = a.partials + (size_t)blockIdx.x * 8;
-            for (int k = 0; k < 8; ++k) {
-                double s = 0.0;
-                for (int w = 0; w < kForceBlock / kWave; ++w) s += red[k][w];
-                P[k] = s;
-            }
-            __threadfence();
-            const unsigned t = atomicAdd(a.counter, 1u);
-            is_last = (t == gridDim.x - 1);
+        if (threadIdx.x < 8) {
+            double t = 0.0;
+            for (int w = 0; w < kForceBlock / kWave; ++w) t += red[threadIdx.x][w];
+            a.partials[(size_t)blockIdx.x * 8 + threadIdx.x] = t;
         }
-        __syncthreads();
-        if (is_last) {
-            __threadfence();
-            const volatile double* P = a.partials;
-            double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-                for (int k = 0; k < 8; ++k) s[k] += P[(size_t)b * 8 + k];
-            __syncthreads();
-            for (int k = 0; k < 8; ++k) {
-                const double v = wave_sum(s[k]);
-                if (lane == 0) red[k][wave] = v;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double t[8];
-                for (int k = 0; k < 8; ++k) {
-                    t[k] = 0.0;
-                    for (int w = 0; w < kForceBlock / kWave; ++w) t[k] += red[k][w];
-                }
-                if (a.energy) {
-                    a.energy[0] = t[0] + t[1];
-                    a.energy[1] = t[0];
-                    a.energy[2] = t[1];
-                }
-                if (a.virial)
-                    for (int k = 0; k < 6; ++k) a.virial[k] = t[2 + k];
-                *a.counter = 0u;
-            }
+    }
+}
+
+// Sum of the per-block partials in block order: energy {FG+CG, FG, CG} and the
+// six virial components.  One block; deterministic.
+__global__ __launch_bounds__(256) void k_reduce_ew(const double* __restrict__ partials, int blocks,
+                                                   double* __restrict__ energy,
+                                                   double* __restrict__ virial)
+{
+    __shared__ double red[8][256 / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < blocks; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += partials[(size_t)b * 8 + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double v = wave_sum(s[k]);
+        if (lane == 0) red[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[8];
+        for (int k = 0; k < 8; ++k) {
+            t[k] = 0.0;
+            for (int w = 0; w < 256 / kWave; ++w) t[k] += red[k][w];
         }
+        if (energy) {
+            energy[0] = t[0] + t[1];
+            energy[1] = t[0];
+            energy[2] = t[1];
+        }
+        if (virial)
+            for (int k = 0; k < 6; ++k) virial[k] = t[2 + k];
     }
 }
 
@@ -567,9 +677,9 @@ hipError_t launch_bin(int n, const double* pos, const double box[3], TopoDev top
     return hipGetLastError();
 }
 
-hipError_t launch_scan(GridDev* grids_dev, int ngrids, hipStream_t s)
+hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan, dim3(ngrids), dim3(1024), 0, s, grids_dev);
+    hipLaunchKernelGGL(k_scan, dim3(ngrids), dim3(kScanThreads), 0, s, grids_dev, st);
     return hipGetLastError();
 }
 
@@ -595,11 +705,11 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, con
 }
 
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, TopoDev topo,
-                        const double box[3], const int* user2arow, int* s_arow, Status* st,
-                        hipStream_t s)
+                        const double box[3], const int* user2arow, int4* a_rec, int4* s_rec,
+                        Status* st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lists, dim3(ncell_a + ncell_s), dim3(kListBlock), 0, s, grids_dev,
-                       ncell_a, topo, box[0], box[1], box[2], user2arow, s_arow, st);
+                       ncell_a, topo, box[0], box[1], box[2], user2arow, a_rec, s_rec, st);
     return hipGetLastError();
 }
 
@@ -607,9 +717,16 @@ hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math,
                          bool ew, hipStream_t s)
 {
     const dim3 grid(a.blocks_a + a.blocks_b), block(kForceBlock);
+    const bool lds = a.ntypes <= kLdsTypes;
 #define RELRES_LAUNCH(S, TF, EW)                                                                 \
-    hipLaunchKernelGGL((k_forces<S, TF, EW>), grid, block, 0, s, a, cut_as<S>(cut64),          \
-                       cut_as<double>(cut64))
+    do {                                                                                         \
+        if (lds)                                                                                 \
+            hipLaunchKernelGGL((k_forces<S, TF, EW, true>), grid, block, 0, s, a,                \
+                               cut_as<S>(cut64), cut_as<double>(cut64));                         \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_forces<S, TF, EW, false>), grid, block, 0, s, a,               \
+                               cut_as<S>(cut64), cut_as<double>(cut64));                         \
+    } while (0)
     if (precision == 64) {
         if (ew) RELRES_LAUNCH(double, double, true); else RELRES_LAUNCH(double, double, false);
     } else if (pair_math == 64) {
@@ -618,6 +735,10 @@ hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math,
         if (ew) RELRES_LAUNCH(float, float, true); else RELRES_LAUNCH(float, float, false);
     }
 #undef RELRES_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ew) return e;
+    hipLaunchKernelGGL(k_reduce_ew, dim3(1), dim3(256), 0, s, a.partials,
+                       a.blocks_a + a.blocks_b, a.energy, a.virial);
     return hipGetLastError();
 }
 
