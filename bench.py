@@ -46,32 +46,68 @@ def algorithmic_bytes(st, force_bytes):
     return n * (24 + 3 * force_bytes) + 4 * (st["atom_entries"] + st["site_entries"]) + 4 * (n + ns)
 
 
-def run_protocol(rr, pos, box, steps, warmup, rebuild_every, timing=False):
+class Stepper:
+    """Runs the protocol: a list rebuild every `rebuild_every` steps, one force
+    call (forces, energy, virial) per step.  With graphs, the force calls
+    between two rebuilds are one captured HIP graph (re-captured whenever the
+    library reallocates a buffer the force call uses)."""
+
+    def __init__(self, rr, pos, box, rebuild_every, use_graph):
+        import torch
+        self.rr, self.pos, self.box = rr, pos, box
+        self.every = rebuild_every
+        self.use_graph = use_graph
+        dt = torch.float32 if rr.precision == 32 else torch.float64
+        self.F = torch.empty((pos.shape[0], 3), dtype=dt, device=pos.device)
+        self.E = torch.empty(3, dtype=torch.float64, device=pos.device)
+        self.W = torch.empty(6, dtype=torch.float64, device=pos.device)
+        self.graph, self.graph_gen, self.graph_len = None, None, 0
+
+    def force(self):
+        self.rr.forces(self.pos, out=self.F, energy=self.E, virial=self.W)
+
+    def _graph(self, n):
+        import torch
+        gen = self.rr.generation()
+        if self.graph is None or gen != self.graph_gen or n != self.graph_len:
+            self.force()                 # sizes internal buffers outside capture
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(n):
+                    self.force()
+            self.graph, self.graph_gen, self.graph_len = g, gen, n
+        return self.graph
+
+    def run(self, steps):
+        k = 0
+        while k < steps:
+            n = min(self.every, steps - k)
+            self.rr.build_lists(self.pos, self.box)
+            if self.use_graph:
+                self._graph(n).replay()
+            else:
+                for _ in range(n):
+                    self.force()
+            k += n
+
+
+def run_protocol(rr, pos, box, steps, warmup, rebuild_every, timing=False, use_graph=True):
     import torch
-    F = torch.empty((pos.shape[0], 3), dtype=torch.float32 if rr.precision == 32 else torch.float64,
-                    device=pos.device)
-    E = torch.empty(3, dtype=torch.float64, device=pos.device)
-    W = torch.empty(6, dtype=torch.float64, device=pos.device)
-    rr.build_lists(pos, box)
-    for k in range(warmup):
-        if k % rebuild_every == 0:
-            rr.build_lists(pos, box)
-        rr.forces(pos, out=F, energy=E, virial=W)
+    st = Stepper(rr, pos, box, rebuild_every, use_graph and not timing)
+    st.run(max(warmup, rebuild_every))
     torch.cuda.synchronize()
     if timing:
         rr.set_timing(True)
         rr.timing()                     # reset counters
     t0 = time.perf_counter()
-    for k in range(steps):
-        if k % rebuild_every == 0:
-            rr.build_lists(pos, box)
-        rr.forces(pos, out=F, energy=E, virial=W)
+    st.run(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tm = rr.timing() if timing else None
     if timing:
         rr.set_timing(False)
-    return dt, tm, (F, E, W)
+    return dt, tm, (st.F, st.E, st.W)
 
 
 def cpu_baseline(sys_, budget_s):
@@ -105,6 +141,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every force call eagerly instead of replaying a HIP graph")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,7 +165,9 @@ def main():
     rr = make(s, precision, args.pair_math)
     if args.lanes:
         rr.set_launch(*args.lanes)
-    dt, _, _ = run_protocol(rr, pos, s.box, args.steps, args.warmup, args.rebuild_every)
+    use_graph = not args.no_graph
+    dt, _, _ = run_protocol(rr, pos, s.box, args.steps, args.warmup, args.rebuild_every,
+                            use_graph=use_graph)
     st = rr.stats()
     value = s.n * args.steps / dt
     log(f"[bench] RelRes: {dt * 1e3 / args.steps:.4f} ms/step, {value:.4e} atom-steps/s; "
@@ -147,7 +187,8 @@ def main():
     if not args.no_conventional:
         sc = s.conventional()
         rc = make(sc, precision, args.pair_math)
-        dtc, _, _ = run_protocol(rc, pos, sc.box, args.steps, args.warmup, args.rebuild_every)
+        dtc, _, _ = run_protocol(rc, pos, sc.box, args.steps, args.warmup, args.rebuild_every,
+                                 use_graph=use_graph)
         stc = rc.stats()
         _, tmc, _ = run_protocol(rc, pos, sc.box, args.steps, 0, args.rebuild_every, timing=True)
         rc.close()
@@ -182,6 +223,7 @@ def main():
             "forces": "fp32" if precision == 32 else "fp64",
             "pair_math": args.pair_math or precision, "energy_virial": "fp64",
             "parallelism": "single GPU",
+            "launch": "hip graph of the force calls between rebuilds" if use_graph else "eager",
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -59,6 +59,7 @@ extern "C" {
 
 #define RELRES_MAX_TYPES      32
 #define RELRES_MAX_ATOMS      (1 << 27)
+#define RELRES_MAX_EXCLUSIONS 64   /* excluded partners per atom, after symmetrisation */
 
 /* Which neighbour list (relres_get_pairs). */
 #define RELRES_LIST_ATOM  0   /* all non-excluded pairs, r < r_s+ + skin        */
@@ -98,6 +99,10 @@ typedef struct relres_stats {
     int atom_cells[3], site_cells[3];     /* cell grid of each list           */
     long long builds, regrows;            /* list builds, capacity regrows    */
     double box[3];                        /* box of the last build            */
+    long long generation;                 /* changes whenever a device buffer that
+                                             relres_forces reads or writes is
+                                             reallocated; a graph that captured
+                                             relres_forces must be re-captured then */
 } relres_stats;
 
 /* Create a context.  Validates the cutoff ordering r_s- <= r_s+ <= r_c- <=
@@ -110,8 +115,9 @@ int relres_create(const relres_params *params, relres_ctx **out);
  * pairs that do not interact at all (neither FG nor CG part): every pair of
  * one molecule if exclude_same_mol != 0, plus the CSR lists
  * excl_idx[excl_offsets[i] .. excl_offsets[i+1]) of caller indices (may be
- * NULL for none; they are symmetrised).  Host arrays, copied.  types[i] must
- * lie in [0, ntypes).  n_atoms may be 0.                                     */
+ * NULL for none; they are symmetrised; at most RELRES_MAX_EXCLUSIONS partners
+ * per atom).  Host arrays, copied.  types[i] must lie in [0, ntypes).
+ * n_atoms may be 0.                                                          */
 int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const int *mol,
                         int exclude_same_mol, const int *excl_offsets, const int *excl_idx);
 
@@ -135,8 +141,14 @@ int relres_build_lists(relres_ctx *ctx, const double *pos, const double box[3], 
 int relres_forces(relres_ctx *ctx, const double *pos, void *forces, double *energy,
                   double *virial, void *stream);
 
-/* List statistics of the last build (host struct; synchronises the device). */
+/* List statistics of the last build (host struct).  Entry counts and row
+ * lengths are computed on demand by a small kernel the first time they are
+ * asked for after a build, which synchronises the device.                   */
 int relres_list_stats(relres_ctx *ctx, relres_stats *out);
+
+/* Cheap query (no device work): the buffer generation of relres_stats.  A
+ * HIP graph that captured relres_forces stays valid while it is unchanged.  */
+int relres_generation(relres_ctx *ctx, long long *generation);
 
 /* Copy one list as canonical caller-index pairs (i, j), i < j, sorted by i
  * then j, into pairs_host (2*cap ints).  *n_out receives the number of pairs,
@@ -151,7 +163,8 @@ int relres_get_pairs(relres_ctx *ctx, int which, int *pairs_host, long long cap,
 int relres_set_launch(relres_ctx *ctx, int lanes_atom, int lanes_site);
 
 /* With enable != 0, HIP events are recorded on the caller's stream right
- * before and after every force launch and around every list build.
+ * before and after every launch of the force kernel (the energy/virial
+ * reduction that follows it is outside the pair) and around every list build.
  * relres_get_timing synchronises, returns the accumulated milliseconds and
  * launch counts since the previous call, and resets them.                  */
 int relres_set_timing(relres_ctx *ctx, int enable);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -114,10 +115,13 @@ struct DBuf {
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-int ensure(DBuf& b, size_t bytes)
+// Grow a device buffer.  `gen` counts (re)allocations of the buffers of one
+// context: device pointers that a graph captured are stale once it changes.
+int ensure(DBuf& b, size_t bytes, long long* gen)
 {
     if (bytes == 0) bytes = 64;
     if (b.p && b.bytes >= bytes) return RELRES_OK;
+    ++*gen;
     if (b.p) HIP_TRY(hipFree(b.p));
     b.p = nullptr;
     b.bytes = 0;
@@ -139,7 +143,8 @@ struct GridHost {
     int cap = 0;
     int members = 0;
     double rl = 0.0;
-    DBuf rank_of_lin, lin_of_rank, count, start, user_unsorted, user, pos, meta, list, nrow;
+    DBuf rank_of_lin, lin_of_rank, nbr, count, start, user_unsorted, user, pos, meta, row_cell, list,
+        nrow;
     GridDev dev{};
 };
 
@@ -165,6 +170,7 @@ struct relres_ctx {
     int n = 0, n_sites = 0;
     int same_mol = 0;
     bool has_excl = false;
+    int max_excl = 0;
     DBuf d_types, d_mol, d_excl_off, d_excl_idx;
 
     GridHost ga, gs;
@@ -175,16 +181,17 @@ struct relres_ctx {
     Status* h_status = nullptr;
     Status* h_zero = nullptr;
     int nonfinite_seen = 0;
-    int max_row[2] = {0, 0};          // reduced list statistics of the last build
-    long long entries[2] = {0, 0};
+    bool stats_fresh = false;         // statistics describe the current lists
+    bool lanes_stale = true;          // automatic lane counts need a refresh
     bool built = false;
     double box[3] = {0, 0, 0};
 
-    DBuf d_partials;
+    DBuf d_partials, d_counter;
     int lanes_a = 0, lanes_b = 0;        // caller override, 0 = automatic
     int auto_la = 4, auto_lb = 16;
 
     relres_stats stats{};
+    long long alloc_generation = 0;
 
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
@@ -223,7 +230,7 @@ int log2i(int v)
     return l;
 }
 
-int setup_grid(GridHost& g, double rl, const double box[3], int members)
+int setup_grid(GridHost& g, double rl, const double box[3], int members, long long* gen)
 {
     int n[3];
     long long total = 1;
@@ -262,26 +269,49 @@ int setup_grid(GridHost& g, double rl, const double box[3], int members)
             rank[code[r].second] = r;
             lin_of[r] = code[r].second;
         }
-        TRY(ensure(g.rank_of_lin, sizeof(int) * g.ncell));
-        TRY(ensure(g.lin_of_rank, sizeof(int) * g.ncell));
-        TRY(ensure(g.count, sizeof(int) * g.ncell));
-        TRY(ensure(g.start, sizeof(int) * (g.ncell + 1)));
+        // stencil ranks per cell; distinct offsets per axis (n = 1, 2 or >= 3)
+        int noff[3], off[3][3];
+        for (int k = 0; k < 3; ++k) {
+            if (n[k] >= 3) { noff[k] = 3; off[k][0] = -1; off[k][1] = 0; off[k][2] = 1; }
+            else if (n[k] == 2) { noff[k] = 2; off[k][0] = 0; off[k][1] = 1; off[k][2] = 0; }
+            else { noff[k] = 1; off[k][0] = off[k][1] = off[k][2] = 0; }
+        }
+        std::vector<int> nbr((size_t)g.ncell * 27, -1);
+        for (int r = 0; r < g.ncell; ++r) {
+            const int lin = lin_of[r];
+            const int cz = lin % n[2], cy = (lin / n[2]) % n[1], cx = lin / (n[1] * n[2]);
+            for (int t = 0; t < 27; ++t) {
+                const int ix = t / 9, iy = (t / 3) % 3, iz = t % 3;
+                if (ix >= noff[0] || iy >= noff[1] || iz >= noff[2]) continue;
+                const int nx = (cx + off[0][ix] + n[0]) % n[0];
+                const int ny = (cy + off[1][iy] + n[1]) % n[1];
+                const int nz = (cz + off[2][iz] + n[2]) % n[2];
+                nbr[(size_t)r * 27 + t] = rank[(nx * n[1] + ny) * n[2] + nz];
+            }
+        }
+        TRY(ensure(g.nbr, sizeof(int) * nbr.size(), gen));
+        HIP_TRY(hipMemcpy(g.nbr.p, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
+        TRY(ensure(g.rank_of_lin, sizeof(int) * g.ncell, gen));
+        TRY(ensure(g.lin_of_rank, sizeof(int) * g.ncell, gen));
+        TRY(ensure(g.count, sizeof(int) * g.ncell, gen));
+        TRY(ensure(g.start, sizeof(int) * (g.ncell + 1), gen));
         HIP_TRY(hipMemcpy(g.rank_of_lin.p, rank.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(g.lin_of_rank.p, lin_of.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
         HIP_TRY(hipMemset(g.count.p, 0, sizeof(int) * g.ncell));
     }
-    TRY(ensure(g.user_unsorted, sizeof(int) * members));
-    TRY(ensure(g.user, sizeof(int) * members));
-    TRY(ensure(g.pos, sizeof(double4) * members));
-    TRY(ensure(g.meta, sizeof(int2) * members));
-    TRY(ensure(g.nrow, sizeof(int) * members));
+    TRY(ensure(g.user_unsorted, sizeof(int) * members, gen));
+    TRY(ensure(g.user, sizeof(int) * members, gen));
+    TRY(ensure(g.pos, sizeof(double4) * members, gen));
+    TRY(ensure(g.meta, sizeof(int2) * members, gen));
+    TRY(ensure(g.row_cell, sizeof(int) * members, gen));
+    TRY(ensure(g.nrow, sizeof(int) * members, gen));
     if (g.cap == 0) {
         const double vol = box[0] * box[1] * box[2];
         const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * members / vol;
         g.cap = std::max(16, (int)std::ceil(expect * 1.5 + 16.0));
         g.cap = (g.cap + 7) & ~7;
     }
-    TRY(ensure(g.list, sizeof(int) * (size_t)members * g.cap));
+    TRY(ensure(g.list, sizeof(int) * (size_t)members * g.cap, gen));
 
     GridDev& d = g.dev;
     for (int k = 0; k < 3; ++k) {
@@ -304,12 +334,14 @@ int setup_grid(GridHost& g, double rl, const double box[3], int members)
     d.cap = g.cap;
     d.rank_of_lin = g.rank_of_lin.as<int>();
     d.lin_of_rank = g.lin_of_rank.as<int>();
+    d.nbr = g.nbr.as<int>();
     d.count = g.count.as<int>();
     d.start = g.start.as<int>();
     d.user_unsorted = g.user_unsorted.as<int>();
     d.user = g.user.as<int>();
     d.pos = g.pos.as<double4>();
     d.meta = g.meta.as<int2>();
+    d.row_cell = g.row_cell.as<int>();
     d.list = g.list.as<int>();
     d.nrow = g.nrow.as<int>();
     return RELRES_OK;
@@ -325,6 +357,7 @@ TopoDev topo_of(relres_ctx* c)
     t.excl_idx = c->has_excl ? c->d_excl_idx.as<int>() : nullptr;
     t.same_mol = c->same_mol;
     t.n = c->n;
+    t.max_excl = c->max_excl;
     return t;
 }
 
@@ -342,18 +375,42 @@ int upload_grids(relres_ctx* c, hipStream_t s)
     return RELRES_OK;
 }
 
-void reduce_status(relres_ctx* c)
+// Exact entries and longest rows of both lists (one small kernel, then a
+// synchronisation); refreshes the statistics and the automatic lane counts.
+int refresh_list_stats(relres_ctx* c, hipStream_t s)
 {
-    for (int g = 0; g < 2; ++g) {
-        int m = 0;
-        long long e = 0;
-        for (int k = 0; k < kStatSlots; ++k) {
-            m = std::max(m, c->h_status->max_row[g][k]);
-            e += (long long)c->h_status->entries[g][k];
-        }
-        c->max_row[g] = m;
-        c->entries[g] = e;
+    const bool sites = c->n_sites > 0;
+    if (c->n > 0) {
+        HIP_TRY(launch_list_stats(c->d_grids.as<GridDev>(), sites ? 2 : 1, c->d_status.as<Status>(), s));
+        HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
+    relres_stats& st = c->stats;
+    st.atom_entries = c->n ? (long long)c->h_status->entries[0] : 0;
+    st.site_entries = (c->n && sites) ? (long long)c->h_status->entries[1] : 0;
+    st.atom_max_row = c->n ? c->h_status->longest[0] : 0;
+    st.site_max_row = (c->n && sites) ? c->h_status->longest[1] : 0;
+    // automatic lanes per row: about four list entries per lane
+    const double avg_a = c->n ? (double)st.atom_entries / c->n : 0.0;
+    const double avg_s = c->n_sites ? (double)st.site_entries / c->n_sites : 0.0;
+    c->auto_la = next_pow2_clamped(avg_a / 4.0, 1, 32);
+    c->auto_lb = next_pow2_clamped((avg_a + avg_s) / 4.0, 1, 64);
+    c->stats_fresh = true;
+    return RELRES_OK;
+}
+
+// List builder: groups of rows per wave (default), or one block per cell for
+// crowded cells.  RELRES_LIST_KERNEL=wave|block overrides the choice.
+bool lists_per_wave(const relres_ctx* c)
+{
+    if (const char* e = std::getenv("RELRES_LIST_KERNEL")) {
+        if (!std::strcmp(e, "wave")) return true;
+        if (!std::strcmp(e, "block")) return false;
+    }
+    auto mean = [](const GridHost& g) { return g.ncell ? (double)g.members / g.ncell : 0.0; };
+    double m = mean(c->ga);
+    if (c->n_sites > 0) m = std::max(m, mean(c->gs));
+    return m <= 64.0;
 }
 
 int run_lists(relres_ctx* c, hipStream_t s)
@@ -363,8 +420,8 @@ int run_lists(relres_ctx* c, hipStream_t s)
     c->h_zero->nonfinite = c->h_status->nonfinite;
     HIP_TRY(hipMemcpyAsync(c->d_status.p, c->h_zero, sizeof(Status), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_lists(c->d_grids.as<GridDev>(), c->ga.ncell, c->n_sites > 0 ? c->gs.ncell : 0,
-                         topo_of(c), c->box, c->d_user2arow.as<int>(), c->d_a_rec.as<int4>(),
-                         c->d_s_rec.as<int4>(), c->d_status.as<Status>(), s));
+                         c->n, c->n_sites, topo_of(c), c->box, c->d_user2arow.as<int>(), c->d_a_rec.as<int4>(),
+                         c->d_s_rec.as<int4>(), c->d_status.as<Status>(), lists_per_wave(c), s));
     HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RELRES_OK;
@@ -486,17 +543,19 @@ int relres_create(const relres_params* p, relres_ctx** out)
     for (int k = 0; k < 4; ++k) c->cut64[4 + k] = c->cut64[k] * c->cut64[k];
 
     int rc;
-    if ((rc = ensure(c->d_coef64, sizeof(PairCoef<double>) * c->coef64.size()))) return bail(rc);
-    if ((rc = ensure(c->d_coef32, sizeof(PairCoef<float>) * coef32.size()))) return bail(rc);
-    if ((rc = ensure(c->d_hybrid, sizeof(int) * nt))) return bail(rc);
-    if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev)))) return bail(rc);
-    if ((rc = ensure(c->d_status, sizeof(Status)))) return bail(rc);
+    if ((rc = ensure(c->d_coef64, sizeof(PairCoef<double>) * c->coef64.size(), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_coef32, sizeof(PairCoef<float>) * coef32.size(), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_hybrid, sizeof(int) * nt, &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_status, sizeof(Status), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_counter, kTicketBytes, &c->alloc_generation))) return bail(rc);
     if (hipMemcpy(c->d_coef64.p, c->coef64.data(), sizeof(PairCoef<double>) * c->coef64.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_coef32.p, coef32.data(), sizeof(PairCoef<float>) * coef32.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_hybrid.p, c->hybrid.data(), sizeof(int) * nt, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->d_status.p, 0, sizeof(Status)) != hipSuccess)
+        hipMemset(c->d_status.p, 0, sizeof(Status)) != hipSuccess ||
+        hipMemset(c->d_counter.p, 0, kTicketBytes) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "uploading parameters failed"));
     if (hipHostMalloc((void**)&c->h_grids, 2 * sizeof(GridDev), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
@@ -544,25 +603,31 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
         for (int i = 0; i < n; ++i) {
             std::sort(part[i].begin(), part[i].end());
             part[i].erase(std::unique(part[i].begin(), part[i].end()), part[i].end());
+            if ((int)part[i].size() > RELRES_MAX_EXCLUSIONS)
+                return fail(RELRES_ERR_TOPOLOGY, "atom %d has %d excluded partners (max %d)", i,
+                            (int)part[i].size(), RELRES_MAX_EXCLUSIONS);
             off[i + 1] = off[i] + (int)part[i].size();
             idx.insert(idx.end(), part[i].begin(), part[i].end());
         }
     }
     c->built = false;
     c->topo_set = false;
+    c->lanes_stale = true;
     c->n = n;
     c->n_sites = sites;
     c->same_mol = exclude_same_mol ? 1 : 0;
     c->has_excl = !idx.empty();
-    TRY(ensure(c->d_types, sizeof(int) * n));
-    TRY(ensure(c->d_mol, sizeof(int) * n));
+    c->max_excl = 0;
+    for (int i = 0; i < n; ++i) c->max_excl = std::max(c->max_excl, off[i + 1] - off[i]);
+    TRY(ensure(c->d_types, sizeof(int) * n, &c->alloc_generation));
+    TRY(ensure(c->d_mol, sizeof(int) * n, &c->alloc_generation));
     if (n > 0) {
         HIP_TRY(hipMemcpy(c->d_types.p, t.data(), sizeof(int) * n, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->d_mol.p, m.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     }
     if (c->has_excl) {
-        TRY(ensure(c->d_excl_off, sizeof(int) * (n + 1)));
-        TRY(ensure(c->d_excl_idx, sizeof(int) * idx.size()));
+        TRY(ensure(c->d_excl_off, sizeof(int) * (n + 1), &c->alloc_generation));
+        TRY(ensure(c->d_excl_idx, sizeof(int) * idx.size(), &c->alloc_generation));
         HIP_TRY(hipMemcpy(c->d_excl_off.p, off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->d_excl_idx.p, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
     }
@@ -587,14 +652,16 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
             return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g must exceed 2 x %g", box[k], rmax);
     c->built = false;
     std::copy(box, box + 3, c->box);
-    TRY(setup_grid(c->ga, rla, box, c->n));
-    if (sites) TRY(setup_grid(c->gs, rls, box, c->n_sites));
-    TRY(ensure(c->d_wpos, sizeof(double4) * c->n));
-    TRY(ensure(c->d_key_a, sizeof(int2) * c->n));
-    TRY(ensure(c->d_key_s, sizeof(int2) * c->n));
-    TRY(ensure(c->d_user2arow, sizeof(int) * c->n));
-    TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n)));
-    TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites)));
+    const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
+    TRY(setup_grid(c->ga, rla, box, c->n, &c->alloc_generation));
+    if (sites) TRY(setup_grid(c->gs, rls, box, c->n_sites, &c->alloc_generation));
+    if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
+    TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_key_a, sizeof(int2) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_key_s, sizeof(int2) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_user2arow, sizeof(int) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n), &c->alloc_generation));
+    TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites), &c->alloc_generation));
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -612,9 +679,10 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
         const int ncs = sites ? c->gs.ncell : 0;
         HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
                                 c->d_user2arow.as<int>(), s));
-        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, topo, box, c->d_user2arow.as<int>(),
+        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->n, c->n_sites, topo, box,
+                             c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
-                             c->d_status.as<Status>(), s));
+                             c->d_status.as<Status>(), lists_per_wave(c), s));
         HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
         if (c->timing) HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -624,23 +692,23 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
         }
         // grow rows that overflowed and rebuild the lists (positions stay sorted)
         for (int attempt = 0; attempt < 3; ++attempt) {
-            reduce_status(c);
-            const bool ov_a = c->max_row[0] > c->ga.cap;
-            const bool ov_s = sites && c->max_row[1] > c->gs.cap;
+            const int mr_a = c->h_status->max_row[0], mr_s = c->h_status->max_row[1];
+            const bool ov_a = mr_a > c->ga.cap;
+            const bool ov_s = sites && mr_s > c->gs.cap;
             if (!ov_a && !ov_s) break;
             if (attempt == 2) return fail(RELRES_ERR_LIST_OVERFLOW, "list capacity did not converge");
             if (ov_a) {
-                c->ga.cap = ((int)(c->max_row[0] * 1.25) + 8 + 7) & ~7;
-                TRY(setup_grid(c->ga, rla, box, c->n));
+                c->ga.cap = ((int)(mr_a * 1.25) + 8 + 7) & ~7;
+                TRY(setup_grid(c->ga, rla, box, c->n, &c->alloc_generation));
             }
             if (ov_s) {
-                c->gs.cap = ((int)(c->max_row[1] * 1.25) + 8 + 7) & ~7;
-                TRY(setup_grid(c->gs, rls, box, c->n_sites));
+                c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
+                TRY(setup_grid(c->gs, rls, box, c->n_sites, &c->alloc_generation));
             }
             c->stats.regrows++;
+            c->lanes_stale = true;
             TRY(run_lists(c, s));
         }
-        reduce_status(c);
     } else if (c->timing) {
         HIP_TRY(hipEventRecord(e1, s));
     }
@@ -649,10 +717,6 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
     relres_stats& st = c->stats;
     st.n_atoms = c->n;
     st.n_sites = c->n_sites;
-    st.atom_entries = c->n ? c->entries[0] : 0;
-    st.site_entries = (c->n && sites) ? c->entries[1] : 0;
-    st.atom_max_row = c->n ? c->max_row[0] : 0;
-    st.site_max_row = (c->n && sites) ? c->max_row[1] : 0;
     st.atom_capacity = c->ga.cap;
     st.site_capacity = sites ? c->gs.cap : 0;
     for (int k = 0; k < 3; ++k) {
@@ -661,12 +725,12 @@ int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], vo
         st.box[k] = box[k];
     }
     st.builds++;
-    // automatic lanes per row: about four list entries per lane
-    const double avg_a = c->n ? (double)st.atom_entries / c->n : 0.0;
-    const double avg_s = c->n_sites ? (double)st.site_entries / c->n_sites : 0.0;
-    c->auto_la = next_pow2_clamped(avg_a / 4.0, 1, 32);
-    c->auto_lb = next_pow2_clamped((avg_a + avg_s) / 4.0, 1, 64);
+    c->stats_fresh = false;
     c->built = true;
+    if (c->lanes_stale) {
+        TRY(refresh_list_stats(c, s));
+        c->lanes_stale = false;
+    }
     return RELRES_OK;
 }
 
@@ -727,8 +791,9 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     a.lanes_b = lb;
     a.log_lanes_a = log2i(la);
     a.log_lanes_b = log2i(lb);
-    TRY(ensure(c->d_partials, sizeof(double) * 8 * (size_t)(a.blocks_a + a.blocks_b)));
+    TRY(ensure(c->d_partials, sizeof(double) * 8 * (size_t)(a.blocks_a + a.blocks_b + kXcdGroups), &c->alloc_generation));
     a.partials = c->d_partials.as<double>();
+    a.counter = c->d_counter.as<unsigned int>();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         TRY(take_events(c, e0, e1));
@@ -745,7 +810,16 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
 int relres_list_stats(relres_ctx* c, relres_stats* out)
 {
     if (!c || !out) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (c->built && !c->stats_fresh) TRY(refresh_list_stats(c, nullptr));
     *out = c->stats;
+    out->generation = c->alloc_generation;
+    return RELRES_OK;
+}
+
+int relres_generation(relres_ctx* c, long long* generation)
+{
+    if (!c || !generation) return fail(RELRES_ERR_ARG, "NULL argument");
+    *generation = c->alloc_generation;
     return RELRES_OK;
 }
 
@@ -823,11 +897,12 @@ void relres_destroy(relres_ctx* c)
     (void)hipDeviceSynchronize();
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
-                    &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials})
+                    &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials,
+                    &c->d_counter})
         release(*b);
     for (GridHost* g : {&c->ga, &c->gs})
-        for (DBuf* b : {&g->rank_of_lin, &g->lin_of_rank, &g->count, &g->start, &g->user_unsorted,
-                        &g->user, &g->pos, &g->meta, &g->list, &g->nrow})
+        for (DBuf* b : {&g->rank_of_lin, &g->lin_of_rank, &g->nbr, &g->count, &g->start, &g->user_unsorted,
+                        &g->user, &g->pos, &g->meta, &g->row_cell, &g->list, &g->nrow})
             release(*b);
     if (c->h_grids) (void)hipHostFree(c->h_grids);
     if (c->h_status) (void)hipHostFree(c->h_status);

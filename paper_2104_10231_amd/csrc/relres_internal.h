@@ -56,12 +56,14 @@ struct GridDev {
     int cap;                  // row capacity of the padded list
     const int* rank_of_lin;   // Morton rank of a linear cell index
     const int* lin_of_rank;
+    const int* nbr;           // ncell x 27 stencil ranks (-1: slot unused after deduplication)
     int* count;               // per cell (by rank); zero between builds
     int* start;               // ncell + 1 exclusive offsets (by rank)
     int* user_unsorted;       // member caller indices, cell-grouped
     int* user;                // member caller indices, cell-grouped, ascending in a cell
     double4* pos;             // wrapped positions of members (w unused)
     int2* meta;               // (type, molecule) of members
+    int* row_cell;            // cell rank of each member row
     int* list;                // rows x cap entries
     int* nrow;                // entries per row (true count, may exceed cap)
 };
@@ -74,18 +76,19 @@ struct TopoDev {
     const int* excl_idx;
     int same_mol;
     int n;
+    int max_excl;             // most excluded partners of any atom
 };
 
-// Build status read back by the host after every build.  The list statistics
-// are spread over kStatSlots slots (block b uses slot b mod kStatSlots) so
-// that thousands of blocks do not serialise on one address; the host reduces
-// the slots.  They are cleared by k_scan at every build.
-constexpr int kStatSlots = 64;
+// Build status, in mapped pinned host memory: the kernels write it directly
+// and the host reads it after synchronising.  max_row is written only by rows
+// that outgrew their capacity (cleared by k_scan at every build); entries and
+// longest are filled on demand by k_list_stats.
 struct Status {
-    int nonfinite;            // cumulative count of non-finite positions seen
+    int nonfinite;                  // cumulative count of non-finite positions seen
+    int max_row[2];                 // longest overflowing row per grid, 0 if none
+    int longest[2];                 // longest row per grid (k_list_stats)
     int pad;
-    int max_row[2][kStatSlots];
-    unsigned long long entries[2][kStatSlots];
+    unsigned long long entries[2];  // entries per grid (k_list_stats)
 };
 
 struct ForceArgs {
@@ -110,7 +113,9 @@ struct ForceArgs {
     void* forces;             // N x 3 of TF, caller order
     double* energy;           // [3] or null
     double* virial;           // [6] or null
-    double* partials;         // 8 per block
+    double* partials;         // 8 per block, then 8 per XCD group
+    unsigned int* counter;    // tickets: one per XCD group + one top, kTicketStride apart;
+                              // zero between launches
     int blocks_a, blocks_b;   // multiples of 8
     int lanes_a, lanes_b;     // lanes per row (powers of two)
     int log_lanes_a, log_lanes_b;
@@ -125,14 +130,19 @@ hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const in
                           hipStream_t s);
 hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,
                            TopoDev topo, int* user2arow, hipStream_t s);
-hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, TopoDev topo,
-                        const double box[3], const int* user2arow, int4* a_rec, int4* s_rec,
-                        Status* st, hipStream_t s);
+// per_wave: one wave per home cell (small cells) instead of one block per cell
+hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int members_a,
+                        int members_s, TopoDev topo, const double box[3], const int* user2arow,
+                        int4* a_rec, int4* s_rec, Status* st, bool per_wave, hipStream_t s);
 // cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares}
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
                          bool ew, hipStream_t s);
+hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
 hipError_t launch_zero_outputs(double* energy, double* virial, hipStream_t s);
 
+constexpr int kXcdGroups = 8;        // workgroups are dealt round-robin to 8 XCDs
+constexpr int kTicketStride = 64;    // unsigned ints between tickets (256 B)
+constexpr size_t kTicketBytes = sizeof(unsigned int) * kTicketStride * (kXcdGroups + 1);
 constexpr int kForceBlock = 256;
 constexpr int kListBlock = 256;
 

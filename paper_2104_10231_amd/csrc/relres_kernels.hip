@@ -24,6 +24,28 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kChunk = 256;    // candidates staged in LDS per pass
+
+// Pointers read from the grid descriptors live in device memory, so the
+// compiler cannot tell they are global and would use flat instructions, which
+// may alias LDS and make every LDS access wait for outstanding global stores.
+// Casting them to the global address space gives plain global loads/stores.
+#define RELRES_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ RELRES_GLOBAL T* gbl(T* p) { return (RELRES_GLOBAL T*)p; }
+// HIP vector types cannot be copied through such pointers; read them as scalars.
+__device__ __forceinline__ void load_xyz(const double4* base, int i, double& x, double& y, double& z)
+{
+    RELRES_GLOBAL const double* p = (RELRES_GLOBAL const double*)base + 4 * (size_t)i;
+    x = p[0];
+    y = p[1];
+    z = p[2];
+}
+__device__ __forceinline__ void load_meta(const int2* base, int i, int& type, int& mol)
+{
+    RELRES_GLOBAL const int* p = (RELRES_GLOBAL const int*)base + 2 * (size_t)i;
+    type = p[0];
+    mol = p[1];
+}
 constexpr int kHomeMax = 256;  // home atoms whose counters live in LDS at once
 
 // Wrap one coordinate into [0, L):  w = x - L floor(x / L), fixed into range.
@@ -89,7 +111,7 @@ __global__ void k_bin(int n, const double* __restrict__ pos, double Lx, double L
         const int lin = (cell_coord(wx, g.inv_cell[0], g.n[0]) * g.n[1] +
                          cell_coord(wy, g.inv_cell[1], g.n[1])) * g.n[2] +
                         cell_coord(wz, g.inv_cell[2], g.n[2]);
-        const int r = g.rank_of_lin[lin];
+        const int r = gbl(g.rank_of_lin)[lin];
         key_a[i] = make_int2(r, atomicAdd(&g.count[r], 1));
     }
     if (topo.hybrid[topo.types[i]]) {
@@ -97,7 +119,7 @@ __global__ void k_bin(int n, const double* __restrict__ pos, double Lx, double L
         const int lin = (cell_coord(wx, g.inv_cell[0], g.n[0]) * g.n[1] +
                          cell_coord(wy, g.inv_cell[1], g.n[1])) * g.n[2] +
                         cell_coord(wz, g.inv_cell[2], g.n[2]);
-        const int r = g.rank_of_lin[lin];
+        const int r = gbl(g.rank_of_lin)[lin];
         key_s[i] = make_int2(r, atomicAdd(&g.count[r], 1));
     } else {
         key_s[i] = make_int2(-1, -1);
@@ -116,19 +138,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(GridDev* __restrict__ gri
     __shared__ int vals[kScanSeg];
     __shared__ int sums[kScanThreads];
     __shared__ int carry_sh;
-    if (blockIdx.x == 0 && threadIdx.x < 2 * kStatSlots) {
-        const int g = threadIdx.x / kStatSlots, k = threadIdx.x % kStatSlots;
-        st->max_row[g][k] = 0;
-        st->entries[g][k] = 0ull;
-    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) st->max_row[threadIdx.x] = 0;
     const GridDev& g = grids[blockIdx.x];
     const int nc = g.ncell;
+    RELRES_GLOBAL int* gcount = gbl(g.count);
+    RELRES_GLOBAL int* gstart = gbl(g.start);
     const int t = threadIdx.x;
     constexpr int per = kScanSeg / kScanThreads;
     if (t == 0) carry_sh = 0;
     for (int seg = 0; seg < nc; seg += kScanSeg) {
         const int len = min(kScanSeg, nc - seg);
-        for (int k = t; k < kScanSeg; k += kScanThreads) vals[k] = k < len ? g.count[seg + k] : 0;
+        for (int k = t; k < kScanSeg; k += kScanThreads) vals[k] = k < len ? gcount[seg + k] : 0;
         __syncthreads();
         int s = 0;
 #pragma unroll
@@ -150,13 +170,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(GridDev* __restrict__ gri
         }
         __syncthreads();
         for (int k = t; k < len; k += kScanThreads) {
-            g.start[seg + k] = vals[k];
-            g.count[seg + k] = 0;
+            gstart[seg + k] = vals[k];
+            gcount[seg + k] = 0;
         }
         if (t == kScanThreads - 1) carry_sh += sums[kScanThreads - 1];
         __syncthreads();
     }
-    if (t == 0) g.start[nc] = carry_sh;
+    if (t == 0) gstart[nc] = carry_sh;
 }
 
 __global__ void k_scatter(int n, const GridDev* __restrict__ grids, const int2* __restrict__ key_a,
@@ -165,9 +185,9 @@ __global__ void k_scatter(int n, const GridDev* __restrict__ grids, const int2* 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int2 ka = key_a[i];
-    grids[0].user_unsorted[grids[0].start[ka.x] + ka.y] = i;
+    gbl(grids[0].user_unsorted)[gbl(grids[0].start)[ka.x] + ka.y] = i;
     const int2 ks = key_s[i];
-    if (ks.x >= 0) grids[1].user_unsorted[grids[1].start[ks.x] + ks.y] = i;
+    if (ks.x >= 0) gbl(grids[1].user_unsorted)[gbl(grids[1].start)[ks.x] + ks.y] = i;
 }
 
 // One wave per cell: order the members of the cell by caller index (rank by
@@ -177,24 +197,31 @@ __global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int n
                            int* __restrict__ user2arow)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
     const int nwaves = (gridDim.x * blockDim.x) / kWave;
     for (int cell = wave; cell < ncell_total; cell += nwaves) {
         const bool site = cell >= ncell_a;
         const GridDev& g = grids[site ? 1 : 0];
+        RELRES_GLOBAL const int* gstart = gbl(g.start);
+        RELRES_GLOBAL const int* guu = gbl(g.user_unsorted);
+        RELRES_GLOBAL int* guser = gbl(g.user);
+        double4* gpos = g.pos;     // vector-type stores stay generic (no LDS use here)
+        int2* gmeta = g.meta;
+        RELRES_GLOBAL int* gcell = gbl(g.row_cell);
         const int c = site ? cell - ncell_a : cell;
-        const int b = g.start[c];
-        const int len = g.start[c + 1] - b;
+        const int b = gstart[c];
+        const int len = gstart[c + 1] - b;
         if (len <= kWave) {
             // rank by counting with cross-lane reads, no memory traffic
-            const int u = lane < len ? g.user_unsorted[b + lane] : 0x7fffffff;
+            const int u = lane < len ? guu[b + lane] : 0x7fffffff;
             int r = 0;
             for (int k = 0; k < len; ++k) r += __shfl(u, k) < u;
             if (lane < len) {
                 const int dst = b + r;
-                g.user[dst] = u;
-                g.pos[dst] = wpos[u];
-                g.meta[dst] = make_int2(topo.types[u], topo.mol[u]);
+                guser[dst] = u;
+                gpos[dst] = wpos[u];
+                gmeta[dst] = make_int2(topo.types[u], topo.mol[u]);
+                gcell[dst] = c;
                 if (!site) user2arow[u] = dst;
             }
             continue;
@@ -202,17 +229,251 @@ __global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int n
         for (int base = 0; base < len; base += kWave) {
             const int t = base + lane;
             if (t < len) {
-                const int u = g.user_unsorted[b + t];
+                const int u = guu[b + t];
                 int r = 0;
-                for (int k = 0; k < len; ++k) r += g.user_unsorted[b + k] < u;
+                for (int k = 0; k < len; ++k) r += guu[b + k] < u;
                 const int dst = b + r;
-                g.user[dst] = u;
-                g.pos[dst] = wpos[u];
-                g.meta[dst] = make_int2(topo.types[u], topo.mol[u]);
+                guser[dst] = u;
+                gpos[dst] = wpos[u];
+                gmeta[dst] = make_int2(topo.types[u], topo.mol[u]);
+                gcell[dst] = c;
                 if (!site) user2arow[u] = dst;
             }
         }
     }
+}
+
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Neighbour lists, one wave per group of kRowsPerWave consecutive member rows
+// (rows are in cell order, so a group spans one or two cells).  Work per wave
+// is bounded by the group size, so crowded cells are spread over many waves.
+// Each lane owns one home row of the group: its position, exclusions and
+// running count live in that lane and are broadcast with readlane while the
+// wave tests 64 staged candidates at a time.  Only wave-level synchronisation
+// is used, so waves of one block may run different trip counts.
+constexpr int kWaveChunk = 128;
+constexpr int kRowsPerWave = 8;
+
+// Membership with the periodic shift of the candidate's stencil slot known in
+// advance.  When a grid has at least four cells along an axis, a neighbour
+// cell reached without wrapping lies within two cells (< L/2) of the home
+// atom, and one reached by wrapping lies more than L/2 away in the direction
+// of the wrap.  The single-shift recipe therefore applies exactly `shift`
+// (0 or -+L), and (x_j - x_i) + shift rounds exactly as the recipe's
+// (x_j - x_i) followed by "-= L" / "+= L".
+__device__ __forceinline__ bool member_shifted(double xi, double yi, double zi, double xj,
+                                               double yj, double zj, double sx, double sy,
+                                               double sz, double rl2)
+{
+#pragma clang fp contract(off)
+    const double dx = (xj - xi) + sx;
+    const double dy = (yj - yi) + sy;
+    const double dz = (zj - zi) + sz;
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    return r2 < rl2;
+}
+
+// Neighbour lists, one wave per group of kRowsPerWave consecutive member rows
+// (rows are in cell order, so a group spans one or two cells).  Work per wave
+// is bounded by the group size, so crowded cells are spread over many waves.
+// Each lane owns one home row of the group: its position, exclusions and
+// running count live in that lane and are broadcast with readlane while the
+// wave tests 64 staged candidates at a time.  Candidates are staged in LDS as
+// structure-of-arrays.  Only wave-level synchronisation is used, so waves of
+// one block may run different trip counts.
+__global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ grids,
+                                                    int waves_a, int waves_total, int max_excl,
+                                                    TopoDev topo,
+                                                    double Lx, double Ly, double Lz,
+                                                    const int* __restrict__ user2arow,
+                                                    int4* __restrict__ a_rec,
+                                                    int4* __restrict__ s_rec,
+                                                    Status* __restrict__ st)
+{
+    __shared__ double c_x[4][kWaveChunk], c_y[4][kWaveChunk], c_z[4][kWaveChunk];
+    __shared__ double c_sx[4][kWaveChunk], c_sy[4][kWaveChunk], c_sz[4][kWaveChunk];
+    __shared__ int c_user[4][kWaveChunk], c_type[4][kWaveChunk], c_mol[4][kWaveChunk];
+    __shared__ int cell_start[4][32], cell_pre[4][32];
+    __shared__ double slot_shift[4][27][3];
+    const int lane = threadIdx.x & (kWave - 1);
+    // wave-uniform by construction; readfirstlane lets the compiler keep it
+    // (and everything derived from it) in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int gw = blockIdx.x * 4 + wv;
+    if (gw >= waves_total) return;            // whole wave; no block barriers below
+    const bool site = gw >= waves_a;
+    const GridDev& g = grids[site ? 1 : 0];
+    const double4* gpos = g.pos;      // read through load_xyz / load_meta
+    const int2* gmeta = g.meta;
+    RELRES_GLOBAL const int* guser = gbl(g.user);
+    RELRES_GLOBAL const int* gstart = gbl(g.start);
+    RELRES_GLOBAL const int* gnbr = gbl(g.nbr);
+    RELRES_GLOBAL int* glist = gbl(g.list);
+    RELRES_GLOBAL const int* glor = gbl(g.lin_of_rank);
+    const int members = g.members;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    // known image shifts need at least four cells along every axis
+    const bool known_shift = n0 >= 4 && n1 >= 4 && n2 >= 4;
+    const int r0 = (site ? gw - waves_a : gw) * kRowsPerWave;
+    const int r1 = min(members, r0 + kRowsPerWave);
+    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+    const double rl2 = g.rl2;
+    const int cap = g.cap;
+    const int* __restrict__ excl_off = topo.excl_off;
+    const int* __restrict__ excl_idx = topo.excl_idx;
+    const int same_mol = topo.same_mol;
+    // exclusion lists of the wave's home rows, staged once (kRowsPerWave x max_excl)
+    extern __shared__ int excl_lds[];
+    int* my_excl = excl_lds + wv * kRowsPerWave * max_excl;
+
+    // lane h < (r1 - r0) owns home row r0 + h
+    const int nh = r1 - r0;
+    const int myrow = r0 + lane;
+    double mx = 0.0, my = 0.0, mz = 0.0;
+    int mt = 0, mmol = 0;
+    int mu = -1, meb = 0, mee = 0, marow = 0, mcell = -1, mcnt = 0;
+    if (lane < nh) {
+        load_xyz(gpos, myrow, mx, my, mz);
+        load_meta(gmeta, myrow, mt, mmol);
+        mu = guser[myrow];
+        mcell = gbl(g.row_cell)[myrow];
+        if (excl_off) {
+            meb = excl_off[mu];
+            mee = excl_off[mu + 1];
+            for (int k = 0; k < mee - meb; ++k) my_excl[lane * max_excl + k] = excl_idx[meb + k];
+        }
+        if (site) marow = user2arow[mu];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int h0 = 0;
+    while (h0 < nh) {
+        // rows h0 .. h1-1 share one cell
+        const int c = readlane_i(mcell, h0);
+        int h1 = h0 + 1;
+        while (h1 < nh && readlane_i(mcell, h1) == c) ++h1;
+        int cnt = 0, s0 = 0;
+        if (lane < 27) {
+            const int r = gnbr[c * 27 + lane];
+            if (r >= 0) {
+                s0 = gstart[r];
+                cnt = gstart[r + 1] - s0;
+            }
+            if (known_shift) {
+                // slot offsets are (-1, 0, 1) on every axis here
+                const int lin = glor[c];
+                const int cz = lin % n2, cy = (lin / n2) % n1, cx = lin / (n1 * n2);
+                const int ox = lane / 9 - 1, oy = (lane / 3) % 3 - 1, oz = lane % 3 - 1;
+                slot_shift[wv][lane][0] = cx + ox < 0 ? -Lx : (cx + ox >= n0 ? Lx : 0.0);
+                slot_shift[wv][lane][1] = cy + oy < 0 ? -Ly : (cy + oy >= n1 ? Ly : 0.0);
+                slot_shift[wv][lane][2] = cz + oz < 0 ? -Lz : (cz + oz >= n2 ? Lz : 0.0);
+            }
+        }
+        int pre = cnt;
+        for (int o = 1; o < 32; o <<= 1) {
+            const int v = __shfl_up(pre, o);
+            if (lane >= o) pre += v;
+        }
+        const int ncand = __builtin_amdgcn_readfirstlane(__shfl(pre, 26));
+        if (lane < 32) {
+            cell_start[wv][lane] = s0;
+            cell_pre[wv][lane] = lane < 27 ? pre - cnt : ncand;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int cb = 0; cb < ncand; cb += kWaveChunk) {
+            const int clen = min(kWaveChunk, ncand - cb);
+            for (int t = lane; t < clen; t += kWave) {
+                const int q = cb + t;
+                // last slot k with cell_pre[k] <= q (slots are sorted; empty ones repeat)
+                int lo = 0, hi = 26;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (cell_pre[wv][mid] <= q) lo = mid; else hi = mid - 1;
+                }
+                const int src = cell_start[wv][lo] + (q - cell_pre[wv][lo]);
+                double px, py, pz;
+                int pt, pm;
+                load_xyz(gpos, src, px, py, pz);
+                load_meta(gmeta, src, pt, pm);
+                c_x[wv][t] = px;
+                c_y[wv][t] = py;
+                c_z[wv][t] = pz;
+                c_user[wv][t] = guser[src];
+                c_type[wv][t] = pt;
+                c_mol[wv][t] = pm;
+                if (known_shift) {
+                    c_sx[wv][t] = slot_shift[wv][lo][0];
+                    c_sy[wv][t] = slot_shift[wv][lo][1];
+                    c_sz[wv][t] = slot_shift[wv][lo][2];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int h = h0; h < h1; ++h) {
+                const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
+                const int ui = readlane_i(mu, h);
+                const int moli = readlane_i(mmol, h);
+                const int ne = readlane_i(mee, h) - readlane_i(meb, h);
+                const int* hex = my_excl + h * max_excl;
+                int hc = readlane_i(mcnt, h);
+                RELRES_GLOBAL int* out = glist + (size_t)(r0 + h) * cap;
+                for (int base = 0; base < clen; base += kWave) {
+                    const int t = base + lane;
+                    bool keep = false;
+                    uint32_t entry = 0u;
+                    if (t < clen) {
+                        const int uj = c_user[wv][t];
+                        keep = uj != ui && !(same_mol && c_mol[wv][t] == moli);
+                        for (int k = 0; k < ne; ++k)
+                            if (hex[k] == uj) keep = false;
+                        if (keep) {
+                            if (known_shift)
+                                keep = member_shifted(xi, yi, zi, c_x[wv][t], c_y[wv][t],
+                                                      c_z[wv][t], c_sx[wv][t], c_sy[wv][t],
+                                                      c_sz[wv][t], rl2);
+                            else
+                                keep = member(make_double4(xi, yi, zi, 0.0),
+                                              make_double4(c_x[wv][t], c_y[wv][t], c_z[wv][t], 0.0),
+                                              Lx, Ly, Lz, hx, hy, hz, rl2);
+                        }
+                        entry = (uint32_t)uj | ((uint32_t)c_type[wv][t] << kIdxBits);
+                    }
+                    const uint64_t mask = __ballot(keep);
+                    if (keep) {
+                        const int p = hc + lanes_below(mask);
+                        if (p < cap) out[p] = (int)entry;
+                    }
+                    hc += __popcll(mask);
+                }
+                if (lane == h) mcnt = hc;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        h0 = h1;
+    }
+    if (lane < nh) {
+        gbl(g.nrow)[myrow] = mcnt;
+        const int stored = min(mcnt, cap);
+        if (site) s_rec[myrow] = make_int4(mu, mt, stored, marow);
+        else a_rec[myrow] = make_int4(mu, mt, stored, topo.hybrid[mt]);
+    }
+    // only a row that outgrew its capacity touches the status word (rare), so
+    // thousands of waves do not serialise on one address
+    if (lane < nh && mcnt > cap) atomicMax(&st->max_row[site ? 1 : 0], mcnt);
 }
 
 // Neighbour lists: one block per home cell (atom-grid cells first, then
@@ -243,25 +504,16 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
     const int nw = blockDim.x / kWave;
 
     if (threadIdx.x < 27) {
-        // one lane per stencil cell: deduplicated offsets, neighbour rank, range
+        // one lane per stencil slot: neighbour rank from the host-built table
         const int t = threadIdx.x;
-        const int ix = t / 9, iy = (t / 3) % 3, iz = t % 3;
-        const bool used = ix < g.noff[0] && iy < g.noff[1] && iz < g.noff[2];
-        int cnt = 0, s0 = 0;
-        if (used) {
-            const int lin = g.lin_of_rank[c];
-            const int cz = lin % g.n[2];
-            const int cy = (lin / g.n[2]) % g.n[1];
-            const int cx = lin / (g.n[1] * g.n[2]);
-            const int nx = (cx + g.off[0][ix] + g.n[0]) % g.n[0];
-            const int ny = (cy + g.off[1][iy] + g.n[1]) % g.n[1];
-            const int nz = (cz + g.off[2][iz] + g.n[2]) % g.n[2];
-            const int r = g.rank_of_lin[(nx * g.n[1] + ny) * g.n[2] + nz];
+        const int r = g.nbr[c * 27 + t];
+        int cnt = -1, s0 = 0;
+        if (r >= 0) {
             s0 = g.start[r];
             cnt = g.start[r + 1] - s0;
         }
         cell_start[t] = s0;
-        cell_cnt[t] = used ? cnt : -1;
+        cell_cnt[t] = cnt;
     }
     if (threadIdx.x == 0) {
         blk_max = 0;
@@ -310,11 +562,12 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
                 const double4 pi = g.pos[row];
                 const int2 mi = g.meta[row];
                 const int ui = g.user[row];
-                int eb = 0, ee = 0;
+                int eb = 0, ne = 0;
                 if (topo.excl_off) {
                     eb = topo.excl_off[ui];
-                    ee = topo.excl_off[ui + 1];
+                    ne = min(topo.excl_off[ui + 1] - eb, kWave);
                 }
+                const int myex = lane < ne ? topo.excl_idx[eb + lane] : -1;
                 int cnt = home_cnt[h];
                 int* out = g.list + (size_t)row * cap;
                 for (int base = 0; base < clen; base += kWave) {
@@ -325,8 +578,8 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
                         const int uj = c_user[t];
                         const int2 mj = c_meta[t];
                         keep = uj != ui && !(topo.same_mol && mj.y == mi.y);
-                        for (int k = eb; k < ee; ++k)
-                            if (topo.excl_idx[k] == uj) keep = false;
+                        for (int k = 0; k < ne; ++k)
+                            if (__shfl(myex, k) == uj) keep = false;
                         if (keep) keep = member(pi, c_pos[t], Lx, Ly, Lz, hx, hy, hz, rl2);
                         entry = (uint32_t)uj | ((uint32_t)mj.x << kIdxBits);
                     }
@@ -356,10 +609,42 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && he > hb) {
-        const int slot = blockIdx.x % kStatSlots;
-        atomicMax(&st->max_row[site ? 1 : 0][slot], blk_max);
-        atomicAdd(&st->entries[site ? 1 : 0][slot], blk_sum);
+    if (threadIdx.x == 0 && blk_max > cap) atomicMax(&st->max_row[site ? 1 : 0], blk_max);
+}
+
+// Exact list statistics on demand: entries (sum of row lengths) and the
+// longest row of each grid.  One block per grid.
+__global__ __launch_bounds__(256) void k_list_stats(const GridDev* __restrict__ grids,
+                                                    Status* __restrict__ st)
+{
+    __shared__ unsigned long long ssum[256 / kWave];
+    __shared__ int smax[256 / kWave];
+    const GridDev& g = grids[blockIdx.x];
+    unsigned long long sum = 0ull;
+    int mx = 0;
+    RELRES_GLOBAL const int* gnrow = gbl(g.nrow);
+    for (int r = threadIdx.x; r < g.members; r += blockDim.x) {
+        const int c = gnrow[r];
+        sum += (unsigned long long)c;
+        mx = max(mx, c);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o);
+        mx = max(mx, __shfl_xor(mx, o));
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane == 0) {
+        ssum[wave] = sum;
+        smax[wave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / kWave; ++w) {
+            ssum[0] += ssum[w];
+            smax[0] = max(smax[0], smax[w]);
+        }
+        st->entries[blockIdx.x] = ssum[0];
+        st->longest[blockIdx.x] = smax[0];
     }
 }
 
@@ -369,7 +654,16 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
 
 template <typename S> __device__ __forceinline__ S rcp(S x);
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+// FP64 reciprocal: hardware estimate refined by two Newton steps (each at
+// least doubles the number of correct bits), within about one ulp.
+template <> __device__ __forceinline__ double rcp<double>(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 template <typename S> __device__ __forceinline__ S sqrt_(S x);
 template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double sqrt_<double>(double x) { return sqrt(x); }
@@ -521,6 +815,111 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Publishes 8 doubles (threads 0..7 hold one each) with agent-scope stores,
+// which are written through to the level shared by all XCDs, waits until they
+// are acknowledged, and takes a ticket on `counter`.  True in every thread of
+// the block that took the last of `expected` tickets.  Relaxed atomics plus an
+// explicit wait avoid the L2 writeback an agent-scope release fence costs.
+__device__ __forceinline__ bool publish_and_ticket(double* dst, double v, unsigned int* counter,
+                                                   unsigned int expected, int* flag)
+{
+    if (threadIdx.x < 8) {
+        __hip_atomic_store(dst + threadIdx.x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the stores (wave 0) must be acknowledged before wave 0 takes the ticket
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        const bool last = t == expected - 1;
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *flag = last;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+__device__ __forceinline__ double load_agent(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sums 8 values per item over items 0..count-1 (item i at base + i*stride*8)
+// in a fixed order; the result is in red[k][0] .. combined by thread 0.
+__device__ void block_sum8(const double* base, int count, int stride, double (*red)[kForceBlock / 64],
+                           double out[8])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < count; i += kForceBlock) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = load_agent(base + (size_t)i * stride * 8 + k);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] += t[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double w = wave_sum(v[k]);
+        if (lane == 0) red[k][wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int w = 0; w < kForceBlock / 64; ++w) t += red[threadIdx.x][w];
+        out[0] = t;
+    }
+    __syncthreads();
+}
+
+// Energy/virial reduction of one force launch, deterministic and in one pass:
+// every block publishes its 8 partial sums; the last block of each XCD group
+// (blocks b with b % 8 == g, which the hardware places on one XCD) adds that
+// group's partials in block order and publishes the group sum; the last group
+// adds the 8 group sums in group order and writes energy and virial.  Two
+// levels of tickets keep the contention on any one counter to ~nb/8 blocks.
+__device__ void ew_finish(const ForceArgs& a, const double acc[8])
+{
+    __shared__ double red[8][kForceBlock / 64];
+    __shared__ int flag;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double w = wave_sum(acc[k]);
+        if (lane == 0) red[k][wave] = w;
+    }
+    __syncthreads();
+    double mine = 0.0;
+    if (threadIdx.x < 8)
+        for (int w = 0; w < kForceBlock / 64; ++w) mine += red[threadIdx.x][w];
+    __syncthreads();
+
+    const int nb = (int)gridDim.x;
+    const int g = (int)blockIdx.x % kXcdGroups;
+    const int ngroups = nb < kXcdGroups ? nb : kXcdGroups;
+    const int gsize = (nb - g + kXcdGroups - 1) / kXcdGroups;
+    if (!publish_and_ticket(a.partials + (size_t)blockIdx.x * 8, mine,
+                            a.counter + g * kTicketStride, (unsigned)gsize, &flag))
+        return;
+    double gsum[1];
+    block_sum8(a.partials + (size_t)g * 8, gsize, kXcdGroups, red, gsum);
+    double* gpart = a.partials + (size_t)nb * 8;
+    if (!publish_and_ticket(gpart + (size_t)g * 8, gsum[0], a.counter + kXcdGroups * kTicketStride,
+                            (unsigned)ngroups, &flag))
+        return;
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int q = 0; q < ngroups; ++q) t += load_agent(gpart + (size_t)q * 8 + threadIdx.x);
+        if (threadIdx.x == 0 && a.energy) a.energy[1] = t;
+        if (threadIdx.x == 1 && a.energy) a.energy[2] = t;
+        if (threadIdx.x >= 2 && a.virial) a.virial[threadIdx.x - 2] = t;
+        red[threadIdx.x][0] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && a.energy) a.energy[0] = red[0][0] + red[1][0];
+}
+
 template <typename S, typename TF, bool EW, bool LDS>
 __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> cut,
                                                        Cutoffs<double> cut64)
@@ -591,59 +990,9 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         F[3 * rec.x + 1] = fy;
         F[3 * rec.x + 2] = fz;
     }
-    if constexpr (EW) {
-        // per-block partial sums in a fixed order; k_reduce_ew adds the blocks
-        __shared__ double red[8][kForceBlock / kWave];
-        const int lane = threadIdx.x & (kWave - 1);
-        const int wave = threadIdx.x / kWave;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double v = wave_sum(acc[k]);
-            if (lane == 0) red[k][wave] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < 8) {
-            double t = 0.0;
-            for (int w = 0; w < kForceBlock / kWave; ++w) t += red[threadIdx.x][w];
-            a.partials[(size_t)blockIdx.x * 8 + threadIdx.x] = t;
-        }
-    }
+    if constexpr (EW) ew_finish(a, acc);
 }
 
-// Sum of the per-block partials in block order: energy {FG+CG, FG, CG} and the
-// six virial components.  One block; deterministic.
-__global__ __launch_bounds__(256) void k_reduce_ew(const double* __restrict__ partials, int blocks,
-                                                   double* __restrict__ energy,
-                                                   double* __restrict__ virial)
-{
-    __shared__ double red[8][256 / kWave];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < blocks; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) s[k] += partials[(size_t)b * 8 + k];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double v = wave_sum(s[k]);
-        if (lane == 0) red[k][wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t[8];
-        for (int k = 0; k < 8; ++k) {
-            t[k] = 0.0;
-            for (int w = 0; w < 256 / kWave; ++w) t[k] += red[k][w];
-        }
-        if (energy) {
-            energy[0] = t[0] + t[1];
-            energy[1] = t[0];
-            energy[2] = t[1];
-        }
-        if (virial)
-            for (int k = 0; k < 6; ++k) virial[k] = t[2 + k];
-    }
-}
 
 __global__ void k_zero_outputs(double* energy, double* virial)
 {
@@ -704,10 +1053,21 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, con
     return hipGetLastError();
 }
 
-hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, TopoDev topo,
-                        const double box[3], const int* user2arow, int4* a_rec, int4* s_rec,
-                        Status* st, hipStream_t s)
+hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int members_a,
+                        int members_s, TopoDev topo, const double box[3], const int* user2arow,
+                        int4* a_rec, int4* s_rec, Status* st, bool per_wave, hipStream_t s)
 {
+    if (per_wave) {
+        const int wa = (members_a + kRowsPerWave - 1) / kRowsPerWave;
+        const int total = wa + (members_s + kRowsPerWave - 1) / kRowsPerWave;
+        if (total == 0) return hipSuccess;
+        const int mx = topo.excl_off ? topo.max_excl : 0;
+        const size_t dyn = sizeof(int) * 4 * kRowsPerWave * (size_t)mx;
+        hipLaunchKernelGGL(k_lists_wave, dim3((total + 3) / 4), dim3(256), dyn, s, grids_dev,
+                           wa, total, mx, topo, box[0], box[1], box[2], user2arow, a_rec, s_rec,
+                           st);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_lists, dim3(ncell_a + ncell_s), dim3(kListBlock), 0, s, grids_dev,
                        ncell_a, topo, box[0], box[1], box[2], user2arow, a_rec, s_rec, st);
     return hipGetLastError();
@@ -735,10 +1095,12 @@ hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math,
         if (ew) RELRES_LAUNCH(float, float, true); else RELRES_LAUNCH(float, float, false);
     }
 #undef RELRES_LAUNCH
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !ew) return e;
-    hipLaunchKernelGGL(k_reduce_ew, dim3(1), dim3(256), 0, s, a.partials,
-                       a.blocks_a + a.blocks_b, a.energy, a.virial);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_list_stats, dim3(ngrids), dim3(256), 0, s, grids_dev, st);
     return hipGetLastError();
 }
 

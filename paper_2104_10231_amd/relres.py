@@ -43,7 +43,7 @@ class Stats(ctypes.Structure):
                 ("atom_capacity", ctypes.c_int), ("site_capacity", ctypes.c_int),
                 ("atom_cells", ctypes.c_int * 3), ("site_cells", ctypes.c_int * 3),
                 ("builds", ctypes.c_longlong), ("regrows", ctypes.c_longlong),
-                ("box", ctypes.c_double * 3)]
+                ("box", ctypes.c_double * 3), ("generation", ctypes.c_longlong)]
 
 
 # exported symbol -> (restype, argtypes); mirrors include/relres.h
@@ -61,6 +61,7 @@ SIGNATURES = {
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "relres_list_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "relres_generation": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]),
     "relres_get_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     "relres_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -208,6 +209,12 @@ class RelRes:
         for k in ("atom_cells", "site_cells", "box"):
             d[k] = list(d[k])
         return d
+
+    def generation(self) -> int:
+        """Buffer generation: a captured graph stays valid while it is unchanged."""
+        g = ctypes.c_longlong()
+        _check(self._lib.relres_generation(self._ctx, ctypes.byref(g)), "relres_generation")
+        return g.value
 
     def pairs(self, which: int) -> np.ndarray:
         n = ctypes.c_longlong()

@@ -255,4 +255,59 @@ def test_errors_are_reported():
     with pytest.raises(RelResError) as e:
         rr.set_topology(np.full(s.n, 5, np.int32), s.mol)
     assert e.value.code == -4
+    # more excluded partners per atom than the builder holds
+    many = [j for j in range(1, 66)]
+    offs = np.array([0, len(many)] + [len(many)] * (s.n - 1), np.int32)
+    with pytest.raises(RelResError) as e:
+        rr.set_topology(s.types, s.mol, False, offs, np.array(many, np.int32))
+    assert e.value.code == -4
+    rr.close()
+
+
+def test_crowded_cells_need_several_passes():
+    """Cells holding more than 64 atoms while the mean occupancy is low: the
+    one-wave-per-cell builder loops over home atoms in passes of 64."""
+    s = w.random_molecules(17, 80, 15.0, kind="propane", min_dist=2.0)
+    big = s.replace(pos=s.pos + 20.0, box=np.full(3, 60.0), skin=8.0)
+    rr, F, E, W = gpu_run(big, 64)
+    st = rr.stats()
+    assert st["atom_max_row"] > 64
+    Fr, Er, Wr = oracle.compute(big)
+    assert rel_rms(F, Fr) <= 1e-11 and abs(E[0] - Er[0]) <= 1e-12 * abs(Er[0])
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(big, which))
+    rr.close()
+
+
+def test_graph_replay_matches_eager():
+    """relres_forces captured in a HIP graph: every replay, with eager library
+    work and synchronisation in between, reproduces the eager results bitwise."""
+    import torch
+    s = w.neopentane_liquid(2)
+    rr = make_relres(s)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)
+    F, E, W = rr.forces(p)                     # warm-up: sizes internal buffers
+    F0, E0, W0 = [t.clone() for t in rr.forces(p)]
+    gen = rr.generation()
+    assert gen == rr.stats()["generation"]
+    Fg = torch.empty_like(F0)
+    Eg = torch.empty_like(E0)
+    Wg = torch.empty_like(W0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(3):
+            rr.forces(p, out=Fg, energy=Eg, virial=Wg)
+    for rep in range(4):
+        Fg.zero_(); Eg.zero_(); Wg.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Fg, F0) and torch.equal(Eg, E0) and torch.equal(Wg, W0), rep
+        # eager work in between replays
+        F1, E1, W1 = rr.forces(p)
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F0)
+        rr.build_lists(p, s.box)
+        assert rr.generation() == gen
     rr.close()
