@@ -6,7 +6,10 @@ r_s-/r_s+/r_c-/r_c+ = 5.5/6.0/12.0/14.0 A, skin 2 A.  One step = one force
 call (forces, energy and virial) on the resident positions; the neighbour
 lists are rebuilt every 10 steps inside the timed region.  The same protocol
 is then run for the conventional all-FG system (r_s -> r_c, list at 16 A),
-and the oracle is timed on the host for the CPU baseline.
+and the oracle is timed on the host for the CPU baseline.  Builds are enqueued
+without waiting and their overflow status is checked after the force calls
+behind them were enqueued; an overflowed build is redone inside the timed
+region together with its force calls.
 
 Prints ONE JSON line (rank 0).  value = RelRes atom-steps/s on this GPU.
 """
@@ -62,6 +65,7 @@ class Stepper:
         self.E = torch.empty(3, dtype=torch.float64, device=pos.device)
         self.W = torch.empty(6, dtype=torch.float64, device=pos.device)
         self.graph, self.graph_gen, self.graph_len = None, None, 0
+        self.redone = 0
 
     def force(self):
         self.rr.forces(self.pos, out=self.F, energy=self.E, virial=self.W)
@@ -79,35 +83,68 @@ class Stepper:
             self.graph, self.graph_gen, self.graph_len = g, gen, n
         return self.graph
 
+    def _forces(self, n):
+        if self.use_graph:
+            self._graph(n).replay()
+        else:
+            for _ in range(n):
+                self.force()
+
     def run(self, steps):
+        """The build is enqueued without waiting and checked after the force
+        calls behind it were enqueued (the check waits for the build only), so
+        the GPU never idles on the host.  A build whose rows overflowed is
+        redone, with the force calls that used it."""
         k = 0
         while k < steps:
             n = min(self.every, steps - k)
-            self.rr.build_lists(self.pos, self.box)
-            if self.use_graph:
-                self._graph(n).replay()
-            else:
-                for _ in range(n):
-                    self.force()
+            self.rr.build_lists(self.pos, self.box, wait=False)
+            self._forces(n)
+            if not self.rr.check_lists():
+                self.redone += 1
+                self.rr.build_lists(self.pos, self.box)
+                self._forces(n)
             k += n
 
 
-def run_protocol(rr, pos, box, steps, warmup, rebuild_every, timing=False, use_graph=True):
+def run_protocol(rr, pos, box, steps, warmup, rebuild_every, use_graph=True):
     import torch
-    st = Stepper(rr, pos, box, rebuild_every, use_graph and not timing)
+    st = Stepper(rr, pos, box, rebuild_every, use_graph)
     st.run(max(warmup, rebuild_every))
     torch.cuda.synchronize()
-    if timing:
-        rr.set_timing(True)
-        rr.timing()                     # reset counters
     t0 = time.perf_counter()
     st.run(steps)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    tm = rr.timing() if timing else None
-    if timing:
-        rr.set_timing(False)
-    return dt, tm, (st.F, st.E, st.W)
+    return time.perf_counter() - t0, st
+
+
+def time_kernels(rr, pos, box, force_calls, builds=20):
+    """Average device time of one force launch (forces, energy, virial) and of
+    one list build.  Force launches: HIP events on the launch stream around
+    replays of a graph of 10 back-to-back launches, so host overhead never
+    leaves the GPU idle inside the bracket.  Builds: the library's own events
+    around the build's kernels."""
+    import torch
+    st = Stepper(rr, pos, box, 10, True)
+    rr.build_lists(pos, box)
+    g = st._graph(10)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, force_calls // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    force_us = e0.elapsed_time(e1) * 1e3 / (10 * reps)
+    rr.set_timing(True)
+    rr.timing()
+    for _ in range(builds):
+        rr.build_lists(pos, box)
+    tm = rr.timing()
+    rr.set_timing(False)
+    return force_us, 1e3 * tm["build_ms"] / max(1, tm["build_calls"])
 
 
 def cpu_baseline(sys_, budget_s):
@@ -143,6 +180,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every force call eagerly instead of replaying a HIP graph")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="finish with 5 device-to-device copies of this many MiB (a kernel "
+                         "of known traffic for scaling HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -166,37 +206,45 @@ def main():
     if args.lanes:
         rr.set_launch(*args.lanes)
     use_graph = not args.no_graph
-    dt, _, _ = run_protocol(rr, pos, s.box, args.steps, args.warmup, args.rebuild_every,
-                            use_graph=use_graph)
+    dt, stp = run_protocol(rr, pos, s.box, args.steps, args.warmup, args.rebuild_every,
+                           use_graph=use_graph)
     st = rr.stats()
     value = s.n * args.steps / dt
     log(f"[bench] RelRes: {dt * 1e3 / args.steps:.4f} ms/step, {value:.4e} atom-steps/s; "
-        f"atom entries {st['atom_entries']}, site entries {st['site_entries']}")
-    # roofline leg: same protocol with HIP events around every force launch
-    dt_t, tm, _ = run_protocol(rr, pos, s.box, args.steps, 0, args.rebuild_every, timing=True)
-    force_us = 1e3 * tm["force_ms"] / max(1, tm["force_calls"])
-    build_us = 1e3 * tm["build_ms"] / max(1, tm["build_calls"])
+        f"atom entries {st['atom_entries']}, site entries {st['site_entries']}, "
+        f"builds redone {stp.redone}")
+    # roofline leg: device time of the force launch
+    force_us, build_us = time_kernels(rr, pos, s.box, args.steps)
     fb = 4 if precision == 32 else 8
     abytes = algorithmic_bytes(st, fb)
     achieved = abytes / (force_us * 1e-6) / 1e9
-    log(f"[bench] force kernel {force_us:.2f} us/launch (HIP events), build {build_us:.1f} us; "
-        f"algorithmic {abytes / 1e6:.3f} MB/launch -> {achieved:.1f} GB/s")
+    log(f"[bench] force launch {force_us:.2f} us (HIP events, graph of back-to-back launches), "
+        f"build {build_us:.1f} us; algorithmic {abytes / 1e6:.3f} MB/launch -> {achieved:.1f} GB/s")
     rr.close()
 
     conv = None
     if not args.no_conventional:
         sc = s.conventional()
         rc = make(sc, precision, args.pair_math)
-        dtc, _, _ = run_protocol(rc, pos, sc.box, args.steps, args.warmup, args.rebuild_every,
-                                 use_graph=use_graph)
+        dtc, _ = run_protocol(rc, pos, sc.box, args.steps, args.warmup, args.rebuild_every,
+                              use_graph=use_graph)
         stc = rc.stats()
-        _, tmc, _ = run_protocol(rc, pos, sc.box, args.steps, 0, args.rebuild_every, timing=True)
+        fc_us, bc_us = time_kernels(rc, pos, sc.box, args.steps)
         rc.close()
         conv = dict(value=s.n * args.steps / dtc, ms_per_step=dtc * 1e3 / args.steps,
-                    force_us=1e3 * tmc["force_ms"] / max(1, tmc["force_calls"]),
-                    atom_entries=stc["atom_entries"])
+                    force_us=fc_us, build_us=bc_us, atom_entries=stc["atom_entries"])
         log(f"[bench] conventional: {conv['ms_per_step']:.4f} ms/step, {conv['value']:.4e} "
-            f"atom-steps/s, force kernel {conv['force_us']:.2f} us, entries {stc['atom_entries']}")
+            f"atom-steps/s, force launch {fc_us:.2f} us, build {bc_us:.1f} us, "
+            f"entries {stc['atom_entries']}")
+
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 5 x {nbytes} B read + {nbytes} B written")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(s, args.cpu_budget)
     if cpu:
@@ -229,6 +277,8 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "k_forces", "kernel_us": force_us,
+            "kernel_us_method": "HIP events on the launch stream around replays of a graph of "
+                                "10 back-to-back force launches",
             "algorithmic_bytes_per_launch": abytes,
         },
         "cpu_baseline": cpu,

@@ -53,6 +53,7 @@ extern "C" {
 #define RELRES_ERR_LIST_OVERFLOW   -7  /* list capacity could not be grown   */
 #define RELRES_ERR_NONFINITE       -8  /* a position was NaN or infinite     */
 #define RELRES_ERR_STATE           -9  /* call out of order                  */
+#define RELRES_ERR_LIST_RETRY     -10  /* asynchronous build overflowed: rows grown, build again */
 
 #define RELRES_MIX_GEOMETRIC   0   /* eps, sigma geometric means (Sec. 2.3)    */
 #define RELRES_MIX_ARITHMETIC  1   /* Lorentz-Berthelot: sigma arithmetic mean */
@@ -132,6 +133,24 @@ int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const in
  * the list capacity; grows the lists and rebuilds when a row overflowed.    */
 int relres_build_lists(relres_ctx *ctx, const double *pos, const double box[3], void *stream);
 
+/* The same build without waiting: everything is enqueued on `stream`, and
+ * relres_forces may be enqueued behind it at once.  The lists are only known
+ * to be complete once relres_check_lists has returned RELRES_OK; results
+ * computed from them before that must be discarded if it does not.  The first
+ * build of a context, and any build after the cell grid or the capacities
+ * changed, waits as relres_build_lists does.  A status left unexamined is
+ * examined by the next build, relres_list_stats or relres_get_pairs (which
+ * then report its non-finite-position error).                              */
+int relres_build_lists_async(relres_ctx *ctx, const double *pos, const double box[3],
+                             void *stream);
+
+/* Waits for the status of the last build and examines it: RELRES_OK when the
+ * lists are complete, RELRES_ERR_NONFINITE for a NaN/inf position, or
+ * RELRES_ERR_LIST_RETRY when a row overflowed its capacity: the capacity has
+ * been grown and the lists are invalid until the next build.  Waits only for
+ * the build itself, not for work enqueued after it.                        */
+int relres_check_lists(relres_ctx *ctx);
+
 /* Forces, energy and virial for device positions pos (N x 3 FP64) using the
  * lists of the last build (and its box).  forces: device N x 3, double* when
  * precision == 64, float* when 32; overwritten.  energy: device double[3] =
@@ -163,8 +182,8 @@ int relres_get_pairs(relres_ctx *ctx, int which, int *pairs_host, long long cap,
 int relres_set_launch(relres_ctx *ctx, int lanes_atom, int lanes_site);
 
 /* With enable != 0, HIP events are recorded on the caller's stream right
- * before and after every launch of the force kernel (the energy/virial
- * reduction that follows it is outside the pair) and around every list build.
+ * before and after every launch of the force kernel (which includes the
+ * energy/virial reduction) and around every list build.
  * relres_get_timing synchronises, returns the accumulated milliseconds and
  * launch counts since the previous call, and resets them.                  */
 int relres_set_timing(relres_ctx *ctx, int enable);

@@ -184,9 +184,13 @@ struct relres_ctx {
     bool stats_fresh = false;         // statistics describe the current lists
     bool lanes_stale = true;          // automatic lane counts need a refresh
     bool built = false;
+    bool check_pending = false;       // a build's status has not been examined yet
+    hipEvent_t ev_status = nullptr;   // recorded after a build's status copy
+    hipEvent_t ev_upload = nullptr;   // recorded after the descriptor upload
+    bool upload_pending = false;
     double box[3] = {0, 0, 0};
 
-    DBuf d_partials, d_counter;
+    DBuf d_partials, d_epoch;
     int lanes_a = 0, lanes_b = 0;        // caller override, 0 = automatic
     int auto_la = 4, auto_lb = 16;
 
@@ -362,14 +366,17 @@ TopoDev topo_of(relres_ctx* c)
 }
 
 // Copy the grid descriptors to the device when they changed since the last
-// upload (new box, cell counts, capacities or buffers).  The staging buffer is
-// reused only after the stream has been synchronised (every build ends so).
+// upload (new box, cell counts, capacities or buffers).  The pinned staging
+// buffer is rewritten only once the previous upload from it has completed.
 int upload_grids(relres_ctx* c, hipStream_t s)
 {
     GridDev want[2] = {c->ga.dev, c->n_sites > 0 ? c->gs.dev : c->ga.dev};
     if (c->grids_valid && std::memcmp(want, c->uploaded, sizeof want) == 0) return RELRES_OK;
+    if (c->upload_pending) HIP_TRY(hipEventSynchronize(c->ev_upload));
     std::memcpy(c->h_grids, want, sizeof want);
     HIP_TRY(hipMemcpyAsync(c->d_grids.p, c->h_grids, sizeof want, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(c->ev_upload, s));
+    c->upload_pending = true;
     std::memcpy(c->uploaded, want, sizeof want);
     c->grids_valid = true;
     return RELRES_OK;
@@ -413,17 +420,141 @@ bool lists_per_wave(const relres_ctx* c)
     return m <= 64.0;
 }
 
-int run_lists(relres_ctx* c, hipStream_t s)
+// Enqueue one list build on `s`: bin, scan, scatter, cell sort, lists, then a
+// copy of the status word to pinned host memory and an event.  Nothing waits;
+// relres_forces may be enqueued behind it at once.  The lists are complete
+// unless examine_status() later reports an overflow.
+int enqueue_build(relres_ctx* c, const double* pos, const double box[3], hipStream_t s)
 {
-    TRY(upload_grids(c, s));
-    // only the list statistics are cleared; the non-finite counter is cumulative
-    c->h_zero->nonfinite = c->h_status->nonfinite;
-    HIP_TRY(hipMemcpyAsync(c->d_status.p, c->h_zero, sizeof(Status), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_lists(c->d_grids.as<GridDev>(), c->ga.ncell, c->n_sites > 0 ? c->gs.ncell : 0,
-                         c->n, c->n_sites, topo_of(c), c->box, c->d_user2arow.as<int>(), c->d_a_rec.as<int4>(),
-                         c->d_s_rec.as<int4>(), c->d_status.as<Status>(), lists_per_wave(c), s));
-    HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
+    if (!box) return fail(RELRES_ERR_ARG, "box is NULL");
+    if (c->n > 0 && !pos) return fail(RELRES_ERR_ARG, "pos is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!(std::isfinite(box[k]) && box[k] > 0.0)) return fail(RELRES_ERR_ARG, "bad box edge %g", box[k]);
+    const double rla = c->rso + c->skin, rls = c->rco + c->skin;
+    const bool sites = c->n_sites > 0;
+    const double rmax = sites ? rls : rla;
+    for (int k = 0; k < 3; ++k)
+        if (!(box[k] > 2.0 * rmax))
+            return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g must exceed 2 x %g", box[k], rmax);
+    c->built = false;
+    std::copy(box, box + 3, c->box);
+    const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
+    TRY(setup_grid(c->ga, rla, box, c->n, &c->alloc_generation));
+    if (sites) TRY(setup_grid(c->gs, rls, box, c->n_sites, &c->alloc_generation));
+    if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
+    TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_key_a, sizeof(int2) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_key_s, sizeof(int2) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_user2arow, sizeof(int) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n), &c->alloc_generation));
+    TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites), &c->alloc_generation));
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        TRY(take_events(c, e0, e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    if (c->n > 0) {
+        TRY(upload_grids(c, s));
+        const TopoDev topo = topo_of(c);
+        GridDev* gd = c->d_grids.as<GridDev>();
+        HIP_TRY(launch_bin(c->n, pos, box, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
+                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), s));
+        HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
+        HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
+        const int ncs = sites ? c->gs.ncell : 0;
+        HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
+                                c->d_user2arow.as<int>(), s));
+        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->n, c->n_sites, topo, box,
+                             c->d_user2arow.as<int>(),
+                             c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
+                             c->d_status.as<Status>(), lists_per_wave(c), s));
+        HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(c->ev_status, s));
+        c->check_pending = true;
+    }
+    if (c->timing) {
+        HIP_TRY(hipEventRecord(e1, s));
+        c->ev_build.push_back({e0, e1});
+    }
+    relres_stats& st = c->stats;
+    st.n_atoms = c->n;
+    st.n_sites = c->n_sites;
+    for (int k = 0; k < 3; ++k) {
+        st.atom_cells[k] = c->ga.n[k];
+        st.site_cells[k] = sites ? c->gs.n[k] : 0;
+        st.box[k] = box[k];
+    }
+    st.builds++;
+    c->stats_fresh = false;
+    c->built = true;
+    return RELRES_OK;
+}
+
+// Wait for the status of the last enqueued build and examine it.  Returns
+// RELRES_OK (lists complete), RELRES_ERR_NONFINITE, or RELRES_ERR_LIST_RETRY
+// after growing the capacities of the rows that overflowed (the lists are
+// then invalid until the next build).
+int examine_status(relres_ctx* c)
+{
+    if (!c->check_pending) return c->built ? RELRES_OK : fail(RELRES_ERR_NO_LISTS, "no lists");
+    HIP_TRY(hipEventSynchronize(c->ev_status));
+    c->check_pending = false;
+    const Status& st = *c->h_status;
+    if (st.nonfinite != c->nonfinite_seen) {
+        c->nonfinite_seen = st.nonfinite;
+        c->built = false;
+        return fail(RELRES_ERR_NONFINITE, "non-finite position");
+    }
+    const bool sites = c->n_sites > 0;
+    const int mr_a = st.max_row[0], mr_s = st.max_row[1];
+    const bool ov_a = mr_a > c->ga.cap;
+    const bool ov_s = sites && mr_s > c->gs.cap;
+    if (!ov_a && !ov_s) return RELRES_OK;
+    if (ov_a) {
+        c->ga.cap = ((int)(mr_a * 1.25) + 8 + 7) & ~7;
+        TRY(setup_grid(c->ga, c->rso + c->skin, c->box, c->n, &c->alloc_generation));
+    }
+    if (ov_s) {
+        c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
+        TRY(setup_grid(c->gs, c->rco + c->skin, c->box, c->n_sites, &c->alloc_generation));
+    }
+    c->stats.regrows++;
+    c->lanes_stale = true;
+    c->built = false;
+    return fail(RELRES_ERR_LIST_RETRY, "list rows overflowed (atom %d/%d, site %d/%d); capacity grown",
+                mr_a, c->ga.cap, mr_s, sites ? c->gs.cap : 0);
+}
+
+// Consume a pending status before a new build replaces it: an overflow only
+// matters for its capacity growth, which examine_status already applied.
+int drain_check(relres_ctx* c)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    const int rc = examine_status(c);
+    return (rc == RELRES_ERR_LIST_RETRY || rc == RELRES_ERR_NO_LISTS) ? RELRES_OK : rc;
+}
+
+// Build, wait, and rebuild with grown rows until the lists are complete.
+int build_checked(relres_ctx* c, const double* pos, const double box[3], hipStream_t s)
+{
+    TRY(drain_check(c));
+    int rc = RELRES_ERR_LIST_RETRY;
+    for (int attempt = 0; attempt < 4 && rc == RELRES_ERR_LIST_RETRY; ++attempt) {
+        TRY(enqueue_build(c, pos, box, s));
+        rc = examine_status(c);
+    }
+    if (rc == RELRES_ERR_LIST_RETRY) return fail(RELRES_ERR_LIST_OVERFLOW, "list capacity did not converge");
+    if (rc != RELRES_OK) return rc;
+    relres_stats& st = c->stats;
+    st.atom_capacity = c->ga.cap;
+    st.site_capacity = c->n_sites > 0 ? c->gs.cap : 0;
+    if (c->lanes_stale) {
+        TRY(refresh_list_stats(c, s));
+        c->lanes_stale = false;
+    }
     return RELRES_OK;
 }
 
@@ -452,6 +583,7 @@ const char* relres_strerror(int code)
     case RELRES_ERR_LIST_OVERFLOW: return "neighbour list capacity could not be grown";
     case RELRES_ERR_NONFINITE: return "non-finite position";
     case RELRES_ERR_STATE: return "call out of order";
+    case RELRES_ERR_LIST_RETRY: return "neighbour lists overflowed: capacity grown, build again";
     default: return "unknown error";
     }
 }
@@ -548,19 +680,22 @@ int relres_create(const relres_params* p, relres_ctx** out)
     if ((rc = ensure(c->d_hybrid, sizeof(int) * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_status, sizeof(Status), &c->alloc_generation))) return bail(rc);
-    if ((rc = ensure(c->d_counter, kTicketBytes, &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_epoch, 256, &c->alloc_generation))) return bail(rc);
     if (hipMemcpy(c->d_coef64.p, c->coef64.data(), sizeof(PairCoef<double>) * c->coef64.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_coef32.p, coef32.data(), sizeof(PairCoef<float>) * coef32.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_hybrid.p, c->hybrid.data(), sizeof(int) * nt, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_status.p, 0, sizeof(Status)) != hipSuccess ||
-        hipMemset(c->d_counter.p, 0, kTicketBytes) != hipSuccess)
+        hipMemset(c->d_epoch.p, 0, 256) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "uploading parameters failed"));
     if (hipHostMalloc((void**)&c->h_grids, 2 * sizeof(GridDev), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_zero, sizeof(Status), hipHostMallocDefault) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "pinned host allocation failed"));
+    if (hipEventCreateWithFlags(&c->ev_status, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_upload, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(RELRES_ERR_HIP, "event creation failed"));
     std::memset(c->h_grids, 0, 2 * sizeof(GridDev));
     std::memset(c->h_status, 0, sizeof(Status));
     std::memset(c->h_zero, 0, sizeof(Status));
@@ -610,6 +745,12 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
             idx.insert(idx.end(), part[i].begin(), part[i].end());
         }
     }
+    if (c->check_pending) {
+        // a build of the previous topology is still unexamined: retire it
+        HIP_TRY(hipEventSynchronize(c->ev_status));
+        c->nonfinite_seen = c->h_status->nonfinite;
+        c->check_pending = false;
+    }
     c->built = false;
     c->topo_set = false;
     c->lanes_stale = true;
@@ -637,101 +778,23 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
 
 int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], void* stream)
 {
-    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
-    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
-    if (!box) return fail(RELRES_ERR_ARG, "box is NULL");
-    if (c->n > 0 && !pos) return fail(RELRES_ERR_ARG, "pos is NULL");
-    for (int k = 0; k < 3; ++k)
-        if (!(std::isfinite(box[k]) && box[k] > 0.0)) return fail(RELRES_ERR_ARG, "bad box edge %g", box[k]);
-    hipStream_t s = (hipStream_t)stream;
-    const double rla = c->rso + c->skin, rls = c->rco + c->skin;
-    const bool sites = c->n_sites > 0;
-    const double rmax = sites ? rls : rla;
-    for (int k = 0; k < 3; ++k)
-        if (!(box[k] > 2.0 * rmax))
-            return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g must exceed 2 x %g", box[k], rmax);
-    c->built = false;
-    std::copy(box, box + 3, c->box);
-    const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
-    TRY(setup_grid(c->ga, rla, box, c->n, &c->alloc_generation));
-    if (sites) TRY(setup_grid(c->gs, rls, box, c->n_sites, &c->alloc_generation));
-    if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
-    TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
-    TRY(ensure(c->d_key_a, sizeof(int2) * c->n, &c->alloc_generation));
-    TRY(ensure(c->d_key_s, sizeof(int2) * c->n, &c->alloc_generation));
-    TRY(ensure(c->d_user2arow, sizeof(int) * c->n, &c->alloc_generation));
-    TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n), &c->alloc_generation));
-    TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites), &c->alloc_generation));
-
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-        TRY(take_events(c, e0, e1));
-        HIP_TRY(hipEventRecord(e0, s));
-    }
-    if (c->n > 0) {
-        TRY(upload_grids(c, s));
-        const TopoDev topo = topo_of(c);
-        GridDev* gd = c->d_grids.as<GridDev>();
-        HIP_TRY(launch_bin(c->n, pos, box, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
-                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), s));
-        HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
-        HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
-        const int ncs = sites ? c->gs.ncell : 0;
-        HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
-                                c->d_user2arow.as<int>(), s));
-        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->n, c->n_sites, topo, box,
-                             c->d_user2arow.as<int>(),
-                             c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
-                             c->d_status.as<Status>(), lists_per_wave(c), s));
-        HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
-        if (c->timing) HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (c->h_status->nonfinite != c->nonfinite_seen) {
-            c->nonfinite_seen = c->h_status->nonfinite;
-            return fail(RELRES_ERR_NONFINITE, "non-finite position");
-        }
-        // grow rows that overflowed and rebuild the lists (positions stay sorted)
-        for (int attempt = 0; attempt < 3; ++attempt) {
-            const int mr_a = c->h_status->max_row[0], mr_s = c->h_status->max_row[1];
-            const bool ov_a = mr_a > c->ga.cap;
-            const bool ov_s = sites && mr_s > c->gs.cap;
-            if (!ov_a && !ov_s) break;
-            if (attempt == 2) return fail(RELRES_ERR_LIST_OVERFLOW, "list capacity did not converge");
-            if (ov_a) {
-                c->ga.cap = ((int)(mr_a * 1.25) + 8 + 7) & ~7;
-                TRY(setup_grid(c->ga, rla, box, c->n, &c->alloc_generation));
-            }
-            if (ov_s) {
-                c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
-                TRY(setup_grid(c->gs, rls, box, c->n_sites, &c->alloc_generation));
-            }
-            c->stats.regrows++;
-            c->lanes_stale = true;
-            TRY(run_lists(c, s));
-        }
-    } else if (c->timing) {
-        HIP_TRY(hipEventRecord(e1, s));
-    }
-    if (c->timing) c->ev_build.push_back({e0, e1});
-
-    relres_stats& st = c->stats;
-    st.n_atoms = c->n;
-    st.n_sites = c->n_sites;
-    st.atom_capacity = c->ga.cap;
-    st.site_capacity = sites ? c->gs.cap : 0;
-    for (int k = 0; k < 3; ++k) {
-        st.atom_cells[k] = c->ga.n[k];
-        st.site_cells[k] = sites ? c->gs.n[k] : 0;
-        st.box[k] = box[k];
-    }
-    st.builds++;
-    c->stats_fresh = false;
-    c->built = true;
-    if (c->lanes_stale) {
-        TRY(refresh_list_stats(c, s));
-        c->lanes_stale = false;
-    }
+    TRY(build_checked(c, pos, box, (hipStream_t)stream));
     return RELRES_OK;
+}
+
+int relres_build_lists_async(relres_ctx* c, const double* pos, const double box[3], void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    TRY(drain_check(c));
+    if (c->lanes_stale) return build_checked(c, pos, box, s);   // first build / new grids
+    TRY(enqueue_build(c, pos, box, s));
+    return RELRES_OK;
+}
+
+int relres_check_lists(relres_ctx* c)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    return examine_status(c);
 }
 
 int relres_set_launch(relres_ctx* c, int lanes_atom, int lanes_site)
@@ -791,9 +854,18 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     a.lanes_b = lb;
     a.log_lanes_a = log2i(la);
     a.log_lanes_b = log2i(lb);
-    TRY(ensure(c->d_partials, sizeof(double) * 8 * (size_t)(a.blocks_a + a.blocks_b + kXcdGroups), &c->alloc_generation));
-    a.partials = c->d_partials.as<double>();
-    a.counter = c->d_counter.as<unsigned int>();
+    {
+        // energy/virial records: a fresh buffer may hold another context's
+        // records, whose tags could match this context's; clear it (tag 0)
+        const long long g0 = c->alloc_generation;
+        const size_t rec_bytes = (size_t)kEwRecBytes * (size_t)(a.blocks_a + a.blocks_b + kXcdGroups);
+        TRY(ensure(c->d_partials, rec_bytes, &c->alloc_generation));
+        if (c->alloc_generation != g0)
+            HIP_TRY(launch_clear_words(c->d_partials.as<unsigned long long>(),
+                                       c->d_partials.bytes / sizeof(unsigned long long), s));
+    }
+    a.ew_rec = c->d_partials.as<unsigned long long>();
+    a.epoch = c->d_epoch.as<unsigned int>();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         TRY(take_events(c, e0, e1));
@@ -810,7 +882,10 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
 int relres_list_stats(relres_ctx* c, relres_stats* out)
 {
     if (!c || !out) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (c->check_pending) TRY(examine_status(c));
     if (c->built && !c->stats_fresh) TRY(refresh_list_stats(c, nullptr));
+    c->stats.atom_capacity = c->ga.cap;
+    c->stats.site_capacity = c->n_sites > 0 ? c->gs.cap : 0;
     *out = c->stats;
     out->generation = c->alloc_generation;
     return RELRES_OK;
@@ -829,6 +904,7 @@ int relres_get_pairs(relres_ctx* c, int which, int* pairs_host, long long cap, l
     if (which != RELRES_LIST_ATOM && which != RELRES_LIST_SITE)
         return fail(RELRES_ERR_ARG, "which must be RELRES_LIST_ATOM or RELRES_LIST_SITE");
     if (cap > 0 && !pairs_host) return fail(RELRES_ERR_ARG, "pairs_host is NULL");
+    if (c->check_pending) TRY(examine_status(c));
     if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists");
     *n_out = 0;
     const bool site = which == RELRES_LIST_SITE;
@@ -898,7 +974,7 @@ void relres_destroy(relres_ctx* c)
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
                     &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials,
-                    &c->d_counter})
+                    &c->d_epoch})
         release(*b);
     for (GridHost* g : {&c->ga, &c->gs})
         for (DBuf* b : {&g->rank_of_lin, &g->lin_of_rank, &g->nbr, &g->count, &g->start, &g->user_unsorted,
@@ -913,6 +989,8 @@ void relres_destroy(relres_ctx* c)
             (void)hipEventDestroy(pr.second);
         }
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    if (c->ev_status) (void)hipEventDestroy(c->ev_status);
+    if (c->ev_upload) (void)hipEventDestroy(c->ev_upload);
     delete c;
 }
 

@@ -113,9 +113,8 @@ struct ForceArgs {
     void* forces;             // N x 3 of TF, caller order
     double* energy;           // [3] or null
     double* virial;           // [6] or null
-    double* partials;         // 8 per block, then 8 per XCD group
-    unsigned int* counter;    // tickets: one per XCD group + one top, kTicketStride apart;
-                              // zero between launches
+    unsigned long long* ew_rec;   // energy/virial records: one per block, then one per group
+    unsigned int* epoch;          // launch epoch, advanced by every energy/virial launch
     int blocks_a, blocks_b;   // multiples of 8
     int lanes_a, lanes_b;     // lanes per row (powers of two)
     int log_lanes_a, log_lanes_b;
@@ -138,11 +137,11 @@ hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int member
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
                          bool ew, hipStream_t s);
 hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
+hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_outputs(double* energy, double* virial, hipStream_t s);
 
 constexpr int kXcdGroups = 8;        // workgroups are dealt round-robin to 8 XCDs
-constexpr int kTicketStride = 64;    // unsigned ints between tickets (256 B)
-constexpr size_t kTicketBytes = sizeof(unsigned int) * kTicketStride * (kXcdGroups + 1);
+constexpr int kEwRecBytes = 128;     // one energy/virial record: 16 tagged 64-bit words
 constexpr int kForceBlock = 256;
 constexpr int kListBlock = 256;
 

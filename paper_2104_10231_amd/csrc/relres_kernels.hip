@@ -652,44 +652,68 @@ __global__ __launch_bounds__(256) void k_list_stats(const GridDev* __restrict__ 
 // force kernel
 // ---------------------------------------------------------------------------
 
-template <typename S> __device__ __forceinline__ S rcp(S x);
-template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-// FP64 reciprocal: hardware estimate refined by two Newton steps (each at
-// least doubles the number of correct bits), within about one ulp.
-template <> __device__ __forceinline__ double rcp<double>(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-template <typename S> __device__ __forceinline__ S sqrt_(S x);
-template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double sqrt_<double>(double x) { return sqrt(x); }
+// Reciprocal and square root of the pair terms.  FP32: hardware estimates.
+// FP64: the FP32 estimate refined by NR Newton steps in FP64, each of which
+// squares the relative error (2^-22 -> ~2^-44 -> rounding level); one step is
+// ample for FP64 energy/virial sums of FP32-force runs, two give full FP64.
+struct MathF32 {
+    using T = float;
+    static __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+    // r = sqrt(x) and ir = 1/r from one reciprocal-square-root estimate
+    static __device__ __forceinline__ void root(float x, float& r, float& ir)
+    {
+        ir = __builtin_amdgcn_rsqf(x);
+        r = x * ir;
+    }
+};
+
+template <int NR>
+struct MathF64 {
+    using T = double;
+    static __device__ __forceinline__ double recip(double x)
+    {
+        double y = (double)__builtin_amdgcn_rcpf((float)x);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) y = fma(y, fma(-x, y, 1.0), y);
+        return y;
+    }
+    static __device__ __forceinline__ void root(double x, double& r, double& ir)
+    {
+        double y = (double)__builtin_amdgcn_rsqf((float)x);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double e = fma(-(x * y), y, 1.0);   // 1 - x y^2
+            y = fma(0.5 * y, e, y);
+        }
+        ir = y;
+        r = x * y;
+        r = fma(0.5 * y, fma(-r, r, x), r);          // one more step on r itself
+    }
+};
 
 // Pair terms of the FG part of Eq. 20 (r < r_s+): fpair = -u~'(r)/r and the
 // energy.  Called only for r2 < r_s+^2.
-template <typename T>
+template <typename M, typename T = typename M::T>
 __device__ __forceinline__ void fg_term(const PairCoef<T>& c, const Cutoffs<T>& cut, T r2,
                                         T& fpair, T& en)
 {
     if (r2 < cut.rsi2) {
-        const T r2i = rcp<T>(r2);
+        const T r2i = M::recip(r2);
         const T r6i = r2i * r2i * r2i;
         fpair = r6i * (c.fg_c12 * r6i - c.fg_c6) * r2i;
         en = r6i * (c.fg_e12 * r6i - c.fg_e6) - c.fg_shift;
     } else {
-        const T r = sqrt_<T>(r2);
+        T r, ir;
+        M::root(r2, r, ir);
         const T d = r - cut.rsi;
         const T dp = c.fg_g[1] + d * (T(2) * c.fg_g[2] + d * (T(3) * c.fg_g[3] + d * (T(4) * c.fg_g[4])));
-        fpair = -dp * rcp<T>(r);
+        fpair = -dp * ir;
         en = c.fg_g[0] + d * (c.fg_g[1] + d * (c.fg_g[2] + d * (c.fg_g[3] + d * c.fg_g[4]))) - c.fg_shift;
     }
 }
 
 // Pair terms of the CG part of Eq. 20 (hybrid pairs, r < r_c+).
-template <typename T>
+template <typename M, typename T = typename M::T>
 __device__ __forceinline__ void cg_term(const PairCoef<T>& c, const Cutoffs<T>& cut, T r2,
                                         T& fpair, T& en)
 {
@@ -697,21 +721,23 @@ __device__ __forceinline__ void cg_term(const PairCoef<T>& c, const Cutoffs<T>& 
         fpair = T(0);
         en = c.sp_g0 - c.cm_shift;
     } else if (r2 < cut.rso2) {
-        const T r = sqrt_<T>(r2);
+        T r, ir;
+        M::root(r2, r, ir);
         const T d = r - cut.rsi;
         const T dp = d * d * (T(3) * c.sp_g3 + T(4) * c.sp_g4 * d);
-        fpair = -dp * rcp<T>(r);
+        fpair = -dp * ir;
         en = c.sp_g0 + d * d * d * (c.sp_g3 + d * c.sp_g4) - c.cm_shift;
     } else if (r2 < cut.rci2) {
-        const T r2i = rcp<T>(r2);
+        const T r2i = M::recip(r2);
         const T r6i = r2i * r2i * r2i;
         fpair = r6i * (c.cg_c12 * r6i - c.cg_c6) * r2i;
         en = r6i * (c.cg_e12 * r6i - c.cg_e6) - c.cm_shift;
     } else {
-        const T r = sqrt_<T>(r2);
+        T r, ir;
+        M::root(r2, r, ir);
         const T d = r - cut.rci;
         const T dp = c.cm_g[1] + d * (T(2) * c.cm_g[2] + d * (T(3) * c.cm_g[3] + d * (T(4) * c.cm_g[4])));
-        fpair = -dp * rcp<T>(r);
+        fpair = -dp * ir;
         en = c.cm_g[0] + d * (c.cm_g[1] + d * (c.cm_g[2] + d * (c.cm_g[3] + d * c.cm_g[4]))) - c.cm_shift;
     }
 }
@@ -779,145 +805,276 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const PairCoef<S>*
             dz -= a.box[2] * rint(dz * a.inv_box[2]);
             const double r2d = dx * dx + dy * dy + dz * dz;
             if (r2d < rmax2) {
-                S fp, en;
-                if constexpr (CG) cg_term<S>(crow[tj], cut, (S)r2d, fp, en);
-                else fg_term<S>(crow[tj], cut, (S)r2d, fp, en);
-                fx += (TF)(fp * (S)dx);
-                fy += (TF)(fp * (S)dy);
-                fz += (TF)(fp * (S)dz);
-                if constexpr (EW) {
+                if constexpr (sizeof(S) == sizeof(double) || EW) {
+                    // FP64 pair terms (full precision in FP64 mode; one Newton
+                    // step when they only feed energy/virial and FP32 forces)
+                    using M = MathF64<sizeof(S) == sizeof(double) ? 2 : 1>;
                     double fpd, end;
-                    if constexpr (sizeof(S) == sizeof(double)) {
-                        fpd = (double)fp;
-                        end = (double)en;
-                    } else if constexpr (CG) {
-                        cg_term<double>(crow64[tj], cut64, r2d, fpd, end);
+                    if constexpr (CG) cg_term<M>(crow64[tj], cut64, r2d, fpd, end);
+                    else fg_term<M>(crow64[tj], cut64, r2d, fpd, end);
+                    if constexpr (sizeof(TF) == sizeof(double)) {
+                        fx += fpd * dx;
+                        fy += fpd * dy;
+                        fz += fpd * dz;
                     } else {
-                        fg_term<double>(crow64[tj], cut64, r2d, fpd, end);
+                        const float fp = (float)fpd;
+                        fx += fp * (float)dx;
+                        fy += fp * (float)dy;
+                        fz += fp * (float)dz;
                     }
-                    const double hf = 0.5 * fpd;
-                    acc[CG ? 1 : 0] += 0.5 * end;
-                    acc[2] += hf * dx * dx;
-                    acc[3] += hf * dy * dy;
-                    acc[4] += hf * dz * dz;
-                    acc[5] += hf * dx * dy;
-                    acc[6] += hf * dx * dz;
-                    acc[7] += hf * dy * dz;
+                    if constexpr (EW) {
+                        const double hf = 0.5 * fpd;
+                        acc[CG ? 1 : 0] += 0.5 * end;
+                        acc[2] += hf * dx * dx;
+                        acc[3] += hf * dy * dy;
+                        acc[4] += hf * dz * dz;
+                        acc[5] += hf * dx * dy;
+                        acc[6] += hf * dx * dz;
+                        acc[7] += hf * dy * dz;
+                    }
+                } else {
+                    float fp, en;
+                    if constexpr (CG) cg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
+                    else fg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
+                    fx += fp * (float)dx;
+                    fy += fp * (float)dy;
+                    fz += fp * (float)dz;
                 }
             }
         }
     }
 }
 
+// Cross-lane moves through DPP (a VALU operand modifier), much cheaper than
+// LDS-routed shuffles.  Lanes a DPP move does not write (masked rows, sources
+// outside the row) read 0.
+constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;   // lane i <- lane 7-i within 8
+constexpr int kDppMirror = 0x140;       // lane i <- lane 15-i within 16
+constexpr int kDppBcast15 = 0x142;      // lane 15 of each row -> next row
+constexpr int kDppBcast31 = 0x143;      // lane 31 -> rows 2 and 3
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                  CTRL, ROWS, 0xf, false));
+}
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave, complete in lane 63 (fixed order).
 __device__ __forceinline__ double wave_sum(double v)
 {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    v += dpp<kDppHalfMirror>(v);
+    v += dpp<kDppMirror>(v);
+    v += dpp<kDppBcast15, 0xA>(v);
+    v += dpp<kDppBcast31, 0xC>(v);
     return v;
 }
 
-// Publishes 8 doubles (threads 0..7 hold one each) with agent-scope stores,
-// which are written through to the level shared by all XCDs, waits until they
-// are acknowledged, and takes a ticket on `counter`.  True in every thread of
-// the block that took the last of `expected` tickets.  Relaxed atomics plus an
-// explicit wait avoid the L2 writeback an agent-scope release fence costs.
-__device__ __forceinline__ bool publish_and_ticket(double* dst, double v, unsigned int* counter,
-                                                   unsigned int expected, int* flag)
+// Sum over each aligned group of G lanes (G a power of two <= 64, uniform in
+// the wave); every lane of a group holds its group's sum.
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int G)
 {
-    if (threadIdx.x < 8) {
-        __hip_atomic_store(dst + threadIdx.x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // the stores (wave 0) must be acknowledged before wave 0 takes the ticket
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        const bool last = t == expected - 1;
-        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        *flag = last;
-    }
-    __syncthreads();
-    return *flag != 0;
+    if (G >= 2) v += dpp<kDppXor1>(v);
+    if (G >= 4) v += dpp<kDppXor2>(v);
+    if (G >= 8) v += dpp<kDppHalfMirror>(v);
+    if (G >= 16) v += dpp<kDppMirror>(v);
+    if (G >= 32) v += __shfl_xor(v, 16);
+    if (G >= 64) v += __shfl_xor(v, 32);
+    return v;
 }
 
-__device__ __forceinline__ double load_agent(const double* p)
+// ---------------------------------------------------------------------------
+// Energy/virial reduction across the blocks of one force launch
+// ---------------------------------------------------------------------------
+// Each block's 8 partial sums (energy FG, CG, virial xx yy zz xy xz yz) are
+// published as one record of 16 64-bit words: the high and low 32-bit halves
+// of every double, each paired with a 32-bit launch tag.  64-bit stores are
+// single-copy atomic, so a reader that sees the current tag in a word sees
+// that word's payload; no store ever has to be waited for, and no atomic
+// read-modify-write (which serialise on one address) is needed.  The tag is
+// the device epoch + 1; the epoch advances once per launch.
+//
+// Blocks b with b % 8 == g form group g.  The highest-numbered block of each
+// group waits for the records of the rest of its group and publishes the group
+// sum; block nb-1 (the highest of all) then waits for the group records and
+// writes energy and virial.  A waiting block only ever waits for blocks with
+// lower numbers, which the hardware dispatched before it, so every wait ends;
+// it is bounded anyway (kSpinLimit polls), after which energy and virial are
+// set to NaN.  Sums are taken in a fixed order: the result does not depend on
+// which block finished when.
+constexpr int kRecWords = 16;
+constexpr int kSpinLimit = 1 << 22;
+constexpr int kPollBatch = 16;   // records polled per thread at once
+
+// Writes one record: called by the whole block, `v` valid in threads 0..7
+// (component threadIdx.x).  Lanes 0..15 of wave 0 store word threadIdx.x, so
+// the record goes out as one contiguous 128-byte write.
+__device__ __forceinline__ void put_record(unsigned long long* rec, double v, unsigned tag)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {
+        const double c = __shfl(v, (int)(threadIdx.x >> 1));
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(c);
+        const unsigned long long half = (threadIdx.x & 1) ? (bits & 0xffffffffull) : (bits >> 32);
+        if (threadIdx.x < kRecWords)
+            __hip_atomic_store(rec + threadIdx.x, ((unsigned long long)tag << 32) | half,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
-// Sums 8 values per item over items 0..count-1 (item i at base + i*stride*8)
-// in a fixed order; the result is in red[k][0] .. combined by thread 0.
-__device__ void block_sum8(const double* base, int count, int stride, double (*red)[kForceBlock / 64],
-                           double out[8])
+// Waits for `count` records (record m at rec + (first + stride*m) * 16 words)
+// to carry `tag` and adds them up.  Sixteen consecutive lanes read the sixteen
+// words of one record, so every load instruction covers whole records.  On
+// return, even lanes hold their record-word pair's component (t % 16) / 2
+// summed over their records in v[]; odd lanes hold zeros.  Sets *failed if a
+// wait gave up.
+__device__ __forceinline__ void gather_records(const unsigned long long* rec, int first, int stride,
+                                               int count, unsigned tag, double v[8], int* failed)
+{
+    const int t = (int)threadIdx.x;
+    const int word = t & (kRecWords - 1);
+    const int comp = word >> 1;
+    double sum = 0.0;
+    for (int base = 0; base < count; base += (kForceBlock / kRecWords) * kPollBatch) {
+        unsigned long long w[kPollBatch];
+        bool need[kPollBatch];
+#pragma unroll
+        for (int u = 0; u < kPollBatch; ++u) {
+            const int m = base + t / kRecWords + (kForceBlock / kRecWords) * u;
+            need[u] = m < count;
+            w[u] = 0;
+        }
+        for (int it = 0;; ++it) {
+            bool pending = false;
+#pragma unroll
+            for (int u = 0; u < kPollBatch; ++u) {
+                if (!need[u]) continue;
+                const int m = base + t / kRecWords + (kForceBlock / kRecWords) * u;
+                w[u] = __hip_atomic_load(rec + (size_t)(first + stride * m) * kRecWords + word,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                need[u] = (unsigned)(w[u] >> 32) != tag;
+                pending |= need[u];
+            }
+            if (!pending) break;
+            if (it >= kSpinLimit) {
+                *failed = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+#pragma unroll
+        for (int u = 0; u < kPollBatch; ++u) {
+            const int m = base + t / kRecWords + (kForceBlock / kRecWords) * u;
+            const unsigned lo = (unsigned)__shfl_down((unsigned)(w[u] & 0xffffffffull), 1);
+            if (!(word & 1) && m < count)
+                sum += __longlong_as_double((long long)(((w[u] & 0xffffffffull) << 32) | lo));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (!(word & 1) && k == comp) ? sum : 0.0;
+}
+
+// Fixed-order block reduction of v[8]: result in threads 0..7 (component
+// threadIdx.x) as the return value; `extra` (threads 0..7) is added last.
+__device__ __forceinline__ double block_reduce8(const double v[8], double extra,
+                                                double (*red)[kForceBlock / 64])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < count; i += kForceBlock) {
-        double t[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) t[k] = load_agent(base + (size_t)i * stride * 8 + k);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] += t[k];
-    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const double w = wave_sum(v[k]);
-        if (lane == 0) red[k][wave] = w;
+        if (lane == 63) red[k][wave] = w;
     }
     __syncthreads();
+    double t = 0.0;
     if (threadIdx.x < 8) {
-        double t = 0.0;
         for (int w = 0; w < kForceBlock / 64; ++w) t += red[threadIdx.x][w];
-        out[0] = t;
+        t += extra;
     }
     __syncthreads();
+    return t;
 }
 
-// Energy/virial reduction of one force launch, deterministic and in one pass:
-// every block publishes its 8 partial sums; the last block of each XCD group
-// (blocks b with b % 8 == g, which the hardware places on one XCD) adds that
-// group's partials in block order and publishes the group sum; the last group
-// adds the 8 group sums in group order and writes energy and virial.  Two
-// levels of tickets keep the contention on any one counter to ~nb/8 blocks.
-__device__ void ew_finish(const ForceArgs& a, const double acc[8])
+__device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
 {
     __shared__ double red[8][kForceBlock / 64];
-    __shared__ int flag;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double w = wave_sum(acc[k]);
-        if (lane == 0) red[k][wave] = w;
+    __shared__ int failed;
+    const int nb = (int)gridDim.x;
+    const int b = (int)blockIdx.x;
+    const int g = b % kXcdGroups;
+    const int ngroups = nb < kXcdGroups ? nb : kXcdGroups;
+    const int last_in_group = g + kXcdGroups * ((nb - 1 - g) / kXcdGroups);
+
+    if (threadIdx.x == 0) failed = 0;
+    const double mine = block_reduce8(acc, 0.0, red);
+    if (b != last_in_group) {
+        put_record(a.ew_rec + (size_t)b * kRecWords, mine, tag);
+        return;
+    }
+    // group g: members g, g+8, ..., b-8 (in that order), then this block
+    double v[8];
+    gather_records(a.ew_rec, g, kXcdGroups, b / kXcdGroups, tag, v, &failed);
+    const double gsum = block_reduce8(v, mine, red);
+    unsigned long long* grec = a.ew_rec + (size_t)nb * kRecWords;
+    if (b != nb - 1) {
+        put_record(grec + (size_t)g * kRecWords, failed ? __builtin_nan("") : gsum, tag);
+        return;
+    }
+    // final block: the group sums in group order.  The other groups' records
+    // are gathered (groups 0..ngroups-1 except g, which is this block's own);
+    // to keep the order fixed, the own group's sum is slotted in at its place.
+    __shared__ double gred[kXcdGroups][8];
+    if (threadIdx.x < 8) gred[g][threadIdx.x] = gsum;
+    {
+        const int t = (int)threadIdx.x;
+        const int q = t / kRecWords, word = t & (kRecWords - 1);
+        unsigned long long w = 0;
+        if (q < ngroups && q != g) {
+            for (int it = 0;; ++it) {
+                w = __hip_atomic_load(grec + (size_t)q * kRecWords + word, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)(w >> 32) == tag) break;
+                if (it >= kSpinLimit) {
+                    failed = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        const unsigned lo = (unsigned)__shfl_down((unsigned)(w & 0xffffffffull), 1);
+        if (q < ngroups && q != g && !(word & 1))
+            gred[q][word >> 1] = __longlong_as_double((long long)(((w & 0xffffffffull) << 32) | lo));
     }
     __syncthreads();
-    double mine = 0.0;
-    if (threadIdx.x < 8)
-        for (int w = 0; w < kForceBlock / 64; ++w) mine += red[threadIdx.x][w];
-    __syncthreads();
-
-    const int nb = (int)gridDim.x;
-    const int g = (int)blockIdx.x % kXcdGroups;
-    const int ngroups = nb < kXcdGroups ? nb : kXcdGroups;
-    const int gsize = (nb - g + kXcdGroups - 1) / kXcdGroups;
-    if (!publish_and_ticket(a.partials + (size_t)blockIdx.x * 8, mine,
-                            a.counter + g * kTicketStride, (unsigned)gsize, &flag))
-        return;
-    double gsum[1];
-    block_sum8(a.partials + (size_t)g * 8, gsize, kXcdGroups, red, gsum);
-    double* gpart = a.partials + (size_t)nb * 8;
-    if (!publish_and_ticket(gpart + (size_t)g * 8, gsum[0], a.counter + kXcdGroups * kTicketStride,
-                            (unsigned)ngroups, &flag))
-        return;
     if (threadIdx.x < 8) {
         double t = 0.0;
-        for (int q = 0; q < ngroups; ++q) t += load_agent(gpart + (size_t)q * 8 + threadIdx.x);
-        if (threadIdx.x == 0 && a.energy) a.energy[1] = t;
-        if (threadIdx.x == 1 && a.energy) a.energy[2] = t;
-        if (threadIdx.x >= 2 && a.virial) a.virial[threadIdx.x - 2] = t;
+        for (int q = 0; q < ngroups; ++q) t += gred[q][threadIdx.x];
         red[threadIdx.x][0] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && a.energy) a.energy[0] = red[0][0] + red[1][0];
+    const bool bad = failed != 0;
+    if (threadIdx.x < 8) {
+        const double val = bad ? __builtin_nan("") : red[threadIdx.x][0];
+        if (threadIdx.x < 2 && a.energy) a.energy[1 + threadIdx.x] = val;
+        if (threadIdx.x >= 2 && a.virial) a.virial[threadIdx.x - 2] = val;
+    }
+    if (threadIdx.x == 0) {
+        if (a.energy) a.energy[0] = bad ? __builtin_nan("") : red[0][0] + red[1][0];
+        __hip_atomic_store(a.epoch, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <typename S, typename TF, bool EW, bool LDS>
@@ -936,6 +1093,12 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const int row = logical * (kForceBlock >> lg) + ((int)threadIdx.x >> lg);
     const int sub = (int)threadIdx.x & (G - 1);
 
+    unsigned tag = 0;
+    if constexpr (EW) {
+        // tag 0 is never used: it marks a cleared record
+        tag = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        tag += tag == 0u;
+    }
     // row record first: it is the head of every dependent load chain
     int4 rec = make_int4(-1, 0, 0, 1);
     int cnt_a = 0;
@@ -979,18 +1142,16 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
                                        xi, yi, zi, a.s_list + (size_t)row * a.s_cap, rec.z, sub,
                                        G, fx, fy, fz, acc);
     }
-    for (int o = G >> 1; o > 0; o >>= 1) {
-        fx += __shfl_xor(fx, o);
-        fy += __shfl_xor(fy, o);
-        fz += __shfl_xor(fz, o);
-    }
+    fx = group_sum(fx, G);
+    fy = group_sum(fy, G);
+    fz = group_sum(fz, G);
     if (own && sub == 0) {
         TF* F = (TF*)a.forces;
         F[3 * rec.x] = fx;
         F[3 * rec.x + 1] = fy;
         F[3 * rec.x + 2] = fz;
     }
-    if constexpr (EW) ew_finish(a, acc);
+    if constexpr (EW) ew_finish(a, acc, tag);
 }
 
 
@@ -1101,6 +1262,22 @@ hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math,
 hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_list_stats, dim3(ngrids), dim3(256), 0, s, grids_dev, st);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_words(unsigned long long* p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_clear_words, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

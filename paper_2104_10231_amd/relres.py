@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librelres_hip.so")
 
 RELRES_OK = 0
+RELRES_ERR_LIST_RETRY = -10
 MIX_GEOMETRIC = 0
 MIX_ARITHMETIC = 1
 LIST_ATOM = 0
@@ -57,6 +58,9 @@ SIGNATURES = {
                                            ctypes.c_void_p]),
     "relres_build_lists": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
                                           ctypes.c_void_p]),
+    "relres_build_lists_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
+                                                ctypes.c_void_p]),
+    "relres_check_lists": (ctypes.c_int, [ctypes.c_void_p]),
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -170,11 +174,23 @@ class RelRes:
             raise ValueError(f"pos has shape {tuple(pos.shape)}, expected ({self.n}, 3)")
         return pos
 
-    def build_lists(self, pos: torch.Tensor, box, stream=None):
+    def build_lists(self, pos: torch.Tensor, box, stream=None, wait: bool = True):
+        """Build both lists.  With wait=False the build is only enqueued; call
+        check_lists() before trusting results computed from these lists."""
         pos = self._pos(pos)
         b = (ctypes.c_double * 3)(*[float(x) for x in box])
-        _check(self._lib.relres_build_lists(self._ctx, pos.data_ptr() if self.n else None, b,
-                                            _stream(stream)), "relres_build_lists")
+        fn = self._lib.relres_build_lists if wait else self._lib.relres_build_lists_async
+        _check(fn(self._ctx, pos.data_ptr() if self.n else None, b, _stream(stream)),
+               "relres_build_lists" if wait else "relres_build_lists_async")
+
+    def check_lists(self) -> bool:
+        """True when the last build's lists are complete; False when a row
+        overflowed (capacity grown: build again and redo what used them)."""
+        rc = self._lib.relres_check_lists(self._ctx)
+        if rc == RELRES_ERR_LIST_RETRY:
+            return False
+        _check(rc, "relres_check_lists")
+        return True
 
     def forces(self, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
                energy: Optional[torch.Tensor] = None, virial: Optional[torch.Tensor] = None,

@@ -73,6 +73,37 @@ def test_neopentane_20480_fp32(pair_math):
     _check(w.neopentane_liquid(0), 32, pair_math=pair_math)
 
 
+@pytest.mark.parametrize("name,precision,pair_math", [("propane", 64, 0), ("neopentane", 32, 32),
+                                                    ("neopentane", 32, 64)])
+def test_forces_only_calls(name, precision, pair_math):
+    """Forces without energy/virial run a kernel of their own (FP32 pair terms
+    when pair_math is 32); they must meet the same force bar and leave the
+    energy/virial buffers alone."""
+    import torch
+    s = w.propane_liquid(0) if name == "propane" else w.neopentane_liquid(0)
+    print(f"[parity] forces-only {s.name} precision={precision} pair_math={pair_math}", flush=True)
+    rr = make_relres(s, precision, pair_math)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)
+    E = torch.full((3,), 123.0, dtype=torch.float64, device="cuda")
+    W = torch.full((6,), 456.0, dtype=torch.float64, device="cuda")
+    F0, _, _ = rr.forces(p, energy=None, virial=None, want_energy=False, want_virial=False)
+    F0 = F0.double().cpu().numpy()
+    F1, E1, W1 = rr.forces(p, energy=E, virial=W)
+    F1 = F1.double().cpu().numpy()
+    Fr, Er, Wr = oracle.compute(s)
+    ftol = TOL[precision][0]
+    assert rel_rms(F0, Fr) <= ftol, rel_rms(F0, Fr)
+    assert rel_rms(F1, Fr) <= ftol, rel_rms(F1, Fr)
+    E2 = torch.full((3,), 123.0, dtype=torch.float64, device="cuda")
+    W2 = torch.full((6,), 456.0, dtype=torch.float64, device="cuda")
+    rr.forces(p, energy=E2, virial=None, want_virial=False)
+    torch.cuda.synchronize()
+    assert abs(E2[0].item() - Er[0]) <= TOL[precision][1] * abs(Er[0])
+    assert torch.all(W2 == 456.0)
+    rr.close()
+
+
 def test_neopentane_20480_conventional():
     s = w.neopentane_liquid(0).conventional()
     _check(s, 32)
@@ -182,6 +213,60 @@ def test_list_regrow_on_a_dense_cluster():
     assert rel_rms(F, Fr) <= 1e-11 and abs(E[0] - Er[0]) <= 1e-12 * abs(Er[0])
     for which in (0, 1):
         assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(big, which))
+    rr.close()
+
+
+def test_async_build_matches_blocking_build():
+    """Enqueued build + forces, checked afterwards: same lists, same bits."""
+    import torch
+    s = w.neopentane_liquid(0)
+    print(f"[parity] async build {s.name}", flush=True)
+    rr = make_relres(s, 32)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)                       # first build always waits
+    F0, E0, W0 = rr.forces(p)
+    F0, E0, W0 = F0.clone(), E0.clone(), W0.clone()
+    moved = torch.from_numpy(s.pos + 0.3).cuda()   # a later build, enqueued
+    rr.build_lists(moved, s.box, wait=False)
+    F1, E1, W1 = rr.forces(moved)
+    assert rr.check_lists()
+    Fr, Er, Wr = oracle.compute(s.replace(pos=s.pos + 0.3))
+    F1n = F1.double().cpu().numpy()
+    assert rel_rms(F1n, Fr) <= TOL[32][0]
+    assert abs(E1[0].item() - Er[0]) <= TOL[32][1] * abs(Er[0])
+    rr.build_lists(p, s.box, wait=False)
+    F2, E2, W2 = rr.forces(p)
+    assert rr.check_lists()
+    assert torch.equal(F2, F0) and torch.equal(E2, E0) and torch.equal(W2, W0)
+    rr.close()
+
+
+def test_async_build_reports_overflow_and_recovers():
+    import torch
+    uniform = w.random_molecules(13, 90, 60.0, kind="propane", min_dist=2.9)
+    dense = w.random_molecules(13, 90, 22.0, kind="propane", min_dist=2.9)
+    dense = dense.replace(pos=dense.pos + 1.0, box=np.full(3, 60.0))
+    assert np.array_equal(uniform.types, dense.types) and np.array_equal(uniform.mol, dense.mol)
+    print(f"[parity] async overflow N={dense.n}", flush=True)
+    rr = make_relres(uniform, 64)
+    rr.build_lists(torch.from_numpy(uniform.pos).cuda(), uniform.box)
+    regrows = rr.stats()["regrows"]
+    p = torch.from_numpy(dense.pos).cuda()
+    rr.build_lists(p, dense.box, wait=False)
+    rr.forces(p)                                    # enqueued on incomplete lists
+    assert not rr.check_lists()                     # ... and reported as such
+    with pytest.raises(Exception):
+        rr.forces(p)                                # lists invalid until rebuilt
+    rr.build_lists(p, dense.box, wait=False)        # grown rows: waits, complete
+    assert rr.check_lists()
+    F, E, W = rr.forces(p)
+    st = rr.stats()
+    assert st["regrows"] > regrows and st["atom_capacity"] >= st["atom_max_row"]
+    Fr, Er, Wr = oracle.compute(dense)
+    assert rel_rms(F.cpu().numpy(), Fr) <= TOL[64][0]
+    assert abs(E[0].item() - Er[0]) <= TOL[64][1] * abs(Er[0])
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(dense, which))
     rr.close()
 
 
