@@ -41,6 +41,28 @@ def make(sys_, precision, pair_math):
     return rr
 
 
+def recorded_traffic(workload):
+    """HBM bytes per force launch measured with rocprofv3 counters (FETCH_SIZE
+    and WRITE_SIZE, scaled by a copy of known size) for this workload, if a
+    summary under profiles/ records them for the kernel sources as they are
+    now; None otherwise (the counters describe another kernel)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_forces_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_t = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    m_h = re.search(r"^kernel_sources_sha256: ([0-9a-f]{64})$", text, re.M)
+    if not (m_t and m_h):
+        return None
+    h = hashlib.sha256()
+    for f in ("relres_kernels.hip", "relres_internal.h"):
+        with open(os.path.join(ROOT, "paper_2104_10231_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_t.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def algorithmic_bytes(st, force_bytes):
     """Bytes one force launch must move at minimum: FP64 positions read once
     (24 B/atom), forces written once, every list entry (4 B) and row count
@@ -157,7 +179,7 @@ def cpu_baseline(sys_, budget_s):
         oracle.compute(sys_, nthreads=threads)
         calls += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or calls >= 50:
+        if el >= budget_s or calls >= 1000:
             break
     return dict(value=sys_.n * calls / el, unit="atom-steps/s", cores=threads, kind="oracle",
                 sample=f"{calls} full FP64 O(N^2) force+energy+virial evaluations of the "
@@ -250,6 +272,7 @@ def main():
     if cpu:
         log(f"[bench] cpu oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
 
+    default_path = args.pair_math == 0 and args.lanes is None
     relres_entries = st["atom_entries"] + st["site_entries"]
     out = {
         "metric": "RelRes atom-steps/s vs conventional 14 Å LJ, 1 MI355X; % FP32/HBM roofline",
@@ -275,7 +298,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": recorded_traffic(args.workload) if default_path else None,
             "kernel": "k_forces", "kernel_us": force_us,
             "kernel_us_method": "HIP events on the launch stream around replays of a graph of "
                                 "10 back-to-back force launches",
