@@ -760,88 +760,111 @@ __device__ __forceinline__ void stage_table(T* dst, const T* __restrict__ src, i
     for (int k = threadIdx.x; k < words; k += blockDim.x) d[k] = s[k];
 }
 
-// Entries handled per lane per batch: their list loads, then their position
-// gathers, are issued together before any pair term is computed.
+// Entries handled per lane per batch (see row_terms).
 constexpr int kBatch = 2;
 
-// One list row: the FG part (CG = false, atom list, zero beyond r_s+) or the
-// CG part (CG = true, site list, zero beyond r_c+) of Eq. 20 for every entry.
-// Differences are taken in FP64 with the minimum image; the force terms are
-// evaluated in S and accumulated in TF; energy and virial terms are always
-// evaluated in FP64 (re-evaluated when S is float) and accumulated in FP64.
+constexpr uint32_t kNoEntry = 0xffffffffu;
+
+// Pair terms of one list entry, the FG part (CG = false, zero beyond r_s+) or
+// the CG part (CG = true, zero beyond r_c+) of Eq. 20, with the neighbour's
+// position already loaded.  Differences are taken in FP64 with the minimum
+// image.  Force terms are evaluated in S and accumulated in TF; energy and
+// virial terms are evaluated in FP64 and accumulated in FP64 (when they are
+// requested, the FP32 force is rounded from the same FP64 terms).
+template <bool CG, typename S, typename TF, bool EW>
+__device__ __forceinline__ void entry_terms(const ForceArgs& a, const PairCoef<S>* crow,
+                                            const PairCoef<double>* crow64,
+                                            const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
+                                            double xi, double yi, double zi, uint32_t e,
+                                            double px, double py, double pz,
+                                            TF& fx, TF& fy, TF& fz, double* acc)
+{
+    if (e == kNoEntry) return;
+    const double rmax2 = CG ? cut64.rco2 : cut64.rso2;
+    const int tj = (int)(e >> kIdxBits);
+    double dx = xi - px;
+    double dy = yi - py;
+    double dz = zi - pz;
+    dx -= a.box[0] * rint(dx * a.inv_box[0]);
+    dy -= a.box[1] * rint(dy * a.inv_box[1]);
+    dz -= a.box[2] * rint(dz * a.inv_box[2]);
+    const double r2d = dx * dx + dy * dy + dz * dz;
+    if (!(r2d < rmax2)) return;
+    if constexpr (sizeof(S) == sizeof(double) || EW) {
+        // FP64 pair terms (full precision in FP64 mode; one Newton step when
+        // they only feed energy/virial and FP32 forces)
+        using M = MathF64<sizeof(S) == sizeof(double) ? 2 : 1>;
+        double fpd, end;
+        if constexpr (CG) cg_term<M>(crow64[tj], cut64, r2d, fpd, end);
+        else fg_term<M>(crow64[tj], cut64, r2d, fpd, end);
+        if constexpr (sizeof(TF) == sizeof(double)) {
+            fx += fpd * dx;
+            fy += fpd * dy;
+            fz += fpd * dz;
+        } else {
+            const float fp = (float)fpd;
+            fx += fp * (float)dx;
+            fy += fp * (float)dy;
+            fz += fp * (float)dz;
+        }
+        if constexpr (EW) {
+            const double hf = 0.5 * fpd;
+            acc[CG ? 1 : 0] += 0.5 * end;
+            acc[2] += hf * dx * dx;
+            acc[3] += hf * dy * dy;
+            acc[4] += hf * dz * dz;
+            acc[5] += hf * dx * dy;
+            acc[6] += hf * dx * dz;
+            acc[7] += hf * dy * dz;
+        }
+    } else {
+        float fp, en;
+        if constexpr (CG) cg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
+        else fg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
+        fx += fp * (float)dx;
+        fy += fp * (float)dy;
+        fz += fp * (float)dz;
+    }
+}
+
+// Positions of a batch of entries (entry-less slots read atom 0, unused).
+__device__ __forceinline__ void gather_batch(const ForceArgs& a, const uint32_t e[kBatch],
+                                             double px[kBatch], double py[kBatch],
+                                             double pz[kBatch])
+{
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+        const int uj = e[u] != kNoEntry ? (int)(e[u] & kIdxMask) : 0;
+        px[u] = a.pos[3 * uj];
+        py[u] = a.pos[3 * uj + 1];
+        pz[u] = a.pos[3 * uj + 2];
+    }
+}
+
+// Entries start, start + G, ... below cnt of one list row, kBatch per lane at
+// a time: their list loads, then their position gathers, are issued together
+// before any pair term is computed.
 template <bool CG, typename S, typename TF, bool EW>
 __device__ __forceinline__ void row_terms(const ForceArgs& a, const PairCoef<S>* crow,
                                           const PairCoef<double>* crow64,
                                           const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
                                           double xi, double yi, double zi,
-                                          const int* __restrict__ lst, int cnt, int sub, int G,
+                                          const int* __restrict__ lst, int start, int cnt, int G,
                                           TF& fx, TF& fy, TF& fz, double* acc)
 {
-    const double rmax2 = CG ? cut64.rco2 : cut64.rso2;
-    for (int base = sub; base < cnt; base += G * kBatch) {
+    for (int base = start; base < cnt; base += G * kBatch) {
         uint32_t e[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int k = base + u * G;
-            e[u] = k < cnt ? (uint32_t)lst[k] : 0xffffffffu;
+            e[u] = k < cnt ? (uint32_t)lst[k] : kNoEntry;
         }
         double px[kBatch], py[kBatch], pz[kBatch];
+        gather_batch(a, e, px, py, pz);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int uj = e[u] != 0xffffffffu ? (int)(e[u] & kIdxMask) : 0;
-            px[u] = a.pos[3 * uj];
-            py[u] = a.pos[3 * uj + 1];
-            pz[u] = a.pos[3 * uj + 2];
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            if (e[u] == 0xffffffffu) continue;
-            const int tj = (int)(e[u] >> kIdxBits);
-            double dx = xi - px[u];
-            double dy = yi - py[u];
-            double dz = zi - pz[u];
-            dx -= a.box[0] * rint(dx * a.inv_box[0]);
-            dy -= a.box[1] * rint(dy * a.inv_box[1]);
-            dz -= a.box[2] * rint(dz * a.inv_box[2]);
-            const double r2d = dx * dx + dy * dy + dz * dz;
-            if (r2d < rmax2) {
-                if constexpr (sizeof(S) == sizeof(double) || EW) {
-                    // FP64 pair terms (full precision in FP64 mode; one Newton
-                    // step when they only feed energy/virial and FP32 forces)
-                    using M = MathF64<sizeof(S) == sizeof(double) ? 2 : 1>;
-                    double fpd, end;
-                    if constexpr (CG) cg_term<M>(crow64[tj], cut64, r2d, fpd, end);
-                    else fg_term<M>(crow64[tj], cut64, r2d, fpd, end);
-                    if constexpr (sizeof(TF) == sizeof(double)) {
-                        fx += fpd * dx;
-                        fy += fpd * dy;
-                        fz += fpd * dz;
-                    } else {
-                        const float fp = (float)fpd;
-                        fx += fp * (float)dx;
-                        fy += fp * (float)dy;
-                        fz += fp * (float)dz;
-                    }
-                    if constexpr (EW) {
-                        const double hf = 0.5 * fpd;
-                        acc[CG ? 1 : 0] += 0.5 * end;
-                        acc[2] += hf * dx * dx;
-                        acc[3] += hf * dy * dy;
-                        acc[4] += hf * dz * dz;
-                        acc[5] += hf * dx * dy;
-                        acc[6] += hf * dx * dz;
-                        acc[7] += hf * dy * dz;
-                    }
-                } else {
-                    float fp, en;
-                    if constexpr (CG) cg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
-                    else fg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
-                    fx += fp * (float)dx;
-                    fy += fp * (float)dy;
-                    fz += fp * (float)dz;
-                }
-            }
-        }
+        for (int u = 0; u < kBatch; ++u)
+            entry_terms<CG, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi, e[u], px[u],
+                                       py[u], pz[u], fx, fy, fz, acc);
     }
 }
 
@@ -923,15 +946,19 @@ constexpr int kPollBatch = 16;   // records polled per thread at once
 // Writes one record: called by the whole block, `v` valid in threads 0..7
 // (component threadIdx.x).  Lanes 0..15 of wave 0 store word threadIdx.x, so
 // the record goes out as one contiguous 128-byte write.
+// Writes one record: called by the whole block, `v` valid in threads 0..7
+// (component threadIdx.x).  Lanes 0..15 of wave 0 store word threadIdx.x, so
+// the record goes out as one contiguous 128-byte write, written through to
+// the level all XCDs share.
 __device__ __forceinline__ void put_record(unsigned long long* rec, double v, unsigned tag)
 {
     if (threadIdx.x < 64) {
         const double c = __shfl(v, (int)(threadIdx.x >> 1));
         const unsigned long long bits = (unsigned long long)__double_as_longlong(c);
         const unsigned long long half = (threadIdx.x & 1) ? (bits & 0xffffffffull) : (bits >> 32);
+        const unsigned long long word = ((unsigned long long)tag << 32) | half;
         if (threadIdx.x < kRecWords)
-            __hip_atomic_store(rec + threadIdx.x, ((unsigned long long)tag << 32) | half,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(rec + threadIdx.x, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -949,25 +976,26 @@ __device__ __forceinline__ void gather_records(const unsigned long long* rec, in
     const int comp = word >> 1;
     double sum = 0.0;
     for (int base = 0; base < count; base += (kForceBlock / kRecWords) * kPollBatch) {
-        unsigned long long w[kPollBatch];
-        bool need[kPollBatch];
+        // every slot loads on every poll (slots past `count` re-read the
+        // first record), so all loads of a poll are in flight together; a
+        // record already complete is final for this launch
+        size_t off[kPollBatch];
+        bool valid[kPollBatch];
 #pragma unroll
         for (int u = 0; u < kPollBatch; ++u) {
             const int m = base + t / kRecWords + (kForceBlock / kRecWords) * u;
-            need[u] = m < count;
-            w[u] = 0;
+            valid[u] = m < count;
+            off[u] = (size_t)(first + stride * (valid[u] ? m : 0)) * kRecWords + word;
         }
+        unsigned long long w[kPollBatch];
         for (int it = 0;; ++it) {
+#pragma unroll
+            for (int u = 0; u < kPollBatch; ++u)
+                w[u] = __hip_atomic_load(rec + off[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             bool pending = false;
 #pragma unroll
-            for (int u = 0; u < kPollBatch; ++u) {
-                if (!need[u]) continue;
-                const int m = base + t / kRecWords + (kForceBlock / kRecWords) * u;
-                w[u] = __hip_atomic_load(rec + (size_t)(first + stride * m) * kRecWords + word,
-                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                need[u] = (unsigned)(w[u] >> 32) != tag;
-                pending |= need[u];
-            }
+            for (int u = 0; u < kPollBatch; ++u)
+                pending |= valid[u] && (unsigned)(w[u] >> 32) != tag;
             if (!pending) break;
             if (it >= kSpinLimit) {
                 *failed = 1;
@@ -977,9 +1005,8 @@ __device__ __forceinline__ void gather_records(const unsigned long long* rec, in
         }
 #pragma unroll
         for (int u = 0; u < kPollBatch; ++u) {
-            const int m = base + t / kRecWords + (kForceBlock / kRecWords) * u;
             const unsigned lo = (unsigned)__shfl_down((unsigned)(w[u] & 0xffffffffull), 1);
-            if (!(word & 1) && m < count)
+            if (!(word & 1) && valid[u])
                 sum += __longlong_as_double((long long)(((w[u] & 0xffffffffull) << 32) | lo));
         }
     }
@@ -1020,6 +1047,8 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
 
     if (threadIdx.x == 0) failed = 0;
     const double mine = block_reduce8(acc, 0.0, red);
+    // records: blocks [0, nb), groups [nb, nb + 8)
+    unsigned long long* grec = a.ew_rec + (size_t)nb * kRecWords;
     if (b != last_in_group) {
         put_record(a.ew_rec + (size_t)b * kRecWords, mine, tag);
         return;
@@ -1028,7 +1057,6 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     double v[8];
     gather_records(a.ew_rec, g, kXcdGroups, b / kXcdGroups, tag, v, &failed);
     const double gsum = block_reduce8(v, mine, red);
-    unsigned long long* grec = a.ew_rec + (size_t)nb * kRecWords;
     if (b != nb - 1) {
         put_record(grec + (size_t)g * kRecWords, failed ? __builtin_nan("") : gsum, tag);
         return;
@@ -1099,14 +1127,42 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         tag = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
         tag += tag == 0u;
     }
-    // row record first: it is the head of every dependent load chain
+    // The row's own list (the atom list for rows of ordinary atoms, the site
+    // list for rows of hybrid atoms) does not depend on the row record, so its
+    // first entries are loaded together with the record.  Slots past the row's
+    // count read the row's padding (in bounds) and are dropped once the count
+    // is known.
+    const bool live = rb ? row < a.n_srow : row < a.n_arow;
+    const int* own_list = rb ? a.s_list + (size_t)row * a.s_cap : a.a_list + (size_t)row * a.a_cap;
+    const int own_cap = rb ? a.s_cap : a.a_cap;
+    uint32_t e_own[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+        const int k = sub + u * G;
+        e_own[u] = (live && k < own_cap) ? (uint32_t)own_list[k] : kNoEntry;
+    }
     int4 rec = make_int4(-1, 0, 0, 1);
-    int cnt_a = 0;
-    if (!rb) {
-        if (row < a.n_arow) rec = a.a_rec[row];
-    } else if (row < a.n_srow) {
-        rec = a.s_rec[row];
-        cnt_a = a.a_rec[rec.w].z;
+    if (live) rec = rb ? a.s_rec[row] : a.a_rec[row];
+    // FG entries: for a hybrid row they sit in the atom-list row named by the
+    // record (loaded together with that row's count)
+    uint32_t e_fg[kBatch];
+    int cnt_a = rec.z;
+    if (rb) {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) e_fg[u] = kNoEntry;
+        cnt_a = 0;
+        if (live) {
+            const int* fl = a.a_list + (size_t)rec.w * a.a_cap;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int k = sub + u * G;
+                if (k < a.a_cap) e_fg[u] = (uint32_t)fl[k];
+            }
+            cnt_a = a.a_rec[rec.w].z;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) e_fg[u] = e_own[u];
     }
 
     const PairCoef<S>* coef;
@@ -1131,16 +1187,40 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const bool own = rb ? rec.x >= 0 : (rec.x >= 0 && rec.w == 0);   // hybrid atom rows belong to the site range
     if (own) {
         const int ui = rec.x, ti = rec.y;
+        const int cnt_s = rb ? rec.z : 0;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int k = sub + u * G;
+            if (k >= cnt_a) e_fg[u] = kNoEntry;
+            if (k >= cnt_s) e_own[u] = kNoEntry;
+        }
         const double xi = a.pos[3 * ui], yi = a.pos[3 * ui + 1], zi = a.pos[3 * ui + 2];
+        // the first batches of both parts: all gathers before any arithmetic
+        double fxp[kBatch], fyp[kBatch], fzp[kBatch], sxp[kBatch], syp[kBatch], szp[kBatch];
+        gather_batch(a, e_fg, fxp, fyp, fzp);
+        if (rb) gather_batch(a, e_own, sxp, syp, szp);
+        const PairCoef<S>* crow = coef + ti * a.ntypes;
+        const PairCoef<double>* crow64 = coef64 + ti * a.ntypes;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            entry_terms<false, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi, e_fg[u],
+                                          fxp[u], fyp[u], fzp[u], fx, fy, fz, acc);
+        if (rb) {
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                entry_terms<true, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi, e_own[u],
+                                             sxp[u], syp[u], szp[u], fx, fy, fz, acc);
+        }
+        // the rest of both rows
         const int ar = rb ? rec.w : row;
-        const int ca = rb ? cnt_a : rec.z;
-        row_terms<false, S, TF, EW>(a, coef + ti * a.ntypes, coef64 + ti * a.ntypes, cut, cut64,
-                                    xi, yi, zi, a.a_list + (size_t)ar * a.a_cap, ca, sub, G,
-                                    fx, fy, fz, acc);
+        const int rest = sub + kBatch * G;
+        row_terms<false, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi,
+                                    a.a_list + (size_t)ar * a.a_cap, rest, cnt_a, G, fx, fy, fz,
+                                    acc);
         if (rb)
-            row_terms<true, S, TF, EW>(a, coef + ti * a.ntypes, coef64 + ti * a.ntypes, cut, cut64,
-                                       xi, yi, zi, a.s_list + (size_t)row * a.s_cap, rec.z, sub,
-                                       G, fx, fy, fz, acc);
+            row_terms<true, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi,
+                                       a.s_list + (size_t)row * a.s_cap, rest, cnt_s, G, fx, fy,
+                                       fz, acc);
     }
     fx = group_sum(fx, G);
     fy = group_sum(fy, G);
