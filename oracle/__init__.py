@@ -10,6 +10,9 @@ Every function follows a passage of arXiv:2104.10231:
   pair          -- Eq. 20, case by case
   compute       -- Eq. 3 energy, forces, pair virial (brute force, all pairs)
   pairs         -- the two neighbour pair sets (Sec. 2.6 lists)
+  grad          -- gradient of e_bar E + sum_i g_i . F_i with respect to the
+                   per-type parameters and the positions (Eqs. 7-9 and 20
+                   differentiated; the systems of Eqs. 7/8 are linear)
 """
 from __future__ import annotations
 
@@ -54,6 +57,10 @@ def lib():
                                    ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
         L.oracle_pairs.restype = ctypes.c_long
+        L.oracle_grad.argtypes = [ctypes.c_int, _d, _d, _i, _i, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _d, _d, _d, _d,
+                                  ctypes.c_int, _d, _d, ctypes.c_double, _d, _d]
+        L.oracle_grad.restype = ctypes.c_int
         assert L.oracle_record_size() == REC
         _LIB = L
     return _LIB
@@ -153,6 +160,27 @@ def compute(sys, pos=None, nthreads: int = 0, sel=None, table=None):
     if sel is not None:
         return F, None, None
     return F, E, W
+
+
+def grad(sys, g, e_bar: float = 0.0, pos=None):
+    """Gradient of J = e_bar * E + sum_i g_i . F_i.
+
+    Returns (dtheta, dpos): dtheta is (4, ntypes) for per-type eps_FG, sigma_FG,
+    eps_CG, sigma_CG (CG rows zero for ordinary types), dpos is (N, 3).
+    """
+    pos = _f64(sys.pos if pos is None else pos)
+    n = pos.shape[0]
+    eo, ei = _excl(sys)
+    dtheta = np.zeros(4 * sys.ntypes)
+    dpos = np.zeros((n, 3))
+    rc = lib().oracle_grad(n, pos, _f64(sys.box), _i32(sys.types), _i32(sys.mol),
+                           int(bool(sys.exclude_same_mol)), _ptr(eo), _ptr(ei), sys.ntypes,
+                           _f64(sys.eps_fg), _f64(sys.sig_fg), _f64(sys.eps_cg), _f64(sys.sig_cg),
+                           int(sys.mix), cutoffs(sys), _f64(np.asarray(g).reshape(n, 3)),
+                           float(e_bar), dtheta, dpos)
+    if rc:
+        raise ValueError(f"oracle_grad failed ({rc})")
+    return dtheta.reshape(4, sys.ntypes), dpos
 
 
 def hybrid_flags(sys) -> np.ndarray:

@@ -23,7 +23,13 @@
  *     periodic orthorhombic box (minimum image), forces F_i = -dE/dx_i and the
  *     pair virial W_ab = sum_{i<j} d_a F_ij,b with d = x_i - x_j;
  *   - the two neighbour pair sets that a list-based code must find: atom pairs
- *     with r < r_s+ + skin and hybrid-hybrid pairs with r < r_c+ + skin.
+ *     with r < r_s+ + skin and hybrid-hybrid pairs with r < r_c+ + skin;
+ *   - the gradient of J = e_bar E + sum_i g_i . F_i with respect to the
+ *     per-type parameters and the positions.  Every smoothing coefficient and
+ *     shifting constant is a linear function of u, u', u'' at a zone
+ *     boundary (Eqs. 7-9 are linear systems), so their parameter derivatives
+ *     come from solving the same systems with differentiated right-hand
+ *     sides; Eq. 20 is then differentiated case by case.
  *
  * Readings where the paper is silent or garbled (also listed in the design doc):
  *   - Eq. 18 prints gamma_4+ with the wrong sign of its u'' term; the oracle
@@ -402,4 +408,190 @@ void oracle_pair_vec(const double *R, const double cut[4], int m, const double *
         u[k] = oracle_pair(R, cut, r[k], dudr + k, which ? which + k : NULL);
         if (e_fg && e_cg) pair_split(R, cut, r[k], e_fg + k, e_cg + k);
     }
+}
+
+/* ---------------------------------------------------------------------------
+ * Gradients
+ * ------------------------------------------------------------------------- */
+
+/* Parameter derivative of u, u', u'' (Eqs. 11/12): wrt = 0 -> d/d eps,
+ * wrt = 1 -> d/d sigma.  With q = sigma/r:
+ *   du/deps   = 4 (q^12 - q^6)              du/dsig   = 4 eps (12 q^12 - 6 q^6) / sigma
+ *   du'/deps  = 4 (-12 q^12 + 6 q^6) / r    du'/dsig  = 4 eps (-144 q^12 + 36 q^6) / (sigma r)
+ *   du''/deps = 4 (156 q^12 - 42 q^6) / r^2 du''/dsig = 4 eps (1872 q^12 - 252 q^6) / (sigma r^2) */
+static void lj_dparam(double eps, double sig, double r, int wrt, double out[3])
+{
+    double q = sig / r;
+    double q6 = q * q * q * q * q * q;
+    double q12 = q6 * q6;
+    if (wrt == 0) {
+        out[0] = 4.0 * (q12 - q6);
+        out[1] = 4.0 * (-12.0 * q12 + 6.0 * q6) / r;
+        out[2] = 4.0 * (156.0 * q12 - 42.0 * q6) / (r * r);
+    } else {
+        out[0] = 4.0 * eps * (12.0 * q12 - 6.0 * q6) / sig;
+        out[1] = 4.0 * eps * (-144.0 * q12 + 36.0 * q6) / (sig * r);
+        out[2] = 4.0 * eps * (1872.0 * q12 - 252.0 * q6) / (sig * r * r);
+    }
+}
+
+static double d2poly(const double g[5], double d)
+{
+    return 2.0 * g[2] + 6.0 * g[3] * d + 12.0 * g[4] * d * d;
+}
+
+/* Derivative of a type-pair record with respect to one pair parameter
+ * (P: 0 eps_FG, 1 sigma_FG, 2 eps_CG, 3 sigma_CG): the polynomial
+ * coefficients solved from Eqs. 7/8 with the differentiated boundary values,
+ * and Eq. 9 applied to them.  The CG part of a pair that is not hybrid-hybrid
+ * is zero by Eq. 14 and does not depend on the CG parameters.              */
+static int dparam_record(const double *R, int P, const double cut[4], double *dR)
+{
+    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    double Ds = rso - rsi, Dc = rco - rci, du[3];
+    memset(dR, 0, sizeof(double) * OR_REC);
+    if (P < 2) {
+        lj_dparam(R[R_EPS_FG], R[R_SIG_FG], rsi, P, du);
+        if (oracle_solve_poly(0, Ds, du, dR + R_FG_SM)) return -2;
+    } else if (R[R_EPS_CG] > 0.0) {
+        lj_dparam(R[R_EPS_CG], R[R_SIG_CG], rso, P - 2, du);
+        if (oracle_solve_poly(1, Ds, du, dR + R_CG_SP)) return -2;
+        lj_dparam(R[R_EPS_CG], R[R_SIG_CG], rci, P - 2, du);
+        if (oracle_solve_poly(0, Dc, du, dR + R_CG_CM)) return -2;
+    }
+    dR[R_G_CM] = poly(dR + R_CG_CM, Dc);
+    dR[R_G_SP] = poly(dR + R_CG_CM, Dc) + poly(dR + R_FG_SM, Ds);
+    dR[R_G_SM] = poly(dR + R_CG_CM, Dc) + poly(dR + R_FG_SM, Ds) - poly(dR + R_CG_SP, 0.0);
+    return 0;
+}
+
+/* d u~/dP and d u~'/dP at r: Eq. 20 differentiated case by case.           */
+static void pair_dparam(const double *R, const double *dR, int P, const double cut[4],
+                        double r, double *du, double *dup)
+{
+    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3], v[3];
+    if (r < rsi) {
+        if (P < 2) {
+            lj_dparam(R[R_EPS_FG], R[R_SIG_FG], r, P, v);
+            *du = v[0] - dR[R_G_SM];
+            *dup = v[1];
+        } else {
+            *du = -dR[R_G_SM];
+            *dup = 0.0;
+        }
+    } else if (r < rso) {
+        double g[5], d = r - rsi;
+        for (int m = 0; m < 5; ++m) g[m] = dR[R_FG_SM + m] + dR[R_CG_SP + m];
+        *du = poly(g, d) - dR[R_G_SP];
+        *dup = dpoly(g, d);
+    } else if (r < rci) {
+        if (P >= 2 && R[R_EPS_CG] > 0.0) {
+            lj_dparam(R[R_EPS_CG], R[R_SIG_CG], r, P - 2, v);
+            *du = v[0] - dR[R_G_CM];
+            *dup = v[1];
+        } else {
+            *du = -dR[R_G_CM];
+            *dup = 0.0;
+        }
+    } else if (r < rco) {
+        double d = r - rci;
+        *du = poly(dR + R_CG_CM, d) - dR[R_G_CM];
+        *dup = dpoly(dR + R_CG_CM, d);
+    } else {
+        *du = 0.0;
+        *dup = 0.0;
+    }
+}
+
+/* Second derivative of Eq. 20, case by case. */
+static double pair_d2(const double *R, const double cut[4], double r)
+{
+    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3], u[3];
+    if (r < rsi) { oracle_lj(R[R_EPS_FG], R[R_SIG_FG], r, u); return u[2]; }
+    if (r < rso) {
+        double g[5];
+        for (int m = 0; m < 5; ++m) g[m] = R[R_FG_SM + m] + R[R_CG_SP + m];
+        return d2poly(g, r - rsi);
+    }
+    if (r < rci) { oracle_lj(R[R_EPS_CG], R[R_SIG_CG], r, u); return u[2]; }
+    if (r < rco) return d2poly(R + R_CG_CM, r - rci);
+    return 0.0;
+}
+
+/* Derivatives of one mixed pair parameter with respect to the two per-type
+ * values it is mixed from: geometric mean sqrt(a b) or arithmetic mean.     */
+static void mix_grad(int arithmetic, double a, double b, double *da, double *db)
+{
+    if (arithmetic) { *da = 0.5; *db = 0.5; return; }
+    *da = 0.5 * sqrt(b / a);
+    *db = 0.5 * sqrt(a / b);
+}
+
+/* Gradient of J = e_bar * E + sum_i g_i . F_i (E of Eq. 3, F_i = -dE/dx_i)
+ * with respect to the per-type parameters (dtheta[P*ntypes + t], P = 0
+ * eps_FG, 1 sigma_FG, 2 eps_CG, 3 sigma_CG) and the positions (dpos, n x 3).
+ * Brute force over all non-excluded pairs i < j, serial.  Per pair, with
+ * d = x_j - x_i, r = |d|, s = u~'(r)/r (F_i gets s d, F_j gets -s d):
+ *   dJ/dx_j = e_bar u~' d/r + grad_d [ s (g_i - g_j) . d ],  dJ/dx_i = -dJ/dx_j,
+ *   grad_d [ s w . d ] = s w + (ds/dr / r) (w . d) d,  ds/dr = u~''/r - u~'/r^2;
+ *   dJ/dP = e_bar du~/dP + (du~'/dP / r) (g_i - g_j) . d,
+ * and dJ/dP is carried to the per-type values through the mixing rule.  The
+ * CG parameters of ordinary types receive nothing (Eq. 14 fixes their pair
+ * parameters at zero).  Per-type parameters entering a geometric mean must be
+ * positive.  Returns 0, or a negative code as oracle_setup.                 */
+int oracle_grad(int n, const double *pos, const double *box, const int *types,
+                const int *mol, int same_mol, const int *eoff, const int *eidx,
+                int ntypes, const double *eps_fg, const double *sig_fg,
+                const double *eps_cg, const double *sig_cg, int mix, const double cut[4],
+                const double *g, double e_bar, double *dtheta, double *dpos)
+{
+    size_t np = (size_t)ntypes * ntypes;
+    double *table = (double *)malloc(sizeof(double) * np * OR_REC);
+    double *dtab = (double *)malloc(sizeof(double) * np * 4 * OR_REC);
+    double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!table || !dtab || !w) { free(table); free(dtab); free(w); return -3; }
+    int rc = oracle_setup(ntypes, eps_fg, sig_fg, eps_cg, sig_cg, mix, cut, table);
+    for (size_t k = 0; rc == 0 && k < np; ++k)
+        for (int P = 0; P < 4 && rc == 0; ++P)
+            rc = dparam_record(table + k * OR_REC, P, cut, dtab + (k * 4 + P) * OR_REC);
+    if (rc) { free(table); free(dtab); free(w); return rc; }
+    oracle_wrap(n, pos, box, w);
+    memset(dtheta, 0, sizeof(double) * 4 * (size_t)ntypes);
+    memset(dpos, 0, sizeof(double) * 3 * (size_t)n);
+    const double *pe[4] = {eps_fg, sig_fg, eps_cg, sig_cg};
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            if (is_excluded(i, j, mol, same_mol, eoff, eidx)) continue;
+            double d[3];
+            min_image(w + 3 * i, w + 3 * j, box, d);      /* d = x_j - x_i */
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r < cut[3])) continue;
+            int p = types[i], q = types[j];
+            size_t k = (size_t)(p * ntypes + q);
+            const double *R = table + k * OR_REC;
+            double u1;
+            (void)oracle_pair(R, cut, r, &u1, NULL);
+            double u2 = pair_d2(R, cut, r);
+            double wv[3] = {g[3 * i] - g[3 * j], g[3 * i + 1] - g[3 * j + 1], g[3 * i + 2] - g[3 * j + 2]};
+            double wd = wv[0] * d[0] + wv[1] * d[1] + wv[2] * d[2];
+            double s = u1 / r;
+            double dsr = (u2 / r - u1 / (r * r)) / r;
+            for (int c = 0; c < 3; ++c) {
+                double gj = e_bar * u1 * d[c] / r + s * wv[c] + dsr * wd * d[c];
+                dpos[3 * j + c] += gj;
+                dpos[3 * i + c] -= gj;
+            }
+            for (int P = 0; P < 4; ++P) {
+                if (P >= 2 && !(R[R_EPS_CG] > 0.0)) continue;
+                double du, dup;
+                pair_dparam(R, dtab + (k * 4 + P) * OR_REC, P, cut, r, &du, &dup);
+                double cP = e_bar * du + (dup / r) * wd;
+                double da, db;
+                mix_grad((P == 1 || P == 3) && mix == 1, pe[P][p], pe[P][q], &da, &db);
+                dtheta[P * ntypes + p] += cP * da;
+                dtheta[P * ntypes + q] += cP * db;
+            }
+        }
+    free(table); free(dtab); free(w);
+    return 0;
 }
