@@ -160,6 +160,33 @@ int relres_check_lists(relres_ctx *ctx);
 int relres_forces(relres_ctx *ctx, const double *pos, void *forces, double *energy,
                   double *virial, void *stream);
 
+/* Replace the pair parameters (Sec. 2.3 mixing bypassed): host arrays of
+ * ntypes*ntypes doubles, row-major [a][b] (ordered entries; a symmetric
+ * table describes the usual physics).  The FG entries need eps >= 0 and
+ * sigma > 0; the CG entries are used only for hybrid-hybrid type pairs
+ * (where they need eps >= 0, sigma > 0) and are zero otherwise (Eq. 14).
+ * Recomputes every coefficient of Eqs. 17-19 on the host and uploads them;
+ * waits for the device first.  Lists stay valid.                          */
+int relres_set_pair_params(relres_ctx *ctx, const double *eps_fg, const double *sig_fg,
+                           const double *eps_cg, const double *sig_cg);
+
+/* Adjoint of relres_forces for J = e_bar * E + sum_i g_i . F_i, where E is
+ * the total energy (Eq. 3) and F the forces, at the device positions pos
+ * (N x 3 FP64) with the lists of the last build:
+ *   grad_forces  device N x 3 FP64: g = dJ/dF (NULL: zero);
+ *   grad_energy  device double[1]: e_bar = dJ/dE (NULL: zero);
+ *   grad_pos     device N x 3 FP64, overwritten with dJ/dx;
+ *   grad_pair    device double[4 * ntypes * ntypes], overwritten with dJ/dP
+ *                for P = eps_FG, sigma_FG, eps_CG, sigma_CG (that order),
+ *                each [a][b] row-major, treating the ordered pair entries
+ *                as independent (chain through the mixing rule outside).
+ * Pair terms are recomputed (FP64), nothing is stored by relres_forces.
+ * Parameter sums are reduced in a fixed order (bitwise repeatable).  At most
+ * 8 types.  Asynchronous on `stream`.                                      */
+int relres_backward(relres_ctx *ctx, const double *pos, const double *grad_forces,
+                    const double *grad_energy, double *grad_pos, double *grad_pair,
+                    void *stream);
+
 /* List statistics of the last build (host struct).  Entry counts and row
  * lengths are computed on demand by a small kernel the first time they are
  * asked for after a build, which synchronises the device.                   */

@@ -105,6 +105,61 @@ double mix_sigma(int mix, double a, double b)
     return mix == RELRES_MIX_GEOMETRIC ? std::sqrt(a * b) : 0.5 * (a + b);
 }
 
+// u, u', u'' (wrt = 0) or their derivatives with respect to eps (wrt = 1) or
+// sigma (wrt = 2).  u is linear in eps; with q = sigma/r the sigma
+// derivatives are 4 eps (12 q^12 - 6 q^6)/sigma, 24 eps (6 q^6 - 24 q^12)/(r
+// sigma) and 24 eps (312 q^12 - 42 q^6)/(r^2 sigma).
+LJ3 lj3_wrt(double eps, double sig, double r, int wrt)
+{
+    if (wrt == 0) return lj3(eps, sig, r);
+    if (wrt == 1) return lj3(1.0, sig, r);
+    const double q2 = (sig / r) * (sig / r);
+    const double q6 = q2 * q2 * q2;
+    const double q12 = q6 * q6;
+    return {4.0 * eps * (12.0 * q12 - 6.0 * q6) / sig, 24.0 * eps / (r * sig) * (6.0 * q6 - 24.0 * q12),
+            24.0 * eps / (r * r * sig) * (312.0 * q12 - 42.0 * q6)};
+}
+
+// A eps sigma^n, or its derivative with respect to eps (wrt 1) or sigma (wrt 2)
+double power_term(double A, double eps, double sig, int n, int wrt)
+{
+    double p = 1.0;
+    for (int k = 0; k < (wrt == 2 ? n - 1 : n); ++k) p *= sig;
+    return wrt == 0 ? A * eps * p : wrt == 1 ? A * p : n * A * eps * p;
+}
+
+// FG part of a pair record (LJ constants of Eq. 11, f_s-^FG of Eq. 17 and its
+// end value), or its derivative with respect to eps / sigma.  Every field is
+// linear in (A eps sigma^n) terms and in u, u', u'' at r_s- (Eqs. 17, 19), so
+// differentiating the inputs differentiates the record.
+void fg_part(PairCoef<double>& k, double e, double s, int wrt, double rsi, double Ds)
+{
+    k.fg_c12 = power_term(48.0, e, s, 12, wrt);
+    k.fg_c6 = power_term(24.0, e, s, 6, wrt);
+    k.fg_e12 = power_term(4.0, e, s, 12, wrt);
+    k.fg_e6 = power_term(4.0, e, s, 6, wrt);
+    switch_off(lj3_wrt(e, s, rsi, wrt), Ds, k.fg_g);
+    k.fg_shift = poly_at(k.fg_g, Ds);
+}
+
+// CG part: LJ constants of Eq. 12, f_s+^CG (Eq. 18), f_c-^CG (Eq. 17) and
+// Gamma_c- (Eq. 19), or their derivatives.
+void cg_part(PairCoef<double>& k, double e, double s, int wrt, double rso, double rci, double Ds,
+             double Dc)
+{
+    k.cg_c12 = power_term(48.0, e, s, 12, wrt);
+    k.cg_c6 = power_term(24.0, e, s, 6, wrt);
+    k.cg_e12 = power_term(4.0, e, s, 12, wrt);
+    k.cg_e6 = power_term(4.0, e, s, 6, wrt);
+    double g[5];
+    switch_on(lj3_wrt(e, s, rso, wrt), Ds, g);
+    k.sp_g0 = g[0];
+    k.sp_g3 = g[3];
+    k.sp_g4 = g[4];
+    switch_off(lj3_wrt(e, s, rci, wrt), Dc, k.cm_g);
+    k.cm_shift = poly_at(k.cm_g, Dc);
+}
+
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
@@ -162,8 +217,9 @@ struct relres_ctx {
     double rsi = 0, rso = 0, rci = 0, rco = 0, skin = 0;
     int ntypes = 0, mix = 0, precision = 64, pair_math = 64;
     std::vector<int> hybrid;
-    std::vector<PairCoef<double>> coef64;
-    DBuf d_coef64, d_coef32, d_hybrid;
+    std::vector<PairCoef<double>> coef64;     // per type pair
+    std::vector<PairCoef<double>> coef_grad;  // [4][pair]: d/d eps_FG, sigma_FG, eps_CG, sigma_CG
+    DBuf d_coef64, d_coef32, d_hybrid, d_coef_grad, d_bpartial;
     double cut64[8] = {0};
 
     bool topo_set = false;
@@ -205,6 +261,51 @@ struct relres_ctx {
 };
 
 namespace {
+
+// Coefficient records of every type pair from pair tables (row-major
+// [a][b]): the record of Eq. 20's FG and CG parts, and its derivatives with
+// respect to the four pair parameters.  The CG part of a pair that is not
+// hybrid-hybrid is zero (Eq. 14).
+void build_tables(relres_ctx* c, const double* ef, const double* sf, const double* ec,
+                  const double* sc)
+{
+    const int nt = c->ntypes;
+    const size_t np = (size_t)nt * nt;
+    const double Ds = c->rso - c->rsi, Dc = c->rco - c->rci;
+    c->coef64.assign(np, PairCoef<double>{});
+    c->coef_grad.assign(4 * np, PairCoef<double>{});
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const size_t q = (size_t)a * nt + b;
+            fg_part(c->coef64[q], ef[q], sf[q], 0, c->rsi, Ds);
+            fg_part(c->coef_grad[0 * np + q], ef[q], sf[q], 1, c->rsi, Ds);
+            fg_part(c->coef_grad[1 * np + q], ef[q], sf[q], 2, c->rsi, Ds);
+            if (c->hybrid[a] && c->hybrid[b]) {
+                cg_part(c->coef64[q], ec[q], sc[q], 0, c->rso, c->rci, Ds, Dc);
+                cg_part(c->coef_grad[2 * np + q], ec[q], sc[q], 1, c->rso, c->rci, Ds, Dc);
+                cg_part(c->coef_grad[3 * np + q], ec[q], sc[q], 2, c->rso, c->rci, Ds, Dc);
+            }
+        }
+}
+
+// Copy the coefficient tables to the device (FP64, an FP32 copy, and the
+// derivative records).  Synchronous.
+int upload_tables(relres_ctx* c)
+{
+    std::vector<PairCoef<float>> coef32(c->coef64.size());
+    for (size_t k = 0; k < coef32.size(); ++k) {
+        const double* src = reinterpret_cast<const double*>(&c->coef64[k]);
+        float* dst = reinterpret_cast<float*>(&coef32[k]);
+        for (size_t q = 0; q < sizeof(PairCoef<double>) / sizeof(double); ++q) dst[q] = (float)src[q];
+    }
+    HIP_TRY(hipMemcpy(c->d_coef64.p, c->coef64.data(), sizeof(PairCoef<double>) * c->coef64.size(),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_coef32.p, coef32.data(), sizeof(PairCoef<float>) * coef32.size(),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_coef_grad.p, c->coef_grad.data(),
+                      sizeof(PairCoef<double>) * c->coef_grad.size(), hipMemcpyHostToDevice));
+    return RELRES_OK;
+}
 
 int take_events(relres_ctx* c, hipEvent_t& a, hipEvent_t& b)
 {
@@ -635,56 +736,30 @@ int relres_create(const relres_params* p, relres_ctx** out)
     c->hybrid.resize(nt);
     for (int t = 0; t < nt; ++t) c->hybrid[t] = p->eps_cg[t] > 0.0 ? 1 : 0;
 
-    const double Ds = c->rso - c->rsi, Dc = c->rco - c->rci;
-    c->coef64.resize((size_t)nt * nt);
-    std::vector<PairCoef<float>> coef32((size_t)nt * nt);
-    for (int a = 0; a < nt; ++a)
-        for (int b = 0; b < nt; ++b) {
-            PairCoef<double> k{};
-            const double ef = std::sqrt(p->eps_fg[a] * p->eps_fg[b]);
-            const double sf = mix_sigma(c->mix, p->sig_fg[a], p->sig_fg[b]);
-            const double sf6 = sf * sf * sf * sf * sf * sf;
-            k.fg_c12 = 48.0 * ef * sf6 * sf6;
-            k.fg_c6 = 24.0 * ef * sf6;
-            k.fg_e12 = 4.0 * ef * sf6 * sf6;
-            k.fg_e6 = 4.0 * ef * sf6;
-            switch_off(lj3(ef, sf, c->rsi), Ds, k.fg_g);
-            k.fg_shift = poly_at(k.fg_g, Ds);
-            if (c->hybrid[a] && c->hybrid[b]) {           // Eq. 14
-                const double ec = std::sqrt(p->eps_cg[a] * p->eps_cg[b]);
-                const double sc = mix_sigma(c->mix, p->sig_cg[a], p->sig_cg[b]);
-                const double sc6 = sc * sc * sc * sc * sc * sc;
-                k.cg_c12 = 48.0 * ec * sc6 * sc6;
-                k.cg_c6 = 24.0 * ec * sc6;
-                k.cg_e12 = 4.0 * ec * sc6 * sc6;
-                k.cg_e6 = 4.0 * ec * sc6;
-                double g[5];
-                switch_on(lj3(ec, sc, c->rso), Ds, g);
-                k.sp_g0 = g[0];
-                k.sp_g3 = g[3];
-                k.sp_g4 = g[4];
-                switch_off(lj3(ec, sc, c->rci), Dc, k.cm_g);
-                k.cm_shift = poly_at(k.cm_g, Dc);         // Gamma_c- (Eq. 19)
+    {
+        std::vector<double> ef((size_t)nt * nt), sf(ef.size()), ec(ef.size()), sc(ef.size());
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b) {
+                const size_t q = (size_t)a * nt + b;
+                ef[q] = std::sqrt(p->eps_fg[a] * p->eps_fg[b]);
+                sf[q] = mix_sigma(c->mix, p->sig_fg[a], p->sig_fg[b]);
+                ec[q] = std::sqrt(p->eps_cg[a] * p->eps_cg[b]);
+                sc[q] = mix_sigma(c->mix, p->sig_cg[a], p->sig_cg[b]);
             }
-            c->coef64[(size_t)a * nt + b] = k;
-            const double* src = reinterpret_cast<const double*>(&k);
-            float* dst = reinterpret_cast<float*>(&coef32[(size_t)a * nt + b]);
-            for (size_t q = 0; q < sizeof(PairCoef<double>) / sizeof(double); ++q) dst[q] = (float)src[q];
-        }
+        build_tables(c, ef.data(), sf.data(), ec.data(), sc.data());
+    }
     c->cut64[0] = c->rsi; c->cut64[1] = c->rso; c->cut64[2] = c->rci; c->cut64[3] = c->rco;
     for (int k = 0; k < 4; ++k) c->cut64[4 + k] = c->cut64[k] * c->cut64[k];
 
     int rc;
     if ((rc = ensure(c->d_coef64, sizeof(PairCoef<double>) * c->coef64.size(), &c->alloc_generation))) return bail(rc);
-    if ((rc = ensure(c->d_coef32, sizeof(PairCoef<float>) * coef32.size(), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_coef32, sizeof(PairCoef<float>) * c->coef64.size(), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_coef_grad, sizeof(PairCoef<double>) * c->coef_grad.size(), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_hybrid, sizeof(int) * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_status, sizeof(Status), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_epoch, 256, &c->alloc_generation))) return bail(rc);
-    if (hipMemcpy(c->d_coef64.p, c->coef64.data(), sizeof(PairCoef<double>) * c->coef64.size(),
-                  hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_coef32.p, coef32.data(), sizeof(PairCoef<float>) * coef32.size(),
-                  hipMemcpyHostToDevice) != hipSuccess ||
+    if (upload_tables(c) != RELRES_OK ||
         hipMemcpy(c->d_hybrid.p, c->hybrid.data(), sizeof(int) * nt, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_status.p, 0, sizeof(Status)) != hipSuccess ||
         hipMemset(c->d_epoch.p, 0, 256) != hipSuccess)
@@ -879,6 +954,86 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     return RELRES_OK;
 }
 
+int relres_set_pair_params(relres_ctx* c, const double* eps_fg, const double* sig_fg,
+                           const double* eps_cg, const double* sig_cg)
+{
+    if (!c || !eps_fg || !sig_fg || !eps_cg || !sig_cg) return fail(RELRES_ERR_ARG, "NULL argument");
+    const int nt = c->ntypes;
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const size_t q = (size_t)a * nt + b;
+            if (!(std::isfinite(eps_fg[q]) && eps_fg[q] >= 0.0 && std::isfinite(sig_fg[q]) &&
+                  sig_fg[q] > 0.0))
+                return fail(RELRES_ERR_ARG, "bad FG pair parameters for types (%d, %d)", a, b);
+            if (c->hybrid[a] && c->hybrid[b] &&
+                !(std::isfinite(eps_cg[q]) && eps_cg[q] >= 0.0 && std::isfinite(sig_cg[q]) &&
+                  sig_cg[q] > 0.0))
+                return fail(RELRES_ERR_ARG, "bad CG pair parameters for types (%d, %d)", a, b);
+        }
+    // the tables may be in use by work still queued on any stream
+    HIP_TRY(hipDeviceSynchronize());
+    build_tables(c, eps_fg, sig_fg, eps_cg, sig_cg);
+    TRY(upload_tables(c));
+    return RELRES_OK;
+}
+
+int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
+                    const double* grad_energy, double* grad_pos, double* grad_pair, void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (c->check_pending) TRY(examine_status(c));
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
+    if (c->ntypes > kBackwardTypes)
+        return fail(RELRES_ERR_ARG, "relres_backward supports at most %d types (got %d)",
+                    kBackwardTypes, c->ntypes);
+    if (!grad_pair || (c->n > 0 && (!pos || !grad_pos)))
+        return fail(RELRES_ERR_ARG, "pos, grad_pos or grad_pair is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = c->ntypes;
+    const int nbins = 4 * nt * nt;
+    BackArgs b{};
+    ForceArgs& a = b.f;
+    const bool sites = c->n_sites > 0;
+    const int la = c->lanes_a ? c->lanes_a : c->auto_la;
+    const int lb = c->lanes_b ? c->lanes_b : c->auto_lb;
+    auto blocks = [](long long rows, int lanes) {
+        long long k = (rows * lanes + kForceBlock - 1) / kForceBlock;
+        return (int)((k + 7) / 8 * 8);
+    };
+    a.pos = pos;
+    for (int k = 0; k < 3; ++k) {
+        a.box[k] = c->box[k];
+        a.inv_box[k] = 1.0 / c->box[k];
+    }
+    a.n_arow = c->n;
+    a.a_rec = c->d_a_rec.as<int4>();
+    a.a_list = c->ga.list.as<int>();
+    a.a_cap = c->ga.cap;
+    a.n_srow = sites ? c->n_sites : 0;
+    if (sites) {
+        a.s_rec = c->d_s_rec.as<int4>();
+        a.s_list = c->gs.list.as<int>();
+        a.s_cap = c->gs.cap;
+    }
+    a.coef64 = c->d_coef64.p;
+    a.ntypes = nt;
+    a.blocks_a = c->n > 0 ? blocks(c->n, la) : 0;
+    a.blocks_b = (c->n > 0 && sites) ? blocks(c->n_sites, lb) : 0;
+    a.lanes_a = la;
+    a.lanes_b = lb;
+    a.log_lanes_a = log2i(la);
+    a.log_lanes_b = log2i(lb);
+    b.gforce = grad_forces;
+    b.genergy = grad_energy;
+    b.gpos = grad_pos;
+    b.cgrad = c->d_coef_grad.as<PairCoef<double>>();
+    const int waves = (a.blocks_a + a.blocks_b) * (kForceBlock / 64);
+    TRY(ensure(c->d_bpartial, sizeof(double) * (size_t)std::max(1, waves) * nbins, &c->alloc_generation));
+    b.partial = c->d_bpartial.as<double>();
+    HIP_TRY(launch_backward(b, c->cut64, waves, grad_pair, s));
+    return RELRES_OK;
+}
+
 int relres_list_stats(relres_ctx* c, relres_stats* out)
 {
     if (!c || !out) return fail(RELRES_ERR_ARG, "NULL argument");
@@ -971,6 +1126,7 @@ void relres_destroy(relres_ctx* c)
 {
     if (!c) return;
     (void)hipDeviceSynchronize();
+    for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial}) release(*b);
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
                     &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials,

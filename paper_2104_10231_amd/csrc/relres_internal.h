@@ -137,6 +137,19 @@ hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int member
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
                          bool ew, hipStream_t s);
 hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
+// Backward (adjoint) pass: ForceArgs (positions, lists, FP64 table) plus
+struct BackArgs {
+    ForceArgs f;
+    const double* gforce;                 // dJ/dF, N x 3, or NULL
+    const double* genergy;                // dJ/dE (device scalar) or NULL
+    double* gpos;                         // out: dJ/dx, N x 3
+    const PairCoef<double>* cgrad;        // [4][ntypes^2] derivative records
+    double* partial;                      // per wave: [ntypes^2][4] parameter sums
+};
+constexpr int kBackwardTypes = 8;
+// waves = wavefronts of the launch; grad_pair receives [4][ntypes][ntypes]
+hipError_t launch_backward(const BackArgs& b, const double* cut64, int waves, double* grad_pair,
+                           hipStream_t s);
 hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_outputs(double* energy, double* virial, hipStream_t s);
 

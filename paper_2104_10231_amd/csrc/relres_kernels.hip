@@ -1345,6 +1345,246 @@ hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStre
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// backward (adjoint) pass
+// ---------------------------------------------------------------------------
+// J = e_bar E + sum_i g_i . F_i.  Per ordered pair (i, j) of a list row, with
+// d = x_i - x_j, fpair = -u~'(r)/r (F_i gets fpair d) and
+// hc = (d fpair/dr)/r:
+//   dJ/dx_i += -e_bar fpair d + fpair (g_i - g_j) + hc ((g_i - g_j) . d) d
+//   dJ/dP_{t_i t_j} += e_bar u~_P / 2 + (g_i . d) fpair_P
+// where u~_P, fpair_P are the pair terms evaluated with the derivative record
+// of parameter P (the terms are linear in the record's coefficients).  Each
+// unordered pair appears in both rows, hence the half energy weight.
+
+// FG part with the Hessian factor, FP64.
+__device__ __forceinline__ void fg_terms2(const PairCoef<double>& c, const Cutoffs<double>& cut,
+                                          double r2, double& fpair, double& en, double& hc)
+{
+    using M = MathF64<2>;
+    if (r2 < cut.rsi2) {
+        const double r2i = M::recip(r2);
+        const double r6i = r2i * r2i * r2i;
+        fpair = r6i * (c.fg_c12 * r6i - c.fg_c6) * r2i;
+        en = r6i * (c.fg_e12 * r6i - c.fg_e6) - c.fg_shift;
+        hc = r2i * r2i * r6i * (8.0 * c.fg_c6 - 14.0 * c.fg_c12 * r6i);
+    } else {
+        double r, ir;
+        M::root(r2, r, ir);
+        const double d = r - cut.rsi;
+        const double dp = c.fg_g[1] + d * (2.0 * c.fg_g[2] + d * (3.0 * c.fg_g[3] + d * (4.0 * c.fg_g[4])));
+        const double dpp = 2.0 * c.fg_g[2] + d * (6.0 * c.fg_g[3] + d * (12.0 * c.fg_g[4]));
+        fpair = -dp * ir;
+        en = c.fg_g[0] + d * (c.fg_g[1] + d * (c.fg_g[2] + d * (c.fg_g[3] + d * c.fg_g[4]))) - c.fg_shift;
+        hc = (-dpp - fpair) * ir * ir;
+    }
+}
+
+// CG part with the Hessian factor, FP64.
+__device__ __forceinline__ void cg_terms2(const PairCoef<double>& c, const Cutoffs<double>& cut,
+                                          double r2, double& fpair, double& en, double& hc)
+{
+    using M = MathF64<2>;
+    if (r2 < cut.rsi2) {
+        fpair = 0.0;
+        en = c.sp_g0 - c.cm_shift;
+        hc = 0.0;
+    } else if (r2 < cut.rso2) {
+        double r, ir;
+        M::root(r2, r, ir);
+        const double d = r - cut.rsi;
+        const double dp = d * d * (3.0 * c.sp_g3 + 4.0 * c.sp_g4 * d);
+        const double dpp = d * (6.0 * c.sp_g3 + 12.0 * c.sp_g4 * d);
+        fpair = -dp * ir;
+        en = c.sp_g0 + d * d * d * (c.sp_g3 + d * c.sp_g4) - c.cm_shift;
+        hc = (-dpp - fpair) * ir * ir;
+    } else if (r2 < cut.rci2) {
+        const double r2i = M::recip(r2);
+        const double r6i = r2i * r2i * r2i;
+        fpair = r6i * (c.cg_c12 * r6i - c.cg_c6) * r2i;
+        en = r6i * (c.cg_e12 * r6i - c.cg_e6) - c.cm_shift;
+        hc = r2i * r2i * r6i * (8.0 * c.cg_c6 - 14.0 * c.cg_c12 * r6i);
+    } else {
+        double r, ir;
+        M::root(r2, r, ir);
+        const double d = r - cut.rci;
+        const double dp = c.cm_g[1] + d * (2.0 * c.cm_g[2] + d * (3.0 * c.cm_g[3] + d * (4.0 * c.cm_g[4])));
+        const double dpp = 2.0 * c.cm_g[2] + d * (6.0 * c.cm_g[3] + d * (12.0 * c.cm_g[4]));
+        fpair = -dp * ir;
+        en = c.cm_g[0] + d * (c.cm_g[1] + d * (c.cm_g[2] + d * (c.cm_g[3] + d * c.cm_g[4]))) - c.cm_shift;
+        hc = (-dpp - fpair) * ir * ir;
+    }
+}
+
+// One list row of the backward pass (FG part when CG is false, CG part when
+// true); TM bounds the number of types.
+template <bool CG, int TM>
+__device__ __forceinline__ void back_row(const BackArgs& b, const Cutoffs<double>& cut, int ti,
+                                         double xi, double yi, double zi, double gix, double giy,
+                                         double giz, double ebar, const int* __restrict__ lst,
+                                         int cnt, int sub, int G, double gp[3], double acc[TM][4])
+{
+    const ForceArgs& a = b.f;
+    const int nt = a.ntypes;
+    const int np = nt * nt;
+    const PairCoef<double>* coef = (const PairCoef<double>*)a.coef64;
+    const double rmax2 = CG ? cut.rco2 : cut.rso2;
+    constexpr int P0 = CG ? 2 : 0;
+    for (int k = sub; k < cnt; k += G) {
+        const uint32_t e = (uint32_t)lst[k];
+        const int uj = (int)(e & kIdxMask), tj = (int)(e >> kIdxBits);
+        double dx = xi - a.pos[3 * uj];
+        double dy = yi - a.pos[3 * uj + 1];
+        double dz = zi - a.pos[3 * uj + 2];
+        dx -= a.box[0] * rint(dx * a.inv_box[0]);
+        dy -= a.box[1] * rint(dy * a.inv_box[1]);
+        dz -= a.box[2] * rint(dz * a.inv_box[2]);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 < rmax2)) continue;
+        const int pi = ti * nt + tj;
+        double fp, en, hc, fe, ee, fs, es;
+        if constexpr (CG) {
+            cg_terms2(coef[pi], cut, r2, fp, en, hc);
+            cg_term<MathF64<2>>(b.cgrad[2 * np + pi], cut, r2, fe, ee);
+            cg_term<MathF64<2>>(b.cgrad[3 * np + pi], cut, r2, fs, es);
+        } else {
+            fg_terms2(coef[pi], cut, r2, fp, en, hc);
+            fg_term<MathF64<2>>(b.cgrad[0 * np + pi], cut, r2, fe, ee);
+            fg_term<MathF64<2>>(b.cgrad[1 * np + pi], cut, r2, fs, es);
+        }
+        double wx = gix, wy = giy, wz = giz;
+        if (b.gforce) {
+            wx -= b.gforce[3 * uj];
+            wy -= b.gforce[3 * uj + 1];
+            wz -= b.gforce[3 * uj + 2];
+        }
+        const double dw = dx * wx + dy * wy + dz * wz;
+        gp[0] += -ebar * fp * dx + fp * wx + hc * dw * dx;
+        gp[1] += -ebar * fp * dy + fp * wy + hc * dw * dy;
+        gp[2] += -ebar * fp * dz + fp * wz + hc * dw * dz;
+        const double gd = gix * dx + giy * dy + giz * dz;
+        const double ve = 0.5 * ebar * ee + gd * fe;
+        const double vs = 0.5 * ebar * es + gd * fs;
+#pragma unroll
+        for (int q = 0; q < TM; ++q)
+            if (q == tj) {
+                acc[q][P0] += ve;
+                acc[q][P0 + 1] += vs;
+            }
+    }
+}
+
+template <int TM>
+__global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b, Cutoffs<double> cut)
+{
+    const ForceArgs& a = b.f;
+    const bool rb = (int)blockIdx.x >= a.blocks_a;
+    const int lb = rb ? (int)blockIdx.x - a.blocks_a : (int)blockIdx.x;
+    const int nb = rb ? a.blocks_b : a.blocks_a;
+    const int per = nb >> 3;
+    const int logical = (lb & 7) * per + (lb >> 3);
+    const int lg = rb ? a.log_lanes_b : a.log_lanes_a;
+    const int G = 1 << lg;
+    const int row = logical * (kForceBlock >> lg) + ((int)threadIdx.x >> lg);
+    const int sub = (int)threadIdx.x & (G - 1);
+
+    int4 rec = make_int4(-1, 0, 0, 1);
+    int cnt_a = 0;
+    if (!rb) {
+        if (row < a.n_arow) rec = a.a_rec[row];
+    } else if (row < a.n_srow) {
+        rec = a.s_rec[row];
+        cnt_a = a.a_rec[rec.w].z;
+    }
+    const bool own = rb ? rec.x >= 0 : (rec.x >= 0 && rec.w == 0);
+    const double ebar = b.genergy ? b.genergy[0] : 0.0;
+    double acc[TM][4];
+#pragma unroll
+    for (int q = 0; q < TM; ++q)
+#pragma unroll
+        for (int P = 0; P < 4; ++P) acc[q][P] = 0.0;
+    double gp[3] = {0.0, 0.0, 0.0};
+    const int ti = rec.y;
+    if (own) {
+        const int ui = rec.x;
+        const double xi = a.pos[3 * ui], yi = a.pos[3 * ui + 1], zi = a.pos[3 * ui + 2];
+        double gix = 0.0, giy = 0.0, giz = 0.0;
+        if (b.gforce) {
+            gix = b.gforce[3 * ui];
+            giy = b.gforce[3 * ui + 1];
+            giz = b.gforce[3 * ui + 2];
+        }
+        const int ar = rb ? rec.w : row;
+        const int ca = rb ? cnt_a : rec.z;
+        back_row<false, TM>(b, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
+                            a.a_list + (size_t)ar * a.a_cap, ca, sub, G, gp, acc);
+        if (rb)
+            back_row<true, TM>(b, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
+                               a.s_list + (size_t)row * a.s_cap, rec.z, sub, G, gp, acc);
+    }
+    for (int c = 0; c < 3; ++c) gp[c] = group_sum(gp[c], G);
+    if (own && sub == 0) {
+        b.gpos[3 * rec.x] = gp[0];
+        b.gpos[3 * rec.x + 1] = gp[1];
+        b.gpos[3 * rec.x + 2] = gp[2];
+    }
+    // per-wave sums per (row type, entry type, parameter), fixed order
+    const int nt = a.ntypes;
+    const int nbins = 4 * nt * nt;
+    const int wave = (int)blockIdx.x * (kForceBlock / 64) + (int)(threadIdx.x >> 6);
+    double* out = b.partial + (size_t)wave * nbins;
+    for (int t = 0; t < nt; ++t)
+#pragma unroll
+        for (int q = 0; q < TM; ++q) {
+            if (q >= nt) break;
+#pragma unroll
+            for (int P = 0; P < 4; ++P) {
+                const double v = wave_sum((own && ti == t) ? acc[q][P] : 0.0);
+                if ((threadIdx.x & 63) == 63) out[(t * nt + q) * 4 + P] = v;
+            }
+        }
+}
+
+// dJ/dP[a][b] = sum over waves of the partial sums, in wave order; one block
+// per bin.
+__global__ __launch_bounds__(256) void k_reduce_bins(const double* __restrict__ partial, int waves,
+                                                     int nt, double* __restrict__ grad_pair)
+{
+    __shared__ double red[4];
+    const int bin = (int)blockIdx.x;             // (t * nt + q) * 4 + P
+    const int nbins = 4 * nt * nt;
+    double s = 0.0;
+    for (int w = (int)threadIdx.x; w < waves; w += 256) s += partial[(size_t)w * nbins + bin];
+    const double v = wave_sum(s);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int P = bin & 3, tq = bin >> 2;
+        grad_pair[(size_t)P * nt * nt + tq] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+hipError_t launch_backward(const BackArgs& b, const double* cut64, int waves, double* grad_pair,
+                           hipStream_t s)
+{
+    const int nt = b.f.ntypes;
+    const int blocks = b.f.blocks_a + b.f.blocks_b;
+    if (blocks > 0) {
+        const dim3 grid(blocks), block(kForceBlock);
+        if (nt <= 2)
+            hipLaunchKernelGGL(k_backward<2>, grid, block, 0, s, b, cut_as<double>(cut64));
+        else if (nt <= 4)
+            hipLaunchKernelGGL(k_backward<4>, grid, block, 0, s, b, cut_as<double>(cut64));
+        else
+            hipLaunchKernelGGL(k_backward<8>, grid, block, 0, s, b, cut_as<double>(cut64));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_reduce_bins, dim3(4 * nt * nt), dim3(256), 0, s, b.partial,
+                       blocks > 0 ? waves : 0, nt, grad_pair);
+    return hipGetLastError();
+}
+
 __global__ void k_clear_words(unsigned long long* p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;

@@ -64,6 +64,11 @@ SIGNATURES = {
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "relres_set_pair_params": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p,
+                                              _c_double_p, _c_double_p]),
+    "relres_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "relres_list_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "relres_generation": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]),
     "relres_get_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -151,6 +156,9 @@ class RelRes:
         _check(self._lib.relres_create(ctypes.byref(p), ctypes.byref(ctx)), "relres_create")
         self._ctx = ctx
         self.precision = int(precision)
+        self.ntypes = nt
+        self.mix = int(mix)
+        self.hybrid = [float(x) > 0.0 for x in self._arrays[2]]
         self.n = 0
         self.device = torch.device("cuda", torch.cuda.current_device())
 
@@ -212,6 +220,42 @@ class RelRes:
                                        virial.data_ptr() if virial is not None else None,
                                        _stream(stream)), "relres_forces")
         return out, energy, virial
+
+    # -- parameters and gradients -------------------------------------------------
+    def set_pair_params(self, eps_fg, sig_fg, eps_cg, sig_cg):
+        """Pair tables (ntypes x ntypes each, host arrays or CPU tensors)."""
+        arrs = []
+        for t in (eps_fg, sig_fg, eps_cg, sig_cg):
+            if isinstance(t, torch.Tensor):
+                t = t.detach().cpu().numpy()
+            a = _f64(t)
+            if a.shape != (self.ntypes, self.ntypes):
+                raise ValueError(f"pair table shape {a.shape}, expected {(self.ntypes,) * 2}")
+            arrs.append(a)
+        _check(self._lib.relres_set_pair_params(self._ctx,
+                                                *[a.ctypes.data_as(_c_double_p) for a in arrs]),
+               "relres_set_pair_params")
+
+    def backward(self, pos: torch.Tensor, grad_forces: Optional[torch.Tensor] = None,
+                 grad_energy: Optional[torch.Tensor] = None, stream=None):
+        """dJ/dx (N, 3) and dJ/dP (4, ntypes, ntypes) for J = e_bar E + sum g.F."""
+        pos = self._pos(pos)
+        gf = None
+        if grad_forces is not None:
+            gf = grad_forces.to(dtype=torch.float64).contiguous()
+            if tuple(gf.shape) != (self.n, 3) or gf.device != pos.device:
+                raise ValueError("grad_forces must be an (N, 3) tensor on the positions' device")
+        ge = None
+        if grad_energy is not None:
+            ge = grad_energy.to(device=pos.device, dtype=torch.float64).reshape(1).contiguous()
+        gpos = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device)
+        gpair = torch.empty((4, self.ntypes, self.ntypes), dtype=torch.float64, device=pos.device)
+        _check(self._lib.relres_backward(self._ctx, pos.data_ptr() if self.n else None,
+                                         gf.data_ptr() if gf is not None and self.n else None,
+                                         ge.data_ptr() if ge is not None else None,
+                                         gpos.data_ptr() if self.n else None, gpair.data_ptr(),
+                                         _stream(stream)), "relres_backward")
+        return gpos, gpair
 
     # -- inspection ------------------------------------------------------------
     def set_launch(self, lanes_atom: int = 0, lanes_site: int = 0):
