@@ -186,6 +186,89 @@ def cpu_baseline(sys_, budget_s):
                        f"{sys_.n}-atom workload ({el:.1f} s)")
 
 
+def grad_bench(args):
+    """Differentiation workload: the 20480-atom liquid over perturbed frames
+    (0.05 A Gaussian noise); per frame a list build, the forward call and the
+    gradients of E and of the force-matching loss sum |F - F_ref|^2 with
+    respect to positions and per-type eps/sigma (FG and CG), F_ref from the
+    oracle at perturbed parameters.  Forward forces FP32, backward FP64."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads as w
+    from paper_2104_10231_amd.autograd import energy_forces
+    s = w.neopentane_liquid(args.seed)
+    frames = w.perturbed_frames(s, n_frames=args.frames, sigma=0.05, seed=args.seed + 1)
+    ref = dict(eps_fg=s.eps_fg * 1.03, sig_fg=s.sig_fg * 0.99, eps_cg=s.eps_cg * 1.05,
+               sig_cg=s.sig_cg * 1.01)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    frefs = [torch.from_numpy(oracle.compute(f.replace(**ref), nthreads=threads)[0]).cuda()
+             for f in frames]
+    log(f"[bench] grad: {len(frames)} frames, F_ref from the oracle in {time.perf_counter() - t0:.1f} s")
+    pos = [torch.from_numpy(f.pos).cuda() for f in frames]
+    rr = make(s, 32, args.pair_math)
+    theta = [torch.tensor(np.asarray(getattr(s, k), np.float64), requires_grad=True)
+             for k in ("eps_fg", "sig_fg", "eps_cg", "sig_cg")]
+
+    def frame(k):
+        p = pos[k].clone().requires_grad_(True)
+        rr.build_lists(p.detach(), s.box)
+        F, E = energy_forces(rr, p, *theta)
+        L = ((F.double() - frefs[k]) ** 2).sum()
+        gL = torch.autograd.grad(L, theta + [p], retain_graph=True)
+        gE = torch.autograd.grad(E, theta + [p])
+        return gL, gE
+
+    for k in range(min(2, len(frames))):
+        frame(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(len(frames)):
+        frame(k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # device time of one adjoint launch (kernel + bin reduction), back to back
+    rr.build_lists(pos[0], s.box)
+    g = torch.randn((s.n, 3), dtype=torch.float64, device="cuda")
+    e1 = torch.ones(1, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        rr.backward(pos[0], g, e1)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50
+    ev0.record()
+    for _ in range(reps):
+        rr.backward(pos[0], g, e1)
+    ev1.record()
+    torch.cuda.synchronize()
+    back_us = ev0.elapsed_time(ev1) * 1e3 / reps
+    st = rr.stats()
+    rr.close()
+    entries = st["atom_entries"] + st["site_entries"]
+    # algorithmic bytes of one adjoint launch: positions and dJ/dF read once,
+    # dJ/dx written once, list entries and row counts read once
+    abytes = s.n * (24 + 24 + 24) + 4 * entries + 4 * (s.n + st["n_sites"])
+    achieved = abytes / (back_us * 1e-6) / 1e9
+    out = {
+        "metric": "RelRes forward+backward frames/s (gradients of E and of a force-matching loss "
+                  "w.r.t. positions and per-type eps/sigma), 1 MI355X",
+        "value": len(frames) / dt, "unit": "frames/s", "n_gpus": 1, "steps": len(frames),
+        "warmup": 2, "ms_per_step": dt * 1e3 / len(frames), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 forward, f64 backward",
+        "data": "synthetic",
+        "config": {"workload": "neopentane_20480 perturbed frames (0.05 A)", "atoms": s.n,
+                   "frames": len(frames), "parallelism": "single GPU",
+                   "per_frame": "list build + forward + 2 adjoint launches (E, force matching)"},
+        "atom_steps_per_s": s.n * len(frames) / dt,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_backward",
+                     "kernel_us": back_us, "algorithmic_bytes_per_launch": abytes},
+    }
+    log(f"[bench] grad: {dt * 1e3 / len(frames):.3f} ms/frame, adjoint launch {back_us:.2f} us")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +285,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every force call eagerly instead of replaying a HIP graph")
+    ap.add_argument("--grad", action="store_true",
+                    help="run the differentiation workload instead (forward + backward over "
+                         "perturbed frames) and print its line")
+    ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="finish with 5 device-to-device copies of this many MiB (a kernel "
                          "of known traffic for scaling HBM byte counters)")
@@ -219,6 +306,9 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.grad:
+        grad_bench(args)
+        return
     s = w.WORKLOADS[args.workload](args.seed)
     precision = s.precision
     pos = torch.from_numpy(s.pos).cuda()

@@ -54,8 +54,12 @@ class _RelResFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rr: RelRes, pos, ef, sf, ec, sc):
         tables = tuple(t.detach().to("cpu", torch.float64).clone() for t in (ef, sf, ec, sc))
-        rr.set_pair_params(*tables)
-        rr._installed_tables = tables
+        cur = getattr(rr, "_installed_tables", None)
+        if cur is None or not all(torch.equal(a, b) for a, b in zip(cur, tables)):
+            rr.set_pair_params(*tables)     # waits for the device: only when changed
+            rr._installed_tables = tables
+        else:
+            tables = cur
         F, E, _ = rr.forces(pos, want_virial=False)
         ctx.rr = rr
         ctx.tables = tables
