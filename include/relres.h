@@ -122,10 +122,20 @@ int relres_create(const relres_params *params, relres_ctx **out);
 int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const int *mol,
                         int exclude_same_mol, const int *excl_offsets, const int *excl_idx);
 
+/* Several independent systems (replicas) in one context: atoms
+ * [atom_offsets[s], atom_offsets[s+1]) form system s (atom_offsets[0] = 0,
+ * atom_offsets[nsys] = n_atoms, non-decreasing; host array, copied).  Each
+ * system has its own periodic box and cell grids; pairs never cross
+ * systems.  Every build, force and backward call then covers all systems in
+ * one launch per step: boxes are nsys x 3, energies nsys x 3 and virials
+ * nsys x 6.  relres_set_topology resets to one system.  Lists must be built
+ * again afterwards.                                                         */
+int relres_set_systems(relres_ctx *ctx, int nsys, const int *atom_offsets);
+
 /* Build both neighbour lists for the FP64 device positions pos (N x 3, any
- * periodic image) in the box {Lx, Ly, Lz} (host array).  Every L_k must
- * exceed twice the largest list radius in use (r_c+ + skin when hybrid atoms
- * exist, else r_s+ + skin).  Membership is decided in FP64 exactly as
+ * periodic image) in the box {Lx, Ly, Lz} (host array; nsys x 3 with
+ * several systems).  Every L_k must exceed twice the largest list radius in
+ * use (r_c+ + skin when the system has hybrid atoms, else r_s+ + skin).  Membership is decided in FP64 exactly as
  *   w = x - L floor(x/L), fixed into [0, L);
  *   d = w_j - w_i; d -= L if d > L/2; d += L if d < -L/2;
  *   r2 = (dx dx + dy dy) + dz dz;   member iff r2 < (r_+ + skin)^2
@@ -143,6 +153,12 @@ int relres_build_lists(relres_ctx *ctx, const double *pos, const double box[3], 
  * then report its non-finite-position error).                              */
 int relres_build_lists_async(relres_ctx *ctx, const double *pos, const double box[3],
                              void *stream);
+/* A build enqueued on a stream that is being captured into a HIP graph runs
+ * at every replay of the graph (status copy included); relres_check_lists
+ * then examines the status of the latest replay, so synchronise the stream
+ * after the replay first.  A RELRES_ERR_LIST_RETRY there grows the rows,
+ * which changes the buffer generation (relres_generation): capture again.
+ * Timing events are not recorded during capture.                           */
 
 /* Waits for the status of the last build and examines it: RELRES_OK when the
  * lists are complete, RELRES_ERR_NONFINITE for a NaN/inf position, or
@@ -154,7 +170,8 @@ int relres_check_lists(relres_ctx *ctx);
 /* Forces, energy and virial for device positions pos (N x 3 FP64) using the
  * lists of the last build (and its box).  forces: device N x 3, double* when
  * precision == 64, float* when 32; overwritten.  energy: device double[3] =
- * {total, FG part, CG part} or NULL; virial: device double[6] or NULL.
+ * {total, FG part, CG part} or NULL; virial: device double[6] or NULL (per
+ * system, nsys x 3 and nsys x 6, with several systems).
  * Energy and virial are accumulated in FP64 and reduced in a fixed order, so
  * repeated calls are bitwise identical.  Asynchronous on `stream`.          */
 int relres_forces(relres_ctx *ctx, const double *pos, void *forces, double *energy,
@@ -174,7 +191,8 @@ int relres_set_pair_params(relres_ctx *ctx, const double *eps_fg, const double *
  * the total energy (Eq. 3) and F the forces, at the device positions pos
  * (N x 3 FP64) with the lists of the last build:
  *   grad_forces  device N x 3 FP64: g = dJ/dF (NULL: zero);
- *   grad_energy  device double[1]: e_bar = dJ/dE (NULL: zero);
+ *   grad_energy  device double[nsys]: e_bar = dJ/dE of each system's
+ *                total energy (NULL: zero);
  *   grad_pos     device N x 3 FP64, overwritten with dJ/dx;
  *   grad_pair    device double[4 * ntypes * ntypes], overwritten with dJ/dP
  *                for P = eps_FG, sigma_FG, eps_CG, sigma_CG (that order),

@@ -65,7 +65,7 @@ class _RelResFunction(torch.autograd.Function):
         ctx.tables = tables
         ctx.devices = tuple(t.device for t in (ef, sf, ec, sc))
         ctx.save_for_backward(pos)
-        return F, E[0]
+        return F, (E[0] if rr.nsys == 1 else E[:, 0])
 
     @staticmethod
     def backward(ctx, grad_forces, grad_energy):
@@ -80,8 +80,9 @@ class _RelResFunction(torch.autograd.Function):
 
 
 def energy_forces(rr: RelRes, pos: torch.Tensor, eps_fg, sig_fg, eps_cg, sig_cg):
-    """Forces (N, 3) and total energy, differentiable with respect to ``pos``
-    and the per-type parameters (1-D tensors of length ntypes).  Lists must
+    """Forces (N, 3) and total energy (one per system when the context holds
+    several), differentiable with respect to ``pos`` and the per-type
+    parameters (1-D tensors of length ntypes).  Lists must
     have been built for ``pos`` (``rr.build_lists``)."""
     tables = mix_pair_tables(eps_fg, sig_fg, eps_cg, sig_cg, rr.mix, rr.hybrid)
     return _RelResFunction.apply(rr, pos, *tables)

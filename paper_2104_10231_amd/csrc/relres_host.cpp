@@ -192,14 +192,19 @@ void release(DBuf& b)
     b.bytes = 0;
 }
 
+// All cell grids of one kind (atom or site), one per system, concatenated.
 struct GridHost {
-    int n[3] = {0, 0, 0};
-    int ncell = 0;
-    int cap = 0;
-    int members = 0;
     double rl = 0.0;
-    DBuf rank_of_lin, lin_of_rank, nbr, count, start, user_unsorted, user, pos, meta, row_cell, list,
-        nrow;
+    int cap = 0;
+    int nsys = 0;
+    int ncell = 0;                    // cells of all grids
+    int members = 0;                  // members of all grids
+    int waves = 0;                    // list-kernel waves (kRowsPerWave rows each)
+    int n[3] = {0, 0, 0};             // cells per axis of system 0 (statistics)
+    std::vector<int> sys_n;           // [nsys][3] cells per axis
+    std::vector<GeomDev> geom;        // per system, as last uploaded
+    DBuf geom_dev, cell_sys, rank_of_lin, lin_of_rank, nbr, count, start, user_unsorted, user, pos,
+        meta, row_cell, list, nrow;
     GridDev dev{};
 };
 
@@ -224,6 +229,14 @@ struct relres_ctx {
 
     bool topo_set = false;
     int n = 0, n_sites = 0;
+    int nsys = 1;                     // systems (atoms grouped by system)
+    std::vector<int> sys_off;         // [nsys + 1] first atom of each system
+    std::vector<int> atoms_sys, sites_sys;   // atoms and hybrid atoms per system
+    std::vector<int> h_types;         // types of the atoms (host copy)
+    DBuf d_sys;                       // system of each atom (nsys > 1)
+    std::vector<double> boxes;        // [nsys][3] of the last build
+    std::vector<double> boxes_dev;    // [nsys][6] as uploaded
+    DBuf d_boxes, d_row_ew;
     int same_mol = 0;
     bool has_excl = false;
     int max_excl = 0;
@@ -241,6 +254,7 @@ struct relres_ctx {
     bool lanes_stale = true;          // automatic lane counts need a refresh
     bool built = false;
     bool check_pending = false;       // a build's status has not been examined yet
+    bool status_in_graph = false;     // ... and it was captured into a graph: no event
     hipEvent_t ev_status = nullptr;   // recorded after a build's status copy
     hipEvent_t ev_upload = nullptr;   // recorded after the descriptor upload
     bool upload_pending = false;
@@ -335,108 +349,151 @@ int log2i(int v)
     return l;
 }
 
-int setup_grid(GridHost& g, double rl, const double box[3], int members, long long* gen)
+int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int* members_sys,
+               long long* gen)
 {
-    int n[3];
-    long long total = 1;
-    for (int k = 0; k < 3; ++k) {
-        // a cell edge is at least the list radius (with a margin far above
-        // rounding), so every pair within rl lies in neighbouring cells
-        n[k] = (int)std::floor(box[k] / (rl * (1.0 + 1e-10)));
-        n[k] = std::max(1, std::min(n[k], 1023));
-        total *= n[k];
-    }
-    while (total > (1ll << 22)) {   // keep the cell tables modest in sparse huge boxes
-        total = 1;
+    // cells per axis of every system: a cell edge is at least the list radius
+    // (with a margin far above rounding), so every pair within rl lies in
+    // neighbouring cells
+    std::vector<int> nn((size_t)nsys * 3);
+    for (int sy = 0; sy < nsys; ++sy) {
+        int* n = &nn[(size_t)sy * 3];
+        long long total = 1;
         for (int k = 0; k < 3; ++k) {
-            n[k] = std::max(1, n[k] / 2);
+            n[k] = (int)std::floor(boxes[3 * sy + k] / (rl * (1.0 + 1e-10)));
+            n[k] = std::max(1, std::min(n[k], 1023));
             total *= n[k];
         }
+        while (total > (1ll << 22)) {   // keep the cell tables modest in sparse huge boxes
+            total = 1;
+            for (int k = 0; k < 3; ++k) {
+                n[k] = std::max(1, n[k] / 2);
+                total *= n[k];
+            }
+        }
     }
-    const bool same = n[0] == g.n[0] && n[1] == g.n[1] && n[2] == g.n[2] && g.rank_of_lin.p;
+    std::vector<int> cell_base(nsys + 1, 0);
+    for (int sy = 0; sy < nsys; ++sy) {
+        const long long cells = (long long)nn[3 * sy] * nn[3 * sy + 1] * nn[3 * sy + 2];
+        if (cell_base[sy] + cells > (1ll << 30)) return fail(RELRES_ERR_ARG, "too many cells");
+        cell_base[sy + 1] = cell_base[sy] + (int)cells;
+    }
+    const bool same = g.nsys == nsys && g.sys_n == nn && g.rank_of_lin.p;
     g.rl = rl;
-    g.members = members;
     if (!same) {
-        g.n[0] = n[0];
-        g.n[1] = n[1];
-        g.n[2] = n[2];
-        g.ncell = (int)total;
-        std::vector<std::pair<uint32_t, int>> code(g.ncell);
-        for (int x = 0; x < n[0]; ++x)
-            for (int y = 0; y < n[1]; ++y)
-                for (int z = 0; z < n[2]; ++z) {
-                    const int lin = (x * n[1] + y) * n[2] + z;
-                    code[lin] = {spread3(x) << 2 | spread3(y) << 1 | spread3(z), lin};
+        // tables may be read by work still queued on any stream
+        HIP_TRY(hipDeviceSynchronize());
+        const int total = cell_base[nsys];
+        std::vector<int> rank_of_lin(total), lin_of_rank(total), cell_sys(total);
+        std::vector<int> nbr((size_t)total * 27, -1);
+        for (int sy = 0; sy < nsys; ++sy) {
+            const int* n = &nn[(size_t)sy * 3];
+            const int cb = cell_base[sy];
+            const int nc = cell_base[sy + 1] - cb;
+            std::vector<std::pair<uint32_t, int>> code(nc);
+            for (int x = 0; x < n[0]; ++x)
+                for (int y = 0; y < n[1]; ++y)
+                    for (int z = 0; z < n[2]; ++z) {
+                        const int lin = (x * n[1] + y) * n[2] + z;
+                        code[lin] = {spread3(x) << 2 | spread3(y) << 1 | spread3(z), lin};
+                    }
+            std::sort(code.begin(), code.end());
+            std::vector<int> rank(nc);
+            for (int r = 0; r < nc; ++r) {
+                rank[code[r].second] = r;
+                lin_of_rank[cb + r] = code[r].second;
+                cell_sys[cb + r] = sy;
+            }
+            for (int lin = 0; lin < nc; ++lin) rank_of_lin[cb + lin] = cb + rank[lin];
+            // stencil ranks per cell; distinct offsets per axis (n = 1, 2 or >= 3)
+            int noff[3], off[3][3];
+            for (int k = 0; k < 3; ++k) {
+                if (n[k] >= 3) { noff[k] = 3; off[k][0] = -1; off[k][1] = 0; off[k][2] = 1; }
+                else if (n[k] == 2) { noff[k] = 2; off[k][0] = 0; off[k][1] = 1; off[k][2] = 0; }
+                else { noff[k] = 1; off[k][0] = off[k][1] = off[k][2] = 0; }
+            }
+            for (int r = 0; r < nc; ++r) {
+                const int lin = lin_of_rank[cb + r];
+                const int cz = lin % n[2], cy = (lin / n[2]) % n[1], cx = lin / (n[1] * n[2]);
+                for (int t = 0; t < 27; ++t) {
+                    const int ix = t / 9, iy = (t / 3) % 3, iz = t % 3;
+                    if (ix >= noff[0] || iy >= noff[1] || iz >= noff[2]) continue;
+                    const int nx = (cx + off[0][ix] + n[0]) % n[0];
+                    const int ny = (cy + off[1][iy] + n[1]) % n[1];
+                    const int nz = (cz + off[2][iz] + n[2]) % n[2];
+                    nbr[(size_t)(cb + r) * 27 + t] = cb + rank[(nx * n[1] + ny) * n[2] + nz];
                 }
-        std::sort(code.begin(), code.end());
-        std::vector<int> rank(g.ncell), lin_of(g.ncell);
-        for (int r = 0; r < g.ncell; ++r) {
-            rank[code[r].second] = r;
-            lin_of[r] = code[r].second;
-        }
-        // stencil ranks per cell; distinct offsets per axis (n = 1, 2 or >= 3)
-        int noff[3], off[3][3];
-        for (int k = 0; k < 3; ++k) {
-            if (n[k] >= 3) { noff[k] = 3; off[k][0] = -1; off[k][1] = 0; off[k][2] = 1; }
-            else if (n[k] == 2) { noff[k] = 2; off[k][0] = 0; off[k][1] = 1; off[k][2] = 0; }
-            else { noff[k] = 1; off[k][0] = off[k][1] = off[k][2] = 0; }
-        }
-        std::vector<int> nbr((size_t)g.ncell * 27, -1);
-        for (int r = 0; r < g.ncell; ++r) {
-            const int lin = lin_of[r];
-            const int cz = lin % n[2], cy = (lin / n[2]) % n[1], cx = lin / (n[1] * n[2]);
-            for (int t = 0; t < 27; ++t) {
-                const int ix = t / 9, iy = (t / 3) % 3, iz = t % 3;
-                if (ix >= noff[0] || iy >= noff[1] || iz >= noff[2]) continue;
-                const int nx = (cx + off[0][ix] + n[0]) % n[0];
-                const int ny = (cy + off[1][iy] + n[1]) % n[1];
-                const int nz = (cz + off[2][iz] + n[2]) % n[2];
-                nbr[(size_t)r * 27 + t] = rank[(nx * n[1] + ny) * n[2] + nz];
             }
         }
         TRY(ensure(g.nbr, sizeof(int) * nbr.size(), gen));
+        TRY(ensure(g.rank_of_lin, sizeof(int) * total, gen));
+        TRY(ensure(g.lin_of_rank, sizeof(int) * total, gen));
+        TRY(ensure(g.cell_sys, sizeof(int) * total, gen));
+        TRY(ensure(g.count, sizeof(int) * total, gen));
+        TRY(ensure(g.start, sizeof(int) * (total + 1), gen));
         HIP_TRY(hipMemcpy(g.nbr.p, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
-        TRY(ensure(g.rank_of_lin, sizeof(int) * g.ncell, gen));
-        TRY(ensure(g.lin_of_rank, sizeof(int) * g.ncell, gen));
-        TRY(ensure(g.count, sizeof(int) * g.ncell, gen));
-        TRY(ensure(g.start, sizeof(int) * (g.ncell + 1), gen));
-        HIP_TRY(hipMemcpy(g.rank_of_lin.p, rank.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(g.lin_of_rank.p, lin_of.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemset(g.count.p, 0, sizeof(int) * g.ncell));
+        HIP_TRY(hipMemcpy(g.rank_of_lin.p, rank_of_lin.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g.lin_of_rank.p, lin_of_rank.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g.cell_sys.p, cell_sys.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(g.count.p, 0, sizeof(int) * total));
+        g.nsys = nsys;
+        g.sys_n = nn;
+        g.ncell = total;
     }
-    TRY(ensure(g.user_unsorted, sizeof(int) * members, gen));
-    TRY(ensure(g.user, sizeof(int) * members, gen));
-    TRY(ensure(g.pos, sizeof(double4) * members, gen));
-    TRY(ensure(g.meta, sizeof(int2) * members, gen));
-    TRY(ensure(g.row_cell, sizeof(int) * members, gen));
-    TRY(ensure(g.nrow, sizeof(int) * members, gen));
+    // rows and list-kernel waves of every grid
+    std::vector<GeomDev> geom(nsys);
+    int rows = 0, waves = 0;
+    double densest = 0.0;
+    for (int sy = 0; sy < nsys; ++sy) {
+        GeomDev& d = geom[sy];
+        std::memset(&d, 0, sizeof d);
+        const double* box = boxes + 3 * sy;
+        for (int k = 0; k < 3; ++k) {
+            d.n[k] = nn[3 * sy + k];
+            d.inv_cell[k] = d.n[k] / box[k];
+            d.box[k] = box[k];
+            d.half[k] = 0.5 * box[k];
+        }
+        d.cell_base = cell_base[sy];
+        d.row_base = rows;
+        d.members = members_sys[sy];
+        d.wave_base = waves;
+        rows += members_sys[sy];
+        waves += (members_sys[sy] + kRowsPerWave - 1) / kRowsPerWave;
+        densest = std::max(densest, members_sys[sy] / (box[0] * box[1] * box[2]));
+    }
+    g.members = rows;
+    g.waves = waves;
+    for (int k = 0; k < 3; ++k) g.n[k] = nn[k];
+    if (geom.size() != g.geom.size() ||
+        std::memcmp(geom.data(), g.geom.data(), sizeof(GeomDev) * geom.size()) != 0) {
+        TRY(ensure(g.geom_dev, sizeof(GeomDev) * std::max(1, nsys), gen));
+        HIP_TRY(hipDeviceSynchronize());   // the old table may still be in use
+        HIP_TRY(hipMemcpy(g.geom_dev.p, geom.data(), sizeof(GeomDev) * nsys, hipMemcpyHostToDevice));
+        g.geom = geom;
+    }
+    TRY(ensure(g.user_unsorted, sizeof(int) * rows, gen));
+    TRY(ensure(g.user, sizeof(int) * rows, gen));
+    TRY(ensure(g.pos, sizeof(double4) * rows, gen));
+    TRY(ensure(g.meta, sizeof(int2) * rows, gen));
+    TRY(ensure(g.row_cell, sizeof(int) * rows, gen));
+    TRY(ensure(g.nrow, sizeof(int) * rows, gen));
     if (g.cap == 0) {
-        const double vol = box[0] * box[1] * box[2];
-        const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * members / vol;
+        const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * densest;
         g.cap = std::max(16, (int)std::ceil(expect * 1.5 + 16.0));
         g.cap = (g.cap + 7) & ~7;
     }
-    TRY(ensure(g.list, sizeof(int) * (size_t)members * g.cap, gen));
+    TRY(ensure(g.list, sizeof(int) * (size_t)rows * g.cap, gen));
 
     GridDev& d = g.dev;
-    for (int k = 0; k < 3; ++k) {
-        d.n[k] = g.n[k];
-        d.inv_cell[k] = g.n[k] / box[k];
-        if (g.n[k] >= 3) {
-            d.noff[k] = 3;
-            d.off[k][0] = -1; d.off[k][1] = 0; d.off[k][2] = 1;
-        } else if (g.n[k] == 2) {
-            d.noff[k] = 2;
-            d.off[k][0] = 0; d.off[k][1] = 1; d.off[k][2] = 0;
-        } else {
-            d.noff[k] = 1;
-            d.off[k][0] = 0; d.off[k][1] = 0; d.off[k][2] = 0;
-        }
-    }
+    d.nsys = nsys;
     d.ncell = g.ncell;
-    d.rl2 = rl * rl;
-    d.members = members;
+    d.members = rows;
     d.cap = g.cap;
+    d.waves = waves;
+    d.rl2 = rl * rl;
+    d.geom = g.geom_dev.as<GeomDev>();
+    d.cell_sys = g.cell_sys.as<int>();
     d.rank_of_lin = g.rank_of_lin.as<int>();
     d.lin_of_rank = g.lin_of_rank.as<int>();
     d.nbr = g.nbr.as<int>();
@@ -463,6 +520,7 @@ TopoDev topo_of(relres_ctx* c)
     t.same_mol = c->same_mol;
     t.n = c->n;
     t.max_excl = c->max_excl;
+    t.sys = c->nsys > 1 ? c->d_sys.as<int>() : nullptr;
     return t;
 }
 
@@ -525,25 +583,46 @@ bool lists_per_wave(const relres_ctx* c)
 // copy of the status word to pinned host memory and an event.  Nothing waits;
 // relres_forces may be enqueued behind it at once.  The lists are complete
 // unless examine_status() later reports an overflow.
-int enqueue_build(relres_ctx* c, const double* pos, const double box[3], hipStream_t s)
+int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream_t s)
 {
     if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
     if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
     if (!box) return fail(RELRES_ERR_ARG, "box is NULL");
     if (c->n > 0 && !pos) return fail(RELRES_ERR_ARG, "pos is NULL");
-    for (int k = 0; k < 3; ++k)
-        if (!(std::isfinite(box[k]) && box[k] > 0.0)) return fail(RELRES_ERR_ARG, "bad box edge %g", box[k]);
+    const int ns = c->nsys;
+    for (int k = 0; k < 3 * ns; ++k)
+        if (!(std::isfinite(box[k]) && box[k] > 0.0))
+            return fail(RELRES_ERR_ARG, "bad box edge %g (system %d)", box[k], k / 3);
     const double rla = c->rso + c->skin, rls = c->rco + c->skin;
     const bool sites = c->n_sites > 0;
-    const double rmax = sites ? rls : rla;
-    for (int k = 0; k < 3; ++k)
-        if (!(box[k] > 2.0 * rmax))
-            return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g must exceed 2 x %g", box[k], rmax);
+    for (int sy = 0; sy < ns; ++sy) {
+        // a system without hybrid atoms only needs the atom-list radius
+        const double rmax = c->sites_sys[sy] > 0 ? rls : rla;
+        for (int k = 0; k < 3; ++k)
+            if (!(box[3 * sy + k] > 2.0 * rmax))
+                return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g of system %d must exceed 2 x %g",
+                            box[3 * sy + k], sy, rmax);
+    }
     c->built = false;
     std::copy(box, box + 3, c->box);
+    c->boxes.assign(box, box + 3 * ns);
+    {
+        std::vector<double> bd((size_t)6 * ns);
+        for (int sy = 0; sy < ns; ++sy)
+            for (int k = 0; k < 3; ++k) {
+                bd[6 * sy + k] = box[3 * sy + k];
+                bd[6 * sy + 3 + k] = 1.0 / box[3 * sy + k];
+            }
+        if (bd != c->boxes_dev) {
+            TRY(ensure(c->d_boxes, sizeof(double) * bd.size(), &c->alloc_generation));
+            HIP_TRY(hipDeviceSynchronize());   // the old values may still be in use
+            HIP_TRY(hipMemcpy(c->d_boxes.p, bd.data(), sizeof(double) * bd.size(), hipMemcpyHostToDevice));
+            c->boxes_dev = bd;
+        }
+    }
     const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
-    TRY(setup_grid(c->ga, rla, box, c->n, &c->alloc_generation));
-    if (sites) TRY(setup_grid(c->gs, rls, box, c->n_sites, &c->alloc_generation));
+    TRY(setup_grid(c->ga, rla, ns, box, c->atoms_sys.data(), &c->alloc_generation));
+    if (sites) TRY(setup_grid(c->gs, rls, ns, box, c->sites_sys.data(), &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
     TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
     TRY(ensure(c->d_key_a, sizeof(int2) * c->n, &c->alloc_generation));
@@ -552,8 +631,12 @@ int enqueue_build(relres_ctx* c, const double* pos, const double box[3], hipStre
     TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n), &c->alloc_generation));
     TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites), &c->alloc_generation));
 
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &capture));
+    const bool capturing = capture != hipStreamCaptureStatusNone;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    const bool timed = c->timing && !capturing;
+    if (timed) {
         TRY(take_events(c, e0, e1));
         HIP_TRY(hipEventRecord(e0, s));
     }
@@ -561,22 +644,25 @@ int enqueue_build(relres_ctx* c, const double* pos, const double box[3], hipStre
         TRY(upload_grids(c, s));
         const TopoDev topo = topo_of(c);
         GridDev* gd = c->d_grids.as<GridDev>();
-        HIP_TRY(launch_bin(c->n, pos, box, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
+        HIP_TRY(launch_bin(c->n, pos, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
                            c->d_key_s.as<int2>(), c->d_status.as<Status>(), s));
         HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
         HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
                                 c->d_user2arow.as<int>(), s));
-        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->n, c->n_sites, topo, box,
+        HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->ga.waves, sites ? c->gs.waves : 0, topo,
                              c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
                              c->d_status.as<Status>(), lists_per_wave(c), s));
         HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(c->ev_status, s));
+        // in a captured graph the copy runs at every replay; the caller
+        // synchronises after the replay before relres_check_lists
+        if (!capturing) HIP_TRY(hipEventRecord(c->ev_status, s));
+        c->status_in_graph = capturing;
         c->check_pending = true;
     }
-    if (c->timing) {
+    if (timed) {
         HIP_TRY(hipEventRecord(e1, s));
         c->ev_build.push_back({e0, e1});
     }
@@ -600,8 +686,11 @@ int enqueue_build(relres_ctx* c, const double* pos, const double box[3], hipStre
 // then invalid until the next build).
 int examine_status(relres_ctx* c)
 {
-    if (!c->check_pending) return c->built ? RELRES_OK : fail(RELRES_ERR_NO_LISTS, "no lists");
-    HIP_TRY(hipEventSynchronize(c->ev_status));
+    // a build captured in a graph is examined at every check (each replay
+    // rebuilds the lists and copies a new status)
+    if (!c->check_pending && !c->status_in_graph)
+        return c->built ? RELRES_OK : fail(RELRES_ERR_NO_LISTS, "no lists");
+    if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
     c->check_pending = false;
     const Status& st = *c->h_status;
     if (st.nonfinite != c->nonfinite_seen) {
@@ -616,11 +705,13 @@ int examine_status(relres_ctx* c)
     if (!ov_a && !ov_s) return RELRES_OK;
     if (ov_a) {
         c->ga.cap = ((int)(mr_a * 1.25) + 8 + 7) & ~7;
-        TRY(setup_grid(c->ga, c->rso + c->skin, c->box, c->n, &c->alloc_generation));
+        TRY(setup_grid(c->ga, c->rso + c->skin, c->nsys, c->boxes.data(), c->atoms_sys.data(),
+                       &c->alloc_generation));
     }
     if (ov_s) {
         c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
-        TRY(setup_grid(c->gs, c->rco + c->skin, c->box, c->n_sites, &c->alloc_generation));
+        TRY(setup_grid(c->gs, c->rco + c->skin, c->nsys, c->boxes.data(), c->sites_sys.data(),
+                       &c->alloc_generation));
     }
     c->stats.regrows++;
     c->lanes_stale = true;
@@ -639,7 +730,7 @@ int drain_check(relres_ctx* c)
 }
 
 // Build, wait, and rebuild with grown rows until the lists are complete.
-int build_checked(relres_ctx* c, const double* pos, const double box[3], hipStream_t s)
+int build_checked(relres_ctx* c, const double* pos, const double* box, hipStream_t s)
 {
     TRY(drain_check(c));
     int rc = RELRES_ERR_LIST_RETRY;
@@ -822,7 +913,7 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
     }
     if (c->check_pending) {
         // a build of the previous topology is still unexamined: retire it
-        HIP_TRY(hipEventSynchronize(c->ev_status));
+        if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
         c->nonfinite_seen = c->h_status->nonfinite;
         c->check_pending = false;
     }
@@ -831,6 +922,11 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
     c->lanes_stale = true;
     c->n = n;
     c->n_sites = sites;
+    c->h_types = t;
+    c->nsys = 1;                      // one system until relres_set_systems says otherwise
+    c->sys_off = {0, n};
+    c->atoms_sys = {n};
+    c->sites_sys = {sites};
     c->same_mol = exclude_same_mol ? 1 : 0;
     c->has_excl = !idx.empty();
     c->max_excl = 0;
@@ -851,13 +947,49 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
     return RELRES_OK;
 }
 
-int relres_build_lists(relres_ctx* c, const double* pos, const double box[3], void* stream)
+int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
+    if (nsys < 1 || !atom_offsets) return fail(RELRES_ERR_ARG, "need nsys >= 1 and atom_offsets");
+    if (atom_offsets[0] != 0 || atom_offsets[nsys] != c->n)
+        return fail(RELRES_ERR_ARG, "atom_offsets must run from 0 to n_atoms (%d)", c->n);
+    std::vector<int> off(atom_offsets, atom_offsets + nsys + 1);
+    std::vector<int> atoms(nsys), sites(nsys, 0), sys(c->n);
+    for (int sy = 0; sy < nsys; ++sy) {
+        if (off[sy + 1] < off[sy]) return fail(RELRES_ERR_ARG, "atom_offsets must not decrease");
+        atoms[sy] = off[sy + 1] - off[sy];
+        for (int i = off[sy]; i < off[sy + 1]; ++i) {
+            sys[i] = sy;
+            sites[sy] += c->hybrid[c->h_types[i]] ? 1 : 0;
+        }
+    }
+    if (c->check_pending) {
+        if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
+        c->nonfinite_seen = c->h_status->nonfinite;
+        c->check_pending = false;
+    }
+    if (nsys > 1 && c->n > 0) {
+        TRY(ensure(c->d_sys, sizeof(int) * c->n, &c->alloc_generation));
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(c->d_sys.p, sys.data(), sizeof(int) * c->n, hipMemcpyHostToDevice));
+    }
+    c->nsys = nsys;
+    c->sys_off = off;
+    c->atoms_sys = atoms;
+    c->sites_sys = sites;
+    c->built = false;
+    c->lanes_stale = true;
+    return RELRES_OK;
+}
+
+int relres_build_lists(relres_ctx* c, const double* pos, const double* box, void* stream)
 {
     TRY(build_checked(c, pos, box, (hipStream_t)stream));
     return RELRES_OK;
 }
 
-int relres_build_lists_async(relres_ctx* c, const double* pos, const double box[3], void* stream)
+int relres_build_lists_async(relres_ctx* c, const double* pos, const double* box, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     TRY(drain_check(c));
@@ -890,7 +1022,7 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
     hipStream_t s = (hipStream_t)stream;
     if (c->n == 0) {
-        if (energy || virial) HIP_TRY(launch_zero_outputs(energy, virial, s));
+        if (energy || virial) HIP_TRY(launch_zero_outputs(energy, virial, c->nsys, s));
         return RELRES_OK;
     }
     if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
@@ -907,6 +1039,8 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
         a.box[k] = c->box[k];
         a.inv_box[k] = 1.0 / c->box[k];
     }
+    a.nsys = c->nsys;
+    a.boxes = c->d_boxes.as<double>();
     a.n_arow = c->n;
     a.a_rec = c->d_a_rec.as<int4>();
     a.a_list = c->ga.list.as<int>();
@@ -942,15 +1076,26 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     a.ew_rec = c->d_partials.as<unsigned long long>();
     a.epoch = c->d_epoch.as<unsigned int>();
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &capture));
+    const bool timed = c->timing && capture == hipStreamCaptureStatusNone;
+    if (timed) {
         TRY(take_events(c, e0, e1));
         HIP_TRY(hipEventRecord(e0, s));
     }
-    HIP_TRY(launch_forces(a, c->cut64, c->pair_math, c->precision, energy || virial, s));
-    if (c->timing) {
+    const bool ew = energy || virial;
+    if (ew && c->nsys > 1) {
+        TRY(ensure(c->d_row_ew, sizeof(double) * 8 * (size_t)(c->n + c->n_sites), &c->alloc_generation));
+        a.row_ew = c->d_row_ew.as<double>();
+    }
+    HIP_TRY(launch_forces(a, c->cut64, c->pair_math, c->precision, ew, s));
+    if (timed) {
         HIP_TRY(hipEventRecord(e1, s));
         c->ev_force.push_back({e0, e1});
     }
+    if (ew && c->nsys > 1)
+        HIP_TRY(launch_reduce_sys_ew(c->d_grids.as<GridDev>(), sites ? 2 : 1, a.row_ew, c->n, c->nsys,
+                                     energy, virial, s));
     return RELRES_OK;
 }
 
@@ -1005,6 +1150,8 @@ int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
         a.box[k] = c->box[k];
         a.inv_box[k] = 1.0 / c->box[k];
     }
+    a.nsys = c->nsys;
+    a.boxes = c->d_boxes.as<double>();
     a.n_arow = c->n;
     a.a_rec = c->d_a_rec.as<int4>();
     a.a_list = c->ga.list.as<int>();
@@ -1126,15 +1273,16 @@ void relres_destroy(relres_ctx* c)
 {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial}) release(*b);
+    for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial, &c->d_sys, &c->d_boxes, &c->d_row_ew}) release(*b);
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
                     &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials,
                     &c->d_epoch})
         release(*b);
     for (GridHost* g : {&c->ga, &c->gs})
-        for (DBuf* b : {&g->rank_of_lin, &g->lin_of_rank, &g->nbr, &g->count, &g->start, &g->user_unsorted,
-                        &g->user, &g->pos, &g->meta, &g->row_cell, &g->list, &g->nrow})
+        for (DBuf* b : {&g->geom_dev, &g->cell_sys, &g->rank_of_lin, &g->lin_of_rank, &g->nbr,
+                        &g->count, &g->start, &g->user_unsorted, &g->user, &g->pos, &g->meta,
+                        &g->row_cell, &g->list, &g->nrow})
             release(*b);
     if (c->h_grids) (void)hipHostFree(c->h_grids);
     if (c->h_status) (void)hipHostFree(c->h_status);

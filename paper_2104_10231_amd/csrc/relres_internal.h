@@ -43,19 +43,34 @@ struct Cutoffs {
     S rsi2, rso2, rci2, rco2;    // their squares
 };
 
-// One cell grid with its sorted members and its neighbour list.  Members of
-// the atom grid are all atoms; members of the site grid are the hybrid atoms.
-struct GridDev {
+// Cell grid of one system for one kind of list (atom grid: cells >= r_s+ +
+// skin over all atoms; site grid: cells >= r_c+ + skin over hybrid atoms).
+struct GeomDev {
     int n[3];                 // cells per axis
-    int ncell;
+    int cell_base;            // global rank of this grid's first cell
     double inv_cell[3];       // n_k / L_k
-    int noff[3];              // distinct stencil offsets per axis (1..3)
-    int off[3][3];
-    double rl2;               // list radius squared (membership test)
+    double box[3];            // L_k of the system
+    double half[3];           // L_k / 2
+    int row_base;             // global row of this grid's first member
     int members;
+    int wave_base;            // first wave of this grid in the list kernel
+    int pad;
+};
+
+// All grids of one kind, one per system, concatenated: cells are numbered
+// grid after grid (Morton order inside a grid) and member rows follow the
+// cells, so the rows of a system are contiguous.
+struct GridDev {
+    int nsys;
+    int ncell;                // cells of all grids
+    int members;              // members of all grids
     int cap;                  // row capacity of the padded list
-    const int* rank_of_lin;   // Morton rank of a linear cell index
-    const int* lin_of_rank;
+    int waves;                // waves of the list kernel for this kind
+    double rl2;               // list radius squared (membership test)
+    const GeomDev* geom;      // [nsys]
+    const int* cell_sys;      // [ncell] system of each cell
+    const int* rank_of_lin;   // [cell_base + local linear index] -> global cell rank
+    const int* lin_of_rank;   // [global cell rank] -> local linear index
     const int* nbr;           // ncell x 27 stencil ranks (-1: slot unused after deduplication)
     int* count;               // per cell (by rank); zero between builds
     int* start;               // ncell + 1 exclusive offsets (by rank)
@@ -77,6 +92,7 @@ struct TopoDev {
     int same_mol;
     int n;
     int max_excl;             // most excluded partners of any atom
+    const int* sys;           // system of each atom, or null when there is one system
 };
 
 // Build status, in mapped pinned host memory: the kernels write it directly
@@ -93,16 +109,19 @@ struct Status {
 
 struct ForceArgs {
     const double* pos;        // caller positions, N x 3
-    double box[3];
+    double box[3];            // box of system 0 (the only one when nsys == 1)
     double inv_box[3];
+    int nsys;
+    const double* boxes;      // [nsys][6]: L_x, L_y, L_z, 1/L_x, 1/L_y, 1/L_z
+    double* row_ew;           // nsys > 1: 8 FP64 partials per row (atom rows, then site rows)
     // atom list rows (all atoms, atom-grid order); record = (caller index,
-    // type, stored entries, 1 if hybrid)
+    // type + 32 system, stored entries, 1 if hybrid)
     int n_arow;
     const int4* a_rec;
     const int* a_list;
     int a_cap;
     // site list rows (hybrid atoms, site-grid order); record = (caller index,
-    // type, stored entries, atom-list row of the same atom)
+    // type + 32 system, stored entries, atom-list row of the same atom)
     int n_srow;
     const int4* s_rec;
     const int* s_list;
@@ -111,8 +130,8 @@ struct ForceArgs {
     const void* coef64;       // PairCoef<double>[ntypes * ntypes]
     int ntypes;
     void* forces;             // N x 3 of TF, caller order
-    double* energy;           // [3] or null
-    double* virial;           // [6] or null
+    double* energy;           // [nsys][3] or null
+    double* virial;           // [nsys][6] or null
     unsigned long long* ew_rec;   // energy/virial records: one per block, then one per group
     unsigned int* epoch;          // launch epoch, advanced by every energy/virial launch
     int blocks_a, blocks_b;   // multiples of 8
@@ -121,18 +140,17 @@ struct ForceArgs {
 };
 
 // Launchers (relres_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_bin(int n, const double* pos, const double box[3], TopoDev topo,
-                      GridDev* grids_dev, double4* wpos, int2* key_a, int2* key_s, Status* st,
-                      hipStream_t s);
+hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev, double4* wpos,
+                      int2* key_a, int2* key_s, Status* st, hipStream_t s);
 hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);
 hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,
                            TopoDev topo, int* user2arow, hipStream_t s);
 // per_wave: one wave per home cell (small cells) instead of one block per cell
-hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int members_a,
-                        int members_s, TopoDev topo, const double box[3], const int* user2arow,
-                        int4* a_rec, int4* s_rec, Status* st, bool per_wave, hipStream_t s);
+hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
+                        TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
+                        bool per_wave, hipStream_t s);
 // cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares}
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
                          bool ew, hipStream_t s);
@@ -141,7 +159,7 @@ hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStre
 struct BackArgs {
     ForceArgs f;
     const double* gforce;                 // dJ/dF, N x 3, or NULL
-    const double* genergy;                // dJ/dE (device scalar) or NULL
+    const double* genergy;                // dJ/dE per system (device, nsys) or NULL
     double* gpos;                         // out: dJ/dx, N x 3
     const PairCoef<double>* cgrad;        // [4][ntypes^2] derivative records
     double* partial;                      // per wave: [ntypes^2][4] parameter sums
@@ -151,8 +169,15 @@ constexpr int kBackwardTypes = 8;
 hipError_t launch_backward(const BackArgs& b, const double* cut64, int waves, double* grad_pair,
                            hipStream_t s);
 hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
-hipError_t launch_zero_outputs(double* energy, double* virial, hipStream_t s);
+hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStream_t s);
+// nsys > 1: energy/virial of each system from the per-row partials
+hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const double* row_ew,
+                                int n_arow, int nsys, double* energy, double* virial,
+                                hipStream_t s);
 
+// Row record field y: atom type in the low kTypeBits bits, system above.
+constexpr int kTypeBits = 5;
+constexpr int kRowsPerWave = 8;       // home rows per wave of the list kernel
 constexpr int kXcdGroups = 8;        // workgroups are dealt round-robin to 8 XCDs
 constexpr int kEwRecBytes = 128;     // one energy/virial record: 16 tagged 64-bit words
 constexpr int kForceBlock = 256;

@@ -92,35 +92,38 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 // build kernels
 // ---------------------------------------------------------------------------
 
-__global__ void k_bin(int n, const double* __restrict__ pos, double Lx, double Ly, double Lz,
-                      TopoDev topo, const GridDev* __restrict__ grids,
-                      double4* __restrict__ wpos, int2* __restrict__ key_a,
-                      int2* __restrict__ key_s, Status* __restrict__ st)
+__global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
+                      const GridDev* __restrict__ grids, double4* __restrict__ wpos,
+                      int2* __restrict__ key_a, int2* __restrict__ key_s, Status* __restrict__ st)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int sy = topo.sys ? topo.sys[i] : 0;
     double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
     if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
         atomicOr(&st->nonfinite, 1);
         x = y = z = 0.0;
     }
-    const double wx = wrap_coord(x, Lx), wy = wrap_coord(y, Ly), wz = wrap_coord(z, Lz);
+    const GridDev& ga = grids[0];
+    const GeomDev& G = ga.geom[sy];
+    const double wx = wrap_coord(x, G.box[0]), wy = wrap_coord(y, G.box[1]),
+                 wz = wrap_coord(z, G.box[2]);
     wpos[i] = make_double4(wx, wy, wz, 0.0);
     {
-        const GridDev& g = grids[0];
-        const int lin = (cell_coord(wx, g.inv_cell[0], g.n[0]) * g.n[1] +
-                         cell_coord(wy, g.inv_cell[1], g.n[1])) * g.n[2] +
-                        cell_coord(wz, g.inv_cell[2], g.n[2]);
-        const int r = gbl(g.rank_of_lin)[lin];
-        key_a[i] = make_int2(r, atomicAdd(&g.count[r], 1));
+        const int lin = (cell_coord(wx, G.inv_cell[0], G.n[0]) * G.n[1] +
+                         cell_coord(wy, G.inv_cell[1], G.n[1])) * G.n[2] +
+                        cell_coord(wz, G.inv_cell[2], G.n[2]);
+        const int r = gbl(ga.rank_of_lin)[G.cell_base + lin];
+        key_a[i] = make_int2(r, atomicAdd(&ga.count[r], 1));
     }
     if (topo.hybrid[topo.types[i]]) {
-        const GridDev& g = grids[1];
-        const int lin = (cell_coord(wx, g.inv_cell[0], g.n[0]) * g.n[1] +
-                         cell_coord(wy, g.inv_cell[1], g.n[1])) * g.n[2] +
-                        cell_coord(wz, g.inv_cell[2], g.n[2]);
-        const int r = gbl(g.rank_of_lin)[lin];
-        key_s[i] = make_int2(r, atomicAdd(&g.count[r], 1));
+        const GridDev& gs = grids[1];
+        const GeomDev& H = gs.geom[sy];
+        const int lin = (cell_coord(wx, H.inv_cell[0], H.n[0]) * H.n[1] +
+                         cell_coord(wy, H.inv_cell[1], H.n[1])) * H.n[2] +
+                        cell_coord(wz, H.inv_cell[2], H.n[2]);
+        const int r = gbl(gs.rank_of_lin)[H.cell_base + lin];
+        key_s[i] = make_int2(r, atomicAdd(&gs.count[r], 1));
     } else {
         key_s[i] = make_int2(-1, -1);
     }
@@ -260,7 +263,6 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 // wave tests 64 staged candidates at a time.  Only wave-level synchronisation
 // is used, so waves of one block may run different trip counts.
 constexpr int kWaveChunk = 128;
-constexpr int kRowsPerWave = 8;
 
 // Membership with the periodic shift of the candidate's stencil slot known in
 // advance.  When a grid has at least four cells along an axis, a neighbour
@@ -292,7 +294,6 @@ __device__ __forceinline__ bool member_shifted(double xi, double yi, double zi, 
 __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ grids,
                                                     int waves_a, int waves_total, int max_excl,
                                                     TopoDev topo,
-                                                    double Lx, double Ly, double Lz,
                                                     const int* __restrict__ user2arow,
                                                     int4* __restrict__ a_rec,
                                                     int4* __restrict__ s_rec,
@@ -318,13 +319,22 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     RELRES_GLOBAL const int* gnbr = gbl(g.nbr);
     RELRES_GLOBAL int* glist = gbl(g.list);
     RELRES_GLOBAL const int* glor = gbl(g.lin_of_rank);
-    const int members = g.members;
-    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    // the system whose grid holds this wave's rows: last grid starting at or
+    // before the wave (wave-uniform; grids with no rows have no waves)
+    const int lw = site ? gw - waves_a : gw;
+    int gs_lo = 0, gs_hi = g.nsys - 1;
+    while (gs_lo < gs_hi) {
+        const int mid = (gs_lo + gs_hi + 1) >> 1;
+        if (g.geom[mid].wave_base <= lw) gs_lo = mid; else gs_hi = mid - 1;
+    }
+    const GeomDev& G = g.geom[gs_lo];
+    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+    const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
     // known image shifts need at least four cells along every axis
     const bool known_shift = n0 >= 4 && n1 >= 4 && n2 >= 4;
-    const int r0 = (site ? gw - waves_a : gw) * kRowsPerWave;
-    const int r1 = min(members, r0 + kRowsPerWave);
-    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+    const int r0 = G.row_base + (lw - G.wave_base) * kRowsPerWave;
+    const int r1 = min(G.row_base + G.members, r0 + kRowsPerWave);
+    const double hx = G.half[0], hy = G.half[1], hz = G.half[2];
     const double rl2 = g.rl2;
     const int cap = g.cap;
     const int* __restrict__ excl_off = topo.excl_off;
@@ -468,8 +478,9 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     if (lane < nh) {
         gbl(g.nrow)[myrow] = mcnt;
         const int stored = min(mcnt, cap);
-        if (site) s_rec[myrow] = make_int4(mu, mt, stored, marow);
-        else a_rec[myrow] = make_int4(mu, mt, stored, topo.hybrid[mt]);
+        const int ty = mt | (gs_lo << kTypeBits);
+        if (site) s_rec[myrow] = make_int4(mu, ty, stored, marow);
+        else a_rec[myrow] = make_int4(mu, ty, stored, topo.hybrid[mt]);
     }
     // only a row that outgrew its capacity touches the status word (rare), so
     // thousands of waves do not serialise on one address
@@ -481,7 +492,6 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
 // is stored even when it exceeds the capacity, so the host can regrow.
 __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict__ grids,
                                                       int ncell_a, TopoDev topo,
-                                                      double Lx, double Ly, double Lz,
                                                       const int* __restrict__ user2arow,
                                                       int4* __restrict__ a_rec,
                                                       int4* __restrict__ s_rec,
@@ -537,7 +547,9 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
     const int ncand = cell_pre[ncells];
     const int hb = g.start[c];
     const int he = g.start[c + 1];
-    const double hx = 0.5 * Lx, hy = 0.5 * Ly, hz = 0.5 * Lz;
+    const GeomDev& G = g.geom[g.cell_sys[c]];
+    const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
+    const double hx = G.half[0], hy = G.half[1], hz = G.half[2];
     const double rl2 = g.rl2;
     const int cap = g.cap;
 
@@ -604,8 +616,9 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
             const int u = g.user[row];
             const int ty = g.meta[row].x;
             const int stored = min(cnt, cap);
-            if (site) s_rec[row] = make_int4(u, ty, stored, user2arow[u]);
-            else a_rec[row] = make_int4(u, ty, stored, topo.hybrid[ty]);
+            const int tys = ty | (g.cell_sys[c] << kTypeBits);
+            if (site) s_rec[row] = make_int4(u, tys, stored, user2arow[u]);
+            else a_rec[row] = make_int4(u, tys, stored, topo.hybrid[ty]);
         }
     }
     __syncthreads();
@@ -765,6 +778,28 @@ constexpr int kBatch = 2;
 
 constexpr uint32_t kNoEntry = 0xffffffffu;
 
+// Periodic box of the system a row belongs to: edges and their reciprocals.
+struct BoxV {
+    double L[3], iL[3];
+};
+
+__device__ __forceinline__ BoxV row_box(const ForceArgs& a, int sys)
+{
+    BoxV b;
+    if (a.nsys == 1) {
+        for (int k = 0; k < 3; ++k) {
+            b.L[k] = a.box[k];
+            b.iL[k] = a.inv_box[k];
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            b.L[k] = a.boxes[6 * sys + k];
+            b.iL[k] = a.boxes[6 * sys + 3 + k];
+        }
+    }
+    return b;
+}
+
 // Pair terms of one list entry, the FG part (CG = false, zero beyond r_s+) or
 // the CG part (CG = true, zero beyond r_c+) of Eq. 20, with the neighbour's
 // position already loaded.  Differences are taken in FP64 with the minimum
@@ -772,7 +807,7 @@ constexpr uint32_t kNoEntry = 0xffffffffu;
 // virial terms are evaluated in FP64 and accumulated in FP64 (when they are
 // requested, the FP32 force is rounded from the same FP64 terms).
 template <bool CG, typename S, typename TF, bool EW>
-__device__ __forceinline__ void entry_terms(const ForceArgs& a, const PairCoef<S>* crow,
+__device__ __forceinline__ void entry_terms(const BoxV& bx, const PairCoef<S>* crow,
                                             const PairCoef<double>* crow64,
                                             const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
                                             double xi, double yi, double zi, uint32_t e,
@@ -785,9 +820,9 @@ __device__ __forceinline__ void entry_terms(const ForceArgs& a, const PairCoef<S
     double dx = xi - px;
     double dy = yi - py;
     double dz = zi - pz;
-    dx -= a.box[0] * rint(dx * a.inv_box[0]);
-    dy -= a.box[1] * rint(dy * a.inv_box[1]);
-    dz -= a.box[2] * rint(dz * a.inv_box[2]);
+    dx -= bx.L[0] * rint(dx * bx.iL[0]);
+    dy -= bx.L[1] * rint(dy * bx.iL[1]);
+    dz -= bx.L[2] * rint(dz * bx.iL[2]);
     const double r2d = dx * dx + dy * dy + dz * dz;
     if (!(r2d < rmax2)) return;
     if constexpr (sizeof(S) == sizeof(double) || EW) {
@@ -845,7 +880,8 @@ __device__ __forceinline__ void gather_batch(const ForceArgs& a, const uint32_t 
 // a time: their list loads, then their position gathers, are issued together
 // before any pair term is computed.
 template <bool CG, typename S, typename TF, bool EW>
-__device__ __forceinline__ void row_terms(const ForceArgs& a, const PairCoef<S>* crow,
+__device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
+                                          const PairCoef<S>* crow,
                                           const PairCoef<double>* crow64,
                                           const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
                                           double xi, double yi, double zi,
@@ -863,7 +899,7 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const PairCoef<S>*
         gather_batch(a, e, px, py, pz);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
-            entry_terms<CG, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi, e[u], px[u],
+            entry_terms<CG, S, TF, EW>(bx, crow, crow64, cut, cut64, xi, yi, zi, e[u], px[u],
                                        py[u], pz[u], fx, fy, fz, acc);
     }
 }
@@ -1186,7 +1222,8 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const bool own = rb ? rec.x >= 0 : (rec.x >= 0 && rec.w == 0);   // hybrid atom rows belong to the site range
     if (own) {
-        const int ui = rec.x, ti = rec.y;
+        const int ui = rec.x, ti = rec.y & ((1 << kTypeBits) - 1);
+        const BoxV bx = row_box(a, rec.y >> kTypeBits);
         const int cnt_s = rb ? rec.z : 0;
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -1203,22 +1240,22 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         const PairCoef<double>* crow64 = coef64 + ti * a.ntypes;
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
-            entry_terms<false, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi, e_fg[u],
+            entry_terms<false, S, TF, EW>(bx, crow, crow64, cut, cut64, xi, yi, zi, e_fg[u],
                                           fxp[u], fyp[u], fzp[u], fx, fy, fz, acc);
         if (rb) {
 #pragma unroll
             for (int u = 0; u < kBatch; ++u)
-                entry_terms<true, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi, e_own[u],
+                entry_terms<true, S, TF, EW>(bx, crow, crow64, cut, cut64, xi, yi, zi, e_own[u],
                                              sxp[u], syp[u], szp[u], fx, fy, fz, acc);
         }
         // the rest of both rows
         const int ar = rb ? rec.w : row;
         const int rest = sub + kBatch * G;
-        row_terms<false, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi,
+        row_terms<false, S, TF, EW>(a, bx, crow, crow64, cut, cut64, xi, yi, zi,
                                     a.a_list + (size_t)ar * a.a_cap, rest, cnt_a, G, fx, fy, fz,
                                     acc);
         if (rb)
-            row_terms<true, S, TF, EW>(a, crow, crow64, cut, cut64, xi, yi, zi,
+            row_terms<true, S, TF, EW>(a, bx, crow, crow64, cut, cut64, xi, yi, zi,
                                        a.s_list + (size_t)row * a.s_cap, rest, cnt_s, G, fx, fy,
                                        fz, acc);
     }
@@ -1231,15 +1268,67 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         F[3 * rec.x + 1] = fy;
         F[3 * rec.x + 2] = fz;
     }
-    if constexpr (EW) ew_finish(a, acc, tag);
+    if constexpr (EW) {
+        if (a.nsys == 1) {
+            ew_finish(a, acc, tag);
+        } else {
+            // several systems: every row publishes its partials; a second
+            // kernel adds each system's rows in row order
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] = group_sum(acc[k], G);
+            if (live && sub == 0) {
+                double* out = a.row_ew + 8 * (size_t)(rb ? a.n_arow + row : row);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) out[k] = own ? acc[k] : 0.0;
+            }
+        }
+    }
 }
 
 
-__global__ void k_zero_outputs(double* energy, double* virial)
+__global__ void k_zero_outputs(double* energy, double* virial, int nsys)
 {
-    const int t = threadIdx.x;
-    if (energy && t < 3) energy[t] = 0.0;
-    if (virial && t < 6) virial[t] = 0.0;
+    for (int t = threadIdx.x; t < 6 * nsys; t += blockDim.x) {
+        if (energy && t < 3 * nsys) energy[t] = 0.0;
+        if (virial) virial[t] = 0.0;
+    }
+}
+
+// Energy and virial of every system (one block per system) from the per-row
+// partials of the force kernel: the system's atom-list rows, then its
+// site-list rows, each thread in row order, then a fixed-order block sum.
+__global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict__ grids,
+                                                       int ngrids, const double* __restrict__ row_ew,
+                                                       int n_arow, double* __restrict__ energy,
+                                                       double* __restrict__ virial)
+{
+    __shared__ double red[8][4];
+    const int sy = (int)blockIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int kind = 0; kind < ngrids; ++kind) {
+        const GeomDev& G = grids[kind].geom[sy];
+        const size_t base = (kind ? (size_t)n_arow : 0) + (size_t)G.row_base;
+        for (int r = (int)threadIdx.x; r < G.members; r += 256) {
+            const double* p = row_ew + 8 * (base + r);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] += p[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double w = wave_sum(v[k]);
+        if ((threadIdx.x & 63) == 63) red[k][threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        const double t = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+        if (k < 2 && energy) energy[3 * sy + 1 + k] = t;
+        if (k >= 2 && virial) virial[6 * sy + k - 2] = t;
+        red[k][0] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && energy) energy[3 * sy] = red[0][0] + red[1][0];
 }
 
 template <typename S>
@@ -1257,13 +1346,12 @@ Cutoffs<S> cut_as(const double* c64)
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_bin(int n, const double* pos, const double box[3], TopoDev topo,
-                      GridDev* grids_dev, double4* wpos, int2* key_a, int2* key_s, Status* st,
-                      hipStream_t s)
+hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev, double4* wpos,
+                      int2* key_a, int2* key_s, Status* st, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, box[0], box[1],
-                       box[2], topo, grids_dev, wpos, key_a, key_s, st);
+    hipLaunchKernelGGL(k_bin, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, topo, grids_dev,
+                       wpos, key_a, key_s, st);
     return hipGetLastError();
 }
 
@@ -1294,23 +1382,22 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, con
     return hipGetLastError();
 }
 
-hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int members_a,
-                        int members_s, TopoDev topo, const double box[3], const int* user2arow,
-                        int4* a_rec, int4* s_rec, Status* st, bool per_wave, hipStream_t s)
+hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
+                        TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
+                        bool per_wave, hipStream_t s)
 {
     if (per_wave) {
-        const int wa = (members_a + kRowsPerWave - 1) / kRowsPerWave;
-        const int total = wa + (members_s + kRowsPerWave - 1) / kRowsPerWave;
+        const int total = waves_a + waves_s;
         if (total == 0) return hipSuccess;
         const int mx = topo.excl_off ? topo.max_excl : 0;
         const size_t dyn = sizeof(int) * 4 * kRowsPerWave * (size_t)mx;
         hipLaunchKernelGGL(k_lists_wave, dim3((total + 3) / 4), dim3(256), dyn, s, grids_dev,
-                           wa, total, mx, topo, box[0], box[1], box[2], user2arow, a_rec, s_rec,
-                           st);
+                           waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
         return hipGetLastError();
     }
+    if (ncell_a + ncell_s == 0) return hipSuccess;
     hipLaunchKernelGGL(k_lists, dim3(ncell_a + ncell_s), dim3(kListBlock), 0, s, grids_dev,
-                       ncell_a, topo, box[0], box[1], box[2], user2arow, a_rec, s_rec, st);
+                       ncell_a, topo, user2arow, a_rec, s_rec, st);
     return hipGetLastError();
 }
 
@@ -1419,7 +1506,8 @@ __device__ __forceinline__ void cg_terms2(const PairCoef<double>& c, const Cutof
 // One list row of the backward pass (FG part when CG is false, CG part when
 // true); TM bounds the number of types.
 template <bool CG, int TM>
-__device__ __forceinline__ void back_row(const BackArgs& b, const Cutoffs<double>& cut, int ti,
+__device__ __forceinline__ void back_row(const BackArgs& b, const BoxV& bx,
+                                         const Cutoffs<double>& cut, int ti,
                                          double xi, double yi, double zi, double gix, double giy,
                                          double giz, double ebar, const int* __restrict__ lst,
                                          int cnt, int sub, int G, double gp[3], double acc[TM][4])
@@ -1436,9 +1524,9 @@ __device__ __forceinline__ void back_row(const BackArgs& b, const Cutoffs<double
         double dx = xi - a.pos[3 * uj];
         double dy = yi - a.pos[3 * uj + 1];
         double dz = zi - a.pos[3 * uj + 2];
-        dx -= a.box[0] * rint(dx * a.inv_box[0]);
-        dy -= a.box[1] * rint(dy * a.inv_box[1]);
-        dz -= a.box[2] * rint(dz * a.inv_box[2]);
+        dx -= bx.L[0] * rint(dx * bx.iL[0]);
+        dy -= bx.L[1] * rint(dy * bx.iL[1]);
+        dz -= bx.L[2] * rint(dz * bx.iL[2]);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (!(r2 < rmax2)) continue;
         const int pi = ti * nt + tj;
@@ -1497,14 +1585,16 @@ __global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b, Cutoffs<do
         cnt_a = a.a_rec[rec.w].z;
     }
     const bool own = rb ? rec.x >= 0 : (rec.x >= 0 && rec.w == 0);
-    const double ebar = b.genergy ? b.genergy[0] : 0.0;
+    const int sy = rec.x >= 0 ? rec.y >> kTypeBits : 0;
+    const double ebar = b.genergy ? b.genergy[sy] : 0.0;
+    const BoxV bx = row_box(a, sy);
     double acc[TM][4];
 #pragma unroll
     for (int q = 0; q < TM; ++q)
 #pragma unroll
         for (int P = 0; P < 4; ++P) acc[q][P] = 0.0;
     double gp[3] = {0.0, 0.0, 0.0};
-    const int ti = rec.y;
+    const int ti = rec.y & ((1 << kTypeBits) - 1);
     if (own) {
         const int ui = rec.x;
         const double xi = a.pos[3 * ui], yi = a.pos[3 * ui + 1], zi = a.pos[3 * ui + 2];
@@ -1516,10 +1606,10 @@ __global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b, Cutoffs<do
         }
         const int ar = rb ? rec.w : row;
         const int ca = rb ? cnt_a : rec.z;
-        back_row<false, TM>(b, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
+        back_row<false, TM>(b, bx, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
                             a.a_list + (size_t)ar * a.a_cap, ca, sub, G, gp, acc);
         if (rb)
-            back_row<true, TM>(b, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
+            back_row<true, TM>(b, bx, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
                                a.s_list + (size_t)row * a.s_cap, rec.z, sub, G, gp, acc);
     }
     for (int c = 0; c < 3; ++c) gp[c] = group_sum(gp[c], G);
@@ -1601,9 +1691,18 @@ hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_zero_outputs(double* energy, double* virial, hipStream_t s)
+hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_outputs, dim3(1), dim3(64), 0, s, energy, virial);
+    hipLaunchKernelGGL(k_zero_outputs, dim3(1), dim3(256), 0, s, energy, virial, nsys);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const double* row_ew,
+                                int n_arow, int nsys, double* energy, double* virial,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_sys_ew, dim3(nsys), dim3(256), 0, s, grids_dev, ngrids, row_ew,
+                       n_arow, energy, virial);
     return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "relres_set_systems": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "relres_set_pair_params": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p,
                                               _c_double_p, _c_double_p]),
     "relres_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -173,6 +174,14 @@ class RelRes:
                                              int(bool(exclude_same_mol)), _ptr(eo), _ptr(ei)),
                "relres_set_topology")
         self.n = int(t.shape[0])
+        self.nsys = 1
+
+    def set_systems(self, atom_offsets):
+        """Atoms [off[s], off[s+1]) form system s; one box per system."""
+        off = _i32(atom_offsets)
+        _check(self._lib.relres_set_systems(self._ctx, int(off.shape[0] - 1), _ptr(off)),
+               "relres_set_systems")
+        self.nsys = int(off.shape[0] - 1)
 
     # -- hot path ------------------------------------------------------------
     def _pos(self, pos: torch.Tensor) -> torch.Tensor:
@@ -186,7 +195,10 @@ class RelRes:
         """Build both lists.  With wait=False the build is only enqueued; call
         check_lists() before trusting results computed from these lists."""
         pos = self._pos(pos)
-        b = (ctypes.c_double * 3)(*[float(x) for x in box])
+        bx = np.asarray(box, dtype=np.float64).reshape(-1)
+        if bx.shape[0] != 3 * self.nsys:
+            raise ValueError(f"box needs {3 * self.nsys} values ({self.nsys} systems x 3)")
+        b = (ctypes.c_double * bx.shape[0])(*bx.tolist())
         fn = self._lib.relres_build_lists if wait else self._lib.relres_build_lists_async
         _check(fn(self._ctx, pos.data_ptr() if self.n else None, b, _stream(stream)),
                "relres_build_lists" if wait else "relres_build_lists_async")
@@ -210,10 +222,15 @@ class RelRes:
             out = torch.empty((self.n, 3), dtype=dt, device=pos.device)
         elif out.dtype != dt or tuple(out.shape) != (self.n, 3) or not out.is_contiguous():
             raise TypeError("out must be a contiguous (N, 3) tensor of the force dtype")
+        eshape = (3,) if self.nsys == 1 else (self.nsys, 3)
+        wshape = (6,) if self.nsys == 1 else (self.nsys, 6)
         if want_energy and energy is None:
-            energy = torch.empty(3, dtype=torch.float64, device=pos.device)
+            energy = torch.empty(eshape, dtype=torch.float64, device=pos.device)
         if want_virial and virial is None:
-            virial = torch.empty(6, dtype=torch.float64, device=pos.device)
+            virial = torch.empty(wshape, dtype=torch.float64, device=pos.device)
+        for t, n in ((energy, 3), (virial, 6)):
+            if t is not None and (t.numel() != n * self.nsys or not t.is_contiguous()):
+                raise ValueError(f"energy/virial buffers need {n} x nsys contiguous doubles")
         _check(self._lib.relres_forces(self._ctx, pos.data_ptr() if self.n else None,
                                        out.data_ptr() if self.n else None,
                                        energy.data_ptr() if energy is not None else None,
@@ -247,7 +264,9 @@ class RelRes:
                 raise ValueError("grad_forces must be an (N, 3) tensor on the positions' device")
         ge = None
         if grad_energy is not None:
-            ge = grad_energy.to(device=pos.device, dtype=torch.float64).reshape(1).contiguous()
+            ge = grad_energy.to(device=pos.device, dtype=torch.float64).reshape(-1).contiguous()
+            if ge.numel() != self.nsys:
+                raise ValueError(f"grad_energy needs {self.nsys} values (one per system)")
         gpos = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device)
         gpair = torch.empty((4, self.ntypes, self.ntypes), dtype=torch.float64, device=pos.device)
         _check(self._lib.relres_backward(self._ctx, pos.data_ptr() if self.n else None,

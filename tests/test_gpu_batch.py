@@ -1,0 +1,127 @@
+"""GPU parity of batched replicas (relres_set_systems): several independent
+systems with their own boxes in one context, one launch per step.  Each
+replica is checked against the oracle on its own: forces, energy and virial
+per system, pair sets, and the adjoint."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from _util import make_relres, pair_set, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: (1e-11, 1e-12), 32: (1e-5, 1e-7)}
+
+
+def _batch(precision):
+    b = w.replica_batch(1, n_systems=6, min_atoms=300, max_atoms=900, total_atoms=3000,
+                        precision=precision)
+    # one replica without hybrid atoms: it has no site list at all
+    s = b.systems[2]
+    t = s.types.copy()
+    t[t == 1] = 0
+    t[t == 3] = 2
+    systems = list(b.systems)
+    systems[2] = s.replace(types=t)
+    return w.batch_of(systems)
+
+
+def _run(b, precision, lanes=None):
+    import torch
+    rr = make_relres(b.whole, precision)
+    rr.set_systems(b.offsets)
+    if lanes:
+        rr.set_launch(*lanes)
+    p = torch.from_numpy(b.whole.pos).cuda()
+    rr.build_lists(p, b.boxes)
+    F, E, W = rr.forces(p)
+    torch.cuda.synchronize()
+    return rr, F.double().cpu().numpy(), E.cpu().numpy(), W.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_replicas_match_the_oracle_one_by_one(precision):
+    b = _batch(precision)
+    print(f"[batch] {b.nsys} replicas, N={b.whole.n}, precision={precision}", flush=True)
+    rr, F, E, W = _run(b, precision)
+    assert E.shape == (b.nsys, 3) and W.shape == (b.nsys, 6)
+    ftol, etol = TOL[precision]
+    want = {0: set(), 1: set()}
+    for k, s in enumerate(b.systems):
+        o0, o1 = int(b.offsets[k]), int(b.offsets[k + 1])
+        Fr, Er, Wr = oracle.compute(s)
+        assert rel_rms(F[o0:o1], Fr) <= ftol, (k, rel_rms(F[o0:o1], Fr))
+        assert abs(E[k, 0] - Er[0]) <= etol * abs(Er[0]), (k, E[k], Er)
+        assert np.abs(W[k] - Wr).max() <= etol * np.abs(Wr).max(), k
+        for which in (0, 1):
+            want[which] |= {(i + o0, j + o0) for i, j in pair_set(oracle.pairs(s, which))}
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == want[which]
+    rr.close()
+
+
+def test_replicas_equal_separate_contexts():
+    import torch
+    b = _batch(32)
+    rr, F, E, W = _run(b, 32, lanes=(4, 16))
+    for k, s in enumerate(b.systems):
+        o0, o1 = int(b.offsets[k]), int(b.offsets[k + 1])
+        r1 = make_relres(s, 32)
+        r1.set_launch(4, 16)
+        p = torch.from_numpy(s.pos).cuda()
+        r1.build_lists(p, s.box)
+        F1, E1, W1 = r1.forces(p)
+        # same lists, same lane split: the same force bits
+        assert np.array_equal(F[o0:o1], F1.double().cpu().numpy()), k
+        assert abs(E[k, 0] - E1[0].item()) <= 1e-12 * abs(E1[0].item())
+        r1.close()
+    rr.close()
+
+
+def test_replica_backward_matches_the_oracle():
+    import torch
+    b = _batch(64)
+    rr = make_relres(b.whole, 64)
+    rr.set_systems(b.offsets)
+    p = torch.from_numpy(b.whole.pos).cuda()
+    rr.build_lists(p, b.boxes)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(b.whole.n, 3))
+    ebar = rng.normal(size=b.nsys)
+    gpos, gpair = rr.backward(p, torch.from_numpy(g).cuda(),
+                              torch.from_numpy(ebar).cuda())
+    gpos = gpos.cpu().numpy()
+    for k, s in enumerate(b.systems):
+        o0, o1 = int(b.offsets[k]), int(b.offsets[k + 1])
+        _, dp = oracle.grad(s, g[o0:o1], ebar[k])
+        assert np.linalg.norm(gpos[o0:o1] - dp) <= 1e-9 * np.linalg.norm(dp), k
+    rr.close()
+
+
+def test_batched_graph_replay_of_build_and_forces():
+    """Rebuild + force calls of all replicas captured in one HIP graph."""
+    import torch
+    b = _batch(32)
+    rr = make_relres(b.whole, 32)
+    rr.set_systems(b.offsets)
+    p = torch.from_numpy(b.whole.pos).cuda()
+    rr.build_lists(p, b.boxes)
+    F0, E0, W0 = rr.forces(p)
+    F0, E0 = F0.clone(), E0.clone()
+    F = torch.empty_like(F0)
+    E = torch.empty_like(E0)
+    Wb = torch.empty_like(W0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rr.build_lists(p, b.boxes, wait=False)
+        for _ in range(3):
+            rr.forces(p, out=F, energy=E, virial=Wb)
+    for _ in range(3):
+        F.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert rr.check_lists()
+        assert torch.equal(F, F0) and torch.equal(E, E0)
+    rr.close()

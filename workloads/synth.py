@@ -484,6 +484,117 @@ def perturbed_frames(base: System, n_frames: int = 64, sigma: float = 0.05,
     return out
 
 
+# Types of the mixed propane/neopentane liquids: 0 propane CH3, 1 propane
+# middle atom (hybrid), 2 neopentane CH3, 3 neopentane central C (hybrid).
+MIXED_EPS_FG = np.array([0.195, 0.195, 1.0074 * ZJ, 0.3474 * ZJ])
+MIXED_SIG_FG = np.array([3.75, 3.75, 3.960, 3.800])
+MIXED_EPS_CG = np.array([0.0, 1.0, 0.0, 21.133 * ZJ])
+MIXED_SIG_CG = np.array([4.6, 4.6, 3.942, 3.942])
+
+
+def mixed_liquid(seed: int, n_atoms: int, density: float, p_neopentane: float = 0.5,
+                 skin: float = 1.5, precision: int = 32, jitter: float = 0.1,
+                 name: str = "mixed_liquid") -> System:
+    """A liquid of propane- and neopentane-like molecules in random order
+    (each molecule neopentane with probability p_neopentane) on a cubic
+    lattice, random orientations, N(0, jitter^2) noise, at least n_atoms
+    atoms at the given density.  Geometric mixing; intramolecular pairs
+    excluded."""
+    rng = np.random.default_rng(seed)
+    kinds = []
+    atoms = 0
+    while atoms < n_atoms:
+        k = bool(rng.random() < p_neopentane)
+        kinds.append(k)
+        atoms += 5 if k else 3
+    kinds = np.array(kinds)
+    n_mol = len(kinds)
+    box_len = (atoms / density) ** (1.0 / 3.0)
+    n_side = int(np.ceil(n_mol ** (1.0 / 3.0) - 1e-9))
+    a = box_len / n_side
+    m = np.arange(n_mol)
+    site = np.stack([m // (n_side * n_side), (m // n_side) % n_side, m % n_side], 1)
+    centres = (site + 0.5) * a
+    rot = random_rotations(rng, n_mol)
+    tp, tn = propane_template(), neopentane_template()
+    pos, types, mol = [], [], []
+    for k in range(n_mol):
+        tpl = tn if kinds[k] else tp
+        pos.append(centres[k] + tpl @ rot[k].T)
+        types.append([3, 2, 2, 2, 2] if kinds[k] else [0, 1, 0])
+        mol.append(np.full(tpl.shape[0], k))
+    pos = np.concatenate(pos)
+    if jitter > 0:
+        pos = pos + rng.normal(scale=jitter, size=pos.shape)
+    box = np.full(3, box_len)
+    n = pos.shape[0]
+    eo, ei = _csr_empty(n)
+    cut = dict(RELRES_CUTOFFS, skin=skin)
+    return System(
+        name=name, pos=wrap(pos, box), box=box, types=np.concatenate(types).astype(np.int32),
+        mol=np.concatenate(mol).astype(np.int32), excl_offsets=eo, excl_idx=ei,
+        exclude_same_mol=True, eps_fg=MIXED_EPS_FG.copy(), sig_fg=MIXED_SIG_FG.copy(),
+        eps_cg=MIXED_EPS_CG.copy(), sig_cg=MIXED_SIG_CG.copy(), mix=MIX_GEOMETRIC,
+        precision=precision, meta=dict(seed=seed, n_mol=n_mol, density=density), **cut)
+
+
+@dataclass
+class Batch:
+    """Replica systems that share one parameter set, concatenated in order.
+
+    ``systems[s]`` is replica s alone; ``whole`` holds the concatenated atoms
+    (molecule ids made unique across replicas, box of replica 0) for the
+    topology call; ``offsets`` (nsys + 1) and ``boxes`` (nsys, 3) describe
+    the replicas."""
+    systems: list
+    offsets: np.ndarray
+    boxes: np.ndarray
+    whole: System
+
+    @property
+    def nsys(self) -> int:
+        return len(self.systems)
+
+
+def batch_of(systems: list) -> Batch:
+    sizes = [s.n for s in systems]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    mol_base = np.concatenate([[0], np.cumsum([int(s.mol.max()) + 1 if s.n else 0
+                                               for s in systems])])
+    s0 = systems[0]
+    n = int(offsets[-1])
+    eo, ei = _csr_empty(n)
+    whole = s0.replace(
+        name="batch", pos=np.concatenate([s.pos for s in systems]),
+        types=np.concatenate([s.types for s in systems]).astype(np.int32),
+        mol=np.concatenate([s.mol + mol_base[k] for k, s in enumerate(systems)]).astype(np.int32),
+        excl_offsets=eo, excl_idx=ei, meta=dict(nsys=len(systems)))
+    return Batch(systems=systems, offsets=offsets,
+                 boxes=np.stack([s.box for s in systems]), whole=whole)
+
+
+def replica_batch(seed: int = 0, n_systems: int = 256, min_atoms: int = 300,
+                  max_atoms: int = 30000, total_atoms: int = 1_200_000,
+                  dmin: float = 0.0080, dmax: float = 0.0100, skin: float = 1.5,
+                  precision: int = 32) -> Batch:
+    """Replicas of uneven size: sizes log-uniform in [min_atoms, max_atoms]
+    rescaled (and clipped) towards total_atoms, densities uniform in
+    [dmin, dmax], each a mixed propane/neopentane liquid with its own
+    neopentane fraction.  The 1.5 A skin keeps the smallest box (300 atoms at
+    0.0100 / A^3, L = 31.07 A) above twice the site-list radius."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(min_atoms), np.log(max_atoms), n_systems))
+    for _ in range(20):
+        sizes = np.clip(sizes * total_atoms / sizes.sum(), min_atoms, max_atoms)
+    dens = rng.uniform(dmin, dmax, n_systems)
+    pneo = rng.uniform(0.0, 1.0, n_systems)
+    seeds = rng.integers(0, 2 ** 31, n_systems)
+    systems = [mixed_liquid(int(seeds[k]), int(sizes[k]), float(dens[k]), float(pneo[k]),
+                            skin=skin, precision=precision, name=f"replica{k}")
+               for k in range(n_systems)]
+    return batch_of(systems)
+
+
 WORKLOADS = {
     "propane_1500": lambda seed=0: propane_liquid(seed),
     "neopentane_20480": lambda seed=0: neopentane_liquid(seed),
