@@ -269,6 +269,137 @@ def grad_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_bench(args):
+    """Batching workload: 256 replicas of 300-18000 atoms (1.2 M atoms),
+    mixed propane/neopentane liquids at 0.0080-0.0100 atoms/A^3, each with
+    its own box.  Batched: one context for all replicas; every cycle (a list
+    rebuild and `rebuild_every` force calls with energy and virial per
+    replica) is one HIP graph replay.  Sequential: one context per replica,
+    the same cycle launched replica after replica."""
+    import torch
+    import workloads as w
+    b = w.replica_batch(args.seed)
+    n = b.whole.n
+    steps, every = args.steps, args.rebuild_every
+    cycles = max(1, steps // every)
+    pos = torch.from_numpy(b.whole.pos).cuda()
+    log(f"[bench] batch: {b.nsys} replicas, {n} atoms, {cycles} cycles of 1 build + {every} force calls")
+
+    rr = make(b.whole, 32, args.pair_math)
+    rr.set_systems(b.offsets)
+    rr.build_lists(pos, b.boxes)
+    F = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    E = torch.empty((b.nsys, 3), dtype=torch.float64, device="cuda")
+    W = torch.empty((b.nsys, 6), dtype=torch.float64, device="cuda")
+    rr.forces(pos, out=F, energy=E, virial=W)
+    torch.cuda.synchronize()
+
+    def capture():
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            rr.build_lists(pos, b.boxes, wait=False)
+            for _ in range(every):
+                rr.forces(pos, out=F, energy=E, virial=W)
+        return g, rr.generation()
+
+    g, gen = capture()
+    redone = 0
+
+    def cycle():
+        nonlocal g, gen, redone
+        g.replay()
+        torch.cuda.synchronize()
+        while not rr.check_lists():            # rows grew: new buffers, new graph
+            redone += 1
+            rr.build_lists(pos, b.boxes)
+            g, gen = capture()
+            g.replay()
+            torch.cuda.synchronize()
+
+    for _ in range(2):
+        cycle()
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        cycle()
+    dt_b = time.perf_counter() - t0
+    st = rr.stats()
+    # force launch alone, graph of back-to-back launches
+    fg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(fg):
+        for _ in range(10):
+            rr.forces(pos, out=F, energy=E, virial=W)
+    fg.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        fg.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    force_us = e0.elapsed_time(e1) * 1e3 / 100
+    rr.close()
+
+    # sequential: one context per replica
+    ctxs = []
+    for k, s in enumerate(b.systems):
+        c = make(s, 32, args.pair_math)
+        p = pos[int(b.offsets[k]):int(b.offsets[k + 1])]
+        c.build_lists(p, s.box)
+        ctxs.append((c, p, s.box, torch.empty((s.n, 3), dtype=torch.float32, device="cuda"),
+                     torch.empty(3, dtype=torch.float64, device="cuda"),
+                     torch.empty(6, dtype=torch.float64, device="cuda")))
+
+    def seq_cycle():
+        for c, p, box, Fk, Ek, Wk in ctxs:
+            c.build_lists(p, box, wait=False)
+            for _ in range(every):
+                c.forces(p, out=Fk, energy=Ek, virial=Wk)
+        for c, p, box, *_ in ctxs:
+            if not c.check_lists():
+                c.build_lists(p, box)
+        torch.cuda.synchronize()
+
+    seq_cycle()
+    t0 = time.perf_counter()
+    seq_cycles = max(1, cycles // 4)
+    for _ in range(seq_cycles):
+        seq_cycle()
+    dt_s = (time.perf_counter() - t0) * cycles / seq_cycles
+    for c, *_ in ctxs:
+        c.close()
+
+    value = n * cycles * every / dt_b
+    seq = n * cycles * every / dt_s
+    fb = 4
+    abytes = algorithmic_bytes(st, fb)
+    achieved = abytes / (force_us * 1e-6) / 1e9
+    log(f"[bench] batch: {dt_b * 1e3 / (cycles * every):.4f} ms/step batched, "
+        f"{dt_s * 1e3 / (cycles * every):.4f} ms/step sequential; force launch {force_us:.1f} us")
+    out = {
+        "metric": "RelRes atom-steps/s, 256 batched replicas (1.2 M atoms) in one launch per step, "
+                  "1 MI355X",
+        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": cycles * every,
+        "warmup": 2 * every, "ms_per_step": dt_b * 1e3 / (cycles * every),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "replica_batch: 256 mixed propane/neopentane liquids, "
+                               "300-18000 atoms, 0.0080-0.0100 atoms/A^3", "atoms": n,
+                   "replicas": b.nsys, "skin_A": b.whole.skin, "rebuild_every": every,
+                   "forces": "fp32", "energy_virial": "fp64 per replica",
+                   "parallelism": "single GPU",
+                   "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)"},
+        "sequential": {"value": seq, "ms_per_step": dt_s * 1e3 / (cycles * every),
+                       "what": "one context per replica, launched replica after replica"},
+        "speedup_vs_sequential": value / seq,
+        "builds_redone": redone,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_forces",
+                     "kernel_us": force_us, "algorithmic_bytes_per_launch": abytes},
+        "list_entries": st["atom_entries"] + st["site_entries"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +420,9 @@ def main():
                     help="run the differentiation workload instead (forward + backward over "
                          "perturbed frames) and print its line")
     ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--batch", action="store_true",
+                    help="run the batching workload (256 replicas in one launch per step) "
+                         "instead and print its line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="finish with 5 device-to-device copies of this many MiB (a kernel "
                          "of known traffic for scaling HBM byte counters)")
@@ -308,6 +442,9 @@ def main():
     torch.cuda.set_device(0)
     if args.grad:
         grad_bench(args)
+        return
+    if args.batch:
+        batch_bench(args)
         return
     s = w.WORKLOADS[args.workload](args.seed)
     precision = s.precision
