@@ -6,7 +6,9 @@ with the HIP library.  The arithmetic lives in ``relres_oracle.c`` (plain C,
 FP64, no FMA contraction); this module only marshals numpy arrays.
 
 Every function follows a passage of arXiv:2104.10231:
-  setup_table   -- mixing (Sec. 2.3), Eq. 14, Eqs. 7/8 solved numerically, Eq. 9
+  setup_table   -- mixing (Sec. 2.3, Sec. 2.5 mix keyword), per-type-pair
+                   distances (Sec. 2.5, Sec. 3.4), Eq. 14, Eqs. 7/8 solved
+                   numerically, Eq. 9 with the Sec. 2.5 shift keyword
   pair          -- Eq. 20, case by case
   compute       -- Eq. 3 energy, forces, pair virial (brute force, all pairs)
   pairs         -- the two neighbour pair sets (Sec. 2.6 lists)
@@ -24,9 +26,10 @@ import numpy as np
 from . import build as _build
 
 _LIB = None
-REC = 22   # doubles per type-pair record
+REC = 27   # doubles per type-pair record
 # record field offsets
 EPS_FG, SIG_FG, EPS_CG, SIG_CG, FG_SM, CG_SP, CG_CM, G_CM, G_SP, G_SM = 0, 1, 2, 3, 4, 9, 14, 19, 20, 21
+CUT, G_OUT = 22, 26   # the pair's r_s-, r_s+, r_c-, r_c+; constant of Eq. 20 cases 3-4
 
 _d = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _i = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -42,13 +45,14 @@ def lib():
         L.oracle_lj.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _d]
         L.oracle_solve_poly.argtypes = [ctypes.c_int, ctypes.c_double, _d, _d]
         L.oracle_solve_poly.restype = ctypes.c_int
-        L.oracle_setup.argtypes = [ctypes.c_int, _d, _d, _d, _d, ctypes.c_int, _d, _d]
+        L.oracle_setup.argtypes = [ctypes.c_int, _d, _d, _d, _d, ctypes.c_int, _d,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _d]
         L.oracle_setup.restype = ctypes.c_int
-        L.oracle_pair_vec.argtypes = [_d, _d, ctypes.c_int, _d, _d, _d,
+        L.oracle_pair_vec.argtypes = [_d, ctypes.c_int, _d, _d, _d,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_wrap.argtypes = [ctypes.c_int, _d, _d, _d]
         L.oracle_compute.argtypes = [ctypes.c_int, _d, _d, _i, _i, ctypes.c_int,
-                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _d, _d,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _d,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                      _d, _d, _d]
         L.oracle_compute.restype = ctypes.c_int
@@ -59,7 +63,8 @@ def lib():
         L.oracle_pairs.restype = ctypes.c_long
         L.oracle_grad.argtypes = [ctypes.c_int, _d, _d, _i, _i, ctypes.c_int,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _d, _d, _d, _d,
-                                  ctypes.c_int, _d, _d, ctypes.c_double, _d, _d]
+                                  ctypes.c_int, _d, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                  _d, ctypes.c_double, _d, _d]
         L.oracle_grad.restype = ctypes.c_int
         assert L.oracle_record_size() == REC
         _LIB = L
@@ -79,7 +84,16 @@ def _ptr(a):
 
 
 def cutoffs(sys) -> np.ndarray:
+    """The global distances r_s-, r_s+, r_c-, r_c+."""
     return np.array([sys.rs_in, sys.rs_out, sys.rc_in, sys.rc_out], np.float64)
+
+
+def _cut_args(sys):
+    ct = getattr(sys, "cut_type", None)
+    cp = getattr(sys, "cut_pair", None)
+    ct = None if ct is None else _f64(ct).reshape(sys.ntypes, 4)
+    cp = None if cp is None else _f64(cp).reshape(sys.ntypes, sys.ntypes, 4)
+    return ct, cp, int(bool(getattr(sys, "shift", True)))
 
 
 def lj(eps, sig, r):
@@ -99,11 +113,14 @@ def solve_poly(kind: int, dr: float, u3) -> np.ndarray:
 
 
 def setup_table(sys) -> np.ndarray:
-    """(ntypes, ntypes, REC) table of mixed parameters, gammas and Gammas."""
+    """(ntypes, ntypes, REC) table of mixed parameters, distances, gammas and
+    Gammas."""
     nt = sys.ntypes
     tab = np.zeros(nt * nt * REC)
+    ct, cp, shift = _cut_args(sys)
     rc = lib().oracle_setup(nt, _f64(sys.eps_fg), _f64(sys.sig_fg), _f64(sys.eps_cg),
-                            _f64(sys.sig_cg), int(sys.mix), cutoffs(sys), tab)
+                            _f64(sys.sig_cg), int(sys.mix), cutoffs(sys), _ptr(ct), _ptr(cp),
+                            shift, tab)
     if rc == -1:
         raise ValueError("cutoffs must satisfy r_s- <= r_s+ <= r_c- <= r_c+")
     if rc:
@@ -111,13 +128,14 @@ def setup_table(sys) -> np.ndarray:
     return tab.reshape(nt, nt, REC)
 
 
-def pair(rec, cut, r):
-    """Eq. 20 for distances r: returns (u, du/dr, case index 1..5, e_fg, e_cg)."""
+def pair(rec, r):
+    """Eq. 20 for distances r with one record (its own distances): returns
+    (u, du/dr, case index 1..5, e_fg, e_cg)."""
     r = _f64(np.atleast_1d(r))
     m = r.shape[0]
     u, du, efg, ecg = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)
     which = np.zeros(m, np.int32)
-    lib().oracle_pair_vec(_f64(rec), _f64(cut), m, r, u, du, _ptr(which), _ptr(efg), _ptr(ecg))
+    lib().oracle_pair_vec(_f64(rec), m, r, u, du, _ptr(which), _ptr(efg), _ptr(ecg))
     return u, du, which, efg, ecg
 
 
@@ -152,7 +170,7 @@ def compute(sys, pos=None, nthreads: int = 0, sel=None, table=None):
     E, W = np.zeros(3), np.zeros(6)
     rc = lib().oracle_compute(n, pos, _f64(sys.box), _i32(sys.types), _i32(sys.mol),
                               int(bool(sys.exclude_same_mol)), _ptr(eo), _ptr(ei),
-                              sys.ntypes, _f64(tab.reshape(-1)), cutoffs(sys),
+                              sys.ntypes, _f64(tab.reshape(-1)),
                               int(nthreads), 0 if sel is None else len(sel), _ptr(sel),
                               F, E, W)
     if rc:
@@ -173,11 +191,12 @@ def grad(sys, g, e_bar: float = 0.0, pos=None):
     eo, ei = _excl(sys)
     dtheta = np.zeros(4 * sys.ntypes)
     dpos = np.zeros((n, 3))
+    ct, cp, shift = _cut_args(sys)
     rc = lib().oracle_grad(n, pos, _f64(sys.box), _i32(sys.types), _i32(sys.mol),
                            int(bool(sys.exclude_same_mol)), _ptr(eo), _ptr(ei), sys.ntypes,
                            _f64(sys.eps_fg), _f64(sys.sig_fg), _f64(sys.eps_cg), _f64(sys.sig_cg),
-                           int(sys.mix), cutoffs(sys), _f64(np.asarray(g).reshape(n, 3)),
-                           float(e_bar), dtheta, dpos)
+                           int(sys.mix), cutoffs(sys), _ptr(ct), _ptr(cp), shift,
+                           _f64(np.asarray(g).reshape(n, 3)), float(e_bar), dtheta, dpos)
     if rc:
         raise ValueError(f"oracle_grad failed ({rc})")
     return dtheta.reshape(4, sys.ntypes), dpos
@@ -187,14 +206,26 @@ def hybrid_flags(sys) -> np.ndarray:
     return (np.asarray(sys.eps_cg) > 0.0).astype(np.int32)
 
 
+def list_radii(sys, table=None):
+    """Outer distances the two lists are built for: the largest r_s+ over all
+    type pairs, and the largest r_c+ over hybrid-hybrid pairs (over all pairs
+    when there is none)."""
+    tab = setup_table(sys) if table is None else table
+    h = hybrid_flags(sys).astype(bool)
+    hh = h[:, None] & h[None, :]
+    rso = float(tab[:, :, CUT + 1].max())
+    rco = float(tab[:, :, CUT + 3][hh].max()) if hh.any() else float(tab[:, :, CUT + 3].max())
+    return rso, rco
+
+
 def pairs(sys, which: int, pos=None, rows=None):
-    """Neighbour pair set: which=0 atom list (r < r_s+ + skin), which=1 site
-    list (hybrid pairs, r < r_c+ + skin).  Returns an (M,2) int32 array of
-    (i, j), i < j, sorted; with ``rows`` the full ordered rows (i, j != i) of
-    the selected atoms."""
+    """Neighbour pair set: which=0 atom list (r < largest r_s+ + skin),
+    which=1 site list (hybrid pairs, r < largest hybrid r_c+ + skin).  Returns
+    an (M,2) int32 array of (i, j), i < j, sorted; with ``rows`` the full
+    ordered rows (i, j != i) of the selected atoms."""
     pos = _f64(sys.pos if pos is None else pos)
     eo, ei = _excl(sys)
-    r_out = sys.rs_out if which == 0 else sys.rc_out
+    r_out = list_radii(sys)[which]
     n = pos.shape[0]
     rsel = None if rows is None else _i32(rows)
     args = (n, pos, _f64(sys.box), _i32(sys.types), hybrid_flags(sys), _i32(sys.mol),

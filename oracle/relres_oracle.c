@@ -10,14 +10,21 @@
  * What it computes (paper: "Relative Resolution: A Computationally Efficient
  * Implementation in LAMMPS", arXiv:2104.10231):
  *   - per type pair: mixed FG/CG LJ parameters (Sec. 2.3, geometric mixing as
- *     stated there, or Lorentz-Berthelot), with the CG energy set to zero
- *     whenever a site is ordinary (Eq. 14);
+ *     stated there, Lorentz-Berthelot, or the sixth-power rule: the mixing
+ *     rules the pair_modify mix keyword selects, Sec. 2.5), with the CG energy
+ *     set to zero whenever a site is ordinary (Eq. 14);
+ *   - per type pair: the four distances r_s-, r_s+, r_c-, r_c+ (Sec. 2.5: a
+ *     global set, optionally overridden per type and mixed for unlike types
+ *     with the same rule as sigma, as the geometric r_s of Sec. 3.4, or given
+ *     per type pair outright);
  *   - the three smoothing polynomials of Eq. 16 obtained by SOLVING the
  *     boundary-condition systems of Eq. 7 (f_{s-}^{FG} at r_s-, f_{c-}^{CG} at
  *     r_c-) and Eq. 8 (f_{s+}^{CG} at r_s+) as 5x5 linear systems by Gaussian
  *     elimination; the closed forms of Eqs. 17/18 are deliberately NOT used
  *     here (the tests compare the two);
- *   - the shifting constants of Eq. 9;
+ *   - the shifting constants of Eq. 9, with the pair_modify shift option of
+ *     Sec. 2.5 (shift no: Gamma_c- is zero where Eq. 20 subtracts it on its
+ *     own, while Gamma_s+ and Gamma_s- keep their Eq. 9 values);
  *   - the pair potential of Eq. 20 evaluated directly, case by case;
  *   - the total energy of Eq. 3 as a sum over all non-excluded pairs i<j of a
  *     periodic orthorhombic box (minimum image), forces F_i = -dE/dx_i and the
@@ -45,6 +52,18 @@
  *       w = x - L*floor(x/L); if w < 0: w += L; if w >= L: w -= L;
  *       if w < 0 or w >= L: w = 0
  *   - An excluded pair loses both its FG and its CG part.
+ *   - shift no: the paper states that the keyword acts on Gamma_c- alone and
+ *     leaves Gamma_s+- untouched.  Read literally, cases 3 and 4 of Eq. 20
+ *     subtract nothing, while cases 1 and 2 subtract Gamma_s- and Gamma_s+ as
+ *     defined by Eq. 9 (which contain f_c-^CG(Dr_c)).  The potential then
+ *     jumps by Gamma_c- at r_s+ and at r_c+; forces do not change.
+ *   - Per-type distances of unlike types are mixed with the sigma rule
+ *     (geometric, arithmetic or sixth-power mean of the two types' values),
+ *     each of the four distances on its own; like types keep their own.
+ *   - Sixth-power mixing: sigma_ab = ((sigma_a^6 + sigma_b^6)/2)^(1/6),
+ *     eps_ab = 2 sqrt(eps_a eps_b) sigma_a^3 sigma_b^3 / (sigma_a^6 + sigma_b^6).
+ *   - Neighbour pair sets use one radius per list: the largest r_s+ (atom
+ *     list) or the largest hybrid-pair r_c+ (site list) plus the skin.
  *
  * Build: gcc -O2 -std=c99 -fPIC -shared -fopenmp -ffp-contract=off -lm
  */
@@ -60,11 +79,14 @@
  *   4..8   gamma_{m-}^{FG} (m = 0..4), f_{s-}^{FG}, delta = r - r_s-
  *   9..13  gamma_{m+}^{CG} (m = 0..4), f_{s+}^{CG}, delta = r - r_s-
  *   14..18 gamma_{m-}^{CG} (m = 0..4), f_{c-}^{CG}, delta = r - r_c-
- *   19 Gamma_{c-}  20 Gamma_{s+}  21 Gamma_{s-}
+ *   19 Gamma_{c-} (Eq. 9)  20 Gamma_{s+}  21 Gamma_{s-}
+ *   22..25 r_s-, r_s+, r_c-, r_c+ of this type pair
+ *   26 the constant cases 3 and 4 of Eq. 20 subtract: Gamma_{c-}, or 0
+ *      under shift no
  */
-#define OR_REC 22
+#define OR_REC 27
 enum { R_EPS_FG = 0, R_SIG_FG, R_EPS_CG, R_SIG_CG, R_FG_SM = 4, R_CG_SP = 9,
-       R_CG_CM = 14, R_G_CM = 19, R_G_SP = 20, R_G_SM = 21 };
+       R_CG_CM = 14, R_G_CM = 19, R_G_SP = 20, R_G_SM = 21, R_CUT = 22, R_G_OUT = 26 };
 
 int oracle_record_size(void) { return OR_REC; }
 
@@ -157,30 +179,56 @@ static double dpoly(const double g[5], double d)
     return g[1] + 2.0 * g[2] * d + 3.0 * g[3] * d * d + 4.0 * g[4] * d * d * d;
 }
 
+/* Mixing rules (Sec. 2.3; Sec. 2.5 mix keyword).  mix: 0 geometric (eps and
+ * sigma geometric means), 1 Lorentz-Berthelot (eps geometric, sigma
+ * arithmetic), 2 sixth-power (see the readings above).                     */
+static double mix_sigma(int mix, double a, double b)
+{
+    if (mix == 1) return 0.5 * (a + b);
+    if (mix == 2) return pow(0.5 * (pow(a, 6.0) + pow(b, 6.0)), 1.0 / 6.0);
+    return sqrt(a * b);
+}
+
+static double mix_eps(int mix, double ea, double eb, double sa, double sb)
+{
+    if (mix == 2) {
+        double sa3 = sa * sa * sa, sb3 = sb * sb * sb;
+        return 2.0 * sqrt(ea * eb) * sa3 * sb3 / (sa3 * sa3 + sb3 * sb3);
+    }
+    return sqrt(ea * eb);
+}
+
 /* Build the per-type-pair table (ntypes*ntypes records of OR_REC doubles).
- * mix: 0 geometric (eps and sigma geometric means, Sec. 2.3), 1 Lorentz-
- * Berthelot (eps geometric, sigma arithmetic).  A type is hybrid iff its CG
- * energy parameter is positive; ordinary-involving pairs get eps_CG = 0
- * (Eq. 14).  cut = {r_s-, r_s+, r_c-, r_c+}.  Returns 0, or -1 when the cutoff
- * ordering r_s- <= r_s+ <= r_c- <= r_c+ is violated, -2 on a singular solve. */
+ * A type is hybrid iff its CG energy parameter is positive; ordinary-involving
+ * pairs get eps_CG = 0 (Eq. 14).  Distances of a pair: cut_pair[(a*ntypes +
+ * b)*4 + k] if cut_pair is given, else cut_type[a*4 + k] for like types and
+ * their mix for unlike ones if cut_type is given, else cut[k] (k = 0..3:
+ * r_s-, r_s+, r_c-, r_c+).  shift = 0 selects pair_modify shift no.
+ * Returns 0, or -1 when a pair violates r_s- <= r_s+ <= r_c- <= r_c+, -2 on
+ * a singular solve.                                                          */
 int oracle_setup(int ntypes, const double *eps_fg, const double *sig_fg,
                  const double *eps_cg, const double *sig_cg, int mix,
-                 const double cut[4], double *table)
+                 const double cut[4], const double *cut_type, const double *cut_pair,
+                 int shift, double *table)
 {
-    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
-    if (!(0.0 <= rsi && rsi <= rso && rso <= rci && rci <= rco)) return -1;
-    double Ds = rso - rsi, Dc = rco - rci;
     for (int a = 0; a < ntypes; ++a)
         for (int b = 0; b < ntypes; ++b) {
             double *R = table + (size_t)(a * ntypes + b) * OR_REC;
             memset(R, 0, sizeof(double) * OR_REC);
-            R[R_EPS_FG] = sqrt(eps_fg[a] * eps_fg[b]);
-            R[R_SIG_FG] = mix == 0 ? sqrt(sig_fg[a] * sig_fg[b])
-                                   : 0.5 * (sig_fg[a] + sig_fg[b]);
+            for (int k = 0; k < 4; ++k) {
+                if (cut_pair) R[R_CUT + k] = cut_pair[(a * ntypes + b) * 4 + k];
+                else if (cut_type && a == b) R[R_CUT + k] = cut_type[a * 4 + k];
+                else if (cut_type) R[R_CUT + k] = mix_sigma(mix, cut_type[a * 4 + k], cut_type[b * 4 + k]);
+                else R[R_CUT + k] = cut[k];
+            }
+            double rsi = R[R_CUT], rso = R[R_CUT + 1], rci = R[R_CUT + 2], rco = R[R_CUT + 3];
+            if (!(0.0 <= rsi && rsi <= rso && rso <= rci && rci <= rco)) return -1;
+            double Ds = rso - rsi, Dc = rco - rci;
+            R[R_EPS_FG] = mix_eps(mix, eps_fg[a], eps_fg[b], sig_fg[a], sig_fg[b]);
+            R[R_SIG_FG] = mix_sigma(mix, sig_fg[a], sig_fg[b]);
             int hybrid_pair = eps_cg[a] > 0.0 && eps_cg[b] > 0.0;
-            R[R_EPS_CG] = hybrid_pair ? sqrt(eps_cg[a] * eps_cg[b]) : 0.0;
-            R[R_SIG_CG] = mix == 0 ? sqrt(sig_cg[a] * sig_cg[b])
-                                   : 0.5 * (sig_cg[a] + sig_cg[b]);
+            R[R_EPS_CG] = hybrid_pair ? mix_eps(mix, eps_cg[a], eps_cg[b], sig_cg[a], sig_cg[b]) : 0.0;
+            R[R_SIG_CG] = hybrid_pair ? mix_sigma(mix, sig_cg[a], sig_cg[b]) : 0.0;
             double u[3];
             /* f_{s-}^{FG}: switch-off of the FG potential, Eq. 7 at r_s- */
             oracle_lj(R[R_EPS_FG], R[R_SIG_FG], rsi, u);
@@ -197,16 +245,17 @@ int oracle_setup(int ntypes, const double *eps_fg, const double *sig_fg,
             R[R_G_CM] = poly(R + R_CG_CM, Dc);
             R[R_G_SP] = poly(R + R_CG_CM, Dc) + poly(R + R_FG_SM, Ds);
             R[R_G_SM] = poly(R + R_CG_CM, Dc) + poly(R + R_FG_SM, Ds) - poly(R + R_CG_SP, 0.0);
+            R[R_G_OUT] = shift ? R[R_G_CM] : 0.0;
         }
     return 0;
 }
 
-/* Eq. 20, case by case: returns u~(r), stores du~/dr and the case index
- * (1..5) that applied.                                                     */
-double oracle_pair(const double *R, const double cut[4], double r,
-                   double *dudr, int *which)
+/* Eq. 20, case by case, with the record's own distances: returns u~(r),
+ * stores du~/dr and the case index (1..5) that applied.                    */
+double oracle_pair(const double *R, double r, double *dudr, int *which)
 {
-    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    const double *C = R + R_CUT;
+    double rsi = C[0], rso = C[1], rci = C[2], rco = C[3];
     double u[3];
     if (r < rsi) {                                  /* [0, r_s-)     */
         oracle_lj(R[R_EPS_FG], R[R_SIG_FG], r, u);
@@ -225,13 +274,13 @@ double oracle_pair(const double *R, const double cut[4], double r,
         oracle_lj(R[R_EPS_CG], R[R_SIG_CG], r, u);
         if (which) *which = 3;
         *dudr = u[1];
-        return u[0] - R[R_G_CM];
+        return u[0] - R[R_G_OUT];
     }
     if (r < rco) {                                  /* [r_c-, r_c+)  */
         double d = r - rci;
         if (which) *which = 4;
         *dudr = dpoly(R + R_CG_CM, d);
-        return poly(R + R_CG_CM, d) - R[R_G_CM];
+        return poly(R + R_CG_CM, d) - R[R_G_OUT];
     }
     if (which) *which = 5;                          /* [r_c+, inf)   */
     *dudr = 0.0;
@@ -241,10 +290,10 @@ double oracle_pair(const double *R, const double cut[4], double r,
 /* Diagnostic split of Eq. 20 into the part carried by the FG potential and
  * the part carried by the CG potential (their sum is Eq. 20; used only to
  * report the FG/CG energy breakdown).                                       */
-static void pair_split(const double *R, const double cut[4], double r,
-                       double *e_fg, double *e_cg)
+static void pair_split(const double *R, double r, double *e_fg, double *e_cg)
 {
-    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    const double *C = R + R_CUT;
+    double rsi = C[0], rso = C[1], rci = C[2], rco = C[3];
     double Ds = rso - rsi, u[3];
     double fs_end = poly(R + R_FG_SM, Ds);
     if (r < rsi) { oracle_lj(R[R_EPS_FG], R[R_SIG_FG], r, u); *e_fg = u[0] - fs_end; }
@@ -252,8 +301,8 @@ static void pair_split(const double *R, const double cut[4], double r,
     else *e_fg = 0.0;
     if (r < rsi) *e_cg = R[R_CG_SP] - R[R_G_CM];
     else if (r < rso) *e_cg = poly(R + R_CG_SP, r - rsi) - R[R_G_CM];
-    else if (r < rci) { oracle_lj(R[R_EPS_CG], R[R_SIG_CG], r, u); *e_cg = u[0] - R[R_G_CM]; }
-    else if (r < rco) *e_cg = poly(R + R_CG_CM, r - rci) - R[R_G_CM];
+    else if (r < rci) { oracle_lj(R[R_EPS_CG], R[R_SIG_CG], r, u); *e_cg = u[0] - R[R_G_OUT]; }
+    else if (r < rco) *e_cg = poly(R + R_CG_CM, r - rci) - R[R_G_OUT];
     else *e_cg = 0.0;
 }
 
@@ -307,7 +356,7 @@ static int is_excluded(int i, int j, const int *mol, int same_mol,
  * (written to F rows 0..nsel) and E, W are not touched.                    */
 int oracle_compute(int n, const double *pos, const double *box, const int *types,
                    const int *mol, int same_mol, const int *eoff, const int *eidx,
-                   int ntypes, const double *table, const double cut[4],
+                   int ntypes, const double *table,
                    int nthreads, int nsel, const int *sel,
                    double *F, double *E_out, double *W_out)
 {
@@ -330,16 +379,16 @@ int oracle_compute(int n, const double *pos, const double *box, const int *types
             double d[3];
             min_image(w + 3 * i, w + 3 * j, box, d);   /* d = x_j - x_i */
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(r < cut[3])) continue;               /* case 5: nothing */
             const double *R = table + (size_t)(types[i] * ntypes + types[j]) * OR_REC;
+            if (!(r < R[R_CUT + 3])) continue;         /* case 5: nothing */
             double dudr;
-            double e = oracle_pair(R, cut, r, &dudr, NULL);
+            double e = oracle_pair(R, r, &dudr, NULL);
             /* F_i = -dE/dx_i = -u~'(r) (x_i - x_j)/r = +u~'(r) d / r */
             double s = dudr / r;
             fx += s * d[0]; fy += s * d[1]; fz += s * d[2];
             if (j > i) {
                 double efg, ecg;
-                pair_split(R, cut, r, &efg, &ecg);
+                pair_split(R, r, &efg, &ecg);
                 acc[0] += e; acc[1] += efg; acc[2] += ecg;
                 /* W_ab += (x_i - x_j)_a F_ij,b with F_ij = +u~' d / r */
                 double ra[3] = { -d[0], -d[1], -d[2] };
@@ -361,8 +410,9 @@ int oracle_compute(int n, const double *pos, const double *box, const int *types
     return 0;
 }
 
-/* Pair sets.  which = 0: all non-excluded pairs with r2 < (r_s+ + skin)^2;
- * which = 1: non-excluded hybrid-hybrid pairs with r2 < (r_c+ + skin)^2.
+/* Pair sets.  which = 0: all non-excluded pairs with r2 < (r_out + skin)^2;
+ * which = 1: non-excluded hybrid-hybrid pairs with r2 < (r_out + skin)^2
+ * (r_out: the largest r_s+, or the largest hybrid-pair r_c+).
  * Hybrid <=> hybrid_flag[type] != 0.  Pairs are written as (i, j) with i < j,
  * i-major then j ascending, up to `cap` pairs; the return value is the total
  * number of pairs (which may exceed cap).  If `row_sel` is non-NULL, only
@@ -401,12 +451,12 @@ long oracle_pairs(int n, const double *pos, const double *box, const int *types,
 }
 
 /* Evaluate Eq. 20 for a vector of distances with one type-pair record. */
-void oracle_pair_vec(const double *R, const double cut[4], int m, const double *r,
+void oracle_pair_vec(const double *R, int m, const double *r,
                      double *u, double *dudr, int *which, double *e_fg, double *e_cg)
 {
     for (int k = 0; k < m; ++k) {
-        u[k] = oracle_pair(R, cut, r[k], dudr + k, which ? which + k : NULL);
-        if (e_fg && e_cg) pair_split(R, cut, r[k], e_fg + k, e_cg + k);
+        u[k] = oracle_pair(R, r[k], dudr + k, which ? which + k : NULL);
+        if (e_fg && e_cg) pair_split(R, r[k], e_fg + k, e_cg + k);
     }
 }
 
@@ -445,9 +495,10 @@ static double d2poly(const double g[5], double d)
  * coefficients solved from Eqs. 7/8 with the differentiated boundary values,
  * and Eq. 9 applied to them.  The CG part of a pair that is not hybrid-hybrid
  * is zero by Eq. 14 and does not depend on the CG parameters.              */
-static int dparam_record(const double *R, int P, const double cut[4], double *dR)
+static int dparam_record(const double *R, int P, int shift, double *dR)
 {
-    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3];
+    const double *C = R + R_CUT;
+    double rsi = C[0], rso = C[1], rci = C[2], rco = C[3];
     double Ds = rso - rsi, Dc = rco - rci, du[3];
     memset(dR, 0, sizeof(double) * OR_REC);
     if (P < 2) {
@@ -462,14 +513,16 @@ static int dparam_record(const double *R, int P, const double cut[4], double *dR
     dR[R_G_CM] = poly(dR + R_CG_CM, Dc);
     dR[R_G_SP] = poly(dR + R_CG_CM, Dc) + poly(dR + R_FG_SM, Ds);
     dR[R_G_SM] = poly(dR + R_CG_CM, Dc) + poly(dR + R_FG_SM, Ds) - poly(dR + R_CG_SP, 0.0);
+    dR[R_G_OUT] = shift ? dR[R_G_CM] : 0.0;
     return 0;
 }
 
 /* d u~/dP and d u~'/dP at r: Eq. 20 differentiated case by case.           */
-static void pair_dparam(const double *R, const double *dR, int P, const double cut[4],
-                        double r, double *du, double *dup)
+static void pair_dparam(const double *R, const double *dR, int P, double r,
+                        double *du, double *dup)
 {
-    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3], v[3];
+    const double *C = R + R_CUT;
+    double rsi = C[0], rso = C[1], rci = C[2], rco = C[3], v[3];
     if (r < rsi) {
         if (P < 2) {
             lj_dparam(R[R_EPS_FG], R[R_SIG_FG], r, P, v);
@@ -487,15 +540,15 @@ static void pair_dparam(const double *R, const double *dR, int P, const double c
     } else if (r < rci) {
         if (P >= 2 && R[R_EPS_CG] > 0.0) {
             lj_dparam(R[R_EPS_CG], R[R_SIG_CG], r, P - 2, v);
-            *du = v[0] - dR[R_G_CM];
+            *du = v[0] - dR[R_G_OUT];
             *dup = v[1];
         } else {
-            *du = -dR[R_G_CM];
+            *du = -dR[R_G_OUT];
             *dup = 0.0;
         }
     } else if (r < rco) {
         double d = r - rci;
-        *du = poly(dR + R_CG_CM, d) - dR[R_G_CM];
+        *du = poly(dR + R_CG_CM, d) - dR[R_G_OUT];
         *dup = dpoly(dR + R_CG_CM, d);
     } else {
         *du = 0.0;
@@ -504,9 +557,10 @@ static void pair_dparam(const double *R, const double *dR, int P, const double c
 }
 
 /* Second derivative of Eq. 20, case by case. */
-static double pair_d2(const double *R, const double cut[4], double r)
+static double pair_d2(const double *R, double r)
 {
-    double rsi = cut[0], rso = cut[1], rci = cut[2], rco = cut[3], u[3];
+    const double *C = R + R_CUT;
+    double rsi = C[0], rso = C[1], rci = C[2], rco = C[3], u[3];
     if (r < rsi) { oracle_lj(R[R_EPS_FG], R[R_SIG_FG], r, u); return u[2]; }
     if (r < rso) {
         double g[5];
@@ -518,13 +572,32 @@ static double pair_d2(const double *R, const double cut[4], double r)
     return 0.0;
 }
 
-/* Derivatives of one mixed pair parameter with respect to the two per-type
- * values it is mixed from: geometric mean sqrt(a b) or arithmetic mean.     */
-static void mix_grad(int arithmetic, double a, double b, double *da, double *db)
+/* Partial derivatives of a mixed pair (eps_ab, sigma_ab) with respect to
+ * the per-type values of type a (J[0] = d/d eps_a, J[1] = d/d sigma_a):
+ *   geometric:    eps_ab = sqrt(ea eb), sigma_ab = sqrt(sa sb)
+ *   Lorentz-Berthelot: sigma_ab = (sa + sb)/2
+ *   sixth-power:  d eps_ab/d eps_a = eps_ab/(2 ea),
+ *                 d eps_ab/d sa = eps_ab (3/sa - 6 sa^5/(sa^6 + sb^6)),
+ *                 d sigma_ab/d sa = sa^5 / (2 sigma_ab^5).
+ * de[] holds the eps_ab derivatives, ds[] the sigma_ab ones.  The values of
+ * type b follow by swapping the arguments.                                */
+static void mix_jacobian(int mix, double ea, double eb, double sa, double sb,
+                         double de[2], double ds[2])
 {
-    if (arithmetic) { *da = 0.5; *db = 0.5; return; }
-    *da = 0.5 * sqrt(b / a);
-    *db = 0.5 * sqrt(a / b);
+    if (mix == 2) {
+        double s6 = pow(sa, 6.0) + pow(sb, 6.0);
+        double e = 2.0 * sqrt(ea * eb) * sa * sa * sa * sb * sb * sb / s6;
+        double sab = pow(0.5 * s6, 1.0 / 6.0);
+        de[0] = e / (2.0 * ea);
+        de[1] = e * (3.0 / sa - 6.0 * pow(sa, 5.0) / s6);
+        ds[0] = 0.0;
+        ds[1] = pow(sa, 5.0) / (2.0 * pow(sab, 5.0));
+        return;
+    }
+    de[0] = 0.5 * sqrt(eb / ea);
+    de[1] = 0.0;
+    ds[0] = 0.0;
+    ds[1] = mix == 1 ? 0.5 : 0.5 * sqrt(sb / sa);
 }
 
 /* Gradient of J = e_bar * E + sum_i g_i . F_i (E of Eq. 3, F_i = -dE/dx_i)
@@ -543,6 +616,7 @@ int oracle_grad(int n, const double *pos, const double *box, const int *types,
                 const int *mol, int same_mol, const int *eoff, const int *eidx,
                 int ntypes, const double *eps_fg, const double *sig_fg,
                 const double *eps_cg, const double *sig_cg, int mix, const double cut[4],
+                const double *cut_type, const double *cut_pair, int shift,
                 const double *g, double e_bar, double *dtheta, double *dpos)
 {
     size_t np = (size_t)ntypes * ntypes;
@@ -550,10 +624,11 @@ int oracle_grad(int n, const double *pos, const double *box, const int *types,
     double *dtab = (double *)malloc(sizeof(double) * np * 4 * OR_REC);
     double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     if (!table || !dtab || !w) { free(table); free(dtab); free(w); return -3; }
-    int rc = oracle_setup(ntypes, eps_fg, sig_fg, eps_cg, sig_cg, mix, cut, table);
+    int rc = oracle_setup(ntypes, eps_fg, sig_fg, eps_cg, sig_cg, mix, cut, cut_type, cut_pair,
+                          shift, table);
     for (size_t k = 0; rc == 0 && k < np; ++k)
         for (int P = 0; P < 4 && rc == 0; ++P)
-            rc = dparam_record(table + k * OR_REC, P, cut, dtab + (k * 4 + P) * OR_REC);
+            rc = dparam_record(table + k * OR_REC, P, shift, dtab + (k * 4 + P) * OR_REC);
     if (rc) { free(table); free(dtab); free(w); return rc; }
     oracle_wrap(n, pos, box, w);
     memset(dtheta, 0, sizeof(double) * 4 * (size_t)ntypes);
@@ -565,13 +640,13 @@ int oracle_grad(int n, const double *pos, const double *box, const int *types,
             double d[3];
             min_image(w + 3 * i, w + 3 * j, box, d);      /* d = x_j - x_i */
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(r < cut[3])) continue;
             int p = types[i], q = types[j];
             size_t k = (size_t)(p * ntypes + q);
             const double *R = table + k * OR_REC;
+            if (!(r < R[R_CUT + 3])) continue;
             double u1;
-            (void)oracle_pair(R, cut, r, &u1, NULL);
-            double u2 = pair_d2(R, cut, r);
+            (void)oracle_pair(R, r, &u1, NULL);
+            double u2 = pair_d2(R, r);
             double wv[3] = {g[3 * i] - g[3 * j], g[3 * i + 1] - g[3 * j + 1], g[3 * i + 2] - g[3 * j + 2]};
             double wd = wv[0] * d[0] + wv[1] * d[1] + wv[2] * d[2];
             double s = u1 / r;
@@ -581,15 +656,26 @@ int oracle_grad(int n, const double *pos, const double *box, const int *types,
                 dpos[3 * j + c] += gj;
                 dpos[3 * i + c] -= gj;
             }
+            double cP[4];
             for (int P = 0; P < 4; ++P) {
+                cP[P] = 0.0;
                 if (P >= 2 && !(R[R_EPS_CG] > 0.0)) continue;
                 double du, dup;
-                pair_dparam(R, dtab + (k * 4 + P) * OR_REC, P, cut, r, &du, &dup);
-                double cP = e_bar * du + (dup / r) * wd;
-                double da, db;
-                mix_grad((P == 1 || P == 3) && mix == 1, pe[P][p], pe[P][q], &da, &db);
-                dtheta[P * ntypes + p] += cP * da;
-                dtheta[P * ntypes + q] += cP * db;
+                pair_dparam(R, dtab + (k * 4 + P) * OR_REC, P, r, &du, &dup);
+                cP[P] = e_bar * du + (dup / r) * wd;
+            }
+            /* through the mixing rule: (eps, sigma) of the FG pair (P = 0, 1)
+             * and of the CG pair (P = 2, 3) to the per-type values            */
+            for (int part = 0; part < 2; ++part) {
+                if (part == 1 && !(R[R_EPS_CG] > 0.0)) continue;
+                const double *E = pe[2 * part], *S = pe[2 * part + 1];
+                double de[2], ds[2];
+                mix_jacobian(mix, E[p], E[q], S[p], S[q], de, ds);
+                for (int y = 0; y < 2; ++y)
+                    dtheta[(2 * part + y) * ntypes + p] += cP[2 * part] * de[y] + cP[2 * part + 1] * ds[y];
+                mix_jacobian(mix, E[q], E[p], S[q], S[p], de, ds);
+                for (int y = 0; y < 2; ++y)
+                    dtheta[(2 * part + y) * ntypes + q] += cP[2 * part] * de[y] + cP[2 * part + 1] * ds[y];
             }
         }
     free(table); free(dtab); free(w);

@@ -308,7 +308,7 @@ def test_two_atoms_every_regime(r, hyb):
     s = w.two_atoms(r, hybrid=hyb, direction=(1.0, 2.0, -0.5))
     rec = oracle.setup_table(s)[s.types[0], s.types[1]]
     near = np.linspace(max(0.5, r - 0.5), r + 0.5, 201)
-    u, du = oracle.pair(rec, oracle.cutoffs(s), near)[:2]
+    u, du = oracle.pair(rec, near)[:2]
     _check(s, 64, fscale=float(np.abs(du).max()), escale=float(np.abs(u).max()))
 
 

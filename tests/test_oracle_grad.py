@@ -32,9 +32,29 @@ def _system(seed=3, mix=0):
     return s
 
 
-@pytest.mark.parametrize("mix", [0, 1])
-def test_parameter_gradient_matches_central_differences(mix):
-    s = _system(mix=mix)
+def _variant(name):
+    """Pair-style options of Sec. 2.5: mixing rules, shift no, distances per
+    type (mixed for the unlike pair)."""
+    if name == "geometric":
+        return _system(mix=0)
+    if name == "lorentz_berthelot":
+        return _system(mix=1)
+    if name == "sixthpower":
+        return _system(mix=2)
+    if name == "shift_no":
+        return _system().replace(shift=False)
+    if name == "per_type_distances":
+        return _system().replace(cut_type=np.array([[5.3, 5.8, 11.5, 13.5],
+                                                    [6.4, 6.9, 12.0, 14.0]]))
+    raise ValueError(name)
+
+
+VARIANTS = ["geometric", "lorentz_berthelot", "sixthpower", "shift_no", "per_type_distances"]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_parameter_gradient_matches_central_differences(variant):
+    s = _variant(variant)
     rng = np.random.default_rng(7)
     g = rng.normal(size=(s.n, 3))
     e_bar = 0.7
@@ -54,8 +74,9 @@ def test_parameter_gradient_matches_central_differences(mix):
             assert abs(dtheta[P, t] - fd) <= 1e-6 * max(abs(fd), 1e-3), (name, t, dtheta[P, t], fd)
 
 
-def test_position_gradient_matches_central_differences():
-    s = _system()
+@pytest.mark.parametrize("variant", ["geometric", "sixthpower", "per_type_distances"])
+def test_position_gradient_matches_central_differences(variant):
+    s = _variant(variant)
     rng = np.random.default_rng(11)
     g = rng.normal(size=(s.n, 3))
     e_bar = -1.3

@@ -130,25 +130,25 @@ def test_continuity_at_all_boundaries(k):
     s, rec, _ = RECORDS[k]
     cut = oracle.cutoffs(s)
     rr = np.linspace(3.0, 15.0, 4001)
-    u, du, _, _, _ = oracle.pair(rec, cut, rr)
+    u, du, _, _, _ = oracle.pair(rec, rr)
     umax = max(1.0, np.abs(u).max())
     dmax = max(1.0, np.abs(du).max())
     h = 1e-9
     for b in cut:
-        u_lo, du_lo = oracle.pair(rec, cut, b - h)[:2]
-        u_hi, du_hi = oracle.pair(rec, cut, b + h)[:2]
+        u_lo, du_lo = oracle.pair(rec, b - h)[:2]
+        u_hi, du_hi = oracle.pair(rec, b + h)[:2]
         assert abs(u_hi[0] - u_lo[0]) <= 4 * h * dmax + 1e-13 * umax, b
         assert abs(du_hi[0] - du_lo[0]) <= 1e-6 * dmax, b
         # second derivative: one-sided difference quotients of u~'
         h2 = 1e-5
-        left = (oracle.pair(rec, cut, b - h2)[1] - oracle.pair(rec, cut, b - 3 * h2)[1]) / (2 * h2)
-        right = (oracle.pair(rec, cut, b + 3 * h2)[1] - oracle.pair(rec, cut, b + h2)[1]) / (2 * h2)
+        left = (oracle.pair(rec, b - h2)[1] - oracle.pair(rec, b - 3 * h2)[1]) / (2 * h2)
+        right = (oracle.pair(rec, b + 3 * h2)[1] - oracle.pair(rec, b + h2)[1]) / (2 * h2)
         assert abs(left[0] - right[0]) <= 1e-3 * dmax, b
     # u~ vanishes from r_c+ on (Eq. 9 with Gamma_c+ = Gamma_c-)
-    far = oracle.pair(rec, cut, np.array([cut[3], cut[3] + 1e-12, 20.0]))
+    far = oracle.pair(rec, np.array([cut[3], cut[3] + 1e-12, 20.0]))
     assert np.all(far[0] == 0.0) and np.all(far[1] == 0.0)
     # the FG/CG split adds up to Eq. 20
-    uu, _, _, efg, ecg = oracle.pair(rec, cut, rr)
+    uu, _, _, efg, ecg = oracle.pair(rec, rr)
     np.testing.assert_allclose(efg + ecg, uu, rtol=0, atol=1e-12 * umax)
 
 
@@ -157,7 +157,7 @@ def test_ordinary_pairs_vanish_beyond_rs():
     rec = oracle.setup_table(s)[0, 1]      # ordinary-hybrid: eps_CG = 0 (Eq. 14)
     cut = oracle.cutoffs(s)
     r = np.linspace(s.rs_out, 20.0, 500)
-    u, du = oracle.pair(rec, cut, r)[:2]
+    u, du = oracle.pair(rec, r)[:2]
     assert np.all(u == 0.0) and np.all(du == 0.0)
 
 
@@ -168,7 +168,7 @@ def test_textbook_lj_in_fg_core_and_cg_window():
     for a, b in [(0, 0), (0, 1), (1, 1)]:
         eps, sig = np.sqrt(s.eps_fg[a] * s.eps_fg[b]), np.sqrt(s.sig_fg[a] * s.sig_fg[b])
         r = np.linspace(2.5, s.rs_in - 1e-6, 50)
-        u, du, which = oracle.pair(tab[a, b], cut, r)[:3]
+        u, du, which = oracle.pair(tab[a, b], r)[:3]
         assert np.all(which == 1)
         ref = np.array([lj_sym(eps, sig, x) for x in r])
         np.testing.assert_allclose(du, ref[:, 1], rtol=1e-13)
@@ -176,7 +176,7 @@ def test_textbook_lj_in_fg_core_and_cg_window():
                                    atol=1e-12 * np.abs(ref[:, 0]).max())
     eps, sig = 1.0, 4.6
     r = np.linspace(s.rs_out, s.rc_in - 1e-6, 50)
-    u, du, which = oracle.pair(tab[1, 1], cut, r)[:3]
+    u, du, which = oracle.pair(tab[1, 1], r)[:3]
     assert np.all(which == 3)
     ref = np.array([lj_sym(eps, sig, x) for x in r])
     np.testing.assert_allclose(du, ref[:, 1], rtol=1e-13)
@@ -188,7 +188,7 @@ def test_empty_zones_give_truncated_shifted_lj():
     rec = oracle.setup_table(s)[1, 1]
     cut = oracle.cutoffs(s)
     r = np.array([3.0, 4.2, 6.0, 9.999, 10.0, 11.0])
-    u, du = oracle.pair(rec, cut, r)[:2]
+    u, du = oracle.pair(rec, r)[:2]
     uc = lj_sym(0.195, 3.75, 10.0)[0]
     for k, x in enumerate(r):
         if x < 10.0:
@@ -209,7 +209,7 @@ def test_reference_limit_is_smoothed_fg_lj():
     g = eq17(lj_sym(eps, sig, 12.0), 2.0)
     shift = polyval(g, 2.0)
     for x in (3.3, 7.7, 11.9, 12.0, 12.5, 13.99, 14.0):
-        u, du = (q[0] for q in oracle.pair(rec, cut, x)[:2])
+        u, du = (q[0] for q in oracle.pair(rec, x)[:2])
         if x < 12.0:
             ref = lj_sym(eps, sig, x)
             assert u == pytest.approx(ref[0] - shift, rel=1e-12, abs=1e-14)
@@ -255,7 +255,7 @@ def _regimes_hit(s):
     hit = set()
     for i, j in zip(iu[0][keep], iu[1][keep]):
         if r[i, j] < cut[3]:
-            hit.add(int(oracle.pair(tab[s.types[i], s.types[j]], cut, r[i, j])[2][0]))
+            hit.add(int(oracle.pair(tab[s.types[i], s.types[j]], r[i, j])[2][0]))
     return hit
 
 
@@ -334,7 +334,7 @@ def test_exclusions_remove_exactly_the_intramolecular_pairs():
                 i, j = idx[a], idx[b]
                 d = s.pos[i] - s.pos[j]
                 d -= s.box * np.round(d / s.box)
-                intra += oracle.pair(tab[s.types[i], s.types[j]], cut, np.linalg.norm(d))[0][0]
+                intra += oracle.pair(tab[s.types[i], s.types[j]], np.linalg.norm(d))[0][0]
     # the bonded intramolecular terms are ~1e4 each: compare on their scale
     assert E_ex[0] == pytest.approx(E_all[0] - intra, rel=0, abs=1e-13 * abs(E_all[0]))
     # the same exclusions given as explicit CSR lists
@@ -456,7 +456,7 @@ def test_empty_switching_zone_keeps_energy_continuous():
     s = w.two_atoms(5.0).replace(rs_in=6.0, rs_out=6.0)
     rec = oracle.setup_table(s)[1, 1]
     cut = oracle.cutoffs(s)
-    lo, hi = oracle.pair(rec, cut, np.array([6.0 - 1e-10, 6.0]))[0]
+    lo, hi = oracle.pair(rec, np.array([6.0 - 1e-10, 6.0]))[0]
     assert hi == pytest.approx(lo, abs=1e-8)
 
 

@@ -34,6 +34,7 @@ ZJ = 6.02214076e23 * 1e-21 / 4184.0
 
 MIX_GEOMETRIC = 0
 MIX_ARITHMETIC = 1   # Lorentz-Berthelot: geometric eps, arithmetic sigma
+MIX_SIXTHPOWER = 2
 
 # Cutoffs used by every workload (Angstrom): r_s- r_s+ r_c- r_c+ and the skin.
 RELRES_CUTOFFS = dict(rs_in=5.5, rs_out=6.0, rc_in=12.0, rc_out=14.0, skin=2.0)
@@ -61,6 +62,9 @@ class System:
     rc_out: float = 14.0
     skin: float = 2.0
     precision: int = 32
+    shift: bool = True         # pair_modify shift yes / no
+    cut_type: np.ndarray | None = None   # (ntypes, 4) per-type r_s-, r_s+, r_c-, r_c+
+    cut_pair: np.ndarray | None = None   # (ntypes, ntypes, 4) per-type-pair distances
     meta: dict = field(default_factory=dict)
 
     @property
