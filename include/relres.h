@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define RELRES_ABI_VERSION 1
+#define RELRES_ABI_VERSION 2
 
 #define RELRES_OK                   0
 #define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
@@ -56,7 +56,10 @@ extern "C" {
 #define RELRES_ERR_LIST_RETRY     -10  /* asynchronous build overflowed: rows grown, build again */
 
 #define RELRES_MIX_GEOMETRIC   0   /* eps, sigma geometric means (Sec. 2.3)    */
-#define RELRES_MIX_ARITHMETIC  1   /* Lorentz-Berthelot: sigma arithmetic mean */
+#define RELRES_MIX_ARITHMETIC  1   /* Lorentz-Berthelot: eps geometric, sigma arithmetic */
+#define RELRES_MIX_SIXTHPOWER  2   /* sigma_ab = ((sigma_a^6 + sigma_b^6)/2)^(1/6),
+                                      eps_ab = 2 sqrt(eps_a eps_b) sigma_a^3 sigma_b^3
+                                               / (sigma_a^6 + sigma_b^6)          */
 
 #define RELRES_MAX_TYPES      32
 #define RELRES_MAX_ATOMS      (1 << 27)
@@ -69,11 +72,17 @@ extern "C" {
 typedef struct relres_ctx relres_ctx;
 
 /* Parameters of the pair style (Sec. 2.5: pair_style lj/relres r_s- r_s+ r_c-
- * r_c+, pair_coeff per type, pair_modify mix; shift yes is implied: the
- * shifting constants of Eq. 19 are always applied so that u~(r_c+) = 0).
- * Per-type arrays are host pointers of length ntypes, copied by
+ * r_c+, pair_coeff per type with optional distances, pair_modify shift and
+ * mix).  Per-type arrays are host pointers of length ntypes, copied by
  * relres_create.  Mixed pair parameters are formed per type pair with `mix`,
  * for FG and CG alike.  An empty zone (r_- == r_+) is allowed (Sec. 2.5).
+ * Distances: the global r_s-, r_s+, r_c-, r_c+ unless cut_type or cut_pair
+ * is given.  With cut_type, type a keeps its own four distances and an
+ * unlike pair mixes each distance with the sigma rule of `mix` (geometric
+ * mixing gives the switching distance sqrt(r_s,a r_s,b) of Sec. 3.4); with
+ * cut_pair every type pair has its own.  Every pair must satisfy r_s- <=
+ * r_s+ <= r_c- <= r_c+; the atom list is then built at the largest r_s+ and
+ * the site list at the largest r_c+ of a hybrid-hybrid pair (plus the skin).
  * The reference (conventional, all-FG) system of Sec. 2.1 is expressed as
  * r_s- = r_c(inner), r_s+ = r_c- = r_c+ = r_c(outer) with all eps_cg = 0.   */
 typedef struct relres_params {
@@ -90,6 +99,16 @@ typedef struct relres_params {
                                              evaluates pairs in FP64 and accumulates
                                              forces in FP32); energy and virial are
                                              always accumulated in FP64 */
+    int no_shift;                         /* pair_modify shift: 0 = yes (Eq. 19, so
+                                             u~(r_c+) = 0), 1 = no: Gamma_c- is zero
+                                             where cases 3-4 of Eq. 20 subtract it,
+                                             Gamma_s+- keep their Eq. 19 values (the
+                                             energy then jumps by Gamma_c- at r_s+ and
+                                             r_c+; forces are the same) */
+    const double *cut_type;               /* NULL or ntypes x 4 {r_s-, r_s+, r_c-, r_c+} */
+    const double *cut_pair;               /* NULL or ntypes x ntypes x 4, row-major
+                                             [a][b][k], symmetric in a, b; takes
+                                             precedence over cut_type */
 } relres_params;
 
 typedef struct relres_stats {
@@ -107,10 +126,33 @@ typedef struct relres_stats {
 } relres_stats;
 
 /* Create a context.  Validates the cutoff ordering r_s- <= r_s+ <= r_c- <=
- * r_c+ (Sec. 2.5), mixes parameters and computes the smoothing coefficients
- * (Eqs. 17/18) and shifting constants (Eq. 19) in FP64 on the host.
- * Binds the context to the current HIP device.  *out is NULL on failure.    */
+ * r_c+ of every type pair (Sec. 2.5), mixes parameters and computes the
+ * smoothing coefficients (Eqs. 17/18) and shifting constants (Eq. 19) in
+ * FP64 on the host.  Binds the context to the current HIP device.  *out is
+ * NULL on failure.                                                          */
 int relres_create(const relres_params *params, relres_ctx **out);
+
+/* CG parameters from FG ones, the parametrisation of Sec. 2.3 (host only, no
+ * context or device needed).
+ * Eq. 15, one CG site l made of n FG sites with per-site eps_fg[k],
+ * sig_fg[k] (valid when the FG model mixes geometrically):
+ *   B12 = sum_k sqrt(eps_k sig_k^12), B6 = sum_k sqrt(eps_k sig_k^6),
+ *   sigma_l = (B12 / B6)^(1/3), eps_l = B6^4 / B12^2.
+ * Eq. 13, one pair of CG sites from the n FG pair parameters eps_mn[k],
+ * sig_mn[k] of all mu-nu pairs between them (any mixing):
+ *   A12 = sum_k eps_k sig_k^12, A6 = sum_k eps_k sig_k^6,
+ *   sigma_ij = (A12 / A6)^(1/6), eps_ij = A6^2 / A12.
+ * n >= 1; eps >= 0 and sigma > 0 with a positive sum.  Results go to
+ * *eps_cg, *sig_cg (host).                                                   */
+int relres_cg_site_params(int n, const double *eps_fg, const double *sig_fg, double *eps_cg,
+                          double *sig_cg);
+int relres_cg_pair_params(int n, const double *eps_mn, const double *sig_mn, double *eps_cg,
+                          double *sig_cg);
+
+/* Mixed distance of two types under `mix` (the rule applied to cut_type for
+ * unlike pairs): geometric sqrt(a b), arithmetic (a + b)/2, sixth-power
+ * ((a^6 + b^6)/2)^(1/6).  Host only; returns NaN for an unknown rule.      */
+double relres_mix_distance(int mix, double a, double b);
 
 /* Atoms, by type and molecule (Sec. 3.1, data-file Atoms section), and the
  * pairs that do not interact at all (neither FG nor CG part): every pair of

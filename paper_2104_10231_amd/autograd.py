@@ -4,8 +4,9 @@
 (N, 3) and the total energy of Eq. 3 as tensors that carry gradients to the
 positions and to the per-type FG/CG Lennard-Jones parameters.  The forward
 pass is ``relres_forces`` on the pair parameters mixed here with torch
-operations (Sec. 2.3: geometric means, or Lorentz-Berthelot for sigma; CG
-parameters only for hybrid-hybrid pairs, Eq. 14), so torch carries the
+operations (Sec. 2.3: geometric means, Lorentz-Berthelot or the sixth-power
+rule of pair_modify mix; CG parameters only for hybrid-hybrid pairs, Eq. 14),
+so torch carries the
 gradient through the mixing rule; the backward pass is ``relres_backward``,
 a HIP kernel that recomputes every pair term in FP64 and returns dJ/dx and
 dJ/d(pair parameter) for J = e_bar E + sum_i g_i . F_i.  Any loss of the
@@ -24,29 +25,36 @@ from .relres import RelRes
 __all__ = ["mix_pair_tables", "energy_forces"]
 
 
-def _outer_mean(a: torch.Tensor, arithmetic: bool) -> torch.Tensor:
-    if arithmetic:
-        return 0.5 * (a[:, None] + a[None, :])
-    return torch.sqrt(a[:, None] * a[None, :])
+def _mix(eps, sig, mix: int, mask=None):
+    """Mixed (eps_ab, sigma_ab) tables of one family (FG or CG) under the
+    pair_modify mix rule: geometric (0), Lorentz-Berthelot (1) or sixth-power
+    (2).  Entries outside ``mask`` are zero and never enter a square root or
+    a division, so ordinary types (eps_CG = 0) get no infinite gradients."""
+    one = torch.ones((), dtype=eps.dtype, device=eps.device)
+    zero = torch.zeros((), dtype=eps.dtype, device=eps.device)
+    m = torch.ones((eps.shape[0], eps.shape[0]), dtype=torch.bool, device=eps.device) \
+        if mask is None else mask
+    ee = torch.where(m, eps[:, None] * eps[None, :], one)
+    if mix == 2:
+        s3 = sig ** 3
+        s6 = torch.where(m, s3[:, None] ** 2 + s3[None, :] ** 2, one)
+        e = torch.where(m, 2.0 * torch.sqrt(ee) * s3[:, None] * s3[None, :] / s6, zero)
+        s = torch.where(m, (0.5 * s6) ** (1.0 / 6.0), zero)
+        return e, s
+    e = torch.where(m, torch.sqrt(ee), zero)
+    if mix == 1:
+        s = torch.where(m, 0.5 * (sig[:, None] + sig[None, :]), zero)
+    else:
+        s = torch.where(m, torch.sqrt(torch.where(m, sig[:, None] * sig[None, :], one)), zero)
+    return e, s
 
 
 def mix_pair_tables(eps_fg, sig_fg, eps_cg, sig_cg, mix: int, hybrid):
-    """Per-type parameters -> (ntypes, ntypes) pair tables (FG and CG)."""
-    ef = _outer_mean(eps_fg, False)
-    sf = _outer_mean(sig_fg, mix == 1)
+    """Per-type parameters -> (ntypes, ntypes) pair tables (FG and CG); the
+    CG tables only for hybrid-hybrid pairs (Eq. 14)."""
+    ef, sf = _mix(eps_fg, sig_fg, mix)
     h = torch.as_tensor(hybrid, dtype=torch.bool, device=eps_cg.device)
-    hm = h[:, None] & h[None, :]
-    one = torch.ones((), dtype=eps_cg.dtype, device=eps_cg.device)
-    zero = torch.zeros((), dtype=eps_cg.dtype, device=eps_cg.device)
-    # only hybrid-hybrid entries enter the square roots, so ordinary types
-    # (eps_CG = 0) never produce infinite gradients
-    eo = torch.where(hm, eps_cg[:, None] * eps_cg[None, :], one)
-    ec = torch.where(hm, torch.sqrt(eo), zero)
-    if mix == 1:
-        sc = torch.where(hm, 0.5 * (sig_cg[:, None] + sig_cg[None, :]), zero)
-    else:
-        so = torch.where(hm, sig_cg[:, None] * sig_cg[None, :], one)
-        sc = torch.where(hm, torch.sqrt(so), zero)
+    ec, sc = _mix(eps_cg, sig_cg, mix, h[:, None] & h[None, :])
     return ef, sf, ec, sc
 
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <utility>
 #include <vector>
@@ -100,9 +101,26 @@ double poly_at(const double g[5], double d)
     return g[0] + d * (g[1] + d * (g[2] + d * (g[3] + d * g[4])));
 }
 
+// Mixed length (sigma, or a distance of per-type cutoffs) of two types.
 double mix_sigma(int mix, double a, double b)
 {
-    return mix == RELRES_MIX_GEOMETRIC ? std::sqrt(a * b) : 0.5 * (a + b);
+    if (mix == RELRES_MIX_ARITHMETIC) return 0.5 * (a + b);
+    if (mix == RELRES_MIX_SIXTHPOWER) {
+        const double a3 = a * a * a, b3 = b * b * b;
+        return std::pow(0.5 * (a3 * a3 + b3 * b3), 1.0 / 6.0);
+    }
+    return std::sqrt(a * b);
+}
+
+// Mixed energy of two types; the sixth-power rule keeps eps sigma^6 a
+// geometric mean, so it depends on the sigmas too.
+double mix_eps(int mix, double ea, double eb, double sa, double sb)
+{
+    if (mix == RELRES_MIX_SIXTHPOWER) {
+        const double a3 = sa * sa * sa, b3 = sb * sb * sb;
+        return 2.0 * std::sqrt(ea * eb) * a3 * b3 / (a3 * a3 + b3 * b3);
+    }
+    return std::sqrt(ea * eb);
 }
 
 // u, u', u'' (wrt = 0) or their derivatives with respect to eps (wrt = 1) or
@@ -143,9 +161,10 @@ void fg_part(PairCoef<double>& k, double e, double s, int wrt, double rsi, doubl
 }
 
 // CG part: LJ constants of Eq. 12, f_s+^CG (Eq. 18), f_c-^CG (Eq. 17) and
-// Gamma_c- (Eq. 19), or their derivatives.
+// Gamma_c- (Eq. 19), or their derivatives.  Cases 1-2 of Eq. 20 always carry
+// Gamma_c- (inside Gamma_s+-); cases 3-4 carry it unless no_shift.
 void cg_part(PairCoef<double>& k, double e, double s, int wrt, double rso, double rci, double Ds,
-             double Dc)
+             double Dc, int no_shift)
 {
     k.cg_c12 = power_term(48.0, e, s, 12, wrt);
     k.cg_c6 = power_term(24.0, e, s, 6, wrt);
@@ -157,7 +176,19 @@ void cg_part(PairCoef<double>& k, double e, double s, int wrt, double rso, doubl
     k.sp_g3 = g[3];
     k.sp_g4 = g[4];
     switch_off(lj3_wrt(e, s, rci, wrt), Dc, k.cm_g);
-    k.cm_shift = poly_at(k.cm_g, Dc);
+    k.sp_shift = poly_at(k.cm_g, Dc);
+    k.cm_shift = no_shift ? 0.0 : k.sp_shift;
+}
+
+// Distances of one type pair with their squares.
+template <typename S>
+Cutoffs<S> cutoffs_of(const double* r4)
+{
+    Cutoffs<S> c;
+    c.rsi = (S)r4[0]; c.rso = (S)r4[1]; c.rci = (S)r4[2]; c.rco = (S)r4[3];
+    c.rsi2 = (S)(r4[0] * r4[0]); c.rso2 = (S)(r4[1] * r4[1]);
+    c.rci2 = (S)(r4[2] * r4[2]); c.rco2 = (S)(r4[3] * r4[3]);
+    return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -219,13 +250,16 @@ uint32_t spread3(uint32_t v)
 
 struct relres_ctx {
     int device = 0;
-    double rsi = 0, rso = 0, rci = 0, rco = 0, skin = 0;
-    int ntypes = 0, mix = 0, precision = 64, pair_math = 64;
+    double skin = 0;
+    std::vector<double> dist;         // [pair][4]: r_s-, r_s+, r_c-, r_c+ of each type pair
+    bool per_pair = false;            // distances differ between type pairs
+    double list_rso = 0, list_rco = 0;   // largest r_s+; largest hybrid-pair r_c+
+    int ntypes = 0, mix = 0, precision = 64, pair_math = 64, no_shift = 0;
     std::vector<int> hybrid;
     std::vector<PairCoef<double>> coef64;     // per type pair
     std::vector<PairCoef<double>> coef_grad;  // [4][pair]: d/d eps_FG, sigma_FG, eps_CG, sigma_CG
-    DBuf d_coef64, d_coef32, d_hybrid, d_coef_grad, d_bpartial;
-    double cut64[8] = {0};
+    DBuf d_coef64, d_coef32, d_hybrid, d_coef_grad, d_bpartial, d_pcut64, d_pcut32;
+    double cut64[8] = {0};            // the distances of every pair when !per_pair
 
     bool topo_set = false;
     int n = 0, n_sites = 0;
@@ -285,19 +319,21 @@ void build_tables(relres_ctx* c, const double* ef, const double* sf, const doubl
 {
     const int nt = c->ntypes;
     const size_t np = (size_t)nt * nt;
-    const double Ds = c->rso - c->rsi, Dc = c->rco - c->rci;
     c->coef64.assign(np, PairCoef<double>{});
     c->coef_grad.assign(4 * np, PairCoef<double>{});
+    const int ns = c->no_shift;
     for (int a = 0; a < nt; ++a)
         for (int b = 0; b < nt; ++b) {
             const size_t q = (size_t)a * nt + b;
-            fg_part(c->coef64[q], ef[q], sf[q], 0, c->rsi, Ds);
-            fg_part(c->coef_grad[0 * np + q], ef[q], sf[q], 1, c->rsi, Ds);
-            fg_part(c->coef_grad[1 * np + q], ef[q], sf[q], 2, c->rsi, Ds);
+            const double* r = &c->dist[4 * q];
+            const double Ds = r[1] - r[0], Dc = r[3] - r[2];
+            fg_part(c->coef64[q], ef[q], sf[q], 0, r[0], Ds);
+            fg_part(c->coef_grad[0 * np + q], ef[q], sf[q], 1, r[0], Ds);
+            fg_part(c->coef_grad[1 * np + q], ef[q], sf[q], 2, r[0], Ds);
             if (c->hybrid[a] && c->hybrid[b]) {
-                cg_part(c->coef64[q], ec[q], sc[q], 0, c->rso, c->rci, Ds, Dc);
-                cg_part(c->coef_grad[2 * np + q], ec[q], sc[q], 1, c->rso, c->rci, Ds, Dc);
-                cg_part(c->coef_grad[3 * np + q], ec[q], sc[q], 2, c->rso, c->rci, Ds, Dc);
+                cg_part(c->coef64[q], ec[q], sc[q], 0, r[1], r[2], Ds, Dc, ns);
+                cg_part(c->coef_grad[2 * np + q], ec[q], sc[q], 1, r[1], r[2], Ds, Dc, ns);
+                cg_part(c->coef_grad[3 * np + q], ec[q], sc[q], 2, r[1], r[2], Ds, Dc, ns);
             }
         }
 }
@@ -318,6 +354,15 @@ int upload_tables(relres_ctx* c)
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_coef_grad.p, c->coef_grad.data(),
                       sizeof(PairCoef<double>) * c->coef_grad.size(), hipMemcpyHostToDevice));
+    const size_t np = c->dist.size() / 4;
+    std::vector<Cutoffs<double>> p64(np);
+    std::vector<Cutoffs<float>> p32(np);
+    for (size_t q = 0; q < np; ++q) {
+        p64[q] = cutoffs_of<double>(&c->dist[4 * q]);
+        p32[q] = cutoffs_of<float>(&c->dist[4 * q]);
+    }
+    HIP_TRY(hipMemcpy(c->d_pcut64.p, p64.data(), sizeof(Cutoffs<double>) * np, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_pcut32.p, p32.data(), sizeof(Cutoffs<float>) * np, hipMemcpyHostToDevice));
     return RELRES_OK;
 }
 
@@ -593,7 +638,7 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     for (int k = 0; k < 3 * ns; ++k)
         if (!(std::isfinite(box[k]) && box[k] > 0.0))
             return fail(RELRES_ERR_ARG, "bad box edge %g (system %d)", box[k], k / 3);
-    const double rla = c->rso + c->skin, rls = c->rco + c->skin;
+    const double rla = c->list_rso + c->skin, rls = c->list_rco + c->skin;
     const bool sites = c->n_sites > 0;
     for (int sy = 0; sy < ns; ++sy) {
         // a system without hybrid atoms only needs the atom-list radius
@@ -705,12 +750,12 @@ int examine_status(relres_ctx* c)
     if (!ov_a && !ov_s) return RELRES_OK;
     if (ov_a) {
         c->ga.cap = ((int)(mr_a * 1.25) + 8 + 7) & ~7;
-        TRY(setup_grid(c->ga, c->rso + c->skin, c->nsys, c->boxes.data(), c->atoms_sys.data(),
+        TRY(setup_grid(c->ga, c->list_rso + c->skin, c->nsys, c->boxes.data(), c->atoms_sys.data(),
                        &c->alloc_generation));
     }
     if (ov_s) {
         c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
-        TRY(setup_grid(c->gs, c->rco + c->skin, c->nsys, c->boxes.data(), c->sites_sys.data(),
+        TRY(setup_grid(c->gs, c->list_rco + c->skin, c->nsys, c->boxes.data(), c->sites_sys.data(),
                        &c->alloc_generation));
     }
     c->stats.regrows++;
@@ -760,6 +805,54 @@ extern "C" {
 
 int relres_abi_version(void) { return RELRES_ABI_VERSION; }
 
+double relres_mix_distance(int mix, double a, double b)
+{
+    if (mix != RELRES_MIX_GEOMETRIC && mix != RELRES_MIX_ARITHMETIC && mix != RELRES_MIX_SIXTHPOWER)
+        return std::numeric_limits<double>::quiet_NaN();
+    return mix_sigma(mix, a, b);
+}
+
+// Eq. 15 (one CG site from its FG sites, geometric FG mixing) and Eq. 13 (a
+// pair of CG sites from all FG pair parameters between them).
+int relres_cg_site_params(int n, const double* eps_fg, const double* sig_fg, double* eps_cg,
+                          double* sig_cg)
+{
+    if (n < 1 || !eps_fg || !sig_fg || !eps_cg || !sig_cg) return fail(RELRES_ERR_ARG, "bad argument");
+    double b12 = 0.0, b6 = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double e = eps_fg[k], sg = sig_fg[k];
+        if (!(std::isfinite(e) && e >= 0.0 && std::isfinite(sg) && sg > 0.0))
+            return fail(RELRES_ERR_ARG, "bad FG parameters of site %d", k);
+        const double s3 = sg * sg * sg;
+        const double se = std::sqrt(e);
+        b12 += se * s3 * s3;          // sqrt(eps sigma^12)
+        b6 += se * s3;                // sqrt(eps sigma^6)
+    }
+    if (!(b6 > 0.0)) return fail(RELRES_ERR_ARG, "all FG energies are zero");
+    *sig_cg = std::cbrt(b12 / b6);
+    *eps_cg = (b6 * b6) * (b6 * b6) / (b12 * b12);
+    return RELRES_OK;
+}
+
+int relres_cg_pair_params(int n, const double* eps_mn, const double* sig_mn, double* eps_cg,
+                          double* sig_cg)
+{
+    if (n < 1 || !eps_mn || !sig_mn || !eps_cg || !sig_cg) return fail(RELRES_ERR_ARG, "bad argument");
+    double a12 = 0.0, a6 = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double e = eps_mn[k], sg = sig_mn[k];
+        if (!(std::isfinite(e) && e >= 0.0 && std::isfinite(sg) && sg > 0.0))
+            return fail(RELRES_ERR_ARG, "bad FG pair parameters at %d", k);
+        const double s6 = (sg * sg * sg) * (sg * sg * sg);
+        a12 += e * s6 * s6;
+        a6 += e * s6;
+    }
+    if (!(a6 > 0.0)) return fail(RELRES_ERR_ARG, "all FG energies are zero");
+    *sig_cg = std::pow(a12 / a6, 1.0 / 6.0);
+    *eps_cg = a6 * a6 / a12;
+    return RELRES_OK;
+}
+
 const char* relres_last_error(void) { return g_last_error.c_str(); }
 
 const char* relres_strerror(int code)
@@ -795,8 +888,10 @@ int relres_create(const relres_params* p, relres_ctx** out)
         return fail(RELRES_ERR_ARG, "pair_math must be 0, 32 or 64");
     if (p->precision == 64 && p->pair_math == 32)
         return fail(RELRES_ERR_ARG, "FP64 forces need FP64 pair terms");
-    if (p->mix != RELRES_MIX_GEOMETRIC && p->mix != RELRES_MIX_ARITHMETIC)
+    if (p->mix != RELRES_MIX_GEOMETRIC && p->mix != RELRES_MIX_ARITHMETIC &&
+        p->mix != RELRES_MIX_SIXTHPOWER)
         return fail(RELRES_ERR_ARG, "unknown mixing rule %d", p->mix);
+    if (p->no_shift != 0 && p->no_shift != 1) return fail(RELRES_ERR_ARG, "no_shift must be 0 or 1");
     const double cut[5] = {p->rs_in, p->rs_out, p->rc_in, p->rc_out, p->skin};
     for (double v : cut)
         if (!std::isfinite(v)) return fail(RELRES_ERR_CUTOFF_ORDER, "non-finite cutoff");
@@ -815,37 +910,79 @@ int relres_create(const relres_params* p, relres_ctx** out)
             return fail(RELRES_ERR_ARG, "hybrid type %d needs sigma_CG > 0", t);
     }
 
+    // distances of every type pair: explicit, mixed from per-type values
+    // (each distance with the sigma rule; like types keep their own), or global
+    std::vector<double> dist((size_t)4 * nt * nt);
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b)
+            for (int k = 0; k < 4; ++k) {
+                const size_t q = (size_t)a * nt + b;
+                double v = cut[k];
+                if (p->cut_pair) v = p->cut_pair[4 * q + k];
+                else if (p->cut_type && a == b) v = p->cut_type[4 * a + k];
+                else if (p->cut_type) v = mix_sigma(p->mix, p->cut_type[4 * a + k], p->cut_type[4 * b + k]);
+                dist[4 * q + k] = v;
+            }
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const double* r = &dist[4 * ((size_t)a * nt + b)];
+            const double* rt = &dist[4 * ((size_t)b * nt + a)];
+            if (!(std::isfinite(r[0]) && std::isfinite(r[3]) && 0.0 < r[0] && r[0] <= r[1] &&
+                  r[1] <= r[2] && r[2] <= r[3]))
+                return fail(RELRES_ERR_CUTOFF_ORDER, "type pair (%d, %d): need 0 < r_s- <= r_s+ <= "
+                            "r_c- <= r_c+ (got %g %g %g %g)", a, b, r[0], r[1], r[2], r[3]);
+            if (!std::equal(r, r + 4, rt))
+                return fail(RELRES_ERR_ARG, "cut_pair is not symmetric for types (%d, %d)", a, b);
+        }
+
     relres_ctx* c = new relres_ctx();
     auto bail = [&](int rc) { relres_destroy(c); return rc; };
     if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(RELRES_ERR_HIP, "no HIP device"));
-    c->rsi = p->rs_in; c->rso = p->rs_out; c->rci = p->rc_in; c->rco = p->rc_out;
     c->skin = p->skin;
     c->ntypes = nt;
     c->mix = p->mix;
+    c->no_shift = p->no_shift;
     c->precision = p->precision;
     c->pair_math = p->pair_math ? p->pair_math : p->precision;
     c->hybrid.resize(nt);
     for (int t = 0; t < nt; ++t) c->hybrid[t] = p->eps_cg[t] > 0.0 ? 1 : 0;
+    c->dist = dist;
+    c->per_pair = false;
+    c->list_rso = c->list_rco = 0.0;
+    double any_rco = 0.0;
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const double* r = &dist[4 * ((size_t)a * nt + b)];
+            if (!std::equal(r, r + 4, &dist[0])) c->per_pair = true;
+            c->list_rso = std::max(c->list_rso, r[1]);
+            any_rco = std::max(any_rco, r[3]);
+            if (c->hybrid[a] && c->hybrid[b]) c->list_rco = std::max(c->list_rco, r[3]);
+        }
+    if (c->list_rco == 0.0) c->list_rco = any_rco;     // no hybrid pair: the site list stays empty
 
     {
         std::vector<double> ef((size_t)nt * nt), sf(ef.size()), ec(ef.size()), sc(ef.size());
         for (int a = 0; a < nt; ++a)
             for (int b = 0; b < nt; ++b) {
                 const size_t q = (size_t)a * nt + b;
-                ef[q] = std::sqrt(p->eps_fg[a] * p->eps_fg[b]);
+                ef[q] = mix_eps(c->mix, p->eps_fg[a], p->eps_fg[b], p->sig_fg[a], p->sig_fg[b]);
                 sf[q] = mix_sigma(c->mix, p->sig_fg[a], p->sig_fg[b]);
-                ec[q] = std::sqrt(p->eps_cg[a] * p->eps_cg[b]);
-                sc[q] = mix_sigma(c->mix, p->sig_cg[a], p->sig_cg[b]);
+                if (c->hybrid[a] && c->hybrid[b]) {
+                    ec[q] = mix_eps(c->mix, p->eps_cg[a], p->eps_cg[b], p->sig_cg[a], p->sig_cg[b]);
+                    sc[q] = mix_sigma(c->mix, p->sig_cg[a], p->sig_cg[b]);
+                }
             }
         build_tables(c, ef.data(), sf.data(), ec.data(), sc.data());
     }
-    c->cut64[0] = c->rsi; c->cut64[1] = c->rso; c->cut64[2] = c->rci; c->cut64[3] = c->rco;
+    for (int k = 0; k < 4; ++k) c->cut64[k] = dist[k];
     for (int k = 0; k < 4; ++k) c->cut64[4 + k] = c->cut64[k] * c->cut64[k];
 
     int rc;
     if ((rc = ensure(c->d_coef64, sizeof(PairCoef<double>) * c->coef64.size(), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_coef32, sizeof(PairCoef<float>) * c->coef64.size(), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_coef_grad, sizeof(PairCoef<double>) * c->coef_grad.size(), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_pcut64, sizeof(Cutoffs<double>) * nt * nt, &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_pcut32, sizeof(Cutoffs<float>) * nt * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_hybrid, sizeof(int) * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_status, sizeof(Status), &c->alloc_generation))) return bail(rc);
@@ -1053,6 +1190,8 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     }
     a.coef32 = c->d_coef32.p;
     a.coef64 = c->d_coef64.p;
+    a.pcut32 = c->d_pcut32.as<Cutoffs<float>>();
+    a.pcut64 = c->d_pcut64.as<Cutoffs<double>>();
     a.ntypes = c->ntypes;
     a.forces = forces;
     a.energy = energy;
@@ -1088,7 +1227,7 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
         TRY(ensure(c->d_row_ew, sizeof(double) * 8 * (size_t)(c->n + c->n_sites), &c->alloc_generation));
         a.row_ew = c->d_row_ew.as<double>();
     }
-    HIP_TRY(launch_forces(a, c->cut64, c->pair_math, c->precision, ew, s));
+    HIP_TRY(launch_forces(a, c->cut64, c->per_pair, c->pair_math, c->precision, ew, s));
     if (timed) {
         HIP_TRY(hipEventRecord(e1, s));
         c->ev_force.push_back({e0, e1});
@@ -1163,6 +1302,7 @@ int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
         a.s_cap = c->gs.cap;
     }
     a.coef64 = c->d_coef64.p;
+    a.pcut64 = c->d_pcut64.as<Cutoffs<double>>();
     a.ntypes = nt;
     a.blocks_a = c->n > 0 ? blocks(c->n, la) : 0;
     a.blocks_b = (c->n > 0 && sites) ? blocks(c->n_sites, lb) : 0;
@@ -1177,7 +1317,7 @@ int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
     const int waves = (a.blocks_a + a.blocks_b) * (kForceBlock / 64);
     TRY(ensure(c->d_bpartial, sizeof(double) * (size_t)std::max(1, waves) * nbins, &c->alloc_generation));
     b.partial = c->d_bpartial.as<double>();
-    HIP_TRY(launch_backward(b, c->cut64, waves, grad_pair, s));
+    HIP_TRY(launch_backward(b, waves, grad_pair, s));
     return RELRES_OK;
 }
 

@@ -19,10 +19,13 @@ constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
 //        r in [r_s-,r_s+) f_s-^FG(delta)     - f_s-^FG(Dr_s)
 //   CG:  r <  r_s-        gamma_0+^CG        - Gamma_c-      (no force)
 //        r in [r_s-,r_s+) f_s+^CG(delta)     - Gamma_c-
-//        r in [r_s+,r_c-) u_CG(r)            - Gamma_c-
-//        r in [r_c-,r_c+) f_c-^CG(delta)     - Gamma_c-
+//        r in [r_s+,r_c-) u_CG(r)            - Gamma_c-'
+//        r in [r_c-,r_c+) f_c-^CG(delta)     - Gamma_c-'
 // Summed, the two parts reproduce every case of Eq. 20 with the constants of
 // Eq. 19 (Gamma_s+ = Gamma_c- + f_s-^FG(Dr_s), Gamma_s- = Gamma_s+ - gamma_0+).
+// Gamma_c-' is Gamma_c- (pair_modify shift yes) or 0 (shift no, which leaves
+// Gamma_s+- as they are).  The distances r_s-, r_s+, r_c-, r_c+ belong to the
+// type pair when they are set per type.
 // LJ terms use  -u'(r)/r = r^-8 (c12 r^-6 - c6),  u(r) = r^-6 (e12 r^-6 - e6)
 // with c12 = 48 eps sig^12, c6 = 24 eps sig^6, e12 = 4 eps sig^12, e6 = 4 eps sig^6.
 template <typename S>
@@ -33,8 +36,8 @@ struct PairCoef {
     S cg_c12, cg_c6, cg_e12, cg_e6;
     S sp_g0, sp_g3, sp_g4;  // f_s+^CG: gamma_0+, gamma_3+, gamma_4+ (gamma_1+ = gamma_2+ = 0)
     S cm_g[5];          // f_c-^CG coefficients
-    S cm_shift;         // Gamma_c-
-    S pad;
+    S cm_shift;         // Gamma_c-' (cases 3-4 of Eq. 20)
+    S sp_shift;         // Gamma_c- (cases 1-2, inside Gamma_s+-)
 };
 
 template <typename S>
@@ -128,6 +131,8 @@ struct ForceArgs {
     int s_cap;
     const void* coef32;       // PairCoef<float>[ntypes * ntypes]
     const void* coef64;       // PairCoef<double>[ntypes * ntypes]
+    const Cutoffs<float>* pcut32;    // distances per type pair [ntypes * ntypes]
+    const Cutoffs<double>* pcut64;
     int ntypes;
     void* forces;             // N x 3 of TF, caller order
     double* energy;           // [nsys][3] or null
@@ -151,9 +156,10 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, con
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
                         TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
                         bool per_wave, hipStream_t s);
-// cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares}
-hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
-                         bool ew, hipStream_t s);
+// cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares} of every type pair, or
+// per_pair: the distances of each type pair come from a.pcut32 / a.pcut64
+hipError_t launch_forces(const ForceArgs& a, const double* cut64, bool per_pair, int pair_math,
+                         int precision, bool ew, hipStream_t s);
 hipError_t launch_list_stats(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
 // Backward (adjoint) pass: ForceArgs (positions, lists, FP64 table) plus
 struct BackArgs {
@@ -165,9 +171,9 @@ struct BackArgs {
     double* partial;                      // per wave: [ntypes^2][4] parameter sums
 };
 constexpr int kBackwardTypes = 8;
-// waves = wavefronts of the launch; grad_pair receives [4][ntypes][ntypes]
-hipError_t launch_backward(const BackArgs& b, const double* cut64, int waves, double* grad_pair,
-                           hipStream_t s);
+// waves = wavefronts of the launch; grad_pair receives [4][ntypes][ntypes];
+// distances per type pair from b.f.pcut64
+hipError_t launch_backward(const BackArgs& b, int waves, double* grad_pair, hipStream_t s);
 hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStream_t s);
 // nsys > 1: energy/virial of each system from the per-row partials

@@ -732,14 +732,14 @@ __device__ __forceinline__ void cg_term(const PairCoef<T>& c, const Cutoffs<T>& 
 {
     if (r2 < cut.rsi2) {
         fpair = T(0);
-        en = c.sp_g0 - c.cm_shift;
+        en = c.sp_g0 - c.sp_shift;
     } else if (r2 < cut.rso2) {
         T r, ir;
         M::root(r2, r, ir);
         const T d = r - cut.rsi;
         const T dp = d * d * (T(3) * c.sp_g3 + T(4) * c.sp_g4 * d);
         fpair = -dp * ir;
-        en = c.sp_g0 + d * d * d * (c.sp_g3 + d * c.sp_g4) - c.cm_shift;
+        en = c.sp_g0 + d * d * d * (c.sp_g3 + d * c.sp_g4) - c.sp_shift;
     } else if (r2 < cut.rci2) {
         const T r2i = M::recip(r2);
         const T r6i = r2i * r2i * r2i;
@@ -762,6 +762,24 @@ template <typename S, bool EW>
 struct CoefLds {
     PairCoef<S> c[kLdsTypes * kLdsTypes];
     PairCoef<double> c64[(EW && sizeof(S) != sizeof(double)) ? kLdsTypes * kLdsTypes : 1];
+};
+
+// Distances per type pair, staged when they are not uniform (PC).
+template <typename S, bool PC>
+struct CutLds {
+    Cutoffs<S> c[PC ? kLdsTypes * kLdsTypes : 1];
+    Cutoffs<double> c64[(PC && sizeof(S) != sizeof(double)) ? kLdsTypes * kLdsTypes : 1];
+};
+
+// The coefficient and distance rows of one row atom's type: pair-math
+// coefficients, FP64 coefficients (energy and virial), and with per-pair
+// distances (PC) the distance rows in both types.
+template <typename S>
+struct RowTab {
+    const PairCoef<S>* c;
+    const PairCoef<double>* c64;
+    const Cutoffs<S>* cut;
+    const Cutoffs<double>* cut64;
 };
 
 template <typename T>
@@ -806,17 +824,18 @@ __device__ __forceinline__ BoxV row_box(const ForceArgs& a, int sys)
 // image.  Force terms are evaluated in S and accumulated in TF; energy and
 // virial terms are evaluated in FP64 and accumulated in FP64 (when they are
 // requested, the FP32 force is rounded from the same FP64 terms).
-template <bool CG, typename S, typename TF, bool EW>
-__device__ __forceinline__ void entry_terms(const BoxV& bx, const PairCoef<S>* crow,
-                                            const PairCoef<double>* crow64,
-                                            const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
+template <bool CG, typename S, typename TF, bool EW, bool PC>
+__device__ __forceinline__ void entry_terms(const BoxV& bx, const RowTab<S>& t,
+                                            const Cutoffs<S>& cut_all,
+                                            const Cutoffs<double>& cut64_all,
                                             double xi, double yi, double zi, uint32_t e,
                                             double px, double py, double pz,
                                             TF& fx, TF& fy, TF& fz, double* acc)
 {
     if (e == kNoEntry) return;
-    const double rmax2 = CG ? cut64.rco2 : cut64.rso2;
     const int tj = (int)(e >> kIdxBits);
+    const Cutoffs<double>& cut64 = PC ? t.cut64[tj] : cut64_all;
+    const double rmax2 = CG ? cut64.rco2 : cut64.rso2;
     double dx = xi - px;
     double dy = yi - py;
     double dz = zi - pz;
@@ -830,8 +849,8 @@ __device__ __forceinline__ void entry_terms(const BoxV& bx, const PairCoef<S>* c
         // they only feed energy/virial and FP32 forces)
         using M = MathF64<sizeof(S) == sizeof(double) ? 2 : 1>;
         double fpd, end;
-        if constexpr (CG) cg_term<M>(crow64[tj], cut64, r2d, fpd, end);
-        else fg_term<M>(crow64[tj], cut64, r2d, fpd, end);
+        if constexpr (CG) cg_term<M>(t.c64[tj], cut64, r2d, fpd, end);
+        else fg_term<M>(t.c64[tj], cut64, r2d, fpd, end);
         if constexpr (sizeof(TF) == sizeof(double)) {
             fx += fpd * dx;
             fy += fpd * dy;
@@ -854,8 +873,9 @@ __device__ __forceinline__ void entry_terms(const BoxV& bx, const PairCoef<S>* c
         }
     } else {
         float fp, en;
-        if constexpr (CG) cg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
-        else fg_term<MathF32>(crow[tj], cut, (float)r2d, fp, en);
+        const Cutoffs<S>& cut = PC ? t.cut[tj] : cut_all;
+        if constexpr (CG) cg_term<MathF32>(t.c[tj], cut, (float)r2d, fp, en);
+        else fg_term<MathF32>(t.c[tj], cut, (float)r2d, fp, en);
         fx += fp * (float)dx;
         fy += fp * (float)dy;
         fz += fp * (float)dz;
@@ -879,10 +899,9 @@ __device__ __forceinline__ void gather_batch(const ForceArgs& a, const uint32_t 
 // Entries start, start + G, ... below cnt of one list row, kBatch per lane at
 // a time: their list loads, then their position gathers, are issued together
 // before any pair term is computed.
-template <bool CG, typename S, typename TF, bool EW>
+template <bool CG, typename S, typename TF, bool EW, bool PC>
 __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
-                                          const PairCoef<S>* crow,
-                                          const PairCoef<double>* crow64,
+                                          const RowTab<S>& t,
                                           const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
                                           double xi, double yi, double zi,
                                           const int* __restrict__ lst, int start, int cnt, int G,
@@ -899,8 +918,8 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
         gather_batch(a, e, px, py, pz);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
-            entry_terms<CG, S, TF, EW>(bx, crow, crow64, cut, cut64, xi, yi, zi, e[u], px[u],
-                                       py[u], pz[u], fx, fy, fz, acc);
+            entry_terms<CG, S, TF, EW, PC>(bx, t, cut, cut64, xi, yi, zi, e[u], px[u], py[u],
+                                           pz[u], fx, fy, fz, acc);
     }
 }
 
@@ -1141,7 +1160,7 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     }
 }
 
-template <typename S, typename TF, bool EW, bool LDS>
+template <typename S, typename TF, bool EW, bool LDS, bool PC>
 __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> cut,
                                                        Cutoffs<double> cut64)
 {
@@ -1203,19 +1222,37 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
 
     const PairCoef<S>* coef;
     const PairCoef<double>* coef64;
+    const Cutoffs<S>* pcut = nullptr;
+    const Cutoffs<double>* pcut64 = nullptr;
+    const Cutoffs<S>* pcut_g = (const Cutoffs<S>*)(sizeof(S) == 8 ? (const void*)a.pcut64
+                                                                   : (const void*)a.pcut32);
     if constexpr (LDS) {
         __shared__ CoefLds<S, EW> tab;
+        __shared__ CutLds<S, PC> ctab;
         const int np = a.ntypes * a.ntypes;
         stage_table(tab.c, (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32), np);
         if constexpr (EW && sizeof(S) != sizeof(double))
             stage_table(tab.c64, (const PairCoef<double>*)a.coef64, np);
+        if constexpr (PC) {
+            stage_table(ctab.c, pcut_g, np);
+            if constexpr (sizeof(S) != sizeof(double)) stage_table(ctab.c64, a.pcut64, np);
+        }
         __syncthreads();
         coef = tab.c;
         if constexpr (EW && sizeof(S) != sizeof(double)) coef64 = tab.c64;
         else coef64 = (const PairCoef<double>*)tab.c;
+        if constexpr (PC) {
+            pcut = ctab.c;
+            if constexpr (sizeof(S) != sizeof(double)) pcut64 = ctab.c64;
+            else pcut64 = (const Cutoffs<double>*)ctab.c;
+        }
     } else {
         coef = (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32);
         coef64 = (const PairCoef<double>*)a.coef64;
+        if constexpr (PC) {
+            pcut = pcut_g;
+            pcut64 = a.pcut64;
+        }
     }
 
     TF fx = TF(0), fy = TF(0), fz = TF(0);
@@ -1236,28 +1273,29 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         double fxp[kBatch], fyp[kBatch], fzp[kBatch], sxp[kBatch], syp[kBatch], szp[kBatch];
         gather_batch(a, e_fg, fxp, fyp, fzp);
         if (rb) gather_batch(a, e_own, sxp, syp, szp);
-        const PairCoef<S>* crow = coef + ti * a.ntypes;
-        const PairCoef<double>* crow64 = coef64 + ti * a.ntypes;
+        const int ro = ti * a.ntypes;
+        const RowTab<S> rt{coef + ro, coef64 + ro, PC ? pcut + ro : nullptr,
+                           PC ? pcut64 + ro : nullptr};
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
-            entry_terms<false, S, TF, EW>(bx, crow, crow64, cut, cut64, xi, yi, zi, e_fg[u],
-                                          fxp[u], fyp[u], fzp[u], fx, fy, fz, acc);
+            entry_terms<false, S, TF, EW, PC>(bx, rt, cut, cut64, xi, yi, zi, e_fg[u], fxp[u],
+                                              fyp[u], fzp[u], fx, fy, fz, acc);
         if (rb) {
 #pragma unroll
             for (int u = 0; u < kBatch; ++u)
-                entry_terms<true, S, TF, EW>(bx, crow, crow64, cut, cut64, xi, yi, zi, e_own[u],
-                                             sxp[u], syp[u], szp[u], fx, fy, fz, acc);
+                entry_terms<true, S, TF, EW, PC>(bx, rt, cut, cut64, xi, yi, zi, e_own[u],
+                                                 sxp[u], syp[u], szp[u], fx, fy, fz, acc);
         }
         // the rest of both rows
         const int ar = rb ? rec.w : row;
         const int rest = sub + kBatch * G;
-        row_terms<false, S, TF, EW>(a, bx, crow, crow64, cut, cut64, xi, yi, zi,
-                                    a.a_list + (size_t)ar * a.a_cap, rest, cnt_a, G, fx, fy, fz,
-                                    acc);
+        row_terms<false, S, TF, EW, PC>(a, bx, rt, cut, cut64, xi, yi, zi,
+                                        a.a_list + (size_t)ar * a.a_cap, rest, cnt_a, G, fx, fy,
+                                        fz, acc);
         if (rb)
-            row_terms<true, S, TF, EW>(a, bx, crow, crow64, cut, cut64, xi, yi, zi,
-                                       a.s_list + (size_t)row * a.s_cap, rest, cnt_s, G, fx, fy,
-                                       fz, acc);
+            row_terms<true, S, TF, EW, PC>(a, bx, rt, cut, cut64, xi, yi, zi,
+                                           a.s_list + (size_t)row * a.s_cap, rest, cnt_s, G, fx,
+                                           fy, fz, acc);
     }
     fx = group_sum(fx, G);
     fy = group_sum(fy, G);
@@ -1401,19 +1439,24 @@ hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_
     return hipGetLastError();
 }
 
-hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math, int precision,
-                         bool ew, hipStream_t s)
+hipError_t launch_forces(const ForceArgs& a, const double* cut64, bool per_pair, int pair_math,
+                         int precision, bool ew, hipStream_t s)
 {
     const dim3 grid(a.blocks_a + a.blocks_b), block(kForceBlock);
     const bool lds = a.ntypes <= kLdsTypes;
-#define RELRES_LAUNCH(S, TF, EW)                                                                 \
+#define RELRES_LAUNCH_PC(S, TF, EW, PC)                                                          \
     do {                                                                                         \
         if (lds)                                                                                 \
-            hipLaunchKernelGGL((k_forces<S, TF, EW, true>), grid, block, 0, s, a,                \
+            hipLaunchKernelGGL((k_forces<S, TF, EW, true, PC>), grid, block, 0, s, a,            \
                                cut_as<S>(cut64), cut_as<double>(cut64));                         \
         else                                                                                     \
-            hipLaunchKernelGGL((k_forces<S, TF, EW, false>), grid, block, 0, s, a,               \
+            hipLaunchKernelGGL((k_forces<S, TF, EW, false, PC>), grid, block, 0, s, a,           \
                                cut_as<S>(cut64), cut_as<double>(cut64));                         \
+    } while (0)
+#define RELRES_LAUNCH(S, TF, EW)                                                                 \
+    do {                                                                                         \
+        if (per_pair) RELRES_LAUNCH_PC(S, TF, EW, true);                                         \
+        else RELRES_LAUNCH_PC(S, TF, EW, false);                                                 \
     } while (0)
     if (precision == 64) {
         if (ew) RELRES_LAUNCH(double, double, true); else RELRES_LAUNCH(double, double, false);
@@ -1423,6 +1466,7 @@ hipError_t launch_forces(const ForceArgs& a, const double* cut64, int pair_math,
         if (ew) RELRES_LAUNCH(float, float, true); else RELRES_LAUNCH(float, float, false);
     }
 #undef RELRES_LAUNCH
+#undef RELRES_LAUNCH_PC
     return hipGetLastError();
 }
 
@@ -1474,7 +1518,7 @@ __device__ __forceinline__ void cg_terms2(const PairCoef<double>& c, const Cutof
     using M = MathF64<2>;
     if (r2 < cut.rsi2) {
         fpair = 0.0;
-        en = c.sp_g0 - c.cm_shift;
+        en = c.sp_g0 - c.sp_shift;
         hc = 0.0;
     } else if (r2 < cut.rso2) {
         double r, ir;
@@ -1483,7 +1527,7 @@ __device__ __forceinline__ void cg_terms2(const PairCoef<double>& c, const Cutof
         const double dp = d * d * (3.0 * c.sp_g3 + 4.0 * c.sp_g4 * d);
         const double dpp = d * (6.0 * c.sp_g3 + 12.0 * c.sp_g4 * d);
         fpair = -dp * ir;
-        en = c.sp_g0 + d * d * d * (c.sp_g3 + d * c.sp_g4) - c.cm_shift;
+        en = c.sp_g0 + d * d * d * (c.sp_g3 + d * c.sp_g4) - c.sp_shift;
         hc = (-dpp - fpair) * ir * ir;
     } else if (r2 < cut.rci2) {
         const double r2i = M::recip(r2);
@@ -1506,8 +1550,7 @@ __device__ __forceinline__ void cg_terms2(const PairCoef<double>& c, const Cutof
 // One list row of the backward pass (FG part when CG is false, CG part when
 // true); TM bounds the number of types.
 template <bool CG, int TM>
-__device__ __forceinline__ void back_row(const BackArgs& b, const BoxV& bx,
-                                         const Cutoffs<double>& cut, int ti,
+__device__ __forceinline__ void back_row(const BackArgs& b, const BoxV& bx, int ti,
                                          double xi, double yi, double zi, double gix, double giy,
                                          double giz, double ebar, const int* __restrict__ lst,
                                          int cnt, int sub, int G, double gp[3], double acc[TM][4])
@@ -1516,7 +1559,6 @@ __device__ __forceinline__ void back_row(const BackArgs& b, const BoxV& bx,
     const int nt = a.ntypes;
     const int np = nt * nt;
     const PairCoef<double>* coef = (const PairCoef<double>*)a.coef64;
-    const double rmax2 = CG ? cut.rco2 : cut.rso2;
     constexpr int P0 = CG ? 2 : 0;
     for (int k = sub; k < cnt; k += G) {
         const uint32_t e = (uint32_t)lst[k];
@@ -1528,8 +1570,9 @@ __device__ __forceinline__ void back_row(const BackArgs& b, const BoxV& bx,
         dy -= bx.L[1] * rint(dy * bx.iL[1]);
         dz -= bx.L[2] * rint(dz * bx.iL[2]);
         const double r2 = dx * dx + dy * dy + dz * dz;
-        if (!(r2 < rmax2)) continue;
         const int pi = ti * nt + tj;
+        const Cutoffs<double>& cut = a.pcut64[pi];
+        if (!(r2 < (CG ? cut.rco2 : cut.rso2))) continue;
         double fp, en, hc, fe, ee, fs, es;
         if constexpr (CG) {
             cg_terms2(coef[pi], cut, r2, fp, en, hc);
@@ -1563,7 +1606,7 @@ __device__ __forceinline__ void back_row(const BackArgs& b, const BoxV& bx,
 }
 
 template <int TM>
-__global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b, Cutoffs<double> cut)
+__global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b)
 {
     const ForceArgs& a = b.f;
     const bool rb = (int)blockIdx.x >= a.blocks_a;
@@ -1606,10 +1649,10 @@ __global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b, Cutoffs<do
         }
         const int ar = rb ? rec.w : row;
         const int ca = rb ? cnt_a : rec.z;
-        back_row<false, TM>(b, bx, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
+        back_row<false, TM>(b, bx, ti, xi, yi, zi, gix, giy, giz, ebar,
                             a.a_list + (size_t)ar * a.a_cap, ca, sub, G, gp, acc);
         if (rb)
-            back_row<true, TM>(b, bx, cut, ti, xi, yi, zi, gix, giy, giz, ebar,
+            back_row<true, TM>(b, bx, ti, xi, yi, zi, gix, giy, giz, ebar,
                                a.s_list + (size_t)row * a.s_cap, rec.z, sub, G, gp, acc);
     }
     for (int c = 0; c < 3; ++c) gp[c] = group_sum(gp[c], G);
@@ -1654,19 +1697,18 @@ __global__ __launch_bounds__(256) void k_reduce_bins(const double* __restrict__ 
     }
 }
 
-hipError_t launch_backward(const BackArgs& b, const double* cut64, int waves, double* grad_pair,
-                           hipStream_t s)
+hipError_t launch_backward(const BackArgs& b, int waves, double* grad_pair, hipStream_t s)
 {
     const int nt = b.f.ntypes;
     const int blocks = b.f.blocks_a + b.f.blocks_b;
     if (blocks > 0) {
         const dim3 grid(blocks), block(kForceBlock);
         if (nt <= 2)
-            hipLaunchKernelGGL(k_backward<2>, grid, block, 0, s, b, cut_as<double>(cut64));
+            hipLaunchKernelGGL(k_backward<2>, grid, block, 0, s, b);
         else if (nt <= 4)
-            hipLaunchKernelGGL(k_backward<4>, grid, block, 0, s, b, cut_as<double>(cut64));
+            hipLaunchKernelGGL(k_backward<4>, grid, block, 0, s, b);
         else
-            hipLaunchKernelGGL(k_backward<8>, grid, block, 0, s, b, cut_as<double>(cut64));
+            hipLaunchKernelGGL(k_backward<8>, grid, block, 0, s, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -21,6 +21,7 @@ RELRES_OK = 0
 RELRES_ERR_LIST_RETRY = -10
 MIX_GEOMETRIC = 0
 MIX_ARITHMETIC = 1
+MIX_SIXTHPOWER = 2
 LIST_ATOM = 0
 LIST_SITE = 1
 
@@ -34,7 +35,8 @@ class Params(ctypes.Structure):
                 ("eps_fg", _c_double_p), ("sig_fg", _c_double_p),
                 ("eps_cg", _c_double_p), ("sig_cg", _c_double_p),
                 ("mix", ctypes.c_int), ("precision", ctypes.c_int),
-                ("pair_math", ctypes.c_int)]
+                ("pair_math", ctypes.c_int), ("no_shift", ctypes.c_int),
+                ("cut_type", _c_double_p), ("cut_pair", _c_double_p)]
 
 
 class Stats(ctypes.Structure):
@@ -50,6 +52,11 @@ class Stats(ctypes.Structure):
 # exported symbol -> (restype, argtypes); mirrors include/relres.h
 SIGNATURES = {
     "relres_abi_version": (ctypes.c_int, []),
+    "relres_mix_distance": (ctypes.c_double, [ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    "relres_cg_site_params": (ctypes.c_int, [ctypes.c_int, _c_double_p, _c_double_p, _c_double_p,
+                                             _c_double_p]),
+    "relres_cg_pair_params": (ctypes.c_int, [ctypes.c_int, _c_double_p, _c_double_p, _c_double_p,
+                                             _c_double_p]),
     "relres_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "relres_last_error": (ctypes.c_char_p, []),
     "relres_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
@@ -131,27 +138,70 @@ def _stream(stream) -> int:
     return stream.cuda_stream
 
 
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def cg_site_params(eps_fg, sig_fg):
+    """Eq. 15: (eps_CG, sigma_CG) of one CG site from the FG parameters of the
+    sites it groups (geometric FG mixing).  Host computation in the library."""
+    e, sg = _f64(eps_fg).ravel(), _f64(sig_fg).ravel()
+    if e.shape != sg.shape:
+        raise ValueError("eps_fg and sig_fg differ in length")
+    eo, so = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().relres_cg_site_params(int(e.shape[0]), _dp(e), _dp(sg),
+                                                ctypes.byref(eo), ctypes.byref(so)),
+           "relres_cg_site_params")
+    return eo.value, so.value
+
+
+def cg_pair_params(eps_mn, sig_mn):
+    """Eq. 13: (eps_CG, sigma_CG) of a pair of CG sites from the FG pair
+    parameters of every mu-nu pair between them (any mixing)."""
+    e, sg = _f64(eps_mn).ravel(), _f64(sig_mn).ravel()
+    if e.shape != sg.shape:
+        raise ValueError("eps_mn and sig_mn differ in length")
+    eo, so = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().relres_cg_pair_params(int(e.shape[0]), _dp(e), _dp(sg),
+                                                ctypes.byref(eo), ctypes.byref(so)),
+           "relres_cg_pair_params")
+    return eo.value, so.value
+
+
+def mix_distance(mix: int, a: float, b: float) -> float:
+    """Distance of an unlike type pair mixed from two per-type values."""
+    return float(load_library().relres_mix_distance(int(mix), float(a), float(b)))
+
+
 class RelRes:
     """One RelRes LJ evaluator bound to the current GPU.
 
     Parameters follow Sec. 2.5 of the paper (pair_style lj/relres r_s- r_s+
     r_c- r_c+ with per-type FG/CG epsilon and sigma); ``eps_cg == 0`` marks an
     ordinary type.  ``precision`` is the force type (32 or 64), ``pair_math``
-    the type of the per-pair terms (0 = same as precision).
+    the type of the per-pair terms (0 = same as precision).  ``shift`` is
+    pair_modify shift yes/no; ``cut_type`` (ntypes x 4) or ``cut_pair``
+    (ntypes x ntypes x 4) give r_s-, r_s+, r_c-, r_c+ per type (mixed for
+    unlike types with the sigma rule) or per type pair.
     """
 
     def __init__(self, *, rs_in: float, rs_out: float, rc_in: float, rc_out: float,
                  skin: float, eps_fg: Sequence[float], sig_fg: Sequence[float],
                  eps_cg: Sequence[float], sig_cg: Sequence[float], mix: int = MIX_GEOMETRIC,
-                 precision: int = 32, pair_math: int = 0):
+                 precision: int = 32, pair_math: int = 0, shift: bool = True,
+                 cut_type=None, cut_pair=None):
         if not torch.cuda.is_available():
             raise RuntimeError("RelRes needs a ROCm GPU; none is visible")
         self._lib = load_library()
         self._arrays = [_f64(eps_fg), _f64(sig_fg), _f64(eps_cg), _f64(sig_cg)]
         nt = len(self._arrays[0])
+        ct = None if cut_type is None else _f64(cut_type).reshape(nt, 4)
+        cp = None if cut_pair is None else _f64(cut_pair).reshape(nt, nt, 4)
+        self._cuts = [ct, cp]
         p = Params(rs_in, rs_out, rc_in, rc_out, skin, nt,
                    *[a.ctypes.data_as(_c_double_p) for a in self._arrays],
-                   int(mix), int(precision), int(pair_math))
+                   int(mix), int(precision), int(pair_math), 0 if shift else 1,
+                   None if ct is None else _dp(ct), None if cp is None else _dp(cp))
         ctx = ctypes.c_void_p()
         torch.cuda.init()
         _check(self._lib.relres_create(ctypes.byref(p), ctypes.byref(ctx)), "relres_create")

@@ -11,7 +11,8 @@ def make_relres(sys, precision=None, pair_math=0):
                 skin=sys.skin, eps_fg=sys.eps_fg, sig_fg=sys.sig_fg, eps_cg=sys.eps_cg,
                 sig_cg=sys.sig_cg, mix=sys.mix,
                 precision=sys.precision if precision is None else precision,
-                pair_math=pair_math)
+                pair_math=pair_math, shift=sys.shift, cut_type=sys.cut_type,
+                cut_pair=sys.cut_pair)
     has_csr = sys.excl_idx is not None and len(sys.excl_idx) > 0
     rr.set_topology(sys.types, sys.mol, sys.exclude_same_mol,
                     sys.excl_offsets if has_csr else None, sys.excl_idx if has_csr else None)
