@@ -269,6 +269,41 @@ def grad_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def sequential_seconds(b, pos, args, cycles, every):
+    """The batch as one context per replica, launched replica after replica:
+    seconds for `cycles` cycles (a quarter of them timed, scaled)."""
+    import torch
+    ctxs = []
+    for k, s in enumerate(b.systems):
+        c = make(s, 32, args.pair_math)
+        p = pos[int(b.offsets[k]):int(b.offsets[k + 1])]
+        c.build_lists(p, s.box)
+        ctxs.append((c, p, s.box, torch.empty((s.n, 3), dtype=torch.float32, device="cuda"),
+                     torch.empty(3, dtype=torch.float64, device="cuda"),
+                     torch.empty(6, dtype=torch.float64, device="cuda")))
+
+    def seq_cycle():
+        for c, p, box, Fk, Ek, Wk in ctxs:
+            c.build_lists(p, box, wait=False)
+            for _ in range(every):
+                c.forces(p, out=Fk, energy=Ek, virial=Wk)
+        for c, p, box, *_ in ctxs:
+            if not c.check_lists():
+                c.build_lists(p, box)
+        torch.cuda.synchronize()
+
+    seq_cycle()
+    t0 = time.perf_counter()
+    seq_cycles = max(1, cycles // 4)
+    for _ in range(seq_cycles):
+        seq_cycle()
+    dt_s = (time.perf_counter() - t0) * cycles / seq_cycles
+    for c, *_ in ctxs:
+        c.close()
+
+    return dt_s
+
+
 def batch_bench(args):
     """Batching workload: 256 replicas of 300-18000 atoms (1.2 M atoms),
     mixed propane/neopentane liquids at 0.0080-0.0100 atoms/A^3, each with
@@ -339,42 +374,15 @@ def batch_bench(args):
     force_us = e0.elapsed_time(e1) * 1e3 / 100
     rr.close()
 
-    # sequential: one context per replica
-    ctxs = []
-    for k, s in enumerate(b.systems):
-        c = make(s, 32, args.pair_math)
-        p = pos[int(b.offsets[k]):int(b.offsets[k + 1])]
-        c.build_lists(p, s.box)
-        ctxs.append((c, p, s.box, torch.empty((s.n, 3), dtype=torch.float32, device="cuda"),
-                     torch.empty(3, dtype=torch.float64, device="cuda"),
-                     torch.empty(6, dtype=torch.float64, device="cuda")))
-
-    def seq_cycle():
-        for c, p, box, Fk, Ek, Wk in ctxs:
-            c.build_lists(p, box, wait=False)
-            for _ in range(every):
-                c.forces(p, out=Fk, energy=Ek, virial=Wk)
-        for c, p, box, *_ in ctxs:
-            if not c.check_lists():
-                c.build_lists(p, box)
-        torch.cuda.synchronize()
-
-    seq_cycle()
-    t0 = time.perf_counter()
-    seq_cycles = max(1, cycles // 4)
-    for _ in range(seq_cycles):
-        seq_cycle()
-    dt_s = (time.perf_counter() - t0) * cycles / seq_cycles
-    for c, *_ in ctxs:
-        c.close()
-
+    dt_s = None if args.no_sequential else sequential_seconds(b, pos, args, cycles, every)
     value = n * cycles * every / dt_b
-    seq = n * cycles * every / dt_s
+    seq = None if dt_s is None else n * cycles * every / dt_s
     fb = 4
     abytes = algorithmic_bytes(st, fb)
     achieved = abytes / (force_us * 1e-6) / 1e9
     log(f"[bench] batch: {dt_b * 1e3 / (cycles * every):.4f} ms/step batched, "
-        f"{dt_s * 1e3 / (cycles * every):.4f} ms/step sequential; force launch {force_us:.1f} us")
+        + ("" if dt_s is None else f"{dt_s * 1e3 / (cycles * every):.4f} ms/step sequential; ")
+        + f"force launch {force_us:.1f} us")
     out = {
         "metric": "RelRes atom-steps/s, 256 batched replicas (1.2 M atoms) in one launch per step, "
                   "1 MI355X",
@@ -388,9 +396,10 @@ def batch_bench(args):
                    "forces": "fp32", "energy_virial": "fp64 per replica",
                    "parallelism": "single GPU",
                    "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)"},
-        "sequential": {"value": seq, "ms_per_step": dt_s * 1e3 / (cycles * every),
-                       "what": "one context per replica, launched replica after replica"},
-        "speedup_vs_sequential": value / seq,
+        "sequential": None if seq is None else {
+            "value": seq, "ms_per_step": dt_s * 1e3 / (cycles * every),
+            "what": "one context per replica, launched replica after replica"},
+        "speedup_vs_sequential": None if seq is None else value / seq,
         "builds_redone": redone,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_forces",
@@ -420,6 +429,8 @@ def main():
                     help="run the differentiation workload instead (forward + backward over "
                          "perturbed frames) and print its line")
     ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch workload only: skip the one-context-per-replica comparison")
     ap.add_argument("--batch", action="store_true",
                     help="run the batching workload (256 replicas in one launch per step) "
                          "instead and print its line")

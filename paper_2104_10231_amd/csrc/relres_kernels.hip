@@ -262,7 +262,6 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 // running count live in that lane and are broadcast with readlane while the
 // wave tests 64 staged candidates at a time.  Only wave-level synchronisation
 // is used, so waves of one block may run different trip counts.
-constexpr int kWaveChunk = 128;
 
 // Membership with the periodic shift of the candidate's stencil slot known in
 // advance.  When a grid has at least four cells along an axis, a neighbour
@@ -287,10 +286,18 @@ __device__ __forceinline__ bool member_shifted(double xi, double yi, double zi, 
 // (rows are in cell order, so a group spans one or two cells).  Work per wave
 // is bounded by the group size, so crowded cells are spread over many waves.
 // Each lane owns one home row of the group: its position, exclusions and
-// running count live in that lane and are broadcast with readlane while the
-// wave tests 64 staged candidates at a time.  Candidates are staged in LDS as
-// structure-of-arrays.  Only wave-level synchronisation is used, so waves of
-// one block may run different trip counts.
+// running count live in that lane and are broadcast with readlane.  The
+// candidates of the home cell's stencil are loaded straight into registers,
+// K per lane per round (candidate q in lane q % 64), and every home row of
+// the cell tests them there, so a candidate is read from memory once per cell
+// and never through LDS.  A larger K takes fewer rounds but more registers:
+// it pays when all waves of the launch are resident at once.  Candidates are visited in stencil-slot
+// order, each row's entries are appended in that order with a wave ballot.
+// Only wave-level synchronisation is used, so waves of one block may run
+// different trip counts.
+constexpr int kResidentListWaves = 256 * 4 * 3;
+
+template <int K>
 __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ grids,
                                                     int waves_a, int waves_total, int max_excl,
                                                     TopoDev topo,
@@ -299,11 +306,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                                                     int4* __restrict__ s_rec,
                                                     Status* __restrict__ st)
 {
-    __shared__ double c_x[4][kWaveChunk], c_y[4][kWaveChunk], c_z[4][kWaveChunk];
-    __shared__ double c_sx[4][kWaveChunk], c_sy[4][kWaveChunk], c_sz[4][kWaveChunk];
-    __shared__ int c_user[4][kWaveChunk], c_type[4][kWaveChunk], c_mol[4][kWaveChunk];
-    __shared__ int cell_start[4][32], cell_pre[4][32];
-    __shared__ double slot_shift[4][27][3];
+    __shared__ int slot_first[4][32], slot_start[4][32];
     const int lane = threadIdx.x & (kWave - 1);
     // wave-uniform by construction; readfirstlane lets the compiler keep it
     // (and everything derived from it) in scalar registers
@@ -371,21 +374,13 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         const int c = readlane_i(mcell, h0);
         int h1 = h0 + 1;
         while (h1 < nh && readlane_i(mcell, h1) == c) ++h1;
+        // stencil slot `lane` (< 27): first member and count of its cell
         int cnt = 0, s0 = 0;
         if (lane < 27) {
             const int r = gnbr[c * 27 + lane];
             if (r >= 0) {
                 s0 = gstart[r];
                 cnt = gstart[r + 1] - s0;
-            }
-            if (known_shift) {
-                // slot offsets are (-1, 0, 1) on every axis here
-                const int lin = glor[c];
-                const int cz = lin % n2, cy = (lin / n2) % n1, cx = lin / (n1 * n2);
-                const int ox = lane / 9 - 1, oy = (lane / 3) % 3 - 1, oz = lane % 3 - 1;
-                slot_shift[wv][lane][0] = cx + ox < 0 ? -Lx : (cx + ox >= n0 ? Lx : 0.0);
-                slot_shift[wv][lane][1] = cy + oy < 0 ? -Ly : (cy + oy >= n1 ? Ly : 0.0);
-                slot_shift[wv][lane][2] = cz + oz < 0 ? -Lz : (cz + oz >= n2 ? Lz : 0.0);
             }
         }
         int pre = cnt;
@@ -395,42 +390,52 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         }
         const int ncand = __builtin_amdgcn_readfirstlane(__shfl(pre, 26));
         if (lane < 32) {
-            cell_start[wv][lane] = s0;
-            cell_pre[wv][lane] = lane < 27 ? pre - cnt : ncand;
+            slot_first[wv][lane] = lane < 27 ? pre - cnt : ncand;
+            slot_start[wv][lane] = s0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int cb = 0; cb < ncand; cb += kWaveChunk) {
-            const int clen = min(kWaveChunk, ncand - cb);
-            for (int t = lane; t < clen; t += kWave) {
-                const int q = cb + t;
-                // last slot k with cell_pre[k] <= q (slots are sorted; empty ones repeat)
+        // home cell coordinates: the periodic shift of every stencil slot
+        int cx = 0, cy = 0, cz = 0;
+        if (known_shift) {
+            const int lin = __builtin_amdgcn_readfirstlane(glor[c]);
+            cz = lin % n2;
+            cy = (lin / n2) % n1;
+            cx = lin / (n1 * n2);
+        }
+        for (int cb = 0; cb < ncand; cb += kWave * K) {
+            double px[K], py[K], pz[K];
+            // periodic shift of the candidate's slot, 2 bits per axis: 1 = -L, 2 = +L
+            int pu[K], pt[K], pm[K], ps[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int q = cb + lane + kWave * k;
+                // the last slot whose first candidate is <= q (empty slots
+                // repeat the next slot's first candidate)
                 int lo = 0, hi = 26;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (cell_pre[wv][mid] <= q) lo = mid; else hi = mid - 1;
+                    if (slot_first[wv][mid] <= q) lo = mid; else hi = mid - 1;
                 }
-                const int src = cell_start[wv][lo] + (q - cell_pre[wv][lo]);
-                double px, py, pz;
-                int pt, pm;
-                load_xyz(gpos, src, px, py, pz);
-                load_meta(gmeta, src, pt, pm);
-                c_x[wv][t] = px;
-                c_y[wv][t] = py;
-                c_z[wv][t] = pz;
-                c_user[wv][t] = guser[src];
-                c_type[wv][t] = pt;
-                c_mol[wv][t] = pm;
-                if (known_shift) {
-                    c_sx[wv][t] = slot_shift[wv][lo][0];
-                    c_sy[wv][t] = slot_shift[wv][lo][1];
-                    c_sz[wv][t] = slot_shift[wv][lo][2];
+                const int slot = lo;
+                const int src = slot_start[wv][slot] + (q - slot_first[wv][slot]);
+                px[k] = py[k] = pz[k] = 0.0;
+                pu[k] = -1;
+                pt[k] = pm[k] = ps[k] = 0;
+                if (q < ncand) {
+                    load_xyz(gpos, src, px[k], py[k], pz[k]);
+                    load_meta(gmeta, src, pt[k], pm[k]);
+                    pu[k] = guser[src];
+                    if (known_shift) {
+                        // slot offsets are (-1, 0, 1) on every axis here
+                        const int ox = slot / 9 - 1, oy = (slot / 3) % 3 - 1, oz = slot % 3 - 1;
+                        ps[k] = (cx + ox < 0 ? 1 : (cx + ox >= n0 ? 2 : 0)) |
+                                (cy + oy < 0 ? 4 : (cy + oy >= n1 ? 8 : 0)) |
+                                (cz + oz < 0 ? 16 : (cz + oz >= n2 ? 32 : 0));
+                    }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int h = h0; h < h1; ++h) {
                 const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
                 const int ui = readlane_i(mu, h);
@@ -439,40 +444,41 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                 const int* hex = my_excl + h * max_excl;
                 int hc = readlane_i(mcnt, h);
                 RELRES_GLOBAL int* out = glist + (size_t)(r0 + h) * cap;
-                for (int base = 0; base < clen; base += kWave) {
-                    const int t = base + lane;
-                    bool keep = false;
-                    uint32_t entry = 0u;
-                    if (t < clen) {
-                        const int uj = c_user[wv][t];
-                        keep = uj != ui && !(same_mol && c_mol[wv][t] == moli);
-                        for (int k = 0; k < ne; ++k)
-                            if (hex[k] == uj) keep = false;
-                        if (keep) {
-                            if (known_shift)
-                                keep = member_shifted(xi, yi, zi, c_x[wv][t], c_y[wv][t],
-                                                      c_z[wv][t], c_sx[wv][t], c_sy[wv][t],
-                                                      c_sz[wv][t], rl2);
-                            else
-                                keep = member(make_double4(xi, yi, zi, 0.0),
-                                              make_double4(c_x[wv][t], c_y[wv][t], c_z[wv][t], 0.0),
-                                              Lx, Ly, Lz, hx, hy, hz, rl2);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (cb + kWave * k >= ncand) break;
+                    const int uj = pu[k];
+                    bool keep = uj >= 0 && uj != ui && !(same_mol && pm[k] == moli);
+                    for (int e = 0; e < ne; ++e)
+                        if (hex[e] == uj) keep = false;
+                    if (keep) {
+                        if (known_shift) {
+                            const int c6 = ps[k];
+                            const double sx = (c6 & 1) ? -Lx : ((c6 & 2) ? Lx : 0.0);
+                            const double sy = (c6 & 4) ? -Ly : ((c6 & 8) ? Ly : 0.0);
+                            const double sz = (c6 & 16) ? -Lz : ((c6 & 32) ? Lz : 0.0);
+                            keep = member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx, sy, sz,
+                                                  rl2);
                         }
-                        entry = (uint32_t)uj | ((uint32_t)c_type[wv][t] << kIdxBits);
+                        else
+                            keep = member(make_double4(xi, yi, zi, 0.0),
+                                          make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx,
+                                          hy, hz, rl2);
                     }
                     const uint64_t mask = __ballot(keep);
                     if (keep) {
                         const int p = hc + lanes_below(mask);
-                        if (p < cap) out[p] = (int)entry;
+                        if (p < cap) out[p] = (int)((uint32_t)uj | ((uint32_t)pt[k] << kIdxBits));
                     }
                     hc += __popcll(mask);
                 }
                 if (lane == h) mcnt = hc;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        // the slot table is rewritten for the next cell
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         h0 = h1;
     }
     if (lane < nh) {
@@ -1429,8 +1435,13 @@ hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_
         if (total == 0) return hipSuccess;
         const int mx = topo.excl_off ? topo.max_excl : 0;
         const size_t dyn = sizeof(int) * 4 * kRowsPerWave * (size_t)mx;
-        hipLaunchKernelGGL(k_lists_wave, dim3((total + 3) / 4), dim3(256), dyn, s, grids_dev,
-                           waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
+        // all waves resident at once (about 3 per SIMD): more candidates per lane
+        if (total <= kResidentListWaves)
+            hipLaunchKernelGGL(k_lists_wave<4>, dim3((total + 3) / 4), dim3(256), dyn, s,
+                               grids_dev, waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
+        else
+            hipLaunchKernelGGL(k_lists_wave<2>, dim3((total + 3) / 4), dim3(256), dyn, s,
+                               grids_dev, waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
         return hipGetLastError();
     }
     if (ncell_a + ncell_s == 0) return hipSuccess;
