@@ -15,6 +15,11 @@ Every function follows a passage of arXiv:2104.10231:
   grad          -- gradient of e_bar E + sum_i g_i . F_i with respect to the
                    per-type parameters and the positions (Eqs. 7-9 and 20
                    differentiated; the systems of Eqs. 7/8 are linear)
+  bonded        -- bonds, angles and Fourier dihedrals of the paper's
+                   simulations (Sec. 3.2), in md_oracle.c
+  pairs14       -- the 1-4 pairs: Eq. 20 scaled (Sec. 3.2)
+  nvt_run       -- velocity Verlet with a Nose-Hoover thermostat (the
+                   canonical ensemble of Sec. 3.2), all forces from the above
 """
 from __future__ import annotations
 
@@ -66,6 +71,13 @@ def lib():
                                   ctypes.c_int, _d, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                   _d, ctypes.c_double, _d, _d]
         L.oracle_grad.restype = ctypes.c_int
+        L.oracle_bonded.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int, _i, _d, _d,
+                                    ctypes.c_int, _i, _d, _d, ctypes.c_int, _i, _d, _i, _d,
+                                    _d, _d, _d]
+        L.oracle_dihedral_angle.argtypes = [_d, _d, _d, _d, _d]
+        L.oracle_dihedral_angle.restype = ctypes.c_double
+        L.oracle_pairs14.argtypes = [_d, _d, _i, ctypes.c_int, _d, ctypes.c_int, _i,
+                                     ctypes.c_double, _d, _d, _d]
         assert L.oracle_record_size() == REC
         _LIB = L
     return _LIB
@@ -256,3 +268,105 @@ def cg_params_eq15(eps_sites, sig_sites):
     b12 = np.sum(np.sqrt(e * s ** 12))
     b6 = np.sum(np.sqrt(e * s ** 6))
     return b12 ** (1.0 / 3.0) / b6 ** (1.0 / 3.0), b6 ** 4 / b12 ** 2
+
+
+# ----------------------------------------------------------------------------
+# molecular dynamics (Sec. 3.2)
+# ----------------------------------------------------------------------------
+
+FTM2V = 4.184e-4          # (kcal/mol/A) / amu -> A/fs^2
+KB = 0.0019872067         # kcal/mol/K
+
+
+def bonded(sys, pos=None):
+    """Bonds, angles and dihedrals of ``sys.bonded``: forces (N,3), energies
+    {bonds, angles, dihedrals} and virial {xx,yy,zz,xy,xz,yz}."""
+    b = sys.bonded
+    pos = _f64(sys.pos if pos is None else pos)
+    n = pos.shape[0]
+    F, E, W = np.zeros((n, 3)), np.zeros(3), np.zeros(6)
+    lib().oracle_bonded(n, pos, _f64(sys.box),
+                        len(b["bonds"]), _i32(b["bonds"]), _f64(b["bond_k"]), _f64(b["bond_r0"]),
+                        len(b["angles"]), _i32(b["angles"]), _f64(b["angle_k"]), _f64(b["angle_t0"]),
+                        len(b["dihedrals"]), _i32(b["dihedrals"]), _f64(b["dih_k"]),
+                        _i32(b["dih_n"]), _f64(b["dih_d"]), F, E, W)
+    return F, E, W
+
+
+def dihedral_angle(xi, xj, xk, xl, box):
+    return lib().oracle_dihedral_angle(_f64(xi), _f64(xj), _f64(xk), _f64(xl), _f64(box))
+
+
+def pairs14(sys, pos=None, table=None):
+    """The 1-4 pairs of ``sys.bonded``: Eq. 20 times ``scale14``.  Forces
+    (N,3), energy {total, FG part, CG part}, virial."""
+    b = sys.bonded
+    pos = _f64(sys.pos if pos is None else pos)
+    tab = setup_table(sys) if table is None else table
+    F, E, W = np.zeros((pos.shape[0], 3)), np.zeros(3), np.zeros(6)
+    p = _i32(b["pairs14"])
+    lib().oracle_pairs14(pos, _f64(sys.box), _i32(sys.types), sys.ntypes, _f64(tab.reshape(-1)),
+                         len(p), p, float(b["scale14"]), F, E, W)
+    return F, E, W
+
+
+def md_forces(sys, pos, table=None, nthreads: int = 0):
+    """All forces of the molecular model: Eq. 20 over non-excluded pairs,
+    scaled 1-4 pairs and bonded terms.  Returns (F, energies) with energies
+    = {non-bonded (Eq. 3), 1-4 pairs, bonds, angles, dihedrals} and the
+    total virial."""
+    tab = setup_table(sys) if table is None else table
+    F, E, W = compute(sys, pos=pos, table=tab, nthreads=nthreads)
+    F14, E14, W14 = pairs14(sys, pos=pos, table=tab)
+    Fb, Eb, Wb = bonded(sys, pos=pos)
+    return F + F14 + Fb, np.array([E[0], E14[0], Eb[0], Eb[1], Eb[2]]), W + W14 + Wb
+
+
+def nvt_run(sys, pos, vel, n_steps: int, dt: float, temperature: float, tau: float,
+            xi: float = 0.0, eta: float = 0.0, nthreads: int = 0):
+    """Velocity Verlet with one Nose-Hoover thermostat (Sec. 3.2's canonical
+    ensemble), the thermostat propagated in symmetric half steps:
+
+      thermostat(dt/2):  xi += dt/4 G;  v *= exp(-xi dt/2);  eta += dt/2 xi;
+                         xi += dt/4 G     with G = (2K - g kT)/Q
+      v += dt/2 F/m;  x += dt v;  F = F(x);  v += dt/2 F/m;  thermostat(dt/2)
+
+    with K the kinetic energy, g = 3N - 3, Q = g kT tau^2, units kcal/mol,
+    A, fs, amu.  Returns (pos, vel, xi, eta, trace) where trace holds per
+    step the potential energies, K and the conserved extended energy
+    K + U + Q xi^2 / 2 + g kT eta."""
+    b = sys.bonded
+    m = np.asarray(b["masses"], np.float64)[:, None]
+    tab = setup_table(sys)
+    x = np.array(pos, np.float64, copy=True)
+    v = np.array(vel, np.float64, copy=True)
+    n = x.shape[0]
+    g = 3 * n - 3
+    kT = KB * temperature
+    Q = g * kT * tau * tau
+
+    def kinetic(v):
+        return 0.5 * float(np.sum(m * v * v)) / FTM2V
+
+    def thermostat(v, xi, eta):
+        K = kinetic(v)
+        xi += 0.25 * dt * (2.0 * K - g * kT) / Q
+        s = np.exp(-xi * 0.5 * dt)
+        v = v * s
+        eta += 0.5 * dt * xi
+        K = kinetic(v)
+        xi += 0.25 * dt * (2.0 * K - g * kT) / Q
+        return v, xi, eta
+
+    F, U, _ = md_forces(sys, x, table=tab, nthreads=nthreads)
+    trace = []
+    for _ in range(n_steps):
+        v, xi, eta = thermostat(v, xi, eta)
+        v = v + 0.5 * dt * FTM2V * F / m
+        x = x + dt * v
+        F, U, _ = md_forces(sys, x, table=tab, nthreads=nthreads)
+        v = v + 0.5 * dt * FTM2V * F / m
+        v, xi, eta = thermostat(v, xi, eta)
+        K = kinetic(v)
+        trace.append(np.concatenate([U, [K, K + U.sum() + 0.5 * Q * xi * xi + g * kT * eta]]))
+    return x, v, xi, eta, np.array(trace)

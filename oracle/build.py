@@ -3,13 +3,13 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "relres_oracle.c")
+SRC = [os.path.join(HERE, "relres_oracle.c"), os.path.join(HERE, "md_oracle.c")]
 LIB = os.path.join(HERE, "librelres_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-ffp-contract=off", "-fno-fast-math", *SRC, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -450,6 +450,39 @@ long oracle_pairs(int n, const double *pos, const double *box, const int *types,
     return cnt;
 }
 
+/* Scaled 1-4 pairs (Sec. 3.2: the non-bonded interaction of atoms three bonds
+ * apart is scaled down, by a factor 2 in the paper): Eq. 20 of each listed
+ * pair (i, j) times `scale`, with d = x_j - x_i by the single-shift minimum
+ * image.  Forces are ADDED to F; E_out = {total, FG part, CG part} and W_out
+ * are added to.                                                            */
+void oracle_pairs14(const double *pos, const double *box, const int *types, int ntypes,
+                    const double *table, int np, const int *pairs, double scale,
+                    double *F, double *E_out, double *W_out)
+{
+    for (int t = 0; t < np; ++t) {
+        int i = pairs[2 * t], j = pairs[2 * t + 1];
+        double d[3];
+        min_image(pos + 3 * i, pos + 3 * j, box, d);        /* d = x_j - x_i */
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double *R = table + (size_t)(types[i] * ntypes + types[j]) * OR_REC;
+        double dudr, efg, ecg;
+        double u = oracle_pair(R, r, &dudr, NULL);
+        pair_split(R, r, &efg, &ecg);
+        double s = scale * dudr / r;                      /* F_i = +u~' d / r */
+        double f[3] = {s * d[0], s * d[1], s * d[2]};
+        for (int c = 0; c < 3; ++c) {
+            F[3 * i + c] += f[c];
+            F[3 * j + c] -= f[c];
+        }
+        E_out[0] += scale * u;
+        E_out[1] += scale * efg;
+        E_out[2] += scale * ecg;
+        /* W += (x_i - x_j) (x) F_i */
+        W_out[0] += -d[0] * f[0]; W_out[1] += -d[1] * f[1]; W_out[2] += -d[2] * f[2];
+        W_out[3] += -d[0] * f[1]; W_out[4] += -d[0] * f[2]; W_out[5] += -d[1] * f[2];
+    }
+}
+
 /* Evaluate Eq. 20 for a vector of distances with one type-pair record. */
 void oracle_pair_vec(const double *R, int m, const double *r,
                      double *u, double *dudr, int *which, double *e_fg, double *e_cg)

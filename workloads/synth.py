@@ -65,6 +65,7 @@ class System:
     shift: bool = True         # pair_modify shift yes / no
     cut_type: np.ndarray | None = None   # (ntypes, 4) per-type r_s-, r_s+, r_c-, r_c+
     cut_pair: np.ndarray | None = None   # (ntypes, ntypes, 4) per-type-pair distances
+    bonded: dict | None = None # bonded topology and parameters (see hexane_liquid)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -604,3 +605,121 @@ WORKLOADS = {
     "neopentane_20480": lambda seed=0: neopentane_liquid(seed),
     "copolymer_98304": lambda seed=0: copolymer_melt(seed),
 }
+
+
+# ----------------------------------------------------------------------------
+# molecular dynamics workload: hexane as a C3H7-C3H7 dimer
+# ----------------------------------------------------------------------------
+
+# united-atom masses (amu)
+MASS_CH3 = 15.035
+MASS_CH2 = 14.027
+# AMBER_UA bonded parameters of the paper's simulations, in kcal/mol and A:
+# E_bond = K (r - r0)^2, E_angle = K (theta - theta0)^2, E_dih = K (1 + cos(n phi - d))
+BOND_K = 180640.0 * ZJ / 100.0       # 180,640 zJ/nm^2
+BOND_R0 = 1.526
+ANGLE_K = 437.7 * ZJ                 # 437.7 zJ/rad^2
+ANGLE_T0 = 1.9618
+DIH_K = 13.9 * ZJ                    # 13.9 zJ (1 + cos 3 phi)
+DIH_N = 3
+SCALE_14 = 0.5
+
+
+def chain_positions(n: int, dihedrals, bond: float = BOND_R0, angle: float = ANGLE_T0) -> np.ndarray:
+    """Positions of an n-atom chain from internal coordinates: bond length,
+    bond angle and the n-3 dihedral angles (trans = pi), centred at the
+    origin."""
+    x = np.zeros((n, 3))
+    x[1] = [bond, 0.0, 0.0]
+    if n > 2:
+        x[2] = x[1] + bond * np.array([-np.cos(angle), np.sin(angle), 0.0])
+    for k in range(3, n):
+        a, b, c = x[k - 3], x[k - 2], x[k - 1]
+        bc = c - b
+        bc /= np.linalg.norm(bc)
+        nrm = np.cross(b - a, bc)
+        nrm /= np.linalg.norm(nrm)
+        m = np.cross(nrm, bc)
+        phi = dihedrals[k - 3]
+        d2 = np.array([-bond * np.cos(angle), bond * np.sin(angle) * np.cos(phi),
+                       bond * np.sin(angle) * np.sin(phi)])
+        x[k] = c + d2[0] * bc + d2[1] * m + d2[2] * nrm
+    return x - x.mean(axis=0)
+
+
+def hexane_liquid(seed: int = 0, n_mol: int = 1000, density: float = 0.0120,
+                  min_dist: float = 3.0, precision: int = 64, p_trans: float = 0.7,
+                  temperature: float = 290.0) -> System:
+    """Hexane as the dimer C3H7-C3H7 of the paper's dimer study: six united
+    atoms CH3-CH2-CH2-CH2-CH2-CH3 in two groups of three, the middle CH2 of
+    each group hybrid (types 0 CH3, 1 CH2, 2 hybrid CH2; Table 1's C3H7 rows,
+    r_s = 0.6 nm with a 0.05 nm zone, r_c 1.2/1.4 nm).  Chains are built from
+    internal coordinates (AMBER_UA bond 1.526 A and angle 1.9618 rad; each
+    dihedral trans with probability p_trans, else gauche +-60 deg), placed at
+    uniform random centres and orientations and redrawn when any atom comes
+    closer than min_dist to another chain.  Intramolecular 1-2, 1-3 and 1-4
+    pairs are excluded from the pair lists; the 1-4 pairs interact through
+    the pair potential scaled by 0.5.  ``bonded`` holds the bonds, angles,
+    dihedrals, 1-4 pairs, their parameters, the masses and Maxwell-Boltzmann
+    velocities at ``temperature`` (K) with zero total momentum."""
+    rng = np.random.default_rng(seed)
+    m = 6
+    n = n_mol * m
+    box_len = (n / density) ** (1.0 / 3.0)
+    box = np.full(3, box_len)
+    placed = np.zeros((0, 3))
+    mols = []
+    tries = 0
+    while len(mols) < n_mol:
+        tries += 1
+        if tries > 400 * n_mol:
+            raise RuntimeError("hexane_liquid: box too crowded")
+        u = rng.uniform(size=m - 3)
+        dih = np.where(u < p_trans, np.pi, np.where(u < 0.5 + 0.5 * p_trans, np.pi / 3, -np.pi / 3))
+        tpl = chain_positions(m, dih)
+        atoms = rng.uniform(0, box_len, size=3) + tpl @ random_rotations(rng, 1)[0].T
+        if len(placed):
+            d = atoms[:, None, :] - placed[None, :, :]
+            d -= box * np.round(d / box)
+            if (np.einsum("ijk,ijk->ij", d, d) < min_dist ** 2).any():
+                continue
+        mols.append(atoms)
+        placed = np.vstack([placed, atoms])
+    pos = np.vstack(mols)
+    types = np.tile(np.array([0, 2, 1, 1, 2, 0], np.int32), n_mol)
+    mol = np.repeat(np.arange(n_mol, dtype=np.int32), m)
+    base = (np.arange(n_mol) * m)[:, None]
+    bonds = (base[:, :, None] + np.array([[0, 1], [1, 2], [2, 3], [3, 4], [4, 5]])[None]).reshape(-1, 2)
+    angles = (base[:, :, None] + np.array([[0, 1, 2], [1, 2, 3], [2, 3, 4], [3, 4, 5]])[None]).reshape(-1, 3)
+    dihs = (base[:, :, None] + np.array([[0, 1, 2, 3], [1, 2, 3, 4], [2, 3, 4, 5]])[None]).reshape(-1, 4)
+    p14 = dihs[:, [0, 3]].copy()
+    # exclusions: 1-2, 1-3 and 1-4 partners of every atom (CSR, symmetric)
+    partners = [[] for _ in range(n)]
+    for a, b in np.vstack([bonds, angles[:, [0, 2]], p14]):
+        partners[a].append(b)
+        partners[b].append(a)
+    offs = np.zeros(n + 1, np.int32)
+    offs[1:] = np.cumsum([len(q) for q in partners])
+    idx = np.array([j for q in partners for j in sorted(q)], np.int32)
+    masses = np.where(types == 0, MASS_CH3, MASS_CH2).astype(np.float64)
+    # Maxwell-Boltzmann velocities in A/fs, zero total momentum
+    kT = 0.0019872067 * temperature                       # kcal/mol
+    sd = np.sqrt(kT / masses * 4.184e-4)                  # A/fs
+    vel = rng.normal(size=(n, 3)) * sd[:, None]
+    vel -= (masses[:, None] * vel).sum(axis=0) / masses.sum()
+    nb, na, nd = len(bonds), len(angles), len(dihs)
+    bonded = dict(bonds=bonds.astype(np.int32), bond_k=np.full(nb, BOND_K), bond_r0=np.full(nb, BOND_R0),
+                  angles=angles.astype(np.int32), angle_k=np.full(na, ANGLE_K),
+                  angle_t0=np.full(na, ANGLE_T0),
+                  dihedrals=dihs.astype(np.int32), dih_k=np.full(nd, DIH_K),
+                  dih_n=np.full(nd, DIH_N, np.int32), dih_d=np.zeros(nd),
+                  pairs14=p14.astype(np.int32), scale14=SCALE_14, masses=masses, velocities=vel)
+    eps = np.array([1.2158, 0.8198, 0.8198]) * ZJ
+    sig = np.array([3.905, 3.905, 3.905])
+    return System(name="hexane_liquid", pos=wrap(pos, box), box=box, types=types, mol=mol,
+                  excl_offsets=offs, excl_idx=idx, exclude_same_mol=False,
+                  eps_fg=eps, sig_fg=sig, eps_cg=np.array([0.0, 0.0, 8.4887 * ZJ]),
+                  sig_cg=np.array([0.0, 0.0, 3.905]), mix=MIX_GEOMETRIC, precision=precision,
+                  rs_in=5.75, rs_out=6.25, rc_in=12.0, rc_out=14.0, skin=2.0,
+                  bonded=bonded, meta=dict(seed=seed, n_mol=n_mol, density=density,
+                                           temperature=temperature))
