@@ -54,6 +54,7 @@ extern "C" {
 #define RELRES_ERR_NONFINITE       -8  /* a position was NaN or infinite     */
 #define RELRES_ERR_STATE           -9  /* call out of order                  */
 #define RELRES_ERR_LIST_RETRY     -10  /* asynchronous build overflowed: rows grown, build again */
+#define RELRES_ERR_STALE_LISTS    -11  /* dynamics: an atom moved more than half the skin between builds */
 
 #define RELRES_MIX_GEOMETRIC   0   /* eps, sigma geometric means (Sec. 2.3)    */
 #define RELRES_MIX_ARITHMETIC  1   /* Lorentz-Berthelot: eps geometric, sigma arithmetic */
@@ -246,6 +247,69 @@ int relres_set_pair_params(relres_ctx *ctx, const double *eps_fg, const double *
 int relres_backward(relres_ctx *ctx, const double *pos, const double *grad_forces,
                     const double *grad_energy, double *grad_pos, double *grad_pair,
                     void *stream);
+
+/* Bonded terms and scaled 1-4 pairs of the molecular model (Sec. 3.2: AMBER
+ * united-atom bonds, angles and Fourier dihedrals, 1-4 non-bonded pairs
+ * scaled down by a factor 2).  Host arrays, copied; atom indices in caller
+ * order, in [0, n_atoms) of the topology:
+ *   bonds     nbonds x 2 (i, j);         E = bond_k (r - bond_r0)^2
+ *   angles    nangles x 3 (i, j, k), j the vertex;
+ *                                        E = angle_k (theta - angle_t0)^2
+ *   dihedrals ndihedrals x 4 (i, j, k, l);
+ *                                        E = dih_k (1 + cos(dih_n phi - dih_d)),
+ *             phi the IUPAC dihedral (trans = pi)
+ *   pairs14   npairs14 x 2: these pairs interact through the pair potential
+ *             of Eq. 20 (FG and CG parts, their own distances) times
+ *             scale14; they should be excluded from the lists
+ *             (relres_set_topology) so that they are not counted twice.
+ * Spring constants follow the AMBER convention (no factor 1/2).  Requires a
+ * single system; replaces any earlier set; waits for the device first.     */
+int relres_set_bonded(relres_ctx *ctx, int nbonds, const int *bonds, const double *bond_k,
+                      const double *bond_r0, int nangles, const int *angles,
+                      const double *angle_k, const double *angle_t0, int ndihedrals,
+                      const int *dihedrals, const double *dih_k, const int *dih_n,
+                      const double *dih_d, int npairs14, const int *pairs14, double scale14);
+
+/* Bonded and scaled 1-4 forces at the device positions pos (N x 3 FP64),
+ * ADDED to forces (device, the type of relres_forces), with the box of the
+ * last build.  energy: device double[4] = {bonds, angles, dihedrals, 1-4
+ * pairs} or NULL; virial: device double[6] (their pair/term virial, the
+ * convention of relres_forces) or NULL.  FP64 throughout; every atom sums
+ * the terms it belongs to in a fixed order (deterministic, no atomics).
+ * Asynchronous on `stream`.                                                */
+int relres_bonded_forces(relres_ctx *ctx, const double *pos, void *forces, double *energy,
+                         double *virial, void *stream);
+
+/* Dynamics in the canonical ensemble (Sec. 3.2): velocity Verlet with one
+ * Nose-Hoover thermostat, propagated in symmetric half steps
+ *   xi += dt/4 G; v *= exp(-xi dt/2); eta += dt/2 xi; xi += dt/4 G,
+ *   G = (2K - g kT)/Q, g = 3N - 3, Q = g kT tau^2,
+ * around v += dt/2 a; x += dt v; forces; v += dt/2 a.
+ * masses: host double[n] (caller order); dt, tau: time unit of the caller;
+ * kT: energy unit; ftm2v converts force / mass to acceleration (4.184e-4 for
+ * kcal/mol, A, amu and fs).  The lists are rebuilt every rebuild_every steps
+ * (waiting for each build); if an atom moved more than half the skin since
+ * the previous build, relres_md_run fails with RELRES_ERR_STALE_LISTS.
+ * Resets the thermostat to xi = eta = 0.                                   */
+int relres_md_setup(relres_ctx *ctx, const double *masses, double dt, double kT, double tau,
+                    double ftm2v, int rebuild_every);
+
+/* Read (set = 0) or write (set = 1) the thermostat state xi, eta (host
+ * doubles).  Waits for the device.                                        */
+int relres_md_state(relres_ctx *ctx, double *xi, double *eta, int set);
+
+/* Run nsteps steps from the device positions pos and velocities vel (N x 3
+ * FP64 each, updated in place; positions are never wrapped), in the box of
+ * the last build.  Forces come from relres_forces (the context's precision)
+ * plus relres_bonded_forces when bonded terms are set.  With thermo_every >
+ * 0, every thermo_every-th step appends one row of 8 doubles to the device
+ * buffer thermo (nsteps / thermo_every rows): non-bonded energy (Eq. 3), 1-4
+ * energy, bond, angle and dihedral energies, kinetic energy, the extended
+ * energy K + U + Q xi^2/2 + g kT eta (conserved by the integrator), and the
+ * trace of the virial.  Enqueued on `stream`; waits at every list build and
+ * at the end.                                                              */
+int relres_md_run(relres_ctx *ctx, double *pos, double *vel, int nsteps, int thermo_every,
+                  double *thermo, void *stream);
 
 /* List statistics of the last build (host struct).  Entry counts and row
  * lengths are computed on demand by a small kernel the first time they are

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librelres_hip.so")
-SOURCES = [os.path.join(CSRC, "relres_kernels.hip"), os.path.join(CSRC, "relres_host.cpp")]
+SOURCES = [os.path.join(CSRC, "relres_kernels.hip"), os.path.join(CSRC, "relres_md.hip"),
+           os.path.join(CSRC, "relres_host.cpp")]
 ARCH = os.environ.get("RELRES_OFFLOAD_ARCH", "gfx950")
 
 

@@ -301,6 +301,18 @@ struct relres_ctx {
     relres_stats stats{};
     long long alloc_generation = 0;
 
+    // bonded terms and scaled 1-4 pairs (relres_set_bonded)
+    bool has_bonded = false;
+    double scale14 = 0.0;
+    DBuf d_term_off, d_term_ent, d_bonds, d_bond_par, d_angles, d_angle_par, d_dihs, d_dih_par;
+    DBuf d_p14_off, d_p14_idx, d_bond_part, d_bond_sum;
+    // dynamics (relres_md_setup / relres_md_run)
+    bool md_ready = false;
+    double md_ftm2v = 0.0;
+    int md_rebuild = 10;
+    DBuf d_mass, d_md_state, d_md_xref, d_md_F, d_md_E, d_md_W, d_md_part, d_md_stale;
+    unsigned int* h_stale = nullptr;
+
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_force, ev_build;
@@ -869,6 +881,7 @@ const char* relres_strerror(int code)
     case RELRES_ERR_NONFINITE: return "non-finite position";
     case RELRES_ERR_STATE: return "call out of order";
     case RELRES_ERR_LIST_RETRY: return "neighbour lists overflowed: capacity grown, build again";
+    case RELRES_ERR_STALE_LISTS: return "an atom moved more than half the skin since the last list build";
     default: return "unknown error";
     }
 }
@@ -1321,6 +1334,315 @@ int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
     return RELRES_OK;
 }
 
+int relres_set_bonded(relres_ctx* c, int nbonds, const int* bonds, const double* bond_k,
+                      const double* bond_r0, int nangles, const int* angles, const double* angle_k,
+                      const double* angle_t0, int ndihedrals, const int* dihedrals,
+                      const double* dih_k, const int* dih_n, const double* dih_d, int npairs14,
+                      const int* pairs14, double scale14)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
+    if (c->nsys != 1) return fail(RELRES_ERR_ARG, "bonded terms need a single system");
+    const int n = c->n;
+    if (nbonds < 0 || nangles < 0 || ndihedrals < 0 || npairs14 < 0)
+        return fail(RELRES_ERR_ARG, "negative term count");
+    if ((nbonds && (!bonds || !bond_k || !bond_r0)) ||
+        (nangles && (!angles || !angle_k || !angle_t0)) ||
+        (ndihedrals && (!dihedrals || !dih_k || !dih_n || !dih_d)) || (npairs14 && !pairs14))
+        return fail(RELRES_ERR_ARG, "term array is NULL");
+    if (!(std::isfinite(scale14) && scale14 >= 0.0)) return fail(RELRES_ERR_ARG, "bad 1-4 factor");
+    const long long total = (long long)nbonds * 2 + (long long)nangles * 3 + (long long)ndihedrals * 4;
+    if (std::max({nbonds, nangles, ndihedrals}) >= (1 << 28) || total > INT32_MAX)
+        return fail(RELRES_ERR_ARG, "too many bonded terms");
+    auto atom_ok = [n](int a) { return a >= 0 && a < n; };
+    for (int t = 0; t < nbonds; ++t)
+        if (!atom_ok(bonds[2 * t]) || !atom_ok(bonds[2 * t + 1]) || bonds[2 * t] == bonds[2 * t + 1] ||
+            !(std::isfinite(bond_k[t]) && std::isfinite(bond_r0[t]) && bond_r0[t] > 0.0))
+            return fail(RELRES_ERR_TOPOLOGY, "bad bond %d", t);
+    for (int t = 0; t < nangles; ++t) {
+        const int* q = angles + 3 * t;
+        if (!atom_ok(q[0]) || !atom_ok(q[1]) || !atom_ok(q[2]) || q[0] == q[1] || q[1] == q[2] ||
+            q[0] == q[2] || !(std::isfinite(angle_k[t]) && std::isfinite(angle_t0[t])))
+            return fail(RELRES_ERR_TOPOLOGY, "bad angle %d", t);
+    }
+    for (int t = 0; t < ndihedrals; ++t) {
+        const int* q = dihedrals + 4 * t;
+        bool ok = std::isfinite(dih_k[t]) && std::isfinite(dih_d[t]) && dih_n[t] >= 0;
+        for (int u = 0; u < 4; ++u) ok = ok && atom_ok(q[u]);
+        for (int u = 0; u < 4 && ok; ++u)
+            for (int v = u + 1; v < 4; ++v) ok = ok && q[u] != q[v];
+        if (!ok) return fail(RELRES_ERR_TOPOLOGY, "bad dihedral %d", t);
+    }
+    for (int t = 0; t < npairs14; ++t)
+        if (!atom_ok(pairs14[2 * t]) || !atom_ok(pairs14[2 * t + 1]) ||
+            pairs14[2 * t] == pairs14[2 * t + 1])
+            return fail(RELRES_ERR_TOPOLOGY, "bad 1-4 pair %d", t);
+
+    // per atom: the terms it belongs to (bonds, angles, dihedrals, in order)
+    std::vector<std::vector<uint32_t>> per(n);
+    auto add = [&](int atom, uint32_t kind, uint32_t slot, int t) {
+        per[atom].push_back((kind << 30) | (slot << 28) | (uint32_t)t);
+    };
+    for (int t = 0; t < nbonds; ++t)
+        for (int u = 0; u < 2; ++u) add(bonds[2 * t + u], 0, u, t);
+    for (int t = 0; t < nangles; ++t)
+        for (int u = 0; u < 3; ++u) add(angles[3 * t + u], 1, u, t);
+    for (int t = 0; t < ndihedrals; ++t)
+        for (int u = 0; u < 4; ++u) add(dihedrals[4 * t + u], 2, u, t);
+    std::vector<int> toff(n + 1, 0);
+    std::vector<uint32_t> tent;
+    for (int a = 0; a < n; ++a) {
+        tent.insert(tent.end(), per[a].begin(), per[a].end());
+        toff[a + 1] = (int)tent.size();
+    }
+    std::vector<std::vector<int>> part(n);
+    for (int t = 0; t < npairs14; ++t) {
+        part[pairs14[2 * t]].push_back(pairs14[2 * t + 1]);
+        part[pairs14[2 * t + 1]].push_back(pairs14[2 * t]);
+    }
+    std::vector<int> poff(n + 1, 0), pidx;
+    for (int a = 0; a < n; ++a) {
+        std::sort(part[a].begin(), part[a].end());
+        pidx.insert(pidx.end(), part[a].begin(), part[a].end());
+        poff[a + 1] = (int)pidx.size();
+    }
+    std::vector<int2> hb(nbonds);
+    std::vector<double2> hbp(nbonds);
+    for (int t = 0; t < nbonds; ++t) {
+        hb[t] = make_int2(bonds[2 * t], bonds[2 * t + 1]);
+        hbp[t] = make_double2(bond_k[t], bond_r0[t]);
+    }
+    std::vector<int4> ha(nangles);
+    std::vector<double2> hap(nangles);
+    for (int t = 0; t < nangles; ++t) {
+        ha[t] = make_int4(angles[3 * t], angles[3 * t + 1], angles[3 * t + 2], 0);
+        hap[t] = make_double2(angle_k[t], angle_t0[t]);
+    }
+    std::vector<int4> hd(ndihedrals);
+    std::vector<double4> hdp(ndihedrals);
+    for (int t = 0; t < ndihedrals; ++t) {
+        hd[t] = make_int4(dihedrals[4 * t], dihedrals[4 * t + 1], dihedrals[4 * t + 2],
+                          dihedrals[4 * t + 3]);
+        hdp[t] = make_double4(dih_k[t], (double)dih_n[t], dih_d[t], 0.0);
+    }
+    // the buffers may be in use by work still queued on any stream
+    HIP_TRY(hipDeviceSynchronize());
+    long long* gen = &c->alloc_generation;
+    auto up = [&](DBuf& b, const void* src, size_t bytes) -> int {
+        TRY(ensure(b, bytes, gen));
+        if (bytes) HIP_TRY(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        return RELRES_OK;
+    };
+    TRY(up(c->d_term_off, toff.data(), sizeof(int) * toff.size()));
+    TRY(up(c->d_term_ent, tent.data(), sizeof(uint32_t) * tent.size()));
+    TRY(up(c->d_bonds, hb.data(), sizeof(int2) * hb.size()));
+    TRY(up(c->d_bond_par, hbp.data(), sizeof(double2) * hbp.size()));
+    TRY(up(c->d_angles, ha.data(), sizeof(int4) * ha.size()));
+    TRY(up(c->d_angle_par, hap.data(), sizeof(double2) * hap.size()));
+    TRY(up(c->d_dihs, hd.data(), sizeof(int4) * hd.size()));
+    TRY(up(c->d_dih_par, hdp.data(), sizeof(double4) * hdp.size()));
+    TRY(up(c->d_p14_off, poff.data(), sizeof(int) * poff.size()));
+    TRY(up(c->d_p14_idx, pidx.data(), sizeof(int) * pidx.size()));
+    TRY(ensure(c->d_bond_part, sizeof(double) * 10 * (size_t)std::max(1, bonded_blocks(n)), gen));
+    TRY(ensure(c->d_bond_sum, sizeof(double) * 16, gen));
+    c->scale14 = scale14;
+    c->has_bonded = true;
+    return RELRES_OK;
+}
+
+namespace {
+
+int enqueue_bonded(relres_ctx* c, const double* pos, void* forces, bool sums, hipStream_t s)
+{
+    BondedArgs b{};
+    b.pos = pos;
+    for (int k = 0; k < 3; ++k) b.box[k] = c->box[k];
+    b.n = c->n;
+    b.term_off = c->d_term_off.as<int>();
+    b.term_ent = c->d_term_ent.as<uint32_t>();
+    b.bonds = c->d_bonds.as<int2>();
+    b.bond_par = c->d_bond_par.as<double2>();
+    b.angles = c->d_angles.as<int4>();
+    b.angle_par = c->d_angle_par.as<double2>();
+    b.dihs = c->d_dihs.as<int4>();
+    b.dih_par = c->d_dih_par.as<double4>();
+    b.p14_off = c->d_p14_off.as<int>();
+    b.p14_idx = c->d_p14_idx.as<int>();
+    b.scale14 = c->scale14;
+    b.types = c->d_types.as<int>();
+    b.ntypes = c->ntypes;
+    b.coef64 = c->d_coef64.as<PairCoef<double>>();
+    b.pcut64 = c->d_pcut64.as<Cutoffs<double>>();
+    b.forces = forces;
+    b.partial = sums ? c->d_bond_part.as<double>() : nullptr;
+    HIP_TRY(launch_bonded(b, c->precision, s));
+    if (sums)
+        HIP_TRY(launch_sum_partials(c->d_bond_part.as<double>(), bonded_blocks(c->n), 10,
+                                    c->d_bond_sum.as<double>(), s));
+    return RELRES_OK;
+}
+
+}  // namespace
+
+int relres_bonded_forces(relres_ctx* c, const double* pos, void* forces, double* energy,
+                         double* virial, void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->has_bonded) return fail(RELRES_ERR_STATE, "relres_set_bonded has not been called");
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no box yet: call relres_build_lists first");
+    if (c->n == 0) return RELRES_OK;
+    if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool sums = energy || virial;
+    TRY(enqueue_bonded(c, pos, forces, sums, s));
+    const double* sum = c->d_bond_sum.as<double>();
+    if (energy) HIP_TRY(hipMemcpyAsync(energy, sum, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (virial) HIP_TRY(hipMemcpyAsync(virial, sum + 4, 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return RELRES_OK;
+}
+
+int relres_md_setup(relres_ctx* c, const double* masses, double dt, double kT, double tau,
+                    double ftm2v, int rebuild_every)
+{
+    if (!c || !masses) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
+    if (c->nsys != 1) return fail(RELRES_ERR_ARG, "dynamics need a single system");
+    if (!(dt > 0.0 && std::isfinite(dt) && kT > 0.0 && std::isfinite(kT) && tau > 0.0 &&
+          ftm2v > 0.0 && std::isfinite(ftm2v) && rebuild_every >= 1 && c->n >= 2))
+        return fail(RELRES_ERR_ARG, "need dt, kT, tau, ftm2v > 0, rebuild_every >= 1, n >= 2");
+    const int n = c->n;
+    for (int i = 0; i < n; ++i)
+        if (!(masses[i] > 0.0 && std::isfinite(masses[i]))) return fail(RELRES_ERR_ARG, "bad mass %d", i);
+    HIP_TRY(hipDeviceSynchronize());
+    long long* gen = &c->alloc_generation;
+    TRY(ensure(c->d_mass, sizeof(double) * n, gen));
+    HIP_TRY(hipMemcpy(c->d_mass.p, masses, sizeof(double) * n, hipMemcpyHostToDevice));
+    TRY(ensure(c->d_md_state, sizeof(MdState), gen));
+    TRY(ensure(c->d_md_xref, sizeof(double) * 3 * n, gen));
+    TRY(ensure(c->d_md_F, (c->precision == 64 ? 8 : 4) * 3 * (size_t)n, gen));
+    TRY(ensure(c->d_md_E, sizeof(double) * 3, gen));
+    TRY(ensure(c->d_md_W, sizeof(double) * 6, gen));
+    TRY(ensure(c->d_md_part, sizeof(double) * (size_t)bonded_blocks(n), gen));
+    TRY(ensure(c->d_md_stale, 64, gen));
+    TRY(ensure(c->d_bond_sum, sizeof(double) * 16, gen));
+    if (!c->h_stale && hipHostMalloc((void**)&c->h_stale, 64, hipHostMallocDefault) != hipSuccess)
+        return fail(RELRES_ERR_HIP, "pinned host allocation failed");
+    MdState st{};
+    st.xi = st.eta = 0.0;
+    st.K = 0.0;
+    st.s2 = 1.0;
+    st.s_apply = 1.0;
+    st.s_last = 1.0;
+    st.dt = dt;
+    st.kT = kT;
+    st.g = 3.0 * n - 3.0;
+    st.Q = st.g * kT * tau * tau;
+    HIP_TRY(hipMemcpy(c->d_md_state.p, &st, sizeof(MdState), hipMemcpyHostToDevice));
+    c->md_ftm2v = ftm2v;
+    c->md_rebuild = rebuild_every;
+    c->md_ready = true;
+    return RELRES_OK;
+}
+
+int relres_md_state(relres_ctx* c, double* xi, double* eta, int set)
+{
+    if (!c || !xi || !eta) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (!c->md_ready) return fail(RELRES_ERR_STATE, "relres_md_setup has not been called");
+    HIP_TRY(hipDeviceSynchronize());
+    MdState st{};
+    HIP_TRY(hipMemcpy(&st, c->d_md_state.p, sizeof(MdState), hipMemcpyDeviceToHost));
+    if (set) {
+        if (!(std::isfinite(*xi) && std::isfinite(*eta))) return fail(RELRES_ERR_ARG, "non-finite state");
+        st.xi = *xi;
+        st.eta = *eta;
+        HIP_TRY(hipMemcpy(c->d_md_state.p, &st, sizeof(MdState), hipMemcpyHostToDevice));
+    } else {
+        *xi = st.xi;
+        *eta = st.eta;
+    }
+    return RELRES_OK;
+}
+
+namespace {
+
+// Build the lists at pos (waiting for the build), after checking that no
+// atom moved more than half the skin since the previous build.
+int md_rebuild(relres_ctx* c, const double* pos, hipStream_t s, bool check)
+{
+    if (check) {
+        HIP_TRY(hipMemcpyAsync(c->h_stale, c->d_md_stale.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*c->h_stale)
+            return fail(RELRES_ERR_STALE_LISTS, "an atom moved more than half the skin between list "
+                        "builds: rebuild more often or use a larger skin");
+    }
+    const double box[3] = {c->box[0], c->box[1], c->box[2]};
+    TRY(build_checked(c, pos, box, s));
+    HIP_TRY(hipMemcpyAsync(c->d_md_xref.p, pos, sizeof(double) * 3 * c->n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_clear_words((unsigned long long*)c->d_md_stale.p, 8, s));
+    return RELRES_OK;
+}
+
+}  // namespace
+
+int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int thermo_every,
+                  double* thermo, void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->md_ready) return fail(RELRES_ERR_STATE, "relres_md_setup has not been called");
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no box yet: call relres_build_lists first");
+    if (!pos || !vel || nsteps < 0 || thermo_every < 0 || (thermo_every > 0 && !thermo))
+        return fail(RELRES_ERR_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int prec = c->precision;
+    void* F = c->d_md_F.p;
+    MdArgs m{};
+    m.n = c->n;
+    m.ftm2v = c->md_ftm2v;
+    m.pos = pos;
+    m.vel = vel;
+    m.forces = F;
+    m.mass = c->d_mass.as<double>();
+    m.xref = c->d_md_xref.as<double>();
+    m.half_skin2 = 0.25 * c->skin * c->skin;
+    m.stale = (unsigned*)c->d_md_stale.p;
+    m.partial = c->d_md_part.as<double>();
+    m.st = c->d_md_state.as<MdState>();
+    const int nblk = bonded_blocks(c->n);
+    // forces at the starting positions and the kinetic energy
+    TRY(md_rebuild(c, pos, s, false));
+    TRY(relres_forces(c, pos, F, nullptr, nullptr, s));
+    if (c->has_bonded) TRY(enqueue_bonded(c, pos, F, false, s));
+    HIP_TRY(launch_md_kick(m, prec, 0, s));
+    HIP_TRY(launch_md_second(m.st, m.partial, nblk, m.ftm2v, 0, s));
+    for (int step = 1; step <= nsteps; ++step) {
+        HIP_TRY(launch_md_first(m.st, s));
+        HIP_TRY(launch_md_drift(m, prec, s));
+        if (step % c->md_rebuild == 0) TRY(md_rebuild(c, pos, s, true));
+        const bool out = thermo_every > 0 && step % thermo_every == 0;
+        TRY(relres_forces(c, pos, F, out ? c->d_md_E.as<double>() : nullptr,
+                          out ? c->d_md_W.as<double>() : nullptr, s));
+        if (c->has_bonded) TRY(enqueue_bonded(c, pos, F, out, s));
+        HIP_TRY(launch_md_kick(m, prec, 1, s));
+        HIP_TRY(launch_md_second(m.st, m.partial, nblk, m.ftm2v, 1, s));
+        if (out) {
+            if (!c->has_bonded)
+                HIP_TRY(launch_clear_words((unsigned long long*)c->d_bond_sum.p, 16, s));
+            HIP_TRY(launch_md_thermo(m.st, c->d_md_E.as<double>(), c->d_md_W.as<double>(),
+                                     c->d_bond_sum.as<double>(),
+                                     thermo + (size_t)8 * (step / thermo_every - 1), s));
+        }
+    }
+    HIP_TRY(launch_md_finish(m, s));
+    // the last steps since the previous build must not have outrun the skin either
+    HIP_TRY(hipMemcpyAsync(c->h_stale, c->d_md_stale.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (*c->h_stale)
+        return fail(RELRES_ERR_STALE_LISTS, "an atom moved more than half the skin between list "
+                    "builds: rebuild more often or use a larger skin");
+    return RELRES_OK;
+}
+
 int relres_list_stats(relres_ctx* c, relres_stats* out)
 {
     if (!c || !out) return fail(RELRES_ERR_ARG, "NULL argument");
@@ -1414,6 +1736,12 @@ void relres_destroy(relres_ctx* c)
     if (!c) return;
     (void)hipDeviceSynchronize();
     for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial, &c->d_sys, &c->d_boxes, &c->d_row_ew}) release(*b);
+    for (DBuf* b : {&c->d_term_off, &c->d_term_ent, &c->d_bonds, &c->d_bond_par, &c->d_angles,
+                    &c->d_angle_par, &c->d_dihs, &c->d_dih_par, &c->d_p14_off, &c->d_p14_idx,
+                    &c->d_bond_part, &c->d_bond_sum, &c->d_mass, &c->d_md_state, &c->d_md_xref,
+                    &c->d_md_F, &c->d_md_E, &c->d_md_W, &c->d_md_part, &c->d_md_stale})
+        release(*b);
+    if (c->h_stale) (void)hipHostFree(c->h_stale);
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
                     &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials,

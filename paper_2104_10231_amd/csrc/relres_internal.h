@@ -181,6 +181,68 @@ hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const doub
                                 int n_arow, int nsys, double* energy, double* virial,
                                 hipStream_t s);
 
+// Bonded terms and scaled 1-4 pairs (relres_md.hip).  Per atom, the terms
+// it belongs to: term_ent packs kind (bits 30-31: 0 bond, 1 angle,
+// 2 dihedral), the atom's slot in the term (bits 28-29) and the term index.
+struct BondedArgs {
+    const double* pos;
+    double box[3];
+    int n;
+    const int* term_off;              // [n + 1]
+    const uint32_t* term_ent;
+    const int2* bonds;
+    const double2* bond_par;          // K, r0
+    const int4* angles;               // i, j (vertex), k, unused
+    const double2* angle_par;         // K, theta0
+    const int4* dihs;
+    const double4* dih_par;           // K, n, d, unused
+    const int* p14_off;               // [n + 1]
+    const int* p14_idx;               // 1-4 partners of each atom
+    double scale14;
+    const int* types;
+    int ntypes;
+    const PairCoef<double>* coef64;
+    const Cutoffs<double>* pcut64;
+    void* forces;                     // N x 3 of the force type; added to
+    double* partial;                  // per block: 4 energies, 6 virial; or null
+};
+hipError_t launch_bonded(const BondedArgs& b, int force_prec, hipStream_t s);
+int bonded_blocks(int n);
+// out[k] = sum of partial[blk * K + k] over blocks, in block order
+hipError_t launch_sum_partials(const double* partial, int nblocks, int K, double* out,
+                               hipStream_t s);
+
+// Thermostat and integrator state on the device.
+struct MdState {
+    double xi, eta;                   // thermostat velocity and position
+    double K;                         // kinetic energy of the true velocities
+    double s2;                        // pending velocity scale (true v = stored v * s2)
+    double s_apply;                   // scale the next drift applies to stored v
+    double s_last;
+    double dt, kT, g, Q;
+};
+struct MdArgs {
+    int n;
+    double ftm2v;                     // force / mass -> acceleration
+    double* pos;                      // N x 3, updated in place
+    double* vel;                      // N x 3, stored velocities
+    const void* forces;               // N x 3 of the force type
+    const double* mass;
+    const double* xref;               // positions at the last list build
+    double half_skin2;                // (skin / 2)^2
+    unsigned int* stale;              // set when an atom moved more than skin / 2
+    double* partial;                  // per block kinetic partial
+    MdState* st;
+};
+hipError_t launch_md_first(MdState* st, hipStream_t s);
+hipError_t launch_md_drift(const MdArgs& m, int force_prec, hipStream_t s);
+hipError_t launch_md_kick(const MdArgs& m, int force_prec, int kick, hipStream_t s);
+hipError_t launch_md_second(MdState* st, const double* partial, int nblocks, double ftm2v,
+                            int thermostat, hipStream_t s);
+hipError_t launch_md_finish(const MdArgs& m, hipStream_t s);
+hipError_t launch_md_thermo(const MdState* st, const double* e_nb, const double* w_nb,
+                            const double* eb, double* row, hipStream_t s);
+
 // Row record field y: atom type in the low kTypeBits bits, system above.
 constexpr int kTypeBits = 5;
 constexpr int kRowsPerWave = 8;       // home rows per wave of the list kernel

@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(HERE, "librelres_hip.so")
 
 RELRES_OK = 0
 RELRES_ERR_LIST_RETRY = -10
+RELRES_ERR_STALE_LISTS = -11
+FTM2V_REAL = 4.184e-4          # (kcal/mol/A) / amu -> A/fs^2
+KB_REAL = 0.0019872067         # kcal/mol/K
 MIX_GEOMETRIC = 0
 MIX_ARITHMETIC = 1
 MIX_SIXTHPOWER = 2
@@ -85,6 +88,18 @@ SIGNATURES = {
     "relres_get_timing": (ctypes.c_int, [ctypes.c_void_p, _c_double_p,
                                          ctypes.POINTER(ctypes.c_longlong), _c_double_p,
                                          ctypes.POINTER(ctypes.c_longlong)]),
+    "relres_set_bonded": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, _c_double_p,
+                                         _c_double_p, ctypes.c_int, ctypes.c_void_p, _c_double_p,
+                                         _c_double_p, ctypes.c_int, ctypes.c_void_p, _c_double_p,
+                                         ctypes.c_void_p, _c_double_p, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_double]),
+    "relres_bonded_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "relres_md_setup": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    "relres_md_state": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, ctypes.c_int]),
+    "relres_md_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_destroy": (None, [ctypes.c_void_p]),
 }
 
@@ -364,6 +379,67 @@ class RelRes:
                                            ctypes.byref(bm), ctypes.byref(bc)), "relres_get_timing")
         return dict(force_ms=fm.value, force_calls=fc.value, build_ms=bm.value,
                     build_calls=bc.value)
+
+    # -- molecular model and dynamics -----------------------------------------
+    def set_bonded(self, bonded: dict):
+        """Bonds, angles, dihedrals and scaled 1-4 pairs (keys as in
+        ``workloads.hexane_liquid``)."""
+        b = bonded
+        arr = dict(bonds=_i32(b["bonds"]), bond_k=_f64(b["bond_k"]), bond_r0=_f64(b["bond_r0"]),
+                   angles=_i32(b["angles"]), angle_k=_f64(b["angle_k"]), angle_t0=_f64(b["angle_t0"]),
+                   dihedrals=_i32(b["dihedrals"]), dih_k=_f64(b["dih_k"]), dih_n=_i32(b["dih_n"]),
+                   dih_d=_f64(b["dih_d"]), pairs14=_i32(b["pairs14"]))
+        self._bonded = arr
+        _check(self._lib.relres_set_bonded(
+            self._ctx, len(arr["bond_k"]), _ptr(arr["bonds"]), _dp(arr["bond_k"]), _dp(arr["bond_r0"]),
+            len(arr["angle_k"]), _ptr(arr["angles"]), _dp(arr["angle_k"]), _dp(arr["angle_t0"]),
+            len(arr["dih_k"]), _ptr(arr["dihedrals"]), _dp(arr["dih_k"]), _ptr(arr["dih_n"]),
+            _dp(arr["dih_d"]), len(arr["pairs14"]), _ptr(arr["pairs14"]), float(b["scale14"])),
+            "relres_set_bonded")
+
+    def bonded_forces(self, pos: torch.Tensor, forces: torch.Tensor, want_energy: bool = True,
+                      stream=None):
+        """Add the bonded and 1-4 forces to ``forces``; returns (energy[4],
+        virial[6]) device tensors (None when not wanted)."""
+        pos = self._pos(pos)
+        E = torch.empty(4, dtype=torch.float64, device=pos.device) if want_energy else None
+        W = torch.empty(6, dtype=torch.float64, device=pos.device) if want_energy else None
+        _check(self._lib.relres_bonded_forces(self._ctx, pos.data_ptr() if self.n else None,
+                                              forces.data_ptr() if self.n else None,
+                                              E.data_ptr() if E is not None else None,
+                                              W.data_ptr() if W is not None else None,
+                                              _stream(stream)), "relres_bonded_forces")
+        return E, W
+
+    def md_setup(self, masses, dt: float, temperature: float, tau: float,
+                 rebuild_every: int = 10, kB: float = KB_REAL, ftm2v: float = FTM2V_REAL):
+        """Nose-Hoover velocity Verlet (defaults: kcal/mol, A, amu, fs, K)."""
+        m = _f64(masses)
+        self._masses = m
+        _check(self._lib.relres_md_setup(self._ctx, _dp(m), float(dt), float(kB * temperature),
+                                         float(tau), float(ftm2v), int(rebuild_every)),
+               "relres_md_setup")
+
+    def md_state(self, xi: Optional[float] = None, eta: Optional[float] = None):
+        """Return (xi, eta); set them when both are given."""
+        a, b = ctypes.c_double(xi or 0.0), ctypes.c_double(eta or 0.0)
+        setting = xi is not None and eta is not None
+        _check(self._lib.relres_md_state(self._ctx, ctypes.byref(a), ctypes.byref(b), int(setting)),
+               "relres_md_state")
+        return a.value, b.value
+
+    def md_run(self, pos: torch.Tensor, vel: torch.Tensor, nsteps: int, thermo_every: int = 0,
+               stream=None):
+        """Advance ``pos`` and ``vel`` (float64 (N, 3) CUDA tensors) in
+        place; returns the thermo rows (nsteps // thermo_every, 8) or None."""
+        pos = self._pos(pos)
+        vel = self._pos(vel)
+        rows = nsteps // thermo_every if thermo_every > 0 else 0
+        th = torch.empty((max(rows, 1), 8), dtype=torch.float64, device=pos.device)
+        _check(self._lib.relres_md_run(self._ctx, pos.data_ptr(), vel.data_ptr(), int(nsteps),
+                                       int(thermo_every), th.data_ptr() if rows else None,
+                                       _stream(stream)), "relres_md_run")
+        return th[:rows] if rows else None
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -110,6 +110,11 @@ def test_null_arguments_are_rejected(lib):
     assert lib.relres_build_lists(None, None, None, None) == -1
     assert lib.relres_forces(None, None, None, None, None, None) == -1
     assert lib.relres_set_launch(None, 4, 4) == -1
+    assert lib.relres_set_bonded(None, 0, None, None, None, 0, None, None, None, 0, None, None,
+                                 None, None, 0, None, 0.5) == -1
+    assert lib.relres_bonded_forces(None, None, None, None, None, None) == -1
+    assert lib.relres_md_setup(None, None, 1.0, 1.0, 1.0, 1.0, 1) == -1
+    assert lib.relres_md_run(None, None, None, 1, 0, None, None) == -1
     lib.relres_destroy(None)
 
 

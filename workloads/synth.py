@@ -655,9 +655,10 @@ def hexane_liquid(seed: int = 0, n_mol: int = 1000, density: float = 0.0120,
     each group hybrid (types 0 CH3, 1 CH2, 2 hybrid CH2; Table 1's C3H7 rows,
     r_s = 0.6 nm with a 0.05 nm zone, r_c 1.2/1.4 nm).  Chains are built from
     internal coordinates (AMBER_UA bond 1.526 A and angle 1.9618 rad; each
-    dihedral trans with probability p_trans, else gauche +-60 deg), placed at
-    uniform random centres and orientations and redrawn when any atom comes
-    closer than min_dist to another chain.  Intramolecular 1-2, 1-3 and 1-4
+    dihedral trans with probability p_trans, else gauche +-60 deg; conformers
+    that bring atoms four or more bonds apart closer than min_dist are
+    redrawn), placed at uniform random centres and orientations and redrawn
+    when any atom comes closer than min_dist to another chain.  Intramolecular 1-2, 1-3 and 1-4
     pairs are excluded from the pair lists; the 1-4 pairs interact through
     the pair potential scaled by 0.5.  ``bonded`` holds the bonds, angles,
     dihedrals, 1-4 pairs, their parameters, the masses and Maxwell-Boltzmann
@@ -677,6 +678,11 @@ def hexane_liquid(seed: int = 0, n_mol: int = 1000, density: float = 0.0120,
         u = rng.uniform(size=m - 3)
         dih = np.where(u < p_trans, np.pi, np.where(u < 0.5 + 0.5 * p_trans, np.pi / 3, -np.pi / 3))
         tpl = chain_positions(m, dih)
+        # atoms four or more bonds apart interact; a g+g- sequence would put
+        # them on top of each other
+        far = [(i, j) for i in range(m) for j in range(i + 4, m)]
+        if any(np.linalg.norm(tpl[i] - tpl[j]) < min_dist for i, j in far):
+            continue
         atoms = rng.uniform(0, box_len, size=3) + tpl @ random_rotations(rng, 1)[0].T
         if len(placed):
             d = atoms[:, None, :] - placed[None, :, :]
