@@ -304,6 +304,70 @@ def sequential_seconds(b, pos, args, cycles, every):
     return dt_s
 
 
+def md_bench(args):
+    """Dynamics workload: hexane as the C3H7-C3H7 dimer (1000 molecules, 6000
+    united atoms, 0.016 atoms/A^3), NVT at 290 K with a Nose-Hoover
+    thermostat (tau 100 fs), dt 1 fs, lists every 10 steps, FP32 forces with
+    FP64 energies; RelRes (r_s = 0.6 nm) and the conventional 14 A model
+    from the same start.  Timed: the production run; reported: atom-steps/s,
+    ns/day, and the means of the non-bonded energy and of the virial per
+    molecule with their RelRes/conventional ratios."""
+    import numpy as np
+    import torch
+    import workloads as w
+    s = w.hexane_liquid(args.seed, n_mol=1000, density=0.016, precision=32)
+    n_mol = int(s.mol.max()) + 1
+    dt_fs, T, tau, every = 1.0, 290.0, 100.0, 10
+    thermo_every = 50
+    legs = {}
+    for name, sys_ in (("relres", s), ("conventional", s.conventional())):
+        rr = make(sys_, 32, 32)
+        rr.set_bonded(sys_.bonded)
+        p = torch.from_numpy(sys_.pos).cuda()
+        v = torch.from_numpy(np.ascontiguousarray(sys_.bonded["velocities"])).cuda()
+        rr.build_lists(p, sys_.box)
+        rr.md_setup(sys_.bonded["masses"], dt_fs, T, tau, rebuild_every=every)
+        rr.md_run(p, v, args.md_equil, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = rr.md_run(p, v, args.md_steps, thermo_every)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        th = th.cpu().numpy()
+        st = rr.stats()
+        rr.close()
+        g = 3 * s.n - 3
+        legs[name] = {
+            "value": s.n * args.md_steps / el, "ms_per_step": el * 1e3 / args.md_steps,
+            "ns_per_day": args.md_steps * dt_fs * 1e-6 / el * 86400.0,
+            "U_nonbonded_per_molecule": float(th[:, 0].mean() / n_mol),
+            "W_per_molecule": float(th[:, 7].mean() / 3.0 / n_mol),
+            "T_mean_K": float((2.0 * th[:, 5] / (g * 0.0019872067)).mean()),
+            "extended_energy_drift_per_atom": float((th[-1, 6] - th[0, 6]) / s.n),
+            "list_entries": st["atom_entries"] + st["site_entries"],
+        }
+        log(f"[bench] md {name}: {legs[name]['ms_per_step']:.4f} ms/step, "
+            f"{legs[name]['ns_per_day']:.1f} ns/day, <U>/N {legs[name]['U_nonbonded_per_molecule']:.3f}")
+    r, c = legs["relres"], legs["conventional"]
+    out = {
+        "metric": "RelRes NVT molecular dynamics atom-steps/s (hexane, 6000 united atoms, "
+                  "bonded + 1-4 + RelRes pairs), 1 MI355X",
+        "value": r["value"], "unit": "atom-steps/s", "n_gpus": 1, "steps": args.md_steps,
+        "warmup": args.md_equil, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 forces, f64 integration",
+        "data": "synthetic",
+        "config": {"workload": "hexane_liquid: 1000 C3H7-C3H7 chains, 0.016 atoms/A^3",
+                   "atoms": s.n, "dt_fs": dt_fs, "T_K": T, "tau_fs": tau,
+                   "rebuild_every": every, "thermostat": "Nose-Hoover",
+                   "parallelism": "single GPU"},
+        "relres": r, "conventional": c,
+        "speedup_vs_conventional": r["value"] / c["value"],
+        "ratio_U": r["U_nonbonded_per_molecule"] / c["U_nonbonded_per_molecule"],
+        "ratio_W": r["W_per_molecule"] / c["W_per_molecule"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def batch_bench(args):
     """Batching workload: 256 replicas of 300-18000 atoms (1.2 M atoms),
     mixed propane/neopentane liquids at 0.0080-0.0100 atoms/A^3, each with
@@ -429,6 +493,10 @@ def main():
                     help="run the differentiation workload instead (forward + backward over "
                          "perturbed frames) and print its line")
     ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--md", action="store_true",
+                    help="dynamics workload (NVT hexane, RelRes vs conventional) instead")
+    ap.add_argument("--md-equil", type=int, default=2000, help="--md: untimed equilibration steps")
+    ap.add_argument("--md-steps", type=int, default=10000, help="--md: timed production steps")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch workload only: skip the one-context-per-replica comparison")
     ap.add_argument("--batch", action="store_true",
@@ -441,7 +509,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the RelRes path "
-              "here is single-GPU, see DESIGN.md for how it would shard.", file=sys.stderr)
+              "here is single-GPU (it would shard by space, one brick and its halo per GPU).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -456,6 +525,9 @@ def main():
         return
     if args.batch:
         batch_bench(args)
+        return
+    if args.md:
+        md_bench(args)
         return
     s = w.WORKLOADS[args.workload](args.seed)
     precision = s.precision

@@ -305,7 +305,8 @@ struct relres_ctx {
     bool has_bonded = false;
     double scale14 = 0.0;
     DBuf d_term_off, d_term_ent, d_bonds, d_bond_par, d_angles, d_angle_par, d_dihs, d_dih_par;
-    DBuf d_p14_off, d_p14_idx, d_bond_part, d_bond_sum;
+    DBuf d_p14_off, d_p14_idx, d_bond_part, d_bond_part2, d_bond_sum, d_ent_force;
+    int n_ent = 0;                    // (term, slot) entries
     // dynamics (relres_md_setup / relres_md_run)
     bool md_ready = false;
     double md_ftm2v = 0.0;
@@ -622,18 +623,16 @@ int refresh_list_stats(relres_ctx* c, hipStream_t s)
     return RELRES_OK;
 }
 
-// List builder: groups of rows per wave (default), or one block per cell for
-// crowded cells.  RELRES_LIST_KERNEL=wave|block overrides the choice.
+// List builder: groups of rows per wave.  One block per cell remains
+// available with RELRES_LIST_KERNEL=block; it is slower at every occupancy
+// measured (94 atoms per cell: 790 us against 72 us per build), because a
+// grid of few, crowded cells gives it few blocks.
 bool lists_per_wave(const relres_ctx* c)
 {
-    if (const char* e = std::getenv("RELRES_LIST_KERNEL")) {
-        if (!std::strcmp(e, "wave")) return true;
+    (void)c;
+    if (const char* e = std::getenv("RELRES_LIST_KERNEL"))
         if (!std::strcmp(e, "block")) return false;
-    }
-    auto mean = [](const GridHost& g) { return g.ncell ? (double)g.members / g.ncell : 0.0; };
-    double m = mean(c->ga);
-    if (c->n_sites > 0) m = std::max(m, mean(c->gs));
-    return m <= 64.0;
+    return true;
 }
 
 // Enqueue one list build on `s`: bin, scan, scatter, cell sort, lists, then a
@@ -1443,8 +1442,12 @@ int relres_set_bonded(relres_ctx* c, int nbonds, const int* bonds, const double*
     TRY(up(c->d_dih_par, hdp.data(), sizeof(double4) * hdp.size()));
     TRY(up(c->d_p14_off, poff.data(), sizeof(int) * poff.size()));
     TRY(up(c->d_p14_idx, pidx.data(), sizeof(int) * pidx.size()));
-    TRY(ensure(c->d_bond_part, sizeof(double) * 10 * (size_t)std::max(1, bonded_blocks(n)), gen));
+    const int n_ent = (int)tent.size();
+    TRY(ensure(c->d_ent_force, sizeof(double) * 3 * (size_t)std::max(1, n_ent), gen));
+    TRY(ensure(c->d_bond_part, sizeof(double) * 10 * (size_t)std::max(1, md_blocks(n_ent)), gen));
+    TRY(ensure(c->d_bond_part2, sizeof(double) * 10 * (size_t)std::max(1, md_blocks(n)), gen));
     TRY(ensure(c->d_bond_sum, sizeof(double) * 16, gen));
+    c->n_ent = n_ent;
     c->scale14 = scale14;
     c->has_bonded = true;
     return RELRES_OK;
@@ -1452,7 +1455,8 @@ int relres_set_bonded(relres_ctx* c, int nbonds, const int* bonds, const double*
 
 namespace {
 
-int enqueue_bonded(relres_ctx* c, const double* pos, void* forces, bool sums, hipStream_t s)
+int enqueue_bonded(relres_ctx* c, const double* pos, void* forces, bool sums, const MdArgs* m,
+                   hipStream_t s)
 {
     BondedArgs b{};
     b.pos = pos;
@@ -1460,6 +1464,8 @@ int enqueue_bonded(relres_ctx* c, const double* pos, void* forces, bool sums, hi
     b.n = c->n;
     b.term_off = c->d_term_off.as<int>();
     b.term_ent = c->d_term_ent.as<uint32_t>();
+    b.n_ent = c->n_ent;
+    b.ent_force = c->d_ent_force.as<double>();
     b.bonds = c->d_bonds.as<int2>();
     b.bond_par = c->d_bond_par.as<double2>();
     b.angles = c->d_angles.as<int4>();
@@ -1475,9 +1481,11 @@ int enqueue_bonded(relres_ctx* c, const double* pos, void* forces, bool sums, hi
     b.pcut64 = c->d_pcut64.as<Cutoffs<double>>();
     b.forces = forces;
     b.partial = sums ? c->d_bond_part.as<double>() : nullptr;
-    HIP_TRY(launch_bonded(b, c->precision, s));
+    b.partial2 = sums ? c->d_bond_part2.as<double>() : nullptr;
+    HIP_TRY(launch_bonded(b, m, c->precision, s));
     if (sums)
-        HIP_TRY(launch_sum_partials(c->d_bond_part.as<double>(), bonded_blocks(c->n), 10,
+        HIP_TRY(launch_sum_partials(c->d_bond_part.as<double>(), c->n_ent > 0 ? md_blocks(c->n_ent) : 0,
+                                    c->d_bond_part2.as<double>(), md_blocks(c->n), 10,
                                     c->d_bond_sum.as<double>(), s));
     return RELRES_OK;
 }
@@ -1494,7 +1502,7 @@ int relres_bonded_forces(relres_ctx* c, const double* pos, void* forces, double*
     if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
     hipStream_t s = (hipStream_t)stream;
     const bool sums = energy || virial;
-    TRY(enqueue_bonded(c, pos, forces, sums, s));
+    TRY(enqueue_bonded(c, pos, forces, sums, nullptr, s));
     const double* sum = c->d_bond_sum.as<double>();
     if (energy) HIP_TRY(hipMemcpyAsync(energy, sum, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (virial) HIP_TRY(hipMemcpyAsync(virial, sum + 4, 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1522,7 +1530,7 @@ int relres_md_setup(relres_ctx* c, const double* masses, double dt, double kT, d
     TRY(ensure(c->d_md_F, (c->precision == 64 ? 8 : 4) * 3 * (size_t)n, gen));
     TRY(ensure(c->d_md_E, sizeof(double) * 3, gen));
     TRY(ensure(c->d_md_W, sizeof(double) * 6, gen));
-    TRY(ensure(c->d_md_part, sizeof(double) * (size_t)bonded_blocks(n), gen));
+    TRY(ensure(c->d_md_part, sizeof(double) * (size_t)md_blocks(n), gen));
     TRY(ensure(c->d_md_stale, 64, gen));
     TRY(ensure(c->d_bond_sum, sizeof(double) * 16, gen));
     if (!c->h_stale && hipHostMalloc((void**)&c->h_stale, 64, hipHostMallocDefault) != hipSuccess)
@@ -1540,6 +1548,11 @@ int relres_md_setup(relres_ctx* c, const double* masses, double dt, double kT, d
     HIP_TRY(hipMemcpy(c->d_md_state.p, &st, sizeof(MdState), hipMemcpyHostToDevice));
     c->md_ftm2v = ftm2v;
     c->md_rebuild = rebuild_every;
+    // the per-atom bonded kernel also gives the half kick: without bonded
+    // terms it runs with none
+    if (!c->has_bonded)
+        TRY(relres_set_bonded(c, 0, nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0,
+                              nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0.0));
     c->md_ready = true;
     return RELRES_OK;
 }
@@ -1608,30 +1621,28 @@ int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int therm
     m.stale = (unsigned*)c->d_md_stale.p;
     m.partial = c->d_md_part.as<double>();
     m.st = c->d_md_state.as<MdState>();
-    const int nblk = bonded_blocks(c->n);
-    // forces at the starting positions and the kinetic energy
+    const int nblk = md_blocks(c->n);
+    const double* e_nb = c->d_md_E.as<double>();
+    const double* w_nb = c->d_md_W.as<double>();
+    const double* eb = c->d_bond_sum.as<double>();
+    // forces at the starting positions, the kinetic energy and the first
+    // thermostat half step
     TRY(md_rebuild(c, pos, s, false));
     TRY(relres_forces(c, pos, F, nullptr, nullptr, s));
-    if (c->has_bonded) TRY(enqueue_bonded(c, pos, F, false, s));
-    HIP_TRY(launch_md_kick(m, prec, 0, s));
-    HIP_TRY(launch_md_second(m.st, m.partial, nblk, m.ftm2v, 0, s));
+    TRY(enqueue_bonded(c, pos, F, false, nullptr, s));
+    HIP_TRY(launch_md_kinetic(m, s));
+    HIP_TRY(launch_md_scalar(m.st, m.partial, nblk, m.ftm2v, 0, nsteps > 0, nullptr, nullptr,
+                             nullptr, nullptr, s));
     for (int step = 1; step <= nsteps; ++step) {
-        HIP_TRY(launch_md_first(m.st, s));
         HIP_TRY(launch_md_drift(m, prec, s));
         if (step % c->md_rebuild == 0) TRY(md_rebuild(c, pos, s, true));
         const bool out = thermo_every > 0 && step % thermo_every == 0;
         TRY(relres_forces(c, pos, F, out ? c->d_md_E.as<double>() : nullptr,
                           out ? c->d_md_W.as<double>() : nullptr, s));
-        if (c->has_bonded) TRY(enqueue_bonded(c, pos, F, out, s));
-        HIP_TRY(launch_md_kick(m, prec, 1, s));
-        HIP_TRY(launch_md_second(m.st, m.partial, nblk, m.ftm2v, 1, s));
-        if (out) {
-            if (!c->has_bonded)
-                HIP_TRY(launch_clear_words((unsigned long long*)c->d_bond_sum.p, 16, s));
-            HIP_TRY(launch_md_thermo(m.st, c->d_md_E.as<double>(), c->d_md_W.as<double>(),
-                                     c->d_bond_sum.as<double>(),
-                                     thermo + (size_t)8 * (step / thermo_every - 1), s));
-        }
+        // bonded and 1-4 forces, the half kick and the kinetic partials
+        TRY(enqueue_bonded(c, pos, F, out, &m, s));
+        HIP_TRY(launch_md_scalar(m.st, m.partial, nblk, m.ftm2v, 1, step < nsteps, e_nb, w_nb, eb,
+                                 out ? thermo + (size_t)8 * (step / thermo_every - 1) : nullptr, s));
     }
     HIP_TRY(launch_md_finish(m, s));
     // the last steps since the previous build must not have outrun the skin either
@@ -1738,7 +1749,8 @@ void relres_destroy(relres_ctx* c)
     for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial, &c->d_sys, &c->d_boxes, &c->d_row_ew}) release(*b);
     for (DBuf* b : {&c->d_term_off, &c->d_term_ent, &c->d_bonds, &c->d_bond_par, &c->d_angles,
                     &c->d_angle_par, &c->d_dihs, &c->d_dih_par, &c->d_p14_off, &c->d_p14_idx,
-                    &c->d_bond_part, &c->d_bond_sum, &c->d_mass, &c->d_md_state, &c->d_md_xref,
+                    &c->d_bond_part, &c->d_bond_part2, &c->d_bond_sum, &c->d_ent_force,
+                    &c->d_mass, &c->d_md_state, &c->d_md_xref,
                     &c->d_md_F, &c->d_md_E, &c->d_md_W, &c->d_md_part, &c->d_md_stale})
         release(*b);
     if (c->h_stale) (void)hipHostFree(c->h_stale);

@@ -189,7 +189,9 @@ struct BondedArgs {
     double box[3];
     int n;
     const int* term_off;              // [n + 1]
-    const uint32_t* term_ent;
+    const uint32_t* term_ent;         // n_ent entries, grouped by atom
+    int n_ent;
+    double* ent_force;                // n_ent x 3: force of each entry on its atom
     const int2* bonds;
     const double2* bond_par;          // K, r0
     const int4* angles;               // i, j (vertex), k, unused
@@ -204,13 +206,17 @@ struct BondedArgs {
     const PairCoef<double>* coef64;
     const Cutoffs<double>* pcut64;
     void* forces;                     // N x 3 of the force type; added to
-    double* partial;                  // per block: 4 energies, 6 virial; or null
+    double* partial;                  // per entry block: 4 energies, 6 virial; or null
+    double* partial2;                 // per atom block: 4 energies, 6 virial; or null
 };
-hipError_t launch_bonded(const BondedArgs& b, int force_prec, hipStream_t s);
-int bonded_blocks(int n);
-// out[k] = sum of partial[blk * K + k] over blocks, in block order
-hipError_t launch_sum_partials(const double* partial, int nblocks, int K, double* out,
-                               hipStream_t s);
+struct MdArgs;
+// Bonded and 1-4 forces added to b.forces; with m, also the half kick of a
+// dynamics step and the kinetic partials (m->partial).
+hipError_t launch_bonded(const BondedArgs& b, const MdArgs* m, int force_prec, hipStream_t s);
+int md_blocks(int n);                 // blocks of the per-atom (and per-entry) kernels
+// out[k] = sum of p1[blk * K + k] over its blocks, then of p2, in block order
+hipError_t launch_sum_partials(const double* p1, int n1, const double* p2, int n2, int K,
+                               double* out, hipStream_t s);
 
 // Thermostat and integrator state on the device.
 struct MdState {
@@ -234,14 +240,14 @@ struct MdArgs {
     double* partial;                  // per block kinetic partial
     MdState* st;
 };
-hipError_t launch_md_first(MdState* st, hipStream_t s);
 hipError_t launch_md_drift(const MdArgs& m, int force_prec, hipStream_t s);
-hipError_t launch_md_kick(const MdArgs& m, int force_prec, int kick, hipStream_t s);
-hipError_t launch_md_second(MdState* st, const double* partial, int nblocks, double ftm2v,
-                            int thermostat, hipStream_t s);
-hipError_t launch_md_finish(const MdArgs& m, hipStream_t s);
-hipError_t launch_md_thermo(const MdState* st, const double* e_nb, const double* w_nb,
+hipError_t launch_md_kinetic(const MdArgs& m, hipStream_t s);
+// kinetic energy from the partials; second / first thermostat half steps;
+// with row, one row of thermodynamic output
+hipError_t launch_md_scalar(MdState* st, const double* partial, int nblocks, double ftm2v,
+                            int second, int first, const double* e_nb, const double* w_nb,
                             const double* eb, double* row, hipStream_t s);
+hipError_t launch_md_finish(const MdArgs& m, hipStream_t s);
 
 // Row record field y: atom type in the low kTypeBits bits, system above.
 constexpr int kTypeBits = 5;

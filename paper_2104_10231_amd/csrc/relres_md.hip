@@ -2,10 +2,12 @@
 // pair potential (Sec. 3.2 of the paper): bonded terms, scaled 1-4 pairs and
 // a Nose-Hoover velocity-Verlet integrator.
 //
-// Bonded terms: one thread per atom walks the terms the atom belongs to and
-// recomputes each term in FP64, keeping the force on its own slot; a term's
-// energy and virial are counted by its first atom.  No atomics, so results
-// are deterministic.  Formulas (forces are -dE/dx):
+// Bonded terms: one thread per (term, slot) entry computes the term in FP64
+// and writes the force on its slot's atom; a second kernel gives each atom
+// the sum of its entries in a fixed order, adds its scaled 1-4 pairs and, in
+// a dynamics step, the half kick.  A term's energy and virial are counted by
+// its first slot.  No atomics, so results are deterministic.  Formulas
+// (forces are -dE/dx):
 //   bond      E = K (r - r0)^2, d = x_i - x_j: F_i = -2K (r - r0) d / r
 //   angle     E = K (theta - theta0)^2, a = x_i - x_j, b = x_k - x_j:
 //             F_i = (dE/dtheta / sin theta)(b/|b| - cos(theta) a/|a|)/|a|,
@@ -79,93 +81,112 @@ __device__ __forceinline__ double block_sum(const double* v, double (*red)[kMdBl
     return r;
 }
 
-// Bonded and 1-4 forces of every atom, added to `forces`; with `partial`
-// each block writes its 10 sums (energies: bonds, angles, dihedrals, 1-4;
-// virial xx yy zz xy xz yz).
+// Force of every (term, slot) entry on its atom, entries in the per-atom
+// order of term_ent; with `partial` each block writes its 10 sums (energies:
+// bonds, angles, dihedrals, 0; virial xx yy zz xy xz yz).
+__global__ __launch_bounds__(kMdBlock) void k_bonded_terms(BondedArgs b)
+{
+    __shared__ double red[10][kMdBlock];
+    const int e = blockIdx.x * kMdBlock + threadIdx.x;
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // energies 0..3, virial 4..9
+    if (e < b.n_ent) {
+        const uint32_t ent = b.term_ent[e];
+        const int kind = (int)(ent >> 30), slot = (int)((ent >> 28) & 3u);
+        const int t = (int)(ent & 0x0fffffffu);
+        double f[4][3];
+        if (kind == 0) {
+            const int2 ij = b.bonds[t];
+            const double2 par = b.bond_par[t];
+            double d[3];
+            mi_diff(b.pos, ij.x, ij.y, b.box, d);
+            const double r = sqrt(dot3(d, d));
+            const double dr = r - par.y;
+            const double sc = -2.0 * par.x * dr / r;
+            for (int c = 0; c < 3; ++c) {
+                f[0][c] = sc * d[c];
+                f[1][c] = -f[0][c];
+            }
+            if (slot == 0) {
+                acc[0] += par.x * dr * dr;
+                add_virial(acc + 4, d, f[0]);
+            }
+        } else if (kind == 1) {
+            const int4 ijk = b.angles[t];
+            const double2 par = b.angle_par[t];
+            double u[3], v[3];
+            mi_diff(b.pos, ijk.x, ijk.y, b.box, u);
+            mi_diff(b.pos, ijk.z, ijk.y, b.box, v);
+            const double lu = sqrt(dot3(u, u)), lv = sqrt(dot3(v, v));
+            double c = dot3(u, v) / (lu * lv);
+            c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+            const double th = acos(c);
+            const double dth = th - par.y;
+            const double g = 2.0 * par.x * dth / sin(th);
+            for (int q = 0; q < 3; ++q) {
+                f[0][q] = g * (v[q] / lv - c * u[q] / lu) / lu;
+                f[2][q] = g * (u[q] / lu - c * v[q] / lv) / lv;
+                f[1][q] = -f[0][q] - f[2][q];
+            }
+            if (slot == 0) {
+                acc[1] += par.x * dth * dth;
+                add_virial(acc + 4, u, f[0]);
+                add_virial(acc + 4, v, f[2]);
+            }
+        } else {
+            const int4 q4 = b.dihs[t];
+            const double4 par = b.dih_par[t];      // K, n, d
+            double b1[3], b2[3], b3[3], m[3], nn[3];
+            mi_diff(b.pos, q4.y, q4.x, b.box, b1);
+            mi_diff(b.pos, q4.z, q4.y, b.box, b2);
+            mi_diff(b.pos, q4.w, q4.z, b.box, b3);
+            cross3(b1, b2, m);
+            cross3(b2, b3, nn);
+            const double lb2 = sqrt(dot3(b2, b2));
+            const double phi = atan2(lb2 * dot3(b1, nn), dot3(m, nn));
+            const double arg = par.y * phi - par.z;
+            const double dE = -par.x * par.y * sin(arg);
+            const double mm = dot3(m, m), n2 = dot3(nn, nn);
+            const double p = dot3(b1, b2) / (lb2 * lb2), q = dot3(b3, b2) / (lb2 * lb2);
+            for (int c = 0; c < 3; ++c) {
+                const double gi = -lb2 * m[c] / mm, gl = lb2 * nn[c] / n2;
+                f[0][c] = -dE * gi;
+                f[3][c] = -dE * gl;
+                f[1][c] = -dE * (-(1.0 + p) * gi + q * gl);
+                f[2][c] = -dE * (p * gi - (1.0 + q) * gl);
+            }
+            if (slot == 0) {
+                acc[2] += par.x * (1.0 + cos(arg));
+                const double li[3] = {-b1[0], -b1[1], -b1[2]};
+                const double ll[3] = {b2[0] + b3[0], b2[1] + b3[1], b2[2] + b3[2]};
+                add_virial(acc + 4, li, f[0]);
+                add_virial(acc + 4, b2, f[2]);
+                add_virial(acc + 4, ll, f[3]);
+            }
+        }
+        for (int c = 0; c < 3; ++c) b.ent_force[3 * (size_t)e + c] = f[slot][c];
+    }
+    if (b.partial) {
+        const double r = block_sum<10>(acc, red);
+        if (threadIdx.x < 10) b.partial[(size_t)blockIdx.x * 10 + threadIdx.x] = r;
+    }
+}
+
+// Per atom: the sum of its term entries (in order) and its scaled 1-4 pairs,
+// added to `forces`; with `partial2` each block writes its 10 sums (energy
+// 3: the 1-4 pairs; virial).  With a dynamics step `m` (kick != 0) the new
+// total force also gives the half kick v += dt/2 F/m and each block writes
+// its kinetic partial sum(m v^2).
 template <typename TF>
-__global__ __launch_bounds__(kMdBlock) void k_bonded(BondedArgs b)
+__global__ __launch_bounds__(kMdBlock) void k_bonded_gather(BondedArgs b, MdArgs m, int kick)
 {
     __shared__ double red[10][kMdBlock];
     const int a = blockIdx.x * kMdBlock + threadIdx.x;
-    double fa[3] = {0.0, 0.0, 0.0};
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // energies 0..3, virial 4..9
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double ke = 0.0;
     if (a < b.n) {
-        for (int e = b.term_off[a]; e < b.term_off[a + 1]; ++e) {
-            const uint32_t ent = b.term_ent[e];
-            const int kind = (int)(ent >> 30), slot = (int)((ent >> 28) & 3u);
-            const int t = (int)(ent & 0x0fffffffu);
-            double f[4][3];
-            if (kind == 0) {
-                const int2 ij = b.bonds[t];
-                const double2 par = b.bond_par[t];
-                double d[3];
-                mi_diff(b.pos, ij.x, ij.y, b.box, d);
-                const double r = sqrt(dot3(d, d));
-                const double dr = r - par.y;
-                const double s = -2.0 * par.x * dr / r;
-                for (int c = 0; c < 3; ++c) {
-                    f[0][c] = s * d[c];
-                    f[1][c] = -f[0][c];
-                }
-                if (slot == 0) {
-                    acc[0] += par.x * dr * dr;
-                    add_virial(acc + 4, d, f[0]);
-                }
-            } else if (kind == 1) {
-                const int4 ijk = b.angles[t];
-                const double2 par = b.angle_par[t];
-                double u[3], v[3];
-                mi_diff(b.pos, ijk.x, ijk.y, b.box, u);
-                mi_diff(b.pos, ijk.z, ijk.y, b.box, v);
-                const double lu = sqrt(dot3(u, u)), lv = sqrt(dot3(v, v));
-                double c = dot3(u, v) / (lu * lv);
-                c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-                const double th = acos(c);
-                const double dth = th - par.y;
-                const double g = 2.0 * par.x * dth / sin(th);
-                for (int q = 0; q < 3; ++q) {
-                    f[0][q] = g * (v[q] / lv - c * u[q] / lu) / lu;
-                    f[2][q] = g * (u[q] / lu - c * v[q] / lv) / lv;
-                    f[1][q] = -f[0][q] - f[2][q];
-                }
-                if (slot == 0) {
-                    acc[1] += par.x * dth * dth;
-                    add_virial(acc + 4, u, f[0]);
-                    add_virial(acc + 4, v, f[2]);
-                }
-            } else {
-                const int4 q4 = b.dihs[t];
-                const double4 par = b.dih_par[t];      // K, n, d
-                double b1[3], b2[3], b3[3], m[3], nn[3];
-                mi_diff(b.pos, q4.y, q4.x, b.box, b1);
-                mi_diff(b.pos, q4.z, q4.y, b.box, b2);
-                mi_diff(b.pos, q4.w, q4.z, b.box, b3);
-                cross3(b1, b2, m);
-                cross3(b2, b3, nn);
-                const double lb2 = sqrt(dot3(b2, b2));
-                const double phi = atan2(lb2 * dot3(b1, nn), dot3(m, nn));
-                const double arg = par.y * phi - par.z;
-                const double dE = -par.x * par.y * sin(arg);
-                const double mm = dot3(m, m), n2 = dot3(nn, nn);
-                const double p = dot3(b1, b2) / (lb2 * lb2), q = dot3(b3, b2) / (lb2 * lb2);
-                for (int c = 0; c < 3; ++c) {
-                    const double gi = -lb2 * m[c] / mm, gl = lb2 * nn[c] / n2;
-                    f[0][c] = -dE * gi;
-                    f[3][c] = -dE * gl;
-                    f[1][c] = -dE * (-(1.0 + p) * gi + q * gl);
-                    f[2][c] = -dE * (p * gi - (1.0 + q) * gl);
-                }
-                if (slot == 0) {
-                    acc[2] += par.x * (1.0 + cos(arg));
-                    const double li[3] = {-b1[0], -b1[1], -b1[2]};
-                    const double ll[3] = {b2[0] + b3[0], b2[1] + b3[1], b2[2] + b3[2]};
-                    add_virial(acc + 4, li, f[0]);
-                    add_virial(acc + 4, b2, f[2]);
-                    add_virial(acc + 4, ll, f[3]);
-                }
-            }
-            for (int c = 0; c < 3; ++c) fa[c] += f[slot][c];
-        }
+        double fa[3] = {0.0, 0.0, 0.0};
+        for (int e = b.term_off[a]; e < b.term_off[a + 1]; ++e)
+            for (int c = 0; c < 3; ++c) fa[c] += b.ent_force[3 * (size_t)e + c];
         // 1-4 pairs through Eq. 20, scaled; each pair is met from both atoms
         const int ta = b.types[a];
         for (int e = b.p14_off[a]; e < b.p14_off[a + 1]; ++e) {
@@ -192,27 +213,42 @@ __global__ __launch_bounds__(kMdBlock) void k_bonded(BondedArgs b)
             const double f[3] = {s * d[0], s * d[1], s * d[2]};
             for (int c = 0; c < 3; ++c) fa[c] += f[c];
             acc[3] += 0.5 * b.scale14 * en;
-            double hd[3] = {0.5 * d[0], 0.5 * d[1], 0.5 * d[2]};
+            const double hd[3] = {0.5 * d[0], 0.5 * d[1], 0.5 * d[2]};
             add_virial(acc + 4, hd, f);
         }
         TF* F = (TF*)b.forces;
         for (int c = 0; c < 3; ++c) F[3 * a + c] += (TF)fa[c];
+        if (kick) {
+            const double dt = m.st->dt;
+            const double am = m.ftm2v / m.mass[a];
+            for (int c = 0; c < 3; ++c) {
+                const double v = m.vel[3 * a + c] + 0.5 * dt * am * (double)F[3 * a + c];
+                m.vel[3 * a + c] = v;
+                ke += m.mass[a] * v * v;
+            }
+        }
     }
-    if (b.partial) {
+    if (b.partial2) {
         const double r = block_sum<10>(acc, red);
-        if (threadIdx.x < 10) b.partial[(size_t)blockIdx.x * 10 + threadIdx.x] = r;
+        if (threadIdx.x < 10) b.partial2[(size_t)blockIdx.x * 10 + threadIdx.x] = r;
+    }
+    if (kick) {
+        const double r = block_sum<1>(&ke, red);
+        if (threadIdx.x == 0) m.partial[blockIdx.x] = r;
     }
 }
 
-// out[k] = sum over blocks of partial[blk * K + k], blocks in order (one
-// thread per component).
-__global__ void k_sum_partials(const double* __restrict__ partial, int nblocks, int K,
+// out[k] = the sums over blocks of p1[blk * K + k] and then of p2 (blocks
+// in order; one thread per component).
+__global__ void k_sum_partials(const double* __restrict__ p1, int n1,
+                               const double* __restrict__ p2, int n2, int K,
                                double* __restrict__ out)
 {
     const int k = threadIdx.x;
     if (k >= K) return;
     double s = 0.0;
-    for (int blk = 0; blk < nblocks; ++blk) s += partial[(size_t)blk * K + k];
+    for (int blk = 0; blk < n1; ++blk) s += p1[(size_t)blk * K + k];
+    for (int blk = 0; blk < n2; ++blk) s += p2[(size_t)blk * K + k];
     out[k] = s;
 }
 
@@ -233,15 +269,6 @@ __device__ __forceinline__ void thermostat_half(MdState* st)
     st->eta += 0.5 * dt * st->xi;
     st->xi += 0.25 * dt * (2.0 * st->K - st->g * st->kT) / st->Q;
     st->s_last = s;
-}
-
-// First thermostat half step of a step (one thread): the scale to apply to
-// the stored velocities becomes s2 * s1.
-__global__ void k_md_first(MdState* st)
-{
-    thermostat_half(st);
-    st->s_apply = st->s2 * st->s_last;
-    st->s2 = 1.0;
 }
 
 template <typename TF>
@@ -267,42 +294,53 @@ __global__ __launch_bounds__(kMdBlock) void k_md_drift(MdArgs m)
     if (dmax2 > m.half_skin2) atomicOr(m.stale, 1u);
 }
 
-// Second half kick and the kinetic-energy partial of every block.
-template <typename TF>
-__global__ __launch_bounds__(kMdBlock) void k_md_kick(MdArgs m, int kick)
+// Kinetic partials of the stored velocities (no kick), at the start of a run.
+__global__ __launch_bounds__(kMdBlock) void k_md_kinetic(MdArgs m)
 {
     __shared__ double red[1][kMdBlock];
     const int i = blockIdx.x * kMdBlock + threadIdx.x;
     double ke = 0.0;
-    if (i < m.n) {
-        const double dt = m.st->dt;
-        const double am = m.ftm2v / m.mass[i];
-        const TF* F = (const TF*)m.forces;
-        for (int c = 0; c < 3; ++c) {
-            double v = m.vel[3 * i + c];
-            if (kick) {
-                v += 0.5 * dt * am * (double)F[3 * i + c];
-                m.vel[3 * i + c] = v;
-            }
-            ke += m.mass[i] * v * v;
-        }
-    }
+    if (i < m.n)
+        for (int c = 0; c < 3; ++c) ke += m.mass[i] * m.vel[3 * i + c] * m.vel[3 * i + c];
     const double r = block_sum<1>(&ke, red);
     if (threadIdx.x == 0) m.partial[blockIdx.x] = r;
 }
 
-// Kinetic energy from the block partials (fixed order), then, if asked, the
-// second thermostat half step of the step (one block).
-__global__ void k_md_second(MdState* st, const double* __restrict__ partial, int nblocks,
-                            double ftm2v, int thermostat)
+// The scalar part between two steps (one thread): the kinetic energy from
+// the block partials (fixed order); with `second` the second thermostat half
+// step of the step just done (and, with `row`, its thermodynamic output: the
+// non-bonded energy of Eq. 3, the 1-4, bond, angle and dihedral energies,
+// the kinetic energy, the extended energy K + U + Q xi^2/2 + g kT eta and
+// the trace of the virial); with `first` the first half step of the next
+// step, whose drift applies s2 s1 to the stored velocities.
+__global__ void k_md_scalar(MdState* st, const double* __restrict__ partial, int nblocks,
+                            double ftm2v, int second, int first, const double* __restrict__ e_nb,
+                            const double* __restrict__ w_nb, const double* __restrict__ eb,
+                            double* __restrict__ row)
 {
     if (threadIdx.x != 0) return;
     double s = 0.0;
     for (int blk = 0; blk < nblocks; ++blk) s += partial[blk];
     st->K = 0.5 * s / ftm2v;
-    if (thermostat) {
+    if (second) {
         thermostat_half(st);
         st->s2 = st->s_last;
+        if (row) {
+            const double u = e_nb[0] + eb[3] + eb[0] + eb[1] + eb[2];
+            row[0] = e_nb[0];
+            row[1] = eb[3];
+            row[2] = eb[0];
+            row[3] = eb[1];
+            row[4] = eb[2];
+            row[5] = st->K;
+            row[6] = st->K + u + 0.5 * st->Q * st->xi * st->xi + st->g * st->kT * st->eta;
+            row[7] = w_nb[0] + w_nb[1] + w_nb[2] + eb[4] + eb[5] + eb[6];
+        }
+    }
+    if (first) {
+        thermostat_half(st);
+        st->s_apply = st->s2 * st->s_last;
+        st->s2 = 1.0;
     }
 }
 
@@ -317,50 +355,30 @@ __global__ __launch_bounds__(kMdBlock) void k_md_finish(MdArgs m)
 
 __global__ void k_md_unit_scale(MdState* st) { st->s2 = 1.0; }
 
-// One row of thermodynamic output: non-bonded energy (Eq. 3), 1-4 energy,
-// bond, angle and dihedral energies, kinetic energy, the extended energy
-// K + U + Q xi^2/2 + g kT eta, and the trace of the total virial.
-__global__ void k_md_thermo(const MdState* st, const double* __restrict__ e_nb,
-                            const double* __restrict__ w_nb, const double* __restrict__ eb,
-                            double* __restrict__ row)
-{
-    if (threadIdx.x != 0) return;
-    const double u = e_nb[0] + eb[3] + eb[0] + eb[1] + eb[2];
-    row[0] = e_nb[0];
-    row[1] = eb[3];
-    row[2] = eb[0];
-    row[3] = eb[1];
-    row[4] = eb[2];
-    row[5] = st->K;
-    row[6] = st->K + u + 0.5 * st->Q * st->xi * st->xi + st->g * st->kT * st->eta;
-    row[7] = w_nb[0] + w_nb[1] + w_nb[2] + eb[4] + eb[5] + eb[6];
-}
-
 }  // namespace
 
-hipError_t launch_bonded(const BondedArgs& b, int force_prec, hipStream_t s)
+hipError_t launch_bonded(const BondedArgs& b, const MdArgs* m, int force_prec, hipStream_t s)
 {
-    const int blocks = (b.n + kMdBlock - 1) / kMdBlock;
-    if (blocks == 0) return hipSuccess;
+    if (b.n == 0) return hipSuccess;
+    if (b.n_ent > 0)
+        hipLaunchKernelGGL(k_bonded_terms, dim3((b.n_ent + kMdBlock - 1) / kMdBlock), dim3(kMdBlock),
+                           0, s, b);
+    const dim3 grid((b.n + kMdBlock - 1) / kMdBlock);
+    const MdArgs none{};
+    const int kick = m ? 1 : 0;
     if (force_prec == 64)
-        hipLaunchKernelGGL(k_bonded<double>, dim3(blocks), dim3(kMdBlock), 0, s, b);
+        hipLaunchKernelGGL(k_bonded_gather<double>, grid, dim3(kMdBlock), 0, s, b, m ? *m : none, kick);
     else
-        hipLaunchKernelGGL(k_bonded<float>, dim3(blocks), dim3(kMdBlock), 0, s, b);
+        hipLaunchKernelGGL(k_bonded_gather<float>, grid, dim3(kMdBlock), 0, s, b, m ? *m : none, kick);
     return hipGetLastError();
 }
 
-int bonded_blocks(int n) { return (n + kMdBlock - 1) / kMdBlock; }
+int md_blocks(int n) { return (n + kMdBlock - 1) / kMdBlock; }
 
-hipError_t launch_sum_partials(const double* partial, int nblocks, int K, double* out,
-                               hipStream_t s)
+hipError_t launch_sum_partials(const double* p1, int n1, const double* p2, int n2, int K,
+                               double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partial, nblocks, K, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_md_first(MdState* st, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_md_first, dim3(1), dim3(1), 0, s, st);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, p1, n1, p2, n2, K, out);
     return hipGetLastError();
 }
 
@@ -374,21 +392,18 @@ hipError_t launch_md_drift(const MdArgs& m, int force_prec, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_md_kick(const MdArgs& m, int force_prec, int kick, hipStream_t s)
+hipError_t launch_md_kinetic(const MdArgs& m, hipStream_t s)
 {
-    const int blocks = (m.n + kMdBlock - 1) / kMdBlock;
-    if (force_prec == 64)
-        hipLaunchKernelGGL(k_md_kick<double>, dim3(blocks), dim3(kMdBlock), 0, s, m, kick);
-    else
-        hipLaunchKernelGGL(k_md_kick<float>, dim3(blocks), dim3(kMdBlock), 0, s, m, kick);
+    hipLaunchKernelGGL(k_md_kinetic, dim3((m.n + kMdBlock - 1) / kMdBlock), dim3(kMdBlock), 0, s, m);
     return hipGetLastError();
 }
 
-hipError_t launch_md_second(MdState* st, const double* partial, int nblocks, double ftm2v,
-                            int thermostat, hipStream_t s)
+hipError_t launch_md_scalar(MdState* st, const double* partial, int nblocks, double ftm2v,
+                            int second, int first, const double* e_nb, const double* w_nb,
+                            const double* eb, double* row, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_md_second, dim3(1), dim3(64), 0, s, st, partial, nblocks, ftm2v,
-                       thermostat);
+    hipLaunchKernelGGL(k_md_scalar, dim3(1), dim3(64), 0, s, st, partial, nblocks, ftm2v, second,
+                       first, e_nb, w_nb, eb, row);
     return hipGetLastError();
 }
 
@@ -397,13 +412,6 @@ hipError_t launch_md_finish(const MdArgs& m, hipStream_t s)
     const int blocks = (m.n + kMdBlock - 1) / kMdBlock;
     hipLaunchKernelGGL(k_md_finish, dim3(blocks), dim3(kMdBlock), 0, s, m);
     hipLaunchKernelGGL(k_md_unit_scale, dim3(1), dim3(1), 0, s, m.st);
-    return hipGetLastError();
-}
-
-hipError_t launch_md_thermo(const MdState* st, const double* e_nb, const double* w_nb,
-                            const double* eb, double* row, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_md_thermo, dim3(1), dim3(1), 0, s, st, e_nb, w_nb, eb, row);
     return hipGetLastError();
 }
 

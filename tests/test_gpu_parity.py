@@ -364,6 +364,15 @@ def test_crowded_cells_need_several_passes():
     rr.close()
 
 
+def test_cell_per_block_list_kernel(monkeypatch):
+    """The one-block-per-cell list builder (chosen by RELRES_LIST_KERNEL=block)
+    gives the same pair sets and forces."""
+    monkeypatch.setenv("RELRES_LIST_KERNEL", "block")
+    s = w.propane_liquid(3)
+    _check(s, 64)
+    _check(s.conventional(), 64)
+
+
 def test_graph_replay_matches_eager():
     """relres_forces captured in a HIP graph: every replay, with eager library
     work and synchronisation in between, reproduces the eager results bitwise."""
