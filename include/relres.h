@@ -161,7 +161,8 @@ double relres_mix_distance(int mix, double a, double b);
  * excl_idx[excl_offsets[i] .. excl_offsets[i+1]) of caller indices (may be
  * NULL for none; they are symmetrised; at most RELRES_MAX_EXCLUSIONS partners
  * per atom).  Host arrays, copied.  types[i] must lie in [0, ntypes).
- * n_atoms may be 0.                                                          */
+ * n_atoms may be 0.  Drops bonded terms and the dynamics setup, which refer
+ * to the previous atoms.                                                     */
 int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const int *mol,
                         int exclude_same_mol, const int *excl_offsets, const int *excl_idx);
 
@@ -171,7 +172,8 @@ int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const in
  * system has its own periodic box and cell grids; pairs never cross
  * systems.  Every build, force and backward call then covers all systems in
  * one launch per step: boxes are nsys x 3, energies nsys x 3 and virials
- * nsys x 6.  relres_set_topology resets to one system.  Lists must be built
+ * nsys x 6.  relres_set_topology resets to one system.  With nsys > 1,
+ * bonded terms and the dynamics setup are dropped.  Lists must be built
  * again afterwards.                                                         */
 int relres_set_systems(relres_ctx *ctx, int nsys, const int *atom_offsets);
 

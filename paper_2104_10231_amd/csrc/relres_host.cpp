@@ -1093,6 +1093,9 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
         HIP_TRY(hipMemcpy(c->d_excl_idx.p, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
     }
     c->topo_set = true;
+    // bonded terms and the integrator describe the previous atoms
+    c->has_bonded = false;
+    c->md_ready = false;
     return RELRES_OK;
 }
 
@@ -1129,6 +1132,11 @@ int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
     c->sites_sys = sites;
     c->built = false;
     c->lanes_stale = true;
+    if (nsys > 1) {
+        // bonded terms and dynamics are single-system
+        c->has_bonded = false;
+        c->md_ready = false;
+    }
     return RELRES_OK;
 }
 

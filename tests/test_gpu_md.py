@@ -132,3 +132,22 @@ def test_stale_lists_are_reported():
         rr.md_run(p, v, 40)
     assert e.value.code == RELRES_ERR_STALE_LISTS
     rr.close()
+
+
+def test_new_topology_drops_bonded_terms():
+    """Bonded terms refer to atoms of one topology: a new topology drops them
+    (and the integrator setup) instead of reading tables of the old size."""
+    import torch
+    from paper_2104_10231_amd.relres import RelResError
+    s = _hexane(n_mol=80, seed=6)
+    rr, p = _ctx(s)
+    small = w.hexane_liquid(7, n_mol=40, density=0.012)
+    rr.set_topology(small.types, small.mol, False, small.excl_offsets, small.excl_idx)
+    ps = torch.from_numpy(small.pos).cuda()
+    rr.build_lists(ps, s.box)
+    F = torch.zeros((small.n, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(RelResError):
+        rr.bonded_forces(ps, F)
+    with pytest.raises(RelResError):
+        rr.md_run(ps, torch.zeros_like(ps), 1)
+    rr.close()
