@@ -33,6 +33,9 @@
  *   Every int-returning function returns RELRES_OK (0) or a negative
  *   RELRES_ERR_* code; relres_strerror() names it and relres_last_error()
  *   returns a message with details.  No C++ exception crosses the ABI.
+ *   relres_build_lists and relres_check_lists may also return the positive
+ *   RELRES_WARN_DANGEROUS_BUILD: the call succeeded (the lists are complete),
+ *   but lists used before it had been kept too long.
  */
 #ifndef RELRES_H
 #define RELRES_H
@@ -41,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RELRES_ABI_VERSION 2
+#define RELRES_ABI_VERSION 3
 
 #define RELRES_OK                   0
 #define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
@@ -55,6 +58,11 @@ extern "C" {
 #define RELRES_ERR_STATE           -9  /* call out of order                  */
 #define RELRES_ERR_LIST_RETRY     -10  /* asynchronous build overflowed: rows grown, build again */
 #define RELRES_ERR_STALE_LISTS    -11  /* dynamics: an atom moved more than half the skin between builds */
+/* Warning (positive; the call succeeded): this build found atoms more than
+ * half the skin from where they were at the previous build of the same
+ * topology and boxes, so forces computed from the previous lists may have
+ * missed pairs (a "dangerous build" in Verlet-list terms).                 */
+#define RELRES_WARN_DANGEROUS_BUILD  1
 
 #define RELRES_MIX_GEOMETRIC   0   /* eps, sigma geometric means (Sec. 2.3)    */
 #define RELRES_MIX_ARITHMETIC  1   /* Lorentz-Berthelot: eps geometric, sigma arithmetic */
@@ -124,6 +132,12 @@ typedef struct relres_stats {
                                              relres_forces reads or writes is
                                              reallocated; a graph that captured
                                              relres_forces must be re-captured then */
+    long long dangerous_builds;           /* builds that returned (or, examined by
+                                             another call, would have returned)
+                                             RELRES_WARN_DANGEROUS_BUILD      */
+    long long moved_at_last_build;        /* atoms the last examined build found
+                                             more than half the skin from their
+                                             previous-build positions          */
 } relres_stats;
 
 /* Create a context.  Validates the cutoff ordering r_s- <= r_s+ <= r_c- <=
@@ -185,7 +199,12 @@ int relres_set_systems(relres_ctx *ctx, int nsys, const int *atom_offsets);
  *   d = w_j - w_i; d -= L if d > L/2; d += L if d < -L/2;
  *   r2 = (dx dx + dy dy) + dz dz;   member iff r2 < (r_+ + skin)^2
  * with separately rounded operations.  Synchronises `stream` once to check
- * the list capacity; grows the lists and rebuilds when a row overflowed.    */
+ * the list capacity; grows the lists and rebuilds when a row overflowed.
+ * Lists built with a skin stay exact while no atom has moved more than half
+ * the skin since the build (the Verlet-list rule behind the paper's
+ * neighbour lists, Sec. 2.6).  Each build checks this for the previous one
+ * (same topology and boxes): RELRES_WARN_DANGEROUS_BUILD if some atom had
+ * moved further; relres_moved_atoms checks it between builds.             */
 int relres_build_lists(relres_ctx *ctx, const double *pos, const double box[3], void *stream);
 
 /* The same build without waiting: everything is enqueued on `stream`, and
@@ -209,8 +228,20 @@ int relres_build_lists_async(relres_ctx *ctx, const double *pos, const double bo
  * lists are complete, RELRES_ERR_NONFINITE for a NaN/inf position, or
  * RELRES_ERR_LIST_RETRY when a row overflowed its capacity: the capacity has
  * been grown and the lists are invalid until the next build.  Waits only for
- * the build itself, not for work enqueued after it.                        */
+ * the build itself, not for work enqueued after it.  Complete lists from a
+ * build that found atoms past half the skin (see relres_build_lists) give
+ * RELRES_WARN_DANGEROUS_BUILD instead of RELRES_OK, once per such build.   */
 int relres_check_lists(relres_ctx *ctx);
+
+/* Number of atoms of pos (device, N x 3 FP64) that are more than half the
+ * skin (minimum image, the box of their system) from where they were at the
+ * last build; 0 means the lists are still exact for pos (Sec. 2.6 Verlet
+ * lists: rebuild when it is not, e.g. every few steps as LAMMPS's "check
+ * yes" does).  A non-finite position counts as moved.  Enqueues one small
+ * kernel on `stream` and waits for it (not allowed while the stream is being
+ * captured: RELRES_ERR_STATE).  RELRES_ERR_NO_LISTS before the first build.
+ * count: host int.                                                          */
+int relres_moved_atoms(relres_ctx *ctx, const double *pos, void *stream, int *count);
 
 /* Forces, energy and virial for device positions pos (N x 3 FP64) using the
  * lists of the last build (and its box).  forces: device N x 3, double* when

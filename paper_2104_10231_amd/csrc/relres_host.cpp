@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -282,8 +283,11 @@ struct relres_ctx {
     GridDev uploaded[2] = {};         // descriptors currently on the device
     bool grids_valid = false;
     Status* h_status = nullptr;
-    Status* h_zero = nullptr;
+    Status* h_query = nullptr;        // pinned landing place of relres_moved_atoms
     int nonfinite_seen = 0;
+    unsigned moved_seen = 0;          // Status::moved at the last examination
+    bool ref_valid = false;           // wpos holds a previous build of this topology
+    bool warn_pending = false;        // a build found atoms past half the skin, not yet reported
     bool stats_fresh = false;         // statistics describe the current lists
     bool lanes_stale = true;          // automatic lane counts need a refresh
     bool built = false;
@@ -660,6 +664,8 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
                             box[3 * sy + k], sy, rmax);
     }
     c->built = false;
+    // positions of the previous build are comparable when the boxes are the same
+    const bool same_boxes = c->boxes.size() == (size_t)3 * ns && std::equal(box, box + 3 * ns, c->boxes.begin());
     std::copy(box, box + 3, c->box);
     c->boxes.assign(box, box + 3 * ns);
     {
@@ -680,7 +686,9 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     TRY(setup_grid(c->ga, rla, ns, box, c->atoms_sys.data(), &c->alloc_generation));
     if (sites) TRY(setup_grid(c->gs, rls, ns, box, c->sites_sys.data(), &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
+    const void* wpos_before = c->d_wpos.p;
     TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
+    const bool check_moved = c->ref_valid && same_boxes && c->d_wpos.p == wpos_before;
     TRY(ensure(c->d_key_a, sizeof(int2) * c->n, &c->alloc_generation));
     TRY(ensure(c->d_key_s, sizeof(int2) * c->n, &c->alloc_generation));
     TRY(ensure(c->d_user2arow, sizeof(int) * c->n, &c->alloc_generation));
@@ -700,8 +708,10 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         TRY(upload_grids(c, s));
         const TopoDev topo = topo_of(c);
         GridDev* gd = c->d_grids.as<GridDev>();
+        const double half_skin2 = check_moved ? 0.25 * c->skin * c->skin : -1.0;
         HIP_TRY(launch_bin(c->n, pos, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
-                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), s));
+                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), half_skin2, s));
+        c->ref_valid = true;
         HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
@@ -749,10 +759,18 @@ int examine_status(relres_ctx* c)
     if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
     c->check_pending = false;
     const Status& st = *c->h_status;
+    const unsigned moved = st.moved - c->moved_seen;
+    c->moved_seen = st.moved;
     if (st.nonfinite != c->nonfinite_seen) {
         c->nonfinite_seen = st.nonfinite;
         c->built = false;
+        c->ref_valid = false;
         return fail(RELRES_ERR_NONFINITE, "non-finite position");
+    }
+    c->stats.moved_at_last_build = moved;
+    if (moved > 0) {
+        c->stats.dangerous_builds++;
+        c->warn_pending = true;
     }
     const bool sites = c->n_sites > 0;
     const int mr_a = st.max_row[0], mr_s = st.max_row[1];
@@ -804,6 +822,15 @@ int build_checked(relres_ctx* c, const double* pos, const double* box, hipStream
         c->lanes_stale = false;
     }
     return RELRES_OK;
+}
+
+// RELRES_WARN_DANGEROUS_BUILD once for every build that found atoms more than
+// half the skin from their previous-build positions (lists complete).
+int take_warning(relres_ctx* c)
+{
+    if (!c->warn_pending) return RELRES_OK;
+    c->warn_pending = false;
+    return RELRES_WARN_DANGEROUS_BUILD;
 }
 
 }  // namespace
@@ -881,6 +908,7 @@ const char* relres_strerror(int code)
     case RELRES_ERR_STATE: return "call out of order";
     case RELRES_ERR_LIST_RETRY: return "neighbour lists overflowed: capacity grown, build again";
     case RELRES_ERR_STALE_LISTS: return "an atom moved more than half the skin since the last list build";
+    case RELRES_WARN_DANGEROUS_BUILD: return "warning: atoms had moved more than half the skin since the previous build";
     default: return "unknown error";
     }
 }
@@ -1006,14 +1034,14 @@ int relres_create(const relres_params* p, relres_ctx** out)
         return bail(fail(RELRES_ERR_HIP, "uploading parameters failed"));
     if (hipHostMalloc((void**)&c->h_grids, 2 * sizeof(GridDev), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_status, sizeof(Status), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_zero, sizeof(Status), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&c->h_query, sizeof(Status), hipHostMallocDefault) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "pinned host allocation failed"));
     if (hipEventCreateWithFlags(&c->ev_status, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_upload, hipEventDisableTiming) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "event creation failed"));
     std::memset(c->h_grids, 0, 2 * sizeof(GridDev));
     std::memset(c->h_status, 0, sizeof(Status));
-    std::memset(c->h_zero, 0, sizeof(Status));
+    std::memset(c->h_query, 0, sizeof(Status));
     *out = c;
     return RELRES_OK;
 }
@@ -1064,8 +1092,11 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
         // a build of the previous topology is still unexamined: retire it
         if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
         c->nonfinite_seen = c->h_status->nonfinite;
+        c->moved_seen = c->h_status->moved;
         c->check_pending = false;
     }
+    c->ref_valid = false;
+    c->warn_pending = false;
     c->built = false;
     c->topo_set = false;
     c->lanes_stale = true;
@@ -1119,8 +1150,11 @@ int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
     if (c->check_pending) {
         if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
         c->nonfinite_seen = c->h_status->nonfinite;
+        c->moved_seen = c->h_status->moved;
         c->check_pending = false;
     }
+    c->ref_valid = false;
+    c->warn_pending = false;
     if (nsys > 1 && c->n > 0) {
         TRY(ensure(c->d_sys, sizeof(int) * c->n, &c->alloc_generation));
         HIP_TRY(hipDeviceSynchronize());
@@ -1143,7 +1177,7 @@ int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
 int relres_build_lists(relres_ctx* c, const double* pos, const double* box, void* stream)
 {
     TRY(build_checked(c, pos, box, (hipStream_t)stream));
-    return RELRES_OK;
+    return take_warning(c);
 }
 
 int relres_build_lists_async(relres_ctx* c, const double* pos, const double* box, void* stream)
@@ -1158,7 +1192,33 @@ int relres_build_lists_async(relres_ctx* c, const double* pos, const double* box
 int relres_check_lists(relres_ctx* c)
 {
     if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
-    return examine_status(c);
+    TRY(examine_status(c));
+    return take_warning(c);
+}
+
+int relres_moved_atoms(relres_ctx* c, const double* pos, void* stream, int* count)
+{
+    if (!c || !count) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (c->check_pending) TRY(examine_status(c));
+    if (!c->built || !c->ref_valid) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
+    if (c->n > 0 && !pos) return fail(RELRES_ERR_ARG, "pos is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &capture));
+    if (capture != hipStreamCaptureStatusNone)
+        return fail(RELRES_ERR_STATE, "relres_moved_atoms waits for its result: not in a captured stream");
+    *count = 0;
+    if (c->n == 0) return RELRES_OK;
+    char* st = (char*)c->d_status.p;
+    static_assert(offsetof(Status, moved_query) % 8 == 0, "moved_query starts a 64-bit word");
+    HIP_TRY(launch_clear_words((unsigned long long*)(st + offsetof(Status, moved_query)), 1, s));
+    HIP_TRY(launch_moved(c->n, pos, topo_of(c), c->d_grids.as<GridDev>(), c->d_wpos.as<double4>(),
+                         0.25 * c->skin * c->skin, c->d_status.as<Status>(), s));
+    HIP_TRY(hipMemcpyAsync(&c->h_query->moved_query, st + offsetof(Status, moved_query),
+                           sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *count = (int)c->h_query->moved_query;
+    return RELRES_OK;
 }
 
 int relres_set_launch(relres_ctx* c, int lanes_atom, int lanes_site)
@@ -1599,6 +1659,7 @@ int md_rebuild(relres_ctx* c, const double* pos, hipStream_t s, bool check)
     }
     const double box[3] = {c->box[0], c->box[1], c->box[2]};
     TRY(build_checked(c, pos, box, s));
+    c->warn_pending = false;          // dynamics checks the displacements itself
     HIP_TRY(hipMemcpyAsync(c->d_md_xref.p, pos, sizeof(double) * 3 * c->n, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_clear_words((unsigned long long*)c->d_md_stale.p, 8, s));
     return RELRES_OK;
@@ -1774,7 +1835,7 @@ void relres_destroy(relres_ctx* c)
             release(*b);
     if (c->h_grids) (void)hipHostFree(c->h_grids);
     if (c->h_status) (void)hipHostFree(c->h_status);
-    if (c->h_zero) (void)hipHostFree(c->h_zero);
+    if (c->h_query) (void)hipHostFree(c->h_query);
     for (auto* v : {&c->ev_force, &c->ev_build})
         for (auto& pr : *v) {
             (void)hipEventDestroy(pr.first);

@@ -106,8 +106,11 @@ struct Status {
     int nonfinite;                  // cumulative count of non-finite positions seen
     int max_row[2];                 // longest overflowing row per grid, 0 if none
     int longest[2];                 // longest row per grid (k_list_stats)
-    int pad;
+    unsigned moved;                 // cumulative count, over builds, of atoms found more
+                                    // than half the skin from their previous-build position
     unsigned long long entries[2];  // entries per grid (k_list_stats)
+    unsigned moved_query;           // the same count for relres_moved_atoms
+    unsigned pad;
 };
 
 struct ForceArgs {
@@ -145,8 +148,14 @@ struct ForceArgs {
 };
 
 // Launchers (relres_kernels.hip).  All return hipError_t of the launch.
+// half_skin2 >= 0: before overwriting wpos, count in st->moved the atoms whose
+// position is more than sqrt(half_skin2) (minimum image) from the wpos of the
+// previous build; < 0: no check (no comparable previous build)
 hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev, double4* wpos,
-                      int2* key_a, int2* key_s, Status* st, hipStream_t s);
+                      int2* key_a, int2* key_s, Status* st, double half_skin2, hipStream_t s);
+// st->moved_query += atoms of pos more than sqrt(half_skin2) from wpos
+hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* grids_dev,
+                        const double4* wpos, double half_skin2, Status* st, hipStream_t s);
 hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);

@@ -93,9 +93,29 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 // build kernels
 // ---------------------------------------------------------------------------
 
+// Minimum-image squared distance of (x, y, z) from a wrapped position.
+__device__ __forceinline__ double image_dist2(double x, double y, double z, double4 w,
+                                              const double* L)
+{
+    double dx = x - w.x, dy = y - w.y, dz = z - w.z;
+    dx -= L[0] * rint(dx / L[0]);
+    dy -= L[1] * rint(dy / L[1]);
+    dz -= L[2] * rint(dz / L[2]);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Add the lanes of the wave with `flag` set to *count (one atomic per wave).
+__device__ __forceinline__ void count_wave(bool flag, unsigned* count)
+{
+    const unsigned long long m = __ballot(flag);
+    if (m != 0ull && (int)(threadIdx.x & (kWave - 1)) == __ffsll((long long)m) - 1)
+        atomicAdd(count, (unsigned)__popcll(m));
+}
+
 __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
                       const GridDev* __restrict__ grids, double4* __restrict__ wpos,
-                      int2* __restrict__ key_a, int2* __restrict__ key_s, Status* __restrict__ st)
+                      int2* __restrict__ key_a, int2* __restrict__ key_s, Status* __restrict__ st,
+                      double half_skin2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -107,6 +127,8 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
     }
     const GridDev& ga = grids[0];
     const GeomDev& G = ga.geom[sy];
+    if (half_skin2 >= 0.0)   // displacement since the previous build (same boxes)
+        count_wave(image_dist2(x, y, z, wpos[i], G.box) > half_skin2, &st->moved);
     const double wx = wrap_coord(x, G.box[0]), wy = wrap_coord(y, G.box[1]),
                  wz = wrap_coord(z, G.box[2]);
     wpos[i] = make_double4(wx, wy, wz, 0.0);
@@ -128,6 +150,20 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
     } else {
         key_s[i] = make_int2(-1, -1);
     }
+}
+
+// Atoms now more than half the skin from their position at the last build.
+__global__ void k_moved(int n, const double* __restrict__ pos, TopoDev topo,
+                        const GridDev* __restrict__ grids, const double4* __restrict__ wpos,
+                        double half_skin2, Status* __restrict__ st)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int sy = topo.sys ? topo.sys[i] : 0;
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const GeomDev& G = grids[0].geom[sy];
+    // a non-finite position counts as moved (the comparison is false for NaN)
+    count_wave(!(image_dist2(x, y, z, wpos[i], G.box) <= half_skin2), &st->moved_query);
 }
 
 // One block per grid: exclusive scan of the per-cell counts into `start`,
@@ -1302,11 +1338,20 @@ Cutoffs<S> cut_as(const double* c64)
 // ---------------------------------------------------------------------------
 
 hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev, double4* wpos,
-                      int2* key_a, int2* key_s, Status* st, hipStream_t s)
+                      int2* key_a, int2* key_s, Status* st, double half_skin2, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bin, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, topo, grids_dev,
-                       wpos, key_a, key_s, st);
+                       wpos, key_a, key_s, st, half_skin2);
+    return hipGetLastError();
+}
+
+hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* grids_dev,
+                        const double4* wpos, double half_skin2, Status* st, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_moved, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, topo, grids_dev,
+                       wpos, half_skin2, st);
     return hipGetLastError();
 }
 

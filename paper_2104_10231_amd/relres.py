@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "librelres_hip.so")
 RELRES_OK = 0
 RELRES_ERR_LIST_RETRY = -10
 RELRES_ERR_STALE_LISTS = -11
+RELRES_WARN_DANGEROUS_BUILD = 1
 FTM2V_REAL = 4.184e-4          # (kcal/mol/A) / amu -> A/fs^2
 KB_REAL = 0.0019872067         # kcal/mol/K
 MIX_GEOMETRIC = 0
@@ -49,7 +50,9 @@ class Stats(ctypes.Structure):
                 ("atom_capacity", ctypes.c_int), ("site_capacity", ctypes.c_int),
                 ("atom_cells", ctypes.c_int * 3), ("site_cells", ctypes.c_int * 3),
                 ("builds", ctypes.c_longlong), ("regrows", ctypes.c_longlong),
-                ("box", ctypes.c_double * 3), ("generation", ctypes.c_longlong)]
+                ("box", ctypes.c_double * 3), ("generation", ctypes.c_longlong),
+                ("dangerous_builds", ctypes.c_longlong),
+                ("moved_at_last_build", ctypes.c_longlong)]
 
 
 # exported symbol -> (restype, argtypes); mirrors include/relres.h
@@ -71,6 +74,8 @@ SIGNATURES = {
     "relres_build_lists_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
                                                 ctypes.c_void_p]),
     "relres_check_lists": (ctypes.c_int, [ctypes.c_void_p]),
+    "relres_moved_atoms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int)]),
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -226,6 +231,7 @@ class RelRes:
         self.mix = int(mix)
         self.hybrid = [float(x) > 0.0 for x in self._arrays[2]]
         self.n = 0
+        self.last_check_dangerous = False   # set by check_lists()
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     # -- topology ----------------------------------------------------------
@@ -256,17 +262,24 @@ class RelRes:
             raise ValueError(f"pos has shape {tuple(pos.shape)}, expected ({self.n}, 3)")
         return pos
 
-    def build_lists(self, pos: torch.Tensor, box, stream=None, wait: bool = True):
+    def build_lists(self, pos: torch.Tensor, box, stream=None, wait: bool = True) -> bool:
         """Build both lists.  With wait=False the build is only enqueued; call
-        check_lists() before trusting results computed from these lists."""
+        check_lists() before trusting results computed from these lists.
+
+        Returns True when the (waited-for) build found atoms more than half
+        the skin from their positions at the previous build
+        (RELRES_WARN_DANGEROUS_BUILD: lists used before it were kept too long)."""
         pos = self._pos(pos)
         bx = np.asarray(box, dtype=np.float64).reshape(-1)
         if bx.shape[0] != 3 * self.nsys:
             raise ValueError(f"box needs {3 * self.nsys} values ({self.nsys} systems x 3)")
         b = (ctypes.c_double * bx.shape[0])(*bx.tolist())
         fn = self._lib.relres_build_lists if wait else self._lib.relres_build_lists_async
-        _check(fn(self._ctx, pos.data_ptr() if self.n else None, b, _stream(stream)),
-               "relres_build_lists" if wait else "relres_build_lists_async")
+        rc = fn(self._ctx, pos.data_ptr() if self.n else None, b, _stream(stream))
+        if rc == RELRES_WARN_DANGEROUS_BUILD:
+            return True
+        _check(rc, "relres_build_lists" if wait else "relres_build_lists_async")
+        return False
 
     def check_lists(self) -> bool:
         """True when the last build's lists are complete; False when a row
@@ -274,8 +287,20 @@ class RelRes:
         rc = self._lib.relres_check_lists(self._ctx)
         if rc == RELRES_ERR_LIST_RETRY:
             return False
-        _check(rc, "relres_check_lists")
+        self.last_check_dangerous = rc == RELRES_WARN_DANGEROUS_BUILD
+        if not self.last_check_dangerous:
+            _check(rc, "relres_check_lists")
         return True
+
+    def moved_atoms(self, pos: torch.Tensor, stream=None) -> int:
+        """Atoms of pos more than half the skin from their positions at the
+        last build (0: the lists are still exact).  Waits for the result."""
+        pos = self._pos(pos)
+        n = ctypes.c_int()
+        _check(self._lib.relres_moved_atoms(self._ctx, pos.data_ptr() if self.n else None,
+                                            _stream(stream), ctypes.byref(n)),
+               "relres_moved_atoms")
+        return n.value
 
     def forces(self, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
                energy: Optional[torch.Tensor] = None, virial: Optional[torch.Tensor] = None,

@@ -45,22 +45,23 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2104_10231_amd.relres import Params, Stats
     c = tmp_path / "sz.c"
     c.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "relres.h"\n'
-                 'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                 'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                  ' sizeof(relres_params), sizeof(relres_stats), offsetof(relres_params, mix),'
                  ' offsetof(relres_params, no_shift), offsetof(relres_params, cut_type),'
                  ' offsetof(relres_params, cut_pair),'
-                 ' offsetof(relres_stats, builds), offsetof(relres_stats, box)); return 0;}\n')
+                 ' offsetof(relres_stats, builds), offsetof(relres_stats, box),'
+                 ' offsetof(relres_stats, moved_at_last_build)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
     got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
     assert got == [ctypes.sizeof(Params), ctypes.sizeof(Stats), Params.mix.offset,
                    Params.no_shift.offset, Params.cut_type.offset, Params.cut_pair.offset,
-                   Stats.builds.offset, Stats.box.offset]
+                   Stats.builds.offset, Stats.box.offset, Stats.moved_at_last_build.offset]
 
 
 def test_version_and_error_strings(lib):
-    assert lib.relres_abi_version() == 2
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9):
+    assert lib.relres_abi_version() == 3
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, 1):
         s = lib.relres_strerror(code).decode()
         assert s and s != "unknown error"
     assert lib.relres_strerror(-100).decode() == "unknown error"
@@ -115,6 +116,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.relres_bonded_forces(None, None, None, None, None, None) == -1
     assert lib.relres_md_setup(None, None, 1.0, 1.0, 1.0, 1.0, 1) == -1
     assert lib.relres_md_run(None, None, None, 1, 0, None, None) == -1
+    assert lib.relres_moved_atoms(None, None, None, None) == -1
+    assert lib.relres_check_lists(None) == -1
     lib.relres_destroy(None)
 
 
