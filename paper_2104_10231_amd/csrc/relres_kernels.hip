@@ -372,8 +372,9 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
     // known image shifts need at least four cells along every axis
     const bool known_shift = n0 >= 4 && n1 >= 4 && n2 >= 4;
-    const int r0 = G.row_base + (lw - G.wave_base) * kRowsPerWave;
-    const int r1 = min(G.row_base + G.members, r0 + kRowsPerWave);
+    const int R = g.rows_per_wave;
+    const int r0 = G.row_base + (lw - G.wave_base) * R;
+    const int r1 = min(G.row_base + G.members, r0 + R);
     const double hx = G.half[0], hy = G.half[1], hz = G.half[2];
     const double rl2 = g.rl2;
     const int cap = g.cap;
@@ -481,13 +482,23 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                 const int* hex = my_excl + h * max_excl;
                 int hc = readlane_i(mcnt, h);
                 RELRES_GLOBAL int* out = glist + (size_t)(r0 + h) * cap;
+                bool keep_k[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    keep_k[k] = pu[k] >= 0 && pu[k] != ui && !(same_mol && pm[k] == moli);
+                // the row's exclusions: each read once for all K candidates,
+                // several reads in flight before the first compare
+#pragma unroll 4
+                for (int e = 0; e < ne; ++e) {
+                    const int x = hex[e];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) keep_k[k] = keep_k[k] && pu[k] != x;
+                }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (cb + kWave * k >= ncand) break;
                     const int uj = pu[k];
-                    bool keep = uj >= 0 && uj != ui && !(same_mol && pm[k] == moli);
-                    for (int e = 0; e < ne; ++e)
-                        if (hex[e] == uj) keep = false;
+                    bool keep = keep_k[k];
                     if (keep) {
                         if (known_shift) {
                             const int c6 = ps[k];

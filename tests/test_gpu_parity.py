@@ -373,6 +373,36 @@ def test_cell_per_block_list_kernel(monkeypatch):
     _check(s.conventional(), 64)
 
 
+@pytest.mark.parametrize("rows", ["1,1", "2,5", "4,3"])
+def test_rows_per_wave_of_the_list_kernel(monkeypatch, rows):
+    """Any number of home rows per list-kernel wave (RELRES_LIST_ROWS =
+    "atom,site") builds the same lists: pair sets equal to the oracle's and
+    forces, energies and virials bitwise equal to the default's, for a liquid
+    with bonded exclusions and for a batch of systems."""
+    import torch
+    s = w.hexane_liquid(2, n_mol=150, density=0.012)
+    b = w.replica_batch(4, n_systems=4, min_atoms=300, max_atoms=700, total_atoms=2000)
+
+    def batch_run():
+        rr = make_relres(b.whole, 32)
+        rr.set_systems(b.offsets)
+        p = torch.from_numpy(b.whole.pos).cuda()
+        rr.build_lists(p, b.boxes)
+        out = [t.double().cpu().numpy() for t in rr.forces(p)]
+        rr.close()
+        return out
+
+    base = gpu_run(s, 32)[1:]
+    base_b = batch_run()
+    monkeypatch.setenv("RELRES_LIST_ROWS", rows)
+    _check(s, 32)
+    got = gpu_run(s, 32)[1:]
+    for x, y in zip(got, base):
+        assert np.array_equal(x, y)
+    for x, y in zip(batch_run(), base_b):
+        assert np.array_equal(x, y)
+
+
 def test_graph_replay_matches_eager():
     """relres_forces captured in a HIP graph: every replay, with eager library
     work and synchronisation in between, reproduces the eager results bitwise."""
