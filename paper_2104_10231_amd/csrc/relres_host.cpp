@@ -310,9 +310,9 @@ struct relres_ctx {
     // bonded terms and scaled 1-4 pairs (relres_set_bonded)
     bool has_bonded = false;
     double scale14 = 0.0;
-    DBuf d_term_off, d_term_ent, d_bonds, d_bond_par, d_angles, d_angle_par, d_dihs, d_dih_par;
-    DBuf d_p14_off, d_p14_idx, d_bond_part, d_bond_part2, d_bond_sum, d_ent_force;
-    int n_ent = 0;                    // (term, slot) entries
+    DBuf d_items, d_bond_par, d_angle_par, d_dih_par, d_bond_part, d_bond_sum;
+    int bond_slots = 1;               // bonded items per atom (padded)
+    int bond_lg = 0;                  // lanes per atom of the bonded kernel = 2^bond_lg
     // dynamics (relres_md_setup / relres_md_run)
     bool md_ready = false;
     double md_ftm2v = 0.0;
@@ -1474,53 +1474,64 @@ int relres_set_bonded(relres_ctx* c, int nbonds, const int* bonds, const double*
             pairs14[2 * t] == pairs14[2 * t + 1])
             return fail(RELRES_ERR_TOPOLOGY, "bad 1-4 pair %d", t);
 
-    // per atom: the terms it belongs to (bonds, angles, dihedrals, in order)
-    std::vector<std::vector<uint32_t>> per(n);
-    auto add = [&](int atom, uint32_t kind, uint32_t slot, int t) {
-        per[atom].push_back((kind << 30) | (slot << 28) | (uint32_t)t);
+    // per atom: the terms it belongs to (bonds, angles, dihedrals, in order),
+    // then its 1-4 partners (ascending)
+    std::vector<std::vector<BondItem>> per(n);
+    auto add = [&](int atom, int kind, int slot, int t, const int* q) {
+        BondItem it{};
+        it.kind = kind;
+        it.slot = slot;
+        it.i = q[0];
+        it.j = q[1];
+        it.k = kind >= 1 ? q[2] : 0;
+        it.l = kind == 2 ? q[3] : 0;
+        it.par = t;
+        per[atom].push_back(it);
     };
     for (int t = 0; t < nbonds; ++t)
-        for (int u = 0; u < 2; ++u) add(bonds[2 * t + u], 0, u, t);
+        for (int u = 0; u < 2; ++u) add(bonds[2 * t + u], 0, u, t, bonds + 2 * t);
     for (int t = 0; t < nangles; ++t)
-        for (int u = 0; u < 3; ++u) add(angles[3 * t + u], 1, u, t);
+        for (int u = 0; u < 3; ++u) add(angles[3 * t + u], 1, u, t, angles + 3 * t);
     for (int t = 0; t < ndihedrals; ++t)
-        for (int u = 0; u < 4; ++u) add(dihedrals[4 * t + u], 2, u, t);
-    std::vector<int> toff(n + 1, 0);
-    std::vector<uint32_t> tent;
-    for (int a = 0; a < n; ++a) {
-        tent.insert(tent.end(), per[a].begin(), per[a].end());
-        toff[a + 1] = (int)tent.size();
-    }
+        for (int u = 0; u < 4; ++u) add(dihedrals[4 * t + u], 2, u, t, dihedrals + 4 * t);
     std::vector<std::vector<int>> part(n);
     for (int t = 0; t < npairs14; ++t) {
         part[pairs14[2 * t]].push_back(pairs14[2 * t + 1]);
         part[pairs14[2 * t + 1]].push_back(pairs14[2 * t]);
     }
-    std::vector<int> poff(n + 1, 0), pidx;
+    const int nt = c->ntypes;
     for (int a = 0; a < n; ++a) {
         std::sort(part[a].begin(), part[a].end());
-        pidx.insert(pidx.end(), part[a].begin(), part[a].end());
-        poff[a + 1] = (int)pidx.size();
+        for (int j : part[a]) {
+            BondItem it{};
+            it.kind = 3;
+            it.i = a;
+            it.j = j;
+            it.par = c->h_types[a] * nt + c->h_types[j];
+            per[a].push_back(it);
+        }
     }
-    std::vector<int2> hb(nbonds);
+    // items per atom: a power of two holding every atom's list; lanes per
+    // atom: as many, at most 32 (more items are taken in turns)
+    size_t most = 1;
+    for (int a = 0; a < n; ++a) most = std::max(most, per[a].size());
+    if (most > 4096) return fail(RELRES_ERR_TOPOLOGY, "an atom has %zu bonded items (max 4096)", most);
+    int slots = 1;
+    while ((size_t)slots < most) slots <<= 1;
+    int lg = 0;
+    while ((1 << lg) < slots && lg < 5) ++lg;
+    BondItem none{};
+    none.kind = -1;
+    std::vector<BondItem> items((size_t)n * slots, none);
+    for (int a = 0; a < n; ++a)
+        std::copy(per[a].begin(), per[a].end(), items.begin() + (size_t)a * slots);
     std::vector<double2> hbp(nbonds);
-    for (int t = 0; t < nbonds; ++t) {
-        hb[t] = make_int2(bonds[2 * t], bonds[2 * t + 1]);
-        hbp[t] = make_double2(bond_k[t], bond_r0[t]);
-    }
-    std::vector<int4> ha(nangles);
+    for (int t = 0; t < nbonds; ++t) hbp[t] = make_double2(bond_k[t], bond_r0[t]);
     std::vector<double2> hap(nangles);
-    for (int t = 0; t < nangles; ++t) {
-        ha[t] = make_int4(angles[3 * t], angles[3 * t + 1], angles[3 * t + 2], 0);
-        hap[t] = make_double2(angle_k[t], angle_t0[t]);
-    }
-    std::vector<int4> hd(ndihedrals);
+    for (int t = 0; t < nangles; ++t) hap[t] = make_double2(angle_k[t], angle_t0[t]);
     std::vector<double4> hdp(ndihedrals);
-    for (int t = 0; t < ndihedrals; ++t) {
-        hd[t] = make_int4(dihedrals[4 * t], dihedrals[4 * t + 1], dihedrals[4 * t + 2],
-                          dihedrals[4 * t + 3]);
-        hdp[t] = make_double4(dih_k[t], (double)dih_n[t], dih_d[t], 0.0);
-    }
+    for (int t = 0; t < ndihedrals; ++t)
+        hdp[t] = make_double4(dih_k[t], (double)dih_n[t], std::cos(dih_d[t]), std::sin(dih_d[t]));
     // the buffers may be in use by work still queued on any stream
     HIP_TRY(hipDeviceSynchronize());
     long long* gen = &c->alloc_generation;
@@ -1529,22 +1540,17 @@ int relres_set_bonded(relres_ctx* c, int nbonds, const int* bonds, const double*
         if (bytes) HIP_TRY(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
         return RELRES_OK;
     };
-    TRY(up(c->d_term_off, toff.data(), sizeof(int) * toff.size()));
-    TRY(up(c->d_term_ent, tent.data(), sizeof(uint32_t) * tent.size()));
-    TRY(up(c->d_bonds, hb.data(), sizeof(int2) * hb.size()));
+    TRY(up(c->d_items, items.data(), sizeof(BondItem) * items.size()));
     TRY(up(c->d_bond_par, hbp.data(), sizeof(double2) * hbp.size()));
-    TRY(up(c->d_angles, ha.data(), sizeof(int4) * ha.size()));
     TRY(up(c->d_angle_par, hap.data(), sizeof(double2) * hap.size()));
-    TRY(up(c->d_dihs, hd.data(), sizeof(int4) * hd.size()));
     TRY(up(c->d_dih_par, hdp.data(), sizeof(double4) * hdp.size()));
-    TRY(up(c->d_p14_off, poff.data(), sizeof(int) * poff.size()));
-    TRY(up(c->d_p14_idx, pidx.data(), sizeof(int) * pidx.size()));
-    const int n_ent = (int)tent.size();
-    TRY(ensure(c->d_ent_force, sizeof(double) * 3 * (size_t)std::max(1, n_ent), gen));
-    TRY(ensure(c->d_bond_part, sizeof(double) * 10 * (size_t)std::max(1, md_blocks(n_ent)), gen));
-    TRY(ensure(c->d_bond_part2, sizeof(double) * 10 * (size_t)std::max(1, md_blocks(n)), gen));
+    const int nblk = bonded_blocks(n, lg);
+    TRY(ensure(c->d_bond_part, sizeof(double) * 10 * (size_t)std::max(1, nblk), gen));
     TRY(ensure(c->d_bond_sum, sizeof(double) * 16, gen));
-    c->n_ent = n_ent;
+    // kinetic partials of the kick (one per bonded block) and of k_md_kinetic
+    TRY(ensure(c->d_md_part, sizeof(double) * (size_t)std::max({1, nblk, md_blocks(n)}), gen));
+    c->bond_lg = lg;
+    c->bond_slots = slots;
     c->scale14 = scale14;
     c->has_bonded = true;
     return RELRES_OK;
@@ -1559,31 +1565,21 @@ int enqueue_bonded(relres_ctx* c, const double* pos, void* forces, bool sums, co
     b.pos = pos;
     for (int k = 0; k < 3; ++k) b.box[k] = c->box[k];
     b.n = c->n;
-    b.term_off = c->d_term_off.as<int>();
-    b.term_ent = c->d_term_ent.as<uint32_t>();
-    b.n_ent = c->n_ent;
-    b.ent_force = c->d_ent_force.as<double>();
-    b.bonds = c->d_bonds.as<int2>();
+    b.items = c->d_items.as<BondItem>();
+    b.slots = c->bond_slots;
     b.bond_par = c->d_bond_par.as<double2>();
-    b.angles = c->d_angles.as<int4>();
     b.angle_par = c->d_angle_par.as<double2>();
-    b.dihs = c->d_dihs.as<int4>();
     b.dih_par = c->d_dih_par.as<double4>();
-    b.p14_off = c->d_p14_off.as<int>();
-    b.p14_idx = c->d_p14_idx.as<int>();
     b.scale14 = c->scale14;
-    b.types = c->d_types.as<int>();
-    b.ntypes = c->ntypes;
     b.coef64 = c->d_coef64.as<PairCoef<double>>();
     b.pcut64 = c->d_pcut64.as<Cutoffs<double>>();
     b.forces = forces;
     b.partial = sums ? c->d_bond_part.as<double>() : nullptr;
-    b.partial2 = sums ? c->d_bond_part2.as<double>() : nullptr;
+    b.log_lanes = c->bond_lg;
     HIP_TRY(launch_bonded(b, m, c->precision, s));
     if (sums)
-        HIP_TRY(launch_sum_partials(c->d_bond_part.as<double>(), c->n_ent > 0 ? md_blocks(c->n_ent) : 0,
-                                    c->d_bond_part2.as<double>(), md_blocks(c->n), 10,
-                                    c->d_bond_sum.as<double>(), s));
+        HIP_TRY(launch_sum_partials(c->d_bond_part.as<double>(), bonded_blocks(c->n, c->bond_lg),
+                                    nullptr, 0, 10, c->d_bond_sum.as<double>(), s));
     return RELRES_OK;
 }
 
@@ -1627,7 +1623,7 @@ int relres_md_setup(relres_ctx* c, const double* masses, double dt, double kT, d
     TRY(ensure(c->d_md_F, (c->precision == 64 ? 8 : 4) * 3 * (size_t)n, gen));
     TRY(ensure(c->d_md_E, sizeof(double) * 3, gen));
     TRY(ensure(c->d_md_W, sizeof(double) * 6, gen));
-    TRY(ensure(c->d_md_part, sizeof(double) * (size_t)md_blocks(n), gen));
+    TRY(ensure(c->d_md_part, sizeof(double) * (size_t)std::max(md_blocks(n), bonded_blocks(n, c->bond_lg)), gen));
     TRY(ensure(c->d_md_stale, 64, gen));
     TRY(ensure(c->d_bond_sum, sizeof(double) * 16, gen));
     if (!c->h_stale && hipHostMalloc((void**)&c->h_stale, 64, hipHostMallocDefault) != hipSuccess)
@@ -1719,7 +1715,8 @@ int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int therm
     m.stale = (unsigned*)c->d_md_stale.p;
     m.partial = c->d_md_part.as<double>();
     m.st = c->d_md_state.as<MdState>();
-    const int nblk = md_blocks(c->n);
+    const int nblk = md_blocks(c->n);                       // partials of k_md_kinetic
+    const int nblk_kick = bonded_blocks(c->n, c->bond_lg);  // partials of the kick
     const double* e_nb = c->d_md_E.as<double>();
     const double* w_nb = c->d_md_W.as<double>();
     const double* eb = c->d_bond_sum.as<double>();
@@ -1739,7 +1736,7 @@ int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int therm
                           out ? c->d_md_W.as<double>() : nullptr, s));
         // bonded and 1-4 forces, the half kick and the kinetic partials
         TRY(enqueue_bonded(c, pos, F, out, &m, s));
-        HIP_TRY(launch_md_scalar(m.st, m.partial, nblk, m.ftm2v, 1, step < nsteps, e_nb, w_nb, eb,
+        HIP_TRY(launch_md_scalar(m.st, m.partial, nblk_kick, m.ftm2v, 1, step < nsteps, e_nb, w_nb, eb,
                                  out ? thermo + (size_t)8 * (step / thermo_every - 1) : nullptr, s));
     }
     HIP_TRY(launch_md_finish(m, s));
@@ -1845,9 +1842,8 @@ void relres_destroy(relres_ctx* c)
     if (!c) return;
     (void)hipDeviceSynchronize();
     for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial, &c->d_sys, &c->d_boxes, &c->d_row_ew}) release(*b);
-    for (DBuf* b : {&c->d_term_off, &c->d_term_ent, &c->d_bonds, &c->d_bond_par, &c->d_angles,
-                    &c->d_angle_par, &c->d_dihs, &c->d_dih_par, &c->d_p14_off, &c->d_p14_idx,
-                    &c->d_bond_part, &c->d_bond_part2, &c->d_bond_sum, &c->d_ent_force,
+    for (DBuf* b : {&c->d_items, &c->d_bond_par, &c->d_angle_par, &c->d_dih_par,
+                    &c->d_bond_part, &c->d_bond_sum,
                     &c->d_mass, &c->d_md_state, &c->d_md_xref,
                     &c->d_md_F, &c->d_md_E, &c->d_md_W, &c->d_md_part, &c->d_md_stale})
         release(*b);

@@ -194,36 +194,39 @@ hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const doub
 // Bonded terms and scaled 1-4 pairs (relres_md.hip).  Per atom, the terms
 // it belongs to: term_ent packs kind (bits 30-31: 0 bond, 1 angle,
 // 2 dihedral), the atom's slot in the term (bits 28-29) and the term index.
+// One item of an atom's bonded work: a (term, slot) entry or a 1-4 partner.
+// Atoms of the term in the term's order (a bond uses i, j; an angle i, j =
+// vertex, k; a dihedral i, j, k, l); a 1-4 item has i = the atom, j = the
+// partner and par = the pair's type-pair index.  kind -1 marks padding.
+struct BondItem {
+    int kind;                         // 0 bond, 1 angle, 2 dihedral, 3 1-4 pair, -1 none
+    int slot;                         // the atom's place in the term
+    int i, j, k, l;
+    int par;                          // row of bond_par / angle_par / dih_par, or type pair
+    int pad;
+};
 struct BondedArgs {
     const double* pos;
     double box[3];
     int n;
-    const int* term_off;              // [n + 1]
-    const uint32_t* term_ent;         // n_ent entries, grouped by atom
-    int n_ent;
-    double* ent_force;                // n_ent x 3: force of each entry on its atom
-    const int2* bonds;
+    const BondItem* items;            // n x slots, atom-major; padded with kind -1
+    int slots;                        // items per atom (a power of two)
     const double2* bond_par;          // K, r0
-    const int4* angles;               // i, j (vertex), k, unused
     const double2* angle_par;         // K, theta0
-    const int4* dihs;
-    const double4* dih_par;           // K, n, d, unused
-    const int* p14_off;               // [n + 1]
-    const int* p14_idx;               // 1-4 partners of each atom
+    const double4* dih_par;           // K, n, cos d, sin d
     double scale14;
-    const int* types;
-    int ntypes;
     const PairCoef<double>* coef64;
     const Cutoffs<double>* pcut64;
     void* forces;                     // N x 3 of the force type; added to
-    double* partial;                  // per entry block: 4 energies, 6 virial; or null
-    double* partial2;                 // per atom block: 4 energies, 6 virial; or null
+    double* partial;                  // per block: 4 energies, 6 virial; or null
+    int log_lanes;                    // lanes per atom = 2^log_lanes (<= slots, <= 32)
 };
 struct MdArgs;
 // Bonded and 1-4 forces added to b.forces; with m, also the half kick of a
 // dynamics step and the kinetic partials (m->partial).
 hipError_t launch_bonded(const BondedArgs& b, const MdArgs* m, int force_prec, hipStream_t s);
-int md_blocks(int n);                 // blocks of the per-atom (and per-entry) kernels
+int md_blocks(int n);                 // blocks of the one-thread-per-atom kernels
+int bonded_blocks(int n, int log_lanes);   // blocks of the bonded kernel
 // out[k] = sum of p1[blk * K + k] over its blocks, then of p2, in block order
 hipError_t launch_sum_partials(const double* p1, int n1, const double* p2, int n2, int K,
                                double* out, hipStream_t s);

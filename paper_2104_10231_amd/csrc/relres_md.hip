@@ -2,11 +2,11 @@
 // pair potential (Sec. 3.2 of the paper): bonded terms, scaled 1-4 pairs and
 // a Nose-Hoover velocity-Verlet integrator.
 //
-// Bonded terms: one thread per (term, slot) entry computes the term in FP64
-// and writes the force on its slot's atom; a second kernel gives each atom
-// the sum of its entries in a fixed order, adds its scaled 1-4 pairs and, in
-// a dynamics step, the half kick.  A term's energy and virial are counted by
-// its first slot.  No atomics, so results are deterministic.  Formulas
+// Bonded terms: a group of lanes per atom evaluates the atom's (term, slot)
+// entries and scaled 1-4 pairs side by side in FP64 and sums their forces
+// with lane moves in a fixed order; in a dynamics step the same kernel gives
+// the half kick.  A term's energy and virial are counted by its first slot.
+// No atomics, so results are deterministic.  Formulas
 // (forces are -dE/dx):
 //   bond      E = K (r - r0)^2, d = x_i - x_j: F_i = -2K (r - r0) d / r
 //   angle     E = K (theta - theta0)^2, a = x_i - x_j, b = x_k - x_j:
@@ -23,6 +23,7 @@
 // parts, the pair's own distances) times the 1-4 factor.
 #include "relres_internal.h"
 #include "relres_pair.h"
+#include "relres_lanes.h"
 
 namespace relres {
 namespace {
@@ -81,156 +82,193 @@ __device__ __forceinline__ double block_sum(const double* v, double (*red)[kMdBl
     return r;
 }
 
-// Force of every (term, slot) entry on its atom, entries in the per-atom
-// order of term_ent; with `partial` each block writes its 10 sums (energies:
-// bonds, angles, dihedrals, 0; virial xx yy zz xy xz yz).
-__global__ __launch_bounds__(kMdBlock) void k_bonded_terms(BondedArgs b)
+// The force of one (term, slot) entry on its atom, added to fa; the term's
+// energy and virial go to acc (energies 0..2, virial 4..9) from its first
+// slot only.
+__device__ __forceinline__ void entry_force(const BondedArgs& b, const BondItem& it,
+                                            double fa[3], double acc[10])
+{
+    const int kind = it.kind, slot = it.slot, t = it.par;
+    double f[4][3];
+    if (kind == 0) {
+        const double2 par = b.bond_par[t];
+        double d[3];
+        mi_diff(b.pos, it.i, it.j, b.box, d);
+        const double r = sqrt(dot3(d, d));
+        const double dr = r - par.y;
+        const double sc = -2.0 * par.x * dr / r;
+        for (int c = 0; c < 3; ++c) {
+            f[0][c] = sc * d[c];
+            f[1][c] = -f[0][c];
+        }
+        if (slot == 0) {
+            acc[0] += par.x * dr * dr;
+            add_virial(acc + 4, d, f[0]);
+        }
+    } else if (kind == 1) {
+        const double2 par = b.angle_par[t];
+        double u[3], v[3];
+        mi_diff(b.pos, it.i, it.j, b.box, u);
+        mi_diff(b.pos, it.k, it.j, b.box, v);
+        // reciprocals once: a divide is a long instruction sequence in FP64
+        const double ilu = 1.0 / sqrt(dot3(u, u)), ilv = 1.0 / sqrt(dot3(v, v));
+        double c = dot3(u, v) * ilu * ilv;
+        c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+        const double th = acos(c);
+        const double dth = th - par.y;
+        const double g = 2.0 * par.x * dth / sqrt((1.0 - c) * (1.0 + c));   // sin theta
+        for (int q = 0; q < 3; ++q) {
+            f[0][q] = g * (v[q] * ilv - c * u[q] * ilu) * ilu;
+            f[2][q] = g * (u[q] * ilu - c * v[q] * ilv) * ilv;
+            f[1][q] = -f[0][q] - f[2][q];
+        }
+        if (slot == 0) {
+            acc[1] += par.x * dth * dth;
+            add_virial(acc + 4, u, f[0]);
+            add_virial(acc + 4, v, f[2]);
+        }
+    } else {
+        const double4 par = b.dih_par[t];      // K, n, cos d, sin d
+        double b1[3], b2[3], b3[3], m[3], nn[3];
+        mi_diff(b.pos, it.j, it.i, b.box, b1);
+        mi_diff(b.pos, it.k, it.j, b.box, b2);
+        mi_diff(b.pos, it.l, it.k, b.box, b3);
+        cross3(b1, b2, m);
+        cross3(b2, b3, nn);
+        const double lb2 = sqrt(dot3(b2, b2));
+        // phi = atan2(y, x) without the library calls: cos phi = x / r,
+        // sin phi = y / r (r = |m||n|), cos and sin of n phi by repeated
+        // angle addition, then of n phi - d with cos d, sin d from the host
+        const double x = dot3(m, nn), y = lb2 * dot3(b1, nn);
+        const double ir = 1.0 / sqrt(x * x + y * y);
+        const double cp = x * ir, sp = y * ir;
+        double cn = 1.0, sn = 0.0;
+        for (int k = 0; k < (int)par.y; ++k) {
+            const double c2 = cn * cp - sn * sp;
+            sn = sn * cp + cn * sp;
+            cn = c2;
+        }
+        const double cos_arg = cn * par.z + sn * par.w;
+        const double sin_arg = sn * par.z - cn * par.w;
+        const double dE = -par.x * par.y * sin_arg;
+        const double imm = lb2 / dot3(m, m), in2 = lb2 / dot3(nn, nn);
+        const double ib2 = 1.0 / (lb2 * lb2);
+        const double p = dot3(b1, b2) * ib2, q = dot3(b3, b2) * ib2;
+        for (int c = 0; c < 3; ++c) {
+            const double gi = -m[c] * imm, gl = nn[c] * in2;
+            f[0][c] = -dE * gi;
+            f[3][c] = -dE * gl;
+            f[1][c] = -dE * (-(1.0 + p) * gi + q * gl);
+            f[2][c] = -dE * (p * gi - (1.0 + q) * gl);
+        }
+        if (slot == 0) {
+            acc[2] += par.x * (1.0 + cos_arg);
+            const double li[3] = {-b1[0], -b1[1], -b1[2]};
+            const double ll[3] = {b2[0] + b3[0], b2[1] + b3[1], b2[2] + b3[2]};
+            add_virial(acc + 4, li, f[0]);
+            add_virial(acc + 4, b2, f[2]);
+            add_virial(acc + 4, ll, f[3]);
+        }
+    }
+    for (int c = 0; c < 3; ++c) fa[c] += f[slot][c];
+}
+
+// The scaled 1-4 pair (a, j) through Eq. 20 (FG and CG parts, the pair's own
+// distances), seen from atom a: its force on a added to fa, half its energy
+// to acc[3] and half its virial to acc[4..9] (the pair is met from both atoms).
+__device__ __forceinline__ void pair14_force(const BondedArgs& b, const BondItem& it,
+                                             double fa[3], double acc[10])
+{
+    double d[3];
+    mi_diff(b.pos, it.i, it.j, b.box, d);      // x_a - x_j
+    const double r2 = dot3(d, d);
+    const int pi = it.par;
+    const Cutoffs<double>& cut = b.pcut64[pi];
+    double fp = 0.0, en = 0.0;
+    if (r2 < cut.rso2) {
+        double f1, e1;
+        fg_term<MathF64<2>>(b.coef64[pi], cut, r2, f1, e1);
+        fp += f1;
+        en += e1;
+    }
+    if (r2 < cut.rco2) {
+        double f2, e2;
+        cg_term<MathF64<2>>(b.coef64[pi], cut, r2, f2, e2);
+        fp += f2;
+        en += e2;
+    }
+    const double s = b.scale14 * fp;           // F_a = s (x_a - x_j)
+    const double f[3] = {s * d[0], s * d[1], s * d[2]};
+    for (int c = 0; c < 3; ++c) fa[c] += f[c];
+    acc[3] += 0.5 * b.scale14 * en;
+    const double hd[3] = {0.5 * d[0], 0.5 * d[1], 0.5 * d[2]};
+    add_virial(acc + 4, hd, f);
+}
+
+// Bonded and 1-4 forces, one aligned group of 2^log_lanes lanes per atom:
+// the lanes take the atom's items (its term entries in order, then its 1-4
+// partners; one padded record each, so a lane needs no offset table) in
+// turn, and the group adds their forces with lane moves in a fixed order, so
+// an atom's items are evaluated side by side and no force passes through
+// memory.  The group's first lane adds the sum to `forces`
+// and, in a dynamics step (kick != 0), gives the half kick v += dt/2 F/m and
+// the kinetic term of the block partial.  With b.partial every block writes
+// its 10 sums (energies: bonds, angles, dihedrals, 1-4; virial).  No
+// atomics, so results are deterministic.
+template <typename TF>
+__global__ __launch_bounds__(kMdBlock) void k_bonded(BondedArgs b, MdArgs m, int kick)
 {
     __shared__ double red[10][kMdBlock];
-    const int e = blockIdx.x * kMdBlock + threadIdx.x;
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // energies 0..3, virial 4..9
-    if (e < b.n_ent) {
-        const uint32_t ent = b.term_ent[e];
-        const int kind = (int)(ent >> 30), slot = (int)((ent >> 28) & 3u);
-        const int t = (int)(ent & 0x0fffffffu);
-        double f[4][3];
-        if (kind == 0) {
-            const int2 ij = b.bonds[t];
-            const double2 par = b.bond_par[t];
-            double d[3];
-            mi_diff(b.pos, ij.x, ij.y, b.box, d);
-            const double r = sqrt(dot3(d, d));
-            const double dr = r - par.y;
-            const double sc = -2.0 * par.x * dr / r;
+    const int lg = b.log_lanes;
+    const int G = 1 << lg;
+    const int gid = blockIdx.x * kMdBlock + (int)threadIdx.x;
+    const int a = gid >> lg;
+    const int sub = gid & (G - 1);
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double fa[3] = {0.0, 0.0, 0.0};
+    const bool live = a < b.n;
+    const bool lead = live && sub == 0;
+    // the leader's own data first: it does not depend on the items
+    TF* F = (TF*)b.forces;
+    TF f0[3] = {TF(0), TF(0), TF(0)};
+    double v0[3] = {0.0, 0.0, 0.0}, ma = 1.0;
+    if (lead) {
+        for (int c = 0; c < 3; ++c) f0[c] = F[3 * a + c];
+        if (kick) {
+            for (int c = 0; c < 3; ++c) v0[c] = m.vel[3 * a + c];
+            ma = m.mass[a];
+        }
+    }
+    if (live) {
+        const BondItem* items = b.items + (size_t)a * b.slots;
+        for (int k = sub; k < b.slots; k += G) {
+            const BondItem it = items[k];
+            if (it.kind == 3) pair14_force(b, it, fa, acc);
+            else if (it.kind >= 0) entry_force(b, it, fa, acc);
+        }
+    }
+    // every lane takes part in the group sums (idle lanes add zeros)
+    for (int c = 0; c < 3; ++c) fa[c] = group_sum(fa[c], G);
+    double ke = 0.0;
+    if (lead) {
+        TF ft[3];
+        for (int c = 0; c < 3; ++c) {
+            ft[c] = f0[c] + (TF)fa[c];
+            F[3 * a + c] = ft[c];
+        }
+        if (kick) {
+            const double dt = m.st->dt;
+            const double am = m.ftm2v / ma;
             for (int c = 0; c < 3; ++c) {
-                f[0][c] = sc * d[c];
-                f[1][c] = -f[0][c];
-            }
-            if (slot == 0) {
-                acc[0] += par.x * dr * dr;
-                add_virial(acc + 4, d, f[0]);
-            }
-        } else if (kind == 1) {
-            const int4 ijk = b.angles[t];
-            const double2 par = b.angle_par[t];
-            double u[3], v[3];
-            mi_diff(b.pos, ijk.x, ijk.y, b.box, u);
-            mi_diff(b.pos, ijk.z, ijk.y, b.box, v);
-            const double lu = sqrt(dot3(u, u)), lv = sqrt(dot3(v, v));
-            double c = dot3(u, v) / (lu * lv);
-            c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-            const double th = acos(c);
-            const double dth = th - par.y;
-            const double g = 2.0 * par.x * dth / sin(th);
-            for (int q = 0; q < 3; ++q) {
-                f[0][q] = g * (v[q] / lv - c * u[q] / lu) / lu;
-                f[2][q] = g * (u[q] / lu - c * v[q] / lv) / lv;
-                f[1][q] = -f[0][q] - f[2][q];
-            }
-            if (slot == 0) {
-                acc[1] += par.x * dth * dth;
-                add_virial(acc + 4, u, f[0]);
-                add_virial(acc + 4, v, f[2]);
-            }
-        } else {
-            const int4 q4 = b.dihs[t];
-            const double4 par = b.dih_par[t];      // K, n, d
-            double b1[3], b2[3], b3[3], m[3], nn[3];
-            mi_diff(b.pos, q4.y, q4.x, b.box, b1);
-            mi_diff(b.pos, q4.z, q4.y, b.box, b2);
-            mi_diff(b.pos, q4.w, q4.z, b.box, b3);
-            cross3(b1, b2, m);
-            cross3(b2, b3, nn);
-            const double lb2 = sqrt(dot3(b2, b2));
-            const double phi = atan2(lb2 * dot3(b1, nn), dot3(m, nn));
-            const double arg = par.y * phi - par.z;
-            const double dE = -par.x * par.y * sin(arg);
-            const double mm = dot3(m, m), n2 = dot3(nn, nn);
-            const double p = dot3(b1, b2) / (lb2 * lb2), q = dot3(b3, b2) / (lb2 * lb2);
-            for (int c = 0; c < 3; ++c) {
-                const double gi = -lb2 * m[c] / mm, gl = lb2 * nn[c] / n2;
-                f[0][c] = -dE * gi;
-                f[3][c] = -dE * gl;
-                f[1][c] = -dE * (-(1.0 + p) * gi + q * gl);
-                f[2][c] = -dE * (p * gi - (1.0 + q) * gl);
-            }
-            if (slot == 0) {
-                acc[2] += par.x * (1.0 + cos(arg));
-                const double li[3] = {-b1[0], -b1[1], -b1[2]};
-                const double ll[3] = {b2[0] + b3[0], b2[1] + b3[1], b2[2] + b3[2]};
-                add_virial(acc + 4, li, f[0]);
-                add_virial(acc + 4, b2, f[2]);
-                add_virial(acc + 4, ll, f[3]);
+                const double v = v0[c] + 0.5 * dt * am * (double)ft[c];
+                m.vel[3 * a + c] = v;
+                ke += ma * v * v;
             }
         }
-        for (int c = 0; c < 3; ++c) b.ent_force[3 * (size_t)e + c] = f[slot][c];
     }
     if (b.partial) {
         const double r = block_sum<10>(acc, red);
         if (threadIdx.x < 10) b.partial[(size_t)blockIdx.x * 10 + threadIdx.x] = r;
-    }
-}
-
-// Per atom: the sum of its term entries (in order) and its scaled 1-4 pairs,
-// added to `forces`; with `partial2` each block writes its 10 sums (energy
-// 3: the 1-4 pairs; virial).  With a dynamics step `m` (kick != 0) the new
-// total force also gives the half kick v += dt/2 F/m and each block writes
-// its kinetic partial sum(m v^2).
-template <typename TF>
-__global__ __launch_bounds__(kMdBlock) void k_bonded_gather(BondedArgs b, MdArgs m, int kick)
-{
-    __shared__ double red[10][kMdBlock];
-    const int a = blockIdx.x * kMdBlock + threadIdx.x;
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double ke = 0.0;
-    if (a < b.n) {
-        double fa[3] = {0.0, 0.0, 0.0};
-        for (int e = b.term_off[a]; e < b.term_off[a + 1]; ++e)
-            for (int c = 0; c < 3; ++c) fa[c] += b.ent_force[3 * (size_t)e + c];
-        // 1-4 pairs through Eq. 20, scaled; each pair is met from both atoms
-        const int ta = b.types[a];
-        for (int e = b.p14_off[a]; e < b.p14_off[a + 1]; ++e) {
-            const int j = b.p14_idx[e];
-            double d[3];
-            mi_diff(b.pos, a, j, b.box, d);            // x_a - x_j
-            const double r2 = dot3(d, d);
-            const int pi = ta * b.ntypes + b.types[j];
-            const Cutoffs<double>& cut = b.pcut64[pi];
-            double fp = 0.0, en = 0.0;
-            if (r2 < cut.rso2) {
-                double f1, e1;
-                fg_term<MathF64<2>>(b.coef64[pi], cut, r2, f1, e1);
-                fp += f1;
-                en += e1;
-            }
-            if (r2 < cut.rco2) {
-                double f2, e2;
-                cg_term<MathF64<2>>(b.coef64[pi], cut, r2, f2, e2);
-                fp += f2;
-                en += e2;
-            }
-            const double s = b.scale14 * fp;           // F_a = s (x_a - x_j)
-            const double f[3] = {s * d[0], s * d[1], s * d[2]};
-            for (int c = 0; c < 3; ++c) fa[c] += f[c];
-            acc[3] += 0.5 * b.scale14 * en;
-            const double hd[3] = {0.5 * d[0], 0.5 * d[1], 0.5 * d[2]};
-            add_virial(acc + 4, hd, f);
-        }
-        TF* F = (TF*)b.forces;
-        for (int c = 0; c < 3; ++c) F[3 * a + c] += (TF)fa[c];
-        if (kick) {
-            const double dt = m.st->dt;
-            const double am = m.ftm2v / m.mass[a];
-            for (int c = 0; c < 3; ++c) {
-                const double v = m.vel[3 * a + c] + 0.5 * dt * am * (double)F[3 * a + c];
-                m.vel[3 * a + c] = v;
-                ke += m.mass[a] * v * v;
-            }
-        }
-    }
-    if (b.partial2) {
-        const double r = block_sum<10>(acc, red);
-        if (threadIdx.x < 10) b.partial2[(size_t)blockIdx.x * 10 + threadIdx.x] = r;
     }
     if (kick) {
         const double r = block_sum<1>(&ke, red);
@@ -238,18 +276,27 @@ __global__ __launch_bounds__(kMdBlock) void k_bonded_gather(BondedArgs b, MdArgs
     }
 }
 
-// out[k] = the sums over blocks of p1[blk * K + k] and then of p2 (blocks
-// in order; one thread per component).
+// Sum over the blocks' partials in a fixed order: lane l of a wave adds
+// blocks l, l + 64, ... of p1 and then of p2, and the wave adds its lanes.
+__device__ __forceinline__ double sum_blocks(const double* __restrict__ p1, int n1,
+                                             const double* __restrict__ p2, int n2, int K, int k)
+{
+    const int lane = (int)threadIdx.x & 63;
+    double s = 0.0;
+    for (int blk = lane; blk < n1; blk += 64) s += p1[(size_t)blk * K + k];
+    for (int blk = lane; blk < n2; blk += 64) s += p2[(size_t)blk * K + k];
+    return wave_sum(s);                // complete in lane 63
+}
+
+// out[k] = the sums over blocks of p1[blk * K + k] and of p2 (one wave per
+// component k).
 __global__ void k_sum_partials(const double* __restrict__ p1, int n1,
                                const double* __restrict__ p2, int n2, int K,
                                double* __restrict__ out)
 {
-    const int k = threadIdx.x;
-    if (k >= K) return;
-    double s = 0.0;
-    for (int blk = 0; blk < n1; ++blk) s += p1[(size_t)blk * K + k];
-    for (int blk = 0; blk < n2; ++blk) s += p2[(size_t)blk * K + k];
-    out[k] = s;
+    const int k = (int)threadIdx.x >> 6;
+    const double s = sum_blocks(p1, n1, p2, n2, K, k);
+    if (((int)threadIdx.x & 63) == 63) out[k] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -318,9 +365,9 @@ __global__ void k_md_scalar(MdState* st, const double* __restrict__ partial, int
                             const double* __restrict__ w_nb, const double* __restrict__ eb,
                             double* __restrict__ row)
 {
-    if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int blk = 0; blk < nblocks; ++blk) s += partial[blk];
+    // one wave: the block partials in a fixed order, then lane 63 alone
+    const double s = sum_blocks(partial, nblocks, nullptr, 0, 1, 0);
+    if (threadIdx.x != 63) return;
     st->K = 0.5 * s / ftm2v;
     if (second) {
         thermostat_half(st);
@@ -360,25 +407,27 @@ __global__ void k_md_unit_scale(MdState* st) { st->s2 = 1.0; }
 hipError_t launch_bonded(const BondedArgs& b, const MdArgs* m, int force_prec, hipStream_t s)
 {
     if (b.n == 0) return hipSuccess;
-    if (b.n_ent > 0)
-        hipLaunchKernelGGL(k_bonded_terms, dim3((b.n_ent + kMdBlock - 1) / kMdBlock), dim3(kMdBlock),
-                           0, s, b);
-    const dim3 grid((b.n + kMdBlock - 1) / kMdBlock);
+    const dim3 grid(bonded_blocks(b.n, b.log_lanes));
     const MdArgs none{};
     const int kick = m ? 1 : 0;
     if (force_prec == 64)
-        hipLaunchKernelGGL(k_bonded_gather<double>, grid, dim3(kMdBlock), 0, s, b, m ? *m : none, kick);
+        hipLaunchKernelGGL(k_bonded<double>, grid, dim3(kMdBlock), 0, s, b, m ? *m : none, kick);
     else
-        hipLaunchKernelGGL(k_bonded_gather<float>, grid, dim3(kMdBlock), 0, s, b, m ? *m : none, kick);
+        hipLaunchKernelGGL(k_bonded<float>, grid, dim3(kMdBlock), 0, s, b, m ? *m : none, kick);
     return hipGetLastError();
 }
 
 int md_blocks(int n) { return (n + kMdBlock - 1) / kMdBlock; }
 
+int bonded_blocks(int n, int log_lanes)
+{
+    return (int)(((long long)n << log_lanes) + kMdBlock - 1) / kMdBlock;
+}
+
 hipError_t launch_sum_partials(const double* p1, int n1, const double* p2, int n2, int K,
                                double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, p1, n1, p2, n2, K, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64 * K), 0, s, p1, n1, p2, n2, K, out);
     return hipGetLastError();
 }
 
