@@ -57,7 +57,7 @@ def recorded_traffic(workload):
     if not (m_t and m_h):
         return None
     h = hashlib.sha256()
-    for f in ("relres_kernels.hip", "relres_internal.h", "relres_pair.h"):
+    for f in ("relres_kernels.hip", "relres_internal.h", "relres_pair.h", "relres_lanes.h"):
         with open(os.path.join(ROOT, "paper_2104_10231_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return int(m_t.group(1)) if h.hexdigest() == m_h.group(1) else None
