@@ -374,10 +374,12 @@ def batch_bench(args):
     its own box.  Batched: one context for all replicas; every cycle (a list
     rebuild and `rebuild_every` force calls with energy and virial per
     replica) is one HIP graph replay.  Sequential: one context per replica,
-    the same cycle launched replica after replica."""
+    the same cycle launched replica after replica.  Skins per replica: 2.0 A
+    where the box allows it, 1.5 A in boxes below 2 (14 + 2.0) A."""
+    import numpy as np
     import torch
     import workloads as w
-    b = w.replica_batch(args.seed)
+    b = w.replica_batch(args.seed, skin_max=2.0)
     n = b.whole.n
     steps, every = args.steps, args.rebuild_every
     cycles = max(1, steps // every)
@@ -386,6 +388,7 @@ def batch_bench(args):
 
     rr = make(b.whole, 32, args.pair_math)
     rr.set_systems(b.offsets)
+    rr.set_skins(b.skins)
     rr.build_lists(pos, b.boxes)
     F = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     E = torch.empty((b.nsys, 3), dtype=torch.float64, device="cuda")
@@ -456,7 +459,9 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": "replica_batch: 256 mixed propane/neopentane liquids, "
                                "300-18000 atoms, 0.0080-0.0100 atoms/A^3", "atoms": n,
-                   "replicas": b.nsys, "skin_A": b.whole.skin, "rebuild_every": every,
+                   "replicas": b.nsys,
+                   "skin_A": {f"{v:g}": int((b.skins == v).sum()) for v in np.unique(b.skins)},
+                   "rebuild_every": every,
                    "forces": "fp32", "energy_virial": "fp64 per replica",
                    "parallelism": "single GPU",
                    "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)"},

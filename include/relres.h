@@ -191,6 +191,16 @@ int relres_set_topology(relres_ctx *ctx, int n_atoms, const int *types, const in
  * again afterwards.                                                         */
 int relres_set_systems(relres_ctx *ctx, int nsys, const int *atom_offsets);
 
+/* Skin of every system (host array of nsys values >= 0, Angstrom), in place
+ * of relres_params.skin, from the next build on: each system's lists use
+ * r_s+ + skin and r_c+ + skin, its box must exceed twice the larger, and its
+ * displacement checks use half its skin.  Lets a batch keep the usual skin
+ * where the boxes allow it and a smaller one in small boxes (a box edge must
+ * exceed 2 (r_c+ + skin) for the minimum image to hold).  relres_set_topology
+ * and relres_set_systems restore the default.  The lists must be built again
+ * before relres_forces.                                                    */
+int relres_set_skins(relres_ctx *ctx, const double *skins);
+
 /* Build both neighbour lists for the FP64 device positions pos (N x 3, any
  * periodic image) in the box {Lx, Ly, Lz} (host array; nsys x 3 with
  * several systems).  Every L_k must exceed twice the largest list radius in

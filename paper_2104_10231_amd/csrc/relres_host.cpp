@@ -253,7 +253,9 @@ uint32_t spread3(uint32_t v)
 
 struct relres_ctx {
     int device = 0;
-    double skin = 0;
+    double skin = 0;                  // default skin of every system
+    std::vector<double> skins;        // per system (relres_set_skins); empty: `skin`
+    std::vector<double> ref_skins;    // skins of the build whose positions wpos holds
     std::vector<double> dist;         // [pair][4]: r_s-, r_s+, r_c-, r_c+ of each type pair
     bool per_pair = false;            // distances differ between type pairs
     double list_rso = 0, list_rco = 0;   // largest r_s+; largest hybrid-pair r_c+
@@ -413,6 +415,26 @@ int log2i(int v)
     return l;
 }
 
+double skin_of(const relres_ctx* c, int sy)
+{
+    return c->skins.empty() ? c->skin : c->skins[sy];
+}
+
+// Skin and list radii (atom list: r_s+ + skin, site list: r_c+ + skin) of
+// every system.
+void list_radii(const relres_ctx* c, std::vector<double>& skin, std::vector<double>& rla,
+                std::vector<double>& rls)
+{
+    skin.resize(c->nsys);
+    rla.resize(c->nsys);
+    rls.resize(c->nsys);
+    for (int sy = 0; sy < c->nsys; ++sy) {
+        skin[sy] = skin_of(c, sy);
+        rla[sy] = c->list_rso + skin[sy];
+        rls[sy] = c->list_rco + skin[sy];
+    }
+}
+
 // Home rows per wave of the list kernel (1 .. kRowsPerWave): the largest
 // power of two that still gives about 2000 waves, so small systems spread
 // their candidate tests over more waves (a wave tests its rows one after
@@ -435,8 +457,8 @@ int list_rows_per_wave(bool site, long long members)
     return r;
 }
 
-int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int* members_sys,
-               long long* gen)
+int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector<double>& skin_sys,
+               int nsys, const double* boxes, const int* members_sys, long long* gen)
 {
     // cells per axis of every system: a cell edge is at least the list radius
     // (with a margin far above rounding), so every pair within rl lies in
@@ -446,7 +468,7 @@ int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int*
         int* n = &nn[(size_t)sy * 3];
         long long total = 1;
         for (int k = 0; k < 3; ++k) {
-            n[k] = (int)std::floor(boxes[3 * sy + k] / (rl * (1.0 + 1e-10)));
+            n[k] = (int)std::floor(boxes[3 * sy + k] / (rl_sys[sy] * (1.0 + 1e-10)));
             n[k] = std::max(1, std::min(n[k], 1023));
             total *= n[k];
         }
@@ -465,6 +487,8 @@ int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int*
         cell_base[sy + 1] = cell_base[sy] + (int)cells;
     }
     const bool same = g.nsys == nsys && g.sys_n == nn && g.rank_of_lin.p;
+    double rl = 0.0;
+    for (int sy = 0; sy < nsys; ++sy) rl = std::max(rl, rl_sys[sy]);
     g.rl = rl;
     if (!same) {
         // tables may be read by work still queued on any stream
@@ -547,9 +571,12 @@ int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int*
         d.row_base = rows;
         d.members = members_sys[sy];
         d.wave_base = waves;
+        d.rl2 = rl_sys[sy] * rl_sys[sy];
+        d.half_skin2 = 0.25 * skin_sys[sy] * skin_sys[sy];
         rows += members_sys[sy];
         waves += (members_sys[sy] + g.rpw - 1) / g.rpw;
-        densest = std::max(densest, members_sys[sy] / (box[0] * box[1] * box[2]));
+        // expected neighbours within the system's list radius
+        densest = std::max(densest, members_sys[sy] / (box[0] * box[1] * box[2]) * d.rl2 * rl_sys[sy]);
     }
     g.members = rows;
     g.waves = waves;
@@ -568,7 +595,7 @@ int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int*
     TRY(ensure(g.row_cell, sizeof(int) * rows, gen));
     TRY(ensure(g.nrow, sizeof(int) * rows, gen));
     if (g.cap == 0) {
-        const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * densest;
+        const double expect = 4.0 / 3.0 * M_PI * densest;
         g.cap = std::max(16, (int)std::ceil(expect * 1.5 + 16.0));
         g.cap = (g.cap + 7) & ~7;
     }
@@ -581,7 +608,6 @@ int setup_grid(GridHost& g, double rl, int nsys, const double* boxes, const int*
     d.cap = g.cap;
     d.waves = waves;
     d.rows_per_wave = g.rpw;
-    d.rl2 = rl * rl;
     d.geom = g.geom_dev.as<GeomDev>();
     d.cell_sys = g.cell_sys.as<int>();
     d.rank_of_lin = g.rank_of_lin.as<int>();
@@ -681,19 +707,21 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     for (int k = 0; k < 3 * ns; ++k)
         if (!(std::isfinite(box[k]) && box[k] > 0.0))
             return fail(RELRES_ERR_ARG, "bad box edge %g (system %d)", box[k], k / 3);
-    const double rla = c->list_rso + c->skin, rls = c->list_rco + c->skin;
+    std::vector<double> skin_sys, rla, rls;
+    list_radii(c, skin_sys, rla, rls);
     const bool sites = c->n_sites > 0;
     for (int sy = 0; sy < ns; ++sy) {
         // a system without hybrid atoms only needs the atom-list radius
-        const double rmax = c->sites_sys[sy] > 0 ? rls : rla;
+        const double rmax = c->sites_sys[sy] > 0 ? rls[sy] : rla[sy];
         for (int k = 0; k < 3; ++k)
             if (!(box[3 * sy + k] > 2.0 * rmax))
                 return fail(RELRES_ERR_BOX_TOO_SMALL, "box edge %g of system %d must exceed 2 x %g",
                             box[3 * sy + k], sy, rmax);
     }
     c->built = false;
-    // positions of the previous build are comparable when the boxes are the same
-    const bool same_boxes = c->boxes.size() == (size_t)3 * ns && std::equal(box, box + 3 * ns, c->boxes.begin());
+    // positions of the previous build are comparable when the boxes and skins are the same
+    const bool same_boxes = c->boxes.size() == (size_t)3 * ns &&
+                            std::equal(box, box + 3 * ns, c->boxes.begin()) && c->ref_skins == skin_sys;
     std::copy(box, box + 3, c->box);
     c->boxes.assign(box, box + 3 * ns);
     {
@@ -711,8 +739,8 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         }
     }
     const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
-    TRY(setup_grid(c->ga, rla, ns, box, c->atoms_sys.data(), &c->alloc_generation));
-    if (sites) TRY(setup_grid(c->gs, rls, ns, box, c->sites_sys.data(), &c->alloc_generation));
+    TRY(setup_grid(c->ga, rla, skin_sys, ns, box, c->atoms_sys.data(), &c->alloc_generation));
+    if (sites) TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
     const void* wpos_before = c->d_wpos.p;
     TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
@@ -736,10 +764,10 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         TRY(upload_grids(c, s));
         const TopoDev topo = topo_of(c);
         GridDev* gd = c->d_grids.as<GridDev>();
-        const double half_skin2 = check_moved ? 0.25 * c->skin * c->skin : -1.0;
         HIP_TRY(launch_bin(c->n, pos, topo, gd, c->d_wpos.as<double4>(), c->d_key_a.as<int2>(),
-                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), half_skin2, s));
+                           c->d_key_s.as<int2>(), c->d_status.as<Status>(), check_moved, s));
         c->ref_valid = true;
+        c->ref_skins = skin_sys;
         HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
@@ -807,12 +835,16 @@ int examine_status(relres_ctx* c)
     if (!ov_a && !ov_s) return RELRES_OK;
     if (ov_a) {
         c->ga.cap = ((int)(mr_a * 1.25) + 8 + 7) & ~7;
-        TRY(setup_grid(c->ga, c->list_rso + c->skin, c->nsys, c->boxes.data(), c->atoms_sys.data(),
+        std::vector<double> skin_sys, rla, rls;
+        list_radii(c, skin_sys, rla, rls);
+        TRY(setup_grid(c->ga, rla, skin_sys, c->nsys, c->boxes.data(), c->atoms_sys.data(),
                        &c->alloc_generation));
     }
     if (ov_s) {
         c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
-        TRY(setup_grid(c->gs, c->list_rco + c->skin, c->nsys, c->boxes.data(), c->sites_sys.data(),
+        std::vector<double> skin_sys, rla, rls;
+        list_radii(c, skin_sys, rla, rls);
+        TRY(setup_grid(c->gs, rls, skin_sys, c->nsys, c->boxes.data(), c->sites_sys.data(),
                        &c->alloc_generation));
     }
     c->stats.regrows++;
@@ -1133,6 +1165,7 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
     c->n_sites = sites;
     c->h_types = t;
     c->nsys = 1;                      // one system until relres_set_systems says otherwise
+    c->skins.clear();
     c->sys_off = {0, n};
     c->atoms_sys = {n};
     c->sites_sys = {sites};
@@ -1190,6 +1223,7 @@ int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
         HIP_TRY(hipMemcpy(c->d_sys.p, sys.data(), sizeof(int) * c->n, hipMemcpyHostToDevice));
     }
     c->nsys = nsys;
+    c->skins.clear();                 // every system at the default skin
     c->sys_off = off;
     c->atoms_sys = atoms;
     c->sites_sys = sites;
@@ -1200,6 +1234,18 @@ int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
         c->has_bonded = false;
         c->md_ready = false;
     }
+    return RELRES_OK;
+}
+
+int relres_set_skins(relres_ctx* c, const double* skins)
+{
+    if (!c || !skins) return fail(RELRES_ERR_ARG, "NULL argument");
+    if (!c->topo_set) return fail(RELRES_ERR_STATE, "relres_set_topology has not been called");
+    for (int sy = 0; sy < c->nsys; ++sy)
+        if (!(std::isfinite(skins[sy]) && skins[sy] >= 0.0))
+            return fail(RELRES_ERR_CUTOFF_ORDER, "bad skin %g of system %d", skins[sy], sy);
+    c->skins.assign(skins, skins + c->nsys);
+    c->built = false;                 // the lists of the old skins are not kept
     return RELRES_OK;
 }
 
@@ -1242,7 +1288,7 @@ int relres_moved_atoms(relres_ctx* c, const double* pos, void* stream, int* coun
     static_assert(offsetof(Status, moved_query) % 8 == 0, "moved_query starts a 64-bit word");
     HIP_TRY(launch_clear_words((unsigned long long*)(st + offsetof(Status, moved_query)), 1, s));
     HIP_TRY(launch_moved(c->n, pos, topo_of(c), c->d_grids.as<GridDev>(), c->d_wpos.as<double4>(),
-                         0.25 * c->skin * c->skin, c->d_status.as<Status>(), s));
+                         c->d_status.as<Status>(), s));
     HIP_TRY(hipMemcpyAsync(&c->h_query->moved_query, st + offsetof(Status, moved_query),
                            sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1711,7 +1757,7 @@ int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int therm
     m.forces = F;
     m.mass = c->d_mass.as<double>();
     m.xref = c->d_md_xref.as<double>();
-    m.half_skin2 = 0.25 * c->skin * c->skin;
+    m.half_skin2 = 0.25 * skin_of(c, 0) * skin_of(c, 0);
     m.stale = (unsigned*)c->d_md_stale.p;
     m.partial = c->d_md_part.as<double>();
     m.st = c->d_md_state.as<MdState>();

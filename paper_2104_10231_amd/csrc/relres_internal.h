@@ -58,6 +58,8 @@ struct GeomDev {
     int members;
     int wave_base;            // first wave of this grid in the list kernel
     int pad;
+    double rl2;               // list radius squared (r_+ + the system's skin)^2
+    double half_skin2;        // (the system's skin / 2)^2
 };
 
 // All grids of one kind, one per system, concatenated: cells are numbered
@@ -70,7 +72,6 @@ struct GridDev {
     int cap;                  // row capacity of the padded list
     int waves;                // waves of the list kernel for this kind
     int rows_per_wave;        // consecutive home rows per wave (<= kRowsPerWave)
-    double rl2;               // list radius squared (membership test)
     const GeomDev* geom;      // [nsys]
     const int* cell_sys;      // [ncell] system of each cell
     const int* rank_of_lin;   // [cell_base + local linear index] -> global cell rank
@@ -149,14 +150,14 @@ struct ForceArgs {
 };
 
 // Launchers (relres_kernels.hip).  All return hipError_t of the launch.
-// half_skin2 >= 0: before overwriting wpos, count in st->moved the atoms whose
-// position is more than sqrt(half_skin2) (minimum image) from the wpos of the
-// previous build; < 0: no check (no comparable previous build)
+// check_moved: before overwriting wpos, count in st->moved the atoms whose
+// position is more than half their system's skin (minimum image) from the
+// wpos of the previous build (a comparable previous build exists)
 hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev, double4* wpos,
-                      int2* key_a, int2* key_s, Status* st, double half_skin2, hipStream_t s);
-// st->moved_query += atoms of pos more than sqrt(half_skin2) from wpos
+                      int2* key_a, int2* key_s, Status* st, bool check_moved, hipStream_t s);
+// st->moved_query += atoms of pos more than half their system's skin from wpos
 hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* grids_dev,
-                        const double4* wpos, double half_skin2, Status* st, hipStream_t s);
+                        const double4* wpos, Status* st, hipStream_t s);
 hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);

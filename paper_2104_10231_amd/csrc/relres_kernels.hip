@@ -116,7 +116,7 @@ __device__ __forceinline__ void count_wave(bool flag, unsigned* count)
 __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
                       const GridDev* __restrict__ grids, double4* __restrict__ wpos,
                       int2* __restrict__ key_a, int2* __restrict__ key_s, Status* __restrict__ st,
-                      double half_skin2)
+                      int check_moved)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -128,8 +128,8 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
     }
     const GridDev& ga = grids[0];
     const GeomDev& G = ga.geom[sy];
-    if (half_skin2 >= 0.0)   // displacement since the previous build (same boxes)
-        count_wave(image_dist2(x, y, z, wpos[i], G.box) > half_skin2, &st->moved);
+    if (check_moved)   // displacement since the previous build (same boxes and skins)
+        count_wave(image_dist2(x, y, z, wpos[i], G.box) > G.half_skin2, &st->moved);
     const double wx = wrap_coord(x, G.box[0]), wy = wrap_coord(y, G.box[1]),
                  wz = wrap_coord(z, G.box[2]);
     wpos[i] = make_double4(wx, wy, wz, 0.0);
@@ -156,7 +156,7 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
 // Atoms now more than half the skin from their position at the last build.
 __global__ void k_moved(int n, const double* __restrict__ pos, TopoDev topo,
                         const GridDev* __restrict__ grids, const double4* __restrict__ wpos,
-                        double half_skin2, Status* __restrict__ st)
+                        Status* __restrict__ st)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -164,7 +164,7 @@ __global__ void k_moved(int n, const double* __restrict__ pos, TopoDev topo,
     const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
     const GeomDev& G = grids[0].geom[sy];
     // a non-finite position counts as moved (the comparison is false for NaN)
-    count_wave(!(image_dist2(x, y, z, wpos[i], G.box) <= half_skin2), &st->moved_query);
+    count_wave(!(image_dist2(x, y, z, wpos[i], G.box) <= G.half_skin2), &st->moved_query);
 }
 
 // One block per grid: exclusive scan of the per-cell counts into `start`,
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     const int r0 = G.row_base + (lw - G.wave_base) * R;
     const int r1 = min(G.row_base + G.members, r0 + R);
     const double hx = G.half[0], hy = G.half[1], hz = G.half[2];
-    const double rl2 = g.rl2;
+    const double rl2 = G.rl2;
     const int cap = g.cap;
     const int* __restrict__ excl_off = topo.excl_off;
     const int* __restrict__ excl_idx = topo.excl_idx;
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
     const GeomDev& G = g.geom[g.cell_sys[c]];
     const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
     const double hx = G.half[0], hy = G.half[1], hz = G.half[2];
-    const double rl2 = g.rl2;
+    const double rl2 = G.rl2;
     const int cap = g.cap;
 
     for (int hg = hb; hg < he; hg += kHomeMax) {
@@ -1299,20 +1299,20 @@ Cutoffs<S> cut_as(const double* c64)
 // ---------------------------------------------------------------------------
 
 hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev, double4* wpos,
-                      int2* key_a, int2* key_s, Status* st, double half_skin2, hipStream_t s)
+                      int2* key_a, int2* key_s, Status* st, bool check_moved, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bin, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, topo, grids_dev,
-                       wpos, key_a, key_s, st, half_skin2);
+                       wpos, key_a, key_s, st, check_moved ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* grids_dev,
-                        const double4* wpos, double half_skin2, Status* st, hipStream_t s)
+                        const double4* wpos, Status* st, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_moved, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, topo, grids_dev,
-                       wpos, half_skin2, st);
+                       wpos, st);
     return hipGetLastError();
 }
 

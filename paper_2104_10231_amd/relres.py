@@ -80,6 +80,7 @@ SIGNATURES = {
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "relres_set_systems": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "relres_set_skins": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
     "relres_set_pair_params": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p,
                                               _c_double_p, _c_double_p]),
     "relres_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -253,6 +254,15 @@ class RelRes:
         _check(self._lib.relres_set_systems(self._ctx, int(off.shape[0] - 1), _ptr(off)),
                "relres_set_systems")
         self.nsys = int(off.shape[0] - 1)
+
+    def set_skins(self, skins):
+        """Skin of every system (nsys values), in place of the context's skin;
+        build the lists again afterwards."""
+        sk = _f64(skins).reshape(-1)
+        if sk.shape[0] != self.nsys:
+            raise ValueError(f"need {self.nsys} skins, got {sk.shape[0]}")
+        _check(self._lib.relres_set_skins(self._ctx, sk.ctypes.data_as(_c_double_p)),
+               "relres_set_skins")
 
     # -- hot path ------------------------------------------------------------
     def _pos(self, pos: torch.Tensor) -> torch.Tensor:

@@ -117,6 +117,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.relres_md_setup(None, None, 1.0, 1.0, 1.0, 1.0, 1) == -1
     assert lib.relres_md_run(None, None, None, 1, 0, None, None) == -1
     assert lib.relres_moved_atoms(None, None, None, None) == -1
+    assert lib.relres_set_skins(None, None) == -1
     assert lib.relres_check_lists(None) == -1
     lib.relres_destroy(None)
 

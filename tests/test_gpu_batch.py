@@ -125,3 +125,55 @@ def test_batched_graph_replay_of_build_and_forces():
         assert rr.check_lists()
         assert torch.equal(F, F0) and torch.equal(E, E0)
     rr.close()
+
+
+def test_per_system_skins():
+    """relres_set_skins: every replica lists its pairs out to r_+ + its own
+    skin (2.0 A where the box allows it, 1.5 A in the smallest boxes): pair
+    sets equal the oracle's at each replica's skin, forces, energies and
+    virials meet the bars, each replica equals a context of its own, and the
+    displacement count uses each replica's half skin.  A skin too large for a
+    box is refused at the build."""
+    import torch
+    from paper_2104_10231_amd.relres import RelResError
+    b = w.replica_batch(10, n_systems=6, min_atoms=300, max_atoms=700, total_atoms=2400,
+                        skin_max=2.0)
+    assert len(set(b.skins.tolist())) == 2
+    print(f"[batch] per-system skins {b.skins.tolist()}", flush=True)
+    rr = make_relres(b.whole, 32)
+    rr.set_systems(b.offsets)
+    rr.set_skins(b.skins)
+    rr.set_launch(4, 16)
+    p = torch.from_numpy(b.whole.pos).cuda()
+    rr.build_lists(p, b.boxes)
+    F, E, W = [t.double().cpu().numpy() for t in rr.forces(p)]
+    ftol, etol = TOL[32]
+    want = {0: set(), 1: set()}
+    for k, s in enumerate(b.systems):
+        o0, o1 = int(b.offsets[k]), int(b.offsets[k + 1])
+        Fr, Er, Wr = oracle.compute(s)
+        assert rel_rms(F[o0:o1], Fr) <= ftol, k
+        assert abs(E[k, 0] - Er[0]) <= etol * abs(Er[0]), k
+        assert np.abs(W[k] - Wr).max() <= etol * np.abs(Wr).max(), k
+        for which in (0, 1):
+            want[which] |= {(i + o0, j + o0) for i, j in pair_set(oracle.pairs(s, which))}
+        r1 = make_relres(s, 32)
+        r1.set_launch(4, 16)
+        p1 = torch.from_numpy(s.pos).cuda()
+        r1.build_lists(p1, s.box)
+        F1 = r1.forces(p1)[0].double().cpu().numpy()
+        assert np.array_equal(F[o0:o1], F1), k
+        r1.close()
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == want[which]
+    # displacements: 0.9 A moves are past half of a 1.5 A skin, not of 2.0 A
+    rng = np.random.default_rng(0)
+    u = rng.normal(size=(b.whole.n, 3))
+    u *= 0.9 / np.linalg.norm(u, axis=1, keepdims=True)
+    small = int(sum(b.offsets[k + 1] - b.offsets[k] for k in range(b.nsys) if b.skins[k] < 2.0))
+    assert rr.moved_atoms(torch.from_numpy(b.whole.pos + u).cuda()) == small
+    # a 2.0 A skin does not fit the smallest box
+    rr.set_skins(np.full(b.nsys, 2.0))
+    with pytest.raises(RelResError):
+        rr.build_lists(p, b.boxes)
+    rr.close()

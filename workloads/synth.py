@@ -550,11 +550,12 @@ class Batch:
     ``systems[s]`` is replica s alone; ``whole`` holds the concatenated atoms
     (molecule ids made unique across replicas, box of replica 0) for the
     topology call; ``offsets`` (nsys + 1) and ``boxes`` (nsys, 3) describe
-    the replicas."""
+    the replicas; ``skins`` (nsys) is each replica's own skin."""
     systems: list
     offsets: np.ndarray
     boxes: np.ndarray
     whole: System
+    skins: np.ndarray = None
 
     @property
     def nsys(self) -> int:
@@ -575,18 +576,21 @@ def batch_of(systems: list) -> Batch:
         mol=np.concatenate([s.mol + mol_base[k] for k, s in enumerate(systems)]).astype(np.int32),
         excl_offsets=eo, excl_idx=ei, meta=dict(nsys=len(systems)))
     return Batch(systems=systems, offsets=offsets,
-                 boxes=np.stack([s.box for s in systems]), whole=whole)
+                 boxes=np.stack([s.box for s in systems]), whole=whole,
+                 skins=np.array([s.skin for s in systems], dtype=np.float64))
 
 
 def replica_batch(seed: int = 0, n_systems: int = 256, min_atoms: int = 300,
                   max_atoms: int = 30000, total_atoms: int = 1_200_000,
                   dmin: float = 0.0080, dmax: float = 0.0100, skin: float = 1.5,
-                  precision: int = 32) -> Batch:
+                  precision: int = 32, skin_max: float = None) -> Batch:
     """Replicas of uneven size: sizes log-uniform in [min_atoms, max_atoms]
     rescaled (and clipped) towards total_atoms, densities uniform in
     [dmin, dmax], each a mixed propane/neopentane liquid with its own
     neopentane fraction.  The 1.5 A skin keeps the smallest box (300 atoms at
-    0.0100 / A^3, L = 31.07 A) above twice the site-list radius."""
+    0.0100 / A^3, L = 31.07 A) above twice the site-list radius.  With
+    skin_max, a replica whose box allows it (every edge above
+    2 (r_c+ + skin_max)) gets skin_max instead: per-replica skins."""
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(np.log(min_atoms), np.log(max_atoms), n_systems))
     for _ in range(20):
@@ -597,6 +601,10 @@ def replica_batch(seed: int = 0, n_systems: int = 256, min_atoms: int = 300,
     systems = [mixed_liquid(int(seeds[k]), int(sizes[k]), float(dens[k]), float(pneo[k]),
                             skin=skin, precision=precision, name=f"replica{k}")
                for k in range(n_systems)]
+    if skin_max is not None:
+        systems = [s.replace(skin=skin_max)
+                   if float(np.min(s.box)) > 2.0 * (s.rc_out + skin_max) * (1.0 + 1e-9) else s
+                   for s in systems]
     return batch_of(systems)
 
 
