@@ -319,6 +319,7 @@ struct relres_ctx {
     bool md_ready = false;
     double md_ftm2v = 0.0;
     int md_rebuild = 10;
+    int md_cur = 0;                   // which of the two state buffers is current
     DBuf d_mass, d_md_state, d_md_xref, d_md_F, d_md_E, d_md_W, d_md_part, d_md_stale;
     unsigned int* h_stale = nullptr;
 
@@ -435,15 +436,17 @@ void list_radii(const relres_ctx* c, std::vector<double>& skin, std::vector<doub
     }
 }
 
-// Home rows per wave of the list kernel (1 .. kRowsPerWave): the largest
-// power of two that still gives about 2000 waves, so small systems spread
-// their candidate tests over more waves (a wave tests its rows one after
-// another) while large ones load each stencil for as many rows as possible.
-// Measured on MI355X: the 20480-atom liquid runs as fast at 8 (atoms) / 2
-// (sites) as at 8 / 8 and slower with fewer atom rows per wave; 6000-atom
-// hexane dynamics takes 5 % less time per step at 2 / 1 than at 8 / 8.  The environment
-// variable RELRES_LIST_ROWS="atom,site" overrides it (for tuning runs).
-int list_rows_per_wave(bool site, long long members)
+// Home rows per wave of the list kernel (1 .. kRowsPerWave).  A wave tests
+// its rows one after another, so a launch with few waves spreads its tests
+// over more of them: when both lists together give fewer than 2048 waves at
+// kRowsPerWave rows, each grid takes the largest power of two that still
+// gives it 2000 waves.  Large launches keep kRowsPerWave and load each
+// stencil for as many rows as possible.  Measured on MI355X: the 20480-atom
+// liquid (3072 waves) builds slower with fewer rows per wave; 6000-atom
+// hexane dynamics (1000 waves) takes 5 % less time per step at 2 / 1 rows
+// than at 8 / 8.  The environment variable RELRES_LIST_ROWS="atom,site"
+// overrides the choice (for tuning runs).
+int list_rows_per_wave(bool site, long long members, long long launch_rows)
 {
     if (const char* e = std::getenv("RELRES_LIST_ROWS")) {
         int a = 0, b = 0;
@@ -453,12 +456,15 @@ int list_rows_per_wave(bool site, long long members)
         }
     }
     int r = kRowsPerWave;
+    if (launch_rows >= 2048LL * kRowsPerWave) return r;
     while (r > 1 && members < 2000LL * r) r >>= 1;
     return r;
 }
 
+// launch_rows: rows of both grids (they share the list-kernel launch)
 int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector<double>& skin_sys,
-               int nsys, const double* boxes, const int* members_sys, long long* gen)
+               int nsys, const double* boxes, const int* members_sys, long long launch_rows,
+               long long* gen)
 {
     // cells per axis of every system: a cell edge is at least the list radius
     // (with a margin far above rounding), so every pair within rl lies in
@@ -553,7 +559,7 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
     // rows and list-kernel waves of every grid
     long long all_members = 0;
     for (int sy = 0; sy < nsys; ++sy) all_members += members_sys[sy];
-    g.rpw = list_rows_per_wave(g.site, all_members);
+    g.rpw = list_rows_per_wave(g.site, all_members, launch_rows);
     std::vector<GeomDev> geom(nsys);
     int rows = 0, waves = 0;
     double densest = 0.0;
@@ -739,8 +745,12 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         }
     }
     const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
-    TRY(setup_grid(c->ga, rla, skin_sys, ns, box, c->atoms_sys.data(), &c->alloc_generation));
-    if (sites) TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), &c->alloc_generation));
+    const long long launch_rows = (long long)c->n + c->n_sites;
+    TRY(setup_grid(c->ga, rla, skin_sys, ns, box, c->atoms_sys.data(), launch_rows,
+                   &c->alloc_generation));
+    if (sites)
+        TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), launch_rows,
+                       &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
     const void* wpos_before = c->d_wpos.p;
     TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
@@ -838,14 +848,14 @@ int examine_status(relres_ctx* c)
         std::vector<double> skin_sys, rla, rls;
         list_radii(c, skin_sys, rla, rls);
         TRY(setup_grid(c->ga, rla, skin_sys, c->nsys, c->boxes.data(), c->atoms_sys.data(),
-                       &c->alloc_generation));
+                       (long long)c->n + c->n_sites, &c->alloc_generation));
     }
     if (ov_s) {
         c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
         std::vector<double> skin_sys, rla, rls;
         list_radii(c, skin_sys, rla, rls);
         TRY(setup_grid(c->gs, rls, skin_sys, c->nsys, c->boxes.data(), c->sites_sys.data(),
-                       &c->alloc_generation));
+                       (long long)c->n + c->n_sites, &c->alloc_generation));
     }
     c->stats.regrows++;
     c->lanes_stale = true;
@@ -1664,7 +1674,7 @@ int relres_md_setup(relres_ctx* c, const double* masses, double dt, double kT, d
     long long* gen = &c->alloc_generation;
     TRY(ensure(c->d_mass, sizeof(double) * n, gen));
     HIP_TRY(hipMemcpy(c->d_mass.p, masses, sizeof(double) * n, hipMemcpyHostToDevice));
-    TRY(ensure(c->d_md_state, sizeof(MdState), gen));
+    TRY(ensure(c->d_md_state, 2 * sizeof(MdState), gen));   // current and next
     TRY(ensure(c->d_md_xref, sizeof(double) * 3 * n, gen));
     TRY(ensure(c->d_md_F, (c->precision == 64 ? 8 : 4) * 3 * (size_t)n, gen));
     TRY(ensure(c->d_md_E, sizeof(double) * 3, gen));
@@ -1685,6 +1695,7 @@ int relres_md_setup(relres_ctx* c, const double* masses, double dt, double kT, d
     st.g = 3.0 * n - 3.0;
     st.Q = st.g * kT * tau * tau;
     HIP_TRY(hipMemcpy(c->d_md_state.p, &st, sizeof(MdState), hipMemcpyHostToDevice));
+    c->md_cur = 0;
     c->md_ftm2v = ftm2v;
     c->md_rebuild = rebuild_every;
     // the per-atom bonded kernel also gives the half kick: without bonded
@@ -1702,12 +1713,13 @@ int relres_md_state(relres_ctx* c, double* xi, double* eta, int set)
     if (!c->md_ready) return fail(RELRES_ERR_STATE, "relres_md_setup has not been called");
     HIP_TRY(hipDeviceSynchronize());
     MdState st{};
-    HIP_TRY(hipMemcpy(&st, c->d_md_state.p, sizeof(MdState), hipMemcpyDeviceToHost));
+    MdState* cur = c->d_md_state.as<MdState>() + c->md_cur;
+    HIP_TRY(hipMemcpy(&st, cur, sizeof(MdState), hipMemcpyDeviceToHost));
     if (set) {
         if (!(std::isfinite(*xi) && std::isfinite(*eta))) return fail(RELRES_ERR_ARG, "non-finite state");
         st.xi = *xi;
         st.eta = *eta;
-        HIP_TRY(hipMemcpy(c->d_md_state.p, &st, sizeof(MdState), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(cur, &st, sizeof(MdState), hipMemcpyHostToDevice));
     } else {
         *xi = st.xi;
         *eta = st.eta;
@@ -1760,7 +1772,8 @@ int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int therm
     m.half_skin2 = 0.25 * skin_of(c, 0) * skin_of(c, 0);
     m.stale = (unsigned*)c->d_md_stale.p;
     m.partial = c->d_md_part.as<double>();
-    m.st = c->d_md_state.as<MdState>();
+    MdState* stb = c->d_md_state.as<MdState>();             // two buffers
+    m.st = stb + c->md_cur;
     const int nblk = md_blocks(c->n);                       // partials of k_md_kinetic
     const int nblk_kick = bonded_blocks(c->n, c->bond_lg);  // partials of the kick
     const double* e_nb = c->d_md_E.as<double>();
@@ -1774,17 +1787,34 @@ int relres_md_run(relres_ctx* c, double* pos, double* vel, int nsteps, int therm
     HIP_TRY(launch_md_kinetic(m, s));
     HIP_TRY(launch_md_scalar(m.st, m.partial, nblk, m.ftm2v, 0, nsteps > 0, nullptr, nullptr,
                              nullptr, nullptr, s));
+    auto row_of = [&](int step) -> double* {
+        return thermo_every > 0 && step % thermo_every == 0
+                   ? thermo + (size_t)8 * (step / thermo_every - 1) : nullptr;
+    };
     for (int step = 1; step <= nsteps; ++step) {
-        HIP_TRY(launch_md_drift(m, prec, s));
+        // from the second step on, the drift also does the scalar work after
+        // the previous step (second thermostat half step, its row, first
+        // half step of this one), reading one state buffer, writing the other
+        if (step == 1) {
+            HIP_TRY(launch_md_drift(m, m.st, m.st, 0, 0, nullptr, nullptr, nullptr, nullptr, prec, s));
+        } else {
+            const int next = 1 - c->md_cur;
+            HIP_TRY(launch_md_drift(m, stb + c->md_cur, stb + next, nblk_kick, 1, e_nb, w_nb, eb,
+                                    row_of(step - 1), prec, s));
+            c->md_cur = next;
+            m.st = stb + next;
+        }
         if (step % c->md_rebuild == 0) TRY(md_rebuild(c, pos, s, true));
-        const bool out = thermo_every > 0 && step % thermo_every == 0;
+        const bool out = row_of(step) != nullptr;
         TRY(relres_forces(c, pos, F, out ? c->d_md_E.as<double>() : nullptr,
                           out ? c->d_md_W.as<double>() : nullptr, s));
         // bonded and 1-4 forces, the half kick and the kinetic partials
         TRY(enqueue_bonded(c, pos, F, out, &m, s));
-        HIP_TRY(launch_md_scalar(m.st, m.partial, nblk_kick, m.ftm2v, 1, step < nsteps, e_nb, w_nb, eb,
-                                 out ? thermo + (size_t)8 * (step / thermo_every - 1) : nullptr, s));
     }
+    // the second half step of the last step
+    if (nsteps > 0)
+        HIP_TRY(launch_md_scalar(m.st, m.partial, nblk_kick, m.ftm2v, 1, 0, e_nb, w_nb, eb,
+                                 row_of(nsteps), s));
     HIP_TRY(launch_md_finish(m, s));
     // the last steps since the previous build must not have outrun the skin either
     HIP_TRY(hipMemcpyAsync(c->h_stale, c->d_md_stale.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));

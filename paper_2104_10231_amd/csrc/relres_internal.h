@@ -254,7 +254,13 @@ struct MdArgs {
     double* partial;                  // per block kinetic partial
     MdState* st;
 };
-hipError_t launch_md_drift(const MdArgs& m, int force_prec, hipStream_t s);
+// Drift of one step; with scalar != 0 every block first does the scalar work
+// between the previous step and this one from st_in (kinetic partials
+// m.partial[0..nparts), the thermodynamic row when row != 0) and block 0
+// stores the new state in st_out (a different buffer).
+hipError_t launch_md_drift(const MdArgs& m, const MdState* st_in, MdState* st_out, int nparts,
+                           int scalar, const double* e_nb, const double* w_nb, const double* eb,
+                           double* row, int force_prec, hipStream_t s);
 hipError_t launch_md_kinetic(const MdArgs& m, hipStream_t s);
 // kinetic energy from the partials; second / first thermostat half steps;
 // with row, one row of thermodynamic output

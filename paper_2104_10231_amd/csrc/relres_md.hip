@@ -318,13 +318,74 @@ __device__ __forceinline__ void thermostat_half(MdState* st)
     st->s_last = s;
 }
 
-template <typename TF>
-__global__ __launch_bounds__(kMdBlock) void k_md_drift(MdArgs m)
+// The scalar work between two steps on a copy of the state: the kinetic
+// energy from the partial sum; with `second` the second thermostat half
+// step of the step just done (and, with `row`, its thermodynamic output: the
+// non-bonded energy of Eq. 3, the 1-4, bond, angle and dihedral energies,
+// the kinetic energy, the extended energy K + U + Q xi^2/2 + g kT eta and
+// the trace of the virial); with `first` the first half step of the next
+// step, whose drift applies s2 s1 to the stored velocities.
+__device__ void scalar_step(MdState& st, double ksum, double ftm2v, int second, int first,
+                            const double* __restrict__ e_nb, const double* __restrict__ w_nb,
+                            const double* __restrict__ eb, double* __restrict__ row)
 {
+    st.K = 0.5 * ksum / ftm2v;
+    if (second) {
+        thermostat_half(&st);
+        st.s2 = st.s_last;
+        if (row) {
+            const double u = e_nb[0] + eb[3] + eb[0] + eb[1] + eb[2];
+            row[0] = e_nb[0];
+            row[1] = eb[3];
+            row[2] = eb[0];
+            row[3] = eb[1];
+            row[4] = eb[2];
+            row[5] = st.K;
+            row[6] = st.K + u + 0.5 * st.Q * st.xi * st.xi + st.g * st.kT * st.eta;
+            row[7] = w_nb[0] + w_nb[1] + w_nb[2] + eb[4] + eb[5] + eb[6];
+        }
+    }
+    if (first) {
+        thermostat_half(&st);
+        st.s_apply = st.s2 * st.s_last;
+        st.s2 = 1.0;
+    }
+}
+
+// Drift of one step.  With `scalar`, every block first does the scalar work
+// between the previous step and this one (the same sums in the same order,
+// so every block gets the same state; block 0 stores it in st_out and writes
+// the row), which saves a launch per step; st_in is not written, so no block
+// can see a half-updated state.  Without it the state in st_in is current.
+template <typename TF>
+__global__ __launch_bounds__(kMdBlock) void k_md_drift(MdArgs m, const MdState* st_in,
+                                                       MdState* st_out, int nparts, int scalar,
+                                                       const double* __restrict__ e_nb,
+                                                       const double* __restrict__ w_nb,
+                                                       const double* __restrict__ eb,
+                                                       double* __restrict__ row)
+{
+    __shared__ double s_sh;
+    double s;
+    if (scalar) {
+        if (threadIdx.x < 64) {
+            const double ks = sum_blocks(m.partial, nparts, nullptr, 0, 1, 0);
+            if (threadIdx.x == 63) {
+                MdState st = *st_in;
+                scalar_step(st, ks, m.ftm2v, 1, 1, e_nb, w_nb, eb,
+                            blockIdx.x == 0 ? row : nullptr);
+                if (blockIdx.x == 0) *st_out = st;
+                s_sh = st.s_apply;
+            }
+        }
+        __syncthreads();
+        s = s_sh;
+    } else {
+        s = st_in->s_apply;
+    }
     const int i = blockIdx.x * kMdBlock + threadIdx.x;
     if (i >= m.n) return;
-    const double s = m.st->s_apply;
-    const double dt = m.st->dt;
+    const double dt = st_in->dt;
     const double am = m.ftm2v / m.mass[i];
     const TF* F = (const TF*)m.forces;
     double dmax2 = 0.0;
@@ -353,13 +414,9 @@ __global__ __launch_bounds__(kMdBlock) void k_md_kinetic(MdArgs m)
     if (threadIdx.x == 0) m.partial[blockIdx.x] = r;
 }
 
-// The scalar part between two steps (one thread): the kinetic energy from
-// the block partials (fixed order); with `second` the second thermostat half
-// step of the step just done (and, with `row`, its thermodynamic output: the
-// non-bonded energy of Eq. 3, the 1-4, bond, angle and dihedral energies,
-// the kinetic energy, the extended energy K + U + Q xi^2/2 + g kT eta and
-// the trace of the virial); with `first` the first half step of the next
-// step, whose drift applies s2 s1 to the stored velocities.
+// The scalar work between two steps as a kernel of its own (one wave; at
+// the start and the end of a run, where no drift follows): scalar_step on
+// the state in place.
 __global__ void k_md_scalar(MdState* st, const double* __restrict__ partial, int nblocks,
                             double ftm2v, int second, int first, const double* __restrict__ e_nb,
                             const double* __restrict__ w_nb, const double* __restrict__ eb,
@@ -368,27 +425,9 @@ __global__ void k_md_scalar(MdState* st, const double* __restrict__ partial, int
     // one wave: the block partials in a fixed order, then lane 63 alone
     const double s = sum_blocks(partial, nblocks, nullptr, 0, 1, 0);
     if (threadIdx.x != 63) return;
-    st->K = 0.5 * s / ftm2v;
-    if (second) {
-        thermostat_half(st);
-        st->s2 = st->s_last;
-        if (row) {
-            const double u = e_nb[0] + eb[3] + eb[0] + eb[1] + eb[2];
-            row[0] = e_nb[0];
-            row[1] = eb[3];
-            row[2] = eb[0];
-            row[3] = eb[1];
-            row[4] = eb[2];
-            row[5] = st->K;
-            row[6] = st->K + u + 0.5 * st->Q * st->xi * st->xi + st->g * st->kT * st->eta;
-            row[7] = w_nb[0] + w_nb[1] + w_nb[2] + eb[4] + eb[5] + eb[6];
-        }
-    }
-    if (first) {
-        thermostat_half(st);
-        st->s_apply = st->s2 * st->s_last;
-        st->s2 = 1.0;
-    }
+    MdState cur = *st;
+    scalar_step(cur, s, ftm2v, second, first, e_nb, w_nb, eb, row);
+    *st = cur;
 }
 
 // Make the stored velocities the true ones (v_s *= s2), at the end of a run.
@@ -431,13 +470,17 @@ hipError_t launch_sum_partials(const double* p1, int n1, const double* p2, int n
     return hipGetLastError();
 }
 
-hipError_t launch_md_drift(const MdArgs& m, int force_prec, hipStream_t s)
+hipError_t launch_md_drift(const MdArgs& m, const MdState* st_in, MdState* st_out, int nparts,
+                           int scalar, const double* e_nb, const double* w_nb, const double* eb,
+                           double* row, int force_prec, hipStream_t s)
 {
     const int blocks = (m.n + kMdBlock - 1) / kMdBlock;
     if (force_prec == 64)
-        hipLaunchKernelGGL(k_md_drift<double>, dim3(blocks), dim3(kMdBlock), 0, s, m);
+        hipLaunchKernelGGL(k_md_drift<double>, dim3(blocks), dim3(kMdBlock), 0, s, m, st_in,
+                           st_out, nparts, scalar, e_nb, w_nb, eb, row);
     else
-        hipLaunchKernelGGL(k_md_drift<float>, dim3(blocks), dim3(kMdBlock), 0, s, m);
+        hipLaunchKernelGGL(k_md_drift<float>, dim3(blocks), dim3(kMdBlock), 0, s, m, st_in,
+                           st_out, nparts, scalar, e_nb, w_nb, eb, row);
     return hipGetLastError();
 }
 
