@@ -275,7 +275,7 @@ struct relres_ctx {
     DBuf d_sys;                       // system of each atom (nsys > 1)
     std::vector<double> boxes;        // [nsys][3] of the last build
     std::vector<double> boxes_dev;    // [nsys][6] as uploaded
-    DBuf d_boxes, d_row_ew;
+    DBuf d_boxes, d_row_ew, d_wave_ew, d_wave_sys;
     int same_mol = 0;
     bool has_excl = false;
     int max_excl = 0;
@@ -1389,8 +1389,13 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     }
     const bool ew = energy || virial;
     if (ew && c->nsys > 1) {
+        const size_t waves = (size_t)(a.blocks_a + a.blocks_b) * (kForceBlock / 64);
         TRY(ensure(c->d_row_ew, sizeof(double) * 8 * (size_t)(c->n + c->n_sites), &c->alloc_generation));
+        TRY(ensure(c->d_wave_ew, sizeof(double) * 8 * waves, &c->alloc_generation));
+        TRY(ensure(c->d_wave_sys, sizeof(int) * waves, &c->alloc_generation));
         a.row_ew = c->d_row_ew.as<double>();
+        a.wave_ew = c->d_wave_ew.as<double>();
+        a.wave_sys = c->d_wave_sys.as<int>();
     }
     HIP_TRY(launch_forces(a, c->cut64, c->per_pair, c->pair_math, c->precision, ew, s));
     if (timed) {
@@ -1398,8 +1403,7 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
         c->ev_force.push_back({e0, e1});
     }
     if (ew && c->nsys > 1)
-        HIP_TRY(launch_reduce_sys_ew(c->d_grids.as<GridDev>(), sites ? 2 : 1, a.row_ew, c->n, c->nsys,
-                                     energy, virial, s));
+        HIP_TRY(launch_reduce_sys_ew(c->d_grids.as<GridDev>(), sites ? 2 : 1, a, energy, virial, s));
     return RELRES_OK;
 }
 
@@ -1917,7 +1921,8 @@ void relres_destroy(relres_ctx* c)
 {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial, &c->d_sys, &c->d_boxes, &c->d_row_ew}) release(*b);
+    for (DBuf* b : {&c->d_coef_grad, &c->d_bpartial, &c->d_sys, &c->d_boxes, &c->d_row_ew, &c->d_wave_ew,
+                    &c->d_wave_sys}) release(*b);
     for (DBuf* b : {&c->d_items, &c->d_bond_par, &c->d_angle_par, &c->d_dih_par,
                     &c->d_bond_part, &c->d_bond_sum,
                     &c->d_mass, &c->d_md_state, &c->d_md_xref,

@@ -121,7 +121,11 @@ struct ForceArgs {
     double inv_box[3];
     int nsys;
     const double* boxes;      // [nsys][6]: L_x, L_y, L_z, 1/L_x, 1/L_y, 1/L_z
-    double* row_ew;           // nsys > 1: 8 FP64 partials per row (atom rows, then site rows)
+    double* row_ew;           // nsys > 1: 8 FP64 partials per row (atom rows, then site
+                              // rows), written only by waves across a system boundary
+    double* wave_ew;          // nsys > 1: 8 FP64 sums per wave (atom waves, then site waves)
+    int* wave_sys;            // ... and the wave's system; -1: across a boundary (rows in
+                              // row_ew), -2: no rows of its own
     // atom list rows (all atoms, atom-grid order); record = (caller index,
     // type + 32 system, stored entries, 1 if hybrid)
     int n_arow;
@@ -187,10 +191,10 @@ constexpr int kBackwardTypes = 8;
 hipError_t launch_backward(const BackArgs& b, int waves, double* grad_pair, hipStream_t s);
 hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStream_t s);
-// nsys > 1: energy/virial of each system from the per-row partials
-hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const double* row_ew,
-                                int n_arow, int nsys, double* energy, double* virial,
-                                hipStream_t s);
+// nsys > 1: energy/virial of each system from the wave sums (and the row
+// partials of waves across a system boundary)
+hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const ForceArgs& a,
+                                double* energy, double* virial, hipStream_t s);
 
 // Bonded terms and scaled 1-4 pairs (relres_md.hip).  Per atom, the terms
 // it belongs to: term_ent packs kind (bits 30-31: 0 bond, 1 angle,

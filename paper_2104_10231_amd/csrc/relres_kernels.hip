@@ -1224,14 +1224,36 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         if (a.nsys == 1) {
             ew_finish(a, acc, tag);
         } else {
-            // several systems: every row publishes its partials; a second
-            // kernel adds each system's rows in row order
+            // several systems (rows are grouped by system): a wave whose own
+            // rows all belong to one system adds its lanes and writes one
+            // record; a wave across a system boundary (rare) writes every
+            // row's partials.  A second kernel adds each system's records.
+            const int lane = (int)threadIdx.x & (kWave - 1);
+            const size_t wrec = (rb ? (size_t)a.blocks_a * (kForceBlock / kWave) : 0) +
+                                (size_t)logical * (kForceBlock / kWave) + (threadIdx.x / kWave);
+            const int sys_row = own ? (rec.y >> kTypeBits) : -1;
+            const uint64_t own_mask = __ballot(own);
+            if (own_mask == 0ull) {
+                if (lane == 0) a.wave_sys[wrec] = -2;
+            } else {
+                const int s0 = __builtin_amdgcn_readlane(sys_row, __ffsll((long long)own_mask) - 1);
+                if (__ballot(own && sys_row != s0) == 0ull) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = group_sum(acc[k], G);
-            if (live && sub == 0) {
-                double* out = a.row_ew + 8 * (size_t)(rb ? a.n_arow + row : row);
+                    for (int k = 0; k < 8; ++k) {
+                        const double w = wave_sum(acc[k]);
+                        if (lane == kWave - 1) a.wave_ew[8 * wrec + k] = w;
+                    }
+                    if (lane == kWave - 1) a.wave_sys[wrec] = s0;
+                } else {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) out[k] = own ? acc[k] : 0.0;
+                    for (int k = 0; k < 8; ++k) acc[k] = group_sum(acc[k], G);
+                    if (live && sub == 0) {
+                        double* out = a.row_ew + 8 * (size_t)(rb ? a.n_arow + row : row);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) out[k] = own ? acc[k] : 0.0;
+                    }
+                    if (lane == 0) a.wave_sys[wrec] = -1;
+                }
             }
         }
     }
@@ -1249,9 +1271,13 @@ __global__ void k_zero_outputs(double* energy, double* virial, int nsys)
 // Energy and virial of every system (one block per system) from the per-row
 // partials of the force kernel: the system's atom-list rows, then its
 // site-list rows, each thread in row order, then a fixed-order block sum.
+// One block per system: the records of the waves that hold its rows (wave
+// w of a kind holds rows w * rpw .. w * rpw + rpw - 1 of that kind, rpw =
+// 64 / lanes per row), and for a wave across a system boundary the partials
+// of its rows in this system; fixed order, so results are deterministic.
 __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict__ grids,
-                                                       int ngrids, const double* __restrict__ row_ew,
-                                                       int n_arow, double* __restrict__ energy,
+                                                       int ngrids, ForceArgs a,
+                                                       double* __restrict__ energy,
                                                        double* __restrict__ virial)
 {
     __shared__ double red[8][4];
@@ -1259,11 +1285,25 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int kind = 0; kind < ngrids; ++kind) {
         const GeomDev& G = grids[kind].geom[sy];
-        const size_t base = (kind ? (size_t)n_arow : 0) + (size_t)G.row_base;
-        for (int r = (int)threadIdx.x; r < G.members; r += 256) {
-            const double* p = row_ew + 8 * (base + r);
+        if (G.members == 0) continue;
+        const int rpw = kWave >> (kind ? a.log_lanes_b : a.log_lanes_a);
+        const int r0 = G.row_base, r1 = G.row_base + G.members;
+        const size_t woff = kind ? (size_t)a.blocks_a * (kForceBlock / kWave) : 0;
+        const size_t rbase = kind ? (size_t)a.n_arow : 0;
+        for (int w = r0 / rpw + (int)threadIdx.x; w <= (r1 - 1) / rpw; w += 256) {
+            const int ws = a.wave_sys[woff + w];
+            if (ws == sy) {
+                const double* p = a.wave_ew + 8 * (woff + w);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] += p[k];
+                for (int k = 0; k < 8; ++k) v[k] += p[k];
+            } else if (ws == -1) {
+                const int e = min((w + 1) * rpw, r1);
+                for (int r = max(w * rpw, r0); r < e; ++r) {
+                    const double* p = a.row_ew + 8 * (rbase + r);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] += p[k];
+                }
+            }
         }
     }
 #pragma unroll
@@ -1667,12 +1707,11 @@ hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const double* row_ew,
-                                int n_arow, int nsys, double* energy, double* virial,
-                                hipStream_t s)
+hipError_t launch_reduce_sys_ew(const GridDev* grids_dev, int ngrids, const ForceArgs& a,
+                                double* energy, double* virial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_sys_ew, dim3(nsys), dim3(256), 0, s, grids_dev, ngrids, row_ew,
-                       n_arow, energy, virial);
+    hipLaunchKernelGGL(k_reduce_sys_ew, dim3(a.nsys), dim3(256), 0, s, grids_dev, ngrids, a,
+                       energy, virial);
     return hipGetLastError();
 }
 
