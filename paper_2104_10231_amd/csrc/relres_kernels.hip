@@ -21,6 +21,8 @@
 #include "relres_pair.h"
 #include "relres_lanes.h"
 
+#include <cstdlib>
+
 namespace relres {
 namespace {
 
@@ -1392,8 +1394,14 @@ hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_
         if (total == 0) return hipSuccess;
         const int mx = topo.excl_off ? topo.max_excl : 0;
         const size_t dyn = sizeof(int) * 4 * kRowsPerWave * (size_t)mx;
-        // all waves resident at once (about 3 per SIMD): more candidates per lane
-        if (total <= kResidentListWaves)
+        // all waves resident at once (about 3 per SIMD): more candidates per
+        // lane; RELRES_LIST_CANDIDATES=2|4 overrides the choice (tuning runs)
+        bool k4 = total <= kResidentListWaves;
+        if (const char* e = std::getenv("RELRES_LIST_CANDIDATES")) {
+            if (e[0] == '2' && e[1] == 0) k4 = false;
+            if (e[0] == '4' && e[1] == 0) k4 = true;
+        }
+        if (k4)
             hipLaunchKernelGGL(k_lists_wave<4>, dim3((total + 3) / 4), dim3(256), dyn, s,
                                grids_dev, waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
         else
