@@ -232,7 +232,7 @@ struct GridHost {
     int ncell = 0;                    // cells of all grids
     int members = 0;                  // members of all grids
     int waves = 0;                    // list-kernel waves (rpw rows each)
-    int rpw = kRowsPerWave;           // home rows per list-kernel wave
+    int rpw = 8;                      // home rows per list-kernel wave
     bool site = false;                // the site grid (hybrid atoms)
     int n[3] = {0, 0, 0};             // cells per axis of system 0 (statistics)
     std::vector<int> sys_n;           // [nsys][3] cells per axis
@@ -439,13 +439,15 @@ void list_radii(const relres_ctx* c, std::vector<double>& skin, std::vector<doub
 // Home rows per wave of the list kernel (1 .. kRowsPerWave).  A wave tests
 // its rows one after another, so a launch with few waves spreads its tests
 // over more of them: when both lists together give fewer than 2048 waves at
-// kRowsPerWave rows, each grid takes the largest power of two that still
-// gives it 2000 waves.  Large launches keep kRowsPerWave and load each
-// stencil for as many rows as possible.  Measured on MI355X: the 20480-atom
-// liquid (3072 waves) builds slower with fewer rows per wave; 6000-atom
-// hexane dynamics (1000 waves) takes 5 % less time per step at 2 / 1 rows
-// than at 8 / 8.  The environment variable RELRES_LIST_ROWS="atom,site"
-// overrides the choice (for tuning runs).
+// 8 rows, each grid takes the largest power of two that still gives it 2000
+// waves.  Launches of at least 2048 waves at 16 rows take 16, so each
+// stencil is loaded for as many rows as possible; the others 8.  Measured on
+// MI355X: the 20480-atom liquid (3072 waves at 8 rows) builds slower with
+// fewer or more rows per wave (50 µs at 8, 58 µs at 16); 6000-atom hexane
+// dynamics (1000 waves) takes 5 % less time per step at 2 / 1 rows than at
+// 8 / 8; the 256-replica batch (1.44 M rows) runs 3 % faster at 16 than at
+// 8.  The environment variable RELRES_LIST_ROWS="atom,site" overrides the
+// choice (for tuning runs).
 int list_rows_per_wave(bool site, long long members, long long launch_rows)
 {
     if (const char* e = std::getenv("RELRES_LIST_ROWS")) {
@@ -455,8 +457,9 @@ int list_rows_per_wave(bool site, long long members, long long launch_rows)
             if (r >= 1 && r <= kRowsPerWave) return r;
         }
     }
-    int r = kRowsPerWave;
-    if (launch_rows >= 2048LL * kRowsPerWave) return r;
+    if (launch_rows >= 2048LL * 16) return 16;
+    int r = 8;
+    if (launch_rows >= 2048LL * r) return r;
     while (r > 1 && members < 2000LL * r) r >>= 1;
     return r;
 }

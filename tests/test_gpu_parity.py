@@ -373,7 +373,7 @@ def test_cell_per_block_list_kernel(monkeypatch):
     _check(s.conventional(), 64)
 
 
-@pytest.mark.parametrize("rows", ["1,1", "2,5", "4,3"])
+@pytest.mark.parametrize("rows", ["1,1", "2,5", "4,3", "16,12"])
 def test_rows_per_wave_of_the_list_kernel(monkeypatch, rows):
     """Any number of home rows per list-kernel wave (RELRES_LIST_ROWS =
     "atom,site") builds the same lists: pair sets equal to the oracle's and
