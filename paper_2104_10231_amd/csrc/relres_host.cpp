@@ -282,7 +282,7 @@ struct relres_ctx {
     DBuf d_types, d_mol, d_excl_off, d_excl_idx;
 
     GridHost ga, gs;
-    DBuf d_grids, d_wpos, d_key_a, d_key_s, d_user2arow, d_a_rec, d_s_rec, d_status;
+    DBuf d_grids, d_wpos, d_key_a, d_key_s, d_user2arow, d_a_rec, d_s_rec, d_status, d_seg_tot;
     GridDev* h_grids = nullptr;       // pinned staging of the device descriptors
     GridDev uploaded[2] = {};         // descriptors currently on the device
     bool grids_valid = false;
@@ -761,6 +761,9 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     TRY(ensure(c->d_key_a, sizeof(int2) * c->n, &c->alloc_generation));
     TRY(ensure(c->d_key_s, sizeof(int2) * c->n, &c->alloc_generation));
     TRY(ensure(c->d_user2arow, sizeof(int) * c->n, &c->alloc_generation));
+    TRY(ensure(c->d_seg_tot, sizeof(int) * (size_t)(scan_segments(c->ga.ncell) +
+                                                   (sites ? scan_segments(c->gs.ncell) : 0) + 1),
+               &c->alloc_generation));
     TRY(ensure(c->d_a_rec, sizeof(int4) * std::max(1, c->n), &c->alloc_generation));
     TRY(ensure(c->d_s_rec, sizeof(int4) * std::max(1, c->n_sites), &c->alloc_generation));
 
@@ -781,7 +784,8 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
                            c->d_key_s.as<int2>(), c->d_status.as<Status>(), check_moved, s));
         c->ref_valid = true;
         c->ref_skins = skin_sys;
-        HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->d_status.as<Status>(), s));
+        HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->ga.ncell, sites ? c->gs.ncell : 0,
+                            c->d_seg_tot.as<int>(), c->d_status.as<Status>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
         HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
@@ -1934,7 +1938,7 @@ void relres_destroy(relres_ctx* c)
     if (c->h_stale) (void)hipHostFree(c->h_stale);
     for (DBuf* b : {&c->d_coef64, &c->d_coef32, &c->d_hybrid, &c->d_types, &c->d_mol, &c->d_excl_off,
                     &c->d_excl_idx, &c->d_grids, &c->d_wpos, &c->d_key_a, &c->d_key_s,
-                    &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials,
+                    &c->d_user2arow, &c->d_a_rec, &c->d_s_rec, &c->d_status, &c->d_partials, &c->d_seg_tot,
                     &c->d_epoch})
         release(*b);
     for (GridHost* g : {&c->ga, &c->gs})

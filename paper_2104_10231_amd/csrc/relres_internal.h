@@ -162,7 +162,12 @@ hipError_t launch_bin(int n, const double* pos, TopoDev topo, GridDev* grids_dev
 // st->moved_query += atoms of pos more than half their system's skin from wpos
 hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* grids_dev,
                         const double4* wpos, Status* st, hipStream_t s);
-hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s);
+// Exclusive scan of the cell counts of both grids (one block per grid, or
+// with more than one segment per grid a two-launch scan over all segments
+// using seg_tot: scan_segments(ncell_a) + scan_segments(ncell_s) ints)
+int scan_segments(int ncell);
+hipError_t launch_scan(GridDev* grids_dev, int ngrids, int ncell_a, int ncell_s, int* seg_tot,
+                       Status* st, hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);
 hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,

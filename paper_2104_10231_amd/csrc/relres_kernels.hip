@@ -175,51 +175,122 @@ __global__ void k_moved(int n, const double* __restrict__ pos, TopoDev topo,
 // contiguous run of its segment.  Block 0 also clears the list statistics.
 constexpr int kScanThreads = 1024;
 constexpr int kScanSeg = 8192;
+
+// One segment of the scan (all threads of the block): start[seg + k] =
+// carry + the exclusive prefix of the segment's counts, the counts cleared.
+// Returns the segment's total in every thread.
+__device__ __forceinline__ int scan_segment(int* vals, int* sums, RELRES_GLOBAL int* gcount,
+                                            RELRES_GLOBAL int* gstart, int seg, int len, int carry)
+{
+    const int t = threadIdx.x;
+    constexpr int per = kScanSeg / kScanThreads;
+    for (int k = t; k < kScanSeg; k += kScanThreads) vals[k] = k < len ? gcount[seg + k] : 0;
+    __syncthreads();
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) s += vals[t * per + k];
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int run = carry + sums[t] - s;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int v = vals[t * per + k];
+        vals[t * per + k] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int k = t; k < len; k += kScanThreads) {
+        gstart[seg + k] = vals[k];
+        gcount[seg + k] = 0;
+    }
+    const int total = sums[kScanThreads - 1];
+    __syncthreads();            // vals and sums are reused by the next segment
+    return total;
+}
+
+// Sum of one int per thread over the block (every thread gets it).
+__device__ __forceinline__ int block_sum_int(int v, int* sums)
+{
+    const int t = threadIdx.x;
+    sums[t] = v;
+    __syncthreads();
+    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+        if (t < off) sums[t] += sums[t + off];
+        __syncthreads();
+    }
+    const int r = sums[0];
+    __syncthreads();
+    return r;
+}
+
+// One block per grid: exclusive scan of the per-cell counts into `start`,
+// then the counts are cleared for the next build.  Counts are staged through
+// LDS in segments of kScanSeg cells with coalesced loads; each thread scans a
+// contiguous run of its segment.  Block 0 also clears the list statistics.
 __global__ __launch_bounds__(kScanThreads) void k_scan(GridDev* __restrict__ grids,
                                                        Status* __restrict__ st)
 {
     __shared__ int vals[kScanSeg];
     __shared__ int sums[kScanThreads];
-    __shared__ int carry_sh;
     if (blockIdx.x == 0 && threadIdx.x < 2) st->max_row[threadIdx.x] = 0;
     const GridDev& g = grids[blockIdx.x];
     const int nc = g.ncell;
-    RELRES_GLOBAL int* gcount = gbl(g.count);
-    RELRES_GLOBAL int* gstart = gbl(g.start);
-    const int t = threadIdx.x;
-    constexpr int per = kScanSeg / kScanThreads;
-    if (t == 0) carry_sh = 0;
-    for (int seg = 0; seg < nc; seg += kScanSeg) {
-        const int len = min(kScanSeg, nc - seg);
-        for (int k = t; k < kScanSeg; k += kScanThreads) vals[k] = k < len ? gcount[seg + k] : 0;
-        __syncthreads();
-        int s = 0;
-#pragma unroll
-        for (int k = 0; k < per; ++k) s += vals[t * per + k];
-        sums[t] = s;
-        __syncthreads();
-        for (int off = 1; off < kScanThreads; off <<= 1) {
-            const int v = t >= off ? sums[t - off] : 0;
-            __syncthreads();
-            sums[t] += v;
-            __syncthreads();
-        }
-        int run = carry_sh + sums[t] - s;
-#pragma unroll
-        for (int k = 0; k < per; ++k) {
-            const int v = vals[t * per + k];
-            vals[t * per + k] = run;
-            run += v;
-        }
-        __syncthreads();
-        for (int k = t; k < len; k += kScanThreads) {
-            gstart[seg + k] = vals[k];
-            gcount[seg + k] = 0;
-        }
-        if (t == kScanThreads - 1) carry_sh += sums[kScanThreads - 1];
-        __syncthreads();
-    }
-    if (t == 0) gstart[nc] = carry_sh;
+    int carry = 0;
+    for (int seg = 0; seg < nc; seg += kScanSeg)
+        carry += scan_segment(vals, sums, gbl(g.count), gbl(g.start), seg, min(kScanSeg, nc - seg),
+                              carry);
+    if (threadIdx.x == 0) gbl(g.start)[nc] = carry;
+}
+
+// Grids of more than one segment: the same scan with every segment in a
+// block of its own.  Blocks 0 .. nseg0-1 are the segments of grid 0, the
+// rest those of grid 1.  First each block sums its segment's counts ...
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(const GridDev* __restrict__ grids,
+                                                              int nseg0, int* __restrict__ seg_tot)
+{
+    __shared__ int sums[kScanThreads];
+    const int b = blockIdx.x;
+    const int gi = b >= nseg0 ? 1 : 0;
+    const int seg = (gi ? b - nseg0 : b) * kScanSeg;
+    const GridDev& g = grids[gi];
+    const int len = min(kScanSeg, g.ncell - seg);
+    RELRES_GLOBAL const int* gcount = gbl(g.count);
+    int s = 0;
+    for (int k = threadIdx.x; k < len; k += kScanThreads) s += gcount[seg + k];
+    s = block_sum_int(s, sums);
+    if (threadIdx.x == 0) seg_tot[b] = s;
+}
+
+// ... then each block adds the totals of its grid's earlier segments and
+// scans its own segment (the grid's last segment also writes start[ncell]).
+// Block 0 also clears the list statistics.
+__global__ __launch_bounds__(kScanThreads) void k_scan_segments(GridDev* __restrict__ grids,
+                                                                int nseg0,
+                                                                const int* __restrict__ seg_tot,
+                                                                Status* __restrict__ st)
+{
+    __shared__ int vals[kScanSeg];
+    __shared__ int sums[kScanThreads];
+    if (blockIdx.x == 0 && threadIdx.x < 2) st->max_row[threadIdx.x] = 0;
+    const int b = blockIdx.x;
+    const int gi = b >= nseg0 ? 1 : 0;
+    const int q = gi ? b - nseg0 : b;
+    const int first = gi ? nseg0 : 0;
+    const GridDev& g = grids[gi];
+    const int nc = g.ncell;
+    const int seg = q * kScanSeg;
+    int carry = 0;
+    for (int j = threadIdx.x; j < q; j += kScanThreads) carry += seg_tot[first + j];
+    carry = block_sum_int(carry, sums);
+    const int len = min(kScanSeg, nc - seg);
+    const int total = scan_segment(vals, sums, gbl(g.count), gbl(g.start), seg, len, carry);
+    if (threadIdx.x == 0 && seg + len == nc) gbl(g.start)[nc] = carry + total;
 }
 
 __global__ void k_scatter(int n, const GridDev* __restrict__ grids, const int2* __restrict__ key_a,
@@ -1358,9 +1429,20 @@ hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* g
     return hipGetLastError();
 }
 
-hipError_t launch_scan(GridDev* grids_dev, int ngrids, Status* st, hipStream_t s)
+int scan_segments(int ncell) { return (ncell + kScanSeg - 1) / kScanSeg; }
+
+hipError_t launch_scan(GridDev* grids_dev, int ngrids, int ncell_a, int ncell_s, int* seg_tot,
+                       Status* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan, dim3(ngrids), dim3(kScanThreads), 0, s, grids_dev, st);
+    const int nseg0 = scan_segments(ncell_a), nseg1 = ngrids > 1 ? scan_segments(ncell_s) : 0;
+    if (nseg0 <= 1 && nseg1 <= 1) {
+        hipLaunchKernelGGL(k_scan, dim3(ngrids), dim3(kScanThreads), 0, s, grids_dev, st);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_totals, dim3(nseg0 + nseg1), dim3(kScanThreads), 0, s, grids_dev,
+                       nseg0, seg_tot);
+    hipLaunchKernelGGL(k_scan_segments, dim3(nseg0 + nseg1), dim3(kScanThreads), 0, s, grids_dev,
+                       nseg0, seg_tot, st);
     return hipGetLastError();
 }
 

@@ -403,6 +403,14 @@ def test_rows_per_wave_of_the_list_kernel(monkeypatch, rows):
         assert np.array_equal(x, y)
 
 
+def test_grid_of_many_cells():
+    """A dilute box of 25^3 atom cells (more than one scan segment: the cell
+    offsets come from the two-launch scan) still gives the oracle's pair sets
+    and forces."""
+    s = w.random_molecules(12, 300, 200.0, kind="propane", min_dist=2.9, hybrid_fraction=0.7)
+    _check(s, 64)
+
+
 def test_graph_replay_matches_eager():
     """relres_forces captured in a HIP graph: every replay, with eager library
     work and synchronisation in between, reproduces the eager results bitwise."""
