@@ -7,7 +7,7 @@
  * the benchmark's CPU-baseline leg; nothing in the product library links or
  * calls it, and it shares no code with the HIP path.
  *
- * Readings (also listed in the design doc):
+ * Readings (where Sec. 3.2 is silent):
  *   - The spring constants are those of the AMBER convention, without a
  *     factor 1/2: E_bond = K (r - r0)^2 and E_angle = K (theta - theta0)^2.
  *     The printed 180,640 zJ/nm^2 is exactly AMBER's 260 kcal/mol/A^2.

@@ -38,7 +38,7 @@
  *     come from solving the same systems with differentiated right-hand
  *     sides; Eq. 20 is then differentiated case by case.
  *
- * Readings where the paper is silent or garbled (also listed in the design doc):
+ * Readings where the paper is silent or garbled:
  *   - Eq. 18 prints gamma_4+ with the wrong sign of its u'' term; the oracle
  *     does not use Eq. 18 at all, it solves Eq. 8 itself.
  *   - An empty smoothing zone (r_- == r_+, allowed in Sec. 2.5) makes the

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
-Bars (see the design doc for their derivation):
+Bars:
   * neighbour pair sets: bit-exact (same FP64 membership decision on both sides);
   * FP64 path: forces within 1e-11 relative RMS, energy and virial within 1e-12;
   * FP32 path: forces within 1e-5 relative RMS, energy and virial (accumulated
