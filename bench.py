@@ -389,6 +389,8 @@ def batch_bench(args):
     rr = make(b.whole, 32, args.pair_math)
     rr.set_systems(b.offsets)
     rr.set_skins(b.skins)
+    if args.lanes:
+        rr.set_launch(*args.lanes)
     rr.build_lists(pos, b.boxes)
     F = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     E = torch.empty((b.nsys, 3), dtype=torch.float64, device="cuda")

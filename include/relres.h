@@ -372,7 +372,8 @@ int relres_get_pairs(relres_ctx *ctx, int which, int *pairs_host, long long cap,
 /* Lanes of a wavefront that share one list row in the force kernel: for rows
  * of ordinary atoms (atom list) and of hybrid atoms (atom + site list).
  * Powers of two up to 64; 0 selects a value from the mean row length of the
- * last build.                                                              */
+ * last build (about 4 entries per lane, 8 or 16 in launches that fill the
+ * GPU many times over).                                                    */
 int relres_set_launch(relres_ctx *ctx, int lanes_atom, int lanes_site);
 
 /* With enable != 0, HIP events are recorded on the caller's stream right

@@ -681,11 +681,22 @@ int refresh_list_stats(relres_ctx* c, hipStream_t s)
     st.site_entries = (c->n && sites) ? (long long)c->h_status->entries[1] : 0;
     st.atom_max_row = c->n ? c->h_status->longest[0] : 0;
     st.site_max_row = (c->n && sites) ? c->h_status->longest[1] : 0;
-    // automatic lanes per row: about four list entries per lane
+    // Automatic lanes per row: about E list entries per lane.  A launch that
+    // fits the machine a few times over is latency-bound and takes E = 4
+    // (short chains per lane); a much larger one is bound by issue, and its
+    // per-row work (record, reductions across the row's lanes) shrinks with
+    // fewer lanes per row: E = 8, then 16.  Measured on MI355X (force launch):
+    // the 20480-atom liquid (2304 waves at E = 4) is fastest at E = 4; the
+    // 98304-atom copolymer (24576 waves) at E = 8, 38.4 against 45.9 us; the
+    // 256-replica batch (210000 waves) at E = 16, 221 against 342 us.
     const double avg_a = c->n ? (double)st.atom_entries / c->n : 0.0;
     const double avg_s = c->n_sites ? (double)st.site_entries / c->n_sites : 0.0;
-    c->auto_la = next_pow2_clamped(avg_a / 4.0, 1, 32);
-    c->auto_lb = next_pow2_clamped((avg_a + avg_s) / 4.0, 1, 64);
+    const long long waves4 =
+        ((long long)c->n * next_pow2_clamped(avg_a / 4.0, 1, 32) +
+         (long long)c->n_sites * next_pow2_clamped((avg_a + avg_s) / 4.0, 1, 64)) / 64;
+    const double per_lane = waves4 <= 8192 ? 4.0 : (waves4 <= 65536 ? 8.0 : 16.0);
+    c->auto_la = next_pow2_clamped(avg_a / per_lane, 1, 32);
+    c->auto_lb = next_pow2_clamped((avg_a + avg_s) / per_lane, 1, 64);
     c->stats_fresh = true;
     return RELRES_OK;
 }

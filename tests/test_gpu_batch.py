@@ -177,3 +177,23 @@ def test_per_system_skins():
     with pytest.raises(RelResError):
         rr.build_lists(p, b.boxes)
     rr.close()
+
+
+def test_skin_override_of_one_system_equals_the_parameter():
+    """relres_set_skins on a single system gives the lists, forces, energy and
+    virial of a context created with that skin, bit for bit."""
+    import torch
+    s = w.neopentane_liquid(3, n_side=8)
+    p = torch.from_numpy(s.pos).cuda()
+    ref = make_relres(s, 32)
+    ref.build_lists(p, s.box)
+    F0, E0, W0 = [t.double().cpu().numpy() for t in ref.forces(p)]
+    r = make_relres(s.replace(skin=0.5), 32)
+    r.set_skins([s.skin])
+    r.build_lists(p, s.box)
+    F1, E1, W1 = [t.double().cpu().numpy() for t in r.forces(p)]
+    assert np.array_equal(F0, F1) and np.array_equal(E0, E1) and np.array_equal(W0, W1)
+    for which in (0, 1):
+        assert np.array_equal(ref.pairs(which), r.pairs(which))
+    ref.close()
+    r.close()
