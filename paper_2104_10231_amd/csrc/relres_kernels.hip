@@ -176,6 +176,33 @@ __global__ void k_moved(int n, const double* __restrict__ pos, TopoDev topo,
 constexpr int kScanThreads = 1024;
 constexpr int kScanSeg = 8192;
 
+// Exclusive prefix sum over the block of one int per thread (in thread
+// order); every thread also gets the block's total.  Each wave scans its
+// lanes with cross-lane shuffles, then adds the totals of the waves before
+// it: two block barriers in all.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wtot, int& total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wtot[w] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / kWave; ++k) {
+        const int t = wtot[k];
+        before += k < w ? t : 0;
+        all += t;
+    }
+    __syncthreads();            // wtot is reused by the next call
+    total = all;
+    return before + x - v;
+}
+
 // One segment of the scan (all threads of the block): start[seg + k] =
 // carry + the exclusive prefix of the segment's counts, the counts cleared.
 // Returns the segment's total in every thread.
@@ -189,15 +216,8 @@ __device__ __forceinline__ int scan_segment(int* vals, int* sums, RELRES_GLOBAL 
     int s = 0;
 #pragma unroll
     for (int k = 0; k < per; ++k) s += vals[t * per + k];
-    sums[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int v = t >= off ? sums[t - off] : 0;
-        __syncthreads();
-        sums[t] += v;
-        __syncthreads();
-    }
-    int run = carry + sums[t] - s;
+    int total;
+    int run = carry + block_exclusive_scan(s, sums, total);
 #pragma unroll
     for (int k = 0; k < per; ++k) {
         const int v = vals[t * per + k];
@@ -209,24 +229,16 @@ __device__ __forceinline__ int scan_segment(int* vals, int* sums, RELRES_GLOBAL 
         gstart[seg + k] = vals[k];
         gcount[seg + k] = 0;
     }
-    const int total = sums[kScanThreads - 1];
-    __syncthreads();            // vals and sums are reused by the next segment
+    __syncthreads();            // vals is reused by the next segment
     return total;
 }
 
 // Sum of one int per thread over the block (every thread gets it).
 __device__ __forceinline__ int block_sum_int(int v, int* sums)
 {
-    const int t = threadIdx.x;
-    sums[t] = v;
-    __syncthreads();
-    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
-        if (t < off) sums[t] += sums[t + off];
-        __syncthreads();
-    }
-    const int r = sums[0];
-    __syncthreads();
-    return r;
+    int total;
+    block_exclusive_scan(v, sums, total);
+    return total;
 }
 
 // One block per grid: exclusive scan of the per-cell counts into `start`,
@@ -480,21 +492,32 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Stencil slot `lane` (< 27) of a home cell: the slot's cell (rank, or
+    // -1), then the first member and the end of its member range.  The next
+    // home cell's reads are issued while this cell is processed (the rank
+    // before this cell's candidate reads, the range at its first home row),
+    // so the two dependent reads leave the per-cell critical path.  Both
+    // reads are unconditional (lanes past the stencil and empty slots read a
+    // valid entry and drop it at use), so no branch makes the compiler wait
+    // for them early.
+    auto rank_of = [&](int h) { return gnbr[readlane_i(mcell, h) * 27 + min(lane, 26)]; };
+    int next_rank = nh > 0 ? rank_of(0) : -1;
+    int next_lo = 0, next_hi = 0;
+    auto range_of = [&]() {
+        const int r = (lane < 27 && next_rank >= 0) ? next_rank : 0;
+        next_lo = gstart[r];
+        next_hi = gstart[r + 1];
+    };
+    if (nh > 0) range_of();
     int h0 = 0;
     while (h0 < nh) {
         // rows h0 .. h1-1 share one cell
         const int c = readlane_i(mcell, h0);
         int h1 = h0 + 1;
         while (h1 < nh && readlane_i(mcell, h1) == c) ++h1;
-        // stencil slot `lane` (< 27): first member and count of its cell
-        int cnt = 0, s0 = 0;
-        if (lane < 27) {
-            const int r = gnbr[c * 27 + lane];
-            if (r >= 0) {
-                s0 = gstart[r];
-                cnt = gstart[r + 1] - s0;
-            }
-        }
+        const bool slot_ok = lane < 27 && next_rank >= 0;
+        const int s0 = slot_ok ? next_lo : 0, cnt = slot_ok ? next_hi - next_lo : 0;
+        next_rank = h1 < nh ? rank_of(h1) : -1;
         int pre = cnt;
         for (int o = 1; o < 32; o <<= 1) {
             const int v = __shfl_up(pre, o);
@@ -518,8 +541,10 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         }
         for (int cb = 0; cb < ncand; cb += kWave * K) {
             double px[K], py[K], pz[K];
-            // periodic shift of the candidate's slot, 2 bits per axis: 1 = -L, 2 = +L
-            int pu[K], pt[K], pm[K], ps[K];
+            // periodic image shift of the candidate's slot (-L, 0 or +L per axis),
+            // taken once per candidate for all the rows
+            double sx[K], sy[K], sz[K];
+            int pu[K], pt[K], pm[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int q = cb + lane + kWave * k;
@@ -533,8 +558,9 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                 const int slot = lo;
                 const int src = slot_start[wv][slot] + (q - slot_first[wv][slot]);
                 px[k] = py[k] = pz[k] = 0.0;
+                sx[k] = sy[k] = sz[k] = 0.0;
                 pu[k] = -1;
-                pt[k] = pm[k] = ps[k] = 0;
+                pt[k] = pm[k] = 0;
                 if (q < ncand) {
                     load_xyz(gpos, src, px[k], py[k], pz[k]);
                     load_meta(gmeta, src, pt[k], pm[k]);
@@ -542,13 +568,14 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                     if (known_shift) {
                         // slot offsets are (-1, 0, 1) on every axis here
                         const int ox = slot / 9 - 1, oy = (slot / 3) % 3 - 1, oz = slot % 3 - 1;
-                        ps[k] = (cx + ox < 0 ? 1 : (cx + ox >= n0 ? 2 : 0)) |
-                                (cy + oy < 0 ? 4 : (cy + oy >= n1 ? 8 : 0)) |
-                                (cz + oz < 0 ? 16 : (cz + oz >= n2 ? 32 : 0));
+                        sx[k] = cx + ox < 0 ? -Lx : (cx + ox >= n0 ? Lx : 0.0);
+                        sy[k] = cy + oy < 0 ? -Ly : (cy + oy >= n1 ? Ly : 0.0);
+                        sz[k] = cz + oz < 0 ? -Lz : (cz + oz >= n2 ? Lz : 0.0);
                     }
                 }
             }
             for (int h = h0; h < h1; ++h) {
+                if (cb == 0 && h == h0) range_of();
                 const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
                 const int ui = readlane_i(mu, h);
                 const int moli = readlane_i(mmol, h);
@@ -574,14 +601,9 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                     const int uj = pu[k];
                     bool keep = keep_k[k];
                     if (keep) {
-                        if (known_shift) {
-                            const int c6 = ps[k];
-                            const double sx = (c6 & 1) ? -Lx : ((c6 & 2) ? Lx : 0.0);
-                            const double sy = (c6 & 4) ? -Ly : ((c6 & 8) ? Ly : 0.0);
-                            const double sz = (c6 & 16) ? -Lz : ((c6 & 32) ? Lz : 0.0);
-                            keep = member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx, sy, sz,
-                                                  rl2);
-                        }
+                        if (known_shift)
+                            keep = member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx[k], sy[k],
+                                                  sz[k], rl2);
                         else
                             keep = member(make_double4(xi, yi, zi, 0.0),
                                           make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx,
@@ -597,6 +619,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                 if (lane == h) mcnt = hc;
             }
         }
+        if (ncand == 0) range_of();
         // the slot table is rewritten for the next cell
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
