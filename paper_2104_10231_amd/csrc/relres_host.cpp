@@ -799,8 +799,9 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
                             c->d_seg_tot.as<int>(), c->d_status.as<Status>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
-        HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, c->d_wpos.as<double4>(), topo,
-                                c->d_user2arow.as<int>(), s));
+        HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs,
+                                (long long)c->n + (sites ? c->n_sites : 0),
+                                c->d_wpos.as<double4>(), topo, c->d_user2arow.as<int>(), s));
         HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->ga.waves, sites ? c->gs.waves : 0, topo,
                              c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),

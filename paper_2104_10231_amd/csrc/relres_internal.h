@@ -170,8 +170,9 @@ hipError_t launch_scan(GridDev* grids_dev, int ngrids, int ncell_a, int ncell_s,
                        Status* st, hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);
-hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,
-                           TopoDev topo, int* user2arow, hipStream_t s);
+// members: rows of both grids (picks cells per wave)
+hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, long long members,
+                           const double4* wpos, TopoDev topo, int* user2arow, hipStream_t s);
 // per_wave: one wave per home cell (small cells) instead of one block per cell
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
                         TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,

@@ -115,13 +115,42 @@ __device__ __forceinline__ void count_wave(bool flag, unsigned* count)
         atomicAdd(count, (unsigned)__popcll(m));
 }
 
+// A slot in cell r of `count` for every lane with `want` set.  Lanes of the
+// wave that share a cell take consecutive slots after one atomic add by the
+// first of them, so a cell sees one atomic per wave rather than one per atom
+// (same-address atomics serialise).  Slot order within a cell is arbitrary;
+// the cell sort orders members by caller index afterwards.
+__device__ __forceinline__ int claim_slot(int* count, int r, bool want)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t todo = __ballot(want);
+    int lead = 0, rank = 0, n_lead = 0;
+    while (todo != 0ull) {
+        const int l = __ffsll((long long)todo) - 1;
+        const int rl = __builtin_amdgcn_readlane(r, l);
+        const uint64_t grp = todo & __ballot(r == rl);
+        if ((grp >> lane) & 1ull) {
+            lead = l;
+            rank = __popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == l) n_lead = __popcll(grp);
+        todo &= ~grp;
+    }
+    // one atomic instruction for all the groups (their cells are distinct)
+    int got = 0;
+    if (n_lead > 0) got = atomicAdd(&count[r], n_lead);
+    return __shfl(got, lead) + rank;
+}
+
 __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
                       const GridDev* __restrict__ grids, double4* __restrict__ wpos,
                       int2* __restrict__ key_a, int2* __restrict__ key_s, Status* __restrict__ st,
                       int check_moved)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    // every lane takes part in the wave's slot claims; lanes past n only vote
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i0 < n;
+    const int i = in ? i0 : n - 1;
     const int sy = topo.sys ? topo.sys[i] : 0;
     double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
     if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
@@ -131,28 +160,31 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
     const GridDev& ga = grids[0];
     const GeomDev& G = ga.geom[sy];
     if (check_moved)   // displacement since the previous build (same boxes and skins)
-        count_wave(image_dist2(x, y, z, wpos[i], G.box) > G.half_skin2, &st->moved);
+        count_wave(in && image_dist2(x, y, z, wpos[i], G.box) > G.half_skin2, &st->moved);
     const double wx = wrap_coord(x, G.box[0]), wy = wrap_coord(y, G.box[1]),
                  wz = wrap_coord(z, G.box[2]);
-    wpos[i] = make_double4(wx, wy, wz, 0.0);
+    if (in) wpos[i] = make_double4(wx, wy, wz, 0.0);
     {
         const int lin = (cell_coord(wx, G.inv_cell[0], G.n[0]) * G.n[1] +
                          cell_coord(wy, G.inv_cell[1], G.n[1])) * G.n[2] +
                         cell_coord(wz, G.inv_cell[2], G.n[2]);
         const int r = gbl(ga.rank_of_lin)[G.cell_base + lin];
-        key_a[i] = make_int2(r, atomicAdd(&ga.count[r], 1));
+        const int slot = claim_slot(ga.count, r, in);
+        if (in) key_a[i] = make_int2(r, slot);
     }
-    if (topo.hybrid[topo.types[i]]) {
+    const bool hyb = in && topo.hybrid[topo.types[i]] != 0;
+    int rs = -1;
+    if (hyb) {
         const GridDev& gs = grids[1];
         const GeomDev& H = gs.geom[sy];
         const int lin = (cell_coord(wx, H.inv_cell[0], H.n[0]) * H.n[1] +
                          cell_coord(wy, H.inv_cell[1], H.n[1])) * H.n[2] +
                         cell_coord(wz, H.inv_cell[2], H.n[2]);
-        const int r = gbl(gs.rank_of_lin)[H.cell_base + lin];
-        key_s[i] = make_int2(r, atomicAdd(&gs.count[r], 1));
-    } else {
-        key_s[i] = make_int2(-1, -1);
+        rs = gbl(gs.rank_of_lin)[H.cell_base + lin];
     }
+    // grids[1] is grids[0] again when there are no sites (no hybrid lanes then)
+    const int slot_s = claim_slot(grids[1].count, rs, hyb);
+    if (in) key_s[i] = hyb ? make_int2(rs, slot_s) : make_int2(-1, -1);
 }
 
 // Atoms now more than half the skin from their position at the last build.
@@ -316,59 +348,6 @@ __global__ void k_scatter(int n, const GridDev* __restrict__ grids, const int2* 
     if (ks.x >= 0) gbl(grids[1].user_unsorted)[gbl(grids[1].start)[ks.x] + ks.y] = i;
 }
 
-// One wave per cell: order the members of the cell by caller index (rank by
-// counting) and write the sorted position / (type, molecule) / index arrays.
-__global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int ncell_total,
-                           const double4* __restrict__ wpos, TopoDev topo,
-                           int* __restrict__ user2arow)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    const int nwaves = (gridDim.x * blockDim.x) / kWave;
-    for (int cell = wave; cell < ncell_total; cell += nwaves) {
-        const bool site = cell >= ncell_a;
-        const GridDev& g = grids[site ? 1 : 0];
-        RELRES_GLOBAL const int* gstart = gbl(g.start);
-        RELRES_GLOBAL const int* guu = gbl(g.user_unsorted);
-        RELRES_GLOBAL int* guser = gbl(g.user);
-        double4* gpos = g.pos;     // vector-type stores stay generic (no LDS use here)
-        int2* gmeta = g.meta;
-        RELRES_GLOBAL int* gcell = gbl(g.row_cell);
-        const int c = site ? cell - ncell_a : cell;
-        const int b = gstart[c];
-        const int len = gstart[c + 1] - b;
-        if (len <= kWave) {
-            // rank by counting with cross-lane reads, no memory traffic
-            const int u = lane < len ? guu[b + lane] : 0x7fffffff;
-            int r = 0;
-            for (int k = 0; k < len; ++k) r += __shfl(u, k) < u;
-            if (lane < len) {
-                const int dst = b + r;
-                guser[dst] = u;
-                gpos[dst] = wpos[u];
-                gmeta[dst] = make_int2(topo.types[u], topo.mol[u]);
-                gcell[dst] = c;
-                if (!site) user2arow[u] = dst;
-            }
-            continue;
-        }
-        for (int base = 0; base < len; base += kWave) {
-            const int t = base + lane;
-            if (t < len) {
-                const int u = guu[b + t];
-                int r = 0;
-                for (int k = 0; k < len; ++k) r += guu[b + k] < u;
-                const int dst = b + r;
-                guser[dst] = u;
-                gpos[dst] = wpos[u];
-                gmeta[dst] = make_int2(topo.types[u], topo.mol[u]);
-                gcell[dst] = c;
-                if (!site) user2arow[u] = dst;
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ double readlane_d(double v, int l)
 {
@@ -377,6 +356,88 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// Cell sort: order the members of every cell by caller index (rank by
+// counting) and write the sorted position / (type, molecule) / index / cell
+// arrays.  A wave takes kWave / G consecutive cells, one group of G lanes
+// each; a cell of at most G members is ranked within its group by cross-lane
+// reads, a larger one by the whole wave after the small ones.  G = 16 suits
+// grids of a few members per cell, G = 64 (one cell per wave) crowded ones.
+
+__device__ __forceinline__ void place_member(const GridDev& g, bool site, int c, int dst, int u,
+                                             const double4* __restrict__ wpos, const TopoDev& topo,
+                                             int* __restrict__ user2arow)
+{
+    gbl(g.user)[dst] = u;
+    g.pos[dst] = wpos[u];       // vector-type stores stay generic (no LDS use here)
+    g.meta[dst] = make_int2(topo.types[u], topo.mol[u]);
+    gbl(g.row_cell)[dst] = c;
+    if (!site) user2arow[u] = dst;
+}
+
+template <int kSortGroup>
+__global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int ncell_total,
+                           const double4* __restrict__ wpos, TopoDev topo,
+                           int* __restrict__ user2arow)
+{
+    constexpr int kSortCells = kWave / kSortGroup;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q = lane / kSortGroup, gl = lane & (kSortGroup - 1);
+    const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const int nwaves = (gridDim.x * blockDim.x) / kWave;
+    for (int c0 = wave * kSortCells; c0 < ncell_total; c0 += nwaves * kSortCells) {
+        // group q: cell c0 + q (cells past the end are empty)
+        const int cell = c0 + q;
+        const bool site = cell >= ncell_a;
+        const GridDev& g = grids[site ? 1 : 0];
+        const int c = site ? cell - ncell_a : cell;
+        int b = 0, len = 0;
+        if (cell < ncell_total) {
+            RELRES_GLOBAL const int* gstart = gbl(g.start);
+            b = gstart[c];
+            len = gstart[c + 1] - b;
+        }
+        const bool small = len <= kSortGroup;
+        const int u = (small && gl < len) ? gbl(g.user_unsorted)[b + gl] : 0x7fffffff;
+        int r = 0;
+        if constexpr (kSortGroup < kWave) {
+#pragma unroll
+            for (int k = 0; k < kSortGroup; ++k)
+                r += __shfl(u, (lane & ~(kSortGroup - 1)) + k) < u;
+        } else {
+            for (int k = 0; k < len; ++k) r += __shfl(u, k) < u;
+        }
+        if (small && gl < len) place_member(g, site, c, b + r, u, wpos, topo, user2arow);
+        // the larger cells of this wave, one at a time with the whole wave
+        for (int k = 0; k < kSortCells; ++k) {
+            const int lenk = readlane_i(len, k * kSortGroup);
+            if (lenk <= kSortGroup) continue;
+            const int cellk = c0 + k;
+            const bool sitek = cellk >= ncell_a;
+            const GridDev& gk = grids[sitek ? 1 : 0];
+            const int ck = sitek ? cellk - ncell_a : cellk;
+            const int bk = readlane_i(b, k * kSortGroup);
+            RELRES_GLOBAL const int* guu = gbl(gk.user_unsorted);
+            if (lenk <= kWave) {
+                const int v = lane < lenk ? guu[bk + lane] : 0x7fffffff;
+                int rk = 0;
+                for (int j = 0; j < lenk; ++j) rk += __shfl(v, j) < v;
+                if (lane < lenk) place_member(gk, sitek, ck, bk + rk, v, wpos, topo, user2arow);
+                continue;
+            }
+            for (int base = 0; base < lenk; base += kWave) {
+                const int t = base + lane;
+                if (t < lenk) {
+                    const int v = guu[bk + t];
+                    int rk = 0;
+                    for (int j = 0; j < lenk; ++j) rk += guu[bk + j] < v;
+                    place_member(gk, sitek, ck, bk + rk, v, wpos, topo, user2arow);
+                }
+            }
+        }
+    }
+}
+
 
 // Neighbour lists, one wave per group of kRowsPerWave consecutive member rows
 // (rows are in cell order, so a group spans one or two cells).  Work per wave
@@ -1478,15 +1539,22 @@ hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const in
     return hipGetLastError();
 }
 
-hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, const double4* wpos,
-                           TopoDev topo, int* user2arow, hipStream_t s)
+hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, long long members,
+                           const double4* wpos, TopoDev topo, int* user2arow, hipStream_t s)
 {
+    // a few members per cell (mean below 8): 4 cells per wave
+    const bool small = (long long)members < 8LL * ncell_total;
     const int waves_per_block = 4;
-    int blocks = (ncell_total + waves_per_block - 1) / waves_per_block;
+    const int cells_per_block = waves_per_block * (small ? 4 : 1);
+    int blocks = (ncell_total + cells_per_block - 1) / cells_per_block;
     if (blocks > 65535) blocks = 65535;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_cellsort, dim3(blocks), dim3(64 * waves_per_block), 0, s, grids_dev,
-                       ncell_a, ncell_total, wpos, topo, user2arow);
+    if (small)
+        hipLaunchKernelGGL(k_cellsort<16>, dim3(blocks), dim3(64 * waves_per_block), 0, s,
+                           grids_dev, ncell_a, ncell_total, wpos, topo, user2arow);
+    else
+        hipLaunchKernelGGL(k_cellsort<64>, dim3(blocks), dim3(64 * waves_per_block), 0, s,
+                           grids_dev, ncell_a, ncell_total, wpos, topo, user2arow);
     return hipGetLastError();
 }
 
