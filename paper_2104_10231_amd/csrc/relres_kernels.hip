@@ -405,7 +405,8 @@ __global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int n
             for (int k = 0; k < kSortGroup; ++k)
                 r += __shfl(u, (lane & ~(kSortGroup - 1)) + k) < u;
         } else {
-            for (int k = 0; k < len; ++k) r += __shfl(u, k) < u;
+            const int m = small ? len : 0;      // one cell per wave: len is uniform
+            for (int k = 0; k < m; ++k) r += __shfl(u, k) < u;
         }
         if (small && gl < len) place_member(g, site, c, b + r, u, wpos, topo, user2arow);
         // the larger cells of this wave, one at a time with the whole wave
