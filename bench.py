@@ -483,7 +483,7 @@ def batch_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--rebuild-every", type=int, default=10)
     ap.add_argument("--workload", default="neopentane_20480",
