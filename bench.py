@@ -389,9 +389,15 @@ def batch_bench(args):
     rr = make(b.whole, 32, args.pair_math)
     rr.set_systems(b.offsets)
     rr.set_skins(b.skins)
+    rr.build_lists(pos, b.boxes)
+    tuned = None
     if args.lanes:
         rr.set_launch(*args.lanes)
-    rr.build_lists(pos, b.boxes)
+    elif not args.no_tune:
+        # setup, outside the timed region: every list and force kernel shape
+        # timed on this batch, the fastest kept
+        tuned = rr.autotune(pos, b.boxes, reps=2)
+        log(f"[bench] autotune: {tuned}")
     F = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     E = torch.empty((b.nsys, 3), dtype=torch.float64, device="cuda")
     W = torch.empty((b.nsys, 6), dtype=torch.float64, device="cuda")
@@ -466,7 +472,11 @@ def batch_bench(args):
                    "rebuild_every": every,
                    "forces": "fp32", "energy_virial": "fp64 per replica",
                    "parallelism": "single GPU",
-                   "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)"},
+                   "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)",
+                   "tuned": None if tuned is None else {
+                       k: tuned[k] for k in ("rows_atom", "rows_site", "cand_per_lane",
+                                             "lanes_atom", "lanes_site", "build_us",
+                                             "build_us_auto", "force_us", "force_us_auto")}},
         "sequential": None if seq is None else {
             "value": seq, "ms_per_step": dt_s * 1e3 / (cycles * every),
             "what": "one context per replica, launched replica after replica"},
@@ -504,6 +514,8 @@ def main():
                     help="dynamics workload (NVT hexane, RelRes vs conventional) instead")
     ap.add_argument("--md-equil", type=int, default=2000, help="--md: untimed equilibration steps")
     ap.add_argument("--md-steps", type=int, default=10000, help="--md: timed production steps")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="--batch: keep the automatic kernel shapes (no autotuning)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch workload only: skip the one-context-per-replica comparison")
     ap.add_argument("--batch", action="store_true",

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RELRES_ABI_VERSION 3
+#define RELRES_ABI_VERSION 4
 
 #define RELRES_OK                   0
 #define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
@@ -375,6 +375,39 @@ int relres_get_pairs(relres_ctx *ctx, int which, int *pairs_host, long long cap,
  * last build (about 4 entries per lane, 8 or 16 in launches that fill the
  * GPU many times over).                                                    */
 int relres_set_launch(relres_ctx *ctx, int lanes_atom, int lanes_site);
+
+/* Shape of the list-build kernel: home rows per wavefront for the atom grid
+ * and for the site grid (1..16, 0 = automatic: 8, or 16 in launches of many
+ * waves, fewer in small launches) and candidates held per lane (2 or 4, 0 =
+ * automatic: 4 when every wave of the launch is resident at once).  Takes
+ * effect at the next build; the lists themselves (pairs and their order in a
+ * row) do not depend on it.  Overrides persist until changed.               */
+int relres_set_list_launch(relres_ctx *ctx, int rows_atom, int rows_site, int cand_per_lane);
+
+/* Result of relres_autotune (host struct).  Chosen shapes (resolved, never
+ * 0), mean device times of the chosen and of the automatic shapes, and the
+ * number of shapes timed.                                                   */
+typedef struct relres_tune {
+    int rows_atom, rows_site, cand_per_lane;   /* list kernel                 */
+    int lanes_atom, lanes_site;                /* force kernel                */
+    int trials;
+    double build_us, build_us_auto;            /* one list build              */
+    double force_us, force_us_auto;            /* one force call with E and W */
+} relres_tune;
+
+/* Autotuner for the caller's own workload: times list builds for every list
+ * kernel shape (rows per wave 4/8/16 for each grid x 2/4 candidates per
+ * lane, and the automatic shape) on the device positions pos and box(es),
+ * keeps the fastest, rebuilds, then times force calls (with energy and
+ * virial) for lanes per row 2..16 (atom rows) x 2..32 (hybrid rows) and the
+ * automatic choice, and keeps the fastest.  Each shape: one untimed call,
+ * then reps (1..1000) timed with HIP events on `stream`.  Leaves valid lists
+ * built from pos and the chosen shapes set (as by relres_set_list_launch and
+ * relres_set_launch).  Synchronises; allocates temporary force, energy and
+ * virial buffers; must not run on a capturing stream (RELRES_ERR_STATE).
+ * Resets the relres_get_timing tallies.  Writes *out.                      */
+int relres_autotune(relres_ctx *ctx, const double *pos, const double *box, void *stream, int reps,
+                    relres_tune *out);
 
 /* With enable != 0, HIP events are recorded on the caller's stream right
  * before and after every launch of the force kernel (which includes the

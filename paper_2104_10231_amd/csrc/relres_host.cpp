@@ -305,6 +305,9 @@ struct relres_ctx {
     DBuf d_partials, d_epoch;
     int lanes_a = 0, lanes_b = 0;        // caller override, 0 = automatic
     int auto_la = 4, auto_lb = 16;
+    // list kernel shape: rows per wave (atom, site grids) and candidates per
+    // lane; caller or autotuner override, 0 = automatic
+    int rows_a = 0, rows_s = 0, cand = 0;
 
     relres_stats stats{};
     long long alloc_generation = 0;
@@ -446,10 +449,12 @@ void list_radii(const relres_ctx* c, std::vector<double>& skin, std::vector<doub
 // fewer or more rows per wave (50 µs at 8, 58 µs at 16); 6000-atom hexane
 // dynamics (1000 waves) takes 5 % less time per step at 2 / 1 rows than at
 // 8 / 8; the 256-replica batch (1.44 M rows) runs 3 % faster at 16 than at
-// 8.  The environment variable RELRES_LIST_ROWS="atom,site" overrides the
-// choice (for tuning runs).
-int list_rows_per_wave(bool site, long long members, long long launch_rows)
+// 8.  A caller override (relres_set_list_launch, relres_autotune) comes
+// first; then the environment variable RELRES_LIST_ROWS="atom,site" (for
+// tuning runs).
+int list_rows_per_wave(bool site, long long members, long long launch_rows, int rows)
 {
+    if (rows >= 1 && rows <= kRowsPerWave) return rows;
     if (const char* e = std::getenv("RELRES_LIST_ROWS")) {
         int a = 0, b = 0;
         if (std::sscanf(e, "%d,%d", &a, &b) == 2) {
@@ -464,10 +469,11 @@ int list_rows_per_wave(bool site, long long members, long long launch_rows)
     return r;
 }
 
-// launch_rows: rows of both grids (they share the list-kernel launch)
+// launch_rows: rows of both grids (they share the list-kernel launch);
+// rows_per_wave: of the list kernel, 0 = automatic
 int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector<double>& skin_sys,
                int nsys, const double* boxes, const int* members_sys, long long launch_rows,
-               long long* gen)
+               int rows_per_wave, long long* gen)
 {
     // cells per axis of every system: a cell edge is at least the list radius
     // (with a margin far above rounding), so every pair within rl lies in
@@ -562,7 +568,7 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
     // rows and list-kernel waves of every grid
     long long all_members = 0;
     for (int sy = 0; sy < nsys; ++sy) all_members += members_sys[sy];
-    g.rpw = list_rows_per_wave(g.site, all_members, launch_rows);
+    g.rpw = list_rows_per_wave(g.site, all_members, launch_rows, rows_per_wave);
     std::vector<GeomDev> geom(nsys);
     int rows = 0, waves = 0;
     double densest = 0.0;
@@ -760,10 +766,10 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     }
     const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
     const long long launch_rows = (long long)c->n + c->n_sites;
-    TRY(setup_grid(c->ga, rla, skin_sys, ns, box, c->atoms_sys.data(), launch_rows,
+    TRY(setup_grid(c->ga, rla, skin_sys, ns, box, c->atoms_sys.data(), launch_rows, c->rows_a,
                    &c->alloc_generation));
     if (sites)
-        TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), launch_rows,
+        TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), launch_rows, c->rows_s,
                        &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
     const void* wpos_before = c->d_wpos.p;
@@ -805,7 +811,7 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->ga.waves, sites ? c->gs.waves : 0, topo,
                              c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
-                             c->d_status.as<Status>(), lists_per_wave(c), s));
+                             c->d_status.as<Status>(), lists_per_wave(c), c->cand, s));
         HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
         // in a captured graph the copy runs at every replay; the caller
         // synchronises after the replay before relres_check_lists
@@ -867,14 +873,14 @@ int examine_status(relres_ctx* c)
         std::vector<double> skin_sys, rla, rls;
         list_radii(c, skin_sys, rla, rls);
         TRY(setup_grid(c->ga, rla, skin_sys, c->nsys, c->boxes.data(), c->atoms_sys.data(),
-                       (long long)c->n + c->n_sites, &c->alloc_generation));
+                       (long long)c->n + c->n_sites, c->rows_a, &c->alloc_generation));
     }
     if (ov_s) {
         c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
         std::vector<double> skin_sys, rla, rls;
         list_radii(c, skin_sys, rla, rls);
         TRY(setup_grid(c->gs, rls, skin_sys, c->nsys, c->boxes.data(), c->sites_sys.data(),
-                       (long long)c->n + c->n_sites, &c->alloc_generation));
+                       (long long)c->n + c->n_sites, c->rows_s, &c->alloc_generation));
     }
     c->stats.regrows++;
     c->lanes_stale = true;
@@ -1334,6 +1340,131 @@ int relres_set_launch(relres_ctx* c, int lanes_atom, int lanes_site)
     c->lanes_a = lanes_atom;
     c->lanes_b = lanes_site;
     return RELRES_OK;
+}
+
+int relres_set_list_launch(relres_ctx* c, int rows_atom, int rows_site, int cand_per_lane)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    for (int v : {rows_atom, rows_site})
+        if (v < 0 || v > kRowsPerWave)
+            return fail(RELRES_ERR_ARG, "rows per wave must be 0 (automatic) or 1..%d", kRowsPerWave);
+    if (cand_per_lane != 0 && cand_per_lane != 2 && cand_per_lane != 4)
+        return fail(RELRES_ERR_ARG, "candidates per lane must be 0 (automatic), 2 or 4");
+    c->rows_a = rows_atom;
+    c->rows_s = rows_site;
+    c->cand = cand_per_lane;
+    return RELRES_OK;
+}
+
+int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* stream, int reps,
+                    relres_tune* out)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!out) return fail(RELRES_ERR_ARG, "out is NULL");
+    if (!box) return fail(RELRES_ERR_ARG, "box is NULL");
+    if (c->n > 0 && !pos) return fail(RELRES_ERR_ARG, "pos is NULL");
+    if (reps < 1 || reps > 1000) return fail(RELRES_ERR_ARG, "reps must be 1..1000");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &capture));
+    if (capture != hipStreamCaptureStatusNone)
+        return fail(RELRES_ERR_STATE, "relres_autotune cannot run on a capturing stream");
+    std::memset(out, 0, sizeof *out);
+    const bool sites = c->n_sites > 0;
+    const bool was_timing = c->timing;
+    TRY(relres_get_timing(c, nullptr, nullptr, nullptr, nullptr));   // start from empty tallies
+    c->timing = true;
+    int rc = RELRES_OK;
+    DBuf f, e, w;
+    long long gen = 0;
+    // mean device time of `reps` timed builds (after one untimed) in us
+    auto time_builds = [&](double& us) -> int {
+        TRY(build_checked(c, pos, box, s));
+        TRY(relres_get_timing(c, nullptr, nullptr, nullptr, nullptr));
+        for (int r = 0; r < reps; ++r) TRY(build_checked(c, pos, box, s));
+        double ms = 0.0;
+        long long calls = 0;
+        TRY(relres_get_timing(c, nullptr, nullptr, &ms, &calls));
+        us = calls > 0 ? 1e3 * ms / (double)calls : 0.0;
+        return RELRES_OK;
+    };
+    auto time_forces = [&](double& us) -> int {
+        void* fp = f.p;
+        TRY(relres_forces(c, pos, fp, e.as<double>(), w.as<double>(), s));
+        TRY(relres_get_timing(c, nullptr, nullptr, nullptr, nullptr));
+        for (int r = 0; r < reps; ++r) TRY(relres_forces(c, pos, fp, e.as<double>(), w.as<double>(), s));
+        double ms = 0.0;
+        long long calls = 0;
+        TRY(relres_get_timing(c, &ms, &calls, nullptr, nullptr));
+        us = calls > 0 ? 1e3 * ms / (double)calls : 0.0;
+        return RELRES_OK;
+    };
+    auto run = [&]() -> int {
+        if (c->n == 0) return RELRES_OK;
+        // list kernel: rows per wave of each grid and candidates per lane;
+        // the automatic choice first, as the reference point
+        struct ListShape { int ra, rs, k; };
+        std::vector<ListShape> shapes{{0, 0, 0}};
+        for (int k : {2, 4})
+            for (int ra : {4, 8, 16})
+                for (int rs : {4, 8, 16})
+                    if (sites || rs == ra) shapes.push_back({ra, rs, k});
+        double best = 0.0;
+        ListShape pick{0, 0, 0};
+        for (size_t i = 0; i < shapes.size(); ++i) {
+            TRY(relres_set_list_launch(c, shapes[i].ra, shapes[i].rs, shapes[i].k));
+            double us = 0.0;
+            TRY(time_builds(us));
+            if (i == 0) out->build_us_auto = us;
+            if (i == 0 || us < best) {
+                best = us;
+                pick = shapes[i];
+            }
+            out->trials++;
+        }
+        TRY(relres_set_list_launch(c, pick.ra, pick.rs, pick.k));
+        TRY(build_checked(c, pos, box, s));
+        out->build_us = best;
+        out->rows_atom = c->ga.rpw;
+        out->rows_site = sites ? c->gs.rpw : 0;
+        out->cand_per_lane = list_candidates(c->ga.waves + (sites ? c->gs.waves : 0), c->cand);
+        // force kernel: lanes per atom row and per hybrid row
+        const size_t fb = (size_t)c->n * 3 * (c->precision == 32 ? sizeof(float) : sizeof(double));
+        TRY(ensure(f, fb, &gen));
+        TRY(ensure(e, sizeof(double) * 3 * (size_t)c->nsys, &gen));
+        TRY(ensure(w, sizeof(double) * 6 * (size_t)c->nsys, &gen));
+        std::vector<std::pair<int, int>> lanes{{0, 0}};
+        for (int la : {2, 4, 8, 16})
+            for (int lb : {2, 4, 8, 16, 32})
+                if (sites || lb == 16) lanes.push_back({la, lb});
+        std::pair<int, int> lpick{0, 0};
+        for (size_t i = 0; i < lanes.size(); ++i) {
+            TRY(relres_set_launch(c, lanes[i].first, lanes[i].second));
+            double us = 0.0;
+            TRY(time_forces(us));
+            if (i == 0) out->force_us_auto = us;
+            if (i == 0 || us < best) {
+                best = us;
+                lpick = lanes[i];
+            }
+            out->trials++;
+        }
+        TRY(relres_set_launch(c, lpick.first, lpick.second));
+        out->force_us = best;
+        out->lanes_atom = lpick.first ? lpick.first : c->auto_la;
+        out->lanes_site = lpick.second ? lpick.second : c->auto_lb;
+        return RELRES_OK;
+    };
+    rc = run();
+    const hipError_t sync = hipStreamSynchronize(s);   // temporaries are idle before release
+    release(f);
+    release(e);
+    release(w);
+    (void)relres_get_timing(c, nullptr, nullptr, nullptr, nullptr);
+    c->timing = was_timing;
+    if (rc == RELRES_OK && sync != hipSuccess)
+        rc = fail(RELRES_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(sync));
+    return rc;
 }
 
 int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy, double* virial,

@@ -174,9 +174,12 @@ hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const in
 hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, long long members,
                            const double4* wpos, TopoDev topo, int* user2arow, hipStream_t s);
 // per_wave: one wave per home cell (small cells) instead of one block per cell
+// Candidates per lane of the row-group list kernel (2 or 4) for a launch of
+// total_waves waves; cand = 2 or 4 forces the value, 0 chooses it.
+int list_candidates(int total_waves, int cand);
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
                         TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
-                        bool per_wave, hipStream_t s);
+                        bool per_wave, int cand, hipStream_t s);
 // cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares} of every type pair, or
 // per_pair: the distances of each type pair come from a.pcut32 / a.pcut64
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, bool per_pair, int pair_math,

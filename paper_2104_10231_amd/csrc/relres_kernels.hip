@@ -1559,22 +1559,28 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, lon
     return hipGetLastError();
 }
 
+int list_candidates(int total_waves, int cand)
+{
+    if (cand == 2 || cand == 4) return cand;
+    // RELRES_LIST_CANDIDATES=2|4 overrides the automatic choice (tuning runs)
+    if (const char* e = std::getenv("RELRES_LIST_CANDIDATES")) {
+        if (e[0] == '2' && e[1] == 0) return 2;
+        if (e[0] == '4' && e[1] == 0) return 4;
+    }
+    // all waves resident at once (about 3 per SIMD): more candidates per lane
+    return total_waves <= kResidentListWaves ? 4 : 2;
+}
+
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
                         TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
-                        bool per_wave, hipStream_t s)
+                        bool per_wave, int cand, hipStream_t s)
 {
     if (per_wave) {
         const int total = waves_a + waves_s;
         if (total == 0) return hipSuccess;
         const int mx = topo.excl_off ? topo.max_excl : 0;
         const size_t dyn = sizeof(int) * 4 * kRowsPerWave * (size_t)mx;
-        // all waves resident at once (about 3 per SIMD): more candidates per
-        // lane; RELRES_LIST_CANDIDATES=2|4 overrides the choice (tuning runs)
-        bool k4 = total <= kResidentListWaves;
-        if (const char* e = std::getenv("RELRES_LIST_CANDIDATES")) {
-            if (e[0] == '2' && e[1] == 0) k4 = false;
-            if (e[0] == '4' && e[1] == 0) k4 = true;
-        }
+        const bool k4 = list_candidates(total, cand) == 4;
         if (k4)
             hipLaunchKernelGGL(k_lists_wave<4>, dim3((total + 3) / 4), dim3(256), dyn, s,
                                grids_dev, waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);

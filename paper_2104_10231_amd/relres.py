@@ -55,6 +55,14 @@ class Stats(ctypes.Structure):
                 ("moved_at_last_build", ctypes.c_longlong)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("rows_atom", ctypes.c_int), ("rows_site", ctypes.c_int),
+                ("cand_per_lane", ctypes.c_int), ("lanes_atom", ctypes.c_int),
+                ("lanes_site", ctypes.c_int), ("trials", ctypes.c_int),
+                ("build_us", ctypes.c_double), ("build_us_auto", ctypes.c_double),
+                ("force_us", ctypes.c_double), ("force_us_auto", ctypes.c_double)]
+
+
 # exported symbol -> (restype, argtypes); mirrors include/relres.h
 SIGNATURES = {
     "relres_abi_version": (ctypes.c_int, []),
@@ -79,6 +87,10 @@ SIGNATURES = {
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "relres_set_list_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int]),
+    "relres_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Tune)]),
     "relres_set_systems": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "relres_set_skins": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
     "relres_set_pair_params": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p,
@@ -380,6 +392,26 @@ class RelRes:
     def set_launch(self, lanes_atom: int = 0, lanes_site: int = 0):
         _check(self._lib.relres_set_launch(self._ctx, int(lanes_atom), int(lanes_site)),
                "relres_set_launch")
+
+    def set_list_launch(self, rows_atom: int = 0, rows_site: int = 0, cand_per_lane: int = 0):
+        """List-kernel shape for the next builds (0 = automatic)."""
+        _check(self._lib.relres_set_list_launch(self._ctx, int(rows_atom), int(rows_site),
+                                                int(cand_per_lane)), "relres_set_list_launch")
+
+    def autotune(self, pos: torch.Tensor, box, reps: int = 3, stream=None) -> dict:
+        """Time every list-kernel and force-kernel shape on these positions and
+        box(es), keep the fastest (lists rebuilt from pos); returns the choice
+        and the mean device times (us) of the chosen and automatic shapes."""
+        pos = self._pos(pos)
+        bx = np.asarray(box, dtype=np.float64).reshape(-1)
+        if bx.shape[0] != 3 * self.nsys:
+            raise ValueError(f"box needs {3 * self.nsys} values ({self.nsys} systems x 3)")
+        b = (ctypes.c_double * bx.shape[0])(*bx.tolist())
+        t = Tune()
+        _check(self._lib.relres_autotune(self._ctx, pos.data_ptr() if self.n else None, b,
+                                         _stream(stream), int(reps), ctypes.byref(t)),
+               "relres_autotune")
+        return {k: getattr(t, k) for k, _ in Tune._fields_}
 
     def stats(self) -> dict:
         s = Stats()

@@ -42,25 +42,28 @@ def test_exports_every_declared_function(lib):
 
 
 def test_struct_layout_matches_header(tmp_path):
-    from paper_2104_10231_amd.relres import Params, Stats
+    from paper_2104_10231_amd.relres import Params, Stats, Tune
     c = tmp_path / "sz.c"
     c.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "relres.h"\n'
-                 'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                 'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                  ' sizeof(relres_params), sizeof(relres_stats), offsetof(relres_params, mix),'
                  ' offsetof(relres_params, no_shift), offsetof(relres_params, cut_type),'
                  ' offsetof(relres_params, cut_pair),'
                  ' offsetof(relres_stats, builds), offsetof(relres_stats, box),'
-                 ' offsetof(relres_stats, moved_at_last_build)); return 0;}\n')
+                 ' offsetof(relres_stats, moved_at_last_build), sizeof(relres_tune),'
+                 ' offsetof(relres_tune, trials), offsetof(relres_tune, force_us_auto));'
+                 ' return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
     got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
     assert got == [ctypes.sizeof(Params), ctypes.sizeof(Stats), Params.mix.offset,
                    Params.no_shift.offset, Params.cut_type.offset, Params.cut_pair.offset,
-                   Stats.builds.offset, Stats.box.offset, Stats.moved_at_last_build.offset]
+                   Stats.builds.offset, Stats.box.offset, Stats.moved_at_last_build.offset,
+                   ctypes.sizeof(Tune), Tune.trials.offset, Tune.force_us_auto.offset]
 
 
 def test_version_and_error_strings(lib):
-    assert lib.relres_abi_version() == 3
+    assert lib.relres_abi_version() == 4
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, 1):
         s = lib.relres_strerror(code).decode()
         assert s and s != "unknown error"
@@ -111,6 +114,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.relres_build_lists(None, None, None, None) == -1
     assert lib.relres_forces(None, None, None, None, None, None) == -1
     assert lib.relres_set_launch(None, 4, 4) == -1
+    assert lib.relres_set_list_launch(None, 8, 8, 4) == -1
+    assert lib.relres_autotune(None, None, None, None, 3, None) == -1
     assert lib.relres_set_bonded(None, 0, None, None, None, 0, None, None, None, 0, None, None,
                                  None, None, 0, None, 0.5) == -1
     assert lib.relres_bonded_forces(None, None, None, None, None, None) == -1

@@ -1,0 +1,110 @@
+"""Autotuner (relres_autotune) and explicit list-kernel shapes
+(relres_set_list_launch).
+
+The tuner times every list-kernel shape and every force-kernel lane split on
+the caller's positions, keeps the fastest and leaves lists built from those
+positions: their pair sets must equal the oracle's, and the forces, energies
+and virials computed afterwards must meet the usual FP32 bars against the
+oracle.  A list-kernel shape changes neither the pairs nor their order in a
+row, so at a fixed lane split every shape gives bitwise the same forces.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from _util import make_relres, pair_set, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+LIST_SHAPES = 1 + 2 * 9          # automatic + (2 or 4 candidates) x rows {4, 8, 16}^2
+LANE_SPLITS = 1 + 4 * 5          # automatic + atom lanes {2..16} x hybrid lanes {2..32}
+
+
+def _forces(rr, p):
+    return [t.double().cpu().numpy() for t in rr.forces(p)]
+
+
+def _check_result(t):
+    assert t["trials"] == LIST_SHAPES + LANE_SPLITS
+    assert 1 <= t["rows_atom"] <= 16 and 1 <= t["rows_site"] <= 16
+    assert t["cand_per_lane"] in (2, 4)
+    for v in (t["lanes_atom"], t["lanes_site"]):
+        assert v >= 1 and v & (v - 1) == 0
+    assert 0.0 < t["build_us"] <= t["build_us_auto"]
+    assert 0.0 < t["force_us"] <= t["force_us_auto"]
+
+
+def test_autotune_keeps_the_physics():
+    import torch
+    s = w.propane_liquid(5).replace(precision=32)
+    rr = make_relres(s, 32)
+    p = torch.from_numpy(s.pos).cuda()
+    print(f"[autotune] propane N={s.n}", flush=True)
+    rr.build_lists(p, s.box)
+    t = rr.autotune(p, s.box, reps=2)
+    print(f"[autotune] {t}", flush=True)
+    _check_result(t)
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(s, which))
+    F, E, W = _forces(rr, p)
+    rr.close()
+    Fr, Er, Wr = oracle.compute(s)
+    assert rel_rms(F, Fr) <= 1e-5
+    assert abs(E[0] - Er[0]) <= 1e-7 * abs(Er[0])
+    assert np.abs(W - Wr).max() <= 1e-7 * np.abs(Wr).max()
+
+
+def test_autotune_on_a_batch_of_replicas():
+    import torch
+    b = w.replica_batch(6, n_systems=5, min_atoms=300, max_atoms=900, total_atoms=2500)
+    rr = make_relres(b.whole, 32)
+    rr.set_systems(b.offsets)
+    p = torch.from_numpy(b.whole.pos).cuda()
+    print(f"[autotune] batch N={b.whole.n} systems={b.nsys}", flush=True)
+    rr.build_lists(p, b.boxes)
+    pairs0 = [pair_set(rr.pairs(which)) for which in (0, 1)]
+    F0, E0, W0 = _forces(rr, p)
+    t = rr.autotune(p, b.boxes, reps=2)
+    print(f"[autotune] {t}", flush=True)
+    _check_result(t)
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pairs0[which]
+    F, E, W = _forces(rr, p)
+    rr.close()
+    assert rel_rms(F, F0) <= 1e-5
+    assert np.abs(E - E0).max() <= 1e-7 * np.abs(E0).max()
+    assert np.abs(W - W0).max() <= 1e-7 * np.abs(W0).max()
+
+
+@pytest.mark.parametrize("shape", [(4, 16, 2), (16, 4, 4), (1, 2, 2)])
+def test_list_shape_does_not_change_the_lists(shape):
+    import torch
+    s = w.hexane_liquid(3, n_mol=150, density=0.012)
+    rr = make_relres(s, 32)
+    rr.set_launch(4, 8)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)
+    base = _forces(rr, p)
+    rr.set_list_launch(*shape)
+    rr.build_lists(p, s.box)
+    got = _forces(rr, p)
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(s, which))
+    rr.close()
+    for x, y in zip(got, base):
+        assert np.array_equal(x, y)
+
+
+def test_list_shape_arguments_are_checked():
+    import torch
+    from paper_2104_10231_amd.relres import RelResError
+    s = w.propane_liquid(1)
+    rr = make_relres(s, 32)
+    for bad in ((17, 8, 0), (8, -1, 0), (8, 8, 3)):
+        with pytest.raises(RelResError):
+            rr.set_list_launch(*bad)
+    p = torch.from_numpy(s.pos).cuda()
+    with pytest.raises(RelResError):
+        rr.autotune(p, s.box, reps=0)
+    rr.close()
