@@ -494,7 +494,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--rebuild-every", type=int, default=10)
     ap.add_argument("--workload", default="neopentane_20480",
                     choices=["neopentane_20480", "propane_1500", "copolymer_98304"])
