@@ -1887,15 +1887,16 @@ namespace {
 // atom moved more than half the skin since the previous build.
 int md_rebuild(relres_ctx* c, const double* pos, hipStream_t s, bool check)
 {
-    if (check) {
+    // the displacement flag of the steps since the previous build is copied
+    // ahead of the build and read once the build has been waited for: one
+    // host wait per rebuild, not two
+    if (check)
         HIP_TRY(hipMemcpyAsync(c->h_stale, c->d_md_stale.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (*c->h_stale)
-            return fail(RELRES_ERR_STALE_LISTS, "an atom moved more than half the skin between list "
-                        "builds: rebuild more often or use a larger skin");
-    }
     const double box[3] = {c->box[0], c->box[1], c->box[2]};
     TRY(build_checked(c, pos, box, s));
+    if (check && *c->h_stale)
+        return fail(RELRES_ERR_STALE_LISTS, "an atom moved more than half the skin between list "
+                    "builds: rebuild more often or use a larger skin");
     c->warn_pending = false;          // dynamics checks the displacements itself
     HIP_TRY(hipMemcpyAsync(c->d_md_xref.p, pos, sizeof(double) * 3 * c->n, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_clear_words((unsigned long long*)c->d_md_stale.p, 8, s));
