@@ -405,7 +405,9 @@ typedef struct relres_tune {
  * built from pos and the chosen shapes set (as by relres_set_list_launch and
  * relres_set_launch).  Synchronises; allocates temporary force, energy and
  * virial buffers; must not run on a capturing stream (RELRES_ERR_STATE).
- * Resets the relres_get_timing tallies.  Writes *out.                      */
+ * Resets the relres_get_timing tallies.  Writes *out.  On an error the
+ * shapes set before the call are restored; build the lists again before the
+ * next force call.                                                          */
 int relres_autotune(relres_ctx *ctx, const double *pos, const double *box, void *stream, int reps,
                     relres_tune *out);
 

@@ -1455,7 +1455,15 @@ int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* s
         out->lanes_site = lpick.second ? lpick.second : c->auto_lb;
         return RELRES_OK;
     };
+    const int saved[5] = {c->rows_a, c->rows_s, c->cand, c->lanes_a, c->lanes_b};
     rc = run();
+    if (rc != RELRES_OK) {            // the caller's shapes again, not a trial's
+        c->rows_a = saved[0];
+        c->rows_s = saved[1];
+        c->cand = saved[2];
+        c->lanes_a = saved[3];
+        c->lanes_b = saved[4];
+    }
     const hipError_t sync = hipStreamSynchronize(s);   // temporaries are idle before release
     release(f);
     release(e);
