@@ -474,3 +474,112 @@ def test_cutoff_order_is_validated():
     s = w.two_atoms(5.0).replace(rs_in=6.5, rs_out=6.0)
     with pytest.raises(ValueError):
         oracle.setup_table(s)
+
+
+# ----------------------------------------------------------------------------
+# the FG/CG energy split (reported as energy[1], energy[2]) against closed
+# forms: Eq. 17 for f_s-^FG and f_c-^CG, the corrected Eq. 18 for f_s+^CG and
+# Eq. 19 for Gamma_c-; none of these goes through the oracle's solver
+# ----------------------------------------------------------------------------
+
+def _split_reference(eps_fg, sig_fg, eps_cg, sig_cg, cut, r, shift=True):
+    """Closed-form FG and CG parts of Eq. 20 at distance r (one pair).
+
+    FG part: u_FG(r) - f_s-(Dr_s) below r_s-, f_s-(d) - f_s-(Dr_s) on
+    [r_s-, r_s+), 0 beyond.  CG part (zero for pairs with an ordinary site,
+    Eq. 14): gamma_0+ - Gamma_c- below r_s-, f_s+(d) - Gamma_c- on
+    [r_s-, r_s+), u_CG(r) - Gamma_c- on [r_s+, r_c-), f_c-(d) - Gamma_c- on
+    [r_c-, r_c+), 0 beyond; under shift no the last two subtract nothing.
+    """
+    rsi, rso, rci, rco = cut
+    Ds, Dc = rso - rsi, rco - rci
+    fs = eq17(lj_sym(eps_fg, sig_fg, rsi), Ds)
+    fs_end = polyval(fs, Ds)
+    if r < rsi:
+        efg = lj_sym(eps_fg, sig_fg, r)[0] - fs_end
+    elif r < rso:
+        efg = polyval(fs, r - rsi) - fs_end
+    else:
+        efg = 0.0
+    if eps_cg == 0.0:
+        return efg, 0.0
+    sp = eq18(lj_sym(eps_cg, sig_cg, rso), Ds)
+    cm = eq17(lj_sym(eps_cg, sig_cg, rci), Dc)
+    gam_c = polyval(cm, Dc)
+    g_out = gam_c if shift else 0.0
+    if r < rsi:
+        ecg = sp[0] - gam_c
+    elif r < rso:
+        ecg = polyval(sp, r - rsi) - gam_c
+    elif r < rci:
+        ecg = lj_sym(eps_cg, sig_cg, r)[0] - g_out
+    elif r < rco:
+        ecg = polyval(cm, r - rci) - g_out
+    else:
+        ecg = 0.0
+    return efg, ecg
+
+
+# distances inside every zone of Eq. 20, plus points next to each boundary
+_SPLIT_R = (3.1, 4.4, 5.49, 5.5, 5.62, 5.8, 5.99, 6.0, 6.7, 9.5, 11.99, 12.0, 12.6, 13.4, 13.99,
+            14.0, 15.5)
+
+
+@pytest.mark.parametrize("shift", [True, False])
+def test_energy_split_matches_closed_forms_per_zone(shift):
+    s = w.propane_liquid(0).replace(shift=shift)
+    tab = oracle.setup_table(s)
+    cut = (s.rs_in, s.rs_out, s.rc_in, s.rc_out)
+    r = np.array(_SPLIT_R)
+    for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)]:
+        e_fg = np.sqrt(s.eps_fg[a] * s.eps_fg[b])
+        s_fg = np.sqrt(s.sig_fg[a] * s.sig_fg[b])
+        hyb = s.eps_cg[a] > 0 and s.eps_cg[b] > 0
+        e_cg = np.sqrt(s.eps_cg[a] * s.eps_cg[b]) if hyb else 0.0
+        s_cg = np.sqrt(s.sig_cg[a] * s.sig_cg[b]) if hyb else 0.0
+        u, _, which, efg, ecg = oracle.pair(tab[a, b], r)
+        for k, x in enumerate(r):
+            rf, rc = _split_reference(e_fg, s_fg, e_cg, s_cg, cut, x, shift)
+            scale = max(1.0, abs(rf), abs(rc))
+            assert abs(efg[k] - rf) <= 1e-12 * scale, (a, b, x, efg[k], rf)
+            assert abs(ecg[k] - rc) <= 1e-12 * scale, (a, b, x, ecg[k], rc)
+        # a pair with an ordinary site carries no CG energy anywhere (Eq. 14)
+        if not hyb:
+            assert np.all(ecg == 0.0)
+        # from r_s+ on the FG part is gone and the CG part is all of Eq. 20
+        beyond = r >= s.rs_out
+        assert np.all(efg[beyond] == 0.0)
+        np.testing.assert_array_equal(ecg[beyond], u[beyond])
+
+
+def test_energy_split_constant_below_rs_minus():
+    """Below r_s- the CG part is the constant gamma_0+ - Gamma_c- (no force):
+    the same value at every distance, and the FG part alone carries the
+    textbook LJ shape there."""
+    s = w.propane_liquid(0)
+    rec = oracle.setup_table(s)[1, 1]
+    r = np.linspace(2.8, s.rs_in - 1e-9, 40)
+    u, du, which, efg, ecg = oracle.pair(rec, r)
+    assert np.all(which == 1)
+    assert np.ptp(ecg) == 0.0
+    sp0 = eq18(lj_sym(1.0, 4.6, s.rs_out), s.rs_out - s.rs_in)[0]
+    gam_c = polyval(eq17(lj_sym(1.0, 4.6, s.rc_in), s.rc_out - s.rc_in), s.rc_out - s.rc_in)
+    assert ecg[0] == pytest.approx(sp0 - gam_c, rel=1e-12)
+    ref = np.array([lj_sym(0.195, 3.75, x)[0] for x in r])
+    np.testing.assert_allclose(efg - efg[0], ref - ref[0], rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_energy_split_reference_limit_has_no_cg_part():
+    """The reference system (Sec. 2.1; r_s -> r_c, no CG interaction) puts the
+    whole energy into the FG part, in every pair and in the system total."""
+    s = w.propane_liquid(0).conventional()
+    tab = oracle.setup_table(s)
+    r = np.array([3.3, 6.0, 11.0, 12.5, 13.9, 14.2])
+    for a in range(s.ntypes):
+        for b in range(s.ntypes):
+            u, _, _, efg, ecg = oracle.pair(tab[a, b], r)
+            assert np.all(ecg == 0.0)
+            np.testing.assert_array_equal(efg, u)
+    sub = w.random_molecules(4, 60, 30.0, kind="propane", min_dist=2.9).conventional()
+    F, E, W = oracle.compute(sub)
+    assert E[2] == 0.0 and E[1] == E[0]
