@@ -24,6 +24,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+FP64_VALU_PEAK_TFLOPS = 78.6    # MI355X vector FP64
+FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (packed; 78.6 without packed FP32)
 
 
 def log(msg):
@@ -73,9 +75,14 @@ def algorithmic_bytes(st, force_bytes):
 
 class Stepper:
     """Runs the protocol: a list rebuild every `rebuild_every` steps, one force
-    call (forces, energy, virial) per step.  With graphs, the force calls
-    between two rebuilds are one captured HIP graph (re-captured whenever the
-    library reallocates a buffer the force call uses)."""
+    call (forces, energy, virial) per step.  With graphs, a cycle (the rebuild
+    and the force calls behind it) is one captured HIP graph, re-captured
+    whenever the library reallocates a buffer the calls use; the host enqueues
+    the cycles of a run without waiting and checks the lists once after them
+    (a captured build's status accumulates over replays on the device, so one
+    check covers every cycle; a run whose builds overflowed is redone with the
+    grown lists).  Without graphs every cycle is launched eagerly and checked
+    after the force calls behind its build were enqueued."""
 
     def __init__(self, rr, pos, box, rebuild_every, use_graph):
         import torch
@@ -86,87 +93,169 @@ class Stepper:
         self.F = torch.empty((pos.shape[0], 3), dtype=dt, device=pos.device)
         self.E = torch.empty(3, dtype=torch.float64, device=pos.device)
         self.W = torch.empty(6, dtype=torch.float64, device=pos.device)
-        self.graph, self.graph_gen, self.graph_len = None, None, 0
+        self.graphs, self.graph_gen = {}, None
         self.redone = 0
 
     def force(self):
         self.rr.forces(self.pos, out=self.F, energy=self.E, virial=self.W)
 
-    def _graph(self, n):
+    def _cycle_graph(self, n, with_build=True):
+        """Graph of one cycle: the rebuild (unless with_build is False) and n
+        force calls."""
         import torch
         gen = self.rr.generation()
-        if self.graph is None or gen != self.graph_gen or n != self.graph_len:
-            self.force()                 # sizes internal buffers outside capture
+        if gen != self.graph_gen:
+            self.graphs = {}
+        key = (n, with_build)
+        if key not in self.graphs:
+            # a waited build sizes every buffer outside capture
+            self.rr.build_lists(self.pos, self.box)
+            self.force()
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
+                if with_build:
+                    self.rr.build_lists(self.pos, self.box, wait=False)
                 for _ in range(n):
                     self.force()
-            self.graph, self.graph_gen, self.graph_len = g, gen, n
-        return self.graph
+            self.graphs[key] = g
+            self.graph_gen = self.rr.generation()
+        return self.graphs[key]
 
-    def _forces(self, n):
-        if self.use_graph:
-            self._graph(n).replay()
-        else:
-            for _ in range(n):
-                self.force()
+    def enqueue(self, steps):
+        """Enqueue `steps` steps (graph mode), no host wait."""
+        k = 0
+        while k < steps:
+            n = min(self.every, steps - k)
+            self._cycle_graph(n).replay()
+            k += n
 
     def run(self, steps):
-        """The build is enqueued without waiting and checked after the force
-        calls behind it were enqueued (the check waits for the build only), so
-        the GPU never idles on the host.  A build whose rows overflowed is
-        redone, with the force calls that used it."""
+        """`steps` steps; returns when the GPU has finished them and the lists
+        of every cycle are known to be complete."""
+        import torch
+        if self.use_graph:
+            while True:
+                self.enqueue(steps)
+                torch.cuda.synchronize()
+                if self.rr.check_lists():
+                    return
+                self.redone += 1          # rows grew: new buffers, new graphs
         k = 0
         while k < steps:
             n = min(self.every, steps - k)
             self.rr.build_lists(self.pos, self.box, wait=False)
-            self._forces(n)
+            for _ in range(n):
+                self.force()
             if not self.rr.check_lists():
                 self.redone += 1
                 self.rr.build_lists(self.pos, self.box)
-                self._forces(n)
+                for _ in range(n):
+                    self.force()
             k += n
+        torch.cuda.synchronize()
 
 
-def run_protocol(rr, pos, box, steps, warmup, rebuild_every, use_graph=True):
+def run_protocol(rr, pos, box, steps, warmup, rebuild_every, repeats, use_graph=True):
+    """`warmup` untimed steps, then `repeats` timed runs of exactly `steps`
+    steps each (bracketed by device synchronisation); returns the seconds of
+    every timed run and the stepper."""
     import torch
     st = Stepper(rr, pos, box, rebuild_every, use_graph)
-    st.run(max(warmup, rebuild_every))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st.run(steps)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, st
+    if use_graph:
+        # capture every graph the runs use before anything is timed
+        for n in {min(rebuild_every, steps - k) for k in range(0, steps, rebuild_every)} | \
+                {min(rebuild_every, warmup - k) for k in range(0, warmup, rebuild_every)}:
+            st._cycle_graph(n)
+    if warmup > 0:
+        st.run(warmup)
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.run(steps)
+        times.append(time.perf_counter() - t0)
+    return times, st
 
 
 def time_kernels(rr, pos, box, force_calls, builds=20):
-    """Average device time of one force launch (forces, energy, virial) and of
-    one list build.  Force launches: HIP events on the launch stream around
-    replays of a graph of 10 back-to-back launches, so host overhead never
-    leaves the GPU idle inside the bracket.  Builds: the library's own events
-    around the build's kernels."""
+    """Average device time of one force launch (forces, energy, virial), of
+    one list build and of one whole cycle (a build and 10 force calls), each
+    with HIP events on the launch stream around replays of a captured graph
+    (10 force launches, 10 builds, or one cycle), so host overhead never
+    leaves the GPU idle inside the bracket."""
     import torch
     st = Stepper(rr, pos, box, 10, True)
-    rr.build_lists(pos, box)
-    g = st._graph(10)
-    g.replay()
-    torch.cuda.synchronize()
-    reps = max(1, force_calls // 10)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+
+    def per_replay(g, reps):
         g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    force_us = e0.elapsed_time(e1) * 1e3 / (10 * reps)
-    rr.set_timing(True)
-    rr.timing()
-    for _ in range(builds):
-        rr.build_lists(pos, box)
-    tm = rr.timing()
-    rr.set_timing(False)
-    return force_us, 1e3 * tm["build_ms"] / max(1, tm["build_calls"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    reps = max(1, force_calls // 10)
+    force_us = per_replay(st._cycle_graph(10, with_build=False), reps) / 10
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb):
+        for _ in range(10):
+            rr.build_lists(pos, box, wait=False)
+    build_us = per_replay(gb, max(1, builds // 10)) / 10
+    cycle_us = per_replay(st._cycle_graph(10), reps)
+    if not rr.check_lists():
+        raise RuntimeError("list rows overflowed while timing kernels")
+    return force_us, build_us, cycle_us
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pair_counts(rr, sys_, pos_np):
+    """Ordered pairs of the lists by regime of Eq. 20, for the FLOP count of
+    the roofline: list entries, pairs inside r_s+ (atom list) or r_c+ (site
+    list) and pairs inside a smoothing zone ([r_s-, r_s+) of the atom list,
+    [r_s-, r_s+) or [r_c-, r_c+) of the site list).  Host bookkeeping from the
+    library's own pair sets; nothing here feeds the computation."""
+    import numpy as np
+    from paper_2104_10231_amd.relres import LIST_ATOM, LIST_SITE
+    box = np.asarray(sys_.box, np.float64)
+    out = {}
+    for name, which in (("atom", LIST_ATOM), ("site", LIST_SITE)):
+        pr = rr.pairs(which)
+        if len(pr) == 0:
+            out[name] = (0, 0, 0)
+            continue
+        d = pos_np[pr[:, 0]] - pos_np[pr[:, 1]]
+        d -= box * np.rint(d / box)
+        r = np.sqrt((d * d).sum(1))
+        if name == "atom":
+            inside = r < sys_.rs_out
+            smooth = (r >= sys_.rs_in) & inside
+        else:
+            inside = r < sys_.rc_out
+            smooth = ((r >= sys_.rs_in) & (r < sys_.rs_out)) | ((r >= sys_.rc_in) & inside)
+        out[name] = (2 * len(pr), 2 * int(inside.sum()), 2 * int(smooth.sum()))
+    return out
+
+
+def algorithmic_flops(counts):
+    """FLOPs of one force launch: 8 per list entry (the distance), 30 per
+    pair inside its cutoff (reciprocal, r^-6, scalar force, vector force and
+    its accumulation, energy, virial), 17 more per smoothing-zone pair (square
+    root and the two polynomials), per ordered pair of the full lists."""
+    return sum(8 * e + 30 * p + 17 * z for e, p, z in counts.values())
 
 
 def cpu_baseline(sys_, budget_s):
@@ -182,6 +271,7 @@ def cpu_baseline(sys_, budget_s):
         if el >= budget_s or calls >= 1000:
             break
     return dict(value=sys_.n * calls / el, unit="atom-steps/s", cores=threads, kind="oracle",
+                cpu=cpu_model(),
                 sample=f"{calls} full FP64 O(N^2) force+energy+virial evaluations of the "
                        f"{sys_.n}-atom workload ({el:.1f} s)")
 
@@ -495,6 +585,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of --steps steps each; the median is reported")
     ap.add_argument("--rebuild-every", type=int, default=10)
     ap.add_argument("--workload", default="neopentane_20480",
                     choices=["neopentane_20480", "propane_1500", "copolymer_98304"])
@@ -552,41 +644,61 @@ def main():
     precision = s.precision
     pos = torch.from_numpy(s.pos).cuda()
     log(f"[bench] workload {args.workload}: N={s.n}, box {s.box[0]:.3f} A, precision {precision}")
-
-    rr = make(s, precision, args.pair_math)
-    if args.lanes:
-        rr.set_launch(*args.lanes)
     use_graph = not args.no_graph
-    dt, stp = run_protocol(rr, pos, s.box, args.steps, args.warmup, args.rebuild_every,
-                           use_graph=use_graph)
-    st = rr.stats()
+
+    def leg(sys_):
+        """Kernel timing (the roofline figures; it also brings the device to
+        its working clocks), then the protocol: warm-up steps and the timed
+        repetitions."""
+        rr = make(sys_, precision, args.pair_math)
+        if args.lanes:
+            rr.set_launch(*args.lanes)
+        rr.build_lists(pos, sys_.box)
+        force_us, build_us, cycle_us = time_kernels(rr, pos, sys_.box, max(args.steps, 200))
+        times, stp = run_protocol(rr, pos, sys_.box, args.steps, args.warmup, args.rebuild_every,
+                                  args.repeats, use_graph=use_graph)
+        st = rr.stats()
+        counts = pair_counts(rr, sys_, s.pos)
+        rr.close()
+        t_med = sorted(times)[len(times) // 2]
+        return dict(times=times, t=t_med, force_us=force_us, build_us=build_us,
+                    cycle_us=cycle_us, stats=st, counts=counts, redone=stp.redone)
+
+    R = leg(s)
+    st = R["stats"]
+    dt = R["t"]
     value = s.n * args.steps / dt
-    log(f"[bench] RelRes: {dt * 1e3 / args.steps:.4f} ms/step, {value:.4e} atom-steps/s; "
+    force_us, build_us = R["force_us"], R["build_us"]
+    log(f"[bench] RelRes: {dt * 1e3 / args.steps:.4f} ms/step (median of "
+        f"{[round(x * 1e3 / args.steps, 4) for x in R['times']]}), {value:.4e} atom-steps/s; "
         f"atom entries {st['atom_entries']}, site entries {st['site_entries']}, "
-        f"builds redone {stp.redone}")
-    # roofline leg: device time of the force launch
-    force_us, build_us = time_kernels(rr, pos, s.box, args.steps)
+        f"builds redone {R['redone']}")
     fb = 4 if precision == 32 else 8
     abytes = algorithmic_bytes(st, fb)
     achieved = abytes / (force_us * 1e-6) / 1e9
-    log(f"[bench] force launch {force_us:.2f} us (HIP events, graph of back-to-back launches), "
-        f"build {build_us:.1f} us; algorithmic {abytes / 1e6:.3f} MB/launch -> {achieved:.1f} GB/s")
-    rr.close()
+    aflops = algorithmic_flops(R["counts"])
+    tflops = aflops / (force_us * 1e-6) / 1e12
+    # energy and virial are requested at every step: the pair terms then run
+    # in the type the library reports for calls with energy/virial
+    pm_ew = int(st.get("pair_math_ew", 64))
+    alu_peak = FP64_VALU_PEAK_TFLOPS if pm_ew == 64 else FP32_VALU_PEAK_TFLOPS
+    log(f"[bench] force launch {force_us:.2f} us, build {build_us:.1f} us, cycle "
+        f"{R['cycle_us']:.1f} us (HIP events around graph replays); algorithmic "
+        f"{abytes / 1e6:.3f} MB/launch -> {achieved:.1f} GB/s, {aflops / 1e6:.2f} MFLOP/launch "
+        f"-> {tflops:.3f} TFLOP/s")
 
     conv = None
     if not args.no_conventional:
         sc = s.conventional()
-        rc = make(sc, precision, args.pair_math)
-        dtc, _ = run_protocol(rc, pos, sc.box, args.steps, args.warmup, args.rebuild_every,
-                              use_graph=use_graph)
-        stc = rc.stats()
-        fc_us, bc_us = time_kernels(rc, pos, sc.box, args.steps)
-        rc.close()
-        conv = dict(value=s.n * args.steps / dtc, ms_per_step=dtc * 1e3 / args.steps,
-                    force_us=fc_us, build_us=bc_us, atom_entries=stc["atom_entries"])
+        C = leg(sc)
+        stc = C["stats"]
+        conv = dict(value=s.n * args.steps / C["t"], ms_per_step=C["t"] * 1e3 / args.steps,
+                    ms_per_step_runs=[x * 1e3 / args.steps for x in C["times"]],
+                    force_us=C["force_us"], build_us=C["build_us"], cycle_us=C["cycle_us"],
+                    atom_entries=stc["atom_entries"])
         log(f"[bench] conventional: {conv['ms_per_step']:.4f} ms/step, {conv['value']:.4e} "
-            f"atom-steps/s, force launch {fc_us:.2f} us, build {bc_us:.1f} us, "
-            f"entries {stc['atom_entries']}")
+            f"atom-steps/s, force launch {conv['force_us']:.2f} us, build "
+            f"{conv['build_us']:.1f} us, entries {stc['atom_entries']}")
 
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
@@ -599,10 +711,30 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(s, args.cpu_budget)
     if cpu:
-        log(f"[bench] cpu oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
+        log(f"[bench] cpu oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads "
+            f"({cpu['cpu']})")
 
     default_path = args.pair_math == 0 and args.lanes is None
     relres_entries = st["atom_entries"] + st["site_entries"]
+    hbm_frac = achieved / HBM_PEAK_GBS
+    alu_frac = tflops / alu_peak
+    hbm_roof = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": hbm_frac,
+        "traffic": recorded_traffic(args.workload) if default_path else None,
+        "kernel": "k_forces", "kernel_us": force_us,
+        "kernel_us_method": "HIP events on the launch stream around replays of a graph of "
+                            "10 back-to-back force launches",
+        "algorithmic_bytes_per_launch": abytes,
+    }
+    alu_roof = {
+        "bound": "alu", "achieved": tflops, "peak": alu_peak, "unit": "TFLOP/s",
+        "frac": alu_frac, "traffic": None, "kernel": "k_forces", "kernel_us": force_us,
+        "valu": f"fp{pm_ew} vector (pair terms of calls with energy/virial)",
+        "algorithmic_flops_per_launch": aflops,
+    }
+    # the binding roofline is the one the kernel comes closer to
+    primary, secondary = (hbm_roof, alu_roof) if hbm_frac >= alu_frac else (alu_roof, hbm_roof)
     out = {
         "metric": "RelRes atom-steps/s vs conventional 14 Å LJ, 1 MI355X; % FP32/HBM roofline",
         "value": value,
@@ -614,32 +746,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if (precision == 32 and args.pair_math in (0, 32)) else "f64",
+        "dtype": "f32" if (precision == 32 and pm_ew == 32) else "f64",
         "data": "synthetic",
         "config": {
             "workload": args.workload, "atoms": s.n, "sites": int(st["n_sites"]),
             "box_A": float(s.box[0]), "cutoffs_A": [s.rs_in, s.rs_out, s.rc_in, s.rc_out],
             "skin_A": s.skin, "rebuild_every": args.rebuild_every, "seed": args.seed,
             "forces": "fp32" if precision == 32 else "fp64",
-            "pair_math": args.pair_math or precision, "energy_virial": "fp64",
+            "pair_math": pm_ew, "energy_virial": "fp64 accumulation, every step",
             "parallelism": "single GPU",
-            "launch": "hip graph of the force calls between rebuilds" if use_graph else "eager",
+            "launch": ("one hip graph per cycle (rebuild + force calls), lists checked once "
+                       "per timed run") if use_graph else "eager",
+            "timing": f"median of {args.repeats} timed runs of {args.steps} steps after "
+                      f"{args.warmup} warm-up steps; kernel timing (graph replays) before them",
         },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic(args.workload) if default_path else None,
-            "kernel": "k_forces", "kernel_us": force_us,
-            "kernel_us_method": "HIP events on the launch stream around replays of a graph of "
-                                "10 back-to-back force launches",
-            "algorithmic_bytes_per_launch": abytes,
-        },
+        "ms_per_step_runs": [x * 1e3 / args.steps for x in R["times"]],
+        "roofline": primary,
+        "roofline_other": secondary,
+        "kernel_sum_us_per_step": force_us + build_us / args.rebuild_every,
+        "cycle_us": R["cycle_us"],
         "cpu_baseline": cpu,
         "conventional": conv,
         "speedup_vs_conventional": (value / conv["value"]) if conv else None,
         "list_entries": {"relres": relres_entries,
                          "conventional": conv["atom_entries"] if conv else None,
                          "N_star": (relres_entries / conv["atom_entries"]) if conv else None},
+        "pairs_by_regime": {k: dict(zip(("entries", "inside_cutoff", "smoothing_zone"), v))
+                            for k, v in R["counts"].items()},
         "build_us": build_us,
     }
     print(json.dumps(out), flush=True)

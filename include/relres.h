@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RELRES_ABI_VERSION 4
+#define RELRES_ABI_VERSION 5
 
 #define RELRES_OK                   0
 #define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
@@ -228,11 +228,13 @@ int relres_build_lists(relres_ctx *ctx, const double *pos, const double box[3], 
 int relres_build_lists_async(relres_ctx *ctx, const double *pos, const double box[3],
                              void *stream);
 /* A build enqueued on a stream that is being captured into a HIP graph runs
- * at every replay of the graph (status copy included); relres_check_lists
- * then examines the status of the latest replay, so synchronise the stream
- * after the replay first.  A RELRES_ERR_LIST_RETRY there grows the rows,
- * which changes the buffer generation (relres_generation): capture again.
- * Timing events are not recorded during capture.                           */
+ * at every replay of the graph.  Its status accumulates on the device, and
+ * relres_check_lists copies it to the host itself and examines every replay
+ * since the previous check at once (one check after many replays is enough):
+ * synchronise the stream after the replays first.  RELRES_ERR_LIST_RETRY
+ * there (some replay overflowed a row) grows the rows, which changes the
+ * buffer generation (relres_generation): capture again and redo the
+ * replays.  Timing events are not recorded during capture.                */
 
 /* Waits for the status of the last build and examines it: RELRES_OK when the
  * lists are complete, RELRES_ERR_NONFINITE for a NaN/inf position, or
@@ -283,13 +285,43 @@ int relres_set_pair_params(relres_ctx *ctx, const double *eps_fg, const double *
  *   grad_pair    device double[4 * ntypes * ntypes], overwritten with dJ/dP
  *                for P = eps_FG, sigma_FG, eps_CG, sigma_CG (that order),
  *                each [a][b] row-major, treating the ordered pair entries
- *                as independent (chain through the mixing rule outside).
+ *                as independent (relres_backward_types carries them through
+ *                the mixing rule to the per-type values).
  * Pair terms are recomputed (FP64), nothing is stored by relres_forces.
  * Parameter sums are reduced in a fixed order (bitwise repeatable).  At most
- * 8 types.  Asynchronous on `stream`.                                      */
+ * 8 types: the kernel bins its parameter sums per neighbour type in
+ * registers (8 x 4 FP64 per lane), and more bins would cut its occupancy;
+ * RELRES_ERR_ARG beyond.  Asynchronous on `stream`.                        */
 int relres_backward(relres_ctx *ctx, const double *pos, const double *grad_forces,
                     const double *grad_energy, double *grad_pos, double *grad_pair,
                     void *stream);
+
+/* Replace the per-type parameters (host arrays of ntypes doubles each, as in
+ * relres_params) and mix them again with the context's rule (Sec. 2.3; CG
+ * pair parameters only for hybrid-hybrid pairs, Eq. 14).  The hybrid types
+ * are fixed by relres_create (they define the site list): a hybrid type keeps
+ * eps_cg > 0 and sigma_cg > 0, an ordinary one eps_cg = 0, else
+ * RELRES_ERR_ARG.  Recomputes every coefficient of Eqs. 17-19 on the host and
+ * uploads them; waits for the device first.  Lists stay valid.             */
+int relres_set_type_params(relres_ctx *ctx, const double *eps_fg, const double *sig_fg,
+                           const double *eps_cg, const double *sig_cg);
+
+/* relres_backward with the parameter gradient carried through the mixing
+ * rule of Sec. 2.3 to the per-type values of relres_create or the last
+ * relres_set_type_params:
+ *   grad_type  device double[4 * ntypes], overwritten with dJ/d eps_FG,
+ *              dJ/d sigma_FG, dJ/d eps_CG, dJ/d sigma_CG of each type (that
+ *              order, ntypes values each).  The CG values of ordinary types
+ *              get 0: Eq. 14 fixes their pair parameters at zero.
+ * The other arguments are those of relres_backward.  The per-type values
+ * must be positive (FG of every type, CG of hybrid types): the mixing rules
+ * have no derivative at zero (RELRES_ERR_ARG).  RELRES_ERR_STATE after
+ * relres_set_pair_params, whose tables have no per-type values.  Uses a
+ * library-owned buffer for the pair gradients: calls on one context must not
+ * overlap.  Asynchronous on `stream`.                                       */
+int relres_backward_types(relres_ctx *ctx, const double *pos, const double *grad_forces,
+                          const double *grad_energy, double *grad_pos, double *grad_type,
+                          void *stream);
 
 /* Bonded terms and scaled 1-4 pairs of the molecular model (Sec. 3.2: AMBER
  * united-atom bonds, angles and Fourier dihedrals, 1-4 non-bonded pairs

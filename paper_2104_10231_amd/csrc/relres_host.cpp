@@ -124,6 +124,31 @@ double mix_eps(int mix, double ea, double eb, double sa, double sb)
     return std::sqrt(ea * eb);
 }
 
+// Derivatives of a mixed pair (eps_ab, sigma_ab) with respect to the values
+// of type a (the first argument), from the definitions of the rules:
+//   geometric        eps_ab = sqrt(ea eb), sigma_ab = sqrt(sa sb)
+//   Lorentz-Berthelot  eps_ab as geometric, sigma_ab = (sa + sb) / 2
+//   sixth-power      eps_ab = 2 sqrt(ea eb) sa^3 sb^3 / (sa^6 + sb^6),
+//                    sigma_ab = ((sa^6 + sb^6) / 2)^(1/6)
+// out = {d eps_ab/d ea, d eps_ab/d sa, d sigma_ab/d sa} (sigma_ab does not
+// depend on the energies).  Type b's derivatives follow by swapping the
+// arguments.  The values must be positive.
+void mix_derivs(int mix, double ea, double eb, double sa, double sb, double out[3])
+{
+    const double e = mix_eps(mix, ea, eb, sa, sb);
+    out[0] = 0.5 * e / ea;
+    if (mix == RELRES_MIX_SIXTHPOWER) {
+        const double a3 = sa * sa * sa, b3 = sb * sb * sb;
+        const double s6 = a3 * a3 + b3 * b3;
+        const double s = mix_sigma(mix, sa, sb);
+        out[1] = e * (3.0 / sa - 6.0 * a3 * sa * sa / s6);
+        out[2] = a3 * sa * sa / (2.0 * s * s * s * s * s);
+        return;
+    }
+    out[1] = 0.0;
+    out[2] = mix == RELRES_MIX_ARITHMETIC ? 0.5 : 0.5 * std::sqrt(sb / sa);
+}
+
 // u, u', u'' (wrt = 0) or their derivatives with respect to eps (wrt = 1) or
 // sigma (wrt = 2).  u is linear in eps; with q = sigma/r the sigma
 // derivatives are 4 eps (12 q^12 - 6 q^6)/sigma, 24 eps (6 q^6 - 24 q^12)/(r
@@ -263,6 +288,12 @@ struct relres_ctx {
     std::vector<int> hybrid;
     std::vector<PairCoef<double>> coef64;     // per type pair
     std::vector<PairCoef<double>> coef_grad;  // [4][pair]: d/d eps_FG, sigma_FG, eps_CG, sigma_CG
+    // per-type parameters the pair tables were mixed from (relres_create,
+    // relres_set_type_params); false after relres_set_pair_params, which
+    // bypasses the mixing (per-type gradients are then undefined)
+    std::vector<double> type_par;     // [4][ntypes]: eps_FG, sigma_FG, eps_CG, sigma_CG
+    bool tables_from_types = true;
+    DBuf d_mix_jac, d_gpair;          // mixing Jacobian (see mix_jacobian); pair gradients
     DBuf d_coef64, d_coef32, d_hybrid, d_coef_grad, d_bpartial, d_pcut64, d_pcut32;
     double cut64[8] = {0};            // the distances of every pair when !per_pair
 
@@ -361,6 +392,54 @@ void build_tables(relres_ctx* c, const double* ef, const double* sf, const doubl
                 cg_part(c->coef_grad[3 * np + q], ec[q], sc[q], 2, r[1], r[2], Ds, Dc, ns);
             }
         }
+}
+
+// Pair tables mixed from per-type parameters (Sec. 2.3 with the context's
+// `mix` rule; CG pair parameters only for hybrid-hybrid pairs, Eq. 14), the
+// coefficient records built from them, and the mixing Jacobian that carries
+// pair gradients back to the per-type values (relres_backward_types):
+// [family FG/CG][pair q = a*nt + b][6] = d eps_ab/d eps_a, d eps_ab/d sigma_a,
+// d sigma_ab/d sigma_a, then the same for type b; zero for the CG family of a
+// pair with an ordinary type, and wherever a value is not positive (no
+// derivative of a geometric mean there; relres_backward_types refuses such
+// parameters).  Host only.
+void install_type_params(relres_ctx* c, const double* eps_fg, const double* sig_fg,
+                         const double* eps_cg, const double* sig_cg, std::vector<double>& jac)
+{
+    const int nt = c->ntypes;
+    const size_t np = (size_t)nt * nt;
+    std::vector<double> ef(np, 0.0), sf(np, 0.0), ec(np, 0.0), sc(np, 0.0);
+    jac.assign(2 * np * 6, 0.0);
+    const double* E[2] = {eps_fg, eps_cg};
+    const double* S[2] = {sig_fg, sig_cg};
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const size_t q = (size_t)a * nt + b;
+            ef[q] = mix_eps(c->mix, eps_fg[a], eps_fg[b], sig_fg[a], sig_fg[b]);
+            sf[q] = mix_sigma(c->mix, sig_fg[a], sig_fg[b]);
+            const bool hyb = c->hybrid[a] && c->hybrid[b];
+            if (hyb) {
+                ec[q] = mix_eps(c->mix, eps_cg[a], eps_cg[b], sig_cg[a], sig_cg[b]);
+                sc[q] = mix_sigma(c->mix, sig_cg[a], sig_cg[b]);
+            }
+            for (int f = 0; f < 2; ++f) {
+                if (f == 1 && !hyb) continue;
+                const double ea = E[f][a], eb = E[f][b], sa = S[f][a], sb = S[f][b];
+                if (!(ea > 0.0 && eb > 0.0 && sa > 0.0 && sb > 0.0)) continue;
+                double* J = &jac[((size_t)f * np + q) * 6];
+                mix_derivs(c->mix, ea, eb, sa, sb, J);
+                mix_derivs(c->mix, eb, ea, sb, sa, J + 3);
+            }
+        }
+    build_tables(c, ef.data(), sf.data(), ec.data(), sc.data());
+    c->type_par.assign(4 * (size_t)nt, 0.0);
+    for (int k = 0; k < nt; ++k) {
+        c->type_par[0 * nt + k] = eps_fg[k];
+        c->type_par[1 * nt + k] = sig_fg[k];
+        c->type_par[2 * nt + k] = eps_cg[k];
+        c->type_par[3 * nt + k] = sig_cg[k];
+    }
+    c->tables_from_types = true;
 }
 
 // Copy the coefficient tables to the device (FP64, an FP32 copy, and the
@@ -719,8 +798,9 @@ bool lists_per_wave(const relres_ctx* c)
     return true;
 }
 
-// Enqueue one list build on `s`: bin, scan, scatter, cell sort, lists, then a
-// copy of the status word to pinned host memory and an event.  Nothing waits;
+// Enqueue one list build on `s`: bin, scan, scatter, cell sort, lists, then
+// (unless the stream is being captured) a copy of the status word to pinned
+// host memory and an event.  Nothing waits;
 // relres_forces may be enqueued behind it at once.  The lists are complete
 // unless examine_status() later reports an overflow.
 int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream_t s)
@@ -802,7 +882,7 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         c->ref_valid = true;
         c->ref_skins = skin_sys;
         HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->ga.ncell, sites ? c->gs.ncell : 0,
-                            c->d_seg_tot.as<int>(), c->d_status.as<Status>(), s));
+                            c->d_seg_tot.as<int>(), s));
         HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
         HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs,
@@ -812,10 +892,13 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
                              c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
                              c->d_status.as<Status>(), lists_per_wave(c), c->cand, s));
-        HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
-        // in a captured graph the copy runs at every replay; the caller
-        // synchronises after the replay before relres_check_lists
-        if (!capturing) HIP_TRY(hipEventRecord(c->ev_status, s));
+        // A captured build copies nothing: the status only accumulates (see
+        // Status), so relres_check_lists copies it once after the caller has
+        // synchronised, covering every replay since the previous check.
+        if (!capturing) {
+            HIP_TRY(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(c->ev_status, s));
+        }
         c->status_in_graph = capturing;
         c->check_pending = true;
     }
@@ -837,6 +920,18 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     return RELRES_OK;
 }
 
+// Make h_status describe the last enqueued build: wait for its copy, or, for
+// a build captured into a graph (the caller has synchronised after the
+// replays), copy the accumulated status now.
+int fetch_status(relres_ctx* c)
+{
+    if (c->status_in_graph)
+        HIP_TRY(hipMemcpy(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost));
+    else
+        HIP_TRY(hipEventSynchronize(c->ev_status));
+    return RELRES_OK;
+}
+
 // Wait for the status of the last enqueued build and examine it.  Returns
 // RELRES_OK (lists complete), RELRES_ERR_NONFINITE, or RELRES_ERR_LIST_RETRY
 // after growing the capacities of the rows that overflowed (the lists are
@@ -847,7 +942,7 @@ int examine_status(relres_ctx* c)
     // rebuilds the lists and copies a new status)
     if (!c->check_pending && !c->status_in_graph)
         return c->built ? RELRES_OK : fail(RELRES_ERR_NO_LISTS, "no lists");
-    if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
+    TRY(fetch_status(c));
     c->check_pending = false;
     const Status& st = *c->h_status;
     const unsigned moved = st.moved - c->moved_seen;
@@ -894,6 +989,13 @@ int examine_status(relres_ctx* c)
 int drain_check(relres_ctx* c)
 {
     if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    // the status of a captured build describes replays, which only
+    // relres_check_lists examines (it copies the status, which must not
+    // happen while a stream is being captured)
+    if (c->status_in_graph) {
+        c->check_pending = false;
+        return RELRES_OK;
+    }
     const int rc = examine_status(c);
     return (rc == RELRES_ERR_LIST_RETRY || rc == RELRES_ERR_NO_LISTS) ? RELRES_OK : rc;
 }
@@ -1096,20 +1198,8 @@ int relres_create(const relres_params* p, relres_ctx** out)
         }
     if (c->list_rco == 0.0) c->list_rco = any_rco;     // no hybrid pair: the site list stays empty
 
-    {
-        std::vector<double> ef((size_t)nt * nt), sf(ef.size()), ec(ef.size()), sc(ef.size());
-        for (int a = 0; a < nt; ++a)
-            for (int b = 0; b < nt; ++b) {
-                const size_t q = (size_t)a * nt + b;
-                ef[q] = mix_eps(c->mix, p->eps_fg[a], p->eps_fg[b], p->sig_fg[a], p->sig_fg[b]);
-                sf[q] = mix_sigma(c->mix, p->sig_fg[a], p->sig_fg[b]);
-                if (c->hybrid[a] && c->hybrid[b]) {
-                    ec[q] = mix_eps(c->mix, p->eps_cg[a], p->eps_cg[b], p->sig_cg[a], p->sig_cg[b]);
-                    sc[q] = mix_sigma(c->mix, p->sig_cg[a], p->sig_cg[b]);
-                }
-            }
-        build_tables(c, ef.data(), sf.data(), ec.data(), sc.data());
-    }
+    std::vector<double> jac;
+    install_type_params(c, p->eps_fg, p->sig_fg, p->eps_cg, p->sig_cg, jac);
     for (int k = 0; k < 4; ++k) c->cut64[k] = dist[k];
     for (int k = 0; k < 4; ++k) c->cut64[4 + k] = c->cut64[k] * c->cut64[k];
 
@@ -1120,11 +1210,14 @@ int relres_create(const relres_params* p, relres_ctx** out)
     if ((rc = ensure(c->d_pcut64, sizeof(Cutoffs<double>) * nt * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_pcut32, sizeof(Cutoffs<float>) * nt * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_hybrid, sizeof(int) * nt, &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_mix_jac, sizeof(double) * jac.size(), &c->alloc_generation))) return bail(rc);
+    if ((rc = ensure(c->d_gpair, sizeof(double) * 4 * nt * nt, &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_grids, 2 * sizeof(GridDev), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_status, sizeof(Status), &c->alloc_generation))) return bail(rc);
     if ((rc = ensure(c->d_epoch, 256, &c->alloc_generation))) return bail(rc);
     if (upload_tables(c) != RELRES_OK ||
         hipMemcpy(c->d_hybrid.p, c->hybrid.data(), sizeof(int) * nt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_mix_jac.p, jac.data(), sizeof(double) * jac.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_status.p, 0, sizeof(Status)) != hipSuccess ||
         hipMemset(c->d_epoch.p, 0, 256) != hipSuccess)
         return bail(fail(RELRES_ERR_HIP, "uploading parameters failed"));
@@ -1184,9 +1277,10 @@ int relres_set_topology(relres_ctx* c, int n, const int* types, const int* mol, 
             idx.insert(idx.end(), part[i].begin(), part[i].end());
         }
     }
-    if (c->check_pending) {
-        // a build of the previous topology is still unexamined: retire it
-        if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
+    if (c->check_pending || c->status_in_graph) {
+        // a build of the previous topology (or replays of a captured one)
+        // is still unexamined: retire it
+        TRY(fetch_status(c));
         c->nonfinite_seen = c->h_status->nonfinite;
         c->moved_seen = c->h_status->moved;
         c->check_pending = false;
@@ -1244,8 +1338,8 @@ int relres_set_systems(relres_ctx* c, int nsys, const int* atom_offsets)
             sites[sy] += c->hybrid[c->h_types[i]] ? 1 : 0;
         }
     }
-    if (c->check_pending) {
-        if (!c->status_in_graph) HIP_TRY(hipEventSynchronize(c->ev_status));
+    if (c->check_pending || c->status_in_graph) {
+        TRY(fetch_status(c));
         c->nonfinite_seen = c->h_status->nonfinite;
         c->moved_seen = c->h_status->moved;
         c->check_pending = false;
@@ -1584,12 +1678,78 @@ int relres_set_pair_params(relres_ctx* c, const double* eps_fg, const double* si
     // the tables may be in use by work still queued on any stream
     HIP_TRY(hipDeviceSynchronize());
     build_tables(c, eps_fg, sig_fg, eps_cg, sig_cg);
+    c->tables_from_types = false;
     TRY(upload_tables(c));
     return RELRES_OK;
 }
 
+int relres_set_type_params(relres_ctx* c, const double* eps_fg, const double* sig_fg,
+                           const double* eps_cg, const double* sig_cg)
+{
+    if (!c || !eps_fg || !sig_fg || !eps_cg || !sig_cg) return fail(RELRES_ERR_ARG, "NULL argument");
+    const int nt = c->ntypes;
+    for (int t = 0; t < nt; ++t) {
+        if (!(std::isfinite(eps_fg[t]) && eps_fg[t] >= 0.0 && std::isfinite(sig_fg[t]) &&
+              sig_fg[t] > 0.0))
+            return fail(RELRES_ERR_ARG, "bad FG parameters for type %d", t);
+        // the hybrid types define the site list: they may not change here
+        if (c->hybrid[t] ? !(std::isfinite(eps_cg[t]) && eps_cg[t] > 0.0 &&
+                             std::isfinite(sig_cg[t]) && sig_cg[t] > 0.0)
+                         : eps_cg[t] != 0.0)
+            return fail(RELRES_ERR_ARG, "type %d: eps_CG must stay %s (with sigma_CG > 0)", t,
+                        c->hybrid[t] ? "positive" : "zero");
+    }
+    HIP_TRY(hipDeviceSynchronize());   // the tables may be in use by queued work
+    std::vector<double> jac;
+    install_type_params(c, eps_fg, sig_fg, eps_cg, sig_cg, jac);
+    TRY(upload_tables(c));
+    HIP_TRY(hipMemcpy(c->d_mix_jac.p, jac.data(), sizeof(double) * jac.size(), hipMemcpyHostToDevice));
+    return RELRES_OK;
+}
+
+namespace {
+
+int enqueue_backward(relres_ctx* c, const double* pos, const double* grad_forces,
+                     const double* grad_energy, double* grad_pos, double* grad_pair, hipStream_t s);
+
+}  // namespace
+
 int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
                     const double* grad_energy, double* grad_pos, double* grad_pair, void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!grad_pair) return fail(RELRES_ERR_ARG, "grad_pair is NULL");
+    return enqueue_backward(c, pos, grad_forces, grad_energy, grad_pos, grad_pair,
+                            (hipStream_t)stream);
+}
+
+int relres_backward_types(relres_ctx* c, const double* pos, const double* grad_forces,
+                          const double* grad_energy, double* grad_pos, double* grad_type,
+                          void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!grad_type) return fail(RELRES_ERR_ARG, "grad_type is NULL");
+    if (!c->tables_from_types)
+        return fail(RELRES_ERR_STATE, "pair parameters were set by relres_set_pair_params: "
+                    "no per-type parameters to differentiate");
+    const int nt = c->ntypes;
+    for (int t = 0; t < nt; ++t) {
+        const double* v = c->type_par.data();
+        if (!(v[t] > 0.0 && v[nt + t] > 0.0) ||
+            (c->hybrid[t] && !(v[2 * nt + t] > 0.0 && v[3 * nt + t] > 0.0)))
+            return fail(RELRES_ERR_ARG, "type %d: per-type gradients need positive eps and sigma "
+                        "(the mixing rules are not differentiable at zero)", t);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    TRY(enqueue_backward(c, pos, grad_forces, grad_energy, grad_pos, c->d_gpair.as<double>(), s));
+    HIP_TRY(launch_type_grad(c->d_gpair.as<double>(), c->d_mix_jac.as<double>(), nt, grad_type, s));
+    return RELRES_OK;
+}
+
+namespace {
+
+int enqueue_backward(relres_ctx* c, const double* pos, const double* grad_forces,
+                     const double* grad_energy, double* grad_pos, double* grad_pair, hipStream_t s)
 {
     if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
     if (c->check_pending) TRY(examine_status(c));
@@ -1597,9 +1757,7 @@ int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
     if (c->ntypes > kBackwardTypes)
         return fail(RELRES_ERR_ARG, "relres_backward supports at most %d types (got %d)",
                     kBackwardTypes, c->ntypes);
-    if (!grad_pair || (c->n > 0 && (!pos || !grad_pos)))
-        return fail(RELRES_ERR_ARG, "pos, grad_pos or grad_pair is NULL");
-    hipStream_t s = (hipStream_t)stream;
+    if (c->n > 0 && (!pos || !grad_pos)) return fail(RELRES_ERR_ARG, "pos or grad_pos is NULL");
     const int nt = c->ntypes;
     const int nbins = 4 * nt * nt;
     BackArgs b{};
@@ -1647,6 +1805,8 @@ int relres_backward(relres_ctx* c, const double* pos, const double* grad_forces,
     HIP_TRY(launch_backward(b, waves, grad_pair, s));
     return RELRES_OK;
 }
+
+}  // namespace
 
 int relres_set_bonded(relres_ctx* c, int nbonds, const int* bonds, const double* bond_k,
                       const double* bond_r0, int nangles, const int* angles, const double* angle_k,

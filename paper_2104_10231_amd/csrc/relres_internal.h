@@ -100,13 +100,16 @@ struct TopoDev {
     const int* sys;           // system of each atom, or null when there is one system
 };
 
-// Build status, in mapped pinned host memory: the kernels write it directly
-// and the host reads it after synchronising.  max_row is written only by rows
-// that outgrew their capacity (cleared by k_scan at every build); entries and
-// longest are filled on demand by k_list_stats.
+// Build status, in device memory; the host copies it to pinned memory to
+// examine it.  Every field but the on-demand statistics only grows, so one
+// examination covers every build since the previous one (for instance all
+// replays of a captured graph): max_row is written only by rows that outgrew
+// their capacity and is never cleared (capacities only grow, past every value
+// seen, so max_row > capacity means a build since the last growth
+// overflowed); entries and longest are filled on demand by k_list_stats.
 struct Status {
     int nonfinite;                  // cumulative count of non-finite positions seen
-    int max_row[2];                 // longest overflowing row per grid, 0 if none
+    int max_row[2];                 // longest overflowing row per grid since creation, 0 if none
     int longest[2];                 // longest row per grid (k_list_stats)
     unsigned moved;                 // cumulative count, over builds, of atoms found more
                                     // than half the skin from their previous-build position
@@ -167,7 +170,7 @@ hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* g
 // using seg_tot: scan_segments(ncell_a) + scan_segments(ncell_s) ints)
 int scan_segments(int ncell);
 hipError_t launch_scan(GridDev* grids_dev, int ngrids, int ncell_a, int ncell_s, int* seg_tot,
-                       Status* st, hipStream_t s);
+                       hipStream_t s);
 hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const int2* key_s,
                           hipStream_t s);
 // members: rows of both grids (picks cells per wave)
@@ -198,6 +201,10 @@ constexpr int kBackwardTypes = 8;
 // waves = wavefronts of the launch; grad_pair receives [4][ntypes][ntypes];
 // distances per type pair from b.f.pcut64
 hipError_t launch_backward(const BackArgs& b, int waves, double* grad_pair, hipStream_t s);
+// per-type gradients [4][nt] from pair gradients [4][nt][nt] and the mixing
+// Jacobian [2][nt][nt][6] (relres_backward_types)
+hipError_t launch_type_grad(const double* gpair, const double* jac, int nt, double* gtype,
+                            hipStream_t s);
 hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStream_t s);
 // nsys > 1: energy/virial of each system from the wave sums (and the row

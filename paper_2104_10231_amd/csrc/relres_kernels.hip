@@ -276,13 +276,11 @@ __device__ __forceinline__ int block_sum_int(int v, int* sums)
 // One block per grid: exclusive scan of the per-cell counts into `start`,
 // then the counts are cleared for the next build.  Counts are staged through
 // LDS in segments of kScanSeg cells with coalesced loads; each thread scans a
-// contiguous run of its segment.  Block 0 also clears the list statistics.
-__global__ __launch_bounds__(kScanThreads) void k_scan(GridDev* __restrict__ grids,
-                                                       Status* __restrict__ st)
+// contiguous run of its segment.
+__global__ __launch_bounds__(kScanThreads) void k_scan(GridDev* __restrict__ grids)
 {
     __shared__ int vals[kScanSeg];
     __shared__ int sums[kScanThreads];
-    if (blockIdx.x == 0 && threadIdx.x < 2) st->max_row[threadIdx.x] = 0;
     const GridDev& g = grids[blockIdx.x];
     const int nc = g.ncell;
     int carry = 0;
@@ -313,15 +311,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_totals(const GridDev* __r
 
 // ... then each block adds the totals of its grid's earlier segments and
 // scans its own segment (the grid's last segment also writes start[ncell]).
-// Block 0 also clears the list statistics.
 __global__ __launch_bounds__(kScanThreads) void k_scan_segments(GridDev* __restrict__ grids,
                                                                 int nseg0,
-                                                                const int* __restrict__ seg_tot,
-                                                                Status* __restrict__ st)
+                                                                const int* __restrict__ seg_tot)
 {
     __shared__ int vals[kScanSeg];
     __shared__ int sums[kScanThreads];
-    if (blockIdx.x == 0 && threadIdx.x < 2) st->max_row[threadIdx.x] = 0;
     const int b = blockIdx.x;
     const int gi = b >= nseg0 ? 1 : 0;
     const int q = gi ? b - nseg0 : b;
@@ -1517,17 +1512,17 @@ hipError_t launch_moved(int n, const double* pos, TopoDev topo, const GridDev* g
 int scan_segments(int ncell) { return (ncell + kScanSeg - 1) / kScanSeg; }
 
 hipError_t launch_scan(GridDev* grids_dev, int ngrids, int ncell_a, int ncell_s, int* seg_tot,
-                       Status* st, hipStream_t s)
+                       hipStream_t s)
 {
     const int nseg0 = scan_segments(ncell_a), nseg1 = ngrids > 1 ? scan_segments(ncell_s) : 0;
     if (nseg0 <= 1 && nseg1 <= 1) {
-        hipLaunchKernelGGL(k_scan, dim3(ngrids), dim3(kScanThreads), 0, s, grids_dev, st);
+        hipLaunchKernelGGL(k_scan, dim3(ngrids), dim3(kScanThreads), 0, s, grids_dev);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_totals, dim3(nseg0 + nseg1), dim3(kScanThreads), 0, s, grids_dev,
                        nseg0, seg_tot);
     hipLaunchKernelGGL(k_scan_segments, dim3(nseg0 + nseg1), dim3(kScanThreads), 0, s, grids_dev,
-                       nseg0, seg_tot, st);
+                       nseg0, seg_tot);
     return hipGetLastError();
 }
 
@@ -1870,6 +1865,44 @@ hipError_t launch_backward(const BackArgs& b, int waves, double* grad_pair, hipS
     }
     hipLaunchKernelGGL(k_reduce_bins, dim3(4 * nt * nt), dim3(256), 0, s, b.partial,
                        blocks > 0 ? waves : 0, nt, grad_pair);
+    return hipGetLastError();
+}
+
+// Chain rule from pair-table gradients to per-type parameters: for type t and
+// family f (FG, CG), dJ/d eps_t = sum over ordered pairs (t, b) and (a, t) of
+// dJ/d eps_ab times d eps_ab/d eps_t, and dJ/d sigma_t likewise through
+// eps_ab and sigma_ab.  jac[(f * nt^2 + q) * 6] holds, for pair q = a*nt + b,
+// the derivatives of (eps_ab, eps_ab, sigma_ab) with respect to (eps_a,
+// sigma_a, sigma_a), then those with respect to type b's values.  One thread
+// per output, sums in a fixed order.
+__global__ __launch_bounds__(256) void k_type_grad(const double* __restrict__ gpair,
+                                                   const double* __restrict__ jac, int nt,
+                                                   double* __restrict__ gtype)
+{
+    const int o = (int)threadIdx.x;
+    if (o >= 4 * nt) return;
+    const int P = o / nt, t = o % nt;
+    const int f = P >> 1, y = P & 1;          // family, 0 = eps / 1 = sigma
+    const size_t np = (size_t)nt * nt;
+    const double* ge = gpair + (size_t)(2 * f) * np;       // dJ/d eps_ab of the family
+    const double* gs = gpair + (size_t)(2 * f + 1) * np;   // dJ/d sigma_ab
+    const double* J = jac + (size_t)f * np * 6;
+    double s = 0.0;
+    for (int b = 0; b < nt; ++b) {            // pairs (t, b): type t is the first
+        const size_t q = (size_t)t * nt + b;
+        s += y == 0 ? ge[q] * J[6 * q] : ge[q] * J[6 * q + 1] + gs[q] * J[6 * q + 2];
+    }
+    for (int a = 0; a < nt; ++a) {            // pairs (a, t): type t is the second
+        const size_t q = (size_t)a * nt + t;
+        s += y == 0 ? ge[q] * J[6 * q + 3] : ge[q] * J[6 * q + 4] + gs[q] * J[6 * q + 5];
+    }
+    gtype[o] = s;
+}
+
+hipError_t launch_type_grad(const double* gpair, const double* jac, int nt, double* gtype,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_type_grad, dim3(1), dim3(256), 0, s, gpair, jac, nt, gtype);
     return hipGetLastError();
 }
 

@@ -98,6 +98,11 @@ SIGNATURES = {
     "relres_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "relres_set_type_params": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p,
+                                              _c_double_p, _c_double_p]),
+    "relres_backward_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "relres_list_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "relres_generation": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]),
     "relres_get_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -364,11 +369,25 @@ class RelRes:
         _check(self._lib.relres_set_pair_params(self._ctx,
                                                 *[a.ctypes.data_as(_c_double_p) for a in arrs]),
                "relres_set_pair_params")
+        self._installed_params = None       # the tables no longer come from per-type values
 
-    def backward(self, pos: torch.Tensor, grad_forces: Optional[torch.Tensor] = None,
-                 grad_energy: Optional[torch.Tensor] = None, stream=None):
-        """dJ/dx (N, 3) and dJ/dP (4, ntypes, ntypes) for J = e_bar E + sum g.F."""
-        pos = self._pos(pos)
+    def set_type_params(self, eps_fg, sig_fg, eps_cg, sig_cg):
+        """Per-type parameters (ntypes each, host arrays or CPU tensors),
+        mixed again by the library."""
+        arrs = []
+        for t in (eps_fg, sig_fg, eps_cg, sig_cg):
+            if isinstance(t, torch.Tensor):
+                t = t.detach().cpu().numpy()
+            a = _f64(t)
+            if a.shape != (self.ntypes,):
+                raise ValueError(f"per-type array shape {a.shape}, expected ({self.ntypes},)")
+            arrs.append(a)
+        _check(self._lib.relres_set_type_params(self._ctx,
+                                                *[a.ctypes.data_as(_c_double_p) for a in arrs]),
+               "relres_set_type_params")
+        self._installed_params = None
+
+    def _grad_args(self, pos, grad_forces, grad_energy):
         gf = None
         if grad_forces is not None:
             gf = grad_forces.to(dtype=torch.float64).contiguous()
@@ -380,12 +399,30 @@ class RelRes:
             if ge.numel() != self.nsys:
                 raise ValueError(f"grad_energy needs {self.nsys} values (one per system)")
         gpos = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device)
+        return (pos.data_ptr() if self.n else None,
+                gf.data_ptr() if gf is not None and self.n else None,
+                ge.data_ptr() if ge is not None else None,
+                gpos.data_ptr() if self.n else None), gpos, (gf, ge)
+
+    def backward_types(self, pos: torch.Tensor, grad_forces: Optional[torch.Tensor] = None,
+                       grad_energy: Optional[torch.Tensor] = None, stream=None):
+        """dJ/dx (N, 3) and dJ/d(per-type parameter) (4, ntypes) for
+        J = e_bar E + sum g.F (relres_backward_types)."""
+        pos = self._pos(pos)
+        ptrs, gpos, keep = self._grad_args(pos, grad_forces, grad_energy)
+        gtype = torch.empty((4, self.ntypes), dtype=torch.float64, device=pos.device)
+        _check(self._lib.relres_backward_types(self._ctx, *ptrs, gtype.data_ptr(),
+                                               _stream(stream)), "relres_backward_types")
+        return gpos, gtype
+
+    def backward(self, pos: torch.Tensor, grad_forces: Optional[torch.Tensor] = None,
+                 grad_energy: Optional[torch.Tensor] = None, stream=None):
+        """dJ/dx (N, 3) and dJ/dP (4, ntypes, ntypes) for J = e_bar E + sum g.F."""
+        pos = self._pos(pos)
+        ptrs, gpos, keep = self._grad_args(pos, grad_forces, grad_energy)
         gpair = torch.empty((4, self.ntypes, self.ntypes), dtype=torch.float64, device=pos.device)
-        _check(self._lib.relres_backward(self._ctx, pos.data_ptr() if self.n else None,
-                                         gf.data_ptr() if gf is not None and self.n else None,
-                                         ge.data_ptr() if ge is not None else None,
-                                         gpos.data_ptr() if self.n else None, gpair.data_ptr(),
-                                         _stream(stream)), "relres_backward")
+        _check(self._lib.relres_backward(self._ctx, *ptrs, gpair.data_ptr(), _stream(stream)),
+               "relres_backward")
         return gpos, gpair
 
     # -- inspection ------------------------------------------------------------

@@ -186,3 +186,51 @@ def test_force_matching_over_perturbed_frames():
             assert abs(dt[P, t] - dt_ref[P, t]) <= 1e-8 * abs(dt_ref[P, t]) + 1e-10 * scale, \
                 (PARAMS[P], t, dt[P, t], dt_ref[P, t])
     rr.close()
+
+
+def test_set_type_params_equals_a_fresh_context():
+    """relres_set_type_params mixes per-type values inside the library: the
+    same forces, energy and virial, bit for bit, as a context created with
+    them (both mixing rules that differ in sigma)."""
+    import torch
+    for mix in (w.MIX_GEOMETRIC, w.MIX_ARITHMETIC, w.MIX_SIXTHPOWER):
+        s = w.random_molecules(4, 97, 34.0, kind="propane", min_dist=2.9).replace(mix=mix)
+        new = dict(eps_fg=np.array([0.21, 0.08]), sig_fg=np.array([3.7, 4.0]),
+                   eps_cg=np.array([0.0, 1.4]), sig_cg=np.array([0.0, 4.4]))
+        rr = make_relres(s, 64)
+        p = torch.from_numpy(s.pos).cuda()
+        rr.build_lists(p, s.box)
+        rr.set_type_params(new["eps_fg"], new["sig_fg"], new["eps_cg"], new["sig_cg"])
+        F1, E1, W1 = rr.forces(p)
+        r2 = make_relres(s.replace(**new), 64)
+        r2.build_lists(p, s.box)
+        F2, E2, W2 = r2.forces(p)
+        assert torch.equal(F1, F2) and torch.equal(E1, E2) and torch.equal(W1, W2), mix
+        rr.close()
+        r2.close()
+
+
+def test_type_params_validation_and_pair_table_state():
+    import torch
+    from paper_2104_10231_amd.relres import RelResError
+    s = w.random_molecules(4, 40, 34.0, kind="propane", min_dist=2.9)
+    rr = make_relres(s, 64)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)
+    # the hybrid types define the site list: an ordinary type stays ordinary
+    with pytest.raises(RelResError):
+        rr.set_type_params(s.eps_fg, s.sig_fg, np.array([0.5, 1.0]), np.array([4.0, 4.6]))
+    with pytest.raises(RelResError):
+        rr.set_type_params(s.eps_fg, s.sig_fg, np.array([0.0, 0.0]), s.sig_cg)
+    gpos, gt = rr.backward_types(p, torch.zeros_like(p), torch.ones(1, dtype=torch.float64))
+    assert gt.shape == (4, s.ntypes)
+    assert torch.all(gt[2:, 0] == 0.0)          # ordinary type: no CG gradient (Eq. 14)
+    # pair tables set directly have no per-type values to differentiate
+    ef = np.sqrt(np.outer(s.eps_fg, s.eps_fg))
+    sf = np.sqrt(np.outer(s.sig_fg, s.sig_fg))
+    ec = np.sqrt(np.outer(s.eps_cg, s.eps_cg))
+    sc = np.sqrt(np.outer(s.sig_cg, s.sig_cg))
+    rr.set_pair_params(ef, sf, ec, sc)
+    with pytest.raises(RelResError):
+        rr.backward_types(p, torch.zeros_like(p))
+    rr.close()
