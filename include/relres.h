@@ -265,6 +265,25 @@ int relres_moved_atoms(relres_ctx *ctx, const double *pos, void *stream, int *co
 int relres_forces(relres_ctx *ctx, const double *pos, void *forces, double *energy,
                   double *virial, void *stream);
 
+/* relres_forces for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The same kernels and results, bit for bit; the energy/virial scratch
+ * (launch epoch and per-block records) lives in a static device array of
+ * RELRES_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends, instead of context buffers.  Nothing is allocated or freed:
+ * the caller passes the outputs, and the lists come from the last
+ * relres_build_lists.  RELRES_ERR_ARG when the launch would need more scratch
+ * than the array holds (8 + 128 bytes per block of 256 threads; about 250k
+ * atoms at 4 lanes per row) or, with energy or virial requested, for several
+ * systems (their per-row partials need context buffers; forces only is
+ * fine).  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (several streams, threads or contexts at once) race and must be
+ * serialised by the caller.  No timing events are recorded.  Asynchronous on
+ * `stream`.                                                               */
+#define RELRES_NOALLOC_SCRATCH_BYTES (2 << 20)
+int relres_forces_noalloc(relres_ctx *ctx, const double *pos, void *forces, double *energy,
+                          double *virial, void *stream);
+
 /* Replace the pair parameters (Sec. 2.3 mixing bypassed): host arrays of
  * ntypes*ntypes doubles, row-major [a][b] (ordered entries; a symmetric
  * table describes the usual physics).  The FG entries need eps >= 0 and

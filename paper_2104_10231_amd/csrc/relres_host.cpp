@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -334,6 +335,8 @@ struct relres_ctx {
     double box[3] = {0, 0, 0};
 
     DBuf d_partials, d_epoch;
+    void* scratch = nullptr;          // this device's static scratch (relres_forces_noalloc)
+    hipError_t scratch_err = hipSuccess;
     int lanes_a = 0, lanes_b = 0;        // caller override, 0 = automatic
     int auto_la = 4, auto_lb = 16;
     // list kernel shape: rows per wave (atom, site grids) and candidates per
@@ -1030,6 +1033,30 @@ int take_warning(relres_ctx* c)
     return RELRES_WARN_DANGEROUS_BUILD;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (the array has one copy per GPU, at its own address).
+int scratch_of_device(int device, void** out, hipError_t* err)
+{
+    static std::mutex mu;
+    static std::vector<void*> addr;
+    static std::vector<hipError_t> errs;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return RELRES_ERR_ARG;
+    if ((size_t)device >= addr.size()) {
+        addr.resize(device + 1, nullptr);
+        errs.resize(device + 1, hipSuccess);
+    }
+    if (!addr[device] && errs[device] == hipSuccess) {
+        void* p = nullptr;
+        const hipError_t e = scratch_address(&p);
+        if (e != hipSuccess || !p) errs[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        else addr[device] = p;
+    }
+    *out = addr[device];
+    *err = errs[device];
+    return RELRES_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1176,6 +1203,10 @@ int relres_create(const relres_params* p, relres_ctx** out)
     c->gs.site = true;
     auto bail = [&](int rc) { relres_destroy(c); return rc; };
     if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(RELRES_ERR_HIP, "no HIP device"));
+    // the static scratch of relres_forces_noalloc, once per device (a failure
+    // only disables that entry point, which reports it)
+    if (scratch_of_device(c->device, &c->scratch, &c->scratch_err) != RELRES_OK)
+        return bail(fail(RELRES_ERR_HIP, "bad device %d", c->device));
     c->skin = p->skin;
     c->ntypes = nt;
     c->mix = p->mix;
@@ -1569,17 +1600,13 @@ int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* s
     return rc;
 }
 
-int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy, double* virial,
-                  void* stream)
+namespace {
+
+// Arguments of one force launch over the lists of the last build, with the
+// lane split of the context; energy/virial buffers are the caller's.
+ForceArgs force_args(const relres_ctx* c, const double* pos, void* forces, double* energy,
+                     double* virial)
 {
-    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
-    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
-    hipStream_t s = (hipStream_t)stream;
-    if (c->n == 0) {
-        if (energy || virial) HIP_TRY(launch_zero_outputs(energy, virial, c->nsys, s));
-        return RELRES_OK;
-    }
-    if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
     const bool sites = c->n_sites > 0;
     const int la = c->lanes_a ? c->lanes_a : c->auto_la;
     const int lb = c->lanes_b ? c->lanes_b : c->auto_lb;
@@ -1619,6 +1646,24 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     a.lanes_b = lb;
     a.log_lanes_a = log2i(la);
     a.log_lanes_b = log2i(lb);
+    return a;
+}
+
+}  // namespace
+
+int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy, double* virial,
+                  void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n == 0) {
+        if (energy || virial) HIP_TRY(launch_zero_outputs(energy, virial, c->nsys, s));
+        return RELRES_OK;
+    }
+    if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
+    const bool sites = c->n_sites > 0;
+    ForceArgs a = force_args(c, pos, forces, energy, virial);
     {
         // energy/virial records: a fresh buffer may hold another context's
         // records, whose tags could match this context's; clear it (tag 0)
@@ -1656,6 +1701,39 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
     }
     if (ew && c->nsys > 1)
         HIP_TRY(launch_reduce_sys_ew(c->d_grids.as<GridDev>(), sites ? 2 : 1, a, energy, virial, s));
+    return RELRES_OK;
+}
+
+int relres_forces_noalloc(relres_ctx* c, const double* pos, void* forces, double* energy,
+                          double* virial, void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    if (!c->built) return fail(RELRES_ERR_NO_LISTS, "no lists: call relres_build_lists first");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n == 0) {
+        if (energy || virial) HIP_TRY(launch_zero_outputs(energy, virial, c->nsys, s));
+        return RELRES_OK;
+    }
+    if (!pos || !forces) return fail(RELRES_ERR_ARG, "pos or forces is NULL");
+    const bool ew = energy || virial;
+    if (ew && c->nsys > 1)
+        return fail(RELRES_ERR_ARG, "relres_forces_noalloc: energy/virial of several systems need "
+                    "per-row buffers (use relres_forces, or pass NULL energy and virial)");
+    if (!c->scratch)
+        return fail(RELRES_ERR_HIP, "relres_forces_noalloc: no address for the static scratch "
+                    "on device %d: %s", c->device, hipGetErrorString(c->scratch_err));
+    ForceArgs a = force_args(c, pos, forces, energy, virial);
+    const size_t need = kScratchEpochBytes +
+                        (size_t)kEwRecBytes * (size_t)(a.blocks_a + a.blocks_b + kXcdGroups);
+    if (ew && need > kScratchBytes)
+        return fail(RELRES_ERR_ARG, "relres_forces_noalloc: this launch needs %zu bytes of "
+                    "energy/virial scratch, the static array holds %zu (fewer lanes per row "
+                    "or relres_forces)", need, (size_t)kScratchBytes);
+    // epoch first, records after it; records of earlier calls carry older
+    // tags (the epoch only advances), so nothing needs clearing
+    a.epoch = static_cast<unsigned int*>(c->scratch);
+    a.ew_rec = reinterpret_cast<unsigned long long*>(static_cast<char*>(c->scratch) + kScratchEpochBytes);
+    HIP_TRY(launch_forces(a, c->cut64, c->per_pair, c->pair_math, c->precision, ew, s));
     return RELRES_OK;
 }
 

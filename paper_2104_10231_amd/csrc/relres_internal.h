@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "relres.h"
+
 namespace relres {
 
 // A list entry packs the caller index of the neighbour (27 bits) and its atom
@@ -206,6 +208,12 @@ hipError_t launch_backward(const BackArgs& b, int waves, double* grad_pair, hipS
 hipError_t launch_type_grad(const double* gpair, const double* jac, int nt, double* gtype,
                             hipStream_t s);
 hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t s);
+// Static scratch of relres_forces_noalloc (relres_kernels.hip): 256 bytes of
+// launch epoch, then energy/virial records.  scratch_address() must be called
+// with the device current; it returns that device's copy.
+constexpr size_t kScratchBytes = RELRES_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kScratchEpochBytes = 256;
+hipError_t scratch_address(void** out);
 hipError_t launch_zero_outputs(double* energy, double* virial, int nsys, hipStream_t s);
 // nsys > 1: energy/virial of each system from the wave sums (and the row
 // partials of waves across a system boundary)

@@ -1906,6 +1906,18 @@ hipError_t launch_type_grad(const double* gpair, const double* jac, int nt, doub
     return hipGetLastError();
 }
 
+// Energy/virial scratch of relres_forces_noalloc, for callers that cannot
+// allocate: the launch epoch in its first 256 bytes, then the block and group
+// records of the force kernel.  One copy per GPU, zero at load, shared by
+// every call on that GPU (calls that overlap on one GPU race).  Host code
+// reaches it only through the address scratch_address() returns.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** out)
+{
+    return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 __global__ void k_clear_words(unsigned long long* p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;

@@ -86,6 +86,8 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_int)]),
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "relres_forces_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "relres_set_list_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int]),
@@ -353,6 +355,26 @@ class RelRes:
                                        energy.data_ptr() if energy is not None else None,
                                        virial.data_ptr() if virial is not None else None,
                                        _stream(stream)), "relres_forces")
+        return out, energy, virial
+
+    def forces_noalloc(self, pos: torch.Tensor, out: torch.Tensor,
+                       energy: Optional[torch.Tensor] = None,
+                       virial: Optional[torch.Tensor] = None, stream=None):
+        """relres_forces_noalloc: the caller passes every output (nothing is
+        allocated here or in the library); energy/virial may be None."""
+        pos = self._pos(pos)
+        dt = torch.float64 if self.precision == 64 else torch.float32
+        if out.dtype != dt or tuple(out.shape) != (self.n, 3) or not out.is_contiguous():
+            raise TypeError("out must be a contiguous (N, 3) tensor of the force dtype")
+        for t, n in ((energy, 3), (virial, 6)):
+            if t is not None and (t.numel() != n * self.nsys or not t.is_contiguous()
+                                  or t.dtype != torch.float64):
+                raise ValueError(f"energy/virial buffers need {n} x nsys contiguous doubles")
+        _check(self._lib.relres_forces_noalloc(
+            self._ctx, pos.data_ptr() if self.n else None, out.data_ptr() if self.n else None,
+            energy.data_ptr() if energy is not None else None,
+            virial.data_ptr() if virial is not None else None, _stream(stream)),
+            "relres_forces_noalloc")
         return out, energy, virial
 
     # -- parameters and gradients -------------------------------------------------
