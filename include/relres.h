@@ -58,6 +58,8 @@ extern "C" {
 #define RELRES_ERR_STATE           -9  /* call out of order                  */
 #define RELRES_ERR_LIST_RETRY     -10  /* asynchronous build overflowed: rows grown, build again */
 #define RELRES_ERR_STALE_LISTS    -11  /* dynamics: an atom moved more than half the skin between builds */
+#define RELRES_ERR_EW_TIMEOUT     -12  /* a force call gave up waiting for its cross-block energy/virial
+                                          sums (its energy and virial are NaN); see relres_sync */
 /* Warning (positive; the call succeeded): this build found atoms more than
  * half the skin from where they were at the previous build of the same
  * topology and boxes, so forces computed from the previous lists may have
@@ -244,6 +246,15 @@ int relres_build_lists_async(relres_ctx *ctx, const double *pos, const double bo
  * build that found atoms past half the skin (see relres_build_lists) give
  * RELRES_WARN_DANGEROUS_BUILD instead of RELRES_OK, once per such build.   */
 int relres_check_lists(relres_ctx *ctx);
+
+/* Waits for all work on `stream` and reports what force calls since the
+ * previous report left in the device status: RELRES_ERR_EW_TIMEOUT if the
+ * cross-block energy/virial reduction of some call (one system) gave up
+ * waiting for other blocks (a bounded wait; that call's energy and virial are
+ * NaN, its forces are valid).  relres_check_lists reports it too for calls
+ * enqueued before the build it examines.  Not allowed while `stream` is
+ * being captured (RELRES_ERR_STATE).                                       */
+int relres_sync(relres_ctx *ctx, void *stream);
 
 /* Number of atoms of pos (device, N x 3 FP64) that are more than half the
  * skin (minimum image, the box of their system) from where they were at the

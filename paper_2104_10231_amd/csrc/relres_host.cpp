@@ -322,6 +322,8 @@ struct relres_ctx {
     Status* h_query = nullptr;        // pinned landing place of relres_moved_atoms
     int nonfinite_seen = 0;
     unsigned moved_seen = 0;          // Status::moved at the last examination
+    unsigned ew_failed_seen = 0;      // Status::ew_failed at the last examination
+    int spin_limit = 1 << 22;         // polls before a cross-block energy/virial wait gives up
     bool ref_valid = false;           // wpos holds a previous build of this topology
     bool warn_pending = false;        // a build found atoms past half the skin, not yet reported
     bool stats_fresh = false;         // statistics describe the current lists
@@ -923,6 +925,17 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     return RELRES_OK;
 }
 
+// RELRES_ERR_EW_TIMEOUT once for force calls whose energy/virial wait gave up
+// since the previous examination (h_status must be current).
+int take_ew_failures(relres_ctx* c)
+{
+    const unsigned f = c->h_status->ew_failed;
+    if (f == c->ew_failed_seen) return RELRES_OK;
+    c->ew_failed_seen = f;
+    return fail(RELRES_ERR_EW_TIMEOUT, "an energy/virial reduction gave up waiting for other "
+                "blocks; the energy and virial of that call are NaN");
+}
+
 // Make h_status describe the last enqueued build: wait for its copy, or, for
 // a build captured into a graph (the caller has synchronised after the
 // replays), copy the accumulated status now.
@@ -1132,6 +1145,7 @@ const char* relres_strerror(int code)
     case RELRES_ERR_STATE: return "call out of order";
     case RELRES_ERR_LIST_RETRY: return "neighbour lists overflowed: capacity grown, build again";
     case RELRES_ERR_STALE_LISTS: return "an atom moved more than half the skin since the last list build";
+    case RELRES_ERR_EW_TIMEOUT: return "a force call gave up waiting for its energy/virial sums (they are NaN)";
     case RELRES_WARN_DANGEROUS_BUILD: return "warning: atoms had moved more than half the skin since the previous build";
     default: return "unknown error";
     }
@@ -1208,6 +1222,9 @@ int relres_create(const relres_params* p, relres_ctx** out)
     if (scratch_of_device(c->device, &c->scratch, &c->scratch_err) != RELRES_OK)
         return bail(fail(RELRES_ERR_HIP, "bad device %d", c->device));
     c->skin = p->skin;
+    // RELRES_EW_SPIN_LIMIT: polls of a cross-block energy/virial wait before it
+    // gives up (a negative value gives up at once: failure handling tests)
+    if (const char* e = std::getenv("RELRES_EW_SPIN_LIMIT")) c->spin_limit = std::atoi(e);
     c->ntypes = nt;
     c->mix = p->mix;
     c->no_shift = p->no_shift;
@@ -1428,7 +1445,24 @@ int relres_check_lists(relres_ctx* c)
 {
     if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
     TRY(examine_status(c));
+    // the status copy just examined also shows force calls enqueued before
+    // the build whose energy/virial wait gave up
+    TRY(take_ew_failures(c));
     return take_warning(c);
+}
+
+int relres_sync(relres_ctx* c, void* stream)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &capture));
+    if (capture != hipStreamCaptureStatusNone)
+        return fail(RELRES_ERR_STATE, "relres_sync on a stream that is being captured");
+    HIP_TRY(hipStreamSynchronize(s));
+    // the status only accumulates: a newer copy serves a pending build check too
+    HIP_TRY(hipMemcpy(c->h_status, c->d_status.p, sizeof(Status), hipMemcpyDeviceToHost));
+    return take_ew_failures(c);
 }
 
 int relres_moved_atoms(relres_ctx* c, const double* pos, void* stream, int* count)
@@ -1646,6 +1680,9 @@ ForceArgs force_args(const relres_ctx* c, const double* pos, void* forces, doubl
     a.lanes_b = lb;
     a.log_lanes_a = log2i(la);
     a.log_lanes_b = log2i(lb);
+    a.ew_failed = reinterpret_cast<unsigned int*>(static_cast<char*>(c->d_status.p) +
+                                                  offsetof(Status, ew_failed));
+    a.spin_limit = c->spin_limit;
     return a;
 }
 

@@ -118,6 +118,8 @@ struct Status {
     unsigned long long entries[2];  // entries per grid (k_list_stats)
     unsigned moved_query;           // the same count for relres_moved_atoms
     unsigned pad;
+    unsigned ew_failed;             // cumulative count of energy/virial waits that gave up
+    unsigned pad2;
 };
 
 struct ForceArgs {
@@ -153,6 +155,8 @@ struct ForceArgs {
     double* virial;           // [nsys][6] or null
     unsigned long long* ew_rec;   // energy/virial records: one per block, then one per group
     unsigned int* epoch;          // launch epoch, advanced by every energy/virial launch
+    unsigned int* ew_failed;      // Status::ew_failed, counted by a wait that gave up
+    int spin_limit;               // polls of a cross-block wait before it gives up (< 0: at once)
     int blocks_a, blocks_b;   // multiples of 8
     int lanes_a, lanes_b;     // lanes per row (powers of two)
     int log_lanes_a, log_lanes_b;

@@ -1058,11 +1058,12 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
 // sum; block nb-1 (the highest of all) then waits for the group records and
 // writes energy and virial.  A waiting block only ever waits for blocks with
 // lower numbers, which the hardware dispatched before it, so every wait ends;
-// it is bounded anyway (kSpinLimit polls), after which energy and virial are
-// set to NaN.  Sums are taken in a fixed order: the result does not depend on
-// which block finished when.
+// it is bounded anyway (a.spin_limit polls; a negative limit gives up at
+// once), after which energy and virial are set to NaN and the status counts
+// the failure, which the host reports (relres_sync, relres_check_lists).
+// Sums are taken in a fixed order: the result does not depend on which block
+// finished when.
 constexpr int kRecWords = 16;
-constexpr int kSpinLimit = 1 << 22;
 constexpr int kPollBatch = 16;   // records polled per thread at once
 
 // Writes one record: called by the whole block, `v` valid in threads 0..7
@@ -1091,7 +1092,8 @@ __device__ __forceinline__ void put_record(unsigned long long* rec, double v, un
 // summed over their records in v[]; odd lanes hold zeros.  Sets *failed if a
 // wait gave up.
 __device__ __forceinline__ void gather_records(const unsigned long long* rec, int first, int stride,
-                                               int count, unsigned tag, double v[8], int* failed)
+                                               int count, unsigned tag, int spin_limit,
+                                               double v[8], int* failed)
 {
     const int t = (int)threadIdx.x;
     const int word = t & (kRecWords - 1);
@@ -1118,8 +1120,9 @@ __device__ __forceinline__ void gather_records(const unsigned long long* rec, in
 #pragma unroll
             for (int u = 0; u < kPollBatch; ++u)
                 pending |= valid[u] && (unsigned)(w[u] >> 32) != tag;
+            pending |= spin_limit < 0 && count > 0;   // give up at once
             if (!pending) break;
-            if (it >= kSpinLimit) {
+            if (it >= spin_limit) {
                 *failed = 1;
                 break;
             }
@@ -1177,10 +1180,11 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     }
     // group g: members g, g+8, ..., b-8 (in that order), then this block
     double v[8];
-    gather_records(a.ew_rec, g, kXcdGroups, b / kXcdGroups, tag, v, &failed);
+    gather_records(a.ew_rec, g, kXcdGroups, b / kXcdGroups, tag, a.spin_limit, v, &failed);
     const double gsum = block_reduce8(v, mine, red);
     if (b != nb - 1) {
         put_record(grec + (size_t)g * kRecWords, failed ? __builtin_nan("") : gsum, tag);
+        if (threadIdx.x == 0 && failed) atomicAdd(a.ew_failed, 1u);
         return;
     }
     // final block: the group sums in group order.  The other groups' records
@@ -1196,8 +1200,8 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
             for (int it = 0;; ++it) {
                 w = __hip_atomic_load(grec + (size_t)q * kRecWords + word, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
-                if ((unsigned)(w >> 32) == tag) break;
-                if (it >= kSpinLimit) {
+                if ((unsigned)(w >> 32) == tag && a.spin_limit >= 0) break;
+                if (it >= a.spin_limit) {
                     failed = 1;
                     break;
                 }
@@ -1216,6 +1220,7 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     }
     __syncthreads();
     const bool bad = failed != 0;
+    if (threadIdx.x == 0 && bad) atomicAdd(a.ew_failed, 1u);
     if (threadIdx.x < 8) {
         const double val = bad ? __builtin_nan("") : red[threadIdx.x][0];
         if (threadIdx.x < 2 && a.energy) a.energy[1 + threadIdx.x] = val;

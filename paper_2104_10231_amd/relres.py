@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "librelres_hip.so")
 RELRES_OK = 0
 RELRES_ERR_LIST_RETRY = -10
 RELRES_ERR_STALE_LISTS = -11
+RELRES_ERR_EW_TIMEOUT = -12
 RELRES_WARN_DANGEROUS_BUILD = 1
 FTM2V_REAL = 4.184e-4          # (kcal/mol/A) / amu -> A/fs^2
 KB_REAL = 0.0019872067         # kcal/mol/K
@@ -82,6 +83,7 @@ SIGNATURES = {
     "relres_build_lists_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
                                                 ctypes.c_void_p]),
     "relres_check_lists": (ctypes.c_int, [ctypes.c_void_p]),
+    "relres_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "relres_moved_atoms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_int)]),
     "relres_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -320,6 +322,11 @@ class RelRes:
         if not self.last_check_dangerous:
             _check(rc, "relres_check_lists")
         return True
+
+    def sync(self, stream=None):
+        """Wait for the stream; raises if a force call's energy/virial wait
+        gave up since the last report (relres_sync)."""
+        _check(self._lib.relres_sync(self._ctx, _stream(stream)), "relres_sync")
 
     def moved_atoms(self, pos: torch.Tensor, stream=None) -> int:
         """Atoms of pos more than half the skin from their positions at the

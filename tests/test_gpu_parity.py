@@ -349,6 +349,38 @@ def test_errors_are_reported():
     rr.close()
 
 
+def test_energy_virial_wait_failure_is_reported(monkeypatch):
+    """The cross-block energy/virial wait is bounded; a wait that gives up
+    leaves NaN energy/virial and is reported by relres_sync.  Forced from the
+    host: a negative spin limit makes every waiting block give up at once, so
+    no kernel ever waits."""
+    import torch
+    from paper_2104_10231_amd.relres import RelResError, RELRES_ERR_EW_TIMEOUT
+    s = w.propane_liquid(0)
+    p = torch.from_numpy(s.pos).cuda()
+    monkeypatch.setenv("RELRES_EW_SPIN_LIMIT", "-1")
+    rr = make_relres(s, 64)                    # the limit is read when the context is made
+    monkeypatch.delenv("RELRES_EW_SPIN_LIMIT")
+    rr.build_lists(p, s.box)
+    F, E, W = rr.forces(p)
+    with pytest.raises(RelResError) as e:
+        rr.sync()
+    assert e.value.code == RELRES_ERR_EW_TIMEOUT
+    assert torch.isnan(E[0]) and torch.isnan(W).any()
+    Fr, Er, Wr = oracle.compute(s)
+    assert rel_rms(F.double().cpu().numpy(), Fr) <= 1e-11      # forces are unaffected
+    rr.sync()                                  # reported once
+    F2, E2, W2 = rr.forces(p, want_energy=False, want_virial=False)
+    rr.sync()                                  # no energy asked: nothing waits
+    rr.close()
+    ok = make_relres(s, 64)
+    ok.build_lists(p, s.box)
+    F3, E3, W3 = ok.forces(p)
+    ok.sync()
+    assert abs(E3[0].item() - Er[0]) <= 1e-12 * abs(Er[0])
+    ok.close()
+
+
 def test_crowded_cells_need_several_passes():
     """Cells holding more than 64 atoms while the mean occupancy is low: the
     one-wave-per-cell builder loops over home atoms in passes of 64."""
