@@ -211,6 +211,49 @@ def time_kernels(rr, pos, box, force_calls, builds=20):
     return force_us, build_us, cycle_us
 
 
+def batch_roofline(pair_math):
+    """Roofline of the force launch at a size where it is not bound by the
+    launch floor: the 256-replica batch (1.2 M atoms) in one context at the
+    automatic kernel shapes, forces with energy and virial per replica, HIP
+    events around replays of a graph of 10 launches (the per-system energy
+    reduction kernel included)."""
+    import torch
+    import workloads as w
+    b = w.replica_batch(0, skin_max=2.0)
+    pos = torch.from_numpy(b.whole.pos).cuda()
+    rr = make(b.whole, 32, pair_math)
+    rr.set_systems(b.offsets)
+    rr.set_skins(b.skins)
+    rr.build_lists(pos, b.boxes)
+    F = torch.empty((b.whole.n, 3), dtype=torch.float32, device="cuda")
+    E = torch.empty((b.nsys, 3), dtype=torch.float64, device="cuda")
+    W = torch.empty((b.nsys, 6), dtype=torch.float64, device="cuda")
+    rr.forces(pos, out=F, energy=E, virial=W)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(10):
+            rr.forces(pos, out=F, energy=E, virial=W)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / 50
+    st = rr.stats()
+    rr.close()
+    abytes = algorithmic_bytes(st, 4)
+    achieved = abytes / (us * 1e-6) / 1e9
+    return {"workload": f"replica_batch: {b.nsys} replicas, {b.whole.n} atoms",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": "k_forces + k_reduce_sys_ew",
+            "kernel_us": us, "algorithmic_bytes_per_launch": abytes,
+            "list_entries": st["atom_entries"] + st["site_entries"]}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -222,7 +265,13 @@ def cpu_model():
     return "unknown"
 
 
-def pair_counts(rr, sys_, pos_np):
+def boxes_by_atom(b):
+    """The box of every atom of a batch (N x 3)."""
+    import numpy as np
+    return np.repeat(np.asarray(b.boxes, np.float64).reshape(-1, 3), np.diff(b.offsets), axis=0)
+
+
+def pair_counts(rr, sys_, pos_np, box_of_atom=None):
     """Ordered pairs of the lists by regime of Eq. 20, for the FLOP count of
     the roofline: list entries, pairs inside r_s+ (atom list) or r_c+ (site
     list) and pairs inside a smoothing zone ([r_s-, r_s+) of the atom list,
@@ -238,7 +287,8 @@ def pair_counts(rr, sys_, pos_np):
             out[name] = (0, 0, 0)
             continue
         d = pos_np[pr[:, 0]] - pos_np[pr[:, 1]]
-        d -= box * np.rint(d / box)
+        bx = box if box_of_atom is None else box_of_atom[pr[:, 0]]
+        d -= bx * np.rint(d / bx)
         r = np.sqrt((d * d).sum(1))
         if name == "atom":
             inside = r < sys_.rs_out
@@ -523,6 +573,7 @@ def batch_bench(args):
         cycle()
     dt_b = time.perf_counter() - t0
     st = rr.stats()
+    counts = pair_counts(rr, b.whole, b.whole.pos, boxes_by_atom(b))
     # force launch alone, graph of back-to-back launches
     fg = torch.cuda.CUDAGraph()
     with torch.cuda.graph(fg):
@@ -545,6 +596,8 @@ def batch_bench(args):
     fb = 4
     abytes = algorithmic_bytes(st, fb)
     achieved = abytes / (force_us * 1e-6) / 1e9
+    aflops = algorithmic_flops(counts)
+    tflops = aflops / (force_us * 1e-6) / 1e12
     log(f"[bench] batch: {dt_b * 1e3 / (cycles * every):.4f} ms/step batched, "
         + ("" if dt_s is None else f"{dt_s * 1e3 / (cycles * every):.4f} ms/step sequential; ")
         + f"force launch {force_us:.1f} us")
@@ -575,7 +628,13 @@ def batch_bench(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_forces",
                      "kernel_us": force_us, "algorithmic_bytes_per_launch": abytes},
+        "roofline_other": {"bound": "alu", "achieved": tflops, "peak": FP64_VALU_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": tflops / FP64_VALU_PEAK_TFLOPS,
+                           "valu": "fp64 vector (pair terms of calls with energy/virial)",
+                           "algorithmic_flops_per_launch": aflops},
         "list_entries": st["atom_entries"] + st["site_entries"],
+        "pairs_by_regime": {k: dict(zip(("entries", "inside_cutoff", "smoothing_zone"), v))
+                            for k, v in counts.items()},
     }
     print(json.dumps(out), flush=True)
 
@@ -595,6 +654,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-conventional", action="store_true")
+    ap.add_argument("--no-batch-roofline", action="store_true",
+                    help="skip the force-launch roofline of the 256-replica batch")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every force call eagerly instead of replaying a HIP graph")
@@ -709,6 +770,11 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 5 x {nbytes} B read + {nbytes} B written")
 
+    big = None if args.no_batch_roofline else batch_roofline(args.pair_math)
+    if big:
+        log(f"[bench] batch force launch {big['kernel_us']:.1f} us, {big['achieved']:.0f} GB/s "
+            f"algorithmic ({100 * big['frac']:.1f} % of HBM)")
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(s, args.cpu_budget)
     if cpu:
         log(f"[bench] cpu oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads "
@@ -763,6 +829,7 @@ def main():
         "ms_per_step_runs": [x * 1e3 / args.steps for x in R["times"]],
         "roofline": primary,
         "roofline_other": secondary,
+        "roofline_batch": big,
         "kernel_sum_us_per_step": force_us + build_us / args.rebuild_every,
         "cycle_us": R["cycle_us"],
         "cpu_baseline": cpu,

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RELRES_ABI_VERSION 5
+#define RELRES_ABI_VERSION 6
 
 #define RELRES_OK                   0
 #define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
@@ -446,6 +446,15 @@ int relres_set_launch(relres_ctx *ctx, int lanes_atom, int lanes_site);
  * row) do not depend on it.  Overrides persist until changed.               */
 int relres_set_list_launch(relres_ctx *ctx, int rows_atom, int rows_site, int cand_per_lane);
 
+/* Cell size of the list grids (Sec. 2.6 cell lists): cells per list radius
+ * along an axis for the atom grid and for the site grid, 1 (cells of at least
+ * the list radius, a 27-cell stencil) or 2 (cells of at least half of it, a
+ * 125-cell stencil: about 42 % less volume to search per row, more cells and
+ * fewer rows sharing a stencil), 0 = automatic (1).  Takes effect at the next
+ * build; the pair sets do not depend on it (the order of a row's entries
+ * does).  Overrides persist until changed.                                 */
+int relres_set_cells(relres_ctx *ctx, int div_atom, int div_site);
+
 /* Result of relres_autotune (host struct).  Chosen shapes (resolved, never
  * 0), mean device times of the chosen and of the automatic shapes, and the
  * number of shapes timed.                                                   */
@@ -455,17 +464,19 @@ typedef struct relres_tune {
     int trials;
     double build_us, build_us_auto;            /* one list build              */
     double force_us, force_us_auto;            /* one force call with E and W */
+    int cell_div_atom, cell_div_site;          /* cells per list radius       */
 } relres_tune;
 
-/* Autotuner for the caller's own workload: times list builds for every list
- * kernel shape (rows per wave 4/8/16 for each grid x 2/4 candidates per
- * lane, and the automatic shape) on the device positions pos and box(es),
+/* Autotuner for the caller's own workload: times list builds for every cell
+ * size of each grid (relres_set_cells 1 or 2) and list kernel shape (rows per
+ * wave 4/8/16 for each grid x 2/4 candidates per lane), and the automatic
+ * choice, on the device positions pos and box(es),
  * keeps the fastest, rebuilds, then times force calls (with energy and
  * virial) for lanes per row 2..16 (atom rows) x 2..32 (hybrid rows) and the
  * automatic choice, and keeps the fastest.  Each shape: one untimed call,
  * then reps (1..1000) timed with HIP events on `stream`.  Leaves valid lists
- * built from pos and the chosen shapes set (as by relres_set_list_launch and
- * relres_set_launch).  Synchronises; allocates temporary force, energy and
+ * built from pos and the chosen shapes set (as by relres_set_cells,
+ * relres_set_list_launch and relres_set_launch).  Synchronises; allocates temporary force, energy and
  * virial buffers; must not run on a capturing stream (RELRES_ERR_STATE).
  * Resets the relres_get_timing tallies.  Writes *out.  On an error the
  * shapes set before the call are restored; build the lists again before the

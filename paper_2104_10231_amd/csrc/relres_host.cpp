@@ -259,6 +259,8 @@ struct GridHost {
     int members = 0;                  // members of all grids
     int waves = 0;                    // list-kernel waves (rpw rows each)
     int rpw = 8;                      // home rows per list-kernel wave
+    int div = 1;                      // cells per list radius along an axis: 1 (27-cell
+                                      // stencil) or 2 (cells of half the radius, 125 cells)
     bool site = false;                // the site grid (hybrid atoms)
     int n[3] = {0, 0, 0};             // cells per axis of system 0 (statistics)
     std::vector<int> sys_n;           // [nsys][3] cells per axis
@@ -344,6 +346,9 @@ struct relres_ctx {
     // list kernel shape: rows per wave (atom, site grids) and candidates per
     // lane; caller or autotuner override, 0 = automatic
     int rows_a = 0, rows_s = 0, cand = 0;
+    // cells per list radius of the atom and the site grid (relres_set_cells
+    // or the autotuner; 0 = automatic, which is 1)
+    int div_a = 0, div_s = 0;
 
     relres_stats stats{};
     long long alloc_generation = 0;
@@ -554,20 +559,22 @@ int list_rows_per_wave(bool site, long long members, long long launch_rows, int 
 }
 
 // launch_rows: rows of both grids (they share the list-kernel launch);
-// rows_per_wave: of the list kernel, 0 = automatic
+// rows_per_wave: of the list kernel, 0 = automatic; div: cells per list
+// radius (1 or 2)
 int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector<double>& skin_sys,
                int nsys, const double* boxes, const int* members_sys, long long launch_rows,
-               int rows_per_wave, long long* gen)
+               int rows_per_wave, int div, long long* gen)
 {
     // cells per axis of every system: a cell edge is at least the list radius
-    // (with a margin far above rounding), so every pair within rl lies in
-    // neighbouring cells
+    // divided by div (with a margin far above rounding), so every pair within
+    // rl lies within div cells along each axis: the 27-cell stencil (div 1)
+    // or the 125-cell stencil (div 2) holds it
     std::vector<int> nn((size_t)nsys * 3);
     for (int sy = 0; sy < nsys; ++sy) {
         int* n = &nn[(size_t)sy * 3];
         long long total = 1;
         for (int k = 0; k < 3; ++k) {
-            n[k] = (int)std::floor(boxes[3 * sy + k] / (rl_sys[sy] * (1.0 + 1e-10)));
+            n[k] = (int)std::floor(boxes[3 * sy + k] * div / (rl_sys[sy] * (1.0 + 1e-10)));
             n[k] = std::max(1, std::min(n[k], 1023));
             total *= n[k];
         }
@@ -585,7 +592,7 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
         if (cell_base[sy] + cells > (1ll << 30)) return fail(RELRES_ERR_ARG, "too many cells");
         cell_base[sy + 1] = cell_base[sy] + (int)cells;
     }
-    const bool same = g.nsys == nsys && g.sys_n == nn && g.rank_of_lin.p;
+    const bool same = g.nsys == nsys && g.sys_n == nn && g.rank_of_lin.p && g.div == div;
     double rl = 0.0;
     for (int sy = 0; sy < nsys; ++sy) rl = std::max(rl, rl_sys[sy]);
     g.rl = rl;
@@ -594,7 +601,9 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
         HIP_TRY(hipDeviceSynchronize());
         const int total = cell_base[nsys];
         std::vector<int> rank_of_lin(total), lin_of_rank(total), cell_sys(total);
-        std::vector<int> nbr((size_t)total * 27, -1);
+        // the 27-cell stencil is tabulated; the list kernel derives the
+        // 125-cell one from the cell coordinates
+        std::vector<int> nbr(div == 1 ? (size_t)total * 27 : 0, -1);
         for (int sy = 0; sy < nsys; ++sy) {
             const int* n = &nn[(size_t)sy * 3];
             const int cb = cell_base[sy];
@@ -614,6 +623,7 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
                 cell_sys[cb + r] = sy;
             }
             for (int lin = 0; lin < nc; ++lin) rank_of_lin[cb + lin] = cb + rank[lin];
+            if (div != 1) continue;
             // stencil ranks per cell; distinct offsets per axis (n = 1, 2 or >= 3)
             int noff[3], off[3][3];
             for (int k = 0; k < 3; ++k) {
@@ -634,19 +644,21 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
                 }
             }
         }
-        TRY(ensure(g.nbr, sizeof(int) * nbr.size(), gen));
+        TRY(ensure(g.nbr, sizeof(int) * std::max<size_t>(1, nbr.size()), gen));
         TRY(ensure(g.rank_of_lin, sizeof(int) * total, gen));
         TRY(ensure(g.lin_of_rank, sizeof(int) * total, gen));
         TRY(ensure(g.cell_sys, sizeof(int) * total, gen));
         TRY(ensure(g.count, sizeof(int) * total, gen));
         TRY(ensure(g.start, sizeof(int) * (total + 1), gen));
-        HIP_TRY(hipMemcpy(g.nbr.p, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
+        if (!nbr.empty())
+            HIP_TRY(hipMemcpy(g.nbr.p, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(g.rank_of_lin.p, rank_of_lin.data(), sizeof(int) * total, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(g.lin_of_rank.p, lin_of_rank.data(), sizeof(int) * total, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(g.cell_sys.p, cell_sys.data(), sizeof(int) * total, hipMemcpyHostToDevice));
         HIP_TRY(hipMemset(g.count.p, 0, sizeof(int) * total));
         g.nsys = nsys;
         g.sys_n = nn;
+        g.div = div;
         g.ncell = total;
     }
     // rows and list-kernel waves of every grid
@@ -712,6 +724,7 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
     d.rank_of_lin = g.rank_of_lin.as<int>();
     d.lin_of_rank = g.lin_of_rank.as<int>();
     d.nbr = g.nbr.as<int>();
+    d.stencil = g.div == 1 ? 3 : 5;
     d.count = g.count.as<int>();
     d.start = g.start.as<int>();
     d.user_unsorted = g.user_unsorted.as<int>();
@@ -852,10 +865,10 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     const int dims_before = c->ga.ncell + (sites ? c->gs.ncell : 0);
     const long long launch_rows = (long long)c->n + c->n_sites;
     TRY(setup_grid(c->ga, rla, skin_sys, ns, box, c->atoms_sys.data(), launch_rows, c->rows_a,
-                   &c->alloc_generation));
+                   c->div_a ? c->div_a : 1, &c->alloc_generation));
     if (sites)
         TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), launch_rows, c->rows_s,
-                       &c->alloc_generation));
+                       c->div_s ? c->div_s : 1, &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
     const void* wpos_before = c->d_wpos.p;
     TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
@@ -896,7 +909,8 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->ga.waves, sites ? c->gs.waves : 0, topo,
                              c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
-                             c->d_status.as<Status>(), lists_per_wave(c), c->cand, s));
+                             c->d_status.as<Status>(), lists_per_wave(c), c->cand,
+                             c->ga.div == 2 ? 5 : 3, (sites && c->gs.div == 2) ? 5 : 3, s));
         // A captured build copies nothing: the status only accumulates (see
         // Status), so relres_check_lists copies it once after the caller has
         // synchronised, covering every replay since the previous check.
@@ -984,14 +998,14 @@ int examine_status(relres_ctx* c)
         std::vector<double> skin_sys, rla, rls;
         list_radii(c, skin_sys, rla, rls);
         TRY(setup_grid(c->ga, rla, skin_sys, c->nsys, c->boxes.data(), c->atoms_sys.data(),
-                       (long long)c->n + c->n_sites, c->rows_a, &c->alloc_generation));
+                       (long long)c->n + c->n_sites, c->rows_a, c->ga.div, &c->alloc_generation));
     }
     if (ov_s) {
         c->gs.cap = ((int)(mr_s * 1.25) + 8 + 7) & ~7;
         std::vector<double> skin_sys, rla, rls;
         list_radii(c, skin_sys, rla, rls);
         TRY(setup_grid(c->gs, rls, skin_sys, c->nsys, c->boxes.data(), c->sites_sys.data(),
-                       (long long)c->n + c->n_sites, c->rows_s, &c->alloc_generation));
+                       (long long)c->n + c->n_sites, c->rows_s, c->gs.div, &c->alloc_generation));
     }
     c->stats.regrows++;
     c->lanes_stale = true;
@@ -1515,6 +1529,17 @@ int relres_set_list_launch(relres_ctx* c, int rows_atom, int rows_site, int cand
     return RELRES_OK;
 }
 
+int relres_set_cells(relres_ctx* c, int div_atom, int div_site)
+{
+    if (!c) return fail(RELRES_ERR_ARG, "ctx is NULL");
+    for (int v : {div_atom, div_site})
+        if (v < 0 || v > 2)
+            return fail(RELRES_ERR_ARG, "cells per list radius must be 0 (automatic), 1 or 2");
+    c->div_a = div_atom;
+    c->div_s = div_site;
+    return RELRES_OK;
+}
+
 int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* stream, int reps,
                     relres_tune* out)
 {
@@ -1562,15 +1587,22 @@ int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* s
         if (c->n == 0) return RELRES_OK;
         // list kernel: rows per wave of each grid and candidates per lane;
         // the automatic choice first, as the reference point
-        struct ListShape { int ra, rs, k; };
-        std::vector<ListShape> shapes{{0, 0, 0}};
-        for (int k : {2, 4})
-            for (int ra : {4, 8, 16})
-                for (int rs : {4, 8, 16})
-                    if (sites || rs == ra) shapes.push_back({ra, rs, k});
+        // and the cell size of each grid (one or half a list radius), grid
+        // by grid outermost so the cell tables are rebuilt only when it changes
+        struct ListShape { int da, ds, ra, rs, k; };
+        std::vector<ListShape> shapes{{0, 0, 0, 0, 0}};
+        for (int da : {1, 2})
+            for (int ds : {1, 2}) {
+                if (!sites && ds != da) continue;
+                for (int k : {2, 4})
+                    for (int ra : {4, 8, 16})
+                        for (int rs : {4, 8, 16})
+                            if (sites || rs == ra) shapes.push_back({da, ds, ra, rs, k});
+            }
         double best = 0.0;
-        ListShape pick{0, 0, 0};
+        ListShape pick{0, 0, 0, 0, 0};
         for (size_t i = 0; i < shapes.size(); ++i) {
+            TRY(relres_set_cells(c, shapes[i].da, shapes[i].ds));
             TRY(relres_set_list_launch(c, shapes[i].ra, shapes[i].rs, shapes[i].k));
             double us = 0.0;
             TRY(time_builds(us));
@@ -1581,9 +1613,12 @@ int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* s
             }
             out->trials++;
         }
+        TRY(relres_set_cells(c, pick.da, pick.ds));
         TRY(relres_set_list_launch(c, pick.ra, pick.rs, pick.k));
         TRY(build_checked(c, pos, box, s));
         out->build_us = best;
+        out->cell_div_atom = c->ga.div;
+        out->cell_div_site = sites ? c->gs.div : 0;
         out->rows_atom = c->ga.rpw;
         out->rows_site = sites ? c->gs.rpw : 0;
         out->cand_per_lane = list_candidates(c->ga.waves + (sites ? c->gs.waves : 0), c->cand);
@@ -1614,7 +1649,8 @@ int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* s
         out->lanes_site = lpick.second ? lpick.second : c->auto_lb;
         return RELRES_OK;
     };
-    const int saved[5] = {c->rows_a, c->rows_s, c->cand, c->lanes_a, c->lanes_b};
+    const int saved[7] = {c->rows_a, c->rows_s, c->cand, c->lanes_a, c->lanes_b, c->div_a,
+                          c->div_s};
     rc = run();
     if (rc != RELRES_OK) {            // the caller's shapes again, not a trial's
         c->rows_a = saved[0];
@@ -1622,6 +1658,8 @@ int relres_autotune(relres_ctx* c, const double* pos, const double* box, void* s
         c->cand = saved[2];
         c->lanes_a = saved[3];
         c->lanes_b = saved[4];
+        c->div_a = saved[5];
+        c->div_s = saved[6];
     }
     const hipError_t sync = hipStreamSynchronize(s);   // temporaries are idle before release
     release(f);

@@ -78,7 +78,10 @@ struct GridDev {
     const int* cell_sys;      // [ncell] system of each cell
     const int* rank_of_lin;   // [cell_base + local linear index] -> global cell rank
     const int* lin_of_rank;   // [global cell rank] -> local linear index
-    const int* nbr;           // ncell x 27 stencil ranks (-1: slot unused after deduplication)
+    const int* nbr;           // ncell x 27 stencil ranks (-1: slot unused after deduplication);
+                              // only for stencil 3
+    int stencil;              // cells per axis of the list stencil: 3 (cells of at least the
+                              // list radius) or 5 (cells of at least half of it)
     int* count;               // per cell (by rank); zero between builds
     int* start;               // ncell + 1 exclusive offsets (by rank)
     int* user_unsorted;       // member caller indices, cell-grouped
@@ -186,9 +189,11 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, lon
 // Candidates per lane of the row-group list kernel (2 or 4) for a launch of
 // total_waves waves; cand = 2 or 4 forces the value, 0 chooses it.
 int list_candidates(int total_waves, int cand);
+// stencil_a, stencil_s: 3 or 5 (GridDev::stencil of each grid); the
+// block-per-cell kernel only serves two 27-cell stencils
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
                         TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
-                        bool per_wave, int cand, hipStream_t s);
+                        bool per_wave, int cand, int stencil_a, int stencil_s, hipStream_t s);
 // cut64 = {r_s-, r_s+, r_c-, r_c+, and their squares} of every type pair, or
 // per_pair: the distances of each type pair come from a.pcut32 / a.pcut64
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, bool per_pair, int pair_math,

@@ -462,49 +462,78 @@ __device__ __forceinline__ bool member_shifted(double xi, double yi, double zi, 
     return r2 < rl2;
 }
 
-// Neighbour lists, one wave per group of kRowsPerWave consecutive member rows
-// (rows are in cell order, so a group spans one or two cells).  Work per wave
-// is bounded by the group size, so crowded cells are spread over many waves.
+constexpr int kResidentListWaves = 256 * 4 * 3;
+
+// Stencil geometry: S cells per axis around the home cell (3 for cells of at
+// least the list radius, 5 for cells of at least half of it), S^3 slots in
+// x-major order, slot tables of kSlotTab entries per wave.
+template <int S>
+struct Stencil {
+    static constexpr int kHalf = S / 2;
+    static constexpr int kSlots = S * S * S;
+    static constexpr int kTab = S == 3 ? 32 : 128;
+    static constexpr int kPerLane = S == 3 ? 1 : 2;   // slots a lane holds: lane, lane + 64
+    // the offset of slot s along axis a (0 = x) in cells
+    static __device__ __forceinline__ int off(int s, int a)
+    {
+        const int d = a == 0 ? s / (S * S) : (a == 1 ? (s / S) % S : s % S);
+        return d - kHalf;
+    }
+};
+
+// Global rank of the cell at offset (ox, oy, oz) from the cell (hx, hy, hz)
+// of a grid of n cells per axis, or -1 when the offset repeats a cell that a
+// smaller offset already reaches (an axis of fewer than S cells keeps its
+// first n offsets, which reach every cell once).
+template <int S>
+__device__ __forceinline__ int stencil_rank(const GeomDev& G, RELRES_GLOBAL const int* grank,
+                                            int hx, int hy, int hz, int s)
+{
+    using St = Stencil<S>;
+    if (s >= St::kSlots) return -1;
+    const int ox = St::off(s, 0), oy = St::off(s, 1), oz = St::off(s, 2);
+    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+    if ((n0 < S && ox + St::kHalf >= n0) || (n1 < S && oy + St::kHalf >= n1) ||
+        (n2 < S && oz + St::kHalf >= n2))
+        return -1;
+    const int x = (hx + ox + 2 * n0) % n0, y = (hy + oy + 2 * n1) % n1, z = (hz + oz + 2 * n2) % n2;
+    return grank[G.cell_base + (x * n1 + y) * n2 + z];
+}
+
+// Neighbour lists, one wave per group of R consecutive member rows (rows are
+// in cell order, so a group spans one or a few cells).  Work per wave is
+// bounded by the group size, so crowded cells are spread over many waves.
 // Each lane owns one home row of the group: its position, exclusions and
 // running count live in that lane and are broadcast with readlane.  The
 // candidates of the home cell's stencil are loaded straight into registers,
 // K per lane per round (candidate q in lane q % 64), and every home row of
 // the cell tests them there, so a candidate is read from memory once per cell
 // and never through LDS.  A larger K takes fewer rounds but more registers:
-// it pays when all waves of the launch are resident at once.  Candidates are visited in stencil-slot
-// order, each row's entries are appended in that order with a wave ballot.
-// Only wave-level synchronisation is used, so waves of one block may run
-// different trip counts.
-constexpr int kResidentListWaves = 256 * 4 * 3;
-
-template <int K>
-__global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ grids,
-                                                    int waves_a, int waves_total, int max_excl,
-                                                    TopoDev topo,
-                                                    const int* __restrict__ user2arow,
-                                                    int4* __restrict__ a_rec,
-                                                    int4* __restrict__ s_rec,
-                                                    Status* __restrict__ st)
+// it pays when all waves of the launch are resident at once.  Candidates are
+// visited in stencil-slot order, each row's entries are appended in that
+// order with a wave ballot.  Only wave-level synchronisation is used, so
+// waves of one block may run different trip counts.  S is the stencil width
+// of the grid the wave's rows belong to (3: cells of one list radius; 5:
+// cells of half of it, fewer candidates per row and more cells per wave).
+template <int K, int S>
+__device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool site, int max_excl,
+                                          const TopoDev& topo, const int* __restrict__ user2arow,
+                                          int4* __restrict__ a_rec, int4* __restrict__ s_rec,
+                                          Status* __restrict__ st, int* slot_first,
+                                          int* slot_start, int* excl_lds)
 {
-    __shared__ int slot_first[4][32], slot_start[4][32];
+    using St = Stencil<S>;
     const int lane = threadIdx.x & (kWave - 1);
-    // wave-uniform by construction; readfirstlane lets the compiler keep it
-    // (and everything derived from it) in scalar registers
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int gw = blockIdx.x * 4 + wv;
-    if (gw >= waves_total) return;            // whole wave; no block barriers below
-    const bool site = gw >= waves_a;
-    const GridDev& g = grids[site ? 1 : 0];
     const double4* gpos = g.pos;      // read through load_xyz / load_meta
     const int2* gmeta = g.meta;
     RELRES_GLOBAL const int* guser = gbl(g.user);
     RELRES_GLOBAL const int* gstart = gbl(g.start);
     RELRES_GLOBAL const int* gnbr = gbl(g.nbr);
+    RELRES_GLOBAL const int* grank = gbl(g.rank_of_lin);
     RELRES_GLOBAL int* glist = gbl(g.list);
     RELRES_GLOBAL const int* glor = gbl(g.lin_of_rank);
     // the system whose grid holds this wave's rows: last grid starting at or
     // before the wave (wave-uniform; grids with no rows have no waves)
-    const int lw = site ? gw - waves_a : gw;
     int gs_lo = 0, gs_hi = g.nsys - 1;
     while (gs_lo < gs_hi) {
         const int mid = (gs_lo + gs_hi + 1) >> 1;
@@ -513,8 +542,11 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     const GeomDev& G = g.geom[gs_lo];
     const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
     const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
-    // known image shifts need at least four cells along every axis
-    const bool known_shift = n0 >= 4 && n1 >= 4 && n2 >= 4;
+    // known image shifts: every stencil slot a distinct cell with one
+    // periodic image (at least four cells per axis for the 27-cell stencil,
+    // five for the 125-cell one)
+    const bool known_shift = S == 3 ? (n0 >= 4 && n1 >= 4 && n2 >= 4)
+                                    : (n0 >= 5 && n1 >= 5 && n2 >= 5);
     const int R = g.rows_per_wave;
     const int r0 = G.row_base + (lw - G.wave_base) * R;
     const int r1 = min(G.row_base + G.members, r0 + R);
@@ -525,7 +557,6 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     const int* __restrict__ excl_idx = topo.excl_idx;
     const int same_mol = topo.same_mol;
     // exclusion lists of the wave's home rows, staged once (kRowsPerWave x max_excl)
-    extern __shared__ int excl_lds[];
     int* my_excl = excl_lds + wv * kRowsPerWave * max_excl;
 
     // lane h < (r1 - r0) owns home row r0 + h
@@ -549,21 +580,43 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // Stencil slot `lane` (< 27) of a home cell: the slot's cell (rank, or
-    // -1), then the first member and the end of its member range.  The next
-    // home cell's reads are issued while this cell is processed (the rank
-    // before this cell's candidate reads, the range at its first home row),
-    // so the two dependent reads leave the per-cell critical path.  Both
-    // reads are unconditional (lanes past the stencil and empty slots read a
-    // valid entry and drop it at use), so no branch makes the compiler wait
-    // for them early.
-    auto rank_of = [&](int h) { return gnbr[readlane_i(mcell, h) * 27 + min(lane, 26)]; };
-    int next_rank = nh > 0 ? rank_of(0) : -1;
-    int next_lo = 0, next_hi = 0;
+    // The stencil slots a lane holds (slot `lane`, and `lane + 64` for the
+    // 125-cell stencil) of a home cell: the slot's cell (rank, or -1), then
+    // the first member and the end of its member range.  The next home cell's
+    // reads are issued while this cell is processed (the ranks before this
+    // cell's candidate reads, the ranges at its first home row), so the
+    // dependent reads leave the per-cell critical path.  The range reads are
+    // unconditional (lanes past the stencil and empty slots read a valid entry
+    // and drop it at use), so no branch makes the compiler wait for them early.
+    int next_rank[St::kPerLane];
+    auto ranks_of = [&](int h) {
+        const int c = readlane_i(mcell, h);
+        if constexpr (S == 3) {
+            next_rank[0] = gnbr[c * 27 + min(lane, 26)];
+        } else {
+            const int lin = __builtin_amdgcn_readfirstlane(glor[c]);
+            const int cz = lin % n2, cy = (lin / n2) % n1, cx = lin / (n1 * n2);
+#pragma unroll
+            for (int u = 0; u < St::kPerLane; ++u)
+                next_rank[u] = stencil_rank<S>(G, grank, cx, cy, cz, lane + kWave * u);
+        }
+    };
+    auto no_ranks = [&]() {
+#pragma unroll
+        for (int u = 0; u < St::kPerLane; ++u) next_rank[u] = -1;
+    };
+    auto slot_valid = [&](int u) {
+        return lane + kWave * u < St::kSlots && next_rank[u] >= 0;
+    };
+    if (nh > 0) ranks_of(0); else no_ranks();
+    int next_lo[St::kPerLane], next_hi[St::kPerLane];
     auto range_of = [&]() {
-        const int r = (lane < 27 && next_rank >= 0) ? next_rank : 0;
-        next_lo = gstart[r];
-        next_hi = gstart[r + 1];
+#pragma unroll
+        for (int u = 0; u < St::kPerLane; ++u) {
+            const int r = slot_valid(u) ? next_rank[u] : 0;
+            next_lo[u] = gstart[r];
+            next_hi[u] = gstart[r + 1];
+        }
     };
     if (nh > 0) range_of();
     int h0 = 0;
@@ -572,18 +625,30 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         const int c = readlane_i(mcell, h0);
         int h1 = h0 + 1;
         while (h1 < nh && readlane_i(mcell, h1) == c) ++h1;
-        const bool slot_ok = lane < 27 && next_rank >= 0;
-        const int s0 = slot_ok ? next_lo : 0, cnt = slot_ok ? next_hi - next_lo : 0;
-        next_rank = h1 < nh ? rank_of(h1) : -1;
-        int pre = cnt;
-        for (int o = 1; o < 32; o <<= 1) {
-            const int v = __shfl_up(pre, o);
-            if (lane >= o) pre += v;
+        int s0[St::kPerLane], cnt[St::kPerLane];
+#pragma unroll
+        for (int u = 0; u < St::kPerLane; ++u) {
+            const bool ok = slot_valid(u);
+            s0[u] = ok ? next_lo[u] : 0;
+            cnt[u] = ok ? next_hi[u] - next_lo[u] : 0;
         }
-        const int ncand = __builtin_amdgcn_readfirstlane(__shfl(pre, 26));
-        if (lane < 32) {
-            slot_first[wv][lane] = lane < 27 ? pre - cnt : ncand;
-            slot_start[wv][lane] = s0;
+        if (h1 < nh) ranks_of(h1); else no_ranks();
+        // first candidate of every slot: a wave scan of the counts in slot
+        // order (slot lane, then slot lane + 64)
+        int ncand = 0;
+#pragma unroll
+        for (int u = 0; u < St::kPerLane; ++u) {
+            int pre = cnt[u];
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int v = __shfl_up(pre, o);
+                if (lane >= o) pre += v;
+            }
+            const int slot = lane + kWave * u;
+            if (slot < St::kTab) {
+                slot_first[slot] = ncand + pre - cnt[u];
+                slot_start[slot] = s0[u];
+            }
+            ncand += __builtin_amdgcn_readfirstlane(__shfl(pre, kWave - 1));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -607,13 +672,13 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                 const int q = cb + lane + kWave * k;
                 // the last slot whose first candidate is <= q (empty slots
                 // repeat the next slot's first candidate)
-                int lo = 0, hi = 26;
+                int lo = 0, hi = St::kSlots - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (slot_first[wv][mid] <= q) lo = mid; else hi = mid - 1;
+                    if (slot_first[mid] <= q) lo = mid; else hi = mid - 1;
                 }
                 const int slot = lo;
-                const int src = slot_start[wv][slot] + (q - slot_first[wv][slot]);
+                const int src = slot_start[slot] + (q - slot_first[slot]);
                 px[k] = py[k] = pz[k] = 0.0;
                 sx[k] = sy[k] = sz[k] = 0.0;
                 pu[k] = -1;
@@ -623,8 +688,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                     load_meta(gmeta, src, pt[k], pm[k]);
                     pu[k] = guser[src];
                     if (known_shift) {
-                        // slot offsets are (-1, 0, 1) on every axis here
-                        const int ox = slot / 9 - 1, oy = (slot / 3) % 3 - 1, oz = slot % 3 - 1;
+                        const int ox = St::off(slot, 0), oy = St::off(slot, 1), oz = St::off(slot, 2);
                         sx[k] = cx + ox < 0 ? -Lx : (cx + ox >= n0 ? Lx : 0.0);
                         sy[k] = cy + oy < 0 ? -Ly : (cy + oy >= n1 ? Ly : 0.0);
                         sz[k] = cz + oz < 0 ? -Lz : (cz + oz >= n2 ? Lz : 0.0);
@@ -693,6 +757,35 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     // only a row that outgrew its capacity touches the status word (rare), so
     // thousands of waves do not serialise on one address
     if (lane < nh && mcnt > cap) atomicMax(&st->max_row[site ? 1 : 0], mcnt);
+}
+
+// One launch for both grids: waves [0, waves_a) build the atom list, the
+// rest the site list; SA and SS are the stencil widths of the two grids.
+template <int K, int SA, int SS>
+__global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ grids,
+                                                    int waves_a, int waves_total, int max_excl,
+                                                    TopoDev topo,
+                                                    const int* __restrict__ user2arow,
+                                                    int4* __restrict__ a_rec,
+                                                    int4* __restrict__ s_rec,
+                                                    Status* __restrict__ st)
+{
+    __shared__ int slot_first[4][Stencil<(SA > SS ? SA : SS)>::kTab];
+    __shared__ int slot_start[4][Stencil<(SA > SS ? SA : SS)>::kTab];
+    extern __shared__ int excl_lds[];
+    // wave-uniform by construction; readfirstlane lets the compiler keep it
+    // (and everything derived from it) in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int gw = blockIdx.x * 4 + wv;
+    if (gw >= waves_total) return;            // whole wave; no block barriers below
+    const bool site = gw >= waves_a;
+    const int lw = site ? gw - waves_a : gw;
+    if (site)
+        list_wave<K, SS>(grids[1], wv, lw, true, max_excl, topo, user2arow, a_rec, s_rec, st,
+                         slot_first[wv], slot_start[wv], excl_lds);
+    else
+        list_wave<K, SA>(grids[0], wv, lw, false, max_excl, topo, user2arow, a_rec, s_rec, st,
+                         slot_first[wv], slot_start[wv], excl_lds);
 }
 
 // Neighbour lists: one block per home cell (atom-grid cells first, then
@@ -1573,20 +1666,30 @@ int list_candidates(int total_waves, int cand)
 
 hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_a, int waves_s,
                         TopoDev topo, const int* user2arow, int4* a_rec, int4* s_rec, Status* st,
-                        bool per_wave, int cand, hipStream_t s)
+                        bool per_wave, int cand, int stencil_a, int stencil_s, hipStream_t s)
 {
-    if (per_wave) {
+    if (per_wave || stencil_a != 3 || stencil_s != 3) {
         const int total = waves_a + waves_s;
         if (total == 0) return hipSuccess;
         const int mx = topo.excl_off ? topo.max_excl : 0;
         const size_t dyn = sizeof(int) * 4 * kRowsPerWave * (size_t)mx;
         const bool k4 = list_candidates(total, cand) == 4;
-        if (k4)
-            hipLaunchKernelGGL(k_lists_wave<4>, dim3((total + 3) / 4), dim3(256), dyn, s,
-                               grids_dev, waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
-        else
-            hipLaunchKernelGGL(k_lists_wave<2>, dim3((total + 3) / 4), dim3(256), dyn, s,
-                               grids_dev, waves_a, total, mx, topo, user2arow, a_rec, s_rec, st);
+        const dim3 grid((total + 3) / 4), block(256);
+#define RELRES_LISTS(K, SA, SS)                                                                   \
+        hipLaunchKernelGGL((k_lists_wave<K, SA, SS>), grid, block, dyn, s, grids_dev, waves_a, \
+                           total, mx, topo, user2arow, a_rec, s_rec, st)
+        const int sel = (k4 ? 4 : 0) | (stencil_a == 5 ? 2 : 0) | (stencil_s == 5 ? 1 : 0);
+        switch (sel) {
+        case 0: RELRES_LISTS(2, 3, 3); break;
+        case 1: RELRES_LISTS(2, 3, 5); break;
+        case 2: RELRES_LISTS(2, 5, 3); break;
+        case 3: RELRES_LISTS(2, 5, 5); break;
+        case 4: RELRES_LISTS(4, 3, 3); break;
+        case 5: RELRES_LISTS(4, 3, 5); break;
+        case 6: RELRES_LISTS(4, 5, 3); break;
+        default: RELRES_LISTS(4, 5, 5); break;
+        }
+#undef RELRES_LISTS
         return hipGetLastError();
     }
     if (ncell_a + ncell_s == 0) return hipSuccess;

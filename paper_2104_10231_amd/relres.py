@@ -61,7 +61,8 @@ class Tune(ctypes.Structure):
                 ("cand_per_lane", ctypes.c_int), ("lanes_atom", ctypes.c_int),
                 ("lanes_site", ctypes.c_int), ("trials", ctypes.c_int),
                 ("build_us", ctypes.c_double), ("build_us_auto", ctypes.c_double),
-                ("force_us", ctypes.c_double), ("force_us_auto", ctypes.c_double)]
+                ("force_us", ctypes.c_double), ("force_us_auto", ctypes.c_double),
+                ("cell_div_atom", ctypes.c_int), ("cell_div_site", ctypes.c_int)]
 
 
 # exported symbol -> (restype, argtypes); mirrors include/relres.h
@@ -93,6 +94,7 @@ SIGNATURES = {
     "relres_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "relres_set_list_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int]),
+    "relres_set_cells": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "relres_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p,
                                        ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Tune)]),
     "relres_set_systems": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
@@ -458,6 +460,12 @@ class RelRes:
     def set_launch(self, lanes_atom: int = 0, lanes_site: int = 0):
         _check(self._lib.relres_set_launch(self._ctx, int(lanes_atom), int(lanes_site)),
                "relres_set_launch")
+
+    def set_cells(self, div_atom: int = 0, div_site: int = 0):
+        """Cells per list radius of the atom and site grids (1 or 2; 0 =
+        automatic) for the next builds."""
+        _check(self._lib.relres_set_cells(self._ctx, int(div_atom), int(div_site)),
+               "relres_set_cells")
 
     def set_list_launch(self, rows_atom: int = 0, rows_site: int = 0, cand_per_lane: int = 0):
         """List-kernel shape for the next builds (0 = automatic)."""

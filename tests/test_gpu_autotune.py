@@ -1,12 +1,13 @@
 """Autotuner (relres_autotune) and explicit list-kernel shapes
 (relres_set_list_launch).
 
-The tuner times every list-kernel shape and every force-kernel lane split on
-the caller's positions, keeps the fastest and leaves lists built from those
-positions: their pair sets must equal the oracle's, and the forces, energies
-and virials computed afterwards must meet the usual FP32 bars against the
-oracle.  A list-kernel shape changes neither the pairs nor their order in a
-row, so at a fixed lane split every shape gives bitwise the same forces.
+The tuner times every cell size and list-kernel shape and every force-
+kernel lane split on the caller's positions, keeps the fastest and leaves
+lists built from those positions: their pair sets must equal the oracle's,
+and the forces, energies and virials computed afterwards must meet the usual
+FP32 bars against the oracle.  A list-kernel shape changes neither the pairs
+nor their order in a row, so at a fixed lane split every shape gives bitwise
+the same forces (a cell size keeps the pairs but not their order).
 """
 import numpy as np
 import pytest
@@ -17,7 +18,8 @@ from _util import make_relres, pair_set, rel_rms
 
 pytestmark = pytest.mark.gpu
 
-LIST_SHAPES = 1 + 2 * 9          # automatic + (2 or 4 candidates) x rows {4, 8, 16}^2
+# automatic + cells per list radius {1, 2}^2 x (2 or 4 candidates) x rows {4, 8, 16}^2
+LIST_SHAPES = 1 + 4 * 2 * 9
 LANE_SPLITS = 1 + 4 * 5          # automatic + atom lanes {2..16} x hybrid lanes {2..32}
 
 
@@ -29,6 +31,7 @@ def _check_result(t):
     assert t["trials"] == LIST_SHAPES + LANE_SPLITS
     assert 1 <= t["rows_atom"] <= 16 and 1 <= t["rows_site"] <= 16
     assert t["cand_per_lane"] in (2, 4)
+    assert t["cell_div_atom"] in (1, 2) and t["cell_div_site"] in (1, 2)
     for v in (t["lanes_atom"], t["lanes_site"]):
         assert v >= 1 and v & (v - 1) == 0
     assert 0.0 < t["build_us"] <= t["build_us_auto"]
