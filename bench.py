@@ -617,9 +617,10 @@ def batch_bench(args):
                    "parallelism": "single GPU",
                    "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)",
                    "tuned": None if tuned is None else {
-                       k: tuned[k] for k in ("rows_atom", "rows_site", "cand_per_lane",
-                                             "lanes_atom", "lanes_site", "build_us",
-                                             "build_us_auto", "force_us", "force_us_auto")}},
+                       k: tuned[k] for k in ("cell_div_atom", "cell_div_site", "rows_atom",
+                                             "rows_site", "cand_per_lane", "lanes_atom",
+                                             "lanes_site", "build_us", "build_us_auto",
+                                             "force_us", "force_us_auto")}},
         "sequential": None if seq is None else {
             "value": seq, "ms_per_step": dt_s * 1e3 / (cycles * every),
             "what": "one context per replica, launched replica after replica"},
