@@ -72,17 +72,23 @@ __device__ __forceinline__ int cell_coord(double w, double inv, int n)
 
 // List membership in FP64 on wrapped positions (a = home atom, b = candidate):
 // single-shift minimum image, r2 = (dx dx + dy dy) + dz dz, strict r2 < rl2.
+// The shift is chosen by selects, not branches: d + (-L) rounds exactly as
+// d - L, and adding 0 leaves d (a -0 becomes +0, which squares the same).
+__device__ __forceinline__ double min_image(double d, double L, double h)
+{
+#pragma clang fp contract(off)
+    const double s = d > h ? -L : (d < -h ? L : 0.0);
+    return d + s;
+}
+
 __device__ __forceinline__ bool member(const double4 a, const double4 b, double Lx, double Ly,
                                        double Lz, double hx, double hy, double hz, double rl2)
 {
 #pragma clang fp contract(off)
-    double dx = b.x - a.x;
-    if (dx > hx) dx -= Lx; else if (dx < -hx) dx += Lx;
-    double dy = b.y - a.y;
-    if (dy > hy) dy -= Ly; else if (dy < -hy) dy += Ly;
-    double dz = b.z - a.z;
-    if (dz > hz) dz -= Lz; else if (dz < -hz) dz += Lz;
-    double r2 = (dx * dx + dy * dy) + dz * dz;
+    const double dx = min_image(b.x - a.x, Lx, hx);
+    const double dy = min_image(b.y - a.y, Ly, hy);
+    const double dz = min_image(b.z - a.z, Lz, hz);
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
     return r2 < rl2;
 }
 
@@ -545,8 +551,9 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     // known image shifts: every stencil slot a distinct cell with one
     // periodic image (at least four cells per axis for the 27-cell stencil,
     // five for the 125-cell one)
-    const bool known_shift = S == 3 ? (n0 >= 4 && n1 >= 4 && n2 >= 4)
-                                    : (n0 >= 5 && n1 >= 5 && n2 >= 5);
+    // (wave-uniform; readfirstlane makes the choice a scalar branch)
+    const bool known_shift = __builtin_amdgcn_readfirstlane(
+        S == 3 ? (n0 >= 4 && n1 >= 4 && n2 >= 4) : (n0 >= 5 && n1 >= 5 && n2 >= 5));
     const int R = g.rows_per_wave;
     const int r0 = G.row_base + (lw - G.wave_base) * R;
     const int r1 = min(G.row_base + G.members, r0 + R);
@@ -720,21 +727,17 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 for (int k = 0; k < K; ++k) {
                     if (cb + kWave * k >= ncand) break;
                     const int uj = pu[k];
-                    bool keep = keep_k[k];
-                    if (keep) {
-                        if (known_shift)
-                            keep = member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx[k], sy[k],
-                                                  sz[k], rl2);
-                        else
-                            keep = member(make_double4(xi, yi, zi, 0.0),
-                                          make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx,
-                                          hy, hz, rl2);
-                    }
+                    // the distance test for every lane (no divergent branch
+                    // around it), then the other conditions
+                    const bool in = known_shift
+                        ? member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx[k], sy[k], sz[k], rl2)
+                        : member(make_double4(xi, yi, zi, 0.0),
+                                 make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx, hy, hz,
+                                 rl2);
+                    const bool keep = keep_k[k] && in;
                     const uint64_t mask = __ballot(keep);
-                    if (keep) {
-                        const int p = hc + lanes_below(mask);
-                        if (p < cap) out[p] = (int)((uint32_t)uj | ((uint32_t)pt[k] << kIdxBits));
-                    }
+                    const int p = hc + lanes_below(mask);
+                    if (keep && p < cap) out[p] = (int)((uint32_t)uj | ((uint32_t)pt[k] << kIdxBits));
                     hc += __popcll(mask);
                 }
                 if (lane == h) mcnt = hc;
