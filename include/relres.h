@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RELRES_ABI_VERSION 6
+#define RELRES_ABI_VERSION 7
 
 #define RELRES_OK                   0
 #define RELRES_ERR_ARG             -1  /* null pointer, bad size or flag     */
@@ -140,6 +140,13 @@ typedef struct relres_stats {
     long long moved_at_last_build;        /* atoms the last examined build found
                                              more than half the skin from their
                                              previous-build positions          */
+    int place_launches;                   /* launches that put the members of the
+                                             last build into cell order: 1 (grids
+                                             of at most 8192 cells, not crowded:
+                                             per-cell buckets filled while binning,
+                                             then one scan-and-sort launch) or 3
+                                             (scan, scatter, cell sort); 0 before
+                                             any build of a non-empty system    */
 } relres_stats;
 
 /* Create a context.  Validates the cutoff ordering r_s- <= r_s+ <= r_c- <=

@@ -326,6 +326,7 @@ struct relres_ctx {
     unsigned moved_seen = 0;          // Status::moved at the last examination
     unsigned ew_failed_seen = 0;      // Status::ew_failed at the last examination
     int spin_limit = 1 << 22;         // polls before a cross-block energy/virial wait gives up
+    bool place_one_launch = true;     // grids of few cells: scan, scatter and sort in one launch
     bool ref_valid = false;           // wpos holds a previous build of this topology
     bool warn_pending = false;        // a build found atoms past half the skin, not yet reported
     bool stats_fresh = false;         // statistics describe the current lists
@@ -737,6 +738,38 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
     return RELRES_OK;
 }
 
+// Bucket slots per cell for the one-launch placement: room for about twice
+// the mean occupancy plus 8, a power of two of at most 64 (0: the grid's cells
+// are too crowded for buckets).
+int bucket_slots(const GridHost& g)
+{
+    if (g.ncell <= 0) return 0;
+    const double mean = (double)g.members / g.ncell;
+    int cap = 8;
+    while (cap < 2.0 * mean + 8.0 && cap <= 64) cap *= 2;
+    return cap <= 64 ? cap : 0;
+}
+
+// Sets both grids' bucket capacity: buckets for all grids or for none.
+int set_buckets(relres_ctx* c, GridHost& ga, GridHost* gs, bool want, bool* used)
+{
+    int cap_a = want ? bucket_slots(ga) : 0;
+    int cap_s = (want && gs) ? bucket_slots(*gs) : 0;
+    const bool use = cap_a > 0 && (!gs || cap_s > 0);
+    if (!use) cap_a = cap_s = 0;
+    if (cap_a > 0) TRY(ensure(ga.user_unsorted, sizeof(int) * (size_t)ga.ncell * cap_a, &c->alloc_generation));
+    ga.dev.bucket_cap = cap_a;
+    ga.dev.user_unsorted = ga.user_unsorted.as<int>();
+    if (gs) {
+        if (cap_s > 0)
+            TRY(ensure(gs->user_unsorted, sizeof(int) * (size_t)gs->ncell * cap_s, &c->alloc_generation));
+        gs->dev.bucket_cap = cap_s;
+        gs->dev.user_unsorted = gs->user_unsorted.as<int>();
+    }
+    *used = use;
+    return RELRES_OK;
+}
+
 TopoDev topo_of(relres_ctx* c)
 {
     TopoDev t;
@@ -870,6 +903,10 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
         TRY(setup_grid(c->gs, rls, skin_sys, ns, box, c->sites_sys.data(), launch_rows, c->rows_s,
                        c->div_s ? c->div_s : 1, &c->alloc_generation));
     if (c->ga.ncell + (sites ? c->gs.ncell : 0) != dims_before) c->lanes_stale = true;
+    bool one_launch = false;
+    TRY(set_buckets(c, c->ga, sites ? &c->gs : nullptr,
+                    c->place_one_launch && c->ga.ncell + (sites ? c->gs.ncell : 0) <= kPlaceMaxCells,
+                    &one_launch));
     const void* wpos_before = c->d_wpos.p;
     TRY(ensure(c->d_wpos, sizeof(double4) * c->n, &c->alloc_generation));
     const bool check_moved = c->ref_valid && same_boxes && c->d_wpos.p == wpos_before;
@@ -899,13 +936,18 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
                            c->d_key_s.as<int2>(), c->d_status.as<Status>(), check_moved, s));
         c->ref_valid = true;
         c->ref_skins = skin_sys;
-        HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->ga.ncell, sites ? c->gs.ncell : 0,
-                            c->d_seg_tot.as<int>(), s));
-        HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
         const int ncs = sites ? c->gs.ncell : 0;
-        HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs,
-                                (long long)c->n + (sites ? c->n_sites : 0),
-                                c->d_wpos.as<double4>(), topo, c->d_user2arow.as<int>(), s));
+        const long long members = (long long)c->n + (sites ? c->n_sites : 0);
+        if (one_launch) {
+            HIP_TRY(launch_place(gd, c->ga.ncell, ncs, members, c->n, c->d_key_a.as<int2>(),
+                                 c->d_key_s.as<int2>(), c->d_wpos.as<double4>(), topo,
+                                 c->d_user2arow.as<int>(), s));
+        } else {
+            HIP_TRY(launch_scan(gd, sites ? 2 : 1, c->ga.ncell, ncs, c->d_seg_tot.as<int>(), s));
+            HIP_TRY(launch_scatter(c->n, gd, c->d_key_a.as<int2>(), c->d_key_s.as<int2>(), s));
+            HIP_TRY(launch_cellsort(gd, c->ga.ncell, c->ga.ncell + ncs, members,
+                                    c->d_wpos.as<double4>(), topo, c->d_user2arow.as<int>(), s));
+        }
         HIP_TRY(launch_lists(gd, c->ga.ncell, ncs, c->ga.waves, sites ? c->gs.waves : 0, topo,
                              c->d_user2arow.as<int>(),
                              c->d_a_rec.as<int4>(), c->d_s_rec.as<int4>(),
@@ -928,6 +970,7 @@ int enqueue_build(relres_ctx* c, const double* pos, const double* box, hipStream
     relres_stats& st = c->stats;
     st.n_atoms = c->n;
     st.n_sites = c->n_sites;
+    if (c->n > 0) st.place_launches = one_launch ? 1 : 3;
     for (int k = 0; k < 3; ++k) {
         st.atom_cells[k] = c->ga.n[k];
         st.site_cells[k] = sites ? c->gs.n[k] : 0;
@@ -1239,6 +1282,10 @@ int relres_create(const relres_params* p, relres_ctx** out)
     // RELRES_EW_SPIN_LIMIT: polls of a cross-block energy/virial wait before it
     // gives up (a negative value gives up at once: failure handling tests)
     if (const char* e = std::getenv("RELRES_EW_SPIN_LIMIT")) c->spin_limit = std::atoi(e);
+    // RELRES_PLACE=classic: the scan / scatter / cell-sort launches for every
+    // grid (the one-launch placement is then never used; parity tests of both)
+    if (const char* e = std::getenv("RELRES_PLACE"))
+        c->place_one_launch = std::strcmp(e, "classic") != 0;
     c->ntypes = nt;
     c->mix = p->mix;
     c->no_shift = p->no_shift;

@@ -84,7 +84,10 @@ struct GridDev {
                               // list radius) or 5 (cells of at least half of it)
     int* count;               // per cell (by rank); zero between builds
     int* start;               // ncell + 1 exclusive offsets (by rank)
-    int* user_unsorted;       // member caller indices, cell-grouped
+    int* user_unsorted;       // member caller indices, cell-grouped; with bucket_cap > 0 the
+                              // per-cell buckets (ncell x bucket_cap) that k_bin fills
+    int bucket_cap;           // > 0: members go straight into per-cell buckets, k_place
+                              // places them and the list kernel clears the counts
     int* user;                // member caller indices, cell-grouped, ascending in a cell
     double4* pos;             // wrapped positions of members (w unused)
     int2* meta;               // (type, molecule) of members
@@ -185,6 +188,16 @@ hipError_t launch_scatter(int n, GridDev* grids_dev, const int2* key_a, const in
 // members: rows of both grids (picks cells per wave)
 hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, long long members,
                            const double4* wpos, TopoDev topo, int* user2arow, hipStream_t s);
+// Grids of few cells: scan, scatter and cell sort in one launch.  k_bin has
+// filed every member into its cell's bucket (GridDev::bucket_cap > 0); each
+// block adds up the counts of the cells before its own, then ranks and places
+// its cells' members (a cell that outgrew its bucket finds its members in the
+// key arrays).  kPlaceMaxCells bounds the cells of both grids together, since
+// the count sums are repeated by every block.
+constexpr int kPlaceMaxCells = 8192;
+hipError_t launch_place(GridDev* grids_dev, int ncell_a, int ncell_s, long long members, int n,
+                        const int2* key_a, const int2* key_s, const double4* wpos, TopoDev topo,
+                        int* user2arow, hipStream_t s);
 // per_wave: one wave per home cell (small cells) instead of one block per cell
 // Candidates per lane of the row-group list kernel (2 or 4) for a launch of
 // total_waves waves; cand = 2 or 4 forces the value, 0 chooses it.

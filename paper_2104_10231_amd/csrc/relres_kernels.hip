@@ -177,6 +177,9 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
         const int r = gbl(ga.rank_of_lin)[G.cell_base + lin];
         const int slot = claim_slot(ga.count, r, in);
         if (in) key_a[i] = make_int2(r, slot);
+        // one-launch placement: the member goes straight into its cell's bucket
+        if (in && slot < ga.bucket_cap)
+            gbl(ga.user_unsorted)[(size_t)r * ga.bucket_cap + slot] = i;
     }
     const bool hyb = in && topo.hybrid[topo.types[i]] != 0;
     int rs = -1;
@@ -191,6 +194,8 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
     // grids[1] is grids[0] again when there are no sites (no hybrid lanes then)
     const int slot_s = claim_slot(grids[1].count, rs, hyb);
     if (in) key_s[i] = hyb ? make_int2(rs, slot_s) : make_int2(-1, -1);
+    if (hyb && slot_s < grids[1].bucket_cap)
+        gbl(grids[1].user_unsorted)[(size_t)rs * grids[1].bucket_cap + slot_s] = i;
 }
 
 // Atoms now more than half the skin from their position at the last build.
@@ -440,6 +445,127 @@ __global__ void k_cellsort(const GridDev* __restrict__ grids, int ncell_a, int n
     }
 }
 
+
+// Scan, scatter and cell sort in one launch, for grids of few cells whose
+// members k_bin has filed into per-cell buckets of bucket_cap slots.  A block
+// takes kCells consecutive cells of one grid (the atom grid's blocks first):
+// it adds up the counts of every cell before its own (each block repeats
+// this, so it suits a few thousand cells), writes its cells' starts, then
+// ranks each cell's members by caller index as k_cellsort does and writes
+// the sorted arrays.  A cell with more members than its bucket holds finds
+// them, already in caller order, by a wave-wide pass over the key array.
+// The counts stay as they are: the list kernel clears them.
+constexpr int kPlaceThreads = 256;
+
+template <int kSortGroup>
+__global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restrict__ grids,
+                                                         int blocks_a, int n,
+                                                         const int2* __restrict__ key_a,
+                                                         const int2* __restrict__ key_s,
+                                                         const double4* __restrict__ wpos,
+                                                         TopoDev topo, int* __restrict__ user2arow)
+{
+    constexpr int kWaves = kPlaceThreads / kWave;
+    constexpr int kCellsPerWave = kWave / kSortGroup;
+    constexpr int kCells = kWaves * kCellsPerWave;     // at most 64: one wave scans them
+    __shared__ int wtot[kWaves];
+    __shared__ int cnt_sh[kCells], first_sh[kCells];
+    const bool site = (int)blockIdx.x >= blocks_a;
+    const GridDev& g = grids[site ? 1 : 0];
+    const int c0 = ((int)blockIdx.x - (site ? blocks_a : 0)) * kCells;
+    const int nc = g.ncell;
+    const int cap = g.bucket_cap;
+    RELRES_GLOBAL const int* gcount = gbl(g.count);
+    RELRES_GLOBAL int* gstart = gbl(g.start);
+    RELRES_GLOBAL const int* bucket = gbl(g.user_unsorted);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+
+    // members of the grid's cells before this block's
+    int s = 0;
+    for (int k = threadIdx.x; k < c0; k += kPlaceThreads) s += gcount[k];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o);
+    if (lane == 0) wtot[wave] = s;
+    __syncthreads();
+    if (wave == 0) {
+        int carry = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) carry += wtot[k];
+        const int v = (lane < kCells && c0 + lane < nc) ? gcount[c0 + lane] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane < kCells) {
+            cnt_sh[lane] = v;
+            first_sh[lane] = carry + x - v;
+            if (c0 + lane < nc) gstart[c0 + lane] = carry + x - v;
+            if (c0 + lane == nc - 1) gstart[nc] = carry + x;
+        }
+    }
+    __syncthreads();
+
+    // group q of G lanes: cell c0 + wave * kCellsPerWave + q
+    const int q = lane / kSortGroup, gl = lane & (kSortGroup - 1);
+    const int ci = wave * kCellsPerWave + q;
+    const int c = c0 + ci;
+    const int len = c < nc ? cnt_sh[ci] : 0;
+    const int b = first_sh[ci];
+    const int in_group = kSortGroup < cap ? kSortGroup : cap;
+    const bool small = len <= in_group;
+    const int u = (small && gl < len) ? bucket[(size_t)c * cap + gl] : 0x7fffffff;
+    int r = 0;
+    if constexpr (kSortGroup < kWave) {
+#pragma unroll
+        for (int k = 0; k < kSortGroup; ++k) r += __shfl(u, (lane & ~(kSortGroup - 1)) + k) < u;
+    } else {
+        const int m = small ? len : 0;      // one cell per wave: len is uniform
+        for (int k = 0; k < m; ++k) r += __shfl(u, k) < u;
+    }
+    if (small && gl < len) place_member(g, site, c, b + r, u, wpos, topo, user2arow);
+    // the larger cells of this wave, one at a time with the whole wave
+    for (int k = 0; k < kCellsPerWave; ++k) {
+        const int lenk = readlane_i(len, k * kSortGroup);
+        if (lenk <= in_group) continue;
+        const int ck = c0 + wave * kCellsPerWave + k;
+        const int bk = readlane_i(b, k * kSortGroup);
+        if (lenk <= cap) {                  // cap <= 64: one member per lane
+            const int v = lane < lenk ? bucket[(size_t)ck * cap + lane] : 0x7fffffff;
+            int rk = 0;
+            for (int j = 0; j < lenk; ++j) rk += __shfl(v, j) < v;
+            if (lane < lenk) place_member(g, site, ck, bk + rk, v, wpos, topo, user2arow);
+            continue;
+        }
+        // the cell outgrew its bucket: its members in caller order from the keys
+        const int2* __restrict__ key = site ? key_s : key_a;
+        int run = 0;
+        for (int i0 = 0; i0 < n; i0 += kWave) {
+            const int i = i0 + lane;
+            const bool mine = i < n && key[i].x == ck;
+            const uint64_t m = __ballot(mine);
+            if (mine) place_member(g, site, ck, bk + run + lanes_below(m), i, wpos, topo, user2arow);
+            run += __popcll(m);
+        }
+    }
+}
+
+// After a one-launch placement the cell counts are still set: the list
+// kernel, the next launch of the build, clears them for the next build (the
+// grid array always has two entries; the second repeats the first when there
+// are no sites).
+__device__ __forceinline__ void clear_bucket_counts(const GridDev* __restrict__ grids)
+{
+    const int stride = (int)(gridDim.x * blockDim.x);
+    for (int gi = 0; gi < 2; ++gi) {
+        const GridDev& g = grids[gi];
+        if (g.bucket_cap <= 0) continue;
+        RELRES_GLOBAL int* cnt = gbl(g.count);
+        for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < g.ncell; c += stride)
+            cnt[c] = 0;
+    }
+}
 
 // Neighbour lists, one wave per group of kRowsPerWave consecutive member rows
 // (rows are in cell order, so a group spans one or two cells).  Work per wave
@@ -776,6 +902,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     __shared__ int slot_first[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ int slot_start[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     extern __shared__ int excl_lds[];
+    clear_bucket_counts(grids);
     // wave-uniform by construction; readfirstlane lets the compiler keep it
     // (and everything derived from it) in scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -810,6 +937,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists(const GridDev* __restrict_
     __shared__ int blk_max;
     __shared__ unsigned long long blk_sum;
 
+    clear_bucket_counts(grids);
     const bool site = (int)blockIdx.x >= ncell_a;
     const GridDev& g = grids[site ? 1 : 0];
     const int c = site ? (int)blockIdx.x - ncell_a : (int)blockIdx.x;
@@ -1346,8 +1474,12 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
 
     unsigned tag = 0;
     if constexpr (EW) {
-        // tag 0 is never used: it marks a cleared record
-        tag = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        // tag 0 is never used: it marks a cleared record.  The epoch is an
+        // ordinary load: only the previous launch wrote it (this launch writes
+        // it after every block has published, i.e. after every block read
+        // it), and the kernel boundary makes that write visible.  A
+        // device-coherent atomic load from every wave cost 0.2 us per launch.
+        tag = a.epoch[0] + 1u;
         tag += tag == 0u;
     }
     // The row's own list (the atom list for rows of ordinary atoms, the site
@@ -1652,6 +1784,24 @@ hipError_t launch_cellsort(GridDev* grids_dev, int ncell_a, int ncell_total, lon
     else
         hipLaunchKernelGGL(k_cellsort<64>, dim3(blocks), dim3(64 * waves_per_block), 0, s,
                            grids_dev, ncell_a, ncell_total, wpos, topo, user2arow);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(GridDev* grids_dev, int ncell_a, int ncell_s, long long members, int n,
+                        const int2* key_a, const int2* key_s, const double4* wpos, TopoDev topo,
+                        int* user2arow, hipStream_t s)
+{
+    // a few members per cell (mean below 8): 4 cells per wave, as k_cellsort
+    const bool small = members < 8LL * (ncell_a + ncell_s);
+    const int cells = (kPlaceThreads / kWave) * (small ? 4 : 1);
+    const int blocks_a = (ncell_a + cells - 1) / cells, blocks_s = (ncell_s + cells - 1) / cells;
+    if (blocks_a + blocks_s == 0) return hipSuccess;
+    if (small)
+        hipLaunchKernelGGL(k_place<16>, dim3(blocks_a + blocks_s), dim3(kPlaceThreads), 0, s,
+                           grids_dev, blocks_a, n, key_a, key_s, wpos, topo, user2arow);
+    else
+        hipLaunchKernelGGL(k_place<64>, dim3(blocks_a + blocks_s), dim3(kPlaceThreads), 0, s,
+                           grids_dev, blocks_a, n, key_a, key_s, wpos, topo, user2arow);
     return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ class Stats(ctypes.Structure):
                 ("builds", ctypes.c_longlong), ("regrows", ctypes.c_longlong),
                 ("box", ctypes.c_double * 3), ("generation", ctypes.c_longlong),
                 ("dangerous_builds", ctypes.c_longlong),
-                ("moved_at_last_build", ctypes.c_longlong)]
+                ("moved_at_last_build", ctypes.c_longlong),
+                ("place_launches", ctypes.c_int)]
 
 
 class Tune(ctypes.Structure):

@@ -63,7 +63,7 @@ def test_struct_layout_matches_header(tmp_path):
 
 
 def test_version_and_error_strings(lib):
-    assert lib.relres_abi_version() == 6
+    assert lib.relres_abi_version() == 7
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11, -12, 1):
         s = lib.relres_strerror(code).decode()
         assert s and s != "unknown error"

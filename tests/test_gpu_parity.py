@@ -284,6 +284,48 @@ def test_repeated_calls_are_bitwise_identical():
     rr.close()
 
 
+
+def test_back_to_back_launches_on_different_positions():
+    """Energy/virial launches on alternating positions, enqueued back to back
+    (eager and inside a captured graph) with no host wait in between: each
+    launch's energy and virial are its own (the cross-block records carry a
+    launch tag, so a waiting block never takes a record of the launch
+    before), bitwise equal to a synchronised single call."""
+    import torch
+    s = w.neopentane_liquid(2)
+    rng = np.random.default_rng(5)
+    pa = torch.from_numpy(s.pos).cuda()
+    pb = torch.from_numpy(s.pos + rng.normal(0.0, 0.05, s.pos.shape)).cuda()
+    rr = make_relres(s)
+    rr.build_lists(pa, s.box)
+    ref = {}
+    for key, p in (("a", pa), ("b", pb)):
+        ref[key] = [t.clone() for t in rr.forces(p)]
+        torch.cuda.synchronize()
+    assert not torch.equal(ref["a"][1], ref["b"][1])
+    outs = [[torch.empty_like(t) for t in ref["a"]] for _ in range(6)]
+    for k, o in enumerate(outs):
+        rr.forces(pa if k % 2 == 0 else pb, out=o[0], energy=o[1], virial=o[2])
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        want = ref["a" if k % 2 == 0 else "b"]
+        assert all(torch.equal(x, y) for x, y in zip(o, want)), k
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for k, o in enumerate(outs):
+            rr.forces(pa if k % 2 == 0 else pb, out=o[0], energy=o[1], virial=o[2])
+    for rep in range(3):
+        for o in outs:
+            for x in o:
+                x.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, o in enumerate(outs):
+            want = ref["a" if k % 2 == 0 else "b"]
+            assert all(torch.equal(x, y) for x, y in zip(o, want)), (rep, k)
+    rr.close()
+
+
 # ---------------------------------------------------------------------------
 # degenerate cases and errors
 # ---------------------------------------------------------------------------
@@ -394,6 +436,71 @@ def test_crowded_cells_need_several_passes():
     for which in (0, 1):
         assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(big, which))
     rr.close()
+
+
+def _one_launch_case(name):
+    if name == "propane":
+        return w.propane_liquid(1)
+    if name == "dense":        # 8 cells of ~19 atoms, no sites: one cell per wave
+        return w.random_molecules(21, 50, 23.0, kind="propane", hybrid_fraction=0.0)
+    if name == "hexane":       # ~38 sites per site cell: too crowded for buckets
+        return w.hexane_liquid(1, n_mol=150, density=0.012)
+    if name == "batch":
+        return w.replica_batch(4, n_systems=4, min_atoms=300, max_atoms=700, total_atoms=2000)
+    s = w.random_molecules(17, 80, 15.0, kind="propane", min_dist=2.0)
+    return s.replace(pos=s.pos + 20.0, box=np.full(3, 60.0), skin=8.0)
+
+
+def _run_placement(s):
+    import torch
+    if isinstance(s, w.Batch):
+        rr = make_relres(s.whole, 64)
+        rr.set_systems(s.offsets)
+        p = torch.from_numpy(s.whole.pos).cuda()
+        rr.build_lists(p, s.boxes)
+    else:
+        rr = make_relres(s, 64)
+        p = torch.from_numpy(s.pos).cuda()
+        rr.build_lists(p, s.box)
+    out = [t.cpu().numpy() for t in rr.forces(p)]
+    torch.cuda.synchronize()
+    return rr, out
+
+
+# path of the default build for each case: 1 = one launch, 3 = classic
+_ONE_LAUNCH = {"propane": 1, "dense": 1, "crowded": 1, "batch": 1, "hexane": 3}
+
+
+@pytest.mark.parametrize("name", list(_ONE_LAUNCH))
+def test_one_launch_placement_matches_the_classic_path(monkeypatch, name):
+    """Grids of few cells put their members into cell order in one launch
+    from per-cell buckets filled while binning (a crowded cell that outgrows
+    its bucket collects its members from the key array; cells of more than
+    28 members on average keep the classic launches); RELRES_PLACE=classic
+    always takes the scan / scatter / cell-sort launches.  Both give the
+    oracle's pair sets and bitwise identical lists, forces, energies and
+    virials."""
+    s = _one_launch_case(name)
+    print(f"[parity] placement {name}", flush=True)
+    out = {}
+    for mode in ("default", "classic"):
+        if mode == "classic":
+            monkeypatch.setenv("RELRES_PLACE", "classic")
+        else:
+            monkeypatch.delenv("RELRES_PLACE", raising=False)
+        rr, res = _run_placement(s)
+        assert rr.stats()["place_launches"] == (_ONE_LAUNCH[name] if mode == "default" else 3)
+        if not isinstance(s, w.Batch):
+            for which in (0, 1):
+                assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(s, which))
+        out[mode] = res + [rr.pairs(0), rr.pairs(1)]
+        rr.close()
+    for a, b in zip(out["default"], out["classic"]):
+        assert np.array_equal(a, b)
+    if not isinstance(s, w.Batch):
+        Fr, Er, Wr = oracle.compute(s)
+        assert rel_rms(out["default"][0], Fr) <= 1e-11
+        assert abs(out["default"][1][0] - Er[0]) <= 1e-12 * max(abs(Er[0]), 1e-300)
 
 
 def test_cell_per_block_list_kernel(monkeypatch):
