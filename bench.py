@@ -606,14 +606,15 @@ def batch_bench(args):
                   "1 MI355X",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": cycles * every,
         "warmup": 2 * every, "ms_per_step": dt_b * 1e3 / (cycles * every),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        # calls with energy/virial evaluate the pair terms in FP64 (forces FP32)
+        "dtype": "f64", "data": "synthetic",
         "config": {"workload": "replica_batch: 256 mixed propane/neopentane liquids, "
                                "300-18000 atoms, 0.0080-0.0100 atoms/A^3", "atoms": n,
                    "replicas": b.nsys,
                    "skin_A": {f"{v:g}": int((b.skins == v).sum()) for v in np.unique(b.skins)},
                    "rebuild_every": every,
-                   "forces": "fp32", "energy_virial": "fp64 per replica",
+                   "forces": "fp32", "pair_math": 64, "energy_virial": "fp64 per replica",
                    "parallelism": "single GPU",
                    "launch": "one HIP graph per cycle (rebuild + force calls of all replicas)",
                    "tuned": None if tuned is None else {

@@ -480,9 +480,23 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restri
     RELRES_GLOBAL const int* bucket = gbl(g.user_unsorted);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 
-    // members of the grid's cells before this block's
+    // members of the grid's cells before this block's: c0 is a multiple of 4,
+    // so the counts are read as int4, four loads per thread in flight at once
     int s = 0;
-    for (int k = threadIdx.x; k < c0; k += kPlaceThreads) s += gcount[k];
+    {
+        const int4* __restrict__ c4 = reinterpret_cast<const int4*>(g.count);
+        const int n4 = c0 >> 2;
+        for (int base = 0; base < n4; base += 4 * kPlaceThreads) {
+            int4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = base + u * kPlaceThreads + (int)threadIdx.x;
+                v[u] = k < n4 ? c4[k] : make_int4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+        }
+    }
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o);
     if (lane == 0) wtot[wave] = s;
@@ -758,6 +772,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
         const int c = readlane_i(mcell, h0);
         int h1 = h0 + 1;
         while (h1 < nh && readlane_i(mcell, h1) == c) ++h1;
+        h1 = __builtin_amdgcn_readfirstlane(h1);   // wave-uniform: a scalar row loop
         int s0[St::kPerLane], cnt[St::kPerLane];
 #pragma unroll
         for (int u = 0; u < St::kPerLane; ++u) {
@@ -828,7 +843,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                     }
                 }
             }
-            for (int h = h0; h < h1; ++h) {
+            for (int h = __builtin_amdgcn_readfirstlane(h0); h < h1; ++h) {
                 if (cb == 0 && h == h0) range_of();
                 const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
                 const int ui = readlane_i(mu, h);
@@ -902,20 +917,21 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     __shared__ int slot_first[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ int slot_start[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     extern __shared__ int excl_lds[];
-    clear_bucket_counts(grids);
     // wave-uniform by construction; readfirstlane lets the compiler keep it
     // (and everything derived from it) in scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int gw = blockIdx.x * 4 + wv;
-    if (gw >= waves_total) return;            // whole wave; no block barriers below
-    const bool site = gw >= waves_a;
-    const int lw = site ? gw - waves_a : gw;
-    if (site)
-        list_wave<K, SS>(grids[1], wv, lw, true, max_excl, topo, user2arow, a_rec, s_rec, st,
-                         slot_first[wv], slot_start[wv], excl_lds);
-    else
-        list_wave<K, SA>(grids[0], wv, lw, false, max_excl, topo, user2arow, a_rec, s_rec, st,
-                         slot_first[wv], slot_start[wv], excl_lds);
+    if (gw < waves_total) {                   // whole wave; no block barriers below
+        const bool site = gw >= waves_a;
+        const int lw = site ? gw - waves_a : gw;
+        if (site)
+            list_wave<K, SS>(grids[1], wv, lw, true, max_excl, topo, user2arow, a_rec, s_rec, st,
+                             slot_first[wv], slot_start[wv], excl_lds);
+        else
+            list_wave<K, SA>(grids[0], wv, lw, false, max_excl, topo, user2arow, a_rec, s_rec,
+                             st, slot_first[wv], slot_start[wv], excl_lds);
+    }
+    clear_bucket_counts(grids);   // last: the stores leave the start of the kernel alone
 }
 
 // Neighbour lists: one block per home cell (atom-grid cells first, then
@@ -1661,6 +1677,8 @@ __global__ void k_zero_outputs(double* energy, double* virial, int nsys)
 // w of a kind holds rows w * rpw .. w * rpw + rpw - 1 of that kind, rpw =
 // 64 / lanes per row), and for a wave across a system boundary the partials
 // of its rows in this system; fixed order, so results are deterministic.
+constexpr int kSysLoads = 4;
+
 __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict__ grids,
                                                        int ngrids, ForceArgs a,
                                                        double* __restrict__ energy,
@@ -1676,18 +1694,34 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
         const int r0 = G.row_base, r1 = G.row_base + G.members;
         const size_t woff = kind ? (size_t)a.blocks_a * (kForceBlock / kWave) : 0;
         const size_t rbase = kind ? (size_t)a.n_arow : 0;
-        for (int w = r0 / rpw + (int)threadIdx.x; w <= (r1 - 1) / rpw; w += 256) {
-            const int ws = a.wave_sys[woff + w];
-            if (ws == sy) {
-                const double* p = a.wave_ew + 8 * (woff + w);
+        // kSysLoads waves per thread per round: their system tags and records
+        // are all requested before any is used (a record is read whatever its
+        // tag says, so the loads do not wait for the tags)
+        const int w0 = r0 / rpw, w1 = (r1 - 1) / rpw;
+        for (int wb = w0 + (int)threadIdx.x; wb <= w1; wb += 256 * kSysLoads) {
+            int ws[kSysLoads];
+            double4 q[kSysLoads][2];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] += p[k];
-            } else if (ws == -1) {
-                const int e = min((w + 1) * rpw, r1);
-                for (int r = max(w * rpw, r0); r < e; ++r) {
-                    const double* p = a.row_ew + 8 * (rbase + r);
+            for (int u = 0; u < kSysLoads; ++u) {
+                const int w = min(wb + 256 * u, w1);
+                const double4* p = reinterpret_cast<const double4*>(a.wave_ew + 8 * (woff + w));
+                ws[u] = wb + 256 * u <= w1 ? a.wave_sys[woff + w] : -2;
+                q[u][0] = p[0];
+                q[u][1] = p[1];
+            }
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) v[k] += p[k];
+            for (int u = 0; u < kSysLoads; ++u) {
+                if (ws[u] == sy) {
+                    v[0] += q[u][0].x; v[1] += q[u][0].y; v[2] += q[u][0].z; v[3] += q[u][0].w;
+                    v[4] += q[u][1].x; v[5] += q[u][1].y; v[6] += q[u][1].z; v[7] += q[u][1].w;
+                } else if (ws[u] == -1) {
+                    const int w = wb + 256 * u;
+                    const int e = min((w + 1) * rpw, r1);
+                    for (int r = max(w * rpw, r0); r < e; ++r) {
+                        const double* p = a.row_ew + 8 * (rbase + r);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) v[k] += p[k];
+                    }
                 }
             }
         }
