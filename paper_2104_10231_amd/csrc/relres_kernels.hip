@@ -1687,41 +1687,51 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
     __shared__ double red[8][4];
     const int sy = (int)blockIdx.x;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int kind = 0; kind < ngrids; ++kind) {
+    // the system's waves of both kinds (atom rows, then site rows) as one
+    // range: both kinds' row ranges are read first, then kSysLoads waves per
+    // thread per round have their system tags and records requested before
+    // any is used (a record is read whatever its tag says)
+    int w0[2] = {0, 0}, nw[2] = {0, 0}, rpw[2] = {1, 1}, r0[2] = {0, 0}, r1[2] = {0, 0};
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+        if (kind >= ngrids) continue;
         const GeomDev& G = grids[kind].geom[sy];
-        if (G.members == 0) continue;
-        const int rpw = kWave >> (kind ? a.log_lanes_b : a.log_lanes_a);
-        const int r0 = G.row_base, r1 = G.row_base + G.members;
-        const size_t woff = kind ? (size_t)a.blocks_a * (kForceBlock / kWave) : 0;
-        const size_t rbase = kind ? (size_t)a.n_arow : 0;
-        // kSysLoads waves per thread per round: their system tags and records
-        // are all requested before any is used (a record is read whatever its
-        // tag says, so the loads do not wait for the tags)
-        const int w0 = r0 / rpw, w1 = (r1 - 1) / rpw;
-        for (int wb = w0 + (int)threadIdx.x; wb <= w1; wb += 256 * kSysLoads) {
-            int ws[kSysLoads];
-            double4 q[kSysLoads][2];
+        rpw[kind] = kWave >> (kind ? a.log_lanes_b : a.log_lanes_a);
+        r0[kind] = G.row_base;
+        r1[kind] = G.row_base + G.members;
+        w0[kind] = r0[kind] / rpw[kind];
+        nw[kind] = G.members > 0 ? (r1[kind] - 1) / rpw[kind] - w0[kind] + 1 : 0;
+    }
+    const size_t woff1 = (size_t)a.blocks_a * (kForceBlock / kWave);
+    const int total = nw[0] + nw[1];
+    for (int jb = (int)threadIdx.x; jb < total; jb += 256 * kSysLoads) {
+        int ws[kSysLoads];
+        double4 q[kSysLoads][2];
 #pragma unroll
-            for (int u = 0; u < kSysLoads; ++u) {
-                const int w = min(wb + 256 * u, w1);
-                const double4* p = reinterpret_cast<const double4*>(a.wave_ew + 8 * (woff + w));
-                ws[u] = wb + 256 * u <= w1 ? a.wave_sys[woff + w] : -2;
-                q[u][0] = p[0];
-                q[u][1] = p[1];
-            }
+        for (int u = 0; u < kSysLoads; ++u) {
+            const int j = min(jb + 256 * u, total - 1);
+            const size_t wg = j < nw[0] ? (size_t)(w0[0] + j) : woff1 + (size_t)(w0[1] + j - nw[0]);
+            const double4* p = reinterpret_cast<const double4*>(a.wave_ew + 8 * wg);
+            ws[u] = jb + 256 * u < total ? a.wave_sys[wg] : -2;
+            q[u][0] = p[0];
+            q[u][1] = p[1];
+        }
 #pragma unroll
-            for (int u = 0; u < kSysLoads; ++u) {
-                if (ws[u] == sy) {
-                    v[0] += q[u][0].x; v[1] += q[u][0].y; v[2] += q[u][0].z; v[3] += q[u][0].w;
-                    v[4] += q[u][1].x; v[5] += q[u][1].y; v[6] += q[u][1].z; v[7] += q[u][1].w;
-                } else if (ws[u] == -1) {
-                    const int w = wb + 256 * u;
-                    const int e = min((w + 1) * rpw, r1);
-                    for (int r = max(w * rpw, r0); r < e; ++r) {
-                        const double* p = a.row_ew + 8 * (rbase + r);
+        for (int u = 0; u < kSysLoads; ++u) {
+            if (ws[u] == sy) {
+                v[0] += q[u][0].x; v[1] += q[u][0].y; v[2] += q[u][0].z; v[3] += q[u][0].w;
+                v[4] += q[u][1].x; v[5] += q[u][1].y; v[6] += q[u][1].z; v[7] += q[u][1].w;
+            } else if (ws[u] == -1) {
+                // a wave across a system boundary: its rows of this system
+                const int j = jb + 256 * u;
+                const int kind = j < nw[0] ? 0 : 1;
+                const int w = kind ? w0[1] + j - nw[0] : w0[0] + j;
+                const size_t rbase = kind ? (size_t)a.n_arow : 0;
+                const int e = min((w + 1) * rpw[kind], r1[kind]);
+                for (int r = max(w * rpw[kind], r0[kind]); r < e; ++r) {
+                    const double* p = a.row_ew + 8 * (rbase + r);
 #pragma unroll
-                        for (int k = 0; k < 8; ++k) v[k] += p[k];
-                    }
+                    for (int k = 0; k < 8; ++k) v[k] += p[k];
                 }
             }
         }
