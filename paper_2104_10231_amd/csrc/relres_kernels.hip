@@ -1690,17 +1690,25 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
     // the system's waves of both kinds (atom rows, then site rows) as one
     // range: both kinds' row ranges are read first, then kSysLoads waves per
     // thread per round have their system tags and records requested before
-    // any is used (a record is read whatever its tag says)
+    // any is used (a record is read whatever its tag says); the waves whose
+    // rows are all this system's (tag sy) are added here
+    // (the grid array always has two entries, so both kinds' ranges are read
+    // unconditionally, as scalar loads all in flight together)
     int w0[2] = {0, 0}, nw[2] = {0, 0}, rpw[2] = {1, 1}, r0[2] = {0, 0}, r1[2] = {0, 0};
+    {
+        RELRES_GLOBAL const GridDev* gg = gbl(grids);
+        RELRES_GLOBAL const GeomDev* ge0 = gbl(gg[0].geom);
+        RELRES_GLOBAL const GeomDev* ge1 = gbl(gg[1].geom);
+        const int base[2] = {ge0[sy].row_base, ge1[sy].row_base};
+        const int mem[2] = {ge0[sy].members, ngrids > 1 ? ge1[sy].members : 0};
 #pragma unroll
-    for (int kind = 0; kind < 2; ++kind) {
-        if (kind >= ngrids) continue;
-        const GeomDev& G = grids[kind].geom[sy];
-        rpw[kind] = kWave >> (kind ? a.log_lanes_b : a.log_lanes_a);
-        r0[kind] = G.row_base;
-        r1[kind] = G.row_base + G.members;
-        w0[kind] = r0[kind] / rpw[kind];
-        nw[kind] = G.members > 0 ? (r1[kind] - 1) / rpw[kind] - w0[kind] + 1 : 0;
+        for (int kind = 0; kind < 2; ++kind) {
+            rpw[kind] = kWave >> (kind ? a.log_lanes_b : a.log_lanes_a);
+            r0[kind] = base[kind];
+            r1[kind] = base[kind] + mem[kind];
+            w0[kind] = r0[kind] / rpw[kind];
+            nw[kind] = mem[kind] > 0 ? (r1[kind] - 1) / rpw[kind] - w0[kind] + 1 : 0;
+        }
     }
     const size_t woff1 = (size_t)a.blocks_a * (kForceBlock / kWave);
     const int total = nw[0] + nw[1];
@@ -1721,18 +1729,35 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
             if (ws[u] == sy) {
                 v[0] += q[u][0].x; v[1] += q[u][0].y; v[2] += q[u][0].z; v[3] += q[u][0].w;
                 v[4] += q[u][1].x; v[5] += q[u][1].y; v[6] += q[u][1].z; v[7] += q[u][1].w;
-            } else if (ws[u] == -1) {
-                // a wave across a system boundary: its rows of this system
-                const int j = jb + 256 * u;
-                const int kind = j < nw[0] ? 0 : 1;
-                const int w = kind ? w0[1] + j - nw[0] : w0[0] + j;
-                const size_t rbase = kind ? (size_t)a.n_arow : 0;
-                const int e = min((w + 1) * rpw[kind], r1[kind]);
-                for (int r = max(w * rpw[kind], r0[kind]); r < e; ++r) {
-                    const double* p = a.row_ew + 8 * (rbase + r);
+            }
+        }
+    }
+    // A wave across a system boundary (tag -1) left partials per row; only
+    // the first or the last wave of a kind's range can be one.  Their rows of
+    // this system, one row per thread, all four waves' loads issued together.
+    {
+        int wsb[4];
+        bool use[4];
+        double4 qb[4][2];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) v[k] += p[k];
-                }
+        for (int q = 0; q < 4; ++q) {
+            const int kind = q >> 1, e = q & 1;
+            const bool any = nw[kind] > 0 && (e == 0 || nw[kind] > 1);
+            const int w = e == 0 ? w0[kind] : w0[kind] + nw[kind] - 1;
+            const int lo = max(w * rpw[kind], r0[kind]), hi = min((w + 1) * rpw[kind], r1[kind]);
+            const int r = lo + (int)threadIdx.x;
+            use[q] = any && r < hi;
+            wsb[q] = any ? a.wave_sys[(kind ? woff1 : 0) + (size_t)w] : -2;
+            const size_t ri = any ? (kind ? (size_t)a.n_arow : 0) + (size_t)(use[q] ? r : lo) : 0;
+            const double4* p = reinterpret_cast<const double4*>(a.row_ew + 8 * ri);
+            qb[q][0] = p[0];
+            qb[q][1] = p[1];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (use[q] && wsb[q] == -1) {
+                v[0] += qb[q][0].x; v[1] += qb[q][0].y; v[2] += qb[q][0].z; v[3] += qb[q][0].w;
+                v[4] += qb[q][1].x; v[5] += qb[q][1].y; v[6] += qb[q][1].z; v[7] += qb[q][1].w;
             }
         }
     }
