@@ -291,8 +291,9 @@ int relres_forces(relres_ctx *ctx, const double *pos, void *forces, double *ener
  * process ends, instead of context buffers.  Nothing is allocated or freed:
  * the caller passes the outputs, and the lists come from the last
  * relres_build_lists.  RELRES_ERR_ARG when the launch would need more scratch
- * than the array holds (8 + 128 bytes per block of 256 threads; about 250k
- * atoms at 4 lanes per row) or, with energy or virial requested, for several
+ * than the array holds (256 bytes, then 128 for every block of 256 threads
+ * and for each of 16 record groups: up to 16366 blocks, e.g. a million rows
+ * at 4 lanes per row) or, with energy or virial requested, for several
  * systems (their per-row partials need context buffers; forces only is
  * fine).  Every call on one GPU shares that GPU's array: calls that overlap
  * on one GPU (several streams, threads or contexts at once) race and must be

@@ -1790,7 +1790,7 @@ int relres_forces(relres_ctx* c, const double* pos, void* forces, double* energy
         // energy/virial records: a fresh buffer may hold another context's
         // records, whose tags could match this context's; clear it (tag 0)
         const long long g0 = c->alloc_generation;
-        const size_t rec_bytes = (size_t)kEwRecBytes * (size_t)(a.blocks_a + a.blocks_b + kXcdGroups);
+        const size_t rec_bytes = (size_t)kEwRecBytes * (size_t)(a.blocks_a + a.blocks_b + kEwGroups);
         TRY(ensure(c->d_partials, rec_bytes, &c->alloc_generation));
         if (c->alloc_generation != g0)
             HIP_TRY(launch_clear_words(c->d_partials.as<unsigned long long>(),
@@ -1846,7 +1846,7 @@ int relres_forces_noalloc(relres_ctx* c, const double* pos, void* forces, double
                     "on device %d: %s", c->device, hipGetErrorString(c->scratch_err));
     ForceArgs a = force_args(c, pos, forces, energy, virial);
     const size_t need = kScratchEpochBytes +
-                        (size_t)kEwRecBytes * (size_t)(a.blocks_a + a.blocks_b + kXcdGroups);
+                        (size_t)kEwRecBytes * (size_t)(a.blocks_a + a.blocks_b + kEwGroups);
     if (ew && need > kScratchBytes)
         return fail(RELRES_ERR_ARG, "relres_forces_noalloc: this launch needs %zu bytes of "
                     "energy/virial scratch, the static array holds %zu (fewer lanes per row "

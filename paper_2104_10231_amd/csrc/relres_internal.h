@@ -322,7 +322,8 @@ hipError_t launch_md_finish(const MdArgs& m, hipStream_t s);
 // Row record field y: atom type in the low kTypeBits bits, system above.
 constexpr int kTypeBits = 5;
 constexpr int kRowsPerWave = 16;      // most home rows per wave of the list kernel
-constexpr int kXcdGroups = 8;        // workgroups are dealt round-robin to 8 XCDs
+constexpr int kEwGroups = 16;        // energy/virial record groups (blocks b % 16; two per
+                                      // XCD under the round-robin dispatch to 8 XCDs)
 constexpr int kEwRecBytes = 128;     // one energy/virial record: 16 tagged 64-bit words
 constexpr int kForceBlock = 256;
 constexpr int kListBlock = 256;

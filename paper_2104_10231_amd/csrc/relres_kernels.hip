@@ -1293,10 +1293,12 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
 // read-modify-write (which serialise on one address) is needed.  The tag is
 // the device epoch + 1; the epoch advances once per launch.
 //
-// Blocks b with b % 8 == g form group g.  The highest-numbered block of each
-// group waits for the records of the rest of its group and publishes the group
-// sum; block nb-1 (the highest of all) then waits for the group records and
-// writes energy and virial.  A waiting block only ever waits for blocks with
+// Blocks b with b % 16 == g form group g (16 groups: fewer records for each
+// group's waiting block to poll than with 8, and still one poll round for the
+// 16 group records).  The highest-numbered block of each group waits for the
+// records of the rest of its group and publishes the group sum; block nb-1
+// (the highest of all) then waits for the group records and writes energy
+// and virial.  A waiting block only ever waits for blocks with
 // lower numbers, which the hardware dispatched before it, so every wait ends;
 // it is bounded anyway (a.spin_limit polls; a negative limit gives up at
 // once), after which energy and virial are set to NaN and the status counts
@@ -1304,11 +1306,7 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
 // Sums are taken in a fixed order: the result does not depend on which block
 // finished when.
 constexpr int kRecWords = 16;
-constexpr int kPollBatch = 16;   // records polled per thread at once
 
-// Writes one record: called by the whole block, `v` valid in threads 0..7
-// (component threadIdx.x).  Lanes 0..15 of wave 0 store word threadIdx.x, so
-// the record goes out as one contiguous 128-byte write.
 // Writes one record: called by the whole block, `v` valid in threads 0..7
 // (component threadIdx.x).  Lanes 0..15 of wave 0 store word threadIdx.x, so
 // the record goes out as one contiguous 128-byte write, written through to
@@ -1331,6 +1329,7 @@ __device__ __forceinline__ void put_record(unsigned long long* rec, double v, un
 // return, even lanes hold their record-word pair's component (t % 16) / 2
 // summed over their records in v[]; odd lanes hold zeros.  Sets *failed if a
 // wait gave up.
+template <int kPollBatch>      // records polled per thread at once
 __device__ __forceinline__ void gather_records(const unsigned long long* rec, int first, int stride,
                                                int count, unsigned tag, int spin_limit,
                                                double v[8], int* failed)
@@ -1385,10 +1384,13 @@ __device__ __forceinline__ double block_reduce8(const double v[8], double extra,
                                                 double (*red)[kForceBlock / 64])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double s[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double w = wave_sum(v[k]);
-        if (lane == 63) red[k][wave] = w;
+    for (int k = 0; k < 8; ++k) s[k] = v[k];
+    wave_sums(s);
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) red[k][wave] = s[k];
     }
     __syncthreads();
     double t = 0.0;
@@ -1406,9 +1408,9 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     __shared__ int failed;
     const int nb = (int)gridDim.x;
     const int b = (int)blockIdx.x;
-    const int g = b % kXcdGroups;
-    const int ngroups = nb < kXcdGroups ? nb : kXcdGroups;
-    const int last_in_group = g + kXcdGroups * ((nb - 1 - g) / kXcdGroups);
+    const int g = b % kEwGroups;
+    const int ngroups = nb < kEwGroups ? nb : kEwGroups;
+    const int last_in_group = g + kEwGroups * ((nb - 1 - g) / kEwGroups);
 
     if (threadIdx.x == 0) failed = 0;
     const double mine = block_reduce8(acc, 0.0, red);
@@ -1420,7 +1422,20 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     }
     // group g: members g, g+8, ..., b-8 (in that order), then this block
     double v[8];
-    gather_records(a.ew_rec, g, kXcdGroups, b / kXcdGroups, tag, a.spin_limit, v, &failed);
+    // records per thread per poll: as few loads as cover the group in one
+    // round (a poll's loads queue on this one CU's memory pipeline, so extra
+    // slots that re-read a record cost time: 16 per thread took 0.5 us more
+    // than 8 for 71 records)
+    const int count = b / kEwGroups;
+    constexpr int kSlots = kForceBlock / kRecWords;      // records per load instruction
+    if (count <= 2 * kSlots)
+        gather_records<2>(a.ew_rec, g, kEwGroups, count, tag, a.spin_limit, v, &failed);
+    else if (count <= 4 * kSlots)
+        gather_records<4>(a.ew_rec, g, kEwGroups, count, tag, a.spin_limit, v, &failed);
+    else if (count <= 8 * kSlots)
+        gather_records<8>(a.ew_rec, g, kEwGroups, count, tag, a.spin_limit, v, &failed);
+    else
+        gather_records<16>(a.ew_rec, g, kEwGroups, count, tag, a.spin_limit, v, &failed);
     const double gsum = block_reduce8(v, mine, red);
     if (b != nb - 1) {
         put_record(grec + (size_t)g * kRecWords, failed ? __builtin_nan("") : gsum, tag);
@@ -1430,7 +1445,7 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     // final block: the group sums in group order.  The other groups' records
     // are gathered (groups 0..ngroups-1 except g, which is this block's own);
     // to keep the order fixed, the own group's sum is slotted in at its place.
-    __shared__ double gred[kXcdGroups][8];
+    __shared__ double gred[kEwGroups][8];
     if (threadIdx.x < 8) gred[g][threadIdx.x] = gsum;
     {
         const int t = (int)threadIdx.x;
@@ -1640,12 +1655,12 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
             } else {
                 const int s0 = __builtin_amdgcn_readlane(sys_row, __ffsll((long long)own_mask) - 1);
                 if (__ballot(own && sys_row != s0) == 0ull) {
+                    wave_sums(acc);
+                    if (lane == kWave - 1) {
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const double w = wave_sum(acc[k]);
-                        if (lane == kWave - 1) a.wave_ew[8 * wrec + k] = w;
+                        for (int k = 0; k < 8; ++k) a.wave_ew[8 * wrec + k] = acc[k];
+                        a.wave_sys[wrec] = s0;
                     }
-                    if (lane == kWave - 1) a.wave_sys[wrec] = s0;
                 } else {
 #pragma unroll
                     for (int k = 0; k < 8; ++k) acc[k] = group_sum(acc[k], G);
@@ -1761,10 +1776,10 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
             }
         }
     }
+    wave_sums(v);
+    if ((threadIdx.x & 63) == 63) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double w = wave_sum(v[k]);
-        if ((threadIdx.x & 63) == 63) red[k][threadIdx.x >> 6] = w;
+        for (int k = 0; k < 8; ++k) red[k][threadIdx.x >> 6] = v[k];
     }
     __syncthreads();
     if (threadIdx.x < 8) {
@@ -2151,10 +2166,14 @@ __global__ __launch_bounds__(kForceBlock) void k_backward(BackArgs b)
 #pragma unroll
         for (int q = 0; q < TM; ++q) {
             if (q >= nt) break;
+            // the four parameters' sums at once (their chains interleaved)
+            double s[4];
 #pragma unroll
-            for (int P = 0; P < 4; ++P) {
-                const double v = wave_sum((own && ti == t) ? acc[q][P] : 0.0);
-                if ((threadIdx.x & 63) == 63) out[(t * nt + q) * 4 + P] = v;
+            for (int P = 0; P < 4; ++P) s[P] = (own && ti == t) ? acc[q][P] : 0.0;
+            wave_sums(s);
+            if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+                for (int P = 0; P < 4; ++P) out[(t * nt + q) * 4 + P] = s[P];
             }
         }
 }

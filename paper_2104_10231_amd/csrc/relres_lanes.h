@@ -45,6 +45,26 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// wave_sum of K values at once, step by step across the values, so the K
+// dependent chains of lane moves and adds overlap (the same sums, in the same
+// order, as K separate wave_sum calls); complete in lane 63.
+template <int K>
+__device__ __forceinline__ void wave_sums(double (&v)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp<kDppXor1>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp<kDppXor2>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp<kDppHalfMirror>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp<kDppMirror>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp<kDppBcast15, 0xA>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp<kDppBcast31, 0xC>(v[k]);
+}
+
 // Sum over each aligned group of G lanes (G a power of two <= 64, uniform in
 // the wave); every lane of a group holds its group's sum.
 template <typename T>

@@ -66,18 +66,25 @@ __device__ __forceinline__ void add_virial(double* w, const double* lever, const
 }
 
 // Fixed-order sum over the block (kMdBlock threads) of v[0..K): the result
-// lands in threads 0..K-1 (component threadIdx.x).
+// lands in threads 0..K-1 (component threadIdx.x).  Lane moves within each
+// wave (the K chains interleaved), then the waves' sums through LDS: two
+// block barriers, where a tree through LDS takes one per halving.
 template <int K>
-__device__ __forceinline__ double block_sum(const double* v, double (*red)[kMdBlock])
+__device__ __forceinline__ double block_sum(const double* v, double (*red)[kMdBlock / 64])
 {
-    for (int k = 0; k < K; ++k) red[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int s = kMdBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = v[k];
+    wave_sums(s);                      // complete in lane 63
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k][w] = s[k];
     }
-    const double r = (int)threadIdx.x < K ? red[threadIdx.x][0] : 0.0;
+    __syncthreads();
+    double r = 0.0;
+    if ((int)threadIdx.x < K)
+        for (int q = 0; q < kMdBlock / 64; ++q) r += red[threadIdx.x][q];
     __syncthreads();
     return r;
 }
@@ -218,7 +225,7 @@ __device__ __forceinline__ void pair14_force(const BondedArgs& b, const BondItem
 template <typename TF>
 __global__ __launch_bounds__(kMdBlock) void k_bonded(BondedArgs b, MdArgs m, int kick)
 {
-    __shared__ double red[10][kMdBlock];
+    __shared__ double red[10][kMdBlock / 64];
     const int lg = b.log_lanes;
     const int G = 1 << lg;
     const int gid = blockIdx.x * kMdBlock + (int)threadIdx.x;
@@ -278,13 +285,34 @@ __global__ __launch_bounds__(kMdBlock) void k_bonded(BondedArgs b, MdArgs m, int
 
 // Sum over the blocks' partials in a fixed order: lane l of a wave adds
 // blocks l, l + 64, ... of p1 and then of p2, and the wave adds its lanes.
+// A lane's loads are issued kSumLoads at a time before any is added, so a
+// few hundred partials cost one or two memory round trips, not one per
+// block of the lane.
+constexpr int kSumLoads = 8;
+
+__device__ __forceinline__ void add_blocks(const double* __restrict__ p, int n, int K, int k,
+                                           int lane, double& s)
+{
+    for (int base = lane; base < n; base += 64 * kSumLoads) {
+        double x[kSumLoads];
+#pragma unroll
+        for (int u = 0; u < kSumLoads; ++u) {
+            const int blk = base + 64 * u;
+            x[u] = blk < n ? p[(size_t)blk * K + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumLoads; ++u)
+            if (base + 64 * u < n) s += x[u];
+    }
+}
+
 __device__ __forceinline__ double sum_blocks(const double* __restrict__ p1, int n1,
                                              const double* __restrict__ p2, int n2, int K, int k)
 {
     const int lane = (int)threadIdx.x & 63;
     double s = 0.0;
-    for (int blk = lane; blk < n1; blk += 64) s += p1[(size_t)blk * K + k];
-    for (int blk = lane; blk < n2; blk += 64) s += p2[(size_t)blk * K + k];
+    add_blocks(p1, n1, K, k, lane, s);
+    add_blocks(p2, n2, K, k, lane, s);
     return wave_sum(s);                // complete in lane 63
 }
 
@@ -405,7 +433,7 @@ __global__ __launch_bounds__(kMdBlock) void k_md_drift(MdArgs m, const MdState* 
 // Kinetic partials of the stored velocities (no kick), at the start of a run.
 __global__ __launch_bounds__(kMdBlock) void k_md_kinetic(MdArgs m)
 {
-    __shared__ double red[1][kMdBlock];
+    __shared__ double red[1][kMdBlock / 64];
     const int i = blockIdx.x * kMdBlock + threadIdx.x;
     double ke = 0.0;
     if (i < m.n)
