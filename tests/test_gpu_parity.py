@@ -73,6 +73,24 @@ def test_neopentane_20480_fp32(pair_math):
     _check(w.neopentane_liquid(0), 32, pair_math=pair_math)
 
 
+@pytest.mark.parametrize("n_side", [8, 16, 20, 26])
+def test_energy_virial_at_every_poll_width(n_side):
+    """Neopentane liquids of 2560 to 87880 atoms: their force launches have
+    from ~70 to ~2500 blocks, so the blocks that gather their record group
+    poll 2, 4, 8 and 16 records per thread.  Energy and virial against the
+    oracle at the FP32 bar, and repeated calls bitwise equal."""
+    import torch
+    s = w.neopentane_liquid(3, n_side=n_side)
+    F, E, W = _check(s, 32)
+    rr = make_relres(s, 32)
+    p = torch.from_numpy(s.pos).cuda()
+    rr.build_lists(p, s.box)
+    for _ in range(3):
+        F2, E2, W2 = [t.cpu().numpy() for t in rr.forces(p)]
+        assert np.array_equal(E2, E) and np.array_equal(W2, W)
+    rr.close()
+
+
 @pytest.mark.parametrize("name,precision,pair_math", [("propane", 64, 0), ("neopentane", 32, 32),
                                                     ("neopentane", 32, 64)])
 def test_forces_only_calls(name, precision, pair_math):
