@@ -170,26 +170,27 @@ __global__ void k_bin(int n, const double* __restrict__ pos, TopoDev topo,
     const double wx = wrap_coord(x, G.box[0]), wy = wrap_coord(y, G.box[1]),
                  wz = wrap_coord(z, G.box[2]);
     if (in) wpos[i] = make_double4(wx, wy, wz, 0.0);
-    {
-        const int lin = (cell_coord(wx, G.inv_cell[0], G.n[0]) * G.n[1] +
-                         cell_coord(wy, G.inv_cell[1], G.n[1])) * G.n[2] +
-                        cell_coord(wz, G.inv_cell[2], G.n[2]);
-        const int r = gbl(ga.rank_of_lin)[G.cell_base + lin];
-        const int slot = claim_slot(ga.count, r, in);
-        if (in) key_a[i] = make_int2(r, slot);
-        // one-launch placement: the member goes straight into its cell's bucket
-        if (in && slot < ga.bucket_cap)
-            gbl(ga.user_unsorted)[(size_t)r * ga.bucket_cap + slot] = i;
-    }
+    // both grids' cell ranks are read before either slot is claimed
+    const int lin = (cell_coord(wx, G.inv_cell[0], G.n[0]) * G.n[1] +
+                     cell_coord(wy, G.inv_cell[1], G.n[1])) * G.n[2] +
+                    cell_coord(wz, G.inv_cell[2], G.n[2]);
+    const int r = gbl(ga.rank_of_lin)[G.cell_base + lin];
     const bool hyb = in && topo.hybrid[topo.types[i]] != 0;
     int rs = -1;
     if (hyb) {
         const GridDev& gs = grids[1];
         const GeomDev& H = gs.geom[sy];
-        const int lin = (cell_coord(wx, H.inv_cell[0], H.n[0]) * H.n[1] +
-                         cell_coord(wy, H.inv_cell[1], H.n[1])) * H.n[2] +
-                        cell_coord(wz, H.inv_cell[2], H.n[2]);
-        rs = gbl(gs.rank_of_lin)[H.cell_base + lin];
+        const int lin_s = (cell_coord(wx, H.inv_cell[0], H.n[0]) * H.n[1] +
+                           cell_coord(wy, H.inv_cell[1], H.n[1])) * H.n[2] +
+                          cell_coord(wz, H.inv_cell[2], H.n[2]);
+        rs = gbl(gs.rank_of_lin)[H.cell_base + lin_s];
+    }
+    {
+        const int slot = claim_slot(ga.count, r, in);
+        if (in) key_a[i] = make_int2(r, slot);
+        // one-launch placement: the member goes straight into its cell's bucket
+        if (in && slot < ga.bucket_cap)
+            gbl(ga.user_unsorted)[(size_t)r * ga.bucket_cap + slot] = i;
     }
     // grids[1] is grids[0] again when there are no sites (no hybrid lanes then)
     const int slot_s = claim_slot(grids[1].count, rs, hyb);
@@ -479,7 +480,18 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restri
     RELRES_GLOBAL int* gstart = gbl(g.start);
     RELRES_GLOBAL const int* bucket = gbl(g.user_unsorted);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    // group q of G lanes: cell c0 + wave * kCellsPerWave + q
+    const int q = lane / kSortGroup, gl = lane & (kSortGroup - 1);
+    const int ci = wave * kCellsPerWave + q;
+    const int c = c0 + ci;
+    const int in_group = kSortGroup < cap ? kSortGroup : cap;
 
+    // Every read that does not depend on another is issued first: the
+    // block's own counts (wave 0), the first in_group bucket slots of each
+    // group's cell (whatever the cell's count; slots past it are dropped
+    // below) and the counts of the cells before this block's.
+    const int own_cnt = (wave == 0 && lane < kCells && c0 + lane < nc) ? gcount[c0 + lane] : 0;
+    const int u_slot = (c < nc && gl < in_group) ? bucket[(size_t)c * cap + gl] : 0x7fffffff;
     // members of the grid's cells before this block's: c0 is a multiple of 4,
     // so the counts are read as int4, four loads per thread in flight at once
     int s = 0;
@@ -505,7 +517,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restri
         int carry = 0;
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) carry += wtot[k];
-        const int v = (lane < kCells && c0 + lane < nc) ? gcount[c0 + lane] : 0;
+        const int v = own_cnt;
         int x = v;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
@@ -521,15 +533,10 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restri
     }
     __syncthreads();
 
-    // group q of G lanes: cell c0 + wave * kCellsPerWave + q
-    const int q = lane / kSortGroup, gl = lane & (kSortGroup - 1);
-    const int ci = wave * kCellsPerWave + q;
-    const int c = c0 + ci;
     const int len = c < nc ? cnt_sh[ci] : 0;
     const int b = first_sh[ci];
-    const int in_group = kSortGroup < cap ? kSortGroup : cap;
     const bool small = len <= in_group;
-    const int u = (small && gl < len) ? bucket[(size_t)c * cap + gl] : 0x7fffffff;
+    const int u = (small && gl < len) ? u_slot : 0x7fffffff;
     int r = 0;
     if constexpr (kSortGroup < kWave) {
 #pragma unroll
