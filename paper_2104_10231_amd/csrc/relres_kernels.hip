@@ -1391,14 +1391,8 @@ __device__ __forceinline__ double block_reduce8(const double v[8], double extra,
                                                 double (*red)[kForceBlock / 64])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double s[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s[k] = v[k];
-    wave_sums(s);
-    if (lane == 63) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) red[k][wave] = s[k];
-    }
+    const double s = wave_sum8(v);
+    if (lane < 8) red[wave_sum8_lane(lane)][wave] = s;
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x < 8) {
@@ -1662,12 +1656,9 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
             } else {
                 const int s0 = __builtin_amdgcn_readlane(sys_row, __ffsll((long long)own_mask) - 1);
                 if (__ballot(own && sys_row != s0) == 0ull) {
-                    wave_sums(acc);
-                    if (lane == kWave - 1) {
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) a.wave_ew[8 * wrec + k] = acc[k];
-                        a.wave_sys[wrec] = s0;
-                    }
+                    const double ws = wave_sum8(acc);
+                    if (lane < 8) a.wave_ew[8 * wrec + wave_sum8_lane(lane)] = ws;
+                    if (lane == 0) a.wave_sys[wrec] = s0;
                 } else {
 #pragma unroll
                     for (int k = 0; k < 8; ++k) acc[k] = group_sum(acc[k], G);
@@ -1783,10 +1774,10 @@ __global__ __launch_bounds__(256) void k_reduce_sys_ew(const GridDev* __restrict
             }
         }
     }
-    wave_sums(v);
-    if ((threadIdx.x & 63) == 63) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) red[k][threadIdx.x >> 6] = v[k];
+    {
+        const double s = wave_sum8(v);
+        const int lane = (int)threadIdx.x & 63;
+        if (lane < 8) red[wave_sum8_lane(lane)][threadIdx.x >> 6] = s;
     }
     __syncthreads();
     if (threadIdx.x < 8) {
