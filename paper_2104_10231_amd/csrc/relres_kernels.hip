@@ -743,12 +743,14 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     // unconditional (lanes past the stencil and empty slots read a valid entry
     // and drop it at use), so no branch makes the compiler wait for them early.
     int next_rank[St::kPerLane];
+    int next_lin = 0;      // the next home cell's linear index (its coordinates)
     auto ranks_of = [&](int h) {
         const int c = readlane_i(mcell, h);
+        next_lin = glor[c];
         if constexpr (S == 3) {
             next_rank[0] = gnbr[c * 27 + min(lane, 26)];
         } else {
-            const int lin = __builtin_amdgcn_readfirstlane(glor[c]);
+            const int lin = __builtin_amdgcn_readfirstlane(next_lin);
             const int cz = lin % n2, cy = (lin / n2) % n1, cx = lin / (n1 * n2);
 #pragma unroll
             for (int u = 0; u < St::kPerLane; ++u)
@@ -767,7 +769,12 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     auto range_of = [&]() {
 #pragma unroll
         for (int u = 0; u < St::kPerLane; ++u) {
-            const int r = slot_valid(u) ? next_rank[u] : 0;
+            int r = next_rank[u];
+            // keeps the rank's first use here, after this cell's candidate
+            // loads were issued: hoisted ahead of them, it would make the
+            // wave wait for the rank read first
+            asm volatile("" : "+v"(r));
+            r = lane + kWave * u < St::kSlots && r >= 0 ? r : 0;
             next_lo[u] = gstart[r];
             next_hi[u] = gstart[r + 1];
         }
@@ -787,17 +794,15 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             s0[u] = ok ? next_lo[u] : 0;
             cnt[u] = ok ? next_hi[u] - next_lo[u] : 0;
         }
+        // this cell's linear index, read one cell ahead with its stencil ranks
+        const int lin_c = __builtin_amdgcn_readfirstlane(next_lin);
         if (h1 < nh) ranks_of(h1); else no_ranks();
         // first candidate of every slot: a wave scan of the counts in slot
         // order (slot lane, then slot lane + 64)
         int ncand = 0;
 #pragma unroll
         for (int u = 0; u < St::kPerLane; ++u) {
-            int pre = cnt[u];
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int v = __shfl_up(pre, o);
-                if (lane >= o) pre += v;
-            }
+            const int pre = wave_inclusive_scan(cnt[u]);
             const int slot = lane + kWave * u;
             if (slot < St::kTab) {
                 slot_first[slot] = ncand + pre - cnt[u];
@@ -811,10 +816,9 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
         // home cell coordinates: the periodic shift of every stencil slot
         int cx = 0, cy = 0, cz = 0;
         if (known_shift) {
-            const int lin = __builtin_amdgcn_readfirstlane(glor[c]);
-            cz = lin % n2;
-            cy = (lin / n2) % n1;
-            cx = lin / (n1 * n2);
+            cz = lin_c % n2;
+            cy = (lin_c / n2) % n1;
+            cx = lin_c / (n1 * n2);
         }
         for (int cb = 0; cb < ncand; cb += kWave * K) {
             double px[K], py[K], pz[K];
@@ -850,7 +854,10 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                     }
                 }
             }
-            for (int h = __builtin_amdgcn_readfirstlane(h0); h < h1; ++h) {
+            // every cell has at least one home row (h1 > h0): a loop that
+            // always runs, so no path skips it with candidate reads pending
+            int h = __builtin_amdgcn_readfirstlane(h0);
+            do {
                 if (cb == 0 && h == h0) range_of();
                 const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
                 const int ui = readlane_i(mu, h);
@@ -889,7 +896,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                     hc += __popcll(mask);
                 }
                 if (lane == h) mcnt = hc;
-            }
+            } while (++h < h1);
         }
         if (ncand == 0) range_of();
         // the slot table is rewritten for the next cell

@@ -17,6 +17,10 @@ constexpr int kDppMirror = 0x140;       // lane i <- lane 15-i within 16
 constexpr int kDppBcast15 = 0x142;      // lane 15 of each row -> next row
 constexpr int kDppBcast31 = 0x143;      // lane 31 -> rows 2 and 3
 constexpr int kDppRor8 = 0x128;         // lane i <- lane i ^ 8 within 16 (rotate by 8)
+constexpr int kDppShr1 = 0x111;         // lane i <- lane i - 1 within 16 (0 past the row)
+constexpr int kDppShr2 = 0x112;
+constexpr int kDppShr4 = 0x114;
+constexpr int kDppShr8 = 0x118;
 
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ float dpp(float v)
@@ -64,6 +68,20 @@ __device__ __forceinline__ void wave_sums(double (&v)[K])
     for (int k = 0; k < K; ++k) v[k] += dpp<kDppBcast15, 0xA>(v[k]);
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += dpp<kDppBcast31, 0xC>(v[k]);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave by DPP lane moves: shifts
+// by 1, 2, 4, 8 within each row of 16, then the rows' totals carried across
+// (lane 15 to the next row, lane 31 to the upper two).
+__device__ __forceinline__ int wave_inclusive_scan(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, kDppShr1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppShr2, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppShr4, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppShr8, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppBcast15, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppBcast31, 0xc, 0xf, false);
+    return v;
 }
 
 // Lane exchange i <-> i ^ X for X in 4, 8, 16 through ds_swizzle (bit mode:
