@@ -854,6 +854,17 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                     }
                 }
             }
+            // The conditions of a (row, candidate) pair other than the
+            // distance are wave lane masks, one per k, combined with scalar
+            // ANDs: a lane's own work per row is its compares and its
+            // distance test.  `live` marks the slots holding a candidate.
+            uint64_t live[K];
+            int word[K];      // the list entry of each candidate
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                live[k] = __ballot(pu[k] >= 0);
+                word[k] = (int)((uint32_t)pu[k] | ((uint32_t)pt[k] << kIdxBits));
+            }
             // every cell has at least one home row (h1 > h0): a loop that
             // always runs, so no path skips it with candidate reads pending
             int h = __builtin_amdgcn_readfirstlane(h0);
@@ -865,23 +876,26 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 const int ne = readlane_i(mee, h) - readlane_i(meb, h);
                 const int* hex = my_excl + h * max_excl;
                 int hc = readlane_i(mcnt, h);
-                RELRES_GLOBAL int* out = glist + (size_t)(r0 + h) * cap;
-                bool keep_k[K];
+                RELRES_GLOBAL int* out =
+                    glist + (size_t)__builtin_amdgcn_readfirstlane(r0 + h) * cap;
+                uint64_t keep[K];
 #pragma unroll
-                for (int k = 0; k < K; ++k)
-                    keep_k[k] = pu[k] >= 0 && pu[k] != ui && !(same_mol && pm[k] == moli);
+                for (int k = 0; k < K; ++k) {
+                    uint64_t m = live[k] & __ballot(pu[k] != ui);
+                    if (same_mol) m &= ~__ballot(pm[k] == moli);
+                    keep[k] = m;
+                }
                 // the row's exclusions: each read once for all K candidates,
                 // several reads in flight before the first compare
 #pragma unroll 4
                 for (int e = 0; e < ne; ++e) {
                     const int x = hex[e];
 #pragma unroll
-                    for (int k = 0; k < K; ++k) keep_k[k] = keep_k[k] && pu[k] != x;
+                    for (int k = 0; k < K; ++k) keep[k] &= __ballot(pu[k] != x);
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (cb + kWave * k >= ncand) break;
-                    const int uj = pu[k];
                     // the distance test for every lane (no divergent branch
                     // around it), then the other conditions
                     const bool in = known_shift
@@ -889,10 +903,13 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                         : member(make_double4(xi, yi, zi, 0.0),
                                  make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx, hy, hz,
                                  rl2);
-                    const bool keep = keep_k[k] && in;
-                    const uint64_t mask = __ballot(keep);
-                    const int p = hc + lanes_below(mask);
-                    if (keep && p < cap) out[p] = (int)((uint32_t)uj | ((uint32_t)pt[k] << kIdxBits));
+                    const uint64_t mask = keep[k] & __ballot(in);
+                    if (__builtin_amdgcn_inverse_ballot_w64(mask)) {
+                        // 32-bit slot index: the store takes the row's scalar
+                        // base and one lane offset
+                        const uint32_t p = (uint32_t)(hc + lanes_below(mask));
+                        if (p < (uint32_t)cap) out[p] = word[k];
+                    }
                     hc += __popcll(mask);
                 }
                 if (lane == h) mcnt = hc;
