@@ -673,7 +673,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                                           const TopoDev& topo, const int* __restrict__ user2arow,
                                           int4* __restrict__ a_rec, int4* __restrict__ s_rec,
                                           Status* __restrict__ st, int* slot_first,
-                                          int* slot_start, int* excl_lds)
+                                          int* slot_start, double* slot_shift, int* excl_lds)
 {
     using St = Stencil<S>;
     const int lane = threadIdx.x & (kWave - 1);
@@ -797,8 +797,17 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
         // this cell's linear index, read one cell ahead with its stencil ranks
         const int lin_c = __builtin_amdgcn_readfirstlane(next_lin);
         if (h1 < nh) ranks_of(h1); else no_ranks();
+        // home cell coordinates: the periodic shift of every stencil slot
+        int cx = 0, cy = 0, cz = 0;
+        if (known_shift) {
+            cz = lin_c % n2;
+            cy = (lin_c / n2) % n1;
+            cx = lin_c / (n1 * n2);
+        }
         // first candidate of every slot: a wave scan of the counts in slot
-        // order (slot lane, then slot lane + 64)
+        // order (slot lane, then slot lane + 64); with known shifts, each
+        // slot's periodic image shift (-L, 0 or +L per axis) is tabulated
+        // once here instead of per candidate
         int ncand = 0;
 #pragma unroll
         for (int u = 0; u < St::kPerLane; ++u) {
@@ -808,22 +817,21 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 slot_first[slot] = ncand + pre - cnt[u];
                 slot_start[slot] = s0[u];
             }
+            if (known_shift && slot < St::kSlots) {
+                const int ox = St::off(slot, 0), oy = St::off(slot, 1), oz = St::off(slot, 2);
+                slot_shift[slot] = cx + ox < 0 ? -Lx : (cx + ox >= n0 ? Lx : 0.0);
+                slot_shift[St::kTab + slot] = cy + oy < 0 ? -Ly : (cy + oy >= n1 ? Ly : 0.0);
+                slot_shift[2 * St::kTab + slot] = cz + oz < 0 ? -Lz : (cz + oz >= n2 ? Lz : 0.0);
+            }
             ncand += __builtin_amdgcn_readfirstlane(__shfl(pre, kWave - 1));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // home cell coordinates: the periodic shift of every stencil slot
-        int cx = 0, cy = 0, cz = 0;
-        if (known_shift) {
-            cz = lin_c % n2;
-            cy = (lin_c / n2) % n1;
-            cx = lin_c / (n1 * n2);
-        }
         for (int cb = 0; cb < ncand; cb += kWave * K) {
             double px[K], py[K], pz[K];
-            // periodic image shift of the candidate's slot (-L, 0 or +L per axis),
-            // taken once per candidate for all the rows
+            // periodic image shift of the candidate's slot, taken once per
+            // candidate for all the rows
             double sx[K], sy[K], sz[K];
             int pu[K], pt[K], pm[K];
 #pragma unroll
@@ -847,10 +855,9 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                     load_meta(gmeta, src, pt[k], pm[k]);
                     pu[k] = guser[src];
                     if (known_shift) {
-                        const int ox = St::off(slot, 0), oy = St::off(slot, 1), oz = St::off(slot, 2);
-                        sx[k] = cx + ox < 0 ? -Lx : (cx + ox >= n0 ? Lx : 0.0);
-                        sy[k] = cy + oy < 0 ? -Ly : (cy + oy >= n1 ? Ly : 0.0);
-                        sz[k] = cz + oz < 0 ? -Lz : (cz + oz >= n2 ? Lz : 0.0);
+                        sx[k] = slot_shift[slot];
+                        sy[k] = slot_shift[St::kTab + slot];
+                        sz[k] = slot_shift[2 * St::kTab + slot];
                     }
                 }
             }
@@ -947,6 +954,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
 {
     __shared__ int slot_first[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ int slot_start[4][Stencil<(SA > SS ? SA : SS)>::kTab];
+    __shared__ double slot_shift[4][3 * Stencil<(SA > SS ? SA : SS)>::kTab];
     extern __shared__ int excl_lds[];
     // wave-uniform by construction; readfirstlane lets the compiler keep it
     // (and everything derived from it) in scalar registers
@@ -957,10 +965,10 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         const int lw = site ? gw - waves_a : gw;
         if (site)
             list_wave<K, SS>(grids[1], wv, lw, true, max_excl, topo, user2arow, a_rec, s_rec, st,
-                             slot_first[wv], slot_start[wv], excl_lds);
+                             slot_first[wv], slot_start[wv], slot_shift[wv], excl_lds);
         else
             list_wave<K, SA>(grids[0], wv, lw, false, max_excl, topo, user2arow, a_rec, s_rec,
-                             st, slot_first[wv], slot_start[wv], excl_lds);
+                             st, slot_first[wv], slot_start[wv], slot_shift[wv], excl_lds);
     }
     clear_bucket_counts(grids);   // last: the stores leave the start of the kernel alone
 }
