@@ -673,7 +673,8 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                                           const TopoDev& topo, const int* __restrict__ user2arow,
                                           int4* __restrict__ a_rec, int4* __restrict__ s_rec,
                                           Status* __restrict__ st, int* slot_first,
-                                          int* slot_start, double* slot_shift, int* excl_lds)
+                                          int* slot_start, double* slot_shift, int* slot_win,
+                                          int* excl_lds)
 {
     using St = Stencil<S>;
     const int lane = threadIdx.x & (kWave - 1);
@@ -809,12 +810,14 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
         // slot's periodic image shift (-L, 0 or +L per axis) is tabulated
         // once here instead of per candidate
         int ncand = 0;
+        int first[St::kPerLane];
 #pragma unroll
         for (int u = 0; u < St::kPerLane; ++u) {
             const int pre = wave_inclusive_scan(cnt[u]);
             const int slot = lane + kWave * u;
+            first[u] = ncand + pre - cnt[u];
             if (slot < St::kTab) {
-                slot_first[slot] = ncand + pre - cnt[u];
+                slot_first[slot] = first[u];
                 slot_start[slot] = s0[u];
             }
             if (known_shift && slot < St::kSlots) {
@@ -828,7 +831,39 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int carry = -1;      // the slot of candidate cb - 1
         for (int cb = 0; cb < ncand; cb += kWave * K) {
+            // The slot of each of the round's 64 K candidates (cb + p for p =
+            // lane + 64 k): every non-empty slot marks its first candidate in
+            // a window of the round (candidate cb + p at (p % 64) K + p / 64,
+            // so a lane's K entries are one vector read), and a running
+            // maximum in candidate order carries each mark over the slot's
+            // other candidates.
+#pragma unroll
+            for (int k = 0; k < K; ++k) slot_win[lane * K + k] = -1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int u = 0; u < St::kPerLane; ++u) {
+                const int p = first[u] - cb;
+                if (cnt[u] > 0 && p >= 0 && p < kWave * K)
+                    slot_win[(p & (kWave - 1)) * K + (p >> 6)] = lane + kWave * u;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int cslot[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) cslot[k] = slot_win[lane * K + k];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                cslot[k] = max(wave_inclusive_max(cslot[k]), carry);
+                carry = __builtin_amdgcn_readlane(cslot[k], kWave - 1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             double px[K], py[K], pz[K];
             // periodic image shift of the candidate's slot, taken once per
             // candidate for all the rows
@@ -837,14 +872,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int q = cb + lane + kWave * k;
-                // the last slot whose first candidate is <= q (empty slots
-                // repeat the next slot's first candidate)
-                int lo = 0, hi = St::kSlots - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (slot_first[mid] <= q) lo = mid; else hi = mid - 1;
-                }
-                const int slot = lo;
+                const int slot = max(cslot[k], 0);
                 const int src = slot_start[slot] + (q - slot_first[slot]);
                 px[k] = py[k] = pz[k] = 0.0;
                 sx[k] = sy[k] = sz[k] = 0.0;
@@ -955,6 +983,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
     __shared__ int slot_first[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ int slot_start[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ double slot_shift[4][3 * Stencil<(SA > SS ? SA : SS)>::kTab];
+    __shared__ __align__(16) int slot_win[4][kWave * K];
     extern __shared__ int excl_lds[];
     // wave-uniform by construction; readfirstlane lets the compiler keep it
     // (and everything derived from it) in scalar registers
@@ -965,10 +994,12 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         const int lw = site ? gw - waves_a : gw;
         if (site)
             list_wave<K, SS>(grids[1], wv, lw, true, max_excl, topo, user2arow, a_rec, s_rec, st,
-                             slot_first[wv], slot_start[wv], slot_shift[wv], excl_lds);
+                             slot_first[wv], slot_start[wv], slot_shift[wv], slot_win[wv],
+                             excl_lds);
         else
             list_wave<K, SA>(grids[0], wv, lw, false, max_excl, topo, user2arow, a_rec, s_rec,
-                             st, slot_first[wv], slot_start[wv], slot_shift[wv], excl_lds);
+                             st, slot_first[wv], slot_start[wv], slot_shift[wv], slot_win[wv],
+                             excl_lds);
     }
     clear_bucket_counts(grids);   // last: the stores leave the start of the kernel alone
 }

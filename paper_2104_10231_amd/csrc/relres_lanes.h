@@ -84,6 +84,22 @@ __device__ __forceinline__ int wave_inclusive_scan(int v)
     return v;
 }
 
+constexpr int kIntMin = -2147483647 - 1;
+
+// Inclusive running maximum over the 64 lanes of a wave (the lane moves of
+// wave_inclusive_scan; lanes without a source lane take INT_MIN, the
+// identity of the maximum, which lets each move fold into the max).
+__device__ __forceinline__ int wave_inclusive_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(kIntMin, v, kDppShr1, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(kIntMin, v, kDppShr2, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(kIntMin, v, kDppShr4, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(kIntMin, v, kDppShr8, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(kIntMin, v, kDppBcast15, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(kIntMin, v, kDppBcast31, 0xc, 0xf, false));
+    return v;
+}
+
 // Lane exchange i <-> i ^ X for X in 4, 8, 16 through ds_swizzle (bit mode:
 // and-mask 31, xor-mask X; within each half of the wave).
 template <int X>
