@@ -588,14 +588,6 @@ __device__ __forceinline__ void clear_bucket_counts(const GridDev* __restrict__ 
     }
 }
 
-// Neighbour lists, one wave per group of kRowsPerWave consecutive member rows
-// (rows are in cell order, so a group spans one or two cells).  Work per wave
-// is bounded by the group size, so crowded cells are spread over many waves.
-// Each lane owns one home row of the group: its position, exclusions and
-// running count live in that lane and are broadcast with readlane while the
-// wave tests 64 staged candidates at a time.  Only wave-level synchronisation
-// is used, so waves of one block may run different trip counts.
-
 // Membership with the periodic shift of the candidate's stencil slot known in
 // advance.  When a grid has at least four cells along an axis, a neighbour
 // cell reached without wrapping lies within two cells (< L/2) of the home
@@ -672,8 +664,8 @@ template <int K, int S>
 __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool site, int max_excl,
                                           const TopoDev& topo, const int* __restrict__ user2arow,
                                           int4* __restrict__ a_rec, int4* __restrict__ s_rec,
-                                          Status* __restrict__ st, int* slot_first,
-                                          int* slot_start, double* slot_shift, int* slot_win,
+                                          Status* __restrict__ st, int* slot_base,
+                                          double* slot_shift, int* slot_win,
                                           int* excl_lds)
 {
     using St = Stencil<S>;
@@ -817,8 +809,8 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             const int slot = lane + kWave * u;
             first[u] = ncand + pre - cnt[u];
             if (slot < St::kTab) {
-                slot_first[slot] = first[u];
-                slot_start[slot] = s0[u];
+                // member index of candidate q of this slot: slot_base + q
+                slot_base[slot] = s0[u] - first[u];
             }
             if (known_shift && slot < St::kSlots) {
                 const int ox = St::off(slot, 0), oy = St::off(slot, 1), oz = St::off(slot, 2);
@@ -873,7 +865,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             for (int k = 0; k < K; ++k) {
                 const int q = cb + lane + kWave * k;
                 const int slot = max(cslot[k], 0);
-                const int src = slot_start[slot] + (q - slot_first[slot]);
+                const int src = slot_base[slot] + q;
                 px[k] = py[k] = pz[k] = 0.0;
                 sx[k] = sy[k] = sz[k] = 0.0;
                 pu[k] = -1;
@@ -980,8 +972,7 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
                                                     int4* __restrict__ s_rec,
                                                     Status* __restrict__ st)
 {
-    __shared__ int slot_first[4][Stencil<(SA > SS ? SA : SS)>::kTab];
-    __shared__ int slot_start[4][Stencil<(SA > SS ? SA : SS)>::kTab];
+    __shared__ int slot_base[4][Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ double slot_shift[4][3 * Stencil<(SA > SS ? SA : SS)>::kTab];
     __shared__ __align__(16) int slot_win[4][kWave * K];
     extern __shared__ int excl_lds[];
@@ -994,11 +985,11 @@ __global__ __launch_bounds__(256) void k_lists_wave(const GridDev* __restrict__ 
         const int lw = site ? gw - waves_a : gw;
         if (site)
             list_wave<K, SS>(grids[1], wv, lw, true, max_excl, topo, user2arow, a_rec, s_rec, st,
-                             slot_first[wv], slot_start[wv], slot_shift[wv], slot_win[wv],
+                             slot_base[wv], slot_shift[wv], slot_win[wv],
                              excl_lds);
         else
             list_wave<K, SA>(grids[0], wv, lw, false, max_excl, topo, user2arow, a_rec, s_rec,
-                             st, slot_first[wv], slot_start[wv], slot_shift[wv], slot_win[wv],
+                             st, slot_base[wv], slot_shift[wv], slot_win[wv],
                              excl_lds);
     }
     clear_bucket_counts(grids);   // last: the stores leave the start of the kernel alone
