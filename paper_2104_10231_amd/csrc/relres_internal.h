@@ -89,7 +89,8 @@ struct GridDev {
     int bucket_cap;           // > 0: members go straight into per-cell buckets, k_place
                               // places them and the list kernel clears the counts
     int* user;                // member caller indices, cell-grouped, ascending in a cell
-    double4* pos;             // wrapped positions of members (w unused)
+    double4* pos;             // wrapped positions of members; w: entry and molecule bits
+                              // (member_tag in the kernels)
     int2* meta;               // (type, molecule) of members
     int* row_cell;            // cell rank of each member row
     int* list;                // rows x cap entries

@@ -37,18 +37,25 @@ constexpr int kChunk = 256;    // candidates staged in LDS per pass
 template <typename T>
 __device__ __forceinline__ RELRES_GLOBAL T* gbl(T* p) { return (RELRES_GLOBAL T*)p; }
 // HIP vector types cannot be copied through such pointers; read them as scalars.
-__device__ __forceinline__ void load_xyz(const double4* base, int i, double& x, double& y, double& z)
+// A cell-sorted member carries its list entry and molecule in the fourth
+// component of its position: the low 32 bits are the entry (caller index |
+// type << kIdxBits), the high 32 bits the molecule.  One 32-byte read gives
+// everything the list kernel needs of a member.
+__device__ __forceinline__ double member_tag(int u, int type, int mol)
+{
+    const uint32_t entry = (uint32_t)u | ((uint32_t)type << kIdxBits);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)mol << 32) | entry));
+}
+__device__ __forceinline__ void load_member(const double4* base, int i, double& x, double& y,
+                                            double& z, uint32_t& entry, int& mol)
 {
     RELRES_GLOBAL const double* p = (RELRES_GLOBAL const double*)base + 4 * (size_t)i;
     x = p[0];
     y = p[1];
     z = p[2];
-}
-__device__ __forceinline__ void load_meta(const int2* base, int i, int& type, int& mol)
-{
-    RELRES_GLOBAL const int* p = (RELRES_GLOBAL const int*)base + 2 * (size_t)i;
-    type = p[0];
-    mol = p[1];
+    const uint64_t w = (uint64_t)__double_as_longlong(p[3]);
+    entry = (uint32_t)w;
+    mol = (int)(uint32_t)(w >> 32);
 }
 constexpr int kHomeMax = 256;  // home atoms whose counters live in LDS at once
 
@@ -375,9 +382,11 @@ __device__ __forceinline__ void place_member(const GridDev& g, bool site, int c,
                                              const double4* __restrict__ wpos, const TopoDev& topo,
                                              int* __restrict__ user2arow)
 {
+    const int ty = topo.types[u], mol = topo.mol[u];
+    const double4 p = wpos[u];
     gbl(g.user)[dst] = u;
-    g.pos[dst] = wpos[u];       // vector-type stores stay generic (no LDS use here)
-    g.meta[dst] = make_int2(topo.types[u], topo.mol[u]);
+    g.pos[dst] = make_double4(p.x, p.y, p.z, member_tag(u, ty, mol));   // generic store (no LDS use here)
+    g.meta[dst] = make_int2(ty, mol);
     gbl(g.row_cell)[dst] = c;
     if (!site) user2arow[u] = dst;
 }
@@ -670,9 +679,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
 {
     using St = Stencil<S>;
     const int lane = threadIdx.x & (kWave - 1);
-    const double4* gpos = g.pos;      // read through load_xyz / load_meta
-    const int2* gmeta = g.meta;
-    RELRES_GLOBAL const int* guser = gbl(g.user);
+    const double4* gpos = g.pos;      // read through load_member
     RELRES_GLOBAL const int* gstart = gbl(g.start);
     RELRES_GLOBAL const int* gnbr = gbl(g.nbr);
     RELRES_GLOBAL const int* grank = gbl(g.rank_of_lin);
@@ -713,9 +720,10 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     int mt = 0, mmol = 0;
     int mu = -1, meb = 0, mee = 0, marow = 0, mcell = -1, mcnt = 0;
     if (lane < nh) {
-        load_xyz(gpos, myrow, mx, my, mz);
-        load_meta(gmeta, myrow, mt, mmol);
-        mu = guser[myrow];
+        uint32_t ment;
+        load_member(gpos, myrow, mx, my, mz, ment, mmol);
+        mu = (int)(ment & kIdxMask);
+        mt = (int)(ment >> kIdxBits);
         mcell = gbl(g.row_cell)[myrow];
         if (excl_off) {
             meb = excl_off[mu];
@@ -860,7 +868,8 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             // periodic image shift of the candidate's slot, taken once per
             // candidate for all the rows
             double sx[K], sy[K], sz[K];
-            int pu[K], pt[K], pm[K];
+            int pu[K], pm[K];
+            uint32_t pe[K];     // the candidate's list entry
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int q = cb + lane + kWave * k;
@@ -869,11 +878,11 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 px[k] = py[k] = pz[k] = 0.0;
                 sx[k] = sy[k] = sz[k] = 0.0;
                 pu[k] = -1;
-                pt[k] = pm[k] = 0;
+                pm[k] = 0;
+                pe[k] = 0;
                 if (q < ncand) {
-                    load_xyz(gpos, src, px[k], py[k], pz[k]);
-                    load_meta(gmeta, src, pt[k], pm[k]);
-                    pu[k] = guser[src];
+                    load_member(gpos, src, px[k], py[k], pz[k], pe[k], pm[k]);
+                    pu[k] = (int)(pe[k] & kIdxMask);
                     if (known_shift) {
                         sx[k] = slot_shift[slot];
                         sy[k] = slot_shift[St::kTab + slot];
@@ -886,12 +895,8 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             // ANDs: a lane's own work per row is its compares and its
             // distance test.  `live` marks the slots holding a candidate.
             uint64_t live[K];
-            int word[K];      // the list entry of each candidate
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                live[k] = __ballot(pu[k] >= 0);
-                word[k] = (int)((uint32_t)pu[k] | ((uint32_t)pt[k] << kIdxBits));
-            }
+            for (int k = 0; k < K; ++k) live[k] = __ballot(pu[k] >= 0);
             // every cell has at least one home row (h1 > h0): a loop that
             // always runs, so no path skips it with candidate reads pending
             int h = __builtin_amdgcn_readfirstlane(h0);
@@ -935,7 +940,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                         // 32-bit slot index: the store takes the row's scalar
                         // base and one lane offset
                         const uint32_t p = (uint32_t)(hc + lanes_below(mask));
-                        if (p < (uint32_t)cap) out[p] = word[k];
+                        if (p < (uint32_t)cap) out[p] = (int)pe[k];
                     }
                     hc += __popcll(mask);
                 }
