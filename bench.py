@@ -7,9 +7,9 @@ call (forces, energy and virial) on the resident positions; the neighbour
 lists are rebuilt every 10 steps inside the timed region.  The same protocol
 is then run for the conventional all-FG system (r_s -> r_c, list at 16 A),
 and the oracle is timed on the host for the CPU baseline.  Builds are enqueued
-without waiting and their overflow status is checked after the force calls
-behind them were enqueued; an overflowed build is redone inside the timed
-region together with its force calls.
+without waiting; the lists of a timed run are checked after its closing
+synchronisation, and a run whose builds overflowed is discarded and run again
+with the grown lists.
 
 Prints ONE JSON line (rank 0).  value = RelRes atom-steps/s on this GPU.
 """
@@ -82,7 +82,10 @@ class Stepper:
     (a captured build's status accumulates over replays on the device, so one
     check covers every cycle; a run whose builds overflowed is redone with the
     grown lists).  Without graphs every cycle is launched eagerly and checked
-    after the force calls behind its build were enqueued."""
+    after the force calls behind its build were enqueued.  `timed_run` is one
+    timed run: with graphs its lists are checked after the closing
+    synchronisation, outside the timed bracket, and an overflowed run is
+    discarded and repeated."""
 
     def __init__(self, rr, pos, box, rebuild_every, use_graph):
         import torch
@@ -156,6 +159,24 @@ class Stepper:
         torch.cuda.synchronize()
 
 
+    def timed_run(self, steps):
+        """Seconds of one run of `steps` steps, bracketed by device
+        synchronisation, whose lists are complete."""
+        import torch
+        while True:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if self.use_graph:
+                self.enqueue(steps)
+                torch.cuda.synchronize()
+            else:
+                self.run(steps)
+            dt = time.perf_counter() - t0
+            if not self.use_graph or self.rr.check_lists():
+                return dt
+            self.redone += 1              # rows grew: new buffers, new graphs
+
+
 def run_protocol(rr, pos, box, steps, warmup, rebuild_every, repeats, use_graph=True):
     """`warmup` untimed steps, then `repeats` timed runs of exactly `steps`
     steps each (bracketed by device synchronisation); returns the seconds of
@@ -169,12 +190,7 @@ def run_protocol(rr, pos, box, steps, warmup, rebuild_every, repeats, use_graph=
             st._cycle_graph(n)
     if warmup > 0:
         st.run(warmup)
-    times = []
-    for _ in range(repeats):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st.run(steps)
-        times.append(time.perf_counter() - t0)
+    times = [st.timed_run(steps) for _ in range(repeats)]
     return times, st
 
 
@@ -824,7 +840,8 @@ def main():
             "pair_math": pm_ew, "energy_virial": "fp64 accumulation, every step",
             "parallelism": "single GPU",
             "launch": ("one hip graph per cycle (rebuild + force calls), lists checked once "
-                       "per timed run") if use_graph else "eager",
+                       "per timed run after its closing synchronisation (an overflowed run "
+                       "is discarded and repeated)") if use_graph else "eager",
             "timing": f"median of {args.repeats} timed runs of {args.steps} steps after "
                       f"{args.warmup} warm-up steps; kernel timing (graph replays) before them",
         },
