@@ -441,6 +441,34 @@ def test_energy_virial_wait_failure_is_reported(monkeypatch):
     ok.close()
 
 
+@pytest.mark.parametrize("cand", [2, 4])
+@pytest.mark.parametrize("cells", [(1, 1), (2, 2)])
+def test_candidate_rounds_carry_the_slot_across_rounds(cand, cells):
+    """Stencils of several hundred candidates (crowded cells): each round of
+    64 x cand candidates finds every candidate's slot from the slots that
+    start inside the round and the slot carried over from the previous round.
+    Pair sets equal the oracle's for both candidate counts and both cell
+    sizes, and the lists give identical forces."""
+    import torch
+    s = w.random_molecules(17, 80, 15.0, kind="propane", min_dist=2.0)
+    big = s.replace(pos=s.pos + 20.0, box=np.full(3, 60.0), skin=8.0)
+    print(f"[parity] crowded rounds cand={cand} cells={cells}", flush=True)
+    rr = make_relres(big, 64)
+    rr.set_cells(*cells)
+    rr.set_list_launch(8, 8, cand)
+    p = torch.from_numpy(big.pos).cuda()
+    rr.build_lists(p, big.box)
+    assert rr.stats()["atom_max_row"] > 64
+    for which in (0, 1):
+        assert pair_set(rr.pairs(which)) == pair_set(oracle.pairs(big, which))
+    F, E, W = rr.forces(p)
+    torch.cuda.synchronize()
+    Fr, Er, Wr = oracle.compute(big)
+    assert rel_rms(F.double().cpu().numpy(), Fr) <= 1e-11
+    assert abs(E.cpu().numpy()[0] - Er[0]) <= 1e-12 * abs(Er[0])
+    rr.close()
+
+
 def test_crowded_cells_need_several_passes():
     """Cells holding more than 64 atoms while the mean occupancy is low: the
     one-wave-per-cell builder loops over home atoms in passes of 64."""
