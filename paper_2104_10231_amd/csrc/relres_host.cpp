@@ -265,7 +265,8 @@ struct GridHost {
     int n[3] = {0, 0, 0};             // cells per axis of system 0 (statistics)
     std::vector<int> sys_n;           // [nsys][3] cells per axis
     std::vector<GeomDev> geom;        // per system, as last uploaded
-    DBuf geom_dev, cell_sys, rank_of_lin, lin_of_rank, nbr, count, start, user_unsorted, user, pos,
+    std::vector<int> wave_sys;        // system of every list-kernel wave, as last uploaded
+    DBuf geom_dev, wave_sys_dev, cell_sys, rank_of_lin, lin_of_rank, nbr, count, start, user_unsorted, user, pos,
         meta, row_cell, list, nrow;
     GridDev dev{};
 };
@@ -700,6 +701,25 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
         HIP_TRY(hipMemcpy(g.geom_dev.p, geom.data(), sizeof(GeomDev) * nsys, hipMemcpyHostToDevice));
         g.geom = geom;
     }
+    // the system of every list-kernel wave (with several systems), so a wave
+    // finds its grid with one read instead of a search over the systems
+    std::vector<int> wave_sys;
+    if (nsys > 1) {
+        wave_sys.resize(waves);
+        for (int sy = 0; sy < nsys; ++sy)
+            for (int v = geom[sy].wave_base; v < geom[sy].wave_base +
+                                                 (members_sys[sy] + g.rpw - 1) / g.rpw; ++v)
+                wave_sys[v] = sy;
+    }
+    if (wave_sys != g.wave_sys) {
+        if (!wave_sys.empty()) {
+            TRY(ensure(g.wave_sys_dev, sizeof(int) * wave_sys.size(), gen));
+            HIP_TRY(hipDeviceSynchronize());   // the old table may still be in use
+            HIP_TRY(hipMemcpy(g.wave_sys_dev.p, wave_sys.data(), sizeof(int) * wave_sys.size(),
+                              hipMemcpyHostToDevice));
+        }
+        g.wave_sys = wave_sys;
+    }
     TRY(ensure(g.user_unsorted, sizeof(int) * rows, gen));
     TRY(ensure(g.user, sizeof(int) * rows, gen));
     TRY(ensure(g.pos, sizeof(double4) * rows, gen));
@@ -721,6 +741,7 @@ int setup_grid(GridHost& g, const std::vector<double>& rl_sys, const std::vector
     d.waves = waves;
     d.rows_per_wave = g.rpw;
     d.geom = g.geom_dev.as<GeomDev>();
+    d.wave_sys = nsys > 1 ? g.wave_sys_dev.as<int>() : nullptr;
     d.cell_sys = g.cell_sys.as<int>();
     d.rank_of_lin = g.rank_of_lin.as<int>();
     d.lin_of_rank = g.lin_of_rank.as<int>();
@@ -2454,7 +2475,7 @@ void relres_destroy(relres_ctx* c)
                     &c->d_epoch})
         release(*b);
     for (GridHost* g : {&c->ga, &c->gs})
-        for (DBuf* b : {&g->geom_dev, &g->cell_sys, &g->rank_of_lin, &g->lin_of_rank, &g->nbr,
+        for (DBuf* b : {&g->geom_dev, &g->wave_sys_dev, &g->cell_sys, &g->rank_of_lin, &g->lin_of_rank, &g->nbr,
                         &g->count, &g->start, &g->user_unsorted, &g->user, &g->pos, &g->meta,
                         &g->row_cell, &g->list, &g->nrow})
             release(*b);

@@ -75,6 +75,7 @@ struct GridDev {
     int waves;                // waves of the list kernel for this kind
     int rows_per_wave;        // consecutive home rows per wave (<= kRowsPerWave)
     const GeomDev* geom;      // [nsys]
+    const int* wave_sys;      // [waves] system of each list-kernel wave (nsys > 1; else null)
     const int* cell_sys;      // [ncell] system of each cell
     const int* rank_of_lin;   // [cell_base + local linear index] -> global cell rank
     const int* lin_of_rank;   // [global cell rank] -> local linear index

@@ -685,13 +685,9 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     RELRES_GLOBAL const int* grank = gbl(g.rank_of_lin);
     RELRES_GLOBAL int* glist = gbl(g.list);
     RELRES_GLOBAL const int* glor = gbl(g.lin_of_rank);
-    // the system whose grid holds this wave's rows: last grid starting at or
-    // before the wave (wave-uniform; grids with no rows have no waves)
-    int gs_lo = 0, gs_hi = g.nsys - 1;
-    while (gs_lo < gs_hi) {
-        const int mid = (gs_lo + gs_hi + 1) >> 1;
-        if (g.geom[mid].wave_base <= lw) gs_lo = mid; else gs_hi = mid - 1;
-    }
+    // the system whose grid holds this wave's rows (wave-uniform; grids with
+    // no rows have no waves)
+    const int gs_lo = g.nsys > 1 ? __builtin_amdgcn_readfirstlane(g.wave_sys[lw]) : 0;
     const GeomDev& G = g.geom[gs_lo];
     const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
     const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
