@@ -1202,13 +1202,24 @@ struct RowTab {
     const Cutoffs<double>* cut64;
 };
 
+// A table of `count` T staged in LDS in two parts: stage_first reads word
+// threadIdx.x (issued early, before the row record), stage_table writes it and
+// copies any words beyond the first blockDim.x.
 template <typename T>
-__device__ __forceinline__ void stage_table(T* dst, const T* __restrict__ src, int count)
+__device__ __forceinline__ uint32_t stage_first(const T* __restrict__ src, int count)
+{
+    const int words = count * (int)(sizeof(T) / sizeof(uint32_t));
+    return (int)threadIdx.x < words ? reinterpret_cast<const uint32_t*>(src)[threadIdx.x] : 0u;
+}
+template <typename T>
+__device__ __forceinline__ void stage_table(T* dst, const T* __restrict__ src, int count,
+                                            uint32_t first)
 {
     const int words = count * (int)(sizeof(T) / sizeof(uint32_t));
     const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-    for (int k = threadIdx.x; k < words; k += blockDim.x) d[k] = s[k];
+    if ((int)threadIdx.x < words) d[threadIdx.x] = first;
+    for (int k = threadIdx.x + blockDim.x; k < words; k += blockDim.x) d[k] = s[k];
 }
 
 // Entries handled per lane per batch (see row_terms).
@@ -1559,6 +1570,23 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const int row = logical * (kForceBlock >> lg) + ((int)threadIdx.x >> lg);
     const int sub = (int)threadIdx.x & (G - 1);
 
+    // the first words of the LDS tables are read before the row record, so
+    // the two reads overlap (written to LDS once the record is in)
+    const PairCoef<S>* coef_g = (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32);
+    const Cutoffs<S>* pcut_g = (const Cutoffs<S>*)(sizeof(S) == 8 ? (const void*)a.pcut64
+                                                                   : (const void*)a.pcut32);
+    const int np = a.ntypes * a.ntypes;
+    uint32_t stg[4] = {0u, 0u, 0u, 0u};
+    if constexpr (LDS) {
+        stg[0] = stage_first(coef_g, np);
+        if constexpr (EW && sizeof(S) != sizeof(double))
+            stg[1] = stage_first((const PairCoef<double>*)a.coef64, np);
+        if constexpr (PC) {
+            stg[2] = stage_first(pcut_g, np);
+            if constexpr (sizeof(S) != sizeof(double)) stg[3] = stage_first(a.pcut64, np);
+        }
+    }
+
     unsigned tag = 0;
     if constexpr (EW) {
         // tag 0 is never used: it marks a cleared record.  The epoch is an
@@ -1611,18 +1639,15 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const PairCoef<double>* coef64;
     const Cutoffs<S>* pcut = nullptr;
     const Cutoffs<double>* pcut64 = nullptr;
-    const Cutoffs<S>* pcut_g = (const Cutoffs<S>*)(sizeof(S) == 8 ? (const void*)a.pcut64
-                                                                   : (const void*)a.pcut32);
     if constexpr (LDS) {
         __shared__ CoefLds<S, EW> tab;
         __shared__ CutLds<S, PC> ctab;
-        const int np = a.ntypes * a.ntypes;
-        stage_table(tab.c, (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32), np);
+        stage_table(tab.c, coef_g, np, stg[0]);
         if constexpr (EW && sizeof(S) != sizeof(double))
-            stage_table(tab.c64, (const PairCoef<double>*)a.coef64, np);
+            stage_table(tab.c64, (const PairCoef<double>*)a.coef64, np, stg[1]);
         if constexpr (PC) {
-            stage_table(ctab.c, pcut_g, np);
-            if constexpr (sizeof(S) != sizeof(double)) stage_table(ctab.c64, a.pcut64, np);
+            stage_table(ctab.c, pcut_g, np, stg[2]);
+            if constexpr (sizeof(S) != sizeof(double)) stage_table(ctab.c64, a.pcut64, np, stg[3]);
         }
         __syncthreads();
         coef = tab.c;
@@ -1634,7 +1659,7 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
             else pcut64 = (const Cutoffs<double>*)ctab.c;
         }
     } else {
-        coef = (const PairCoef<S>*)(sizeof(S) == 8 ? a.coef64 : a.coef32);
+        coef = coef_g;
         coef64 = (const PairCoef<double>*)a.coef64;
         if constexpr (PC) {
             pcut = pcut_g;
@@ -1647,7 +1672,6 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const bool own = rb ? rec.x >= 0 : (rec.x >= 0 && rec.w == 0);   // hybrid atom rows belong to the site range
     if (own) {
         const int ui = rec.x, ti = rec.y & ((1 << kTypeBits) - 1);
-        const BoxV bx = row_box(a, rec.y >> kTypeBits);
         const int cnt_s = rb ? rec.z : 0;
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -1660,6 +1684,9 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         double fxp[kBatch], fyp[kBatch], fzp[kBatch], sxp[kBatch], syp[kBatch], szp[kBatch];
         gather_batch(a, e_fg, fxp, fyp, fzp);
         if (rb) gather_batch(a, e_own, sxp, syp, szp);
+        // the row's box (several systems: a read) after the gathers, so the
+        // wave does not wait for it before issuing them
+        const BoxV bx = row_box(a, rec.y >> kTypeBits);
         const int ro = ti * a.ntypes;
         const RowTab<S> rt{coef + ro, coef64 + ro, PC ? pcut + ro : nullptr,
                            PC ? pcut64 + ro : nullptr};
