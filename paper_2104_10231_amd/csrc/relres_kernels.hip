@@ -378,17 +378,22 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 // reads, a larger one by the whole wave after the small ones.  G = 16 suits
 // grids of a few members per cell, G = 64 (one cell per wave) crowded ones.
 
-__device__ __forceinline__ void place_member(const GridDev& g, bool site, int c, int dst, int u,
-                                             const double4* __restrict__ wpos, const TopoDev& topo,
-                                             int* __restrict__ user2arow)
+__device__ __forceinline__ void place_read(const GridDev& g, bool site, int c, int dst, int u,
+                                           double4 p, int ty, int mol,
+                                           int* __restrict__ user2arow)
 {
-    const int ty = topo.types[u], mol = topo.mol[u];
-    const double4 p = wpos[u];
     gbl(g.user)[dst] = u;
     g.pos[dst] = make_double4(p.x, p.y, p.z, member_tag(u, ty, mol));   // generic store (no LDS use here)
     g.meta[dst] = make_int2(ty, mol);
     gbl(g.row_cell)[dst] = c;
     if (!site) user2arow[u] = dst;
+}
+
+__device__ __forceinline__ void place_member(const GridDev& g, bool site, int c, int dst, int u,
+                                             const double4* __restrict__ wpos, const TopoDev& topo,
+                                             int* __restrict__ user2arow)
+{
+    place_read(g, site, c, dst, u, wpos[u], topo.types[u], topo.mol[u], user2arow);
 }
 
 template <int kSortGroup>
@@ -503,21 +508,36 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restri
     const int u_slot = (c < nc && gl < in_group) ? bucket[(size_t)c * cap + gl] : 0x7fffffff;
     // members of the grid's cells before this block's: c0 is a multiple of 4,
     // so the counts are read as int4, four loads per thread in flight at once
+    // (the first round outside the loop, so its reads go out with the ones
+    // above; grids of more than 4096 cells before the block loop further)
+    // (global 16-byte reads of clamped index, the ones past the end dropped,
+    // so no branch splits them)
     int s = 0;
-    {
-        const int4* __restrict__ c4 = reinterpret_cast<const int4*>(g.count);
-        const int n4 = c0 >> 2;
-        for (int base = 0; base < n4; base += 4 * kPlaceThreads) {
-            int4 v[4];
+    const int n4 = c0 >> 2;
+    if (n4 > 0) {
+        typedef int int4v __attribute__((ext_vector_type(4)));
+        RELRES_GLOBAL const int4v* c4 = (RELRES_GLOBAL const int4v*)gcount;
+        auto round = [&](int base) {
+            int4v q4[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = base + u * kPlaceThreads + (int)threadIdx.x;
-                v[u] = k < n4 ? c4[k] : make_int4(0, 0, 0, 0);
+                const int4v v = c4[min(k, n4 - 1)];
+                q4[u] = k < n4 ? v : (int4v)(0);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s += (v[u].x + v[u].y) + (v[u].z + v[u].w);
-        }
+            for (int u = 0; u < 4; ++u) s += (q4[u].x + q4[u].y) + (q4[u].z + q4[u].w);
+        };
+        round(0);
+        for (int base = 4 * kPlaceThreads; base < n4; base += 4 * kPlaceThreads) round(base);
     }
+    // the slot's member (position, type, molecule) is read once its index
+    // and the counts are in, while the counts are summed and scanned: a slot past its cell's count
+    // holds an index of an earlier build (garbage before the first), so only
+    // indices below n are read, and such a read is dropped
+    const int u_pre = (unsigned)u_slot < (unsigned)n ? u_slot : 0;
+    const double4 p_pre = wpos[u_pre];
+    const int ty_pre = topo.types[u_pre], mol_pre = topo.mol[u_pre];
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o);
     if (lane == 0) wtot[wave] = s;
@@ -554,7 +574,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const GridDev* __restri
         const int m = small ? len : 0;      // one cell per wave: len is uniform
         for (int k = 0; k < m; ++k) r += __shfl(u, k) < u;
     }
-    if (small && gl < len) place_member(g, site, c, b + r, u, wpos, topo, user2arow);
+    if (small && gl < len) place_read(g, site, c, b + r, u, p_pre, ty_pre, mol_pre, user2arow);
     // the larger cells of this wave, one at a time with the whole wave
     for (int k = 0; k < kCellsPerWave; ++k) {
         const int lenk = readlane_i(len, k * kSortGroup);
