@@ -30,16 +30,32 @@ namespace {
 
 constexpr int kMdBlock = 256;
 
-__device__ __forceinline__ void mi_diff(const double* __restrict__ pos, int a, int b,
+// d = x_a - x_b with the single-shift minimum image, from positions already
+// read.  The shift is taken by selects (both shifted values computed), so the
+// same roundings as subtracting or adding the box under a branch.
+__device__ __forceinline__ void mi_diff(const double xa[3], const double xb[3],
                                         const double box[3], double d[3])
 {
-    // d = x_a - x_b with the single-shift minimum image
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double v = pos[3 * a + k] - pos[3 * b + k];
+        const double v = xa[k] - xb[k];
         const double h = 0.5 * box[k];
-        if (v > h) v -= box[k];
-        else if (v < -h) v += box[k];
-        d[k] = v;
+        const double lo = v - box[k], hi = v + box[k];
+        d[k] = v > h ? lo : (v < -h ? hi : v);
+    }
+}
+
+// The positions of an item's atoms i, j, k, l (unused ones, and the padding
+// items' atoms, read as atom 0 and ignored), all read before any is used.
+__device__ __forceinline__ void item_positions(const double* __restrict__ pos, int n,
+                                               const BondItem& it, double x[4][3])
+{
+    const int at[4] = {it.i, it.j, it.k, it.l};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int a = (unsigned)at[q] < (unsigned)n ? at[q] : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[q][c] = pos[3 * (size_t)a + c];
     }
 }
 
@@ -93,14 +109,14 @@ __device__ __forceinline__ double block_sum(const double* v, double (*red)[kMdBl
 // energy and virial go to acc (energies 0..2, virial 4..9) from its first
 // slot only.
 __device__ __forceinline__ void entry_force(const BondedArgs& b, const BondItem& it,
-                                            double fa[3], double acc[10])
+                                            const double x[4][3], double fa[3], double acc[10])
 {
     const int kind = it.kind, slot = it.slot, t = it.par;
     double f[4][3];
     if (kind == 0) {
         const double2 par = b.bond_par[t];
         double d[3];
-        mi_diff(b.pos, it.i, it.j, b.box, d);
+        mi_diff(x[0], x[1], b.box, d);
         const double r = sqrt(dot3(d, d));
         const double dr = r - par.y;
         const double sc = -2.0 * par.x * dr / r;
@@ -115,8 +131,8 @@ __device__ __forceinline__ void entry_force(const BondedArgs& b, const BondItem&
     } else if (kind == 1) {
         const double2 par = b.angle_par[t];
         double u[3], v[3];
-        mi_diff(b.pos, it.i, it.j, b.box, u);
-        mi_diff(b.pos, it.k, it.j, b.box, v);
+        mi_diff(x[0], x[1], b.box, u);
+        mi_diff(x[2], x[1], b.box, v);
         // reciprocals once: a divide is a long instruction sequence in FP64
         const double ilu = 1.0 / sqrt(dot3(u, u)), ilv = 1.0 / sqrt(dot3(v, v));
         double c = dot3(u, v) * ilu * ilv;
@@ -137,9 +153,9 @@ __device__ __forceinline__ void entry_force(const BondedArgs& b, const BondItem&
     } else {
         const double4 par = b.dih_par[t];      // K, n, cos d, sin d
         double b1[3], b2[3], b3[3], m[3], nn[3];
-        mi_diff(b.pos, it.j, it.i, b.box, b1);
-        mi_diff(b.pos, it.k, it.j, b.box, b2);
-        mi_diff(b.pos, it.l, it.k, b.box, b3);
+        mi_diff(x[1], x[0], b.box, b1);
+        mi_diff(x[2], x[1], b.box, b2);
+        mi_diff(x[3], x[2], b.box, b3);
         cross3(b1, b2, m);
         cross3(b2, b3, nn);
         const double lb2 = sqrt(dot3(b2, b2));
@@ -184,10 +200,10 @@ __device__ __forceinline__ void entry_force(const BondedArgs& b, const BondItem&
 // distances), seen from atom a: its force on a added to fa, half its energy
 // to acc[3] and half its virial to acc[4..9] (the pair is met from both atoms).
 __device__ __forceinline__ void pair14_force(const BondedArgs& b, const BondItem& it,
-                                             double fa[3], double acc[10])
+                                             const double x[4][3], double fa[3], double acc[10])
 {
     double d[3];
-    mi_diff(b.pos, it.i, it.j, b.box, d);      // x_a - x_j
+    mi_diff(x[0], x[1], b.box, d);             // x_a - x_j
     const double r2 = dot3(d, d);
     const int pi = it.par;
     const Cutoffs<double>& cut = b.pcut64[pi];
@@ -250,8 +266,10 @@ __global__ __launch_bounds__(kMdBlock) void k_bonded(BondedArgs b, MdArgs m, int
         const BondItem* items = b.items + (size_t)a * b.slots;
         for (int k = sub; k < b.slots; k += G) {
             const BondItem it = items[k];
-            if (it.kind == 3) pair14_force(b, it, fa, acc);
-            else if (it.kind >= 0) entry_force(b, it, fa, acc);
+            double x[4][3];
+            item_positions(b.pos, b.n, it, x);
+            if (it.kind == 3) pair14_force(b, it, x, fa, acc);
+            else if (it.kind >= 0) entry_force(b, it, x, fa, acc);
         }
     }
     // every lane takes part in the group sums (idle lanes add zeros)
