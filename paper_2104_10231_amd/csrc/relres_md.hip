@@ -311,7 +311,7 @@ constexpr int kSumLoads = 8;
 __device__ __forceinline__ void add_blocks(const double* __restrict__ p, int n, int K, int k,
                                            int lane, double& s)
 {
-    for (int base = lane; base < n; base += 64 * kSumLoads) {
+    auto round = [&](int base) {
         double x[kSumLoads];
 #pragma unroll
         for (int u = 0; u < kSumLoads; ++u) {
@@ -321,7 +321,11 @@ __device__ __forceinline__ void add_blocks(const double* __restrict__ p, int n, 
 #pragma unroll
         for (int u = 0; u < kSumLoads; ++u)
             if (base + 64 * u < n) s += x[u];
-    }
+    };
+    // the first round outside the loop: its reads are not held back until
+    // the caller's earlier reads are in
+    if (lane < n) round(lane);
+    for (int base = lane + 64 * kSumLoads; base < n; base += 64 * kSumLoads) round(base);
 }
 
 __device__ __forceinline__ double sum_blocks(const double* __restrict__ p1, int n1,
@@ -412,6 +416,24 @@ __global__ __launch_bounds__(kMdBlock) void k_md_drift(MdArgs m, const MdState* 
                                                        double* __restrict__ row)
 {
     __shared__ double s_sh;
+    // the atom's data first: none of it depends on the scalar work, so its
+    // reads overlap the sum of the partials
+    const int i = blockIdx.x * kMdBlock + threadIdx.x;
+    const bool in = i < m.n;
+    const TF* F = (const TF*)m.forces;
+    double v0[3] = {0.0, 0.0, 0.0}, x0[3] = {0.0, 0.0, 0.0}, xr[3] = {0.0, 0.0, 0.0};
+    TF f0[3] = {TF(0), TF(0), TF(0)};
+    double mass = 1.0;
+    if (in) {
+        for (int c = 0; c < 3; ++c) {
+            v0[c] = m.vel[3 * i + c];
+            x0[c] = m.pos[3 * i + c];
+            xr[c] = m.xref[3 * i + c];
+            f0[c] = F[3 * i + c];
+        }
+        mass = m.mass[i];
+    }
+    const double dt = st_in->dt;
     double s;
     if (scalar) {
         if (threadIdx.x < 64) {
@@ -429,18 +451,15 @@ __global__ __launch_bounds__(kMdBlock) void k_md_drift(MdArgs m, const MdState* 
     } else {
         s = st_in->s_apply;
     }
-    const int i = blockIdx.x * kMdBlock + threadIdx.x;
-    if (i >= m.n) return;
-    const double dt = st_in->dt;
-    const double am = m.ftm2v / m.mass[i];
-    const TF* F = (const TF*)m.forces;
+    if (!in) return;
+    const double am = m.ftm2v / mass;
     double dmax2 = 0.0;
     for (int c = 0; c < 3; ++c) {
-        const double v = m.vel[3 * i + c] * s + 0.5 * dt * am * (double)F[3 * i + c];
+        const double v = v0[c] * s + 0.5 * dt * am * (double)f0[c];
         m.vel[3 * i + c] = v;
-        const double x = m.pos[3 * i + c] + dt * v;
+        const double x = x0[c] + dt * v;
         m.pos[3 * i + c] = x;
-        const double dx = x - m.xref[3 * i + c];
+        const double dx = x - xr[c];
         dmax2 += dx * dx;
     }
     // an atom that moved more than half the skin since the last build
