@@ -363,6 +363,15 @@ __global__ void k_scatter(int n, const GridDev* __restrict__ grids, const int2* 
 }
 
 __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double readfirst_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int l)
 {
     const long long b = __double_as_longlong(v);
@@ -709,7 +718,13 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     // no rows have no waves)
     const int gs_lo = g.nsys > 1 ? __builtin_amdgcn_readfirstlane(g.wave_sys[lw]) : 0;
     const GeomDev& G = g.geom[gs_lo];
-    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+    // the grid's cell counts are wave-uniform: readfirstlane keeps them (and
+    // the cell arithmetic on them) in scalar registers, where the compiler
+    // would otherwise hold the values it read in vector registers (the box
+    // edges stay there: the selects of the image shifts take them so)
+    const int n0 = __builtin_amdgcn_readfirstlane(G.n[0]);
+    const int n1 = __builtin_amdgcn_readfirstlane(G.n[1]);
+    const int n2 = __builtin_amdgcn_readfirstlane(G.n[2]);
     const double Lx = G.box[0], Ly = G.box[1], Lz = G.box[2];
     // known image shifts: every stencil slot a distinct cell with one
     // periodic image (at least four cells per axis for the 27-cell stencil,
@@ -718,10 +733,10 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     const bool known_shift = __builtin_amdgcn_readfirstlane(
         S == 3 ? (n0 >= 4 && n1 >= 4 && n2 >= 4) : (n0 >= 5 && n1 >= 5 && n2 >= 5));
     const int R = g.rows_per_wave;
-    const int r0 = G.row_base + (lw - G.wave_base) * R;
-    const int r1 = min(G.row_base + G.members, r0 + R);
+    const int r0 = __builtin_amdgcn_readfirstlane(G.row_base + (lw - G.wave_base) * R);
+    const int r1 = __builtin_amdgcn_readfirstlane(min(G.row_base + G.members, r0 + R));
     const double hx = G.half[0], hy = G.half[1], hz = G.half[2];
-    const double rl2 = G.rl2;
+    const double rl2 = readfirst_d(G.rl2);
     const int cap = g.cap;
     const int* __restrict__ excl_off = topo.excl_off;
     const int* __restrict__ excl_idx = topo.excl_idx;
