@@ -647,6 +647,13 @@ __device__ __forceinline__ bool member_shifted(double xi, double yi, double zi, 
 
 constexpr int kResidentListWaves = 256 * 4 * 3;
 
+// A compile-time bool as a value (selects one of two instantiations of a
+// generic lambda).
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
 // Stencil geometry: S cells per axis around the home cell (3 for cells of at
 // least the list radius, 5 for cells of at least half of it), S^3 slots in
 // x-major order, slot tables of kSlotTab entries per wave.
@@ -928,8 +935,13 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             uint64_t live[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) live[k] = __ballot(pu[k] >= 0);
-            // every cell has at least one home row (h1 > h0): a loop that
-            // always runs, so no path skips it with candidate reads pending
+            // The rows' loop, instantiated once for known image shifts and
+            // once for the minimum image by comparison, so the choice is one
+            // scalar branch per round and not a select per test.  Every cell
+            // has at least one home row (h1 > h0): a loop that always runs,
+            // so no path skips it with candidate reads pending.
+            auto row_loop = [&](auto known) {
+            constexpr bool kKnown = decltype(known)::value;
             int h = __builtin_amdgcn_readfirstlane(h0);
             do {
                 if (cb == 0 && h == h0) range_of();
@@ -961,11 +973,14 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                     if (cb + kWave * k >= ncand) break;
                     // the distance test for every lane (no divergent branch
                     // around it), then the other conditions
-                    const bool in = known_shift
-                        ? member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx[k], sy[k], sz[k], rl2)
-                        : member(make_double4(xi, yi, zi, 0.0),
-                                 make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx, hy, hz,
-                                 rl2);
+                    bool in;
+                    if constexpr (kKnown)
+                        in = member_shifted(xi, yi, zi, px[k], py[k], pz[k], sx[k], sy[k], sz[k],
+                                            rl2);
+                    else
+                        in = member(make_double4(xi, yi, zi, 0.0),
+                                    make_double4(px[k], py[k], pz[k], 0.0), Lx, Ly, Lz, hx, hy,
+                                    hz, rl2);
                     const uint64_t mask = keep[k] & __ballot(in);
                     if (__builtin_amdgcn_inverse_ballot_w64(mask)) {
                         // 32-bit slot index: the store takes the row's scalar
@@ -977,6 +992,9 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 }
                 if (lane == h) mcnt = hc;
             } while (++h < h1);
+            };
+            if (known_shift) row_loop(BoolC<true>());
+            else row_loop(BoolC<false>());
         }
         if (ncand == 0) range_of();
         // the slot table is rewritten for the next cell
