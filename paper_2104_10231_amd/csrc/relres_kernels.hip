@@ -777,7 +777,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     // 125-cell stencil) of a home cell: the slot's cell (rank, or -1), then
     // the first member and the end of its member range.  The next home cell's
     // reads are issued while this cell is processed (the ranks before this
-    // cell's candidate reads, the ranges at its first home row), so the
+    // cell's first candidate reads, the ranges at its first round), so the
     // dependent reads leave the per-cell critical path.  The range reads are
     // unconditional (lanes past the stencil and empty slots read a valid entry
     // and drop it at use), so no branch makes the compiler wait for them early.
@@ -903,29 +903,36 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             double px[K], py[K], pz[K];
-            // periodic image shift of the candidate's slot, taken once per
-            // candidate for all the rows
-            double sx[K], sy[K], sz[K];
-            int pu[K], pm[K];
             uint32_t pe[K];     // the candidate's list entry
+            int pm[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int q = cb + lane + kWave * k;
-                const int slot = max(cslot[k], 0);
-                const int src = slot_base[slot] + q;
                 px[k] = py[k] = pz[k] = 0.0;
-                sx[k] = sy[k] = sz[k] = 0.0;
-                pu[k] = -1;
-                pm[k] = 0;
                 pe[k] = 0;
-                if (q < ncand) {
-                    load_member(gpos, src, px[k], py[k], pz[k], pe[k], pm[k]);
-                    pu[k] = (int)(pe[k] & kIdxMask);
-                    if (known_shift) {
-                        sx[k] = slot_shift[slot];
-                        sy[k] = slot_shift[St::kTab + slot];
-                        sz[k] = slot_shift[2 * St::kTab + slot];
-                    }
+                pm[k] = 0;
+                if (q < ncand)
+                    load_member(gpos, slot_base[max(cslot[k], 0)] + q, px[k], py[k], pz[k],
+                                pe[k], pm[k]);
+            }
+            // the next cell's member ranges (its stencil ranks were read at
+            // this cell's start), issued after this cell's first candidate
+            // reads and once per cell, outside the rows' loop
+            if (cb == 0) range_of();
+            // periodic image shift of the candidate's slot, taken once per
+            // candidate for all the rows
+            double sx[K], sy[K], sz[K];
+            int pu[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool ok = cb + lane + kWave * k < ncand;
+                const int slot = max(cslot[k], 0);
+                pu[k] = ok ? (int)(pe[k] & kIdxMask) : -1;
+                sx[k] = sy[k] = sz[k] = 0.0;
+                if (known_shift && ok) {
+                    sx[k] = slot_shift[slot];
+                    sy[k] = slot_shift[St::kTab + slot];
+                    sz[k] = slot_shift[2 * St::kTab + slot];
                 }
             }
             // The conditions of a (row, candidate) pair other than the
@@ -944,7 +951,6 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             constexpr bool kKnown = decltype(known)::value;
             int h = __builtin_amdgcn_readfirstlane(h0);
             do {
-                if (cb == 0 && h == h0) range_of();
                 const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
                 const int ui = readlane_i(mu, h);
                 const int moli = readlane_i(mmol, h);
