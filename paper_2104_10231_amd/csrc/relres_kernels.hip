@@ -756,7 +756,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
     const int myrow = r0 + lane;
     double mx = 0.0, my = 0.0, mz = 0.0;
     int mt = 0, mmol = 0;
-    int mu = -1, meb = 0, mee = 0, marow = 0, mcell = -1, mcnt = 0;
+    int mu = -1, mne = 0, marow = 0, mcell = -1, mcnt = 0;   // mne: exclusions of the row
     if (lane < nh) {
         uint32_t ment;
         load_member(gpos, myrow, mx, my, mz, ment, mmol);
@@ -764,9 +764,9 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
         mt = (int)(ment >> kIdxBits);
         mcell = gbl(g.row_cell)[myrow];
         if (excl_off) {
-            meb = excl_off[mu];
-            mee = excl_off[mu + 1];
-            for (int k = 0; k < mee - meb; ++k) my_excl[lane * max_excl + k] = excl_idx[meb + k];
+            const int meb = excl_off[mu];
+            mne = excl_off[mu + 1] - meb;
+            for (int k = 0; k < mne; ++k) my_excl[lane * max_excl + k] = excl_idx[meb + k];
         }
         if (site) marow = user2arow[mu];
     }
@@ -942,19 +942,21 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
             uint64_t live[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) live[k] = __ballot(pu[k] >= 0);
-            // The rows' loop, instantiated once for known image shifts and
-            // once for the minimum image by comparison, so the choice is one
-            // scalar branch per round and not a select per test.  Every cell
+            // The rows' loop, instantiated for known image shifts and for
+            // the minimum image by comparison, each with and without the
+            // same-molecule exclusion, so each choice is one scalar branch
+            // per round and not a select or a branch per test.  Every cell
             // has at least one home row (h1 > h0): a loop that always runs,
             // so no path skips it with candidate reads pending.
-            auto row_loop = [&](auto known) {
+            auto row_loop = [&](auto known, auto own_mol) {
             constexpr bool kKnown = decltype(known)::value;
+            constexpr bool kSameMol = decltype(own_mol)::value;
             int h = __builtin_amdgcn_readfirstlane(h0);
             do {
                 const double xi = readlane_d(mx, h), yi = readlane_d(my, h), zi = readlane_d(mz, h);
                 const int ui = readlane_i(mu, h);
                 const int moli = readlane_i(mmol, h);
-                const int ne = readlane_i(mee, h) - readlane_i(meb, h);
+                const int ne = readlane_i(mne, h);
                 const int* hex = my_excl + h * max_excl;
                 int hc = readlane_i(mcnt, h);
                 RELRES_GLOBAL int* out =
@@ -963,7 +965,7 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     uint64_t m = live[k] & __ballot(pu[k] != ui);
-                    if (same_mol) m &= ~__ballot(pm[k] == moli);
+                    if constexpr (kSameMol) m &= ~__ballot(pm[k] == moli);
                     keep[k] = m;
                 }
                 // the row's exclusions: each read once for all K candidates,
@@ -999,8 +1001,13 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 if (lane == h) mcnt = hc;
             } while (++h < h1);
             };
-            if (known_shift) row_loop(BoolC<true>());
-            else row_loop(BoolC<false>());
+            if (known_shift) {
+                if (same_mol) row_loop(BoolC<true>(), BoolC<true>());
+                else row_loop(BoolC<true>(), BoolC<false>());
+            } else {
+                if (same_mol) row_loop(BoolC<false>(), BoolC<true>());
+                else row_loop(BoolC<false>(), BoolC<false>());
+            }
         }
         if (ncand == 0) range_of();
         // the slot table is rewritten for the next cell
