@@ -964,9 +964,10 @@ __device__ __forceinline__ void list_wave(const GridDev& g, int wv, int lw, bool
                 uint64_t keep[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    uint64_t m = live[k] & __ballot(pu[k] != ui);
-                    if constexpr (kSameMol) m &= ~__ballot(pm[k] == moli);
-                    keep[k] = m;
+                    // the row's own atom shares its molecule: with the
+                    // same-molecule exclusion, one test drops both
+                    if constexpr (kSameMol) keep[k] = live[k] & ~__ballot(pm[k] == moli);
+                    else keep[k] = live[k] & __ballot(pu[k] != ui);
                 }
                 // the row's exclusions: each read once for all K candidates,
                 // several reads in flight before the first compare
