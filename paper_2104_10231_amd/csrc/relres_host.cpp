@@ -1789,6 +1789,11 @@ ForceArgs force_args(const relres_ctx* c, const double* pos, void* forces, doubl
     a.ew_failed = reinterpret_cast<unsigned int*>(static_cast<char*>(c->d_status.p) +
                                                   offsetof(Status, ew_failed));
     a.spin_limit = c->spin_limit;
+    // rows of at least 8 list entries per lane (from the last list
+    // statistics) take 4 entries per lane per batch in forces-only launches
+    const double avg_a = c->n ? (double)c->stats.atom_entries / c->n : 0.0;
+    const double avg_s = c->n_sites ? (double)c->stats.site_entries / c->n_sites : 0.0;
+    a.wide_batch = c->n > 0 && avg_a >= 8.0 * la && (!sites || avg_a + avg_s >= 8.0 * lb);
     return a;
 }
 

@@ -165,6 +165,7 @@ struct ForceArgs {
     unsigned int* epoch;          // launch epoch, advanced by every energy/virial launch
     unsigned int* ew_failed;      // Status::ew_failed, counted by a wait that gave up
     int spin_limit;               // polls of a cross-block wait before it gives up (< 0: at once)
+    int wide_batch;               // forces-only launches: 4 entries per lane per batch, not 2
     int blocks_a, blocks_b;   // multiples of 8
     int lanes_a, lanes_b;     // lanes per row (powers of two)
     int log_lanes_a, log_lanes_b;

@@ -1291,6 +1291,11 @@ __device__ __forceinline__ void stage_table(T* dst, const T* __restrict__ src, i
 
 // Entries handled per lane per batch (see row_terms).
 constexpr int kBatch = 2;
+// ... and in forces-only launches of at least 8 entries per lane (issue-bound
+// launches of large systems), where more gathers in flight per lane pay: the
+// 256-replica batch's forces-only launch took 157 against 180 us, while every
+// energy/virial launch and the launches of small systems were slower with 4.
+constexpr int kBatchWide = 4;
 
 constexpr uint32_t kNoEntry = 0xffffffffu;
 
@@ -1381,12 +1386,12 @@ __device__ __forceinline__ void entry_terms(const BoxV& bx, const RowTab<S>& t,
 }
 
 // Positions of a batch of entries (entry-less slots read atom 0, unused).
-__device__ __forceinline__ void gather_batch(const ForceArgs& a, const uint32_t e[kBatch],
-                                             double px[kBatch], double py[kBatch],
-                                             double pz[kBatch])
+template <int B>
+__device__ __forceinline__ void gather_batch(const ForceArgs& a, const uint32_t e[B],
+                                             double px[B], double py[B], double pz[B])
 {
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < B; ++u) {
         const int uj = e[u] != kNoEntry ? (int)(e[u] & kIdxMask) : 0;
         px[u] = a.pos[3 * uj];
         py[u] = a.pos[3 * uj + 1];
@@ -1394,10 +1399,10 @@ __device__ __forceinline__ void gather_batch(const ForceArgs& a, const uint32_t 
     }
 }
 
-// Entries start, start + G, ... below cnt of one list row, kBatch per lane at
+// Entries start, start + G, ... below cnt of one list row, B per lane at
 // a time: their list loads, then their position gathers, are issued together
 // before any pair term is computed.
-template <bool CG, typename S, typename TF, bool EW, bool PC>
+template <bool CG, typename S, typename TF, bool EW, bool PC, int B>
 __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
                                           const RowTab<S>& t,
                                           const Cutoffs<S>& cut, const Cutoffs<double>& cut64,
@@ -1405,17 +1410,17 @@ __device__ __forceinline__ void row_terms(const ForceArgs& a, const BoxV& bx,
                                           const int* __restrict__ lst, int start, int cnt, int G,
                                           TF& fx, TF& fy, TF& fz, double* acc)
 {
-    for (int base = start; base < cnt; base += G * kBatch) {
-        uint32_t e[kBatch];
+    for (int base = start; base < cnt; base += G * B) {
+        uint32_t e[B];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < B; ++u) {
             const int k = base + u * G;
             e[u] = k < cnt ? (uint32_t)lst[k] : kNoEntry;
         }
-        double px[kBatch], py[kBatch], pz[kBatch];
-        gather_batch(a, e, px, py, pz);
+        double px[B], py[B], pz[B];
+        gather_batch<B>(a, e, px, py, pz);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
+        for (int u = 0; u < B; ++u)
             entry_terms<CG, S, TF, EW, PC>(bx, t, cut, cut64, xi, yi, zi, e[u], px[u], py[u],
                                            pz[u], fx, fy, fz, acc);
     }
@@ -1621,7 +1626,7 @@ __device__ void ew_finish(const ForceArgs& a, const double acc[8], unsigned tag)
     }
 }
 
-template <typename S, typename TF, bool EW, bool LDS, bool PC>
+template <typename S, typename TF, bool EW, bool LDS, bool PC, int B>
 __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> cut,
                                                        Cutoffs<double> cut64)
 {
@@ -1672,9 +1677,9 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     const bool live = rb ? row < a.n_srow : row < a.n_arow;
     const int* own_list = rb ? a.s_list + (size_t)row * a.s_cap : a.a_list + (size_t)row * a.a_cap;
     const int own_cap = rb ? a.s_cap : a.a_cap;
-    uint32_t e_own[kBatch];
+    uint32_t e_own[B];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < B; ++u) {
         const int k = sub + u * G;
         e_own[u] = (live && k < own_cap) ? (uint32_t)own_list[k] : kNoEntry;
     }
@@ -1682,16 +1687,16 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
     if (live) rec = rb ? a.s_rec[row] : a.a_rec[row];
     // FG entries: for a hybrid row they sit in the atom-list row named by the
     // record (loaded together with that row's count)
-    uint32_t e_fg[kBatch];
+    uint32_t e_fg[B];
     int cnt_a = rec.z;
     if (rb) {
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) e_fg[u] = kNoEntry;
+        for (int u = 0; u < B; ++u) e_fg[u] = kNoEntry;
         cnt_a = 0;
         if (live) {
             const int* fl = a.a_list + (size_t)rec.w * a.a_cap;
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < B; ++u) {
                 const int k = sub + u * G;
                 if (k < a.a_cap) e_fg[u] = (uint32_t)fl[k];
             }
@@ -1699,7 +1704,7 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) e_fg[u] = e_own[u];
+        for (int u = 0; u < B; ++u) e_fg[u] = e_own[u];
     }
 
     const PairCoef<S>* coef;
@@ -1741,16 +1746,16 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         const int ui = rec.x, ti = rec.y & ((1 << kTypeBits) - 1);
         const int cnt_s = rb ? rec.z : 0;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < B; ++u) {
             const int k = sub + u * G;
             if (k >= cnt_a) e_fg[u] = kNoEntry;
             if (k >= cnt_s) e_own[u] = kNoEntry;
         }
         const double xi = a.pos[3 * ui], yi = a.pos[3 * ui + 1], zi = a.pos[3 * ui + 2];
         // the first batches of both parts: all gathers before any arithmetic
-        double fxp[kBatch], fyp[kBatch], fzp[kBatch], sxp[kBatch], syp[kBatch], szp[kBatch];
-        gather_batch(a, e_fg, fxp, fyp, fzp);
-        if (rb) gather_batch(a, e_own, sxp, syp, szp);
+        double fxp[B], fyp[B], fzp[B], sxp[B], syp[B], szp[B];
+        gather_batch<B>(a, e_fg, fxp, fyp, fzp);
+        if (rb) gather_batch<B>(a, e_own, sxp, syp, szp);
         // the row's box (several systems: a read) after the gathers, so the
         // wave does not wait for it before issuing them
         const BoxV bx = row_box(a, rec.y >> kTypeBits);
@@ -1758,23 +1763,23 @@ __global__ __launch_bounds__(kForceBlock) void k_forces(ForceArgs a, Cutoffs<S> 
         const RowTab<S> rt{coef + ro, coef64 + ro, PC ? pcut + ro : nullptr,
                            PC ? pcut64 + ro : nullptr};
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
+        for (int u = 0; u < B; ++u)
             entry_terms<false, S, TF, EW, PC>(bx, rt, cut, cut64, xi, yi, zi, e_fg[u], fxp[u],
                                               fyp[u], fzp[u], fx, fy, fz, acc);
         if (rb) {
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u)
+            for (int u = 0; u < B; ++u)
                 entry_terms<true, S, TF, EW, PC>(bx, rt, cut, cut64, xi, yi, zi, e_own[u],
                                                  sxp[u], syp[u], szp[u], fx, fy, fz, acc);
         }
         // the rest of both rows
         const int ar = rb ? rec.w : row;
-        const int rest = sub + kBatch * G;
-        row_terms<false, S, TF, EW, PC>(a, bx, rt, cut, cut64, xi, yi, zi,
+        const int rest = sub + B * G;
+        row_terms<false, S, TF, EW, PC, B>(a, bx, rt, cut, cut64, xi, yi, zi,
                                         a.a_list + (size_t)ar * a.a_cap, rest, cnt_a, G, fx, fy,
                                         fz, acc);
         if (rb)
-            row_terms<true, S, TF, EW, PC>(a, bx, rt, cut, cut64, xi, yi, zi,
+            row_terms<true, S, TF, EW, PC, B>(a, bx, rt, cut, cut64, xi, yi, zi,
                                            a.s_list + (size_t)row * a.s_cap, rest, cnt_s, G, fx,
                                            fy, fz, acc);
     }
@@ -2082,6 +2087,23 @@ hipError_t launch_lists(GridDev* grids_dev, int ncell_a, int ncell_s, int waves_
     return hipGetLastError();
 }
 
+// One force launch; forces-only launches of wide rows take kBatchWide entries
+// per lane per batch.
+template <typename S, typename TF, bool EW, bool LDS, bool PC>
+void launch_force_kernel(const ForceArgs& a, const double* cut64, dim3 grid, dim3 block,
+                         hipStream_t s)
+{
+    if constexpr (!EW) {
+        if (a.wide_batch) {
+            hipLaunchKernelGGL((k_forces<S, TF, EW, LDS, PC, kBatchWide>), grid, block, 0, s, a,
+                               cut_as<S>(cut64), cut_as<double>(cut64));
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_forces<S, TF, EW, LDS, PC, kBatch>), grid, block, 0, s, a,
+                       cut_as<S>(cut64), cut_as<double>(cut64));
+}
+
 hipError_t launch_forces(const ForceArgs& a, const double* cut64, bool per_pair, int pair_math,
                          int precision, bool ew, hipStream_t s)
 {
@@ -2090,11 +2112,9 @@ hipError_t launch_forces(const ForceArgs& a, const double* cut64, bool per_pair,
 #define RELRES_LAUNCH_PC(S, TF, EW, PC)                                                          \
     do {                                                                                         \
         if (lds)                                                                                 \
-            hipLaunchKernelGGL((k_forces<S, TF, EW, true, PC>), grid, block, 0, s, a,            \
-                               cut_as<S>(cut64), cut_as<double>(cut64));                         \
+            launch_force_kernel<S, TF, EW, true, PC>(a, cut64, grid, block, s);                  \
         else                                                                                     \
-            hipLaunchKernelGGL((k_forces<S, TF, EW, false, PC>), grid, block, 0, s, a,           \
-                               cut_as<S>(cut64), cut_as<double>(cut64));                         \
+            launch_force_kernel<S, TF, EW, false, PC>(a, cut64, grid, block, s);                 \
     } while (0)
 #define RELRES_LAUNCH(S, TF, EW)                                                                 \
     do {                                                                                         \

@@ -52,6 +52,12 @@ def test_replica_batch_256_full_size():
     E = E.cpu().numpy()
     W = W.cpu().numpy()
     assert np.all(np.isfinite(F)) and np.all(np.isfinite(E)) and np.all(np.isfinite(W))
+    # forces only: rows of at least 8 list entries per lane (this batch's
+    # automatic lane split) take the force kernel's 4-entry batches
+    st = rr.stats()
+    assert st["atom_entries"] / n >= 16, st                 # 8 per lane at 2 lanes per row
+    F0, _, _ = rr.forces(p, energy=None, virial=None, want_energy=False, want_virial=False)
+    F0 = F0.double().cpu().numpy()
     sizes = np.diff(b.offsets)
     order = np.argsort(sizes, kind="stable")
     small_box = int(np.argmin([s.box[0] for s in b.systems]))
@@ -68,6 +74,7 @@ def test_replica_batch_256_full_size():
         print(f"[fullsize] replica {k}: N={s.n}, box {s.box[0]:.2f} A, skin {s.skin}", flush=True)
         Fr, Er, Wr = oracle.compute(s)
         assert rel_rms(F[o0:o1], Fr) <= 1e-5, (k, rel_rms(F[o0:o1], Fr))
+        assert rel_rms(F0[o0:o1], Fr) <= 1e-5, (k, rel_rms(F0[o0:o1], Fr))
         assert abs(E[k, 0] - Er[0]) <= 1e-7 * abs(Er[0]), (k, E[k], Er)
         assert np.abs(W[k] - Wr).max() <= 1e-7 * np.abs(Wr).max(), (k, W[k], Wr)
         for which, got in ((0, pa), (1, ps)):
